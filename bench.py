@@ -1,0 +1,186 @@
+"""Throughput of the fused ternary colour-gradient LBM step on one MI355X.
+
+Prints ONE JSON line.  The headline ``value`` is the plain FP64 step in MLUPS (million
+lattice-node updates per second) on the 4096^2 droplet-tiling workload, with inputs
+resident in HBM; extra fields report the FP32-storage / FP32 variants, the batched
+morphology sweep and the adjoint step, the HBM roofline of the dominant kernel and the
+FP64 CPU oracle timed on the host as a reported baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline: plain FP64 vs FP32 batched vs adjoint step"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LU = {"fp64": 432, "fp32_storage": 216, "fp32": 216}  # 27 reads + 27 writes
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("lbm3_step.hip", "lbm3_internal.h"):
+        with open(os.path.join(ROOT, "paper_1808_08555_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_tag: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary of this kernel, if the
+    summary was taken from the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != kernel_source_hash():
+        return None
+    return float(t.group(1))
+
+
+def time_steps(torch, lbm3, L, steps: int, reps: int = 3):
+    """Median over reps of the time of `steps` steps, HIP events on the library's stream."""
+    st = torch.cuda.current_stream()
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        L.step(steps)
+        b.record(st)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b) / 1e3)
+    return float(np.median(times))
+
+
+def copy_bandwidth(torch, lbm3, nbytes: int = 2 << 30, reps: int = 5) -> float:
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    st = torch.cuda.current_stream()
+    lbm3.lbm3_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, st)
+    best = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        lbm3.lbm3_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, st)
+        b.record(st)
+        torch.cuda.synchronize()
+        best.append(a.elapsed_time(b) / 1e3)
+    del src, dst
+    return 2 * nbytes / float(np.median(best)) / 1e9
+
+
+def bench_plain(torch, lbm3, w, precision: str, steps: int, warmup: int):
+    st = torch.cuda.current_stream()
+    L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, precision=precision, stream=st)
+    L.init(w.rho)
+    L.step(warmup)
+    torch.cuda.synchronize()
+    t = time_steps(torch, lbm3, L, steps)
+    tile = L.tile()
+    obs = L.observables()[0]
+    L.close()
+    n = w.nx * w.ny
+    mlups = n * steps / t / 1e6
+    return {"mlups": mlups, "ms_per_step": t / steps * 1e3, "tile": list(tile),
+            "gbs": BYTES_PER_LU[precision] * n * steps / t / 1e9, "nonfinite": obs["nonfinite"]}
+
+
+def cpu_baseline(w, steps: int = 2):
+    import oracle
+
+    p = oracle.Params(w.nx, w.ny, w.sigma, w.tau)
+    f = oracle.init(p, w.rho)
+    t0 = time.perf_counter()
+    f = oracle.run(p, f, steps)
+    dt = time.perf_counter() - t0
+    return {"value": w.nx * w.ny * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} FP64 steps of the full {w.nx}x{w.ny} droplet-tiling lattice "
+                      f"({dt:.1f} s, OpenMP over rows)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-plain", action="store_true", help="time the headline workload only")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the step, its batched form and its adjoint run on a "
+              "single MI355X; multi-GPU runs are not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1808_08555_amd import inputs, lbm3
+
+    torch.cuda.set_device(0)
+    w = inputs.droplet_tiling(4096)
+    log(f"workload {w.name}: {w.nx}x{w.ny}, FP64, {args.warmup} warm-up + {args.steps} timed steps")
+    main_res = bench_plain(torch, lbm3, w, "fp64", args.steps, args.warmup)
+    log(f"fp64 {main_res}")
+    extra = {}
+    if not args.only_plain:
+        for prec in ("fp32_storage", "fp32"):
+            extra[prec] = bench_plain(torch, lbm3, w, prec, args.steps, args.warmup)
+            log(f"{prec} {extra[prec]}")
+        w2 = inputs.compound_droplet(256, 30.0, 60.0, 0.01, 0.01)
+        extra["compound_256_fp64"] = bench_plain(torch, lbm3, w2, "fp64", 2000, 100)
+        log(f"compound 256 fp64 {extra['compound_256_fp64']}")
+    copy_gbs = copy_bandwidth(torch, lbm3)
+    log(f"device copy {copy_gbs:.0f} GB/s")
+
+    n = w.nx * w.ny
+    achieved = main_res["gbs"]
+    traffic = measured_traffic("lbm3_step_fp64_R4096")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "bytes_per_lu": BYTES_PER_LU["fp64"], "lu_per_launch": n,
+                "frac_of_device_copy": round(achieved / copy_gbs, 4), "device_copy_gbs": round(copy_gbs, 1)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("oracle CPU baseline ...")
+        cpu = cpu_baseline(w)
+        log(f"cpu {cpu}")
+    line = {
+        "metric": METRIC, "value": round(main_res["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(main_res["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "droplet tiling 4096x4096 periodic D2Q9 (16x16 cells of two tangent "
+                               "R=40 disks in fluid 3, interface noise seed 1808), sigma=0.01, tau=1",
+                   "nx": w.nx, "ny": w.ny, "tile": main_res["tile"], "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    for k, v in extra.items():
+        line[k] = {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 4),
+                   "gbs": round(v["gbs"], 1), "tile": v["tile"]}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

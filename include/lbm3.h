@@ -1,0 +1,169 @@
+/*
+ * lbm3.h -- C ABI of the MI355X ternary colour-gradient lattice Boltzmann library.
+ *
+ * The library advances three immiscible fluids on a periodic D2Q9 lattice with
+ * the model of Yu, Liu, Liang and Zhang, "A versatile lattice Boltzmann model
+ * for immiscible ternary fluid flows" (arXiv:1808.08555), Sec. 2.  One time step
+ * computes the colour gradients of the three densities, the N-phase interfacial
+ * force (Eq. 7) applied as a Guo body force (Eqs. 8-9) in the BGK collision of
+ * the total distribution (Eqs. 1-3) with a harmonic-mean viscosity (Eqs. 10-11),
+ * the generalized recolouring (Eq. 13) with the proposed segregation parameters
+ * (Eqs. 18-20), and streaming (Eq. 22).
+ *
+ * Conventions shared by every call
+ *   - Fluids k = 0, 1, 2 are the paper's red, green, blue ("fluid 1, 2, 3").
+ *   - sigma[0] = sigma_rg (12), sigma[1] = sigma_rb (13), sigma[2] = sigma_gb (23).
+ *   - Host arrays are C-contiguous float64 with x fastest:
+ *       densities  rho[3][ny][nx],  velocities u[2][ny][nx],
+ *       populations f[3][9][ny][nx]  (post-streaming state, direction order
+ *       e_0 = (0,0), e_1 = (1,0), e_2 = (0,1), e_3 = (-1,0), e_4 = (0,-1),
+ *       e_5 = (1,1), e_6 = (-1,1), e_7 = (-1,-1), e_8 = (1,-1)).
+ *   - Return value: LBM3_OK (0) or a negative LBM3_E* code; a message is kept in
+ *     lbm3_last_error() (per thread).  No call exits, aborts or throws.
+ *   - Ownership: a handle owns all of its device memory; the caller owns every
+ *     host array, which calls read or fill before they return and never keep.
+ *   - Streams: work is ordered on the HIP stream given at create time (NULL =
+ *     the null stream).  Only calls documented as blocking synchronise the host.
+ */
+#ifndef LBM3_H
+#define LBM3_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBM3_OK = 0,
+    LBM3_EINVAL = -1,      /* invalid argument, parameter or field */
+    LBM3_ENOMEM = -2,      /* device or host allocation failed */
+    LBM3_EDEVICE = -3,     /* a HIP runtime call failed (message names it) */
+    LBM3_EUNSUPPORTED = -4,/* a feature the library does not provide (walls) */
+    LBM3_ENONFINITE = -5,  /* the state holds a NaN or Inf */
+    LBM3_ESTATE = -6       /* call out of order (e.g. step before init_fields) */
+};
+
+enum {
+    LBM3_FP64 = 0,         /* populations stored and computed in FP64 */
+    LBM3_FP32_STORAGE = 1, /* populations stored in FP32, arithmetic in FP64 */
+    LBM3_FP32 = 2          /* populations stored and computed in FP32 */
+};
+
+enum { LBM3_PERIODIC = 0 };
+
+/* The problem as the paper states it (Sec. 2 and the set-ups of Sec. 3):
+ * lattice size, pure-fluid densities rho_k^0 (Eq. 6), interfacial tensions
+ * sigma_kl (Eq. 7), per-fluid relaxation times tau_k (nu_k = (tau_k - 1/2)/3,
+ * Eq. 11), reference segregation parameter beta^0 (Eq. 19), periodic
+ * boundaries.  Wall wettability is reserved: the paper has no wall model. */
+typedef struct {
+    int32_t nx, ny;              /* >= 1 each; 27*nx*ny < 2^31 */
+    double rho0[3];              /* > 0 (the paper validates equal densities 1) */
+    double sigma[3];             /* finite, > 0 */
+    double tau[3];               /* finite, > 0.5 */
+    double beta0;                /* 0 selects 0.7; else finite, > 0 */
+    int32_t boundary;            /* LBM3_PERIODIC only, else LBM3_EUNSUPPORTED */
+    double wall_wettability[3];  /* reserved: must be 0, else LBM3_EUNSUPPORTED */
+    int32_t precision;           /* LBM3_FP64 | LBM3_FP32_STORAGE | LBM3_FP32 */
+} lbm3_params;
+
+/* Observables of the current state (the velocity is the half-force velocity of
+ * Eq. 9; u_max is the maximum spurious velocity of Table 2). */
+typedef struct {
+    int64_t step;            /* steps taken since init_fields / set_state */
+    double mass[3];          /* sum over nodes of rho_k */
+    double momentum[2];      /* sum over nodes of rho u */
+    double kinetic_energy;   /* sum over nodes of rho |u|^2 / 2 */
+    double u_max;            /* max over nodes of |u| */
+    int32_t nonfinite;       /* 1 when any population is NaN or Inf */
+} lbm3_obs;
+
+typedef struct lbm3 lbm3_t;
+typedef struct lbm3_batch lbm3_batch_t;
+
+/* Validates *p (EINVAL / EUNSUPPORTED before any device work), precomputes the
+ * segregation constants of Eqs. (18)-(20) on the host in FP64 and allocates the
+ * two population buffers on the current HIP device.  hip_stream: a hipStream_t
+ * or NULL.  On failure *out is set to NULL. */
+int lbm3_create(const lbm3_params *p, void *hip_stream, lbm3_t **out);
+
+/* Sets the state from densities (and optionally velocities): with u == NULL
+ * f_{i,k} = w_i rho_k, else f_{i,k} = (rho_k/rho) f_eq_i(rho, u) with f_eq of
+ * Eq. (3).  rho: host [3][ny][nx], finite, >= 0, with rho > 0 at every node;
+ * u: host [2][ny][nx] finite, or NULL.  EINVAL leaves the state unchanged.
+ * Resets the step counter.  Returns after the host arrays have been copied. */
+int lbm3_init_fields(lbm3_t *h, const double *rho, const double *u);
+
+/* Sets the state from post-streaming populations f: host [3][9][ny][nx],
+ * finite.  Resets the step counter. */
+int lbm3_set_state(lbm3_t *h, const double *f);
+
+/* Enqueues n >= 0 full time steps (Sec. 2: gradient, force, collision,
+ * recolouring, streaming) on the handle's stream; does not wait.  ESTATE
+ * before the first init_fields / set_state. */
+int lbm3_step(lbm3_t *h, int64_t n);
+
+/* Blocking.  Computes the observables of the current state into *out (may be
+ * NULL) and, when non-NULL, copies the densities rho_k (host [3][ny][nx]) and
+ * the post-streaming populations (host [3][9][ny][nx], converted to FP64).
+ * Returns LBM3_ENONFINITE (after filling *out) when the state is not finite. */
+int lbm3_observables(lbm3_t *h, lbm3_obs *out, double *rho_out, double *f_out);
+
+/* Releases the handle and its device memory.  NULL is accepted. */
+int lbm3_destroy(lbm3_t *h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *lbm3_last_error(void);
+
+/* Host-side constants the step uses for *p (validated as in lbm3_create):
+ * X[p] of Eq. (18) and g[p] = g(X) of Eq. (20) for the pairs (rg, rb, gb), and
+ * nu[k] = (tau_k - 1/2)/3.  Any output pointer may be NULL.  No device work. */
+int lbm3_derived(const lbm3_params *p, double X[3], double g[3], double nu[3]);
+
+/* Launch shape of the fused step: threads per workgroup (64, 128, 256 or 512;
+ * each workgroup owns a strip of threads-4 columns) and rows marched per
+ * workgroup (>= 1).  Results do not depend on the shape (bitwise). */
+int lbm3_set_tile(lbm3_t *h, int32_t threads, int32_t rows);
+int lbm3_get_tile(const lbm3_t *h, int32_t *threads, int32_t *rows);
+
+/* Device pointer of the buffer that holds the current state (populations after
+ * collision and recolouring, before streaming: plane (k*9+i) at element offset
+ * (k*9+i)*plane_stride, row pitch nx), its element size in bytes and the plane
+ * stride in elements.  For measurement tools; the layout is not a stable API. */
+int lbm3_state_buffer(const lbm3_t *h, void **dev_ptr, int32_t *elem_bytes, int64_t *plane_stride);
+
+/* ---- batched form: many independent lattices advanced together ---------------
+ * count instances with parameters p[0..count-1] (all the same precision; sizes
+ * may differ) share one device arena; lbm3_batch_step advances every instance by
+ * n steps with one graph launch per chunk of steps (a captured hipGraph of
+ * fused-step launches over a flat list of tiles spanning all instances). */
+int lbm3_batch_create(const lbm3_params *p, int32_t count, void *hip_stream, lbm3_batch_t **out);
+int lbm3_batch_init_fields(lbm3_batch_t *b, int32_t idx, const double *rho, const double *u);
+int lbm3_batch_step(lbm3_batch_t *b, int64_t n);
+int lbm3_batch_observables(lbm3_batch_t *b, int32_t idx, lbm3_obs *out, double *rho_out);
+int lbm3_batch_set_tile(lbm3_batch_t *b, int32_t size_class_side, int32_t threads, int32_t rows);
+int lbm3_batch_destroy(lbm3_batch_t *b);
+
+/* ---- adjoint (reverse-mode derivative) of the FP64 step ----------------------
+ * lbm3_adjoint_record: advances the FP64 state by nsteps (as lbm3_step) and keeps
+ * a checkpoint of the state every ckpt_every steps (device memory).
+ * lbm3_adjoint: given drho1_T = dL/drho_1(x, T) (host [ny][nx]) for the state at
+ * the end of the last recording, returns dL/dsigma (3, order rg, rb, gb) and
+ * dL/drho_k(x, 0) (host [3][ny][nx]) for the densities given to init_fields
+ * (u == NULL), by a hand-written reverse sweep over the step (recolouring,
+ * collision with Guo forcing, force divergence, colour gradient, streaming) with
+ * segment recomputation from the checkpoints.  Blocking.  The forward state is
+ * left at step T.  Requires LBM3_FP64 and a preceding lbm3_adjoint_record. */
+int lbm3_adjoint_record(lbm3_t *h, int64_t nsteps, int32_t ckpt_every);
+int lbm3_adjoint(lbm3_t *h, const double *drho1_T, double dsigma[3], double *drho0);
+
+/* Plain device copy of nbytes (multiple of 16) from src to dst on hip_stream:
+ * the bandwidth reference the roofline figures are compared with. */
+int lbm3_device_copy(void *dst, const void *src, int64_t nbytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM3_H */

@@ -1,0 +1,465 @@
+// Host side of the C ABI declared in include/lbm3.h: parameter validation, the FP64
+// host precompute of the segregation law, device buffers and stream-ordered launches.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "lbm3_handle.h"
+
+namespace tcg {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+const char* last_error() { return g_err; }
+
+int hip_fail(hipError_t e, const char* what)
+{
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? LBM3_ENOMEM : LBM3_EDEVICE;
+}
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int validate_params(const lbm3_params* p)
+{
+    if (!p) {
+        set_error("params is NULL");
+        return LBM3_EINVAL;
+    }
+    if (p->nx < 1 || p->ny < 1) {
+        set_error("nx and ny must be >= 1 (got %d x %d)", p->nx, p->ny);
+        return LBM3_EINVAL;
+    }
+    if ((int64_t)27 * p->nx * p->ny >= ((int64_t)1 << 31)) {
+        set_error("lattice too large: 27*nx*ny must be < 2^31");
+        return LBM3_EINVAL;
+    }
+    for (int k = 0; k < 3; ++k) {
+        if (!finite_pos(p->rho0[k])) {
+            set_error("rho0[%d] must be finite and > 0", k);
+            return LBM3_EINVAL;
+        }
+        if (!finite_pos(p->sigma[k])) {
+            set_error("sigma[%d] must be finite and > 0", k);
+            return LBM3_EINVAL;
+        }
+        if (!std::isfinite(p->tau[k]) || !(p->tau[k] > 0.5)) {
+            set_error("tau[%d] must be finite and > 1/2 (viscosity (tau - 1/2)/3 > 0)", k);
+            return LBM3_EINVAL;
+        }
+    }
+    if (p->beta0 != 0.0 && !finite_pos(p->beta0)) {
+        set_error("beta0 must be 0 (default 0.7) or finite and > 0");
+        return LBM3_EINVAL;
+    }
+    if (p->boundary != LBM3_PERIODIC) {
+        set_error("only periodic boundaries are provided (the model has no wall treatment)");
+        return LBM3_EUNSUPPORTED;
+    }
+    for (int k = 0; k < 3; ++k)
+        if (p->wall_wettability[k] != 0.0) {
+            set_error("wall wettability is reserved and must be 0");
+            return LBM3_EUNSUPPORTED;
+        }
+    if (p->precision < LBM3_FP64 || p->precision > LBM3_FP32) {
+        set_error("precision must be LBM3_FP64, LBM3_FP32_STORAGE or LBM3_FP32");
+        return LBM3_EINVAL;
+    }
+    return LBM3_OK;
+}
+
+// Pair p of fluids (k, l) and the third fluid m; sigma index of an unordered pair.
+static const int PK[3] = {0, 0, 1}, PL[3] = {1, 2, 2};
+static int pair_index(int a, int b)
+{
+    if (a > b) {
+        int t = a;
+        a = b;
+        b = t;
+    }
+    return a == 0 ? (b == 1 ? 0 : 1) : 2;
+}
+
+// g(X) of Eq. (20) with sin(arccos X) = sqrt((1 - X)(1 + X)); within 1e-12 of |X| = 1
+// the limiting value is used (g = -1 at X = 1, +1 at X = -1), so that the critical
+// states, where X = +-1 exactly in real arithmetic, do not depend on the rounding of X.
+static double seg_g(double X)
+{
+    if (X >= 1.0 - 1e-12) return -1.0;
+    if (X <= -1.0 + 1e-12) return 1.0;
+    const double s = std::sqrt((1.0 - X) * (1.0 + X));
+    return X < 0.0 ? 1.0 - s : s - 1.0;
+}
+
+void derive(const lbm3_params* p, KParams* kp, double X[3], double g[3], double nu[3])
+{
+    double Xl[3], gl[3], nul[3];
+    for (int q = 0; q < 3; ++q) {
+        const int k = PK[q], l = PL[q], m = 3 - k - l;
+        const double smk = p->sigma[pair_index(m, k)], sml = p->sigma[pair_index(m, l)];
+        const double skl = p->sigma[q];
+        Xl[q] = (smk * smk + sml * sml - skl * skl) / (2.0 * smk * sml);  // Eq. (18)
+        gl[q] = seg_g(Xl[q]);
+        nul[q] = (p->tau[q] - 0.5) / 3.0;  // Eq. (11) with c_s^2 = 1/3
+    }
+    if (X)
+        for (int q = 0; q < 3; ++q) X[q] = Xl[q];
+    if (g)
+        for (int q = 0; q < 3; ++q) g[q] = gl[q];
+    if (nu)
+        for (int q = 0; q < 3; ++q) nu[q] = nul[q];
+    if (kp) {
+        std::memset(kp, 0, sizeof *kp);
+        kp->nx = p->nx;
+        kp->ny = p->ny;
+        const int64_t n = (int64_t)p->nx * p->ny;
+        kp->plane = (n + 255) / 256 * 256;  // planes start on 1 KiB (FP32) / 2 KiB (FP64) boundaries
+        for (int q = 0; q < 3; ++q) {
+            kp->sigma[q] = p->sigma[q];
+            kp->g[q] = gl[q];
+            kp->inv_nu[q] = 1.0 / nul[q];
+            kp->cfac[q] = 1e6 / (p->rho0[PK[q]] * p->rho0[PL[q]]);
+        }
+        kp->beta0 = p->beta0 == 0.0 ? 0.7 : p->beta0;
+        kp->guard = p->precision == LBM3_FP32 ? 1e-6 : 1e-12;
+    }
+}
+
+Prec prec_of(int precision)
+{
+    return precision == LBM3_FP64 ? Prec::F64 : (precision == LBM3_FP32_STORAGE ? Prec::F32S : Prec::F32);
+}
+
+void default_tile(const KParams& kp, int* threads, int* rows)
+{
+    const int t = kp.nx >= 512 ? 256 : (kp.nx >= 124 ? 128 : 64);
+    const int nstrips = (kp.nx + t - 5) / (t - 4);
+    int r = (int)(((int64_t)kp.ny * nstrips + 1023) / 1024);
+    r = r < 16 ? 16 : (r > 64 ? 64 : r);
+    *threads = t;
+    *rows = r;
+}
+
+int check_rho_fields(const double* rho, const double* u, int64_t n)
+{
+    if (!rho) {
+        set_error("rho is NULL");
+        return LBM3_EINVAL;
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double v = rho[k * n + j];
+            if (!std::isfinite(v) || v < 0.0) {
+                set_error("rho[%d] at node %lld must be finite and >= 0", k, (long long)j);
+                return LBM3_EINVAL;
+            }
+            s += v;
+        }
+        if (!(s > 0.0)) {
+            set_error("total density must be > 0 at every node (node %lld)", (long long)j);
+            return LBM3_EINVAL;
+        }
+        if (u)
+            for (int a = 0; a < 2; ++a)
+                if (!std::isfinite(u[a * n + j])) {
+                    set_error("u[%d] at node %lld is not finite", a, (long long)j);
+                    return LBM3_EINVAL;
+                }
+    }
+    return LBM3_OK;
+}
+
+}  // namespace tcg
+
+using namespace tcg;
+
+static int ensure_staging(lbm3* h, size_t doubles)
+{
+    if (h->staging_cap >= doubles) return LBM3_OK;
+    if (h->staging) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->staging);
+        h->staging = nullptr;
+        h->staging_cap = 0;
+    }
+    hipError_t e = hipMalloc((void**)&h->staging, doubles * sizeof(double));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(staging)");
+    h->staging_cap = doubles;
+    return LBM3_OK;
+}
+
+static int ensure_partials(lbm3* h, int nblocks)
+{
+    if (h->partials_cap >= nblocks) return LBM3_OK;
+    if (h->partials) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->partials);
+        h->partials = nullptr;
+        h->partials_cap = 0;
+    }
+    hipError_t e = hipMalloc((void**)&h->partials, (size_t)nblocks * kObsFields * sizeof(double));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(partials)");
+    h->partials_cap = nblocks;
+    return LBM3_OK;
+}
+
+extern "C" {
+
+const char* lbm3_last_error(void) { return tcg::last_error(); }
+
+int lbm3_derived(const lbm3_params* p, double X[3], double g[3], double nu[3])
+{
+    int rc = validate_params(p);
+    if (rc) return rc;
+    derive(p, nullptr, X, g, nu);
+    return LBM3_OK;
+}
+
+int lbm3_create(const lbm3_params* p, void* hip_stream, lbm3_t** out)
+{
+    if (!out) {
+        set_error("out is NULL");
+        return LBM3_EINVAL;
+    }
+    *out = nullptr;
+    int rc = validate_params(p);
+    if (rc) return rc;
+    lbm3* h = new (std::nothrow) lbm3();
+    if (!h) {
+        set_error("host allocation failed");
+        return LBM3_ENOMEM;
+    }
+    h->p = *p;
+    derive(p, &h->kp, nullptr, nullptr, nullptr);
+    h->prec = prec_of(p->precision);
+    h->stream = (hipStream_t)hip_stream;
+    default_tile(h->kp, &h->threads, &h->rows);
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipGetDevice");
+    }
+    const size_t bytes = (size_t)27 * h->kp.plane * elem_bytes(h->prec);
+    for (int b = 0; b < 2; ++b) {
+        e = hipMalloc(&h->buf[b], bytes);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "hipMalloc(populations)");
+            lbm3_destroy(h);
+            return rc;
+        }
+    }
+    e = hipMalloc((void**)&h->obs_dev, kObsFields * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&h->obs_host, kObsFields * sizeof(double));
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "allocation of observables buffers");
+        lbm3_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return LBM3_OK;
+}
+
+int lbm3_init_fields(lbm3_t* h, const double* rho, const double* u)
+{
+    if (!h) {
+        set_error("handle is NULL");
+        return LBM3_EINVAL;
+    }
+    const int64_t n = (int64_t)h->kp.nx * h->kp.ny;
+    int rc = check_rho_fields(rho, u, n);
+    if (rc) return rc;
+    rc = ensure_staging(h, (size_t)27 * n);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(h->staging, rho, 3 * n * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && u)
+        e = hipMemcpyAsync(h->staging + 3 * n, u, 2 * n * sizeof(double), hipMemcpyHostToDevice,
+                           h->stream);
+    if (e == hipSuccess)
+        e = launch_init(h->prec, h->staging, u ? h->staging + 3 * n : nullptr, h->buf[0], h->kp,
+                        h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "init_fields");
+    h->cur = 0;
+    h->step = 0;
+    h->ready = true;
+    h->tape_valid = false;
+    h->init_at_rest = (u == nullptr);
+    return LBM3_OK;
+}
+
+int lbm3_set_state(lbm3_t* h, const double* f)
+{
+    if (!h || !f) {
+        set_error("handle or f is NULL");
+        return LBM3_EINVAL;
+    }
+    const int64_t n = (int64_t)h->kp.nx * h->kp.ny;
+    for (int64_t j = 0; j < 27 * n; ++j)
+        if (!std::isfinite(f[j])) {
+            set_error("f is not finite at element %lld", (long long)j);
+            return LBM3_EINVAL;
+        }
+    int rc = ensure_staging(h, (size_t)27 * n);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(h->staging, f, 27 * n * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = launch_import(h->prec, h->staging, h->buf[0], h->kp, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "set_state");
+    h->cur = 0;
+    h->step = 0;
+    h->ready = true;
+    h->tape_valid = false;
+    h->init_at_rest = false;
+    return LBM3_OK;
+}
+
+int lbm3_step(lbm3_t* h, int64_t n)
+{
+    if (!h) {
+        set_error("handle is NULL");
+        return LBM3_EINVAL;
+    }
+    if (n < 0) {
+        set_error("n must be >= 0");
+        return LBM3_EINVAL;
+    }
+    if (!h->ready) {
+        set_error("lbm3_step before lbm3_init_fields / lbm3_set_state");
+        return LBM3_ESTATE;
+    }
+    for (int64_t s = 0; s < n; ++s) {
+        hipError_t e = launch_step(h->prec, h->buf[h->cur], h->buf[h->cur ^ 1], h->kp, h->threads,
+                                   h->rows, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        h->cur ^= 1;
+        h->step += 1;
+    }
+    h->tape_valid = false;
+    return LBM3_OK;
+}
+
+int lbm3_observables(lbm3_t* h, lbm3_obs* out, double* rho_out, double* f_out)
+{
+    if (!h) {
+        set_error("handle is NULL");
+        return LBM3_EINVAL;
+    }
+    if (!h->ready) {
+        set_error("lbm3_observables before lbm3_init_fields / lbm3_set_state");
+        return LBM3_ESTATE;
+    }
+    const int64_t n = (int64_t)h->kp.nx * h->kp.ny;
+    int rc = ensure_partials(h, step_blocks(h->kp, h->threads, h->rows));
+    if (!rc && (rho_out || f_out)) rc = ensure_staging(h, (size_t)27 * n);
+    if (rc) return rc;
+    int nb = 0;
+    hipError_t e = launch_observe(h->prec, h->buf[h->cur], h->kp, h->threads, h->rows,
+                                  h->partials, &nb, rho_out ? h->staging : nullptr, h->stream);
+    if (e == hipSuccess) e = launch_reduce_obs(h->partials, nb, h->obs_dev, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->obs_host, h->obs_dev, kObsFields * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && rho_out)
+        e = hipMemcpyAsync(rho_out, h->staging, 3 * n * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream);
+    if (e == hipSuccess && f_out) {
+        e = launch_export(h->prec, h->buf[h->cur], h->staging, h->kp, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(f_out, h->staging, 27 * n * sizeof(double), hipMemcpyDeviceToHost,
+                               h->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "observables");
+    const double* o = h->obs_host;
+    if (out) {
+        out->step = h->step;
+        for (int k = 0; k < 3; ++k) out->mass[k] = o[k];
+        out->momentum[0] = o[3];
+        out->momentum[1] = o[4];
+        out->kinetic_energy = o[5];
+        out->u_max = o[6];
+        out->nonfinite = o[7] != 0.0 ? 1 : 0;
+    }
+    if (o[7] != 0.0) {
+        set_error("state is not finite at step %lld", (long long)h->step);
+        return LBM3_ENONFINITE;
+    }
+    return LBM3_OK;
+}
+
+int lbm3_destroy(lbm3_t* h)
+{
+    if (!h) return LBM3_OK;
+    (void)hipStreamSynchronize(h->stream);
+    for (int b = 0; b < 2; ++b)
+        if (h->buf[b]) (void)hipFree(h->buf[b]);
+    if (h->staging) (void)hipFree(h->staging);
+    if (h->partials) (void)hipFree(h->partials);
+    if (h->obs_dev) (void)hipFree(h->obs_dev);
+    if (h->obs_host) (void)hipHostFree(h->obs_host);
+    adjoint_release(h);
+    delete h;
+    return LBM3_OK;
+}
+
+int lbm3_set_tile(lbm3_t* h, int32_t threads, int32_t rows)
+{
+    if (!h) {
+        set_error("handle is NULL");
+        return LBM3_EINVAL;
+    }
+    if (!(threads == 64 || threads == 128 || threads == 256) || rows < 1) {
+        set_error("threads must be 64, 128 or 256 and rows >= 1");
+        return LBM3_EINVAL;
+    }
+    h->threads = threads;
+    h->rows = rows;
+    return LBM3_OK;
+}
+
+int lbm3_get_tile(const lbm3_t* h, int32_t* threads, int32_t* rows)
+{
+    if (!h) {
+        set_error("handle is NULL");
+        return LBM3_EINVAL;
+    }
+    if (threads) *threads = h->threads;
+    if (rows) *rows = h->rows;
+    return LBM3_OK;
+}
+
+int lbm3_state_buffer(const lbm3_t* h, void** dev_ptr, int32_t* eb, int64_t* plane)
+{
+    if (!h) {
+        set_error("handle is NULL");
+        return LBM3_EINVAL;
+    }
+    if (dev_ptr) *dev_ptr = h->buf[h->cur];
+    if (eb) *eb = (int32_t)elem_bytes(h->prec);
+    if (plane) *plane = h->kp.plane;
+    return LBM3_OK;
+}
+
+int lbm3_device_copy(void* dst, const void* src, int64_t nbytes, void* hip_stream)
+{
+    if (!dst || !src || nbytes < 0 || nbytes % 16) {
+        set_error("device_copy: non-NULL pointers and nbytes a multiple of 16 required");
+        return LBM3_EINVAL;
+    }
+    hipError_t e = launch_copy(dst, src, nbytes, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "device_copy");
+    return LBM3_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,42 @@
+// The handle behind lbm3_t and helpers shared by the host sources.
+#pragma once
+
+#include <vector>
+
+#include "lbm3_internal.h"
+
+struct lbm3 {
+    lbm3_params p;
+    tcg::KParams kp;
+    tcg::Prec prec;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    void* buf[2] = {nullptr, nullptr};  // population buffers (pull scheme, ping-pong)
+    int cur = 0;                        // buffer holding the current state
+    int64_t step = 0;
+    bool ready = false;
+    bool init_at_rest = false;          // state came from init_fields with u == NULL
+    int threads = 256, rows = 64;
+    double* staging = nullptr;          // device FP64 staging for host transfers
+    size_t staging_cap = 0;
+    double* partials = nullptr;         // per-workgroup observables partials
+    int partials_cap = 0;
+    double* obs_dev = nullptr;
+    double* obs_host = nullptr;         // pinned
+    // adjoint tape (lbm3_adjoint.hip)
+    bool tape_valid = false;
+    int64_t tape_steps = 0;
+    int32_t tape_every = 0;
+    std::vector<void*> ckpt;            // checkpoint states (post-streaming buffer layout)
+    void* adj_ws = nullptr;             // adjoint workspace
+    size_t adj_ws_bytes = 0;
+};
+
+namespace tcg {
+int hip_fail(hipError_t e, const char* what);
+const char* last_error();
+Prec prec_of(int precision);
+void default_tile(const KParams& kp, int* threads, int* rows);
+int check_rho_fields(const double* rho, const double* u, int64_t n);
+void adjoint_release(lbm3* h);
+}  // namespace tcg

@@ -1,0 +1,324 @@
+"""ctypes binding of liblbm3.so (the HIP library), one Python function per C entry point.
+
+The functions keep the C names and only marshal arguments: NumPy float64 arrays in
+and out, a HIP stream handle (a ``torch.cuda.Stream``, its integer handle, or None for
+the null stream).  Every step of the method runs in the library's HIP kernels; if the
+library is missing this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm3.so")
+
+LBM3_OK, LBM3_EINVAL, LBM3_ENOMEM, LBM3_EDEVICE, LBM3_EUNSUPPORTED, LBM3_ENONFINITE, \
+    LBM3_ESTATE = 0, -1, -2, -3, -4, -5, -6
+LBM3_FP64, LBM3_FP32_STORAGE, LBM3_FP32 = 0, 1, 2
+LBM3_PERIODIC = 0
+PRECISIONS = {"fp64": LBM3_FP64, "fp32_storage": LBM3_FP32_STORAGE, "fp32": LBM3_FP32}
+ERROR_NAMES = {0: "LBM3_OK", -1: "LBM3_EINVAL", -2: "LBM3_ENOMEM", -3: "LBM3_EDEVICE",
+               -4: "LBM3_EUNSUPPORTED", -5: "LBM3_ENONFINITE", -6: "LBM3_ESTATE"}
+
+
+class lbm3_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("rho0", ctypes.c_double * 3), ("sigma", ctypes.c_double * 3),
+        ("tau", ctypes.c_double * 3), ("beta0", ctypes.c_double),
+        ("boundary", ctypes.c_int32), ("wall_wettability", ctypes.c_double * 3),
+        ("precision", ctypes.c_int32),
+    ]
+
+
+class lbm3_obs(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64), ("mass", ctypes.c_double * 3),
+        ("momentum", ctypes.c_double * 2), ("kinetic_energy", ctypes.c_double),
+        ("u_max", ctypes.c_double), ("nonfinite", ctypes.c_int32),
+    ]
+
+
+class Lbm3Error(RuntimeError):
+    def __init__(self, code: int, func: str, msg: str):
+        super().__init__(f"{func} -> {ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+_DP = ctypes.POINTER(ctypes.c_double)
+_VP = ctypes.c_void_p
+
+
+def lib():
+    """Load liblbm3.so from the package directory (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1808_08555_amd.build` (no fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(lbm3_params)
+        H = ctypes.c_void_p
+        I = ctypes.c_int
+        protos = {
+            "lbm3_create": (I, [P, _VP, ctypes.POINTER(H)]),
+            "lbm3_init_fields": (I, [H, _DP, _DP]),
+            "lbm3_set_state": (I, [H, _DP]),
+            "lbm3_step": (I, [H, ctypes.c_int64]),
+            "lbm3_observables": (I, [H, ctypes.POINTER(lbm3_obs), _DP, _DP]),
+            "lbm3_destroy": (I, [H]),
+            "lbm3_last_error": (ctypes.c_char_p, []),
+            "lbm3_derived": (I, [P, _DP, _DP, _DP]),
+            "lbm3_set_tile": (I, [H, ctypes.c_int32, ctypes.c_int32]),
+            "lbm3_get_tile": (I, [H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+            "lbm3_state_buffer": (I, [H, ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int64)]),
+            "lbm3_batch_create": (I, [P, ctypes.c_int32, _VP, ctypes.POINTER(H)]),
+            "lbm3_batch_init_fields": (I, [H, ctypes.c_int32, _DP, _DP]),
+            "lbm3_batch_step": (I, [H, ctypes.c_int64]),
+            "lbm3_batch_observables": (I, [H, ctypes.c_int32, ctypes.POINTER(lbm3_obs), _DP]),
+            "lbm3_batch_set_tile": (I, [H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+            "lbm3_batch_destroy": (I, [H]),
+            "lbm3_adjoint_record": (I, [H, ctypes.c_int64, ctypes.c_int32]),
+            "lbm3_adjoint": (I, [H, _DP, _DP, _DP]),
+            "lbm3_device_copy": (I, [_VP, _VP, ctypes.c_int64, _VP]),
+        }
+        for name, (res, args) in protos.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def lbm3_last_error() -> str:
+    return lib().lbm3_last_error().decode()
+
+
+def _check(rc: int, func: str):
+    if rc != LBM3_OK:
+        raise Lbm3Error(rc, func, lbm3_last_error())
+
+
+def _dptr(a):
+    if a is None:
+        return None
+    assert isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_DP)
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream: HIP stream under ROCm
+
+
+def make_params(nx: int, ny: int, sigma=(0.01, 0.01, 0.01), tau=(1.0, 1.0, 1.0),
+                rho0=(1.0, 1.0, 1.0), beta0: float = 0.7, precision="fp64",
+                boundary: int = LBM3_PERIODIC, wall_wettability=(0.0, 0.0, 0.0)) -> lbm3_params:
+    p = lbm3_params()
+    p.nx, p.ny = int(nx), int(ny)
+    for a in range(3):
+        p.rho0[a] = float(rho0[a])
+        p.sigma[a] = float(sigma[a])
+        p.tau[a] = float(tau[a])
+        p.wall_wettability[a] = float(wall_wettability[a])
+    p.beta0 = float(beta0)
+    p.boundary = int(boundary)
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return p
+
+
+# ----------------------------------------------------------------- plain lattice
+def lbm3_create(params: lbm3_params, stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().lbm3_create(ctypes.byref(params), _stream_handle(stream), ctypes.byref(h)),
+           "lbm3_create")
+    return h
+
+
+def lbm3_init_fields(h, rho: np.ndarray, u: np.ndarray | None = None):
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    u = None if u is None else np.ascontiguousarray(u, dtype=np.float64)
+    _check(lib().lbm3_init_fields(h, _dptr(rho), _dptr(u)), "lbm3_init_fields")
+
+
+def lbm3_set_state(h, f: np.ndarray):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    _check(lib().lbm3_set_state(h, _dptr(f)), "lbm3_set_state")
+
+
+def lbm3_step(h, n: int):
+    _check(lib().lbm3_step(h, int(n)), "lbm3_step")
+
+
+def _obs_dict(o: lbm3_obs) -> dict:
+    return {"step": int(o.step), "mass": np.array(o.mass[:]), "momentum": np.array(o.momentum[:]),
+            "kinetic_energy": float(o.kinetic_energy), "u_max": float(o.u_max),
+            "nonfinite": int(o.nonfinite)}
+
+
+def lbm3_observables(h, nx: int, ny: int, want_rho: bool = False, want_f: bool = False,
+                     raise_nonfinite: bool = True):
+    """Returns (observables dict, rho[3,ny,nx] or None, f[3,9,ny,nx] or None)."""
+    o = lbm3_obs()
+    rho = np.empty((3, ny, nx)) if want_rho else None
+    f = np.empty((3, 9, ny, nx)) if want_f else None
+    rc = lib().lbm3_observables(h, ctypes.byref(o), _dptr(rho), _dptr(f))
+    if rc != LBM3_OK and not (rc == LBM3_ENONFINITE and not raise_nonfinite):
+        _check(rc, "lbm3_observables")
+    return _obs_dict(o), rho, f
+
+
+def lbm3_destroy(h):
+    if h is not None:
+        _check(lib().lbm3_destroy(h), "lbm3_destroy")
+
+
+def lbm3_derived(params: lbm3_params):
+    X = (ctypes.c_double * 3)()
+    g = (ctypes.c_double * 3)()
+    nu = (ctypes.c_double * 3)()
+    _check(lib().lbm3_derived(ctypes.byref(params), X, g, nu), "lbm3_derived")
+    return np.array(X[:]), np.array(g[:]), np.array(nu[:])
+
+
+def lbm3_set_tile(h, threads: int, rows: int):
+    _check(lib().lbm3_set_tile(h, int(threads), int(rows)), "lbm3_set_tile")
+
+
+def lbm3_get_tile(h):
+    t = ctypes.c_int32()
+    r = ctypes.c_int32()
+    _check(lib().lbm3_get_tile(h, ctypes.byref(t), ctypes.byref(r)), "lbm3_get_tile")
+    return t.value, r.value
+
+
+def lbm3_state_buffer(h):
+    p = ctypes.c_void_p()
+    eb = ctypes.c_int32()
+    pl = ctypes.c_int64()
+    _check(lib().lbm3_state_buffer(h, ctypes.byref(p), ctypes.byref(eb), ctypes.byref(pl)),
+           "lbm3_state_buffer")
+    return p.value, eb.value, pl.value
+
+
+def lbm3_device_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream=None):
+    _check(lib().lbm3_device_copy(dst_ptr, src_ptr, int(nbytes), _stream_handle(stream)),
+           "lbm3_device_copy")
+
+
+# ----------------------------------------------------------------- batched form
+def lbm3_batch_create(params_list, stream=None):
+    arr = (lbm3_params * len(params_list))(*params_list)
+    h = ctypes.c_void_p()
+    _check(lib().lbm3_batch_create(arr, len(params_list), _stream_handle(stream), ctypes.byref(h)),
+           "lbm3_batch_create")
+    return h
+
+
+def lbm3_batch_init_fields(b, idx: int, rho: np.ndarray, u: np.ndarray | None = None):
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    u = None if u is None else np.ascontiguousarray(u, dtype=np.float64)
+    _check(lib().lbm3_batch_init_fields(b, int(idx), _dptr(rho), _dptr(u)), "lbm3_batch_init_fields")
+
+
+def lbm3_batch_step(b, n: int):
+    _check(lib().lbm3_batch_step(b, int(n)), "lbm3_batch_step")
+
+
+def lbm3_batch_observables(b, idx: int, nx: int, ny: int, want_rho: bool = False):
+    o = lbm3_obs()
+    rho = np.empty((3, ny, nx)) if want_rho else None
+    _check(lib().lbm3_batch_observables(b, int(idx), ctypes.byref(o), _dptr(rho)),
+           "lbm3_batch_observables")
+    return _obs_dict(o), rho
+
+
+def lbm3_batch_set_tile(b, side: int, threads: int, rows: int):
+    _check(lib().lbm3_batch_set_tile(b, int(side), int(threads), int(rows)), "lbm3_batch_set_tile")
+
+
+def lbm3_batch_destroy(b):
+    if b is not None:
+        _check(lib().lbm3_batch_destroy(b), "lbm3_batch_destroy")
+
+
+# ----------------------------------------------------------------- adjoint
+def lbm3_adjoint_record(h, nsteps: int, ckpt_every: int):
+    _check(lib().lbm3_adjoint_record(h, int(nsteps), int(ckpt_every)), "lbm3_adjoint_record")
+
+
+def lbm3_adjoint(h, drho1_T: np.ndarray, nx: int, ny: int):
+    """Returns (dL/dsigma[3], dL/drho0[3, ny, nx])."""
+    g = np.ascontiguousarray(drho1_T, dtype=np.float64)
+    assert g.shape == (ny, nx)
+    ds = np.zeros(3)
+    dr = np.zeros((3, ny, nx))
+    _check(lib().lbm3_adjoint(h, _dptr(g), _dptr(ds), _dptr(dr)), "lbm3_adjoint")
+    return ds, dr
+
+
+# ----------------------------------------------------------------- convenience
+@dataclass
+class Lattice:
+    """Owning wrapper around one lbm3 handle."""
+    nx: int
+    ny: int
+    sigma: tuple = (0.01, 0.01, 0.01)
+    tau: tuple = (1.0, 1.0, 1.0)
+    rho0: tuple = (1.0, 1.0, 1.0)
+    beta0: float = 0.7
+    precision: str = "fp64"
+    stream: object = None
+
+    def __post_init__(self):
+        self.params = make_params(self.nx, self.ny, self.sigma, self.tau, self.rho0, self.beta0,
+                                  self.precision)
+        self.h = lbm3_create(self.params, self.stream)
+
+    def init(self, rho, u=None):
+        lbm3_init_fields(self.h, rho, u)
+        return self
+
+    def set_state(self, f):
+        lbm3_set_state(self.h, f)
+        return self
+
+    def step(self, n: int = 1):
+        lbm3_step(self.h, n)
+        return self
+
+    def observables(self, want_rho=False, want_f=False, raise_nonfinite=True):
+        return lbm3_observables(self.h, self.nx, self.ny, want_rho, want_f, raise_nonfinite)
+
+    def state(self) -> np.ndarray:
+        return self.observables(want_f=True)[2]
+
+    def densities(self) -> np.ndarray:
+        return self.observables(want_rho=True)[1]
+
+    def set_tile(self, threads: int, rows: int):
+        lbm3_set_tile(self.h, threads, rows)
+        return self
+
+    def tile(self):
+        return lbm3_get_tile(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            lbm3_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -12,3 +12,33 @@ if HERE not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP C-ABI)")
     config.addinivalue_line("markers", "slow: longer CPU test")
+
+
+_GPU = None
+
+
+def gpu_available() -> bool:
+    global _GPU
+    if _GPU is None:
+        try:
+            import torch
+            _GPU = torch.cuda.device_count() > 0
+        except Exception:
+            _GPU = False
+    return _GPU
+
+
+def pytest_collection_modifyitems(config, items):
+    import pytest
+    if gpu_available():
+        return
+    skip = pytest.mark.skip(reason="no GPU in this environment")
+    for item in items:
+        if "gpu" in item.keywords:
+            item.add_marker(skip)
+
+
+def pytest_runtest_setup(item):
+    # name the case before any GPU work starts, so a failing run still says which one
+    if "gpu" in item.keywords:
+        print(f"\n[gpu-test] {item.nodeid}", flush=True)
