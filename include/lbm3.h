@@ -122,16 +122,20 @@ const char *lbm3_last_error(void);
 int lbm3_derived(const lbm3_params *p, double X[3], double g[3], double nu[3]);
 
 /* Launch shape of the fused step: threads per workgroup (64, 128, 256 or 512;
- * each workgroup owns a strip of threads-4 columns) and rows marched per
- * workgroup (>= 1).  Results do not depend on the shape (bitwise). */
+ * each workgroup owns a strip of at most threads-4 columns) and rows marched
+ * per workgroup (>= 1; 0 = chosen so that the number of workgroups fits the
+ * device's resident slots).  Results do not depend on the shape (bitwise).
+ * get_tile returns the rows actually used. */
 int lbm3_set_tile(lbm3_t *h, int32_t threads, int32_t rows);
 int lbm3_get_tile(const lbm3_t *h, int32_t *threads, int32_t *rows);
 
 /* Device pointer of the buffer that holds the current state (populations after
- * collision and recolouring, before streaming: plane (k*9+i) at element offset
- * (k*9+i)*plane_stride, row pitch nx), its element size in bytes and the plane
- * stride in elements.  For measurement tools; the layout is not a stable API. */
-int lbm3_state_buffer(const lbm3_t *h, void **dev_ptr, int32_t *elem_bytes, int64_t *plane_stride);
+ * collision and recolouring, before streaming), its element size in bytes, and
+ * its strides in elements: population q = k*9+i of node (x, y) is element
+ * q*plane_stride + y*row_pitch + x.  For measurement tools; the layout is not a
+ * stable API. */
+int lbm3_state_buffer(const lbm3_t *h, void **dev_ptr, int32_t *elem_bytes, int64_t *plane_stride,
+                      int64_t *row_pitch);
 
 /* ---- batched form: many independent lattices advanced together ---------------
  * count instances with parameters p[0..count-1] (all the same precision; sizes

@@ -260,17 +260,23 @@ void oracle_stress_node(const oracle_problem *p, const double *rho_k, const doub
 /* ------------------------------------------------------------------------ */
 
 /* Isotropic difference, Eq. (12): d_alpha phi(x) = (1/c_s^2) sum_i w_i phi(x + e_i) e_{i alpha},
- * periodic in x and y. */
+ * periodic in x and y.  Reading: the sum is taken over the four pairs of opposite
+ * directions (i, -i), i = 1, 2, 5, 6, as w_i e_{i alpha} [phi(x + e_i) - phi(x - e_i)]
+ * (algebraically the same sum, since w_{-i} = w_i and e_{-i} = -e_i); data that are
+ * mirror-symmetric about x then give an exactly zero derivative. */
 void oracle_gradient(int32_t nx, int32_t ny, const double *phi, double *dx, double *dy)
 {
+    static const int PAIR_DIR[4] = {1, 2, 5, 6};
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             double sx = 0.0, sy = 0.0;
-            for (int i = 0; i < 9; ++i) {
-                double v = phi[(size_t)wrap(y + EY[i], ny) * nx + wrap(x + EX[i], nx)];
-                sx += W[i] * v * EX[i];
-                sy += W[i] * v * EY[i];
+            for (int q = 0; q < 4; ++q) {
+                int i = PAIR_DIR[q];
+                double fwd = phi[(size_t)wrap(y + EY[i], ny) * nx + wrap(x + EX[i], nx)];
+                double bwd = phi[(size_t)wrap(y - EY[i], ny) * nx + wrap(x - EX[i], nx)];
+                sx += W[i] * EX[i] * (fwd - bwd);
+                sy += W[i] * EY[i] * (fwd - bwd);
             }
             dx[(size_t)y * nx + x] = INV_CS2 * sx;
             dy[(size_t)y * nx + x] = INV_CS2 * sy;

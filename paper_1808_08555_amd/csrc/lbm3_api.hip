@@ -122,8 +122,21 @@ void derive(const lbm3_params* p, KParams* kp, double X[3], double g[3], double 
         std::memset(kp, 0, sizeof *kp);
         kp->nx = p->nx;
         kp->ny = p->ny;
+#ifndef LBM3_ROW_INTERLEAVE
+#define LBM3_ROW_INTERLEAVE 1
+#endif
+#if LBM3_ROW_INTERLEAVE
+        // row y of all 27 planes in one contiguous block: the rows a workgroup reads
+        // together share DRAM pages
+        kp->plane = ((int64_t)p->nx + 63) / 64 * 64;
+        kp->pitch = 27 * kp->plane;
+        kp->span = kp->pitch * p->ny;
+#else
         const int64_t n = (int64_t)p->nx * p->ny;
-        kp->plane = (n + 255) / 256 * 256;  // planes start on 1 KiB (FP32) / 2 KiB (FP64) boundaries
+        kp->plane = (n + 255) / 256 * 256;
+        kp->pitch = p->nx;
+        kp->span = 27 * kp->plane;
+#endif
         for (int q = 0; q < 3; ++q) {
             kp->sigma[q] = p->sigma[q];
             kp->g[q] = gl[q];
@@ -142,12 +155,8 @@ Prec prec_of(int precision)
 
 void default_tile(const KParams& kp, int* threads, int* rows)
 {
-    const int t = kp.nx >= 512 ? 256 : (kp.nx >= 124 ? 128 : 64);
-    const int nstrips = (kp.nx + t - 5) / (t - 4);
-    int r = (int)(((int64_t)kp.ny * nstrips + 1023) / 1024);
-    r = r < 16 ? 16 : (r > 64 ? 64 : r);
-    *threads = t;
-    *rows = r;
+    *threads = kp.nx >= 2000 ? 512 : (kp.nx >= 500 ? 256 : (kp.nx >= 124 ? 128 : 64));
+    *rows = 0;
 }
 
 int check_rho_fields(const double* rho, const double* u, int64_t n)
@@ -177,6 +186,33 @@ int check_rho_fields(const double* rho, const double* u, int64_t n)
                     return LBM3_EINVAL;
                 }
     }
+    return LBM3_OK;
+}
+
+// Builds the tile list for the handle's launch shape and uploads it with the one-entry
+// instance table.
+int upload_plan(lbm3* h)
+{
+    int rows = h->rows_request;
+    const int eb = (int)elem_bytes(h->prec);
+    if (rows <= 0)
+        rows = auto_rows(h->kp.nx, h->kp.ny, h->threads, device_slots(h->prec, h->threads), eb);
+    std::vector<Tile> L;
+    plan_lattice(0, h->kp.nx, h->kp.ny, h->threads, rows, eb, L);
+    std::vector<Tile> T = xcd_order(L, 8);
+    (void)hipStreamSynchronize(h->stream);
+    if (h->dtiles) (void)hipFree(h->dtiles);
+    h->dtiles = nullptr;
+    hipError_t e = hipMalloc((void**)&h->dtiles, T.size() * sizeof(Tile));
+    if (e == hipSuccess && !h->dinst) e = hipMalloc((void**)&h->dinst, sizeof(Instance));
+    Instance I{};
+    I.kp = h->kp;
+    I.offset = 0;
+    if (e == hipSuccess) e = hipMemcpy(h->dtiles, T.data(), T.size() * sizeof(Tile), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->dinst, &I, sizeof I, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "tile plan upload");
+    h->ntiles = (int)T.size();
+    h->rows = rows;
     return LBM3_OK;
 }
 
@@ -250,7 +286,7 @@ int lbm3_create(const lbm3_params* p, void* hip_stream, lbm3_t** out)
         delete h;
         return hip_fail(e, "hipGetDevice");
     }
-    const size_t bytes = (size_t)27 * h->kp.plane * elem_bytes(h->prec);
+    const size_t bytes = (size_t)h->kp.span * elem_bytes(h->prec);
     for (int b = 0; b < 2; ++b) {
         e = hipMalloc(&h->buf[b], bytes);
         if (e != hipSuccess) {
@@ -263,6 +299,11 @@ int lbm3_create(const lbm3_params* p, void* hip_stream, lbm3_t** out)
     if (e == hipSuccess) e = hipHostMalloc((void**)&h->obs_host, kObsFields * sizeof(double));
     if (e != hipSuccess) {
         rc = hip_fail(e, "allocation of observables buffers");
+        lbm3_destroy(h);
+        return rc;
+    }
+    rc = upload_plan(h);
+    if (rc) {
         lbm3_destroy(h);
         return rc;
     }
@@ -339,8 +380,8 @@ int lbm3_step(lbm3_t* h, int64_t n)
         return LBM3_ESTATE;
     }
     for (int64_t s = 0; s < n; ++s) {
-        hipError_t e = launch_step(h->prec, h->buf[h->cur], h->buf[h->cur ^ 1], h->kp, h->threads,
-                                   h->rows, h->stream);
+        hipError_t e = launch_tiles(h->prec, h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst, h->dtiles,
+                                    h->ntiles, h->threads, h->step, h->stream);
         if (e != hipSuccess) return hip_fail(e, "step launch");
         h->cur ^= 1;
         h->step += 1;
@@ -360,13 +401,13 @@ int lbm3_observables(lbm3_t* h, lbm3_obs* out, double* rho_out, double* f_out)
         return LBM3_ESTATE;
     }
     const int64_t n = (int64_t)h->kp.nx * h->kp.ny;
-    int rc = ensure_partials(h, step_blocks(h->kp, h->threads, h->rows));
+    int rc = ensure_partials(h, h->ntiles);
     if (!rc && (rho_out || f_out)) rc = ensure_staging(h, (size_t)27 * n);
     if (rc) return rc;
-    int nb = 0;
-    hipError_t e = launch_observe(h->prec, h->buf[h->cur], h->kp, h->threads, h->rows,
-                                  h->partials, &nb, rho_out ? h->staging : nullptr, h->stream);
-    if (e == hipSuccess) e = launch_reduce_obs(h->partials, nb, h->obs_dev, h->stream);
+    hipError_t e = launch_observe_tiles(h->prec, h->buf[h->cur], h->dinst, h->dtiles, h->ntiles,
+                                        h->threads, h->partials, rho_out ? h->staging : nullptr,
+                                        h->stream);
+    if (e == hipSuccess) e = launch_reduce_obs(h->partials, h->ntiles, h->obs_dev, h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->obs_host, h->obs_dev, kObsFields * sizeof(double),
                            hipMemcpyDeviceToHost, h->stream);
@@ -408,6 +449,8 @@ int lbm3_destroy(lbm3_t* h)
     if (h->partials) (void)hipFree(h->partials);
     if (h->obs_dev) (void)hipFree(h->obs_dev);
     if (h->obs_host) (void)hipHostFree(h->obs_host);
+    if (h->dtiles) (void)hipFree(h->dtiles);
+    if (h->dinst) (void)hipFree(h->dinst);
     adjoint_release(h);
     delete h;
     return LBM3_OK;
@@ -419,13 +462,20 @@ int lbm3_set_tile(lbm3_t* h, int32_t threads, int32_t rows)
         set_error("handle is NULL");
         return LBM3_EINVAL;
     }
-    if (!(threads == 64 || threads == 128 || threads == 256) || rows < 1) {
-        set_error("threads must be 64, 128 or 256 and rows >= 1");
+    if (!(threads == 64 || threads == 128 || threads == 256 || threads == 512) || rows < 0) {
+        set_error("threads must be 64, 128, 256 or 512 and rows >= 0 (0 = automatic)");
         return LBM3_EINVAL;
     }
+    const int old_t = h->threads, old_r = h->rows_request;
     h->threads = threads;
-    h->rows = rows;
-    return LBM3_OK;
+    h->rows_request = rows;
+    int rc = upload_plan(h);
+    if (rc) {
+        h->threads = old_t;
+        h->rows_request = old_r;
+        (void)upload_plan(h);
+    }
+    return rc;
 }
 
 int lbm3_get_tile(const lbm3_t* h, int32_t* threads, int32_t* rows)
@@ -439,7 +489,7 @@ int lbm3_get_tile(const lbm3_t* h, int32_t* threads, int32_t* rows)
     return LBM3_OK;
 }
 
-int lbm3_state_buffer(const lbm3_t* h, void** dev_ptr, int32_t* eb, int64_t* plane)
+int lbm3_state_buffer(const lbm3_t* h, void** dev_ptr, int32_t* eb, int64_t* plane, int64_t* pitch)
 {
     if (!h) {
         set_error("handle is NULL");
@@ -448,6 +498,7 @@ int lbm3_state_buffer(const lbm3_t* h, void** dev_ptr, int32_t* eb, int64_t* pla
     if (dev_ptr) *dev_ptr = h->buf[h->cur];
     if (eb) *eb = (int32_t)elem_bytes(h->prec);
     if (plane) *plane = h->kp.plane;
+    if (pitch) *pitch = h->kp.pitch;
     return LBM3_OK;
 }
 

@@ -16,7 +16,11 @@ struct lbm3 {
     int64_t step = 0;
     bool ready = false;
     bool init_at_rest = false;          // state came from init_fields with u == NULL
-    int threads = 256, rows = 64;
+    int threads = 256, rows = 64;       // launch shape: threads per workgroup, rows per segment
+    int rows_request = 0;               // rows asked for (0 = fitted to the resident slots)
+    tcg::Instance* dinst = nullptr;     // device copy of the one-instance table
+    tcg::Tile* dtiles = nullptr;        // device tile list (XCD-aware order)
+    int ntiles = 0;
     double* staging = nullptr;          // device FP64 staging for host transfers
     size_t staging_cap = 0;
     double* partials = nullptr;         // per-workgroup observables partials
@@ -38,5 +42,6 @@ const char* last_error();
 Prec prec_of(int precision);
 void default_tile(const KParams& kp, int* threads, int* rows);
 int check_rho_fields(const double* rho, const double* u, int64_t n);
+int upload_plan(lbm3* h);
 void adjoint_release(lbm3* h);
 }  // namespace tcg

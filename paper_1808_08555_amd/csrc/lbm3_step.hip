@@ -16,8 +16,10 @@
 //             (rho_k rho_l / rho) n_kl with beta_kl of Eqs. (19)-(20)       (Eq. 13)
 //   store:    buffer'_{i,k}(x) = f_ddag_{i,k}(x)
 //
-// Layout: 27 planes (k*9 + i) of nx*ny values, x fastest (structure of arrays), so a
-// wavefront's 64 lanes read and write 64 consecutive values of one plane row.
+// Layout: population q = k*9 + i of node (x, y) at element q*plane + y*pitch + x, x fastest,
+// so a wavefront's 64 lanes read and write 64 consecutive values of one plane row.  The
+// host chooses the strides (see derive()): rows of the 27 planes interleaved
+// (plane = padded nx, pitch = 27 plane), or whole planes one after another.
 //
 // Work decomposition (y-marching strips).  A workgroup of NT threads owns a strip of
 // NT-4 output columns and a run of `rows` output rows.  Thread t sits on column
@@ -31,16 +33,62 @@
 // read) and written once; densities, gradients and stress never leave the chip.
 #include "lbm3_internal.h"
 
+#ifndef LBM3_NT_STORE
+#define LBM3_NT_STORE 0
+#endif
+
 namespace tcg {
 namespace {
 
 constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
+// D2Q9 weights.  In FP64 the rest weight is taken as 1 - 4 w_1 - 4 w_5, the double one
+// ulp above the nearest to 4/9, so that the nine weights sum to exactly 1: with the nearest
+// doubles the sum is 1 - 5.55e-17 and every collision would scale the mass by that much.
 template <typename C>
 __device__ __forceinline__ constexpr C wgt(int i)
 {
-    return i == 0 ? C(4.0 / 9.0) : (i < 5 ? C(1.0 / 9.0) : C(1.0 / 36.0));
+    if constexpr (sizeof(C) == 8)
+        return i == 0 ? 1.0 - 4.0 * (1.0 / 9.0) - 4.0 * (1.0 / 36.0)
+                      : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    else
+        return i == 0 ? C(4.0 / 9.0) : (i < 5 ? C(1.0 / 9.0) : C(1.0 / 36.0));
+}
+
+// 32-bit integer mixer ("lowbias32", from Wellons' hash-prospector search): a bijection with
+// low output bias, used as a counter-based generator keyed by (step, node, population).
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+// FP64 -> FP32 with stochastic rounding: v plus a uniform offset in [-ulp/2, ulp/2) of the
+// float grid at v, then round to nearest, so the rounding error has zero mean.  Round to
+// nearest would lose the sub-ulp per-step changes of the near-uniform bulk with a sign that
+// is the same at many nodes, which shows up as a steady drift of each fluid's mass.
+__device__ __forceinline__ float round_stochastic(double v, uint32_t bits)
+{
+    const float t = (float)v;
+    const uint32_t e = __float_as_uint(t) & 0x7f800000u;
+    const float ulp = e > (23u << 23) ? __uint_as_float(e - (23u << 23)) : 0.0f;
+    const double r = ((double)(bits >> 8) * (1.0 / 16777216.0) - 0.5) * (double)ulp;
+    return (float)(v + r);
+}
+
+// Store of one population in the storage type S from the compute type C.
+template <typename S, typename C>
+__device__ __forceinline__ S to_storage(C v, uint32_t key)
+{
+    if constexpr (sizeof(S) == 4 && sizeof(C) == 8)
+        return round_stochastic(v, mix32(key));
+    else
+        return S(v);
 }
 
 __device__ __forceinline__ int wrapi(int a, int n)
@@ -75,7 +123,11 @@ __device__ __forceinline__ void st_at(T* base, unsigned byte_off, T v)
     typedef __attribute__((address_space(1))) char gchar;
     typedef __attribute__((address_space(1))) T gT;
     gchar* b = (gchar*)uniform_u64(reinterpret_cast<uint64_t>(base));
+#if LBM3_NT_STORE
+    __builtin_nontemporal_store(v, (gT*)(b + byte_off));
+#else
     *(gT*)(b + byte_off) = v;
+#endif
 }
 
 // Isotropic difference of Eq. (12), 3 sum_i w_i phi(x + e_i) e_i, written as weighted
@@ -163,19 +215,22 @@ __device__ __forceinline__ void collide_recolour(const C (&f)[9], const C (&rk)[
     }
 }
 
-// The y-marching body shared by the plain, observing and batched kernels.
+// The y-marching body shared by the stepping and observing kernels.  The workgroup owns
+// output columns [x0, x0 + cols) (cols <= NT - 4) and output rows [y0, y0 + rows).
 // Loop-carried per-thread state at the top of iteration j (input row j):
+//   vn     = the 27 raw populations of row j, loaded one iteration ahead so that the loads
+//            are in flight while the previous row's stages 2 and 3 compute;
 //   fA, rA = totals and densities of row j-1;  fB, rB = those of row j-2;
-//   nB = pair normals of row j-2 (formed by stage 2 of the previous iteration).
+//   nB     = pair normals of row j-2 (formed by stage 2 of the previous iteration).
 // LDS rings are indexed by input row mod 3.
 template <typename S, typename C, int NT, bool OBS>
 __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__ fout,
-                                      const KParams& kp, int x0, int y0, int rows,
+                                      const KParams& kp, int x0, int y0, int rows, int cols,
                                       C (*cring)[3][NT], C (*tring)[3][NT], double (&acc)[kObsFields],
-                                      double* __restrict__ rho_out)
+                                      double* __restrict__ rho_out, uint32_t salt)
 {
     const int nx = kp.nx, ny = kp.ny;
-    const int64_t plane = kp.plane;
+    const int64_t plane = kp.plane, pitch = kp.pitch;
     const int t = threadIdx.x;
     const int xr = x0 - 2 + t;
     const int x = wrapi(xr, nx);
@@ -184,36 +239,46 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
                               (unsigned)x * (unsigned)sizeof(S),
                               (unsigned)wrapi(x - 1, nx) * (unsigned)sizeof(S)};
     const unsigned xoff = (unsigned)x * (unsigned)sizeof(S);
-    const bool in2 = (t >= 1) && (t <= NT - 2);
-    const bool in3 = (t >= 2) && (t <= NT - 3) && (xr < nx);
+    const bool in1 = t < cols + 4;
+    const bool in2 = (t >= 1) && (t <= cols + 2);
+    const bool in3 = (t >= 2) && (t <= cols + 1);
     const StepConsts<C> K(kp);
 
-    C fA[9], fB[9], rA[3], rB[3], nB[6];
+    auto load_row = [&](int j, C (&v)[27]) {
+        const int r = wrapi(y0 - 2 + j, ny);
+        const int64_t srow[3] = {(int64_t)wrapi(r + 1, ny) * pitch, (int64_t)r * pitch,
+                                 (int64_t)wrapi(r - 1, ny) * pitch};
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                v[k * 9 + i] = C(ld_at(fin + ((int64_t)(k * 9 + i) * plane + srow[EY[i] + 1]),
+                                       scol[EX[i] + 1]));
+    };
+
+    C fA[9], fB[9], rA[3], rB[3], nB[6], vn[27];
 #pragma unroll
     for (int i = 0; i < 9; ++i) fA[i] = fB[i] = C(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) rA[k] = rB[k] = C(1);
 #pragma unroll
     for (int q = 0; q < 6; ++q) nB[q] = C(0);
+#pragma unroll
+    for (int q = 0; q < 27; ++q) vn[q] = C(1);
+    if (in1) load_row(0, vn);
 
     const int J = rows + 4;
     for (int j = 0; j < J; ++j) {
         const int s0 = j % 3;        // slot of row j
         const int s1 = (j + 2) % 3;  // slot of row j-1
         const int s2 = (j + 1) % 3;  // slot of row j-2 (and j-3 + 3)
-        // ---- stage 1: pull row j, totals, densities, concentrations
+        // ---- stage 1: totals, densities, concentrations of row j; prefetch row j+1
         C f0[9], r0[3];
         {
-            const int r = wrapi(y0 - 2 + j, ny);
-            const int64_t srow[3] = {(int64_t)wrapi(r + 1, ny) * nx, (int64_t)r * nx,
-                                     (int64_t)wrapi(r - 1, ny) * nx};
             C v[27];
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
-#pragma unroll
-                for (int i = 0; i < 9; ++i)
-                    v[k * 9 + i] = C(ld_at(fin + ((int64_t)(k * 9 + i) * plane + srow[EY[i] + 1]),
-                                           scol[EX[i] + 1]));
+            for (int q = 0; q < 27; ++q) v[q] = vn[q];
+            if (in1 && j + 1 < J) load_row(j + 1, vn);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 C sum = C(0);
@@ -246,9 +311,15 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
 #pragma unroll
             for (int p = 0; p < 3; ++p) {
                 const int k = PK[p], l = PL[p];
-                const C Gx = cc[l] * gx[k] - cc[k] * gx[l];
-                const C Gy = cc[l] * gy[k] - cc[k] * gy[l];
-                const C mag = sqrt(Gx * Gx + Gy * Gy);
+                C Gx, Gy, mag;
+                {
+                    // The two products of G nearly cancel where a fluid is present only as a
+                    // trace; unfused, their rounding matches the plain IEEE evaluation.
+#pragma clang fp contract(off)
+                    Gx = cc[l] * gx[k] - cc[k] * gx[l];
+                    Gy = cc[l] * gy[k] - cc[k] * gy[l];
+                    mag = sqrt(Gx * Gx + Gy * Gy);
+                }
                 if (mag > K.guard) {
                     const C inv = C(1) / mag;
                     nA[2 * p] = Gx * inv;
@@ -283,9 +354,11 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
             C out[27], ux, uy, mxh, myh;
             collide_recolour<C>(fB, rB, nB, Fx, Fy, K, out, ux, uy, mxh, myh);
             if constexpr (!OBS) {
-                const int64_t orow = (int64_t)yo * nx;
+                const int64_t orow = (int64_t)yo * pitch;
+                const uint32_t key = ((uint32_t)yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt;
 #pragma unroll
-                for (int q = 0; q < 27; ++q) st_at(fout + ((int64_t)q * plane + orow), xoff, S(out[q]));
+                for (int q = 0; q < 27; ++q)
+                    st_at(fout + ((int64_t)q * plane + orow), xoff, to_storage<S, C>(out[q], key + (uint32_t)q));
             } else {
                 const double rho = double(rB[0]) + double(rB[1]) + double(rB[2]);
                 acc[0] += double(rB[0]);
@@ -326,20 +399,6 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
     }
 }
 
-template <typename S, typename C, int NT>
-__global__ __launch_bounds__(NT) void k_step(const S* __restrict__ fin, S* __restrict__ fout,
-                                             KParams kp, int rows_per, int nstrips)
-{
-    __shared__ C cring[3][3][NT];
-    __shared__ C tring[3][3][NT];
-    const int b = blockIdx.x;
-    const int sx = b % nstrips, sy = b / nstrips;
-    const int x0 = sx * (NT - 4), y0 = sy * rows_per;
-    const int rows = min(rows_per, kp.ny - y0);
-    double acc[kObsFields];
-    march<S, C, NT, false>(fin, fout, kp, x0, y0, rows, cring, tring, acc, nullptr);
-}
-
 template <int NT>
 __device__ void block_reduce_obs(double (&acc)[kObsFields], double* __restrict__ partials)
 {
@@ -365,21 +424,26 @@ __device__ void block_reduce_obs(double (&acc)[kObsFields], double* __restrict__
     if (t < kObsFields) partials[(int64_t)blockIdx.x * kObsFields + t] = red[t][0];
 }
 
-template <typename S, typename C, int NT>
-__global__ __launch_bounds__(NT) void k_observe(const S* __restrict__ fin, KParams kp,
-                                                int rows_per, int nstrips,
-                                                double* __restrict__ partials,
-                                                double* __restrict__ rho_out)
+// One fused time step over a list of tiles: workgroup b takes tiles[b] of instance
+// tiles[b].inst (the plain lattice is a list with one instance).  With OBS the workgroup
+// instead accumulates the observables of its output nodes into partials[b].
+template <typename S, typename C, int NT, bool OBS>
+__global__ __launch_bounds__(NT) void k_tiles(const S* __restrict__ fin, S* __restrict__ fout,
+                                              const Instance* __restrict__ inst,
+                                              const Tile* __restrict__ tiles, uint32_t salt,
+                                              double* __restrict__ partials,
+                                              double* __restrict__ rho_out)
 {
     __shared__ C cring[3][3][NT];
     __shared__ C tring[3][3][NT];
-    const int b = blockIdx.x;
-    const int sx = b % nstrips, sy = b / nstrips;
-    const int x0 = sx * (NT - 4), y0 = sy * rows_per;
-    const int rows = min(rows_per, kp.ny - y0);
+    const Tile tl = tiles[blockIdx.x];
+    const KParams kp = inst[tl.inst].kp;
+    const int64_t off = inst[tl.inst].offset;
     double acc[kObsFields] = {0, 0, 0, 0, 0, 0, 0, 0};
-    march<S, C, NT, true>(fin, nullptr, kp, x0, y0, rows, cring, tring, acc, rho_out);
-    block_reduce_obs<NT>(acc, partials);
+    march<S, C, NT, OBS>(fin + off, OBS ? nullptr : fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols,
+                         cring, tring, acc, rho_out,
+                         salt ^ mix32((uint32_t)tl.inst * 0x9E3779B9U + 0x51ed270bU));
+    if constexpr (OBS) block_reduce_obs<NT>(acc, partials);
 }
 
 // Fixed-order second pass over the per-workgroup partials (deterministic).
@@ -419,22 +483,6 @@ __global__ __launch_bounds__(256) void k_reduce_obs(const double* __restrict__ p
     if (t < kObsFields) out[t] = red[t][0];
 }
 
-// Batched form: workgroup b takes tiles[b] of instance tiles[b].inst.
-template <typename S, typename C, int NT>
-__global__ __launch_bounds__(NT) void k_step_batch(const S* __restrict__ fin, S* __restrict__ fout,
-                                                   const Instance* __restrict__ inst,
-                                                   const Tile* __restrict__ tiles)
-{
-    __shared__ C cring[3][3][NT];
-    __shared__ C tring[3][3][NT];
-    const Tile tl = tiles[blockIdx.x];
-    const KParams kp = inst[tl.inst].kp;
-    const int64_t off = inst[tl.inst].offset;
-    double acc[kObsFields];
-    march<S, C, NT, false>(fin + off, fout + off, kp, tl.x0, tl.y0, tl.rows, cring, tring, acc,
-                           nullptr);
-}
-
 // Initial populations: with u == null f_{i,k} = w_i rho_k, else (rho_k/rho) f_eq_i(rho, u);
 // stored so that the next pull reads them back at x (buffer(x - e_i) = f(x)).
 template <typename S, typename C>
@@ -463,7 +511,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho,
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const C v = u ? (rk[k] / r) * feq[i] : wgt<C>(i) * rk[k];
-            const int64_t d = (int64_t)wrapi(y - EY[i], ny) * nx + wrapi(x - EX[i], nx);
+            const int64_t d = (int64_t)wrapi(y - EY[i], ny) * kp.pitch + wrapi(x - EX[i], nx);
             fout[(int64_t)(k * 9 + i) * kp.plane + d] = S(v);
         }
 }
@@ -479,7 +527,7 @@ __global__ __launch_bounds__(256) void k_import(const double* __restrict__ f, S*
 #pragma unroll
     for (int q = 0; q < 27; ++q) {
         const int i = q % 9;
-        const int64_t d = (int64_t)wrapi(y - EY[i], ny) * nx + wrapi(x - EX[i], nx);
+        const int64_t d = (int64_t)wrapi(y - EY[i], ny) * kp.pitch + wrapi(x - EX[i], nx);
         fout[(int64_t)q * kp.plane + d] = S(f[q * N + j]);
     }
 }
@@ -495,7 +543,7 @@ __global__ __launch_bounds__(256) void k_export(const S* __restrict__ fin, doubl
 #pragma unroll
     for (int q = 0; q < 27; ++q) {
         const int i = q % 9;
-        const int64_t s = (int64_t)wrapi(y - EY[i], ny) * nx + wrapi(x - EX[i], nx);
+        const int64_t s = (int64_t)wrapi(y - EY[i], ny) * kp.pitch + wrapi(x - EX[i], nx);
         f[q * N + j] = double(fin[(int64_t)q * kp.plane + s]);
     }
 }
@@ -503,96 +551,105 @@ __global__ __launch_bounds__(256) void k_export(const S* __restrict__ fin, doubl
 __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
                                               int64_t n)
 {
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[i];
 }
 
-template <typename S, typename C, int NT>
-hipError_t do_step(const void* fin, void* fout, const KParams& kp, int rows, hipStream_t st)
+template <typename S, typename C, int NT, bool OBS>
+hipError_t do_tiles(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
+                    int ntiles, uint32_t salt, double* partials, double* rho_out, hipStream_t st)
 {
-    const int nstrips = (kp.nx + NT - 5) / (NT - 4);
-    const int nseg = (kp.ny + rows - 1) / rows;
-    hipLaunchKernelGGL((k_step<S, C, NT>), dim3(nstrips * nseg), dim3(NT), 0, st,
-                       (const S*)fin, (S*)fout, kp, rows, nstrips);
+    hipLaunchKernelGGL((k_tiles<S, C, NT, OBS>), dim3(ntiles), dim3(NT), 0, st, (const S*)fin,
+                       (S*)fout, inst, tiles, salt, partials, rho_out);
     return hipGetLastError();
 }
 
 template <typename S, typename C, int NT>
-hipError_t do_observe(const void* fin, const KParams& kp, int rows, double* partials, int* nb,
-                      double* rho_out, hipStream_t st)
+int occupancy_of()
 {
-    const int nstrips = (kp.nx + NT - 5) / (NT - 4);
-    const int nseg = (kp.ny + rows - 1) / rows;
-    *nb = nstrips * nseg;
-    hipLaunchKernelGGL((k_observe<S, C, NT>), dim3(nstrips * nseg), dim3(NT), 0, st,
-                       (const S*)fin, kp, rows, nstrips, partials, rho_out);
-    return hipGetLastError();
-}
-
-template <typename S, typename C, int NT>
-hipError_t do_step_batch(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
-                         int ntiles, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_step_batch<S, C, NT>), dim3(ntiles), dim3(NT), 0, st, (const S*)fin,
-                       (S*)fout, inst, tiles);
-    return hipGetLastError();
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<S, C, NT, false>, NT, 0) != hipSuccess)
+        return 0;
+    return nb;
 }
 
 }  // namespace
 
 size_t elem_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }
 
-int step_blocks(const KParams& kp, int threads, int rows)
+uint32_t step_salt(int64_t step)
 {
-    const int nstrips = (kp.nx + threads - 5) / (threads - 4);
-    return nstrips * ((kp.ny + rows - 1) / rows);
+    uint32_t x = (uint32_t)step ^ (uint32_t)(step >> 32) * 0x9E3779B9U;
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
 }
 
-#define LBM3_DISPATCH_NT(FN, S, C, ...)                               \
+#define LBM3_DISPATCH_NT(FN, S, C, OBS, ...)                          \
     switch (threads) {                                                \
-        case 64: return FN<S, C, 64>(__VA_ARGS__);                    \
-        case 128: return FN<S, C, 128>(__VA_ARGS__);                  \
-        case 256: return FN<S, C, 256>(__VA_ARGS__);                  \
+        case 64: return FN<S, C, 64, OBS>(__VA_ARGS__);               \
+        case 128: return FN<S, C, 128, OBS>(__VA_ARGS__);             \
+        case 256: return FN<S, C, 256, OBS>(__VA_ARGS__);             \
+        case 512: return FN<S, C, 512, OBS>(__VA_ARGS__);             \
         default: return hipErrorInvalidValue;                         \
     }
 
-hipError_t launch_step(Prec prec, const void* fin, void* fout, const KParams& kp, int threads,
-                       int rows, hipStream_t st)
+hipError_t launch_tiles(Prec prec, const void* fin, void* fout, const Instance* inst,
+                        const Tile* tiles, int ntiles, int threads, int64_t step, hipStream_t st)
 {
+    const uint32_t salt = step_salt(step);
     switch (prec) {
-        case Prec::F64: LBM3_DISPATCH_NT(do_step, double, double, fin, fout, kp, rows, st);
-        case Prec::F32S: LBM3_DISPATCH_NT(do_step, float, double, fin, fout, kp, rows, st);
-        case Prec::F32: LBM3_DISPATCH_NT(do_step, float, float, fin, fout, kp, rows, st);
+        case Prec::F64:
+            LBM3_DISPATCH_NT(do_tiles, double, double, false, fin, fout, inst, tiles, ntiles, salt,
+                             nullptr, nullptr, st);
+        case Prec::F32S:
+            LBM3_DISPATCH_NT(do_tiles, float, double, false, fin, fout, inst, tiles, ntiles, salt,
+                             nullptr, nullptr, st);
+        case Prec::F32:
+            LBM3_DISPATCH_NT(do_tiles, float, float, false, fin, fout, inst, tiles, ntiles, salt,
+                             nullptr, nullptr, st);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_observe(Prec prec, const void* fin, const KParams& kp, int threads, int rows,
-                          double* partials, int* nb, double* rho_out, hipStream_t st)
+hipError_t launch_observe_tiles(Prec prec, const void* fin, const Instance* inst, const Tile* tiles,
+                                int ntiles, int threads, double* partials, double* rho_out,
+                                hipStream_t st)
 {
     switch (prec) {
         case Prec::F64:
-            LBM3_DISPATCH_NT(do_observe, double, double, fin, kp, rows, partials, nb, rho_out, st);
+            LBM3_DISPATCH_NT(do_tiles, double, double, true, fin, nullptr, inst, tiles, ntiles, 0u,
+                             partials, rho_out, st);
         case Prec::F32S:
-            LBM3_DISPATCH_NT(do_observe, float, double, fin, kp, rows, partials, nb, rho_out, st);
+            LBM3_DISPATCH_NT(do_tiles, float, double, true, fin, nullptr, inst, tiles, ntiles, 0u,
+                             partials, rho_out, st);
         case Prec::F32:
-            LBM3_DISPATCH_NT(do_observe, float, float, fin, kp, rows, partials, nb, rho_out, st);
+            LBM3_DISPATCH_NT(do_tiles, float, float, true, fin, nullptr, inst, tiles, ntiles, 0u,
+                             partials, rho_out, st);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_step_batch(Prec prec, const void* fin, void* fout, const Instance* inst,
-                             const Tile* tiles, int ntiles, int threads, hipStream_t st)
+int blocks_per_cu(Prec prec, int threads)
 {
-    switch (prec) {
-        case Prec::F64:
-            LBM3_DISPATCH_NT(do_step_batch, double, double, fin, fout, inst, tiles, ntiles, st);
-        case Prec::F32S:
-            LBM3_DISPATCH_NT(do_step_batch, float, double, fin, fout, inst, tiles, ntiles, st);
-        case Prec::F32:
-            LBM3_DISPATCH_NT(do_step_batch, float, float, fin, fout, inst, tiles, ntiles, st);
+#define LBM3_OCC(S, C)                                         \
+    switch (threads) {                                         \
+        case 64: return occupancy_of<S, C, 64>();              \
+        case 128: return occupancy_of<S, C, 128>();            \
+        case 256: return occupancy_of<S, C, 256>();            \
+        case 512: return occupancy_of<S, C, 512>();            \
+        default: return 0;                                     \
     }
-    return hipErrorInvalidValue;
+    switch (prec) {
+        case Prec::F64: LBM3_OCC(double, double);
+        case Prec::F32S: LBM3_OCC(float, double);
+        case Prec::F32: LBM3_OCC(float, float);
+    }
+#undef LBM3_OCC
+    return 0;
 }
 
 hipError_t launch_reduce_obs(const double* partials, int nblocks, double* out, hipStream_t st)
@@ -646,7 +703,6 @@ hipError_t launch_copy(void* dst, const void* src, int64_t nbytes, hipStream_t s
 {
     const int64_t n = nbytes / 16;
     int64_t blocks = (n + 255) / 256;
-    if (blocks > 256 * 64) blocks = 256 * 64;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const uint4*)src,
                        (uint4*)dst, n);

@@ -14,7 +14,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblbm3.so")
+# the in-tree build; LBM3_LIBRARY may name another build of the same sources
+LIB_PATH = os.environ.get("LBM3_LIBRARY") or os.path.join(_HERE, "liblbm3.so")
 
 LBM3_OK, LBM3_EINVAL, LBM3_ENOMEM, LBM3_EDEVICE, LBM3_EUNSUPPORTED, LBM3_ENONFINITE, \
     LBM3_ESTATE = 0, -1, -2, -3, -4, -5, -6
@@ -77,7 +78,7 @@ def lib():
             "lbm3_set_tile": (I, [H, ctypes.c_int32, ctypes.c_int32]),
             "lbm3_get_tile": (I, [H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
             "lbm3_state_buffer": (I, [H, ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int32),
-                                      ctypes.POINTER(ctypes.c_int64)]),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
             "lbm3_batch_create": (I, [P, ctypes.c_int32, _VP, ctypes.POINTER(H)]),
             "lbm3_batch_init_fields": (I, [H, ctypes.c_int32, _DP, _DP]),
             "lbm3_batch_step": (I, [H, ctypes.c_int64]),
@@ -202,12 +203,14 @@ def lbm3_get_tile(h):
 
 
 def lbm3_state_buffer(h):
+    """(device pointer, element bytes, plane stride, row pitch) of the current state buffer."""
     p = ctypes.c_void_p()
     eb = ctypes.c_int32()
     pl = ctypes.c_int64()
-    _check(lib().lbm3_state_buffer(h, ctypes.byref(p), ctypes.byref(eb), ctypes.byref(pl)),
-           "lbm3_state_buffer")
-    return p.value, eb.value, pl.value
+    pt = ctypes.c_int64()
+    _check(lib().lbm3_state_buffer(h, ctypes.byref(p), ctypes.byref(eb), ctypes.byref(pl),
+                                   ctypes.byref(pt)), "lbm3_state_buffer")
+    return p.value, eb.value, pl.value, pt.value
 
 
 def lbm3_device_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream=None):

@@ -28,7 +28,8 @@ MUTANTS = {
     "recolour_transposed_direction": ("(n[0] * EX[i] + n[1] * EY[i])", "(n[0] * EY[i] + n[1] * EX[i])"),
     "recolour_wrong_colour_share": ("out[k * 9 + i] = c[k] * fdag[i];",
                                     "out[k * 9 + i] = c[(k + 1) % 3] * fdag[i];"),
-    "gradient_transposed": ("sy += W[i] * v * EY[i];", "sy += W[i] * v * EX[i];"),
+    "gradient_transposed": ("sy += W[i] * EY[i] * (fwd - bwd);", "sy += W[i] * EX[i] * (fwd - bwd);"),
+    "gradient_one_sided": ("sx += W[i] * EX[i] * (fwd - bwd);", "sx += W[i] * EX[i] * fwd;"),
     "streaming_backwards": ("size_t d = (size_t)wrap(y + EY[i], ny) * nx + wrap(x + EX[i], nx);",
                             "size_t d = (size_t)wrap(y - EY[i], ny) * nx + wrap(x - EX[i], nx);"),
     "lattice_diagonal_swap": ("static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};",
