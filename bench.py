@@ -106,6 +106,58 @@ def bench_plain(torch, lbm3, w, precision: str, steps: int, warmup: int):
             "gbs": BYTES_PER_LU[precision] * n * steps / t / 1e9, "nonfinite": obs["nonfinite"]}
 
 
+def bench_batched(torch, lbm3, inputs, steps: int):
+    """The 64-instance morphology sweep (sides from {128..512}, FP32) advanced by graph
+    launches; baselines: the plain FP32 step on one square lattice of the same node count,
+    and the same 64 instances stepped with one launch per instance per step."""
+    from paper_1808_08555_amd import autotune
+
+    ws = inputs.morphology_batch()
+    nodes = sum(w.nx * w.ny for w in ws)
+    ps = [lbm3.make_params(w.nx, w.ny, w.sigma, w.tau, precision="fp32") for w in ws]
+    st = torch.cuda.Stream()
+    b = lbm3.lbm3_batch_create(ps, st)
+    for i, w in enumerate(ws):
+        lbm3.lbm3_batch_init_fields(b, i, w.rho)
+    with torch.cuda.stream(st):
+        threads, rows = autotune.tune_batch(b, [w.nx for w in ws], "fp32", steps=20)
+        lbm3.lbm3_batch_step(b, 40)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        lbm3.lbm3_batch_step(b, steps)
+        e.record(st)
+        torch.cuda.synchronize()
+    t = a.elapsed_time(e) / 1e3
+    lbm3.lbm3_batch_destroy(b)
+    res = {"instances": len(ws), "nodes": nodes, "mlups": nodes * steps / t / 1e6,
+           "ms_per_step": t / steps * 1e3, "gbs": 216 * nodes * steps / t / 1e9,
+           "threads": threads, "rows_by_side": {str(k): v for k, v in rows.items()}}
+    side = int(round(nodes ** 0.5))
+    weq = inputs.droplet_tiling(side - side % 256 if side >= 512 else side, cell=256)
+    res["plain_equal_nodes"] = bench_plain(torch, lbm3, weq, "fp32", steps, 20)["mlups"]
+    # one launch per instance per step
+    cur = torch.cuda.current_stream()
+    Ls = [lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, precision="fp32", stream=cur).init(w.rho)
+          for w in ws]
+    seq_steps = max(10, steps // 20)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    a.record(cur)
+    for _ in range(seq_steps):
+        for L in Ls:
+            L.step(1)
+    e.record(cur)
+    torch.cuda.synchronize()
+    ts = a.elapsed_time(e) / 1e3
+    for L in Ls:
+        L.close()
+    res["per_instance_launches"] = nodes * seq_steps / ts / 1e6
+    return res
+
+
 def cpu_baseline(w, steps: int = 2):
     import oracle
 
@@ -150,6 +202,8 @@ def main():
         w2 = inputs.compound_droplet(256, 30.0, 60.0, 0.01, 0.01)
         extra["compound_256_fp64"] = bench_plain(torch, lbm3, w2, "fp64", 2000, 100)
         log(f"compound 256 fp64 {extra['compound_256_fp64']}")
+        batched = bench_batched(torch, lbm3, inputs, 1000)
+        log(f"batched {batched}")
     copy_gbs = copy_bandwidth(torch, lbm3)
     log(f"device copy {copy_gbs:.0f} GB/s")
 
@@ -178,7 +232,19 @@ def main():
     }
     for k, v in extra.items():
         line[k] = {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 4),
-                   "gbs": round(v["gbs"], 1), "tile": v["tile"]}
+                   "gbs": round(v["gbs"], 1), "tile": v["tile"],
+                   "frac_of_peak": round(v["gbs"] / HBM_PEAK_GBS, 4)}
+    if not args.only_plain:
+        line["batched_fp32"] = {
+            "workload": "64 instances, sides {128..512} (SplitMix64 seed 855), two tangent disks "
+                        "of radius side/6, 8x8 grid of tension ratios, FP32, one graph launch "
+                        "per 20 steps",
+            "mlups": round(batched["mlups"], 1), "ms_per_step": round(batched["ms_per_step"], 4),
+            "gbs": round(batched["gbs"], 1), "frac_of_peak": round(batched["gbs"] / HBM_PEAK_GBS, 4),
+            "nodes": batched["nodes"], "threads": batched["threads"],
+            "rows_by_side": batched["rows_by_side"],
+            "baseline_plain_fp32_equal_nodes_mlups": round(batched["plain_equal_nodes"], 1),
+            "baseline_one_launch_per_instance_mlups": round(batched["per_instance_launches"], 1)}
     print(json.dumps(line), flush=True)
 
 

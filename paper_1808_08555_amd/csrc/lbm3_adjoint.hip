@@ -1,7 +1,492 @@
-// Adjoint of the FP64 step (reverse sweep with checkpointed recomputation).
+// Reverse-mode derivative (adjoint) of the FP64 step, with checkpointed recomputation.
+//
+// Notation: the population buffer B holds, at node y, the recoloured populations of y
+// before streaming; the post-streaming populations are f_{i,k}(x) = B_{i,k}(x - e_i).
+// One step maps B to B'.  Given lam' = dL/dB' the reverse step returns lam = dL/dB and
+// adds to dL/dsigma.  Per node the forward step is (Sec. 2):
+//   rho_k = sum_i f_{i,k}, f_i = sum_k f_{i,k}, c_k = rho_k/rho, grad c_k = D c_k (Eq. 12)
+//   G_p = c_l grad c_k - c_k grad c_l, m_p = |G_p|, n_p = G_p/m_p, C_p = min(cf_p rho_k rho_l, 1)
+//   T = sum_p sigma_p C_p (m_p^2 I - G_p G_p^T)/m_p,  F = div T  (Eqs. 6, 7)
+//   tau = 3 rho / sum_k(rho_k/nu_k) + 1/2, u = (sum_i f_i e_i + F/2)/rho   (Eqs. 9-11)
+//   fd_i = f_i - (f_i - feq_i)/tau + Phi_i                                 (Eqs. 1-3, 8)
+//   ct = min(35 rho_0 rho_1 rho_2/rho^3, 1), beta_p = beta0 (1 + ct g_p), a_p = beta_p rho_k rho_l/rho
+//   B'_{i,k} = c_k fd_i + w_i V_k . e_i,  V_k = sum_{l != k} a_kl n_kl, n_lk = -n_kl   (Eqs. 13, 19)
+// and the reverse pass applies the transposed chain rule to each line, right to left.
+// The difference operator of Eq. (12) is antisymmetric on a periodic lattice (D^T = -D),
+// so the transposes of the gradient and of the force divergence are -divergence and
+// -gradient with the same stencil.  Non-smooth points take one-sided derivatives:
+// d min(a, 1)/da = 1 for a < 1 and 0 otherwise; pairs with |G| at or below the guard
+// (n = 0, no stress) pass no derivative; g(X) has zero derivative where |X| is snapped to 1.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include "lbm3_handle.h"
 
 namespace tcg {
+namespace {
+
+constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int PK[3] = {0, 0, 1}, PL[3] = {1, 2, 2};
+
+__device__ __forceinline__ double wgt(int i)
+{
+    return i == 0 ? 1.0 - 4.0 * (1.0 / 9.0) - 4.0 * (1.0 / 36.0) : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+__device__ __forceinline__ int wrapi(int a, int n)
+{
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// Workspace fields, each [components][N] in FP64 with node index y*nx + x.
+struct AdjWS {
+    double* rho;    // 3   densities
+    double* ftot;   // 9   total populations
+    double* gc;     // 6   grad c_k (x, y per fluid)
+    double* fbar;   // 9   dL/df_i (collision part)
+    double* rbar;   // 3   dL/drho_k accumulated (all node-local contributions)
+    double* Fbar;   // 2   dL/dF
+    double* Gbar;   // 6   dL/dG_p from the recolouring normals
+    double* gcbar;  // 6   dL/d(grad c_k)
+    double* sig;    // [nblocks][6] per-workgroup sums: beta part (3), stress part (3)
+};
+
+struct Geo {
+    int nx, ny;
+    int64_t plane, pitch;
+    double sigma[3], g[3], beta0, inv_nu[3], cfac[3], guard;
+};
+
+// paired-difference form of Eq. (12) at node (x, y) of a scalar field
+__device__ __forceinline__ void grad_at(const double* __restrict__ phi, int nx, int ny, int x, int y,
+                                        double& dx, double& dy)
+{
+    const int xm = wrapi(x - 1, nx), xp = wrapi(x + 1, nx), ym = wrapi(y - 1, ny), yp = wrapi(y + 1, ny);
+    const double e = phi[(int64_t)y * nx + xp], w = phi[(int64_t)y * nx + xm];
+    const double n = phi[(int64_t)yp * nx + x], s = phi[(int64_t)ym * nx + x];
+    const double ne = phi[(int64_t)yp * nx + xp], nw = phi[(int64_t)yp * nx + xm];
+    const double se = phi[(int64_t)ym * nx + xp], sw = phi[(int64_t)ym * nx + xm];
+    dx = 3.0 * ((1.0 / 9.0) * (e - w) + (1.0 / 36.0) * ((ne - sw) + (se - nw)));
+    dy = 3.0 * ((1.0 / 9.0) * (n - s) + (1.0 / 36.0) * ((ne - sw) + (nw - se)));
+}
+
+// colour gradient, modulus, normal and concentration factor of pair p at a node
+struct PairFwd {
+    double Gx, Gy, m, nx, ny, C;
+    bool on;  // m > guard
+    bool unclipped;
+};
+
+__device__ __forceinline__ PairFwd pair_fwd(const Geo& g, int p, const double (&c)[3], const double (&gx)[3],
+                                            const double (&gy)[3], const double (&rk)[3])
+{
+    const int k = PK[p], l = PL[p];
+    PairFwd r;
+    r.Gx = c[l] * gx[k] - c[k] * gx[l];
+    r.Gy = c[l] * gy[k] - c[k] * gy[l];
+    r.m = sqrt(r.Gx * r.Gx + r.Gy * r.Gy);
+    r.on = r.m > g.guard;
+    r.nx = r.on ? r.Gx / r.m : 0.0;
+    r.ny = r.on ? r.Gy / r.m : 0.0;
+    const double cf = g.cfac[p] * rk[k] * rk[l];
+    r.unclipped = cf < 1.0;
+    r.C = r.unclipped ? cf : 1.0;
+    return r;
+}
+
+__device__ __forceinline__ void node_fields(const AdjWS& w, int64_t N, int64_t j, double (&rk)[3], double (&c)[3],
+                                            double (&gx)[3], double (&gy)[3])
+{
+    for (int k = 0; k < 3; ++k) rk[k] = w.rho[k * N + j];
+    const double r = rk[0] + rk[1] + rk[2];
+    for (int k = 0; k < 3; ++k) {
+        c[k] = rk[k] / r;
+        gx[k] = w.gc[(2 * k) * N + j];
+        gy[k] = w.gc[(2 * k + 1) * N + j];
+    }
+}
+
+// stress tensor (xx, xy, yy) at a node from its fields
+__device__ __forceinline__ void stress_at(const Geo& g, const AdjWS& w, int64_t N, int64_t j, double (&T)[3])
+{
+    double rk[3], c[3], gx[3], gy[3];
+    node_fields(w, N, j, rk, c, gx, gy);
+    T[0] = T[1] = T[2] = 0.0;
+    for (int p = 0; p < 3; ++p) {
+        const PairFwd f = pair_fwd(g, p, c, gx, gy, rk);
+        if (!f.on) continue;
+        const double h = g.sigma[p] * f.C / f.m;
+        T[0] += h * f.Gy * f.Gy;
+        T[1] -= h * f.Gx * f.Gy;
+        T[2] += h * f.Gx * f.Gx;
+    }
+}
+
+// ---- A0: pull the state, densities and totals
+__global__ __launch_bounds__(256) void k_adj_pull(const double* __restrict__ B, Geo g, AdjWS w)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    if (x >= g.nx) return;
+    const int64_t N = (int64_t)g.nx * g.ny, j = (int64_t)y * g.nx + x;
+    double ft[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < 3; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            const int64_t src = (int64_t)wrapi(y - EY[i], g.ny) * g.pitch + wrapi(x - EX[i], g.nx);
+            const double v = B[(int64_t)(k * 9 + i) * g.plane + src];
+            s += v;
+            ft[i] += v;
+        }
+        w.rho[k * N + j] = s;
+    }
+    for (int i = 0; i < 9; ++i) w.ftot[i * N + j] = ft[i];
+}
+
+// ---- A1: concentration gradients
+__global__ __launch_bounds__(256) void k_adj_grad(Geo g, AdjWS w, double* __restrict__ cbuf)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    if (x >= g.nx) return;
+    const int64_t N = (int64_t)g.nx * g.ny, j = (int64_t)y * g.nx + x;
+    (void)cbuf;
+    for (int k = 0; k < 3; ++k) {
+        // concentration of fluid k at the 9 nodes of the stencil, from the densities
+        double v[3][3];
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int64_t q = (int64_t)wrapi(y + dy, g.ny) * g.nx + wrapi(x + dx, g.nx);
+                const double r = w.rho[q] + w.rho[N + q] + w.rho[2 * N + q];
+                v[dy + 1][dx + 1] = w.rho[k * N + q] / r;
+            }
+        const double e = v[1][2], ww = v[1][0], n = v[2][1], s = v[0][1];
+        const double ne = v[2][2], nw = v[2][0], se = v[0][2], sw = v[0][0];
+        w.gc[(2 * k) * N + j] = 3.0 * ((1.0 / 9.0) * (e - ww) + (1.0 / 36.0) * ((ne - sw) + (se - nw)));
+        w.gc[(2 * k + 1) * N + j] = 3.0 * ((1.0 / 9.0) * (n - s) + (1.0 / 36.0) * ((ne - sw) + (nw - se)));
+    }
+}
+
+// ---- A2: node-local reverse of collision and recolouring
+__global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ lamp, Geo g, AdjWS w)
+{
+    __shared__ double red[3][256];
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    const int t = threadIdx.x;
+    double sig_beta[3] = {0.0, 0.0, 0.0};
+    if (x < g.nx) {
+        const int64_t N = (int64_t)g.nx * g.ny, j = (int64_t)y * g.nx + x;
+        double rk[3], c[3], gx[3], gy[3];
+        node_fields(w, N, j, rk, c, gx, gy);
+        const double rho = rk[0] + rk[1] + rk[2];
+        double f[9];
+        for (int i = 0; i < 9; ++i) f[i] = w.ftot[i * N + j];
+        PairFwd pf[3];
+        for (int p = 0; p < 3; ++p) pf[p] = pair_fwd(g, p, c, gx, gy, rk);
+        // force from the stress at the 8 neighbours
+        double Tn[3][3][3];
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dx == 0 && dy == 0) continue;
+                const int64_t q = (int64_t)wrapi(y + dy, g.ny) * g.nx + wrapi(x + dx, g.nx);
+                stress_at(g, w, N, q, Tn[dy + 1][dx + 1]);
+            }
+        double dT[3][2];
+        for (int a = 0; a < 3; ++a) {
+            const double e = Tn[1][2][a], ww = Tn[1][0][a], n = Tn[2][1][a], s = Tn[0][1][a];
+            const double ne = Tn[2][2][a], nw = Tn[2][0][a], se = Tn[0][2][a], sw = Tn[0][0][a];
+            dT[a][0] = 3.0 * ((1.0 / 9.0) * (e - ww) + (1.0 / 36.0) * ((ne - sw) + (se - nw)));
+            dT[a][1] = 3.0 * ((1.0 / 9.0) * (n - s) + (1.0 / 36.0) * ((ne - sw) + (nw - se)));
+        }
+        const double Fx = dT[0][0] + dT[1][1], Fy = dT[1][0] + dT[2][1];
+        // ---- forward collision
+        const double S = rk[0] * g.inv_nu[0] + rk[1] * g.inv_nu[1] + rk[2] * g.inv_nu[2];
+        const double tau = 3.0 * rho / S + 0.5;
+        const double itau = 1.0 / tau;
+        double mx = 0.0, my = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            mx += f[i] * EX[i];
+            my += f[i] * EY[i];
+        }
+        const double ux = (mx + 0.5 * Fx) / rho, uy = (my + 0.5 * Fy) / rho;
+        const double uu = ux * ux + uy * uy, uF = ux * Fx + uy * Fy, pref = 1.0 - 0.5 * itau;
+        double eu[9], eF[9], feq[9], phi[9], fd[9];
+        for (int i = 0; i < 9; ++i) {
+            eu[i] = EX[i] * ux + EY[i] * uy;
+            eF[i] = EX[i] * Fx + EY[i] * Fy;
+            feq[i] = wgt(i) * rho * (1.0 + 3.0 * eu[i] + 4.5 * eu[i] * eu[i] - 1.5 * uu);
+            phi[i] = wgt(i) * pref * (3.0 * (eF[i] - uF) + 9.0 * eu[i] * eF[i]);
+            fd[i] = f[i] - (f[i] - feq[i]) * itau + phi[i];
+        }
+        // ---- forward recolouring quantities
+        const double q35 = 35.0 * rk[0] * rk[1] * rk[2] / (rho * rho * rho);
+        const bool ct_free = q35 < 1.0;
+        const double ct = ct_free ? q35 : 1.0;
+        double beta[3], aa[3], prod[3];
+        for (int p = 0; p < 3; ++p) {
+            beta[p] = g.beta0 * (1.0 + ct * g.g[p]);
+            prod[p] = rk[PK[p]] * rk[PL[p]];
+            aa[p] = beta[p] * prod[p] / rho;
+        }
+        // ---- reverse of the recolouring
+        double ob[27];
+        for (int q = 0; q < 27; ++q) {
+            const int i = q % 9;
+            const int64_t d = (int64_t)y * g.pitch + x;
+            ob[q] = lamp[(int64_t)q * g.plane + d];
+            (void)i;
+        }
+        double fdb[9], cb[3] = {0, 0, 0}, Vb[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+        for (int i = 0; i < 9; ++i) fdb[i] = c[0] * ob[i] + c[1] * ob[9 + i] + c[2] * ob[18 + i];
+        for (int k = 0; k < 3; ++k)
+            for (int i = 0; i < 9; ++i) {
+                cb[k] += fd[i] * ob[k * 9 + i];
+                Vb[k][0] += wgt(i) * EX[i] * ob[k * 9 + i];
+                Vb[k][1] += wgt(i) * EY[i] * ob[k * 9 + i];
+            }
+        double rb[3] = {0, 0, 0}, rhob = 0.0, ctb = 0.0, Gbr[3][2];
+        for (int p = 0; p < 3; ++p) {
+            const int k = PK[p], l = PL[p];
+            const double dVx = Vb[k][0] - Vb[l][0], dVy = Vb[k][1] - Vb[l][1];
+            const double ab = dVx * pf[p].nx + dVy * pf[p].ny;
+            // n_p = G/m: dL/dG = (nb - n (n . nb)) / m with nb = a_p (Vb_k - Vb_l)
+            Gbr[p][0] = Gbr[p][1] = 0.0;
+            if (pf[p].on) {
+                const double nbx = aa[p] * dVx, nby = aa[p] * dVy;
+                const double nn = pf[p].nx * nbx + pf[p].ny * nby;
+                Gbr[p][0] = (nbx - pf[p].nx * nn) / pf[p].m;
+                Gbr[p][1] = (nby - pf[p].ny * nn) / pf[p].m;
+            }
+            // a_p = beta_p rho_k rho_l / rho
+            const double betab = ab * prod[p] / rho;
+            rb[k] += ab * beta[p] * rk[l] / rho;
+            rb[l] += ab * beta[p] * rk[k] / rho;
+            rhob -= ab * aa[p] / rho;
+            // beta_p = beta0 (1 + ct g_p)
+            ctb += betab * g.beta0 * g.g[p];
+            sig_beta[p] = betab * g.beta0 * ct;  // times g'(X_p) dX_p/dsigma on the host
+        }
+        if (ct_free) {
+            rb[0] += ctb * 35.0 * rk[1] * rk[2] / (rho * rho * rho);
+            rb[1] += ctb * 35.0 * rk[0] * rk[2] / (rho * rho * rho);
+            rb[2] += ctb * 35.0 * rk[0] * rk[1] / (rho * rho * rho);
+            rhob -= ctb * 3.0 * q35 / rho;
+        }
+        // ---- reverse of the collision
+        double fb[9], ub[2] = {0, 0}, Fb[2] = {0, 0}, itaub = 0.0, prefb = 0.0, uub = 0.0, uFb = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            const double feqb = fdb[i] * itau;
+            fb[i] = fdb[i] * (1.0 - itau);
+            itaub += fdb[i] * (feq[i] - f[i]);
+            const double phib = fdb[i];
+            prefb += phib * wgt(i) * (3.0 * (eF[i] - uF) + 9.0 * eu[i] * eF[i]);
+            const double A = phib * wgt(i) * pref;
+            const double eFb = A * (3.0 + 9.0 * eu[i]);
+            double eub = 9.0 * A * eF[i];
+            uFb -= 3.0 * A;
+            rhob += feqb * wgt(i) * (1.0 + 3.0 * eu[i] + 4.5 * eu[i] * eu[i] - 1.5 * uu);
+            const double Bf = feqb * wgt(i) * rho;
+            eub += Bf * (3.0 + 9.0 * eu[i]);
+            uub -= 1.5 * Bf;
+            ub[0] += eub * EX[i];
+            ub[1] += eub * EY[i];
+            Fb[0] += eFb * EX[i];
+            Fb[1] += eFb * EY[i];
+        }
+        ub[0] += uFb * Fx + 2.0 * uub * ux;
+        ub[1] += uFb * Fy + 2.0 * uub * uy;
+        Fb[0] += uFb * ux;
+        Fb[1] += uFb * uy;
+        itaub -= 0.5 * prefb;
+        // u = (m + F/2)/rho
+        const double mbx = ub[0] / rho, mby = ub[1] / rho;
+        Fb[0] += 0.5 * mbx;
+        Fb[1] += 0.5 * mby;
+        rhob -= (ub[0] * ux + ub[1] * uy) / rho;
+        for (int i = 0; i < 9; ++i) fb[i] += mbx * EX[i] + mby * EY[i];
+        // itau = 1/tau, tau = 3 rho / S + 1/2, S = sum_k rho_k inv_nu_k
+        const double taub = -itaub * itau * itau;
+        rhob += taub * 3.0 / S;
+        const double Sb = -taub * 3.0 * rho / (S * S);
+        for (int k = 0; k < 3; ++k) rb[k] += Sb * g.inv_nu[k];
+        // c_k = rho_k / rho (the node-local uses of c)
+        double cr = 0.0;
+        for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
+        for (int k = 0; k < 3; ++k) rb[k] += cb[k] / rho - cr / (rho * rho);
+        for (int k = 0; k < 3; ++k) rb[k] += rhob;  // rho = sum_k rho_k
+        for (int i = 0; i < 9; ++i) w.fbar[i * N + j] = fb[i];
+        for (int k = 0; k < 3; ++k) w.rbar[k * N + j] = rb[k];
+        w.Fbar[j] = Fb[0];
+        w.Fbar[N + j] = Fb[1];
+        for (int p = 0; p < 3; ++p) {
+            w.Gbar[(2 * p) * N + j] = Gbr[p][0];
+            w.Gbar[(2 * p + 1) * N + j] = Gbr[p][1];
+        }
+    }
+    for (int p = 0; p < 3; ++p) red[p][t] = sig_beta[p];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h)
+            for (int p = 0; p < 3; ++p) red[p][t] += red[p][t + h];
+        __syncthreads();
+    }
+    if (t < 3) {
+        const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        w.sig[b * 6 + t] += red[t][0];
+    }
+}
+
+// ---- A3: reverse of the stress (force divergence transposed) and of the pair quantities
+__global__ __launch_bounds__(256) void k_adj_stress(Geo g, AdjWS w)
+{
+    __shared__ double red[3][256];
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    const int t = threadIdx.x;
+    double sig_st[3] = {0.0, 0.0, 0.0};
+    if (x < g.nx) {
+        const int64_t N = (int64_t)g.nx * g.ny, j = (int64_t)y * g.nx + x;
+        // T-bar = -(transpose-free form) : Tb_xx = -Dx Fbx, Tb_xy = -(Dy Fbx + Dx Fby), Tb_yy = -Dy Fby
+        double dFx_dx, dFx_dy, dFy_dx, dFy_dy;
+        grad_at(w.Fbar, g.nx, g.ny, x, y, dFx_dx, dFx_dy);
+        grad_at(w.Fbar + N, g.nx, g.ny, x, y, dFy_dx, dFy_dy);
+        const double Tbxx = -dFx_dx, Tbxy = -(dFx_dy + dFy_dx), Tbyy = -dFy_dy;
+        double rk[3], c[3], gx[3], gy[3];
+        node_fields(w, N, j, rk, c, gx, gy);
+        const double rho = rk[0] + rk[1] + rk[2];
+        double cb[3] = {0, 0, 0}, gcb[3][2] = {{0, 0}, {0, 0}, {0, 0}}, rb[3] = {0, 0, 0};
+        for (int p = 0; p < 3; ++p) {
+            const int k = PK[p], l = PL[p];
+            const PairFwd f = pair_fwd(g, p, c, gx, gy, rk);
+            if (!f.on) continue;
+            double Gbx = w.Gbar[(2 * p) * N + j], Gby = w.Gbar[(2 * p + 1) * N + j];
+            const double Q = Tbxx * f.Gy * f.Gy - Tbxy * f.Gx * f.Gy + Tbyy * f.Gx * f.Gx;
+            const double h = g.sigma[p] * f.C / f.m;
+            Gbx += h * (2.0 * Tbyy * f.Gx - Tbxy * f.Gy);
+            Gby += h * (2.0 * Tbxx * f.Gy - Tbxy * f.Gx);
+            const double mb = -Q * g.sigma[p] * f.C / (f.m * f.m);
+            Gbx += mb * f.Gx / f.m;
+            Gby += mb * f.Gy / f.m;
+            sig_st[p] = Q * f.C / f.m;
+            if (f.unclipped) {
+                const double Cb = Q * g.sigma[p] / f.m;
+                rb[k] += Cb * g.cfac[p] * rk[l];
+                rb[l] += Cb * g.cfac[p] * rk[k];
+            }
+            // G = c_l grad c_k - c_k grad c_l
+            cb[l] += Gbx * gx[k] + Gby * gy[k];
+            cb[k] -= Gbx * gx[l] + Gby * gy[l];
+            gcb[k][0] += c[l] * Gbx;
+            gcb[k][1] += c[l] * Gby;
+            gcb[l][0] -= c[k] * Gbx;
+            gcb[l][1] -= c[k] * Gby;
+        }
+        double cr = 0.0;
+        for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
+        for (int k = 0; k < 3; ++k) w.rbar[k * N + j] += rb[k] + cb[k] / rho - cr / (rho * rho);
+        for (int k = 0; k < 3; ++k) {
+            w.gcbar[(2 * k) * N + j] = gcb[k][0];
+            w.gcbar[(2 * k + 1) * N + j] = gcb[k][1];
+        }
+    }
+    for (int p = 0; p < 3; ++p) red[p][t] = sig_st[p];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h)
+            for (int p = 0; p < 3; ++p) red[p][t] += red[p][t + h];
+        __syncthreads();
+    }
+    if (t < 3) {
+        const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        w.sig[b * 6 + 3 + t] += red[t][0];
+    }
+}
+
+// ---- A4: reverse of the gradient (c-bar = -div gcbar), densities, totals and streaming
+__global__ __launch_bounds__(256) void k_adj_final(Geo g, AdjWS w, double* __restrict__ lam)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    if (x >= g.nx) return;
+    const int64_t N = (int64_t)g.nx * g.ny, j = (int64_t)y * g.nx + x;
+    double rk[3];
+    for (int k = 0; k < 3; ++k) rk[k] = w.rho[k * N + j];
+    const double rho = rk[0] + rk[1] + rk[2];
+    double cb[3];
+    for (int k = 0; k < 3; ++k) {
+        double a, b, dum;
+        grad_at(w.gcbar + (2 * k) * N, g.nx, g.ny, x, y, a, dum);
+        grad_at(w.gcbar + (2 * k + 1) * N, g.nx, g.ny, x, y, dum, b);
+        cb[k] = -(a + b);
+    }
+    double cr = 0.0;
+    for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
+    double rb[3];
+    for (int k = 0; k < 3; ++k) rb[k] = w.rbar[k * N + j] + cb[k] / rho - cr / (rho * rho);
+    // f_{i,k}(x) = B_{i,k}(x - e_i): dL/dB_{i,k}(x - e_i) = dL/df_{i,k}(x) = fbar_i + rhobar_k
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 9; ++i) {
+            const int64_t d = (int64_t)wrapi(y - EY[i], g.ny) * g.pitch + wrapi(x - EX[i], g.nx);
+            lam[(int64_t)(k * 9 + i) * g.plane + d] = w.fbar[i * N + j] + rb[k];
+        }
+}
+
+// dL/drho_1(x, T) as dL/dB: lam_{i,1}(x - e_i) = g(x), other colours 0
+__global__ __launch_bounds__(256) void k_adj_seed(const double* __restrict__ gT, Geo g, double* __restrict__ lam)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    if (x >= g.nx) return;
+    const int64_t j = (int64_t)y * g.nx + x;
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 9; ++i) {
+            const int64_t d = (int64_t)wrapi(y - EY[i], g.ny) * g.pitch + wrapi(x - EX[i], g.nx);
+            lam[(int64_t)(k * 9 + i) * g.plane + d] = k == 0 ? gT[j] : 0.0;
+        }
+}
+
+// initial state B_{i,k}(y) = w_i rho_k(y + e_i):  dL/drho_k(x) = sum_i w_i lam_{i,k}(x - e_i)
+__global__ __launch_bounds__(256) void k_adj_rho0(const double* __restrict__ lam, Geo g, double* __restrict__ out)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    if (x >= g.nx) return;
+    const int64_t N = (int64_t)g.nx * g.ny, j = (int64_t)y * g.nx + x;
+    for (int k = 0; k < 3; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            const int64_t d = (int64_t)wrapi(y - EY[i], g.ny) * g.pitch + wrapi(x - EX[i], g.nx);
+            s += wgt(i) * lam[(int64_t)(k * 9 + i) * g.plane + d];
+        }
+        out[k * N + j] = s;
+    }
+}
+
+Geo geo_of(const KParams& kp)
+{
+    Geo g;
+    g.nx = kp.nx;
+    g.ny = kp.ny;
+    g.plane = kp.plane;
+    g.pitch = kp.pitch;
+    for (int p = 0; p < 3; ++p) {
+        g.sigma[p] = kp.sigma[p];
+        g.g[p] = kp.g[p];
+        g.inv_nu[p] = kp.inv_nu[p];
+        g.cfac[p] = kp.cfac[p];
+    }
+    g.beta0 = kp.beta0;
+    g.guard = kp.guard;
+    return g;
+}
+
+// derivative of g(X) of Eq. (20) (zero where |X| is snapped to 1 and outside [-1, 1])
+double dg_dX(double X)
+{
+    if (X >= 1.0 - 1e-12 || X <= -1.0 + 1e-12) return 0.0;
+    const double s = std::sqrt((1.0 - X) * (1.0 + X));
+    return X < 0.0 ? X / s : -X / s;
+}
+
+}  // namespace
+
 void adjoint_release(lbm3* h)
 {
     for (void* p : h->ckpt)
@@ -12,21 +497,171 @@ void adjoint_release(lbm3* h)
     h->adj_ws_bytes = 0;
     h->tape_valid = false;
 }
+
 }  // namespace tcg
 
 using namespace tcg;
 
+static int ensure_ws(lbm3* h, size_t bytes)
+{
+    if (h->adj_ws_bytes >= bytes) return LBM3_OK;
+    if (h->adj_ws) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->adj_ws);
+        h->adj_ws = nullptr;
+        h->adj_ws_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&h->adj_ws, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(adjoint workspace)");
+    h->adj_ws_bytes = bytes;
+    return LBM3_OK;
+}
+
 extern "C" {
+
 int lbm3_adjoint_record(lbm3_t* h, int64_t nsteps, int32_t ckpt_every)
 {
-    (void)h; (void)nsteps; (void)ckpt_every;
-    set_error("adjoint not built yet");
-    return LBM3_EUNSUPPORTED;
+    if (!h) {
+        set_error("handle is NULL");
+        return LBM3_EINVAL;
+    }
+    if (h->prec != Prec::F64) {
+        set_error("the adjoint is provided for LBM3_FP64 only");
+        return LBM3_EUNSUPPORTED;
+    }
+    if (!h->ready || h->step != 0 || !h->init_at_rest) {
+        set_error("lbm3_adjoint_record needs the state set by lbm3_init_fields(rho, NULL) at step 0");
+        return LBM3_ESTATE;
+    }
+    if (nsteps < 1 || ckpt_every < 1 || nsteps % ckpt_every) {
+        set_error("nsteps >= 1 must be a multiple of ckpt_every >= 1");
+        return LBM3_EINVAL;
+    }
+    adjoint_release(h);
+    const size_t bytes = (size_t)h->kp.span * sizeof(double);
+    const int64_t nck = nsteps / ckpt_every + 1;
+    h->ckpt.assign(nck, nullptr);
+    for (int64_t c = 0; c < nck; ++c) {
+        hipError_t e = hipMalloc(&h->ckpt[c], bytes);
+        if (e != hipSuccess) {
+            int rc = hip_fail(e, "hipMalloc(checkpoint)");
+            adjoint_release(h);
+            return rc;
+        }
+    }
+    hipError_t e = hipMemcpyAsync(h->ckpt[0], h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+    for (int64_t c = 1; c < nck; ++c) {
+        int rc = lbm3_step(h, ckpt_every);
+        if (rc) return rc;
+        e = hipMemcpyAsync(h->ckpt[c], h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+    }
+    h->tape_steps = nsteps;
+    h->tape_every = ckpt_every;
+    h->tape_valid = true;
+    return LBM3_OK;
 }
+
 int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drho0)
 {
-    (void)h; (void)drho1_T; (void)dsigma; (void)drho0;
-    set_error("adjoint not built yet");
-    return LBM3_EUNSUPPORTED;
+    if (!h || !drho1_T) {
+        set_error("handle or drho1_T is NULL");
+        return LBM3_EINVAL;
+    }
+    if (!h->tape_valid) {
+        set_error("lbm3_adjoint needs a preceding lbm3_adjoint_record (and no step since)");
+        return LBM3_ESTATE;
+    }
+    const KParams& kp = h->kp;
+    const int64_t N = (int64_t)kp.nx * kp.ny;
+    for (int64_t j = 0; j < N; ++j)
+        if (!std::isfinite(drho1_T[j])) {
+            set_error("drho1_T is not finite at node %lld", (long long)j);
+            return LBM3_EINVAL;
+        }
+    const Geo g = geo_of(kp);
+    const dim3 grid((kp.nx + 255) / 256, kp.ny), blk(256);
+    const int64_t nblocks = (int64_t)grid.x * grid.y;
+    const size_t sbytes = (size_t)kp.span * sizeof(double);
+    const int K = h->tape_every;
+    const int64_t nseg = h->tape_steps / K;
+    // workspace: 44 fields of N doubles, two adjoint buffers, K recomputed states, sums
+    const size_t fields = (size_t)(3 + 9 + 6 + 9 + 3 + 2 + 6 + 6) * N;
+    const size_t need = fields * sizeof(double) + 2 * sbytes + (size_t)K * sbytes +
+                        (size_t)nblocks * 6 * sizeof(double) + 3 * N * sizeof(double);
+    int rc = ensure_ws(h, need);
+    if (rc) return rc;
+    char* base = (char*)h->adj_ws;
+    double* d = (double*)base;
+    AdjWS w;
+    w.rho = d;
+    w.ftot = w.rho + 3 * N;
+    w.gc = w.ftot + 9 * N;
+    w.fbar = w.gc + 6 * N;
+    w.rbar = w.fbar + 9 * N;
+    w.Fbar = w.rbar + 3 * N;
+    w.Gbar = w.Fbar + 2 * N;
+    w.gcbar = w.Gbar + 6 * N;
+    double* lam[2];
+    lam[0] = w.gcbar + 6 * N;
+    lam[1] = (double*)((char*)lam[0] + sbytes);
+    char* seg = (char*)lam[1] + sbytes;
+    w.sig = (double*)(seg + (size_t)K * sbytes);
+    double* gT = w.sig + nblocks * 6;
+    hipError_t e = hipMemsetAsync(w.sig, 0, (size_t)nblocks * 6 * sizeof(double), h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(gT, drho1_T, N * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint set-up");
+    int cl = 0;
+    hipLaunchKernelGGL(k_adj_seed, grid, blk, 0, h->stream, gT, g, lam[cl]);
+    for (int64_t s = nseg - 1; s >= 0; --s) {
+        // recompute the states B^{sK + j}, j = 0..K-1, of this segment
+        e = hipMemcpyAsync(seg, h->ckpt[s], sbytes, hipMemcpyDeviceToDevice, h->stream);
+        for (int j = 1; j < K && e == hipSuccess; ++j)
+            e = launch_tiles(Prec::F64, seg + (size_t)(j - 1) * sbytes, seg + (size_t)j * sbytes, h->dinst,
+                             h->dtiles, h->ntiles, h->threads, s * K + j - 1, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "adjoint segment recompute");
+        for (int j = K - 1; j >= 0; --j) {
+            const double* Bj = (const double*)(seg + (size_t)j * sbytes);
+            hipLaunchKernelGGL(k_adj_pull, grid, blk, 0, h->stream, Bj, g, w);
+            hipLaunchKernelGGL(k_adj_grad, grid, blk, 0, h->stream, g, w, nullptr);
+            hipLaunchKernelGGL(k_adj_local, grid, blk, 0, h->stream, (const double*)lam[cl], g, w);
+            hipLaunchKernelGGL(k_adj_stress, grid, blk, 0, h->stream, g, w);
+            hipLaunchKernelGGL(k_adj_final, grid, blk, 0, h->stream, g, w, lam[cl ^ 1]);
+            cl ^= 1;
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "adjoint kernels");
+    }
+    double* r0 = (double*)seg;  // reuse: dL/drho_k(x, 0)
+    hipLaunchKernelGGL(k_adj_rho0, grid, blk, 0, h->stream, (const double*)lam[cl], g, r0);
+    std::vector<double> sig((size_t)nblocks * 6);
+    e = hipGetLastError();
+    if (e == hipSuccess && drho0) e = hipMemcpyAsync(drho0, r0, 3 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sig.data(), w.sig, sig.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint results");
+    // sigma: stress part directly; segregation part through g'(X_p) dX_p/dsigma_q
+    double Sb[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t b = 0; b < nblocks; ++b)
+        for (int a = 0; a < 6; ++a) Sb[a] += sig[b * 6 + a];
+    double ds[3] = {Sb[3], Sb[4], Sb[5]};
+    const double* sgm = h->p.sigma;
+    auto pidx = [](int a, int b) { return (a > b ? (b == 0 ? (a == 1 ? 0 : 1) : 2) : (a == 0 ? (b == 1 ? 0 : 1) : 2)); };
+    for (int p = 0; p < 3; ++p) {
+        const int k = PK[p], l = PL[p], m = 3 - k - l;
+        const int imk = pidx(m, k), iml = pidx(m, l);
+        const double smk = sgm[imk], sml = sgm[iml], skl = sgm[p];
+        const double X = (smk * smk + sml * sml - skl * skl) / (2.0 * smk * sml);
+        const double gp = dg_dX(X) * Sb[p];
+        ds[p] += gp * (-skl / (smk * sml));
+        ds[imk] += gp * (1.0 / sml - X / smk);
+        ds[iml] += gp * (1.0 / smk - X / sml);
+    }
+    if (dsigma)
+        for (int p = 0; p < 3; ++p) dsigma[p] = ds[p];
+    return LBM3_OK;
 }
-}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+"""The hand-written adjoint through the C ABI, against central finite differences of the
+FP64 oracle (h = 1e-6): gradients of L = sum_x (rho_1(x, T) - rho*(x))^2 with respect to
+the three interfacial tensions and the initial densities."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1808_08555_amd import inputs, lbm3
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SIGMA = (0.006, 0.010, 0.012)  # a strict Neumann triangle: |X_kl| < 1 for every pair
+
+
+def sharp_janus(nx, ny, R):
+    """A disk of fluids 0 | 1 (split at the centre column) in fluid 2, as the 256^2 case.
+    Pure fluids have exactly zero colour gradients (guarded, no derivative), so the loss
+    is smooth in the directions the tests perturb: tensions, and each node's own fluid."""
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    xc, yc = nx / 2.0, ny / 2.0
+    inside = (x - xc) ** 2 + (y - yc) ** 2 <= R * R
+    lab = np.full((ny, nx), 2)
+    lab[inside & (x < xc)] = 0
+    lab[inside & (x >= xc)] = 1
+    return inputs.rho_from_labels(lab), lab
+
+
+def gpu_gradient(rho0, target, sigma, tau, steps, every):
+    ny, nx = rho0.shape[1:]
+    L = lbm3.Lattice(nx, ny, sigma, tau).init(rho0)
+    lbm3.lbm3_adjoint_record(L.h, steps, every)
+    rho_T = L.densities()
+    g = 2.0 * (rho_T[0] - target)
+    ds, dr = lbm3.lbm3_adjoint(L.h, g, nx, ny)
+    loss = float(((rho_T[0] - target) ** 2).sum())
+    obs = L.observables()[0]
+    L.close()
+    assert obs["step"] == steps
+    return loss, ds, dr
+
+
+def oracle_loss(rho0, target, sigma, tau, steps):
+    ny, nx = rho0.shape[1:]
+    p = oracle.Params(nx, ny, tuple(sigma), tuple(tau))
+    f = oracle.run(p, oracle.init(p, rho0), steps)
+    return float(((f[0].sum(axis=0) - target) ** 2).sum())
+
+
+@pytest.mark.parametrize("steps,every", [(1, 1), (4, 2), (12, 4), (30, 10)])
+def test_adjoint_matches_oracle_finite_differences(steps, every):
+    nx, ny, h = 24, 20, 1e-6
+    tau = (0.7, 0.8, 0.9)
+    rho0, lab = sharp_janus(nx, ny, 6.0)
+    target = inputs.loss_target(rho0[0], seed=5550)
+    loss, ds, dr = gpu_gradient(rho0, target, SIGMA, tau, steps, every)
+    assert abs(loss / oracle_loss(rho0, target, SIGMA, tau, steps) - 1) < 1e-12
+    for q in range(3):
+        sp, sm = list(SIGMA), list(SIGMA)
+        sp[q] += h
+        sm[q] -= h
+        fd = (oracle_loss(rho0, target, sp, tau, steps) - oracle_loss(rho0, target, sm, tau, steps)) / (2 * h)
+        print(f"T={steps} dL/dsigma[{q}] adjoint {ds[q]:.10e} fd {fd:.10e}")
+        assert abs(ds[q] - fd) <= 1e-5 * max(1e-3, abs(fd))
+    rng = np.random.default_rng(steps)
+    nodes = [(10, 7), (10, 12), (9, 14), (16, 10)] + [tuple(rng.integers(0, (ny, nx))) for _ in range(3)]
+    for (y, x) in nodes:
+        k = int(lab[y, x])
+        rp, rm = rho0.copy(), rho0.copy()
+        rp[k, y, x] += h
+        rm[k, y, x] -= h
+        fd = (oracle_loss(rp, target, SIGMA, tau, steps) - oracle_loss(rm, target, SIGMA, tau, steps)) / (2 * h)
+        print(f"T={steps} dL/drho0[{k},{y},{x}] adjoint {dr[k, y, x]:.10e} fd {fd:.10e}")
+        assert abs(dr[k, y, x] - fd) <= 1e-5 * max(1e-3, abs(fd))
+
+
+def test_adjoint_taylor_remainder_is_second_order():
+    """With the GPU forward alone: L(rho0 + e d) - L(rho0) - e <grad, d> shrinks as e^2
+    (d perturbs each node's own fluid)."""
+    nx, ny = 32, 28
+    rho0, lab = sharp_janus(nx, ny, 8.0)
+    target = inputs.loss_target(rho0[0], seed=7)
+    loss, ds, dr = gpu_gradient(rho0, target, SIGMA, (0.8, 0.8, 0.8), 20, 5)
+    d = np.zeros_like(rho0)
+    u = np.random.default_rng(3).uniform(-1, 1, lab.shape) * 0.01
+    for k in range(3):
+        d[k][lab == k] = u[lab == k]
+
+    def L_at(r):
+        M = lbm3.Lattice(nx, ny, SIGMA, (0.8, 0.8, 0.8)).init(r).step(20)
+        v = float(((M.densities()[0] - target) ** 2).sum())
+        M.close()
+        return v
+
+    lin = float((dr * d).sum())
+    rem = [abs(L_at(rho0 + e * d) - loss - e * lin) for e in (1e-2, 5e-3, 2.5e-3)]
+    print("Taylor remainders:", rem, "first-order term", 1e-2 * lin)
+    assert rem[1] / rem[0] < 0.3 and rem[2] / rem[1] < 0.3  # ~1/4 for a second-order remainder
+
+
+def test_adjoint_janus_256_5000_steps_against_stored_finite_differences():
+    """The 256^2 Janus droplet of two half-disks (R = 40), 5000 steps with a checkpoint every
+    100: the adjoint gradient against central differences of the oracle stored by
+    tests/golden/make_adjoint_fd.py."""
+    path = os.path.join(HERE, "golden", "janus256_fd.json")
+    ref = json.load(open(path))
+    w = inputs.janus_halves(256, 40.0, SIGMA, (0.8, 0.8, 0.8), ref["steps"])
+    target = inputs.loss_target(w.rho[0], seed=5550)
+    loss, ds, dr = gpu_gradient(w.rho, target, SIGMA, w.tau, ref["steps"], 100)
+    print("loss gpu", loss, "oracle", ref["loss"])
+    assert abs(loss / ref["loss"] - 1) < 1e-9
+    for q in range(3):
+        fd = ref["dL_dsigma"][q]
+        print(f"dL/dsigma[{q}] adjoint {ds[q]:.10e} fd {fd:.10e}")
+        assert abs(ds[q] - fd) <= 1e-4 * abs(fd)
+    for k, y, x, fd in ref["dL_drho0"]:
+        print(f"dL/drho0[{k},{y},{x}] adjoint {dr[k, y, x]:.10e} fd {fd:.10e}")
+        assert abs(dr[k, y, x] - fd) <= 1e-4 * max(abs(fd), 1e-3)
+
+
+def test_adjoint_errors():
+    L = lbm3.Lattice(8, 8)
+    rho = inputs.random_mixture(8, 8, 1, tiny_fraction=0.0)
+    with pytest.raises(lbm3.Lbm3Error):
+        lbm3.lbm3_adjoint(L.h, np.zeros((8, 8)), 8, 8)  # no recording yet
+    L.init(rho).step(1)
+    with pytest.raises(lbm3.Lbm3Error) as e:
+        lbm3.lbm3_adjoint_record(L.h, 4, 2)  # not at step 0
+    assert e.value.code == lbm3.LBM3_ESTATE
+    L.init(rho)
+    with pytest.raises(lbm3.Lbm3Error):
+        lbm3.lbm3_adjoint_record(L.h, 5, 2)  # not a multiple
+    L.close()
+    F = lbm3.Lattice(8, 8, precision="fp32").init(rho)
+    with pytest.raises(lbm3.Lbm3Error) as e:
+        lbm3.lbm3_adjoint_record(F.h, 2, 1)
+    assert e.value.code == lbm3.LBM3_EUNSUPPORTED
+    F.close()
