@@ -158,6 +158,32 @@ def bench_batched(torch, lbm3, inputs, steps: int):
     return res
 
 
+def bench_adjoint(torch, lbm3, inputs, n: int, steps: int, every: int):
+    """Adjoint of the FP64 step on an n x n Janus droplet: forward with checkpoints, then the
+    reverse sweep (segment recompute + reverse steps), each timed on the host around the
+    blocking calls.  Adjoint MLUPS = nodes x steps / reverse-sweep time."""
+    import time as _t
+    R = 40.0 * n / 256.0
+    w = inputs.janus_halves(n, R, (0.006, 0.010, 0.012), (0.8, 0.8, 0.8), steps)
+    target = inputs.loss_target(w.rho[0], seed=5550)
+    L = lbm3.Lattice(n, n, w.sigma, w.tau).init(w.rho)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    lbm3.lbm3_adjoint_record(L.h, steps, every)
+    rho_T = L.densities()
+    t1 = _t.perf_counter()
+    lbm3.lbm3_adjoint(L.h, 2.0 * (rho_T[0] - target), n, n)
+    t2 = _t.perf_counter()
+    L.close()
+    nodes = n * n
+    return {"workload": f"Janus droplet {n}x{n}, R={R:g}, FP64, {steps} steps, checkpoint every {every}",
+            "adjoint_mlups": round(nodes * steps / (t2 - t1) / 1e6, 1),
+            "forward_with_checkpoints_mlups": round(nodes * steps / (t1 - t0) / 1e6, 1),
+            "bytes_per_lu_stated": 1080,
+            "frac_of_peak": round(1080 * nodes * steps / (t2 - t1) / 1e9 / HBM_PEAK_GBS, 4),
+            "reverse_s": round(t2 - t1, 3), "forward_s": round(t1 - t0, 3)}
+
+
 def cpu_baseline(w, steps: int = 2):
     import oracle
 
@@ -204,6 +230,9 @@ def main():
         log(f"compound 256 fp64 {extra['compound_256_fp64']}")
         batched = bench_batched(torch, lbm3, inputs, 1000)
         log(f"batched {batched}")
+        adjoint = {"janus_256": bench_adjoint(torch, lbm3, inputs, 256, 5000, 100),
+                   "janus_2048": bench_adjoint(torch, lbm3, inputs, 2048, 200, 20)}
+        log(f"adjoint {adjoint}")
     copy_gbs = copy_bandwidth(torch, lbm3)
     log(f"device copy {copy_gbs:.0f} GB/s")
 
@@ -245,6 +274,7 @@ def main():
             "rows_by_side": batched["rows_by_side"],
             "baseline_plain_fp32_equal_nodes_mlups": round(batched["plain_equal_nodes"], 1),
             "baseline_one_launch_per_instance_mlups": round(batched["per_instance_launches"], 1)}
+        line["adjoint_fp64"] = adjoint
     print(json.dumps(line), flush=True)
 
 
