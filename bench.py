@@ -184,7 +184,7 @@ def bench_adjoint(torch, lbm3, inputs, n: int, steps: int, every: int):
             "reverse_s": round(t2 - t1, 3), "forward_s": round(t1 - t0, 3)}
 
 
-def cpu_baseline(w, steps: int = 2):
+def cpu_baseline(w, steps: int = 8):
     import oracle
 
     p = oracle.Params(w.nx, w.ny, w.sigma, w.tau)

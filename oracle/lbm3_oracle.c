@@ -23,6 +23,11 @@
  * time, (12) isotropic difference, (13) recolouring, (14) Neumann angle,
  * (15)-(17) earlier segregation laws, (18)-(20) proposed segregation law,
  * (22) streaming.
+ *
+ * Parity unpinned: the coefficient 35 of C_t in Eq. (19) only matters where
+ * C_t < 1 (near triple junctions) and no closed form fixes it; the checks
+ * against the paper cover C_t = 1 and C_t = 0.  The scale 1e6 of C_kl in
+ * Eq. (6) is pinned only through C_kl saturating to 1 at interfaces.
  */
 #include <math.h>
 #include <stddef.h>

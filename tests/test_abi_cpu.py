@@ -103,3 +103,12 @@ def test_morphology_of_the_seven_printed_cases():
              ((0.5, 1.7), morphology.ENGULF_0_BY_1)]
     for (gb, rb), expect in cases:
         assert morphology.classify(0.01, rb * 0.01, gb * 0.01) == expect
+
+
+def test_autograd_wrapper_rejects_bad_shapes():
+    import torch
+    from paper_1808_08555_amd.autograd import ternary_run
+    with pytest.raises(ValueError):
+        ternary_run(torch.zeros(3, dtype=torch.float64), torch.zeros(2, 4, 4, dtype=torch.float64), 2)
+    with pytest.raises(ValueError):
+        ternary_run(torch.zeros(2, dtype=torch.float64), torch.zeros(3, 4, 4, dtype=torch.float64), 2)
