@@ -76,7 +76,7 @@ typedef struct {
     double momentum[2];      /* sum over nodes of rho u */
     double kinetic_energy;   /* sum over nodes of rho |u|^2 / 2 */
     double u_max;            /* max over nodes of |u| */
-    int32_t nonfinite;       /* 1 when any population is NaN or Inf */
+    int32_t nonfinite;       /* 1 when a density, momentum or velocity is NaN or Inf */
 } lbm3_obs;
 
 typedef struct lbm3 lbm3_t;
@@ -122,20 +122,25 @@ const char *lbm3_last_error(void);
 int lbm3_derived(const lbm3_params *p, double X[3], double g[3], double nu[3]);
 
 /* Launch shape of the fused step: threads per workgroup (64, 128, 256 or 512;
- * each workgroup owns a strip of at most threads-4 columns) and rows marched
+ * each workgroup owns a strip of at most threads-6 columns) and rows marched
  * per workgroup (>= 1; 0 = chosen so that the number of workgroups fits the
  * device's resident slots).  Results do not depend on the shape (bitwise).
  * get_tile returns the rows actually used. */
 int lbm3_set_tile(lbm3_t *h, int32_t threads, int32_t rows);
 int lbm3_get_tile(const lbm3_t *h, int32_t *threads, int32_t *rows);
 
-/* Device pointer of the buffer that holds the current state (populations after
- * collision and recolouring, before streaming), its element size in bytes, and
- * its strides in elements: population q = k*9+i of node (x, y) is element
- * q*plane_stride + y*row_pitch + x.  For measurement tools; the layout is not a
- * stable API. */
+/* Device pointer of the buffer that holds the current state, its element size in
+ * bytes, its strides in elements and its number of planes: plane q of node (x, y)
+ * is element q*plane_stride + y*row_pitch + x.  After init_fields / set_state
+ * (and during an adjoint recording) the state is the 27 populations after
+ * collision and recolouring, before streaming (q = k*9 + i, nplanes = 27).  After
+ * lbm3_step it is held factored per node, nplanes = 18: f_dag_i after collision
+ * (q = i), c_k = rho_k/rho (q = 9 + k) and V_k = sum_{l != k} beta_kl (rho_k
+ * rho_l / rho) n_kl (q = 12 + 2k, 13 + 2k), from which Eq. (13) gives every
+ * recoloured population as c_k f_dag_i + w_i V_k . e_i.  For measurement tools;
+ * the layout is not a stable API. */
 int lbm3_state_buffer(const lbm3_t *h, void **dev_ptr, int32_t *elem_bytes, int64_t *plane_stride,
-                      int64_t *row_pitch);
+                      int64_t *row_pitch, int32_t *nplanes);
 
 /* ---- batched form: many independent lattices advanced together ---------------
  * count instances with parameters p[0..count-1] (all the same precision; sizes

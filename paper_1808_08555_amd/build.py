@@ -27,7 +27,8 @@ CFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
-SOURCES = ["lbm3_step.hip", "lbm3_plan.hip", "lbm3_api.hip", "lbm3_batch.hip", "lbm3_adjoint.hip"]
+SOURCES = ["lbm3_tiles_f64.hip", "lbm3_tiles_f32s.hip", "lbm3_tiles_f32.hip", "lbm3_step.hip",
+           "lbm3_plan.hip", "lbm3_api.hip", "lbm3_batch.hip", "lbm3_adjoint.hip"]
 
 
 def _compile(src: str) -> str:

@@ -552,7 +552,7 @@ int lbm3_adjoint_record(lbm3_t* h, int64_t nsteps, int32_t ckpt_every)
     hipError_t e = hipMemcpyAsync(h->ckpt[0], h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream);
     if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
     for (int64_t c = 1; c < nck; ++c) {
-        int rc = lbm3_step(h, ckpt_every);
+        int rc = step_handle(h, ckpt_every, false);
         if (rc) return rc;
         e = hipMemcpyAsync(h->ckpt[c], h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream);
         if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
@@ -618,8 +618,9 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
         // recompute the states B^{sK + j}, j = 0..K-1, of this segment
         e = hipMemcpyAsync(seg, h->ckpt[s], sbytes, hipMemcpyDeviceToDevice, h->stream);
         for (int j = 1; j < K && e == hipSuccess; ++j)
-            e = launch_tiles(Prec::F64, seg + (size_t)(j - 1) * sbytes, seg + (size_t)j * sbytes, h->dinst,
-                             h->dtiles, h->ntiles, h->threads, s * K + j - 1, h->stream);
+            e = launch_tiles(Prec::F64, Fmt::F27, Fmt::F27, seg + (size_t)(j - 1) * sbytes,
+                             seg + (size_t)j * sbytes, h->dinst, h->dtiles, h->ntiles, h->threads,
+                             s * K + j - 1, 0, h->stream);
         if (e != hipSuccess) return hip_fail(e, "adjoint segment recompute");
         for (int j = K - 1; j >= 0; --j) {
             const double* Bj = (const double*)(seg + (size_t)j * sbytes);

@@ -122,21 +122,12 @@ void derive(const lbm3_params* p, KParams* kp, double X[3], double g[3], double 
         std::memset(kp, 0, sizeof *kp);
         kp->nx = p->nx;
         kp->ny = p->ny;
-#ifndef LBM3_ROW_INTERLEAVE
-#define LBM3_ROW_INTERLEAVE 1
-#endif
-#if LBM3_ROW_INTERLEAVE
-        // row y of all 27 planes in one contiguous block: the rows a workgroup reads
-        // together share DRAM pages
+        // the rows of all planes in one contiguous block: the rows a workgroup reads together
+        // share DRAM pages
         kp->plane = ((int64_t)p->nx + 63) / 64 * 64;
         kp->pitch = 27 * kp->plane;
+        kp->fpitch = kFacPlanes * kp->plane;
         kp->span = kp->pitch * p->ny;
-#else
-        const int64_t n = (int64_t)p->nx * p->ny;
-        kp->plane = (n + 255) / 256 * 256;
-        kp->pitch = p->nx;
-        kp->span = 27 * kp->plane;
-#endif
         for (int q = 0; q < 3; ++q) {
             kp->sigma[q] = p->sigma[q];
             kp->g[q] = gl[q];
@@ -213,6 +204,27 @@ int upload_plan(lbm3* h)
     if (e != hipSuccess) return hip_fail(e, "tile plan upload");
     h->ntiles = (int)T.size();
     h->rows = rows;
+    return LBM3_OK;
+}
+
+// Enqueues n fused steps.  A state in the 27-population format (after init_fields or
+// set_state) is converted to the factored format by its first step when `factored`.
+int step_handle(lbm3* h, int64_t n, bool factored)
+{
+    for (int64_t s = 0; s < n; ++s) {
+        const Fmt out = factored ? Fmt::FAC : Fmt::F27;
+        if (h->fmt == Fmt::FAC && !factored) {
+            set_error("the 27-population step needs a state in that format (init_fields / set_state)");
+            return LBM3_ESTATE;
+        }
+        hipError_t e = launch_tiles(h->prec, h->fmt, out, h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst,
+                                    h->dtiles, h->ntiles, h->threads, h->step, 0, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        h->cur ^= 1;
+        h->fmt = out;
+        h->step += 1;
+    }
+    h->tape_valid = false;
     return LBM3_OK;
 }
 
@@ -332,6 +344,7 @@ int lbm3_init_fields(lbm3_t* h, const double* rho, const double* u)
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "init_fields");
     h->cur = 0;
+    h->fmt = Fmt::F27;
     h->step = 0;
     h->ready = true;
     h->tape_valid = false;
@@ -358,6 +371,7 @@ int lbm3_set_state(lbm3_t* h, const double* f)
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "set_state");
     h->cur = 0;
+    h->fmt = Fmt::F27;
     h->step = 0;
     h->ready = true;
     h->tape_valid = false;
@@ -379,15 +393,7 @@ int lbm3_step(lbm3_t* h, int64_t n)
         set_error("lbm3_step before lbm3_init_fields / lbm3_set_state");
         return LBM3_ESTATE;
     }
-    for (int64_t s = 0; s < n; ++s) {
-        hipError_t e = launch_tiles(h->prec, h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst, h->dtiles,
-                                    h->ntiles, h->threads, h->step, h->stream);
-        if (e != hipSuccess) return hip_fail(e, "step launch");
-        h->cur ^= 1;
-        h->step += 1;
-    }
-    h->tape_valid = false;
-    return LBM3_OK;
+    return step_handle(h, n, true);
 }
 
 int lbm3_observables(lbm3_t* h, lbm3_obs* out, double* rho_out, double* f_out)
@@ -404,9 +410,9 @@ int lbm3_observables(lbm3_t* h, lbm3_obs* out, double* rho_out, double* f_out)
     int rc = ensure_partials(h, h->ntiles);
     if (!rc && (rho_out || f_out)) rc = ensure_staging(h, (size_t)27 * n);
     if (rc) return rc;
-    hipError_t e = launch_observe_tiles(h->prec, h->buf[h->cur], h->dinst, h->dtiles, h->ntiles,
-                                        h->threads, h->partials, rho_out ? h->staging : nullptr,
-                                        h->stream);
+    hipError_t e = launch_observe_tiles(h->prec, h->fmt, h->buf[h->cur], h->dinst, h->dtiles,
+                                        h->ntiles, h->threads, h->partials,
+                                        rho_out ? h->staging : nullptr, h->stream);
     if (e == hipSuccess) e = launch_reduce_obs(h->partials, h->ntiles, h->obs_dev, h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->obs_host, h->obs_dev, kObsFields * sizeof(double),
@@ -415,7 +421,7 @@ int lbm3_observables(lbm3_t* h, lbm3_obs* out, double* rho_out, double* f_out)
         e = hipMemcpyAsync(rho_out, h->staging, 3 * n * sizeof(double), hipMemcpyDeviceToHost,
                            h->stream);
     if (e == hipSuccess && f_out) {
-        e = launch_export(h->prec, h->buf[h->cur], h->staging, h->kp, h->stream);
+        e = launch_export(h->prec, h->fmt, h->buf[h->cur], h->staging, h->kp, h->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(f_out, h->staging, 27 * n * sizeof(double), hipMemcpyDeviceToHost,
                                h->stream);
@@ -489,16 +495,19 @@ int lbm3_get_tile(const lbm3_t* h, int32_t* threads, int32_t* rows)
     return LBM3_OK;
 }
 
-int lbm3_state_buffer(const lbm3_t* h, void** dev_ptr, int32_t* eb, int64_t* plane, int64_t* pitch)
+int lbm3_state_buffer(const lbm3_t* h, void** dev_ptr, int32_t* eb, int64_t* plane, int64_t* pitch,
+                      int32_t* nplanes)
 {
     if (!h) {
         set_error("handle is NULL");
         return LBM3_EINVAL;
     }
+    const bool fac = h->fmt == Fmt::FAC;
     if (dev_ptr) *dev_ptr = h->buf[h->cur];
     if (eb) *eb = (int32_t)elem_bytes(h->prec);
     if (plane) *plane = h->kp.plane;
-    if (pitch) *pitch = h->kp.pitch;
+    if (pitch) *pitch = fac ? h->kp.fpitch : h->kp.pitch;
+    if (nplanes) *nplanes = fac ? kFacPlanes : 27;
     return LBM3_OK;
 }
 

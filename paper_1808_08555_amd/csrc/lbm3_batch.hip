@@ -2,6 +2,9 @@
 // one precision) in one device arena.  One launch of the fused step covers the tiles of
 // every instance (a flat tile list, dealt to the XCDs in contiguous runs); a captured
 // hipGraph of kGraphSteps such launches advances all instances with one graph launch.
+// Instances hold the factored state after their first step; a step that finds some
+// instances freshly initialised (27-population format) runs as two launches over the same
+// list, each skipping the instances of the other format.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -38,6 +41,7 @@ struct lbm3_batch {
     double* obs_dev = nullptr;
     double* obs_host = nullptr;
     std::vector<char> ready;
+    std::vector<tcg::Fmt> fmt;  // per instance: F27 after init_fields, FAC after a step
 };
 
 using namespace tcg;
@@ -128,8 +132,8 @@ static int build_graph(lbm3_batch* b, int parity)
     int c = parity;
     hipError_t le = hipSuccess;
     for (int s = 0; s < kGraphSteps && le == hipSuccess; ++s) {
-        le = launch_tiles(b->prec, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles, b->ntiles,
-                          b->threads, s, b->stream);
+        le = launch_tiles(b->prec, Fmt::FAC, Fmt::FAC, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles,
+                          b->ntiles, b->threads, s, 0, b->stream);
         c ^= 1;
     }
     e = hipStreamEndCapture(b->stream, &g);
@@ -196,6 +200,7 @@ int lbm3_batch_create(const lbm3_params* p, int32_t count, void* hip_stream, lbm
     b->prec = prec_of(p[0].precision);
     b->inst.resize(count);
     b->ready.assign(count, 0);
+    b->fmt.assign(count, Fmt::F27);
     int64_t total = 0;
     int max_side = 0;
     for (int i = 0; i < count; ++i) {
@@ -279,6 +284,7 @@ int lbm3_batch_init_fields(lbm3_batch_t* b, int32_t idx, const double* rho, cons
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return hip_fail(e, "batch init_fields");
     b->ready[idx] = 1;
+    b->fmt[idx] = Fmt::F27;
     return LBM3_OK;
 }
 
@@ -297,6 +303,32 @@ int lbm3_batch_step(lbm3_batch_t* b, int64_t n)
             set_error("instance %d has not been initialised", i);
             return LBM3_ESTATE;
         }
+    if (n > 0) {
+        // first step of freshly initialised instances: 27-population -> factored format
+        int n27 = 0;
+        for (Fmt f : b->fmt) n27 += f == Fmt::F27;
+        if (n27 > 0) {
+            hipError_t e = hipSuccess;
+            if (n27 < b->count) {
+                for (int i = 0; i < b->count; ++i) b->inst[i].fmt = (int32_t)b->fmt[i];
+                e = hipMemcpyAsync(b->dinst, b->inst.data(), b->count * sizeof(Instance),
+                                   hipMemcpyHostToDevice, b->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+                if (e == hipSuccess)
+                    e = launch_tiles(b->prec, Fmt::FAC, Fmt::FAC, b->buf[b->cur], b->buf[b->cur ^ 1],
+                                     b->dinst, b->dtiles, b->ntiles, b->threads, b->step, 1, b->stream);
+            }
+            if (e == hipSuccess)
+                e = launch_tiles(b->prec, Fmt::F27, Fmt::FAC, b->buf[b->cur], b->buf[b->cur ^ 1],
+                                 b->dinst, b->dtiles, b->ntiles, b->threads, b->step,
+                                 n27 < b->count ? 1 : 0, b->stream);
+            if (e != hipSuccess) return hip_fail(e, "batch step launch");
+            for (auto& f : b->fmt) f = Fmt::FAC;
+            b->cur ^= 1;
+            b->step += 1;
+            n -= 1;
+        }
+    }
     while (n >= kGraphSteps) {
         if (!b->exec[b->cur]) {
             int rc = build_graph(b, b->cur);
@@ -308,8 +340,8 @@ int lbm3_batch_step(lbm3_batch_t* b, int64_t n)
         b->step += kGraphSteps;
     }
     for (; n > 0; --n) {
-        hipError_t e = launch_tiles(b->prec, b->buf[b->cur], b->buf[b->cur ^ 1], b->dinst, b->dtiles,
-                                    b->ntiles, b->threads, b->step, b->stream);
+        hipError_t e = launch_tiles(b->prec, Fmt::FAC, Fmt::FAC, b->buf[b->cur], b->buf[b->cur ^ 1],
+                                    b->dinst, b->dtiles, b->ntiles, b->threads, b->step, 0, b->stream);
         if (e != hipSuccess) return hip_fail(e, "batch step launch");
         b->cur ^= 1;
         b->step += 1;
@@ -343,8 +375,9 @@ int lbm3_batch_observables(lbm3_batch_t* b, int32_t idx, lbm3_obs* out, double* 
         int rc = ensure_batch_staging(b, (size_t)3 * n);
         if (rc) return rc;
     }
-    hipError_t e = launch_observe_tiles(b->prec, b->buf[b->cur], b->dinst, b->dobs + b->obs_first[idx], nb,
-                                        b->threads, b->partials, rho_out ? b->staging : nullptr, b->stream);
+    hipError_t e = launch_observe_tiles(b->prec, b->fmt[idx], b->buf[b->cur], b->dinst,
+                                        b->dobs + b->obs_first[idx], nb, b->threads, b->partials,
+                                        rho_out ? b->staging : nullptr, b->stream);
     if (e == hipSuccess) e = launch_reduce_obs(b->partials, nb, b->obs_dev, b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->obs_host, b->obs_dev, kObsFields * sizeof(double), hipMemcpyDeviceToHost, b->stream);

@@ -13,6 +13,7 @@ struct lbm3 {
     int device = 0;
     void* buf[2] = {nullptr, nullptr};  // population buffers (pull scheme, ping-pong)
     int cur = 0;                        // buffer holding the current state
+    tcg::Fmt fmt = tcg::Fmt::F27;       // its format: F27 after init / set_state, FAC after a step
     int64_t step = 0;
     bool ready = false;
     bool init_at_rest = false;          // state came from init_fields with u == NULL
@@ -44,4 +45,6 @@ void default_tile(const KParams& kp, int* threads, int* rows);
 int check_rho_fields(const double* rho, const double* u, int64_t n);
 int upload_plan(lbm3* h);
 void adjoint_release(lbm3* h);
+// Enqueues n steps; factored = false keeps the 27-population format (the adjoint's tape).
+int step_handle(lbm3* h, int64_t n, bool factored);
 }  // namespace tcg

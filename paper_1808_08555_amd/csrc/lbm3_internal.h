@@ -15,9 +15,10 @@ namespace tcg {
 // Pair index p: 0 = (red, green), 1 = (red, blue), 2 = (green, blue).
 struct KParams {
     int32_t nx, ny;
-    int64_t plane;      // elements between the same node in consecutive population planes
-    int64_t pitch;      // elements between consecutive rows of one plane
-    int64_t span;       // elements of one population buffer (27 planes)
+    int64_t plane;      // elements between the same node in consecutive planes
+    int64_t pitch;      // row pitch of the 27-population layout (27 planes, rows interleaved)
+    int64_t fpitch;     // row pitch of the factored layout (18 planes, rows interleaved)
+    int64_t span;       // elements of one state buffer (room for 27 planes)
     double sigma[3];    // sigma_kl per pair
     double g[3];        // g(X_kl) of the segregation law, Eq. (20)
     double beta0;       // reference segregation parameter, Eq. (19)
@@ -26,7 +27,7 @@ struct KParams {
     double guard;       // |G_kl| at or below which n_kl = 0 and the stress is 0
 };
 
-// One workgroup's share of a lattice: output columns [x0, x0 + cols) (cols <= threads - 4)
+// One workgroup's share of a lattice: output columns [x0, x0 + cols) (cols <= threads - 6)
 // and output rows [y0, y0 + rows) of instance `inst`.
 struct Tile {
     int32_t inst;
@@ -38,6 +39,8 @@ struct Tile {
 struct Instance {
     KParams kp;
     int64_t offset;  // element offset of plane 0 in each of the two arenas
+    int32_t fmt;     // Fmt of the instance's current state (read when a launch filters by it)
+    int32_t pad;
 };
 
 // Observables partials: 3 masses, 2 momenta, kinetic energy, max|u|, nonfinite flag.
@@ -45,25 +48,34 @@ constexpr int kObsFields = 8;
 
 enum class Prec { F64, F32S, F32 };
 
-// Launchers (lbm3_step.hip).  All asynchronous on `stream`.
-hipError_t launch_tiles(Prec prec, const void* fin, void* fout, const Instance* inst,
-                        const Tile* tiles, int ntiles, int threads, int64_t step, hipStream_t stream);
-hipError_t launch_observe_tiles(Prec prec, const void* fin, const Instance* inst, const Tile* tiles,
-                                int ntiles, int threads, double* partials, double* rho_out,
-                                hipStream_t stream);
+// State formats.  F27: the 27 recoloured populations f_ddag_{i,k} of every node, before
+// streaming.  FAC: the same state factored per node as f_dag_i (9), c_k (3) and V_k (6), from
+// which f_ddag_{i,k} = c_k f_dag_i + w_i V_k . e_i is rebuilt exactly where it is pulled.
+enum class Fmt : int32_t { F27 = 0, FAC = 1 };
+constexpr int kFacPlanes = 18;
+
+// Launchers (lbm3_step.hip).  All asynchronous on `stream`.  One fused step from a state in
+// format `in` to one in format `out` (F27 -> F27, F27 -> FAC or FAC -> FAC); with
+// filter != 0 a workgroup whose instance is not in format `in` does nothing.
+hipError_t launch_tiles(Prec prec, Fmt in, Fmt out, const void* fin, void* fout, const Instance* inst,
+                        const Tile* tiles, int ntiles, int threads, int64_t step, int filter,
+                        hipStream_t stream);
+hipError_t launch_observe_tiles(Prec prec, Fmt in, const void* fin, const Instance* inst,
+                                const Tile* tiles, int ntiles, int threads, double* partials,
+                                double* rho_out, hipStream_t stream);
 hipError_t launch_reduce_obs(const double* partials, int nblocks, double* out, hipStream_t stream);
 hipError_t launch_init(Prec prec, const double* rho, const double* u, void* fout,
                        const KParams& kp, hipStream_t stream);
 hipError_t launch_import(Prec prec, const double* f, void* fout, const KParams& kp,
                          hipStream_t stream);
-hipError_t launch_export(Prec prec, const void* fin, double* f, const KParams& kp,
+hipError_t launch_export(Prec prec, Fmt in, const void* fin, double* f, const KParams& kp,
                          hipStream_t stream);
 hipError_t launch_copy(void* dst, const void* src, int64_t nbytes, hipStream_t stream);
 int blocks_per_cu(Prec prec, int threads);
 
 // Tile plans (lbm3_plan.hip).
 // Tiles of one lattice in locality order (strip by strip, rows upward): strips of at most
-// threads-4 columns spread evenly over nx (line-aligned when nx allows), segments of about
+// threads-6 columns spread evenly over nx (line-aligned when nx allows), segments of about
 // `rows` rows spread evenly over ny.
 void plan_lattice(int inst, int nx, int ny, int threads, int rows, int elem_bytes,
                   std::vector<Tile>& out);
@@ -76,6 +88,18 @@ int auto_rows(int nx, int ny, int threads, int slots, int elem_bytes);
 int device_slots(Prec prec, int threads);
 
 size_t elem_bytes(Prec p);
+uint32_t step_salt(int64_t step);
+
+// Per-precision instantiations of the fused step (lbm3_tiles_*.hip).
+#define LBM3_TILES_DECL(NAME)                                                                    \
+    hipError_t NAME(Fmt in, Fmt out, bool obs, const void* fin, void* fout, const Instance* inst, \
+                    const Tile* tiles, int ntiles, int threads, uint32_t salt, int filter,        \
+                    double* partials, double* rho_out, hipStream_t stream);                       \
+    int NAME##_occupancy(int threads);
+LBM3_TILES_DECL(tiles_f64)
+LBM3_TILES_DECL(tiles_f32s)
+LBM3_TILES_DECL(tiles_f32)
+#undef LBM3_TILES_DECL
 
 // Host-side helpers (lbm3_api.hip).
 void set_error(const char* fmt, ...);

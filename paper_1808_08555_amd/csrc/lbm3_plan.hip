@@ -8,17 +8,17 @@ namespace tcg {
 void plan_lattice(int inst, int nx, int ny, int threads, int rows, int elem_bytes,
                   std::vector<Tile>& out)
 {
-    const int wmax = threads - 4;
+    const int wmax = threads - 6;
     const int nseg = std::max(1, (ny + std::max(rows, 1) - 1) / std::max(rows, 1));
     // Line-aligned strips: widths in units of A elements (one 128-byte line) and strips
-    // starting at x = 2 (mod A), so that lane 0 of every wavefront (column x0 - 2 + 64 w) sits
-    // on a line boundary and unshifted loads and all stores cover whole lines.  Used when nx
-    // is a multiple of A and a unit-aligned strip width fits the workgroup.
+    // starting at x = 3 (mod A), so that lane 0 of every wavefront (column x0 - 3 + 64 w) sits
+    // on a line boundary and unshifted loads cover whole lines.  Used when nx is a multiple
+    // of A and a unit-aligned strip width fits the workgroup.
     const int A = 128 / elem_bytes;
     const int wA = wmax / A * A;
-    const bool aligned = nx % A == 0 && wA >= A && nx > 4;
+    const bool aligned = nx % A == 0 && wA >= A && nx > 6;
     const int nstrips = aligned ? (nx / A + wA / A - 1) / (wA / A) : (nx + wmax - 1) / wmax;
-    int x0 = aligned ? 2 : 0;
+    int x0 = aligned ? 3 : 0;
     for (int sx = 0; sx < nstrips; ++sx) {
         const int cols = aligned ? ((nx / A) / nstrips + (sx < (nx / A) % nstrips ? 1 : 0)) * A
                                  : nx / nstrips + (sx < nx % nstrips ? 1 : 0);

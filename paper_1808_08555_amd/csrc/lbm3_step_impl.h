@@ -1,0 +1,706 @@
+// The fused ternary colour-gradient LBM time step for CDNA4 (gfx950): device code shared by
+// the per-precision instantiations (lbm3_tiles_*.hip) and the companion kernels
+// (lbm3_step.hip).
+//
+// One time step (Yu, Liu, Liang, Zhang, arXiv:1808.08555, Sec. 2) at node x:
+//   pull:     f_{i,k}(x) = state_{i,k}(x - e_i)                              (Eq. 22)
+//   moments:  rho_k = sum_i f_{i,k}, f_i = sum_k f_{i,k}, c_k = rho_k / rho
+//   gradient: grad c_k by the isotropic difference of Eq. (12)
+//   stress:   T = sum over pairs sigma_kl C_kl |G_kl| (I - n_kl n_kl)   (Eq. 7, the
+//             ordered double sum with 1/2 collapsed to one term per unordered pair,
+//             since G_lk = -G_kl), C_kl of Eq. (6), G_kl = c_l grad c_k - c_k grad c_l
+//   force:    F = div T, again with the difference of Eq. (12)
+//   collide:  local tau from the harmonic viscosity mean (Eqs. 10-11), u with the
+//             half force (Eq. 9), f_eq (Eq. 3), Guo term (Eq. 8), BGK (Eqs. 1-2)
+//   recolour: f_ddag_{i,k} = c_k f_dag_i + w_i V_k . e_i, V_k = sum_{l != k} beta_kl
+//             (rho_k rho_l / rho) n_kl with beta_kl of Eqs. (19)-(20)      (Eq. 13)
+//   store:    the recoloured state of x, in one of two formats:
+//             F27  the 27 values f_ddag_{i,k}(x);
+//             FAC  the 18 values f_dag_i(x), c_k(x), V_k(x).  Eq. (13) makes every
+//                  f_ddag_{i,k}(x) a function of these, so the next step rebuilds the
+//                  populations it pulls from x - e_i, with the same arithmetic (recon()) the
+//                  F27 store uses: both formats give bitwise the same next state when the
+//                  storage type is the compute type.  FAC moves 2/3 of the bytes of F27.
+//
+// Layout: plane q of node (x, y) at element q*plane + y*pitch + x, x fastest, with the rows of
+// all planes interleaved (pitch = 27 plane for F27, 18 plane for FAC), so one lattice row
+// of the state is one contiguous block and a wavefront's 64 lanes touch 64 consecutive values
+// of one plane row.  FAC planes: 0-8 f_dag_i, 9-11 c_k, 12-17 (V_kx, V_ky) for k = 0, 1, 2.
+//
+// Work decomposition (y-marching strips).  A workgroup of NT threads owns a strip of
+// cols <= NT-6 output columns and a run of `rows` output rows.  Thread t sits on column
+// x0 - 3 + t and marches up the rows.  Per row, stage 1 obtains the 9 totals and 3
+// densities of its column (F27: 27 pulled loads; FAC: 9 pulled f_dag loads plus the c_k and
+// V_k of the source row, shared with the neighbouring columns through LDS) and keeps them
+// in a register pipeline; the concentrations go to a three-row LDS ring.  One row behind,
+// stage 2 forms the colour gradients, pair normals and the stress T (three-row LDS ring);
+// two rows behind, stage 3 takes the divergence of T and finishes collision and
+// recolouring for the output row.  Every stored value is read from HBM once per step (plus
+// a 3-column and 4-row halo that other workgroups also read) and written once; densities,
+// gradients and stress never leave the chip.
+#pragma once
+
+#include "lbm3_internal.h"
+
+namespace tcg {
+namespace {
+
+constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+// D2Q9 weights.  In FP64 the rest weight is taken as 1 - 4 w_1 - 4 w_5, the double one
+// ulp above the nearest to 4/9, so that the nine weights sum to exactly 1: with the nearest
+// doubles the sum is 1 - 5.55e-17 and every collision would scale the mass by that much.
+template <typename C>
+__device__ __forceinline__ constexpr C wgt(int i)
+{
+    if constexpr (sizeof(C) == 8)
+        return i == 0 ? 1.0 - 4.0 * (1.0 / 9.0) - 4.0 * (1.0 / 36.0)
+                      : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    else
+        return i == 0 ? C(4.0 / 9.0) : (i < 5 ? C(1.0 / 9.0) : C(1.0 / 36.0));
+}
+
+// 32-bit integer mixer ("lowbias32", from Wellons' hash-prospector search): a bijection with
+// low output bias, used as a counter-based generator keyed by (step, node, value index).
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+// FP64 -> FP32 with stochastic rounding: v lies between two adjacent floats a (toward zero)
+// and b (away from zero); the result is b with probability (v - a)/(b - a), else a, so its
+// expected value is v.  Round to nearest would lose the sub-ulp per-step changes of the
+// near-uniform bulk with a sign that is the same at many nodes, which shows up as a steady
+// drift of each fluid's mass.  The gap is taken on the correct side of a power of two:
+// values just below one (the concentration of a nearly pure fluid) round on the finer grid
+// below it.
+__device__ __forceinline__ float round_stochastic(double v, uint32_t bits)
+{
+    const float a = __double2float_rz(v);
+    const double rem = fabs(v - (double)a);
+    if (!(rem > 0.0)) return a;
+    const float b = nextafterf(a, v > 0.0 ? __builtin_huge_valf() : -__builtin_huge_valf());
+    const double gap = fabs((double)b - (double)a);
+    const double u = (double)(bits >> 8) * (1.0 / 16777216.0);
+    return u * gap < rem ? b : a;
+}
+
+// Store of one value in the storage type S from the compute type C.
+template <typename S, typename C>
+__device__ __forceinline__ S to_storage(C v, uint32_t key)
+{
+    if constexpr (sizeof(S) == 4 && sizeof(C) == 8)
+        return round_stochastic(v, mix32(key));
+    else
+        return S(v);
+}
+
+__device__ __forceinline__ int wrapi(int a, int n)
+{
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// Row pointers that are the same in every lane are rebuilt from scalar registers in the
+// global address space, opaque to the optimiser, so that they are not re-associated with
+// the per-lane column offset (which would turn every access into a hoisted 64-bit
+// per-lane address) and every access compiles to the scalar-base + 32-bit vector-offset
+// form of the global load/store.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* base, unsigned byte_off)
+{
+    typedef const __attribute__((address_space(1))) char gchar;
+    typedef const __attribute__((address_space(1))) T gT;
+    gchar* b = (gchar*)uniform_u64(reinterpret_cast<uint64_t>(base));
+    return *(gT*)(b + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T* base, unsigned byte_off, T v)
+{
+    typedef __attribute__((address_space(1))) char gchar;
+    typedef __attribute__((address_space(1))) T gT;
+    gchar* b = (gchar*)uniform_u64(reinterpret_cast<uint64_t>(base));
+    *(gT*)(b + byte_off) = v;
+}
+
+// Isotropic difference of Eq. (12), 3 sum_i w_i phi(x + e_i) e_i, written as weighted
+// differences of opposite neighbours.  The grouping keeps exact zeros for data that
+// are mirror-symmetric about the node, also when the compiler fuses multiply-adds.
+template <typename C>
+__device__ __forceinline__ C ddx(C e, C w, C ne, C nw, C se, C sw)
+{
+    return C(3) * (C(1.0 / 9.0) * (e - w) + C(1.0 / 36.0) * ((ne - sw) + (se - nw)));
+}
+template <typename C>
+__device__ __forceinline__ C ddy(C n, C s, C ne, C nw, C se, C sw)
+{
+    return C(3) * (C(1.0 / 9.0) * (n - s) + C(1.0 / 36.0) * ((ne - sw) + (nw - se)));
+}
+
+// V . e_i for the nine lattice directions, written out (no multiplications by 0 or 1).
+template <typename C>
+__device__ __forceinline__ C dot_e(C vx, C vy, int i)
+{
+    switch (i) {
+        case 1: return vx;
+        case 2: return vy;
+        case 3: return -vx;
+        case 4: return -vy;
+        case 5: return vx + vy;
+        case 6: return vy - vx;
+        case 7: return -(vx + vy);
+        case 8: return vx - vy;
+        default: return C(0);
+    }
+}
+
+// One recoloured population of Eq. (13) from the factored node state: c_k f_dag_i +
+// w_i V_k . e_i, as one fused multiply-add.  The F27 store and the FAC pull both call this.
+template <typename C>
+__device__ __forceinline__ C recon(C ck, C fdi, C vx, C vy, int i)
+{
+    // the rest population's product is rounded on its own, never fused into a later sum, so
+    // a value rebuilt in registers equals the same value stored and loaded back
+#pragma clang fp contract(off)
+    if (i == 0) return ck * fdi;
+    return fma(ck, fdi, wgt<C>(i) * dot_e<C>(vx, vy, i));
+}
+
+// Densities from the 27 pulled populations v[k*9 + i], summed in a fixed order that groups
+// the directions by the source row they come from (e_y = +1, 0, -1), so that the F27 pull
+// and the row-by-row FAC pull add the same values in the same order.
+template <typename C>
+__device__ __forceinline__ C group_sum(C a, C b, C c)
+{
+    return (a + b) + c;
+}
+
+template <typename C>
+struct StepConsts {
+    C sig[3], g[3], beta0, inv_nu[3], cfac[3], guard;
+    __device__ explicit StepConsts(const KParams& kp)
+    {
+        for (int p = 0; p < 3; ++p) {
+            sig[p] = C(kp.sigma[p]);
+            g[p] = C(kp.g[p]);
+            inv_nu[p] = C(kp.inv_nu[p]);
+            cfac[p] = C(kp.cfac[p]);
+        }
+        beta0 = C(kp.beta0);
+        guard = C(kp.guard);
+    }
+};
+
+// Collision (Eqs. 1-3, 8-11) and the recolouring factors (Eqs. 13, 19, 20) at one node,
+// given the totals f[9], densities rk[3], pair normals n[6] (pairs rg, rb, gb) and the
+// force.  Returns f_dag, c_k, V_k (V[2k], V[2k+1]) and u, rho u for observables.
+template <typename C>
+__device__ __forceinline__ void collide_recolour(const C (&f)[9], const C (&rk)[3],
+                                                 const C (&n)[6], C Fx, C Fy,
+                                                 const StepConsts<C>& K, C (&fd)[9], C (&ck)[3],
+                                                 C (&V)[6], C& ux, C& uy, C& mxh, C& myh)
+{
+    const C rho = rk[0] + rk[1] + rk[2];
+    const C irho = C(1) / rho;
+    // rho / nu = sum_k rho_k / nu_k ; tau = 3 nu + 1/2
+    const C rho_over_nu = rk[0] * K.inv_nu[0] + rk[1] * K.inv_nu[1] + rk[2] * K.inv_nu[2];
+    const C tau = C(3) * rho / rho_over_nu + C(0.5);
+    const C itau = C(1) / tau;
+    // rho u = sum_i f_i e_i + F/2
+    const C mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const C my = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
+    mxh = mx + C(0.5) * Fx;
+    myh = my + C(0.5) * Fy;
+    ux = mxh * irho;
+    uy = myh * irho;
+    const C uu = ux * ux + uy * uy;
+    const C uF = ux * Fx + uy * Fy;
+    const C pref = C(1) - C(0.5) * itau;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const C eu = C(EX[i]) * ux + C(EY[i]) * uy;
+        const C eF = C(EX[i]) * Fx + C(EY[i]) * Fy;
+        const C feq = wgt<C>(i) * rho * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
+        const C phi = wgt<C>(i) * pref * (C(3) * (eF - uF) + C(9) * eu * eF);
+        fd[i] = f[i] - (f[i] - feq) * itau + phi;
+    }
+    // C_t and beta_kl of Eq. (19); a_p = beta_p rho_k rho_l / rho
+    C ct = C(35) * rk[0] * rk[1] * rk[2] * (irho * irho * irho);
+    ct = ct < C(1) ? ct : C(1);
+    const C a0 = K.beta0 * (C(1) + ct * K.g[0]) * (rk[0] * rk[1]) * irho;
+    const C a1 = K.beta0 * (C(1) + ct * K.g[1]) * (rk[0] * rk[2]) * irho;
+    const C a2 = K.beta0 * (C(1) + ct * K.g[2]) * (rk[1] * rk[2]) * irho;
+    // V_k = sum_{l != k} a_kl n_kl with n_lk = -n_kl
+    V[0] = a0 * n[0] + a1 * n[2];
+    V[1] = a0 * n[1] + a1 * n[3];
+    V[2] = a2 * n[4] - a0 * n[0];
+    V[3] = a2 * n[5] - a0 * n[1];
+    V[4] = -(a1 * n[2] + a2 * n[4]);
+    V[5] = -(a1 * n[3] + a2 * n[5]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ck[k] = rk[k] * irho;
+}
+
+// The y-marching body shared by the stepping and observing kernels.  The workgroup owns
+// output columns [x0, x0 + cols) (cols <= NT - 6) and output rows [y0, y0 + rows).  Lane t
+// sits on column x0 - 3 + t; lanes 1..cols+4 form densities, 2..cols+3 gradients and
+// stress, 3..cols+2 outputs (FAC input: lanes 0..cols+5 also load their column's c_k, V_k
+// for the neighbours).  Iteration j completes the densities of row y0 - 2 + j (stage 1),
+// the stress of the row below (stage 2) and the output row y0 - 4 + j (stage 3).
+// Loop-carried per-thread state: the next input prefetched one iteration ahead (so that
+// the loads are in flight while stages 2 and 3 compute); fA, rA = totals and densities of
+// the row below, fB, rB two rows below; nB = pair normals two rows below.  With FAC input,
+// also the partial totals and densities of the two rows above (they collect the pulls of
+// each source row as it arrives).  LDS rings are indexed by row mod 3.
+template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT>
+__device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__ fout,
+                                      const KParams& kp, int x0, int y0, int rows, int cols,
+                                      C (*cring)[3][NT], C (*tring)[3][NT], C (*xb)[NT],
+                                      double (&acc)[kObsFields], double* __restrict__ rho_out,
+                                      uint32_t salt)
+{
+    const int nx = kp.nx, ny = kp.ny;
+    const int64_t plane = kp.plane;
+    const int t = threadIdx.x;
+    const int xr = x0 - 3 + t;
+    const int x = wrapi(xr, nx);
+    // source column for e_x = -1, 0, +1 as byte offsets from a uniform row pointer
+    const unsigned scol[3] = {(unsigned)wrapi(x + 1, nx) * (unsigned)sizeof(S),
+                              (unsigned)x * (unsigned)sizeof(S),
+                              (unsigned)wrapi(x - 1, nx) * (unsigned)sizeof(S)};
+    const unsigned xoff = (unsigned)x * (unsigned)sizeof(S);
+    const bool in0 = t <= cols + 5;
+    const bool in1 = (t >= 1) && (t <= cols + 4);
+    const bool in2 = (t >= 2) && (t <= cols + 3);
+    const bool in3 = (t >= 3) && (t <= cols + 2);
+    const StepConsts<C> K(kp);
+    const int J = rows + 4;
+
+    // ---- input: F27 pulls all 27 populations of a row directly
+    constexpr int NV = IN == Fmt::F27 ? 27 : 18;
+    auto load_f27 = [&](int j, C (&v)[NV]) {
+        const int64_t pitch = kp.pitch;
+        const int r = wrapi(y0 - 2 + j, ny);
+        const int64_t srow[3] = {(int64_t)wrapi(r + 1, ny) * pitch, (int64_t)r * pitch,
+                                 (int64_t)wrapi(r - 1, ny) * pitch};
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                v[k * 9 + i] = C(ld_at(fin + ((int64_t)(k * 9 + i) * plane + srow[EY[i] + 1]),
+                                       scol[EX[i] + 1]));
+    };
+    // ---- input: FAC loads source row s: v[0..8] = f_dag_i(x - e_x,i, s) (pulled along x),
+    // v[9..17] = c_k, V_k of the lane's own column
+    auto load_fac = [&](int s, C (&v)[NV]) {
+        const int64_t rowo = (int64_t)wrapi(s, ny) * kp.fpitch;
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            v[i] = C(ld_at(fin + ((int64_t)i * plane + rowo), scol[EX[i] + 1]));
+#pragma unroll
+        for (int q = 9; q < NV; ++q) v[q] = C(ld_at(fin + ((int64_t)q * plane + rowo), xoff));
+    };
+    // FAC partial sums: D0 = row s (directions with e_y = +1 and 0 received), D1 = row s + 1
+    // (e_y = +1 received).  Direction groups by e_y: +1 {2, 5, 6}, 0 {0, 1, 3}, -1 {4, 7, 8}.
+    C d0r[3], d0f[6], d1r[3], d1f[3];  // d0f: f_2, f_5, f_6, f_0, f_1, f_3; d1f: f_2, f_5, f_6
+    // FAC: publish the c_k, V_k of this lane's column of the source row (v[9..17]) to the
+    // neighbouring lanes; the caller synchronises before consume_fac reads them.
+    auto publish = [&](const C (&v)[NV]) {
+        if constexpr (IN == Fmt::FAC) {
+            if (in0) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) xb[q][t] = v[9 + q];
+            }
+        }
+    };
+    // FAC: the pulls of source row s (f_dag in v[0..8], c_k and V_k in xb) to rows s+1, s
+    // and s-1, in the fixed group order; completes row s-1 into r0, f0.
+    auto consume_fac = [&](const C (&v)[NV], C (&r0)[3], C (&f0)[9]) {
+        if (!in1) return;
+        auto pull = [&](int i, C (&fk)[3]) {
+            const int l = t - EX[i];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                fk[k] = recon<C>(xb[k][l], v[i], xb[3 + 2 * k][l], xb[4 + 2 * k][l], i);
+        };
+        auto group = [&](int a, int b, int c, C (&g)[3], C& ta, C& tb, C& tc) {
+            C fa[3], fb[3], fc[3];
+            pull(a, fa);
+            pull(b, fb);
+            pull(c, fc);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) g[k] = group_sum<C>(fa[k], fb[k], fc[k]);
+            ta = (fa[0] + fa[1]) + fa[2];
+            tb = (fb[0] + fb[1]) + fb[2];
+            tc = (fc[0] + fc[1]) + fc[2];
+        };
+        C g[3];
+        // e_y = -1: completes row s - 1 as (P + Z) + M.  (The scheduling barriers keep the
+        // LDS reads of one group from being hoisted above the previous group, which would
+        // hold all 81 of them in registers at once.)
+        group(4, 7, 8, g, f0[4], f0[7], f0[8]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r0[k] = d0r[k] + g[k];
+        f0[2] = d0f[0];
+        f0[5] = d0f[1];
+        f0[6] = d0f[2];
+        f0[0] = d0f[3];
+        f0[1] = d0f[4];
+        f0[3] = d0f[5];
+        // e_y = 0: row s is P (from s - 1) + Z
+        group(0, 1, 3, g, d0f[3], d0f[4], d0f[5]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d0r[k] = d1r[k] + g[k];
+        d0f[0] = d1f[0];
+        d0f[1] = d1f[1];
+        d0f[2] = d1f[2];
+        __builtin_amdgcn_sched_barrier(0);
+        // e_y = +1: row s + 1 starts with P
+        group(2, 5, 6, d1r, d1f[0], d1f[1], d1f[2]);
+    };
+    // F27: densities and totals of a row from its 27 pulled populations, same order.
+    auto consume_f27 = [&](const C (&v)[NV], C (&r0)[3], C (&f0)[9]) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const C P = group_sum<C>(v[k * 9 + 2], v[k * 9 + 5], v[k * 9 + 6]);
+            const C Z = group_sum<C>(v[k * 9 + 0], v[k * 9 + 1], v[k * 9 + 3]);
+            const C M = group_sum<C>(v[k * 9 + 4], v[k * 9 + 7], v[k * 9 + 8]);
+            r0[k] = (P + Z) + M;
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f0[i] = (v[i] + v[9 + i]) + v[18 + i];
+    };
+
+    C fA[9], fB[9], rA[3], rB[3], nB[6], vn[NV];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fA[i] = fB[i] = C(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rA[k] = rB[k] = C(1);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) nB[q] = C(0);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) vn[q] = C(1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d0r[k] = d1r[k] = C(0);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) d0f[q] = C(0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) d1f[q] = C(0);
+
+    if constexpr (IN == Fmt::F27) {
+        if (in1) load_f27(0, vn);
+    } else {
+        // pre-roll: source rows y0 - 3 and y0 - 2 start the partial sums of row y0 - 2
+        if (in0) load_fac(y0 - 3, vn);
+#pragma unroll 1
+        for (int p = 0; p < 2; ++p) {
+            C v[NV], r_[3], f_[9];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[q] = vn[q];
+            publish(v);
+            if (in0) load_fac(y0 - 2 + p, vn);
+            __syncthreads();
+            consume_fac(v, r_, f_);
+            __syncthreads();  // xb is rewritten by the next source row
+        }
+    }
+
+#pragma unroll 1
+    for (int j = 0; j < J; ++j) {
+        const int s0 = j % 3;        // slot of row j
+        const int s1 = (j + 2) % 3;  // slot of row j-1
+        const int s2 = (j + 1) % 3;  // slot of row j-2 (and j-3 + 3)
+        // ---- stage 1: totals, densities, concentrations of row j; prefetch the next input
+        C f0[9], r0[3];
+        {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f0[i] = C(0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) r0[k] = C(1);
+            C v[NV];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[q] = vn[q];
+            if constexpr (IN == Fmt::F27) {
+                if (in1 && j + 1 < J) load_f27(j + 1, vn);
+                consume_f27(v, r0, f0);
+            } else {
+                publish(v);
+                if (in0 && j + 1 < J) load_fac(y0 + j, vn);
+                __syncthreads();
+                consume_fac(v, r0, f0);
+            }
+            const C irho = C(1) / ((r0[0] + r0[1]) + r0[2]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cring[s0][k][t] = r0[k] * irho;
+        }
+        __syncthreads();
+        // ---- stage 2: gradients, normals and stress of row j-1 (densities rA)
+        C nA[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
+        if (j >= 2 && in2) {
+            C gx[3], gy[3], cc[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const C* N = cring[s0][k];
+                const C* M = cring[s1][k];
+                const C* S_ = cring[s2][k];
+                gx[k] = ddx<C>(M[t + 1], M[t - 1], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
+                gy[k] = ddy<C>(N[t], S_[t], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
+                cc[k] = M[t];
+            }
+            C Txx = C(0), Txy = C(0), Tyy = C(0);
+            constexpr int PK[3] = {0, 0, 1}, PL[3] = {1, 2, 2};
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const int k = PK[p], l = PL[p];
+                C Gx, Gy, mag;
+                {
+                    // The two products of G nearly cancel where a fluid is present only as a
+                    // trace; unfused, their rounding matches the plain IEEE evaluation.
+#pragma clang fp contract(off)
+                    Gx = cc[l] * gx[k] - cc[k] * gx[l];
+                    Gy = cc[l] * gy[k] - cc[k] * gy[l];
+                    mag = sqrt(Gx * Gx + Gy * Gy);
+                }
+                if (mag > K.guard) {
+                    const C inv = C(1) / mag;
+                    nA[2 * p] = Gx * inv;
+                    nA[2 * p + 1] = Gy * inv;
+                    C cf = K.cfac[p] * (rA[k] * rA[l]);
+                    cf = cf < C(1) ? cf : C(1);
+                    const C coef = K.sig[p] * cf * inv;
+                    Txx += coef * (Gy * Gy);
+                    Txy -= coef * (Gx * Gy);
+                    Tyy += coef * (Gx * Gx);
+                }
+            }
+            tring[s1][0][t] = Txx;
+            tring[s1][1][t] = Txy;
+            tring[s1][2][t] = Tyy;
+        }
+        __syncthreads();
+        // ---- stage 3: force, collision, recolouring of row j-2 (fB, rB, nB)
+        if (j >= 4 && in3) {
+            const int yo = y0 + j - 4;
+            C d[3][2];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const C* N = tring[s1][a];  // row j-1
+                const C* M = tring[s2][a];  // row j-2
+                const C* S_ = tring[s0][a]; // row j-3
+                d[a][0] = ddx<C>(M[t + 1], M[t - 1], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
+                d[a][1] = ddy<C>(N[t], S_[t], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
+            }
+            const C Fx = d[0][0] + d[1][1];  // d_x T_xx + d_y T_yx
+            const C Fy = d[1][0] + d[2][1];  // d_x T_xy + d_y T_yy
+            C fd[9], ck[3], V[6], ux, uy, mxh, myh;
+            collide_recolour<C>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
+            if constexpr (!OBS) {
+                const uint32_t key = ((uint32_t)yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt;
+                if constexpr (OUT == Fmt::F27) {
+                    const int64_t orow = (int64_t)yo * kp.pitch;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) {
+                            const int q = k * 9 + i;
+                            const C val = recon<C>(ck[k], fd[i], V[2 * k], V[2 * k + 1], i);
+                            st_at(fout + ((int64_t)q * plane + orow), xoff,
+                                  to_storage<S, C>(val, key + (uint32_t)q));
+                        }
+                } else {
+                    const int64_t orow = (int64_t)yo * kp.fpitch;
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        st_at(fout + ((int64_t)i * plane + orow), xoff,
+                              to_storage<S, C>(fd[i], key + (uint32_t)i));
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        st_at(fout + ((int64_t)(9 + k) * plane + orow), xoff,
+                              to_storage<S, C>(ck[k], key + (uint32_t)(9 + k)));
+#pragma unroll
+                    for (int q = 0; q < 6; ++q)
+                        st_at(fout + ((int64_t)(12 + q) * plane + orow), xoff,
+                              to_storage<S, C>(V[q], key + (uint32_t)(12 + q)));
+                }
+            } else {
+                const double rho = double(rB[0]) + double(rB[1]) + double(rB[2]);
+                acc[0] += double(rB[0]);
+                acc[1] += double(rB[1]);
+                acc[2] += double(rB[2]);
+                acc[3] += double(mxh);
+                acc[4] += double(myh);
+                const double uu = double(ux) * double(ux) + double(uy) * double(uy);
+                acc[5] += 0.5 * rho * uu;
+                const double um = sqrt(uu);
+                acc[6] = (um > acc[6] || um != um) ? um : acc[6];
+                const bool fin_ok = isfinite(double(rB[0])) && isfinite(double(rB[1])) &&
+                                    isfinite(double(rB[2])) && isfinite(double(mxh)) &&
+                                    isfinite(double(myh)) && isfinite(uu);
+                if (!fin_ok) acc[7] = 1.0;
+                if (rho_out) {
+                    const int64_t N = (int64_t)nx * ny;
+                    const int64_t o = (int64_t)yo * nx + x;
+                    rho_out[o] = double(rB[0]);
+                    rho_out[N + o] = double(rB[1]);
+                    rho_out[2 * N + o] = double(rB[2]);
+                }
+            }
+        }
+        // ---- rotate the pipeline
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            fB[i] = fA[i];
+            fA[i] = f0[i];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            rB[k] = rA[k];
+            rA[k] = r0[k];
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) nB[q] = nA[q];
+    }
+}
+
+template <int NT>
+__device__ void block_reduce_obs(double (&acc)[kObsFields], double* __restrict__ partials)
+{
+    __shared__ double red[kObsFields][NT];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int a = 0; a < kObsFields; ++a) red[a][t] = acc[a];
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if (t < h) {
+#pragma unroll
+            for (int a = 0; a < kObsFields; ++a) {
+                if (a == 6 || a == 7) {
+                    const double o = red[a][t + h];
+                    red[a][t] = (o > red[a][t] || o != o) ? o : red[a][t];
+                } else {
+                    red[a][t] += red[a][t + h];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (t < kObsFields) partials[(int64_t)blockIdx.x * kObsFields + t] = red[t][0];
+}
+
+template <typename C, int NT, Fmt IN>
+struct ExchangeLds {
+    __device__ static C (*get())[NT]
+    {
+        __shared__ C xb[9][NT];
+        return xb;
+    }
+};
+template <typename C, int NT>
+struct ExchangeLds<C, NT, Fmt::F27> {
+    __device__ static C (*get())[NT] { return nullptr; }
+};
+
+// One fused time step over a list of tiles: workgroup b takes tiles[b] of instance
+// tiles[b].inst (the plain lattice is a list with one instance).  With OBS the workgroup
+// instead accumulates the observables of its output nodes into partials[b].  With filter,
+// a workgroup whose instance's state is not in format IN returns at once.
+template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles(const S* __restrict__ fin, S* __restrict__ fout,
+                                              const Instance* __restrict__ inst,
+                                              const Tile* __restrict__ tiles, uint32_t salt,
+                                              int filter, double* __restrict__ partials,
+                                              double* __restrict__ rho_out)
+{
+    __shared__ C cring[3][3][NT];
+    __shared__ C tring[3][3][NT];
+    const Tile tl = tiles[blockIdx.x];
+    if (filter && inst[tl.inst].fmt != (int32_t)IN) return;
+    const KParams kp = inst[tl.inst].kp;
+    const int64_t off = inst[tl.inst].offset;
+    double acc[kObsFields] = {0, 0, 0, 0, 0, 0, 0, 0};
+    march<S, C, NT, OBS, IN, OUT>(fin + off, OBS ? nullptr : fout + off, kp, tl.x0, tl.y0, tl.rows,
+                                  tl.cols, cring, tring, ExchangeLds<C, NT, IN>::get(), acc, rho_out,
+                                  salt ^ mix32((uint32_t)tl.inst * 0x9E3779B9U + 0x51ed270bU));
+    if constexpr (OBS) block_reduce_obs<NT>(acc, partials);
+}
+
+template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT>
+hipError_t do_tiles(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
+                    int ntiles, uint32_t salt, int filter, double* partials, double* rho_out,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL((k_tiles<S, C, NT, OBS, IN, OUT>), dim3(ntiles), dim3(NT), 0, st,
+                       (const S*)fin, (S*)fout, inst, tiles, salt, filter, partials, rho_out);
+    return hipGetLastError();
+}
+
+template <typename S, typename C, int NT>
+hipError_t tiles_nt(Fmt in, Fmt out, bool obs, const void* fin, void* fout, const Instance* inst,
+                    const Tile* tiles, int ntiles, uint32_t salt, int filter, double* partials,
+                    double* rho_out, hipStream_t st)
+{
+    if (obs) {
+        if (in == Fmt::F27)
+            return do_tiles<S, C, NT, true, Fmt::F27, Fmt::F27>(fin, nullptr, inst, tiles, ntiles, 0u,
+                                                               filter, partials, rho_out, st);
+        return do_tiles<S, C, NT, true, Fmt::FAC, Fmt::FAC>(fin, nullptr, inst, tiles, ntiles, 0u,
+                                                           filter, partials, rho_out, st);
+    }
+    if (in == Fmt::FAC && out == Fmt::FAC)
+        return do_tiles<S, C, NT, false, Fmt::FAC, Fmt::FAC>(fin, fout, inst, tiles, ntiles, salt,
+                                                            filter, nullptr, nullptr, st);
+    if (in == Fmt::F27 && out == Fmt::FAC)
+        return do_tiles<S, C, NT, false, Fmt::F27, Fmt::FAC>(fin, fout, inst, tiles, ntiles, salt,
+                                                            filter, nullptr, nullptr, st);
+    if (in == Fmt::F27 && out == Fmt::F27)
+        return do_tiles<S, C, NT, false, Fmt::F27, Fmt::F27>(fin, fout, inst, tiles, ntiles, salt,
+                                                            filter, nullptr, nullptr, st);
+    return hipErrorInvalidValue;
+}
+
+template <typename S, typename C>
+hipError_t tiles_any(Fmt in, Fmt out, bool obs, const void* fin, void* fout, const Instance* inst,
+                     const Tile* tiles, int ntiles, int threads, uint32_t salt, int filter,
+                     double* partials, double* rho_out, hipStream_t st)
+{
+    switch (threads) {
+        case 64: return tiles_nt<S, C, 64>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
+        case 128: return tiles_nt<S, C, 128>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
+        case 256: return tiles_nt<S, C, 256>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
+        case 512: return tiles_nt<S, C, 512>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Resident workgroups per CU of the steady-state (FAC -> FAC) step.
+template <typename S, typename C>
+int tiles_occupancy(int threads)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (threads) {
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<S, C, 64, false, Fmt::FAC, Fmt::FAC>, 64, 0); break;
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<S, C, 128, false, Fmt::FAC, Fmt::FAC>, 128, 0); break;
+        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<S, C, 256, false, Fmt::FAC, Fmt::FAC>, 256, 0); break;
+        case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<S, C, 512, false, Fmt::FAC, Fmt::FAC>, 512, 0); break;
+        default: break;
+    }
+    return e == hipSuccess ? nb : 0;
+}
+
+}  // namespace
+}  // namespace tcg

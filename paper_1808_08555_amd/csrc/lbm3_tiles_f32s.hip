@@ -1,0 +1,16 @@
+// Instantiations of the fused step (lbm3_step_impl.h) for storage float, compute double.
+#include "lbm3_step_impl.h"
+
+namespace tcg {
+
+hipError_t tiles_f32s(Fmt in, Fmt out, bool obs, const void* fin, void* fout, const Instance* inst,
+                    const Tile* tiles, int ntiles, int threads, uint32_t salt, int filter,
+                    double* partials, double* rho_out, hipStream_t stream)
+{
+    return tiles_any<float, double>(in, out, obs, fin, fout, inst, tiles, ntiles, threads, salt, filter,
+                                partials, rho_out, stream);
+}
+
+int tiles_f32s_occupancy(int threads) { return tiles_occupancy<float, double>(threads); }
+
+}  // namespace tcg

@@ -78,7 +78,8 @@ def lib():
             "lbm3_set_tile": (I, [H, ctypes.c_int32, ctypes.c_int32]),
             "lbm3_get_tile": (I, [H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
             "lbm3_state_buffer": (I, [H, ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int32),
-                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int32)]),
             "lbm3_batch_create": (I, [P, ctypes.c_int32, _VP, ctypes.POINTER(H)]),
             "lbm3_batch_init_fields": (I, [H, ctypes.c_int32, _DP, _DP]),
             "lbm3_batch_step": (I, [H, ctypes.c_int64]),
@@ -203,14 +204,16 @@ def lbm3_get_tile(h):
 
 
 def lbm3_state_buffer(h):
-    """(device pointer, element bytes, plane stride, row pitch) of the current state buffer."""
+    """(device pointer, element bytes, plane stride, row pitch, planes) of the current state
+    buffer: 27 planes of populations after init / set_state, 18 factored planes after a step."""
     p = ctypes.c_void_p()
     eb = ctypes.c_int32()
     pl = ctypes.c_int64()
     pt = ctypes.c_int64()
+    nq = ctypes.c_int32()
     _check(lib().lbm3_state_buffer(h, ctypes.byref(p), ctypes.byref(eb), ctypes.byref(pl),
-                                   ctypes.byref(pt)), "lbm3_state_buffer")
-    return p.value, eb.value, pl.value, pt.value
+                                   ctypes.byref(pt), ctypes.byref(nq)), "lbm3_state_buffer")
+    return p.value, eb.value, pl.value, pt.value, nq.value
 
 
 def lbm3_device_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream=None):

@@ -212,7 +212,9 @@ def test_full_size_sampled_parity_in_bench_configuration():
     xs = list(rng.integers(0, 4096, 300))
     ys = list(rng.integers(0, 4096, 300))
     t, r = tile
-    for x in [0, 1, 2, t - 5, t - 4, t - 3, 4093, 4094, 4095]:
+    # strips start at x = 3 and are a multiple of 16 columns wide (at most t - 6)
+    w0 = (t - 6) // 16 * 16
+    for x in [0, 1, 2, 3, 4, w0 + 2, w0 + 3, w0 + 4, 4093, 4094, 4095]:
         for y in [0, 1, r - 1, r, r + 1, 4094, 4095]:
             xs.append(x)
             ys.append(y)
@@ -275,3 +277,32 @@ def test_set_state_round_trip_and_resume():
     assert np.array_equal(c.state(), full)
     for L in (a, b, c):
         L.close()
+
+
+@pytest.mark.parametrize("case", ["two_droplets", "ragged_droplet", "ragged_random"])
+def test_factored_state_matches_27_population_path_bitwise(case):
+    """The step stores the factored node state (f_dag, c_k, V_k) and rebuilds the pulled
+    populations from it; the adjoint's recording keeps the 27 populations.  Both must give
+    bitwise the same states, observables and densities (FP64)."""
+    if case == "two_droplets":
+        w, counts = inputs.two_droplets_64(), (1, 2, 37)
+    elif case == "ragged_droplet":
+        w, counts = inputs.single_droplet(37, 9.0), (1, 3, 50)
+    else:  # node-wise random mixture: far from equilibrium, kept to a few steps
+        w, counts = _wl("rand", inputs.random_mixture(77, 45, 9, tiny_fraction=0.0)), (1, 2, 4)
+    for steps in counts:
+        A = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau).init(w.rho)
+        assert lbm3.lbm3_state_buffer(A.h)[4] == 27
+        lbm3.lbm3_adjoint_record(A.h, steps, steps)  # 27-population steps
+        assert lbm3.lbm3_state_buffer(A.h)[4] == 27
+        B = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau).init(w.rho).step(steps)
+        assert lbm3.lbm3_state_buffer(B.h)[4] == 18
+        oa, ra, fa = A.observables(want_rho=True, want_f=True)
+        ob, rb, fb = B.observables(want_rho=True, want_f=True)
+        assert np.array_equal(fa, fb), (case, steps)
+        assert np.array_equal(ra, rb)
+        assert oa["nonfinite"] == 0
+        for key in oa:
+            assert np.array_equal(np.asarray(oa[key]), np.asarray(ob[key])), key
+        A.close()
+        B.close()
