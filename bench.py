@@ -26,9 +26,9 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS & % HBM roofline: plain FP64 vs FP32 batched vs adjoint step"
 HBM_PEAK_GBS = 8000.0
-# The step keeps the recoloured state factored per node (f_dag_i, c_k, V_k: 18 values) and
-# reads and writes it once per update: 36 values per lattice update.
-BYTES_PER_LU = {"fp64": 288, "fp32_storage": 144, "fp32": 144}
+# Values read and written once per lattice update.  FP64 and FP32 keep the recoloured state
+# factored per node (f_dag_i, c_k, V_k: 18 values); FP32 storage keeps the 27 populations.
+BYTES_PER_LU = {"fp64": 2 * 18 * 8, "fp32_storage": 2 * 27 * 4, "fp32": 2 * 18 * 4}
 
 
 def log(msg: str):

@@ -134,7 +134,8 @@ int lbm3_get_tile(const lbm3_t *h, int32_t *threads, int32_t *rows);
  * is element q*plane_stride + y*row_pitch + x.  After init_fields / set_state
  * (and during an adjoint recording) the state is the 27 populations after
  * collision and recolouring, before streaming (q = k*9 + i, nplanes = 27).  After
- * lbm3_step it is held factored per node, nplanes = 18: f_dag_i after collision
+ * lbm3_step with LBM3_FP64 or LBM3_FP32 (LBM3_FP32_STORAGE keeps the 27
+ * populations) it is held factored per node, nplanes = 18: f_dag_i after collision
  * (q = i), c_k = rho_k/rho (q = 9 + k) and V_k = sum_{l != k} beta_kl (rho_k
  * rho_l / rho) n_kl (q = 12 + 2k, 13 + 2k), from which Eq. (13) gives every
  * recoloured population as c_k f_dag_i + w_i V_k . e_i.  For measurement tools;

@@ -2,9 +2,10 @@
 // one precision) in one device arena.  One launch of the fused step covers the tiles of
 // every instance (a flat tile list, dealt to the XCDs in contiguous runs); a captured
 // hipGraph of kGraphSteps such launches advances all instances with one graph launch.
-// Instances hold the factored state after their first step; a step that finds some
-// instances freshly initialised (27-population format) runs as two launches over the same
-// list, each skipping the instances of the other format.
+// Instances hold the factored state after their first step (FP64 and FP32; FP32 storage
+// keeps the 27 populations); a step that finds some instances freshly initialised
+// (27-population format) runs as two launches over the same list, each skipping the
+// instances of the other format.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -74,7 +75,7 @@ static int batch_plan(lbm3_batch* b)
             plan_lattice(i, b->inst[i].kp.nx, b->inst[i].kp.ny, b->threads, r, eb, L);
             tiles += (long)L.size();
         }
-        const double cost = (double)((tiles + slots - 1) / slots) * (r + 4);
+        const double cost = (double)((tiles + slots - 1) / slots) * (r + 6);
         if (cost < best) {
             best = cost;
             auto_r = r;
@@ -132,8 +133,9 @@ static int build_graph(lbm3_batch* b, int parity)
     int c = parity;
     hipError_t le = hipSuccess;
     for (int s = 0; s < kGraphSteps && le == hipSuccess; ++s) {
-        le = launch_tiles(b->prec, Fmt::FAC, Fmt::FAC, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles,
-                          b->ntiles, b->threads, s, 0, b->stream);
+        const Fmt sf = steady_fmt(b->prec);
+        le = launch_tiles(b->prec, sf, sf, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles, b->ntiles,
+                          b->threads, s, 0, b->stream);
         c ^= 1;
     }
     e = hipStreamEndCapture(b->stream, &g);
@@ -303,7 +305,8 @@ int lbm3_batch_step(lbm3_batch_t* b, int64_t n)
             set_error("instance %d has not been initialised", i);
             return LBM3_ESTATE;
         }
-    if (n > 0) {
+    const Fmt sf = steady_fmt(b->prec);
+    if (n > 0 && sf == Fmt::FAC) {
         // first step of freshly initialised instances: 27-population -> factored format
         int n27 = 0;
         for (Fmt f : b->fmt) n27 += f == Fmt::F27;
@@ -340,8 +343,8 @@ int lbm3_batch_step(lbm3_batch_t* b, int64_t n)
         b->step += kGraphSteps;
     }
     for (; n > 0; --n) {
-        hipError_t e = launch_tiles(b->prec, Fmt::FAC, Fmt::FAC, b->buf[b->cur], b->buf[b->cur ^ 1],
-                                    b->dinst, b->dtiles, b->ntiles, b->threads, b->step, 0, b->stream);
+        hipError_t e = launch_tiles(b->prec, sf, sf, b->buf[b->cur], b->buf[b->cur ^ 1], b->dinst,
+                                    b->dtiles, b->ntiles, b->threads, b->step, 0, b->stream);
         if (e != hipSuccess) return hip_fail(e, "batch step launch");
         b->cur ^= 1;
         b->step += 1;

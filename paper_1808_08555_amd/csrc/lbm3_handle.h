@@ -41,7 +41,7 @@ namespace tcg {
 int hip_fail(hipError_t e, const char* what);
 const char* last_error();
 Prec prec_of(int precision);
-void default_tile(const KParams& kp, int* threads, int* rows);
+void default_tile(const KParams& kp, Prec prec, int* threads, int* rows);
 int check_rho_fields(const double* rho, const double* u, int64_t n);
 int upload_plan(lbm3* h);
 void adjoint_release(lbm3* h);

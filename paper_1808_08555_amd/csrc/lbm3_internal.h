@@ -7,7 +7,7 @@
 
 #include <vector>
 
-#include "../../include/lbm3.h"
+#include "lbm3.h"
 
 namespace tcg {
 
@@ -53,6 +53,11 @@ enum class Prec { F64, F32S, F32 };
 // which f_ddag_{i,k} = c_k f_dag_i + w_i V_k . e_i is rebuilt exactly where it is pulled.
 enum class Fmt : int32_t { F27 = 0, FAC = 1 };
 constexpr int kFacPlanes = 18;
+
+// Format the step keeps between steps.  With FP32 storage and FP64 arithmetic the step is
+// bound by its arithmetic rather than by memory, and there the 27-population pull measured
+// faster than rebuilding the populations from the factored state.
+inline Fmt steady_fmt(Prec p) { return p == Prec::F32S ? Fmt::F27 : Fmt::FAC; }
 
 // Launchers (lbm3_step.hip).  All asynchronous on `stream`.  One fused step from a state in
 // format `in` to one in format `out` (F27 -> F27, F27 -> FAC or FAC -> FAC); with

@@ -59,7 +59,8 @@ int auto_rows(int nx, int ny, int threads, int slots, int elem_bytes)
     plan_lattice(0, nx, 1, threads, 1, elem_bytes, probe);
     const int nstrips = (int)probe.size();
     if (slots < 1) slots = 1;
-    // time ~ rounds * (rows per segment + 4 warm-up rows); fewest rounds, then fewest rows
+    // time ~ rounds * (rows per segment + 6 warm-up rows: the pipeline is two rows deep
+    // and the factored pull starts two source rows further down); fewest rounds, then rows
     double best = 1e300;
     int best_rows = std::min(ny, 64);
     for (int nseg = 1; nseg <= ny; ++nseg) {
@@ -68,7 +69,7 @@ int auto_rows(int nx, int ny, int threads, int slots, int elem_bytes)
         if (rows > 512) continue;
         const long tiles = (long)nstrips * nseg;
         const long rounds = (tiles + slots - 1) / slots;
-        const double cost = (double)rounds * (rows + 4) * (1.0 + 1e-9 * nseg);
+        const double cost = (double)rounds * (rows + 6) * (1.0 + 1e-9 * nseg);
         if (cost < best) {
             best = cost;
             best_rows = rows;

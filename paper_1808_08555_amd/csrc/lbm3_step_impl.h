@@ -82,13 +82,19 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x)
 // below it.
 __device__ __forceinline__ float round_stochastic(double v, uint32_t bits)
 {
-    const float a = __double2float_rz(v);
+    // a: the float next to v toward zero (the nearest float, stepped back one ulp in
+    // magnitude when it lies beyond v); b: the float next to a away from zero (adding one to
+    // the magnitude bits; from a signed zero this gives the smallest subnormal of that sign).
+    // Branch-free: with v a float already, rem = 0 and a is returned.  Beyond the float range
+    // (and for NaN) the result is that of round to nearest, so overflow still shows as Inf.
+    const float t = (float)v;
+    const float a = fabs((double)t) > fabs(v) ? __uint_as_float(__float_as_uint(t) - 1u) : t;
+    const float b = __uint_as_float(__float_as_uint(a) + 1u);
     const double rem = fabs(v - (double)a);
-    if (!(rem > 0.0)) return a;
-    const float b = nextafterf(a, v > 0.0 ? __builtin_huge_valf() : -__builtin_huge_valf());
     const double gap = fabs((double)b - (double)a);
     const double u = (double)(bits >> 8) * (1.0 / 16777216.0);
-    return u * gap < rem ? b : a;
+    const float r = u * gap < rem ? b : a;
+    return fabs(v) <= 3.4028234663852886e38 ? r : t;  // overflow and NaN as round to nearest
 }
 
 // Store of one value in the storage type S from the compute type C.
@@ -268,7 +274,7 @@ __device__ __forceinline__ void collide_recolour(const C (&f)[9], const C (&rk)[
 template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT>
 __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__ fout,
                                       const KParams& kp, int x0, int y0, int rows, int cols,
-                                      C (*cring)[3][NT], C (*tring)[3][NT], C (*xb)[NT],
+                                      C (*cring)[3][NT], C (*tring)[3][NT], C (*xb)[9][NT],
                                       double (&acc)[kObsFields], double* __restrict__ rho_out,
                                       uint32_t salt)
 {
@@ -316,25 +322,27 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
     // FAC partial sums: D0 = row s (directions with e_y = +1 and 0 received), D1 = row s + 1
     // (e_y = +1 received).  Direction groups by e_y: +1 {2, 5, 6}, 0 {0, 1, 3}, -1 {4, 7, 8}.
     C d0r[3], d0f[6], d1r[3], d1f[3];  // d0f: f_2, f_5, f_6, f_0, f_1, f_3; d1f: f_2, f_5, f_6
-    // FAC: publish the c_k, V_k of this lane's column of the source row (v[9..17]) to the
-    // neighbouring lanes; the caller synchronises before consume_fac reads them.
-    auto publish = [&](const C (&v)[NV]) {
+    // FAC: publish the c_k, V_k of this lane's column of a source row (v[9..17]) to the
+    // neighbouring lanes, in exchange slot `slot` (two slots, used by alternate rows); a
+    // barrier separates this from consume_fac's reads.
+    auto publish = [&](const C (&v)[NV], int slot) {
         if constexpr (IN == Fmt::FAC) {
             if (in0) {
 #pragma unroll
-                for (int q = 0; q < 9; ++q) xb[q][t] = v[9 + q];
+                for (int q = 0; q < 9; ++q) xb[slot][q][t] = v[9 + q];
             }
         }
     };
-    // FAC: the pulls of source row s (f_dag in v[0..8], c_k and V_k in xb) to rows s+1, s
-    // and s-1, in the fixed group order; completes row s-1 into r0, f0.
-    auto consume_fac = [&](const C (&v)[NV], C (&r0)[3], C (&f0)[9]) {
+    // FAC: the pulls of source row s (f_dag in v[0..8], c_k and V_k in exchange slot `slot`)
+    // to rows s+1, s and s-1, in the fixed group order; completes row s-1 into r0, f0.
+    auto consume_fac = [&](const C (&v)[NV], int slot, C (&r0)[3], C (&f0)[9]) {
         if (!in1) return;
+        const C (*X)[NT] = xb[slot];
         auto pull = [&](int i, C (&fk)[3]) {
             const int l = t - EX[i];
 #pragma unroll
             for (int k = 0; k < 3; ++k)
-                fk[k] = recon<C>(xb[k][l], v[i], xb[3 + 2 * k][l], xb[4 + 2 * k][l], i);
+                fk[k] = recon<C>(X[k][l], v[i], X[3 + 2 * k][l], X[4 + 2 * k][l], i);
         };
         auto group = [&](int a, int b, int c, C (&g)[3], C& ta, C& tb, C& tc) {
             C fa[3], fb[3], fc[3];
@@ -404,19 +412,23 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
     if constexpr (IN == Fmt::F27) {
         if (in1) load_f27(0, vn);
     } else {
-        // pre-roll: source rows y0 - 3 and y0 - 2 start the partial sums of row y0 - 2
+        // pre-roll: source rows y0 - 3 and y0 - 2 start the partial sums of row y0 - 2, and
+        // source row y0 - 1 is published for the first iteration (slots alternate by row)
         if (in0) load_fac(y0 - 3, vn);
 #pragma unroll 1
         for (int p = 0; p < 2; ++p) {
             C v[NV], r_[3], f_[9];
 #pragma unroll
             for (int q = 0; q < NV; ++q) v[q] = vn[q];
-            publish(v);
+            publish(v, p);
             if (in0) load_fac(y0 - 2 + p, vn);
             __syncthreads();
-            consume_fac(v, r_, f_);
-            __syncthreads();  // xb is rewritten by the next source row
+            consume_fac(v, p, r_, f_);
         }
+        // slot 0 was last read before the barrier above (row y0 - 3); slot 1 (row y0 - 2) is
+        // next written after the first iteration's first barrier
+        publish(vn, 0);
+        __syncthreads();
     }
 
 #pragma unroll 1
@@ -438,10 +450,9 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
                 if (in1 && j + 1 < J) load_f27(j + 1, vn);
                 consume_f27(v, r0, f0);
             } else {
-                publish(v);
+                // source row y0 - 1 + j was published in slot j % 2 before the last barrier
                 if (in0 && j + 1 < J) load_fac(y0 + j, vn);
-                __syncthreads();
-                consume_fac(v, r0, f0);
+                consume_fac(v, j & 1, r0, f0);
             }
             const C irho = C(1) / ((r0[0] + r0[1]) + r0[2]);
 #pragma unroll
@@ -490,6 +501,11 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
             tring[s1][0][t] = Txx;
             tring[s1][1][t] = Txy;
             tring[s1][2][t] = Tyy;
+        }
+        // the next source row (prefetched at the top of this iteration) goes to the other
+        // exchange slot, last read before the previous barrier
+        if constexpr (IN == Fmt::FAC) {
+            if (j + 1 < J) publish(vn, (j + 1) & 1);
         }
         __syncthreads();
         // ---- stage 3: force, collision, recolouring of row j-2 (fB, rB, nB)
@@ -576,10 +592,12 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
     }
 }
 
+// Workgroup reduction of the observables partials in `red` (LDS, kObsFields x NT doubles);
+// the caller has synchronised the workgroup before `red` is reused.
 template <int NT>
-__device__ void block_reduce_obs(double (&acc)[kObsFields], double* __restrict__ partials)
+__device__ void block_reduce_obs(double (&acc)[kObsFields], double (*red)[NT],
+                                 double* __restrict__ partials)
 {
-    __shared__ double red[kObsFields][NT];
     const int t = threadIdx.x;
 #pragma unroll
     for (int a = 0; a < kObsFields; ++a) red[a][t] = acc[a];
@@ -603,15 +621,15 @@ __device__ void block_reduce_obs(double (&acc)[kObsFields], double* __restrict__
 
 template <typename C, int NT, Fmt IN>
 struct ExchangeLds {
-    __device__ static C (*get())[NT]
+    __device__ static C (*get())[9][NT]
     {
-        __shared__ C xb[9][NT];
+        __shared__ C xb[2][9][NT];
         return xb;
     }
 };
 template <typename C, int NT>
 struct ExchangeLds<C, NT, Fmt::F27> {
-    __device__ static C (*get())[NT] { return nullptr; }
+    __device__ static C (*get())[9][NT] { return nullptr; }
 };
 
 // One fused time step over a list of tiles: workgroup b takes tiles[b] of instance
@@ -625,8 +643,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                               int filter, double* __restrict__ partials,
                                               double* __restrict__ rho_out)
 {
-    __shared__ C cring[3][3][NT];
-    __shared__ C tring[3][3][NT];
+    // the two rings in one array, so that the observables reduction can reuse them
+    static_assert(sizeof(C) * 18 >= sizeof(double) * kObsFields, "rings too small for the reduction");
+    __shared__ alignas(16) C rings[2][3][3][NT];
+    C (*cring)[3][NT] = rings[0];
+    C (*tring)[3][NT] = rings[1];
     const Tile tl = tiles[blockIdx.x];
     if (filter && inst[tl.inst].fmt != (int32_t)IN) return;
     const KParams kp = inst[tl.inst].kp;
@@ -635,7 +656,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     march<S, C, NT, OBS, IN, OUT>(fin + off, OBS ? nullptr : fout + off, kp, tl.x0, tl.y0, tl.rows,
                                   tl.cols, cring, tring, ExchangeLds<C, NT, IN>::get(), acc, rho_out,
                                   salt ^ mix32((uint32_t)tl.inst * 0x9E3779B9U + 0x51ed270bU));
-    if constexpr (OBS) block_reduce_obs<NT>(acc, partials);
+    if constexpr (OBS) {
+        __syncthreads();  // the rings are free once every lane has left the march
+        block_reduce_obs<NT>(acc, reinterpret_cast<double (*)[NT]>(&rings[0][0][0][0]), partials);
+    }
 }
 
 template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT>
@@ -648,27 +672,34 @@ hipError_t do_tiles(const void* fin, void* fout, const Instance* inst, const Til
     return hipGetLastError();
 }
 
+// FP32 storage with FP64 arithmetic keeps the 27-population format (see steady_fmt), so its
+// factored variants are not built.
+template <typename S, typename C>
+constexpr bool kHasFac = !(sizeof(S) == 4 && sizeof(C) == 8);
+
 template <typename S, typename C, int NT>
 hipError_t tiles_nt(Fmt in, Fmt out, bool obs, const void* fin, void* fout, const Instance* inst,
                     const Tile* tiles, int ntiles, uint32_t salt, int filter, double* partials,
                     double* rho_out, hipStream_t st)
 {
-    if (obs) {
-        if (in == Fmt::F27)
+    if (in == Fmt::F27 && (obs || out == Fmt::F27)) {
+        if (obs)
             return do_tiles<S, C, NT, true, Fmt::F27, Fmt::F27>(fin, nullptr, inst, tiles, ntiles, 0u,
                                                                filter, partials, rho_out, st);
-        return do_tiles<S, C, NT, true, Fmt::FAC, Fmt::FAC>(fin, nullptr, inst, tiles, ntiles, 0u,
-                                                           filter, partials, rho_out, st);
-    }
-    if (in == Fmt::FAC && out == Fmt::FAC)
-        return do_tiles<S, C, NT, false, Fmt::FAC, Fmt::FAC>(fin, fout, inst, tiles, ntiles, salt,
-                                                            filter, nullptr, nullptr, st);
-    if (in == Fmt::F27 && out == Fmt::FAC)
-        return do_tiles<S, C, NT, false, Fmt::F27, Fmt::FAC>(fin, fout, inst, tiles, ntiles, salt,
-                                                            filter, nullptr, nullptr, st);
-    if (in == Fmt::F27 && out == Fmt::F27)
         return do_tiles<S, C, NT, false, Fmt::F27, Fmt::F27>(fin, fout, inst, tiles, ntiles, salt,
                                                             filter, nullptr, nullptr, st);
+    }
+    if constexpr (kHasFac<S, C>) {
+        if (obs && in == Fmt::FAC)
+            return do_tiles<S, C, NT, true, Fmt::FAC, Fmt::FAC>(fin, nullptr, inst, tiles, ntiles, 0u,
+                                                               filter, partials, rho_out, st);
+        if (in == Fmt::FAC && out == Fmt::FAC)
+            return do_tiles<S, C, NT, false, Fmt::FAC, Fmt::FAC>(fin, fout, inst, tiles, ntiles, salt,
+                                                                filter, nullptr, nullptr, st);
+        if (in == Fmt::F27 && out == Fmt::FAC)
+            return do_tiles<S, C, NT, false, Fmt::F27, Fmt::FAC>(fin, fout, inst, tiles, ntiles, salt,
+                                                                filter, nullptr, nullptr, st);
+    }
     return hipErrorInvalidValue;
 }
 
@@ -686,20 +717,27 @@ hipError_t tiles_any(Fmt in, Fmt out, bool obs, const void* fin, void* fout, con
     }
 }
 
-// Resident workgroups per CU of the steady-state (FAC -> FAC) step.
+// Resident workgroups per CU of the steady-state step (the format of steady_fmt).
+template <typename S, typename C, int NT>
+int occupancy_nt()
+{
+    constexpr Fmt F = kHasFac<S, C> ? Fmt::FAC : Fmt::F27;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<S, C, NT, false, F, F>, NT, 0) != hipSuccess)
+        return 0;
+    return nb;
+}
+
 template <typename S, typename C>
 int tiles_occupancy(int threads)
 {
-    int nb = 0;
-    hipError_t e = hipErrorInvalidValue;
     switch (threads) {
-        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<S, C, 64, false, Fmt::FAC, Fmt::FAC>, 64, 0); break;
-        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<S, C, 128, false, Fmt::FAC, Fmt::FAC>, 128, 0); break;
-        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<S, C, 256, false, Fmt::FAC, Fmt::FAC>, 256, 0); break;
-        case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<S, C, 512, false, Fmt::FAC, Fmt::FAC>, 512, 0); break;
-        default: break;
+        case 64: return occupancy_nt<S, C, 64>();
+        case 128: return occupancy_nt<S, C, 128>();
+        case 256: return occupancy_nt<S, C, 256>();
+        case 512: return occupancy_nt<S, C, 512>();
+        default: return 0;
     }
-    return e == hipSuccess ? nb : 0;
 }
 
 }  // namespace
