@@ -1,5 +1,11 @@
 // Reverse-mode derivative (adjoint) of the FP64 step, with checkpointed recomputation.
 //
+// The forward run keeps a checkpoint every K steps.  The reverse sweep takes the segments
+// last to first: it recomputes the segment's K forward steps from its checkpoint with the
+// fused step in its tape mode, which records the densities, totals and concentration
+// gradients it pulled and formed at every node (18 values per node and step), then takes
+// the K reverse steps, each three node-parallel kernels reading that tape.
+//
 // Notation: the population buffer B holds, at node y, the recoloured populations of y
 // before streaming; the post-streaming populations are f_{i,k}(x) = B_{i,k}(x - e_i).
 // One step maps B to B'.  Given lam' = dL/dB' the reverse step returns lam = dL/dB and
@@ -41,7 +47,8 @@ __device__ __forceinline__ int wrapi(int a, int n)
     return r < 0 ? r + n : r;
 }
 
-// Workspace fields, each [components][N] in FP64 with node index y*nx + x.
+// Workspace fields, each [components][N] in FP64 with node index y*nx + x.  rho, ftot and
+// gc point into the tape of the step being reversed.
 struct AdjWS {
     double* rho;    // 3   densities
     double* ftot;   // 9   total populations
@@ -125,50 +132,7 @@ __device__ __forceinline__ void stress_at(const Geo& g, const AdjWS& w, int64_t 
     }
 }
 
-// ---- A0: pull the state, densities and totals
-__global__ __launch_bounds__(256) void k_adj_pull(const double* __restrict__ B, Geo g, AdjWS w)
-{
-    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-    if (x >= g.nx) return;
-    const int64_t N = (int64_t)g.nx * g.ny, j = (int64_t)y * g.nx + x;
-    double ft[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < 3; ++k) {
-        double s = 0.0;
-        for (int i = 0; i < 9; ++i) {
-            const int64_t src = (int64_t)wrapi(y - EY[i], g.ny) * g.pitch + wrapi(x - EX[i], g.nx);
-            const double v = B[(int64_t)(k * 9 + i) * g.plane + src];
-            s += v;
-            ft[i] += v;
-        }
-        w.rho[k * N + j] = s;
-    }
-    for (int i = 0; i < 9; ++i) w.ftot[i * N + j] = ft[i];
-}
-
-// ---- A1: concentration gradients
-__global__ __launch_bounds__(256) void k_adj_grad(Geo g, AdjWS w, double* __restrict__ cbuf)
-{
-    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-    if (x >= g.nx) return;
-    const int64_t N = (int64_t)g.nx * g.ny, j = (int64_t)y * g.nx + x;
-    (void)cbuf;
-    for (int k = 0; k < 3; ++k) {
-        // concentration of fluid k at the 9 nodes of the stencil, from the densities
-        double v[3][3];
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int64_t q = (int64_t)wrapi(y + dy, g.ny) * g.nx + wrapi(x + dx, g.nx);
-                const double r = w.rho[q] + w.rho[N + q] + w.rho[2 * N + q];
-                v[dy + 1][dx + 1] = w.rho[k * N + q] / r;
-            }
-        const double e = v[1][2], ww = v[1][0], n = v[2][1], s = v[0][1];
-        const double ne = v[2][2], nw = v[2][0], se = v[0][2], sw = v[0][0];
-        w.gc[(2 * k) * N + j] = 3.0 * ((1.0 / 9.0) * (e - ww) + (1.0 / 36.0) * ((ne - sw) + (se - nw)));
-        w.gc[(2 * k + 1) * N + j] = 3.0 * ((1.0 / 9.0) * (n - s) + (1.0 / 36.0) * ((ne - sw) + (nw - se)));
-    }
-}
-
-// ---- A2: node-local reverse of collision and recolouring
+// ---- A1: node-local reverse of collision and recolouring
 __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ lamp, Geo g, AdjWS w)
 {
     __shared__ double red[3][256];
@@ -337,7 +301,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ la
     }
 }
 
-// ---- A3: reverse of the stress (force divergence transposed) and of the pair quantities
+// ---- A2: reverse of the stress (force divergence transposed) and of the pair quantities
 __global__ __launch_bounds__(256) void k_adj_stress(Geo g, AdjWS w)
 {
     __shared__ double red[3][256];
@@ -402,7 +366,7 @@ __global__ __launch_bounds__(256) void k_adj_stress(Geo g, AdjWS w)
     }
 }
 
-// ---- A4: reverse of the gradient (c-bar = -div gcbar), densities, totals and streaming
+// ---- A3: reverse of the gradient (c-bar = -div gcbar), densities, totals and streaming
 __global__ __launch_bounds__(256) void k_adj_final(Geo g, AdjWS w, double* __restrict__ lam)
 {
     const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
@@ -489,6 +453,7 @@ double dg_dX(double X)
 
 void adjoint_release(lbm3* h)
 {
+    if (h->adj_stream) (void)hipStreamSynchronize(h->adj_stream);
     for (void* p : h->ckpt)
         if (p) (void)hipFree(p);
     h->ckpt.clear();
@@ -496,6 +461,15 @@ void adjoint_release(lbm3* h)
     h->adj_ws = nullptr;
     h->adj_ws_bytes = 0;
     h->tape_valid = false;
+}
+
+void adjoint_destroy(lbm3* h)
+{
+    adjoint_release(h);
+    if (h->adj_event) (void)hipEventDestroy(h->adj_event);
+    if (h->adj_stream) (void)hipStreamDestroy(h->adj_stream);
+    h->adj_event = nullptr;
+    h->adj_stream = nullptr;
 }
 
 }  // namespace tcg
@@ -538,23 +512,27 @@ int lbm3_adjoint_record(lbm3_t* h, int64_t nsteps, int32_t ckpt_every)
         return LBM3_EINVAL;
     }
     adjoint_release(h);
-    const size_t bytes = (size_t)h->kp.span * sizeof(double);
-    const int64_t nck = nsteps / ckpt_every + 1;
-    h->ckpt.assign(nck, nullptr);
-    for (int64_t c = 0; c < nck; ++c) {
-        hipError_t e = hipMalloc(&h->ckpt[c], bytes);
+    // checkpoint s holds the state at step s K: the 27 populations for s = 0 (from
+    // init_fields), the factored state after that
+    const int64_t nseg = nsteps / ckpt_every;
+    const size_t bytes27 = (size_t)h->kp.span * sizeof(double);
+    const size_t bytesfac = (size_t)h->kp.fpitch * h->kp.ny * sizeof(double);
+    h->ckpt.assign(nseg, nullptr);
+    for (int64_t c = 0; c < nseg; ++c) {
+        hipError_t e = hipMalloc(&h->ckpt[c], c == 0 ? bytes27 : bytesfac);
         if (e != hipSuccess) {
             int rc = hip_fail(e, "hipMalloc(checkpoint)");
             adjoint_release(h);
             return rc;
         }
     }
-    hipError_t e = hipMemcpyAsync(h->ckpt[0], h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream);
+    hipError_t e = hipMemcpyAsync(h->ckpt[0], h->buf[h->cur], bytes27, hipMemcpyDeviceToDevice, h->stream);
     if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
-    for (int64_t c = 1; c < nck; ++c) {
-        int rc = step_handle(h, ckpt_every, false);
+    for (int64_t c = 1; c <= nseg; ++c) {
+        int rc = step_handle(h, ckpt_every, true);
         if (rc) return rc;
-        e = hipMemcpyAsync(h->ckpt[c], h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream);
+        if (c == nseg) break;
+        e = hipMemcpyAsync(h->ckpt[c], h->buf[h->cur], bytesfac, hipMemcpyDeviceToDevice, h->stream);
         if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
     }
     h->tape_steps = nsteps;
@@ -584,21 +562,21 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     const dim3 grid((kp.nx + 255) / 256, kp.ny), blk(256);
     const int64_t nblocks = (int64_t)grid.x * grid.y;
     const size_t sbytes = (size_t)kp.span * sizeof(double);
+    const size_t fbytes = (size_t)kp.fpitch * kp.ny * sizeof(double);
+    const size_t tbytes = (size_t)kTapeFields * N * sizeof(double);
     const int K = h->tape_every;
     const int64_t nseg = h->tape_steps / K;
-    // workspace: 44 fields of N doubles, two adjoint buffers, K recomputed states, sums
-    const size_t fields = (size_t)(3 + 9 + 6 + 9 + 3 + 2 + 6 + 6) * N;
-    const size_t need = fields * sizeof(double) + 2 * sbytes + (size_t)K * sbytes +
-                        (size_t)nblocks * 6 * sizeof(double) + 3 * N * sizeof(double);
+    // workspace: 26 adjoint fields of N doubles, two adjoint buffers, two forward state
+    // buffers, the tape of K steps (18 fields each), the dL/dsigma partial sums, dL/drho_1(T)
+    const size_t fields = (size_t)(9 + 3 + 2 + 6 + 6) * N;
+    const size_t need = fields * sizeof(double) + 4 * sbytes + (size_t)K * tbytes +
+                        (size_t)nblocks * 6 * sizeof(double) + N * sizeof(double);
     int rc = ensure_ws(h, need);
     if (rc) return rc;
-    char* base = (char*)h->adj_ws;
-    double* d = (double*)base;
+    double* d = (double*)h->adj_ws;
     AdjWS w;
-    w.rho = d;
-    w.ftot = w.rho + 3 * N;
-    w.gc = w.ftot + 9 * N;
-    w.fbar = w.gc + 6 * N;
+    w.rho = w.ftot = w.gc = nullptr;  // per step: the tape of that step
+    w.fbar = d;
     w.rbar = w.fbar + 9 * N;
     w.Fbar = w.rbar + 3 * N;
     w.Gbar = w.Fbar + 2 * N;
@@ -606,42 +584,90 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     double* lam[2];
     lam[0] = w.gcbar + 6 * N;
     lam[1] = (double*)((char*)lam[0] + sbytes);
-    char* seg = (char*)lam[1] + sbytes;
-    w.sig = (double*)(seg + (size_t)K * sbytes);
+    char* fwd[2] = {(char*)lam[1] + sbytes, (char*)lam[1] + 2 * sbytes};
+    double* tape = (double*)(fwd[1] + sbytes);
+    w.sig = tape + (size_t)K * kTapeFields * N;
     double* gT = w.sig + nblocks * 6;
-    hipError_t e = hipMemsetAsync(w.sig, 0, (size_t)nblocks * 6 * sizeof(double), h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(gT, drho1_T, N * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    // The sweep runs on the handle's own adjoint stream (graph capture needs a stream other
+    // than the null stream), ordered after the work already on the handle's stream.
+    hipError_t e = hipSuccess;
+    if (!h->adj_stream) e = hipStreamCreateWithFlags(&h->adj_stream, hipStreamNonBlocking);
+    if (e == hipSuccess && !h->adj_event) e = hipEventCreateWithFlags(&h->adj_event, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(h->adj_event, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint stream set-up");
+    hipStream_t st = h->adj_stream;
+    e = hipStreamWaitEvent(st, h->adj_event, 0);
+    if (e == hipSuccess) e = hipMemsetAsync(w.sig, 0, (size_t)nblocks * 6 * sizeof(double), st);
+    if (e == hipSuccess) e = hipMemcpyAsync(gT, drho1_T, N * sizeof(double), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "adjoint set-up");
     int cl = 0;
-    hipLaunchKernelGGL(k_adj_seed, grid, blk, 0, h->stream, gT, g, lam[cl]);
-    for (int64_t s = nseg - 1; s >= 0; --s) {
-        // recompute the states B^{sK + j}, j = 0..K-1, of this segment
-        e = hipMemcpyAsync(seg, h->ckpt[s], sbytes, hipMemcpyDeviceToDevice, h->stream);
-        for (int j = 1; j < K && e == hipSuccess; ++j)
-            e = launch_tiles(Prec::F64, Fmt::F27, Fmt::F27, seg + (size_t)(j - 1) * sbytes,
-                             seg + (size_t)j * sbytes, h->dinst, h->dtiles, h->ntiles, h->threads,
-                             s * K + j - 1, 0, h->stream);
-        if (e != hipSuccess) return hip_fail(e, "adjoint segment recompute");
-        for (int j = K - 1; j >= 0; --j) {
-            const double* Bj = (const double*)(seg + (size_t)j * sbytes);
-            hipLaunchKernelGGL(k_adj_pull, grid, blk, 0, h->stream, Bj, g, w);
-            hipLaunchKernelGGL(k_adj_grad, grid, blk, 0, h->stream, g, w, nullptr);
-            hipLaunchKernelGGL(k_adj_local, grid, blk, 0, h->stream, (const double*)lam[cl], g, w);
-            hipLaunchKernelGGL(k_adj_stress, grid, blk, 0, h->stream, g, w);
-            hipLaunchKernelGGL(k_adj_final, grid, blk, 0, h->stream, g, w, lam[cl ^ 1]);
-            cl ^= 1;
+    hipLaunchKernelGGL(k_adj_seed, grid, blk, 0, st, gT, g, lam[cl]);
+    // One segment: from the checkpoint in fwd[0] (format `in`), recompute the K forward steps
+    // recording the tape of each, then take the K reverse steps from adjoint buffer lam[cl0].
+    // The launch arguments do not depend on the segment, so after the first the sequence is
+    // captured once per starting parity and replayed (segment 0 starts from the
+    // 27-population state and runs eagerly).
+    auto enqueue_segment = [&](hipStream_t q, Fmt in, int cl0) -> hipError_t {
+        hipError_t r = hipSuccess;
+        for (int j = 0; j < K && r == hipSuccess; ++j)
+            r = tiles_f64_tape(j == 0 ? in : Fmt::FAC, fwd[j & 1], fwd[(j + 1) & 1], h->dinst, h->dtiles,
+                               h->ntiles, h->threads, tape + (size_t)j * kTapeFields * N, q);
+        int c = cl0;
+        for (int j = K - 1; j >= 0 && r == hipSuccess; --j) {
+            AdjWS wj = w;
+            wj.rho = tape + (size_t)j * kTapeFields * N;
+            wj.ftot = wj.rho + 3 * N;
+            wj.gc = wj.rho + 12 * N;
+            hipLaunchKernelGGL(k_adj_local, grid, blk, 0, q, (const double*)lam[c], g, wj);
+            hipLaunchKernelGGL(k_adj_stress, grid, blk, 0, q, g, wj);
+            hipLaunchKernelGGL(k_adj_final, grid, blk, 0, q, g, wj, lam[c ^ 1]);
+            c ^= 1;
+            r = hipGetLastError();
         }
-        e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "adjoint kernels");
+        return r;
+    };
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    auto drop = [&]() {
+        for (auto& x : gexec)
+            if (x) (void)hipGraphExecDestroy(x);
+    };
+    for (int64_t s = nseg - 1; s >= 0 && e == hipSuccess; --s) {
+        const Fmt in = s == 0 ? Fmt::F27 : Fmt::FAC;
+        e = hipMemcpyAsync(fwd[0], h->ckpt[s], in == Fmt::F27 ? sbytes : fbytes, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) break;
+        if (s == 0 || nseg < 3) {
+            e = enqueue_segment(st, in, cl);
+        } else {
+            if (!gexec[cl]) {
+                hipGraph_t gr = nullptr;
+                e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) break;
+                const hipError_t le = enqueue_segment(st, Fmt::FAC, cl);
+                e = hipStreamEndCapture(st, &gr);
+                if (e == hipSuccess) e = le;
+                if (e == hipSuccess) e = hipGraphInstantiate(&gexec[cl], gr, nullptr, nullptr, 0);
+                if (gr) (void)hipGraphDestroy(gr);
+                if (e != hipSuccess) break;
+            }
+            e = hipGraphLaunch(gexec[cl], st);
+        }
+        cl ^= K & 1;
     }
-    double* r0 = (double*)seg;  // reuse: dL/drho_k(x, 0)
-    hipLaunchKernelGGL(k_adj_rho0, grid, blk, 0, h->stream, (const double*)lam[cl], g, r0);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(st);
+        drop();
+        return hip_fail(e, "adjoint sweep");
+    }
+    double* r0 = (double*)fwd[0];  // reuse: dL/drho_k(x, 0)
+    hipLaunchKernelGGL(k_adj_rho0, grid, blk, 0, st, (const double*)lam[cl], g, r0);
     std::vector<double> sig((size_t)nblocks * 6);
     e = hipGetLastError();
-    if (e == hipSuccess && drho0) e = hipMemcpyAsync(drho0, r0, 3 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && drho0) e = hipMemcpyAsync(drho0, r0, 3 * N * sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(sig.data(), w.sig, sig.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        e = hipMemcpyAsync(sig.data(), w.sig, sig.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+    const hipError_t es = hipStreamSynchronize(st);
+    drop();
+    if (e == hipSuccess) e = es;
     if (e != hipSuccess) return hip_fail(e, "adjoint results");
     // sigma: stress part directly; segregation part through g'(X_p) dX_p/dsigma_q
     double Sb[6] = {0, 0, 0, 0, 0, 0};

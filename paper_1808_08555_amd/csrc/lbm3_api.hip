@@ -460,7 +460,7 @@ int lbm3_destroy(lbm3_t* h)
     if (h->obs_host) (void)hipHostFree(h->obs_host);
     if (h->dtiles) (void)hipFree(h->dtiles);
     if (h->dinst) (void)hipFree(h->dinst);
-    adjoint_release(h);
+    adjoint_destroy(h);
     delete h;
     return LBM3_OK;
 }

@@ -35,6 +35,8 @@ struct lbm3 {
     std::vector<void*> ckpt;            // checkpoint states (post-streaming buffer layout)
     void* adj_ws = nullptr;             // adjoint workspace
     size_t adj_ws_bytes = 0;
+    hipStream_t adj_stream = nullptr;   // the reverse sweep's own stream (graph capture)
+    hipEvent_t adj_event = nullptr;
 };
 
 namespace tcg {
@@ -45,6 +47,7 @@ void default_tile(const KParams& kp, Prec prec, int* threads, int* rows);
 int check_rho_fields(const double* rho, const double* u, int64_t n);
 int upload_plan(lbm3* h);
 void adjoint_release(lbm3* h);
+void adjoint_destroy(lbm3* h);  // adjoint_release plus the adjoint stream and event
 // Enqueues n steps; factored = false keeps the 27-population format (the adjoint's tape).
 int step_handle(lbm3* h, int64_t n, bool factored);
 }  // namespace tcg

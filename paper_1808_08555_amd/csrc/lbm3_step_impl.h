@@ -271,7 +271,7 @@ __device__ __forceinline__ void collide_recolour(const C (&f)[9], const C (&rk)[
 // the row below, fB, rB two rows below; nB = pair normals two rows below.  With FAC input,
 // also the partial totals and densities of the two rows above (they collect the pulls of
 // each source row as it arrives).  LDS rings are indexed by row mod 3.
-template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT>
+template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT, bool TAPE>
 __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__ fout,
                                       const KParams& kp, int x0, int y0, int rows, int cols,
                                       C (*cring)[3][NT], C (*tring)[3][NT], C (*xb)[9][NT],
@@ -457,6 +457,17 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
             const C irho = C(1) / ((r0[0] + r0[1]) + r0[2]);
 #pragma unroll
             for (int k = 0; k < 3; ++k) cring[s0][k][t] = r0[k] * irho;
+            if constexpr (TAPE) {
+                // the pulled densities and totals of the tile's own nodes of this row
+                const int yd = y0 - 2 + j;
+                if (in3 && yd >= y0 && yd < y0 + rows) {
+                    const int64_t N = (int64_t)nx * ny, o = (int64_t)yd * nx + x;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) rho_out[k * N + o] = double(r0[k]);
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) rho_out[(3 + i) * N + o] = double(f0[i]);
+                }
+            }
         }
         __syncthreads();
         // ---- stage 2: gradients, normals and stress of row j-1 (densities rA)
@@ -471,6 +482,18 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
                 gx[k] = ddx<C>(M[t + 1], M[t - 1], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
                 gy[k] = ddy<C>(N[t], S_[t], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
                 cc[k] = M[t];
+            }
+            if constexpr (TAPE) {
+                // and their concentration gradients, one row later
+                const int yd = y0 - 3 + j;
+                if (in3 && yd >= y0 && yd < y0 + rows) {
+                    const int64_t N = (int64_t)nx * ny, o = (int64_t)yd * nx + x;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        rho_out[(12 + 2 * k) * N + o] = double(gx[k]);
+                        rho_out[(13 + 2 * k) * N + o] = double(gy[k]);
+                    }
+                }
             }
             C Txx = C(0), Txy = C(0), Tyy = C(0);
             constexpr int PK[3] = {0, 0, 1}, PL[3] = {1, 2, 2};
@@ -634,9 +657,13 @@ struct ExchangeLds<C, NT, Fmt::F27> {
 
 // One fused time step over a list of tiles: workgroup b takes tiles[b] of instance
 // tiles[b].inst (the plain lattice is a list with one instance).  With OBS the workgroup
-// instead accumulates the observables of its output nodes into partials[b].  With filter,
-// a workgroup whose instance's state is not in format IN returns at once.
-template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT>
+// instead accumulates the observables of its output nodes into partials[b] (and their
+// densities into rho_out when given).  With TAPE the step also writes, for every node, the
+// densities rho_k, totals f_i and concentration gradients it pulled and formed, to
+// rho_out as [18][ny][nx] (rho_k, f_i, then d_x c_k, d_y c_k per fluid): the forward
+// quantities the adjoint needs.  With filter, a workgroup whose instance's state is not in
+// format IN returns at once.
+template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT, bool TAPE = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles(const S* __restrict__ fin, S* __restrict__ fout,
                                               const Instance* __restrict__ inst,
                                               const Tile* __restrict__ tiles, uint32_t salt,
@@ -653,7 +680,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const KParams kp = inst[tl.inst].kp;
     const int64_t off = inst[tl.inst].offset;
     double acc[kObsFields] = {0, 0, 0, 0, 0, 0, 0, 0};
-    march<S, C, NT, OBS, IN, OUT>(fin + off, OBS ? nullptr : fout + off, kp, tl.x0, tl.y0, tl.rows,
+    march<S, C, NT, OBS, IN, OUT, TAPE>(fin + off, OBS ? nullptr : fout + off, kp, tl.x0, tl.y0, tl.rows,
                                   tl.cols, cring, tring, ExchangeLds<C, NT, IN>::get(), acc, rho_out,
                                   salt ^ mix32((uint32_t)tl.inst * 0x9E3779B9U + 0x51ed270bU));
     if constexpr (OBS) {
@@ -662,12 +689,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
 }
 
-template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT>
+template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT, bool TAPE = false>
 hipError_t do_tiles(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                     int ntiles, uint32_t salt, int filter, double* partials, double* rho_out,
                     hipStream_t st)
 {
-    hipLaunchKernelGGL((k_tiles<S, C, NT, OBS, IN, OUT>), dim3(ntiles), dim3(NT), 0, st,
+    hipLaunchKernelGGL((k_tiles<S, C, NT, OBS, IN, OUT, TAPE>), dim3(ntiles), dim3(NT), 0, st,
                        (const S*)fin, (S*)fout, inst, tiles, salt, filter, partials, rho_out);
     return hipGetLastError();
 }
@@ -701,6 +728,18 @@ hipError_t tiles_nt(Fmt in, Fmt out, bool obs, const void* fin, void* fout, cons
                                                                 filter, nullptr, nullptr, st);
     }
     return hipErrorInvalidValue;
+}
+
+// The FP64 step writing the adjoint's tape (rho_out as [18][ny][nx]), factored output.
+template <int NT>
+hipError_t tiles_tape_nt(Fmt in, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
+                         int ntiles, double* tape, hipStream_t st)
+{
+    if (in == Fmt::F27)
+        return do_tiles<double, double, NT, false, Fmt::F27, Fmt::FAC, true>(
+            fin, fout, inst, tiles, ntiles, 0u, 0, nullptr, tape, st);
+    return do_tiles<double, double, NT, false, Fmt::FAC, Fmt::FAC, true>(fin, fout, inst, tiles, ntiles,
+                                                                        0u, 0, nullptr, tape, st);
 }
 
 template <typename S, typename C>

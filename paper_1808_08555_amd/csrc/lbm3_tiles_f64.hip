@@ -13,4 +13,16 @@ hipError_t tiles_f64(Fmt in, Fmt out, bool obs, const void* fin, void* fout, con
 
 int tiles_f64_occupancy(int threads) { return tiles_occupancy<double, double>(threads); }
 
+hipError_t tiles_f64_tape(Fmt in, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
+                          int ntiles, int threads, double* tape, hipStream_t stream)
+{
+    switch (threads) {
+        case 64: return tiles_tape_nt<64>(in, fin, fout, inst, tiles, ntiles, tape, stream);
+        case 128: return tiles_tape_nt<128>(in, fin, fout, inst, tiles, ntiles, tape, stream);
+        case 256: return tiles_tape_nt<256>(in, fin, fout, inst, tiles, ntiles, tape, stream);
+        case 512: return tiles_tape_nt<512>(in, fin, fout, inst, tiles, ntiles, tape, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace tcg
