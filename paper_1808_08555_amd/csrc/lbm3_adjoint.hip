@@ -2,9 +2,9 @@
 //
 // The forward run keeps a checkpoint every K steps.  The reverse sweep takes the segments
 // last to first: it recomputes the segment's K forward steps from its checkpoint with the
-// fused step in its tape mode, which records the densities, totals and concentration
-// gradients it pulled and formed at every node (18 values per node and step), then takes
-// the K reverse steps, each three node-parallel kernels reading that tape.
+// fused step in its tape mode, which records the densities, totals, concentration
+// gradients and force it pulled and formed at every node (20 values per node and step),
+// then takes the K reverse steps, each three node-parallel kernels reading that tape.
 //
 // Notation: the population buffer B holds, at node y, the recoloured populations of y
 // before streaming; the post-streaming populations are f_{i,k}(x) = B_{i,k}(x - e_i).
@@ -53,6 +53,7 @@ struct AdjWS {
     double* rho;    // 3   densities
     double* ftot;   // 9   total populations
     double* gc;     // 6   grad c_k (x, y per fluid)
+    double* F;      // 2   force
     double* fbar;   // 9   dL/df_i (collision part)
     double* rbar;   // 3   dL/drho_k accumulated (all node-local contributions)
     double* Fbar;   // 2   dL/dF
@@ -116,22 +117,6 @@ __device__ __forceinline__ void node_fields(const AdjWS& w, int64_t N, int64_t j
     }
 }
 
-// stress tensor (xx, xy, yy) at a node from its fields
-__device__ __forceinline__ void stress_at(const Geo& g, const AdjWS& w, int64_t N, int64_t j, double (&T)[3])
-{
-    double rk[3], c[3], gx[3], gy[3];
-    node_fields(w, N, j, rk, c, gx, gy);
-    T[0] = T[1] = T[2] = 0.0;
-    for (int p = 0; p < 3; ++p) {
-        const PairFwd f = pair_fwd(g, p, c, gx, gy, rk);
-        if (!f.on) continue;
-        const double h = g.sigma[p] * f.C / f.m;
-        T[0] += h * f.Gy * f.Gy;
-        T[1] -= h * f.Gx * f.Gy;
-        T[2] += h * f.Gx * f.Gx;
-    }
-}
-
 // ---- A1: node-local reverse of collision and recolouring
 __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ lamp, Geo g, AdjWS w)
 {
@@ -148,22 +133,8 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ la
         for (int i = 0; i < 9; ++i) f[i] = w.ftot[i * N + j];
         PairFwd pf[3];
         for (int p = 0; p < 3; ++p) pf[p] = pair_fwd(g, p, c, gx, gy, rk);
-        // force from the stress at the 8 neighbours
-        double Tn[3][3][3];
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (dx == 0 && dy == 0) continue;
-                const int64_t q = (int64_t)wrapi(y + dy, g.ny) * g.nx + wrapi(x + dx, g.nx);
-                stress_at(g, w, N, q, Tn[dy + 1][dx + 1]);
-            }
-        double dT[3][2];
-        for (int a = 0; a < 3; ++a) {
-            const double e = Tn[1][2][a], ww = Tn[1][0][a], n = Tn[2][1][a], s = Tn[0][1][a];
-            const double ne = Tn[2][2][a], nw = Tn[2][0][a], se = Tn[0][2][a], sw = Tn[0][0][a];
-            dT[a][0] = 3.0 * ((1.0 / 9.0) * (e - ww) + (1.0 / 36.0) * ((ne - sw) + (se - nw)));
-            dT[a][1] = 3.0 * ((1.0 / 9.0) * (n - s) + (1.0 / 36.0) * ((ne - sw) + (nw - se)));
-        }
-        const double Fx = dT[0][0] + dT[1][1], Fy = dT[1][0] + dT[2][1];
+        // the force the forward step formed at this node (div T, Eq. 7 with Eq. 12)
+        const double Fx = w.F[j], Fy = w.F[N + j];
         // ---- forward collision
         const double S = rk[0] * g.inv_nu[0] + rk[1] * g.inv_nu[1] + rk[2] * g.inv_nu[2];
         const double tau = 3.0 * rho / S + 0.5;
@@ -567,7 +538,7 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     const int K = h->tape_every;
     const int64_t nseg = h->tape_steps / K;
     // workspace: 26 adjoint fields of N doubles, two adjoint buffers, two forward state
-    // buffers, the tape of K steps (18 fields each), the dL/dsigma partial sums, dL/drho_1(T)
+    // buffers, the tape of K steps (20 fields each), the dL/dsigma partial sums, dL/drho_1(T)
     const size_t fields = (size_t)(9 + 3 + 2 + 6 + 6) * N;
     const size_t need = fields * sizeof(double) + 4 * sbytes + (size_t)K * tbytes +
                         (size_t)nblocks * 6 * sizeof(double) + N * sizeof(double);
@@ -575,7 +546,7 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     if (rc) return rc;
     double* d = (double*)h->adj_ws;
     AdjWS w;
-    w.rho = w.ftot = w.gc = nullptr;  // per step: the tape of that step
+    w.rho = w.ftot = w.gc = w.F = nullptr;  // per step: the tape of that step
     w.fbar = d;
     w.rbar = w.fbar + 9 * N;
     w.Fbar = w.rbar + 3 * N;
@@ -618,6 +589,7 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
             wj.rho = tape + (size_t)j * kTapeFields * N;
             wj.ftot = wj.rho + 3 * N;
             wj.gc = wj.rho + 12 * N;
+            wj.F = wj.rho + 18 * N;
             hipLaunchKernelGGL(k_adj_local, grid, blk, 0, q, (const double*)lam[c], g, wj);
             hipLaunchKernelGGL(k_adj_stress, grid, blk, 0, q, g, wj);
             hipLaunchKernelGGL(k_adj_final, grid, blk, 0, q, g, wj, lam[c ^ 1]);

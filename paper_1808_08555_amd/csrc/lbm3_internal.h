@@ -106,10 +106,11 @@ LBM3_TILES_DECL(tiles_f32s)
 LBM3_TILES_DECL(tiles_f32)
 #undef LBM3_TILES_DECL
 // One FP64 step (F27 or FAC in, FAC out) that also records, for every node, the pulled
-// densities, totals and concentration gradients in tape[18][ny][nx] (for the adjoint).
+// densities, totals, concentration gradients and the force in tape[20][ny][nx] (for the
+// adjoint).
 hipError_t tiles_f64_tape(Fmt in, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                           int ntiles, int threads, double* tape, hipStream_t stream);
-constexpr int kTapeFields = 18;
+constexpr int kTapeFields = 20;
 
 // Host-side helpers (lbm3_api.hip).
 void set_error(const char* fmt, ...);

@@ -545,6 +545,11 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
             }
             const C Fx = d[0][0] + d[1][1];  // d_x T_xx + d_y T_yx
             const C Fy = d[1][0] + d[2][1];  // d_x T_xy + d_y T_yy
+            if constexpr (TAPE) {
+                const int64_t N = (int64_t)nx * ny, o = (int64_t)yo * nx + x;
+                rho_out[18 * N + o] = double(Fx);
+                rho_out[19 * N + o] = double(Fy);
+            }
             C fd[9], ck[3], V[6], ux, uy, mxh, myh;
             collide_recolour<C>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
             if constexpr (!OBS) {
@@ -659,9 +664,9 @@ struct ExchangeLds<C, NT, Fmt::F27> {
 // tiles[b].inst (the plain lattice is a list with one instance).  With OBS the workgroup
 // instead accumulates the observables of its output nodes into partials[b] (and their
 // densities into rho_out when given).  With TAPE the step also writes, for every node, the
-// densities rho_k, totals f_i and concentration gradients it pulled and formed, to
-// rho_out as [18][ny][nx] (rho_k, f_i, then d_x c_k, d_y c_k per fluid): the forward
-// quantities the adjoint needs.  With filter, a workgroup whose instance's state is not in
+// densities rho_k, totals f_i, concentration gradients and force it pulled and formed, to
+// rho_out as [20][ny][nx] (rho_k, f_i, d_x c_k and d_y c_k per fluid, F_x, F_y): the
+// forward quantities the adjoint needs.  With filter, a workgroup whose instance's state is not in
 // format IN returns at once.
 template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT, bool TAPE = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles(const S* __restrict__ fin, S* __restrict__ fout,
@@ -730,7 +735,7 @@ hipError_t tiles_nt(Fmt in, Fmt out, bool obs, const void* fin, void* fout, cons
     return hipErrorInvalidValue;
 }
 
-// The FP64 step writing the adjoint's tape (rho_out as [18][ny][nx]), factored output.
+// The FP64 step writing the adjoint's tape (rho_out as [20][ny][nx]), factored output.
 template <int NT>
 hipError_t tiles_tape_nt(Fmt in, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                          int ntiles, double* tape, hipStream_t st)
