@@ -15,7 +15,7 @@ import os
 from . import inputs, lbm3
 
 THREADS = (64, 128, 256, 512)
-ROWS = (0, 16, 32, 64, 128, 256)
+ROWS = (0, 2, 4, 8, 16, 32, 64, 128, 256)
 
 
 def cache_path() -> str:

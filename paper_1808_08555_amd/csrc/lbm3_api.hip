@@ -144,12 +144,13 @@ Prec prec_of(int precision)
     return precision == LBM3_FP64 ? Prec::F64 : (precision == LBM3_FP32_STORAGE ? Prec::F32S : Prec::F32);
 }
 
-// Default launch shape (measured on 4096^2): FP64 runs best with the widest strips; with
-// 4-byte storage, two workgroups of 256 per CU beat one of 512.
+// Default launch shape, from sweeps on 256^2 to 4096^2: 256 threads except for FP64 on wide
+// lattices, where one workgroup of 512 per CU with the widest strips is fastest; rows
+// fitted to the resident slots (auto_rows).
 void default_tile(const KParams& kp, Prec prec, int* threads, int* rows)
 {
     const int wide = prec == Prec::F64 ? 512 : 256;
-    *threads = kp.nx >= 2000 ? wide : (kp.nx >= 500 ? 256 : (kp.nx >= 124 ? 128 : 64));
+    *threads = kp.nx >= 2000 ? wide : (kp.nx >= 250 ? 256 : (kp.nx >= 124 ? 128 : 64));
     *rows = 0;
 }
 

@@ -68,7 +68,7 @@ static int batch_plan(lbm3_batch* b)
     const int slots = std::max(1, device_slots(b->prec, b->threads));
     int auto_r = 64;
     double best = 1e300;
-    for (int r : {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512}) {
+    for (int r : {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512}) {
         long tiles = 0;
         for (int i = 0; i < b->count; ++i) {
             std::vector<Tile> L;

@@ -65,7 +65,7 @@ int auto_rows(int nx, int ny, int threads, int slots, int elem_bytes)
     int best_rows = std::min(ny, 64);
     for (int nseg = 1; nseg <= ny; ++nseg) {
         const int rows = (ny + nseg - 1) / nseg;
-        if (rows < 8 && nseg > 1) break;
+        if (rows < 2 && nseg > 1) break;
         if (rows > 512) continue;
         const long tiles = (long)nstrips * nseg;
         const long rounds = (tiles + slots - 1) / slots;
