@@ -144,13 +144,13 @@ Prec prec_of(int precision)
     return precision == LBM3_FP64 ? Prec::F64 : (precision == LBM3_FP32_STORAGE ? Prec::F32S : Prec::F32);
 }
 
-// Default launch shape, from sweeps on 256^2 to 4096^2: 256 threads except for FP64 on wide
-// lattices, where one workgroup of 512 per CU with the widest strips is fastest; rows
-// fitted to the resident slots (auto_rows).
+// Default launch shape, from sweeps on 256^2 to 4096^2 in every precision: 256 threads (two
+// workgroups per CU) once the lattice is wide enough, rows fitted to the resident slots
+// (auto_rows).
 void default_tile(const KParams& kp, Prec prec, int* threads, int* rows)
 {
-    const int wide = prec == Prec::F64 ? 512 : 256;
-    *threads = kp.nx >= 2000 ? wide : (kp.nx >= 250 ? 256 : (kp.nx >= 124 ? 128 : 64));
+    (void)prec;
+    *threads = kp.nx >= 250 ? 256 : (kp.nx >= 124 ? 128 : 64);
     *rows = 0;
 }
 
