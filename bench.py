@@ -228,8 +228,9 @@ def main():
             extra[prec] = bench_plain(torch, lbm3, w, prec, args.steps, args.warmup)
             log(f"{prec} {extra[prec]}")
         w2 = inputs.compound_droplet(256, 30.0, 60.0, 0.01, 0.01)
-        extra["compound_256_fp64"] = bench_plain(torch, lbm3, w2, "fp64", 2000, 100)
-        log(f"compound 256 fp64 {extra['compound_256_fp64']}")
+        for prec in ("fp64", "fp32_storage"):
+            extra[f"compound_256_{prec}"] = bench_plain(torch, lbm3, w2, prec, 2000, 100)
+            log(f"compound 256 {prec} {extra[f'compound_256_{prec}']}")
         batched = bench_batched(torch, lbm3, inputs, 1000)
         log(f"batched {batched}")
         adjoint = {"janus_256": bench_adjoint(torch, lbm3, inputs, 256, 5000, 100),

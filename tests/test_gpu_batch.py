@@ -163,3 +163,27 @@ def test_morphology_sweep_classes():
         else:
             assert rg > 0 and rb > 0 and gb > 0
     lbm3.lbm3_batch_destroy(b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_reinitialised_instance_in_a_stepped_batch(precision):
+    """Re-initialising one instance after the batch has stepped leaves it in the 27-population
+    format next to factored ones; the next step runs both kinds (each launch skipping the
+    other format) and every instance still equals its plain run bitwise."""
+    ws = _mixed_workloads()
+    b = _make_batch(ws, precision)
+    lbm3.lbm3_batch_step(b, 30)
+    fresh = inputs.single_droplet(37, 7.0)
+    assert (fresh.nx, fresh.ny) == (ws[2].nx, ws[2].ny)
+    lbm3.lbm3_batch_init_fields(b, 2, fresh.rho)
+    lbm3.lbm3_batch_step(b, 25)
+    for i, w in enumerate(ws):
+        _, rho = _batch_state(b, i, w)
+        if i == 2:
+            L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, w.rho0, w.beta0, precision).init(fresh.rho).step(25)
+        else:
+            L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, w.rho0, w.beta0, precision).init(w.rho).step(55)
+        ref = L.densities()
+        L.close()
+        assert np.array_equal(rho, ref), (i, w.name)
+    lbm3.lbm3_batch_destroy(b)
