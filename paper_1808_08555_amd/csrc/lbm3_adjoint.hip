@@ -54,7 +54,6 @@ struct AdjWS {
     double* ftot;   // 9   total populations
     double* gc;     // 6   grad c_k (x, y per fluid)
     double* F;      // 2   force
-    double* fbar;   // 9   dL/df_i (collision part)
     double* rbar;   // 3   dL/drho_k accumulated (all node-local contributions)
     double* Fbar;   // 2   dL/dF
     double* Gbar;   // 6   dL/dG_p from the recolouring normals
@@ -118,7 +117,8 @@ __device__ __forceinline__ void node_fields(const AdjWS& w, int64_t N, int64_t j
 }
 
 // ---- A1: node-local reverse of collision and recolouring
-__global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ lamp, Geo g, AdjWS w)
+__global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ lamp, Geo g, AdjWS w,
+                                                   double* __restrict__ lamn)
 {
     __shared__ double red[3][256];
     const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
@@ -165,12 +165,12 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ la
             aa[p] = beta[p] * prod[p] / rho;
         }
         // ---- reverse of the recolouring
+        // dL/dB'_{i,k}(x) = dL/df'_{i,k}(x + e_i) = fbar'_i(x + e_i) + rhobar'_k(x + e_i)
         double ob[27];
-        for (int q = 0; q < 27; ++q) {
-            const int i = q % 9;
-            const int64_t d = (int64_t)y * g.pitch + x;
-            ob[q] = lamp[(int64_t)q * g.plane + d];
-            (void)i;
+        for (int i = 0; i < 9; ++i) {
+            const int64_t nb = (int64_t)wrapi(y + EY[i], g.ny) * g.nx + wrapi(x + EX[i], g.nx);
+            const double fbi = lamp[i * N + nb];
+            for (int k = 0; k < 3; ++k) ob[k * 9 + i] = fbi + lamp[(9 + k) * N + nb];
         }
         double fdb[9], cb[3] = {0, 0, 0}, Vb[3][2] = {{0, 0}, {0, 0}, {0, 0}};
         for (int i = 0; i < 9; ++i) fdb[i] = c[0] * ob[i] + c[1] * ob[9 + i] + c[2] * ob[18 + i];
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ la
         for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
         for (int k = 0; k < 3; ++k) rb[k] += cb[k] / rho - cr / (rho * rho);
         for (int k = 0; k < 3; ++k) rb[k] += rhob;  // rho = sum_k rho_k
-        for (int i = 0; i < 9; ++i) w.fbar[i * N + j] = fb[i];
+        for (int i = 0; i < 9; ++i) lamn[i * N + j] = fb[i];
         for (int k = 0; k < 3; ++k) w.rbar[k * N + j] = rb[k];
         w.Fbar[j] = Fb[0];
         w.Fbar[N + j] = Fb[1];
@@ -337,7 +337,8 @@ __global__ __launch_bounds__(256) void k_adj_stress(Geo g, AdjWS w)
     }
 }
 
-// ---- A3: reverse of the gradient (c-bar = -div gcbar), densities, totals and streaming
+// ---- A3: reverse of the gradient (c-bar = -div gcbar) and of the densities; with the
+// totals' part written by A1 this completes the adjoint state of the previous step
 __global__ __launch_bounds__(256) void k_adj_final(Geo g, AdjWS w, double* __restrict__ lam)
 {
     const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
@@ -355,30 +356,22 @@ __global__ __launch_bounds__(256) void k_adj_final(Geo g, AdjWS w, double* __res
     }
     double cr = 0.0;
     for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
-    double rb[3];
-    for (int k = 0; k < 3; ++k) rb[k] = w.rbar[k * N + j] + cb[k] / rho - cr / (rho * rho);
-    // f_{i,k}(x) = B_{i,k}(x - e_i): dL/dB_{i,k}(x - e_i) = dL/df_{i,k}(x) = fbar_i + rhobar_k
-    for (int k = 0; k < 3; ++k)
-        for (int i = 0; i < 9; ++i) {
-            const int64_t d = (int64_t)wrapi(y - EY[i], g.ny) * g.pitch + wrapi(x - EX[i], g.nx);
-            lam[(int64_t)(k * 9 + i) * g.plane + d] = w.fbar[i * N + j] + rb[k];
-        }
+    for (int k = 0; k < 3; ++k) lam[(9 + k) * N + j] = w.rbar[k * N + j] + cb[k] / rho - cr / (rho * rho);
 }
 
-// dL/drho_1(x, T) as dL/dB: lam_{i,1}(x - e_i) = g(x), other colours 0
+// The adjoint state is kept factored per node as (dL/df_i, dL/drho_k), 12 values: f_{i,k}
+// enters the step only through f_i = sum_k f_{i,k} and rho_k = sum_i f_{i,k}, so
+// dL/df_{i,k}(x) = dL/df_i(x) + dL/drho_k(x) and dL/dB_{i,k}(x - e_i) is that sum.
+// Seed: dL/drho_1(x, T) = g(x), everything else 0.
 __global__ __launch_bounds__(256) void k_adj_seed(const double* __restrict__ gT, Geo g, double* __restrict__ lam)
 {
     const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
     if (x >= g.nx) return;
-    const int64_t j = (int64_t)y * g.nx + x;
-    for (int k = 0; k < 3; ++k)
-        for (int i = 0; i < 9; ++i) {
-            const int64_t d = (int64_t)wrapi(y - EY[i], g.ny) * g.pitch + wrapi(x - EX[i], g.nx);
-            lam[(int64_t)(k * 9 + i) * g.plane + d] = k == 0 ? gT[j] : 0.0;
-        }
+    const int64_t N = (int64_t)g.nx * g.ny, j = (int64_t)y * g.nx + x;
+    for (int q = 0; q < 12; ++q) lam[q * N + j] = q == 9 ? gT[j] : 0.0;
 }
 
-// initial state B_{i,k}(y) = w_i rho_k(y + e_i):  dL/drho_k(x) = sum_i w_i lam_{i,k}(x - e_i)
+// initial state B_{i,k}(y) = w_i rho_k(y + e_i):  dL/drho_k(x) = sum_i w_i dL/dB_{i,k}(x - e_i)
 __global__ __launch_bounds__(256) void k_adj_rho0(const double* __restrict__ lam, Geo g, double* __restrict__ out)
 {
     const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
@@ -386,10 +379,7 @@ __global__ __launch_bounds__(256) void k_adj_rho0(const double* __restrict__ lam
     const int64_t N = (int64_t)g.nx * g.ny, j = (int64_t)y * g.nx + x;
     for (int k = 0; k < 3; ++k) {
         double s = 0.0;
-        for (int i = 0; i < 9; ++i) {
-            const int64_t d = (int64_t)wrapi(y - EY[i], g.ny) * g.pitch + wrapi(x - EX[i], g.nx);
-            s += wgt(i) * lam[(int64_t)(k * 9 + i) * g.plane + d];
-        }
+        for (int i = 0; i < 9; ++i) s += wgt(i) * (lam[i * N + j] + lam[(9 + k) * N + j]);
         out[k * N + j] = s;
     }
 }
@@ -537,25 +527,26 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     const size_t tbytes = (size_t)kTapeFields * N * sizeof(double);
     const int K = h->tape_every;
     const int64_t nseg = h->tape_steps / K;
-    // workspace: 26 adjoint fields of N doubles, two adjoint buffers, two forward state
-    // buffers, the tape of K steps (20 fields each), the dL/dsigma partial sums, dL/drho_1(T)
-    const size_t fields = (size_t)(9 + 3 + 2 + 6 + 6) * N;
-    const size_t need = fields * sizeof(double) + 4 * sbytes + (size_t)K * tbytes +
+    // workspace: 17 adjoint fields of N doubles, two factored adjoint states (12 fields), two
+    // forward state buffers, the tape of K steps (20 fields each), the dL/dsigma partial
+    // sums, dL/drho_1(T)
+    const size_t fields = (size_t)(3 + 2 + 6 + 6) * N;
+    const size_t lbytes = (size_t)12 * N * sizeof(double);
+    const size_t need = fields * sizeof(double) + 2 * lbytes + 2 * sbytes + (size_t)K * tbytes +
                         (size_t)nblocks * 6 * sizeof(double) + N * sizeof(double);
     int rc = ensure_ws(h, need);
     if (rc) return rc;
     double* d = (double*)h->adj_ws;
     AdjWS w;
     w.rho = w.ftot = w.gc = w.F = nullptr;  // per step: the tape of that step
-    w.fbar = d;
-    w.rbar = w.fbar + 9 * N;
+    w.rbar = d;
     w.Fbar = w.rbar + 3 * N;
     w.Gbar = w.Fbar + 2 * N;
     w.gcbar = w.Gbar + 6 * N;
     double* lam[2];
     lam[0] = w.gcbar + 6 * N;
-    lam[1] = (double*)((char*)lam[0] + sbytes);
-    char* fwd[2] = {(char*)lam[1] + sbytes, (char*)lam[1] + 2 * sbytes};
+    lam[1] = lam[0] + 12 * N;
+    char* fwd[2] = {(char*)(lam[1] + 12 * N), (char*)(lam[1] + 12 * N) + sbytes};
     double* tape = (double*)(fwd[1] + sbytes);
     w.sig = tape + (size_t)K * kTapeFields * N;
     double* gT = w.sig + nblocks * 6;
@@ -590,7 +581,7 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
             wj.ftot = wj.rho + 3 * N;
             wj.gc = wj.rho + 12 * N;
             wj.F = wj.rho + 18 * N;
-            hipLaunchKernelGGL(k_adj_local, grid, blk, 0, q, (const double*)lam[c], g, wj);
+            hipLaunchKernelGGL(k_adj_local, grid, blk, 0, q, (const double*)lam[c], g, wj, lam[c ^ 1]);
             hipLaunchKernelGGL(k_adj_stress, grid, blk, 0, q, g, wj);
             hipLaunchKernelGGL(k_adj_final, grid, blk, 0, q, g, wj, lam[c ^ 1]);
             c ^= 1;
