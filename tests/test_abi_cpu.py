@@ -5,6 +5,7 @@ import math
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -112,3 +113,15 @@ def test_autograd_wrapper_rejects_bad_shapes():
         ternary_run(torch.zeros(3, dtype=torch.float64), torch.zeros(2, 4, 4, dtype=torch.float64), 2)
     with pytest.raises(ValueError):
         ternary_run(torch.zeros(2, dtype=torch.float64), torch.zeros(3, 4, 4, dtype=torch.float64), 2)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """No fallback: with the HIP library absent the binding raises at first use."""
+    env = dict(os.environ, LBM3_LIBRARY=str(tmp_path / "absent" / "liblbm3.so"))
+    code = ("from paper_1808_08555_amd import lbm3\n"
+            "try:\n    lbm3.Lattice(8, 8)\nexcept RuntimeError as e:\n"
+            "    print('raised:', e)\n    raise SystemExit(3)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True, text=True)
+    assert r.returncode == 3, r.stdout + r.stderr
+    assert "no fallback" in r.stdout
