@@ -79,13 +79,13 @@ hipError_t launch_copy(void* dst, const void* src, int64_t nbytes, hipStream_t s
 int blocks_per_cu(Prec prec, int threads);
 
 // Tile plans (lbm3_plan.hip).
-// Tiles of one lattice in locality order (strip by strip, rows upward): strips of at most
-// threads-6 columns spread evenly over nx (line-aligned when nx allows), segments of about
-// `rows` rows spread evenly over ny.
+// Tiles of one lattice in locality order (row of tiles after row of tiles): strips of at
+// most threads-6 columns spread evenly over nx (line-aligned when nx allows), segments of
+// about `rows` rows spread evenly over ny.
 void plan_lattice(int inst, int nx, int ny, int threads, int rows, int elem_bytes,
                   std::vector<Tile>& out);
 // Reorders a locality-ordered list so that each XCD (workgroups are dealt to the XCDs in turn)
-// receives one contiguous run of it, keeping neighbouring tiles, and their shared halos, in
+// receives one contiguous run of it, keeping neighbouring tiles, and the halos they share, in
 // the same L2.
 std::vector<Tile> xcd_order(const std::vector<Tile>& L, int nxcd);
 // Rows per segment that fit the tile count to the resident workgroup slots.

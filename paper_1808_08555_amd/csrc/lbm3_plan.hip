@@ -18,26 +18,34 @@ void plan_lattice(int inst, int nx, int ny, int threads, int rows, int elem_byte
     const int wA = wmax / A * A;
     const bool aligned = nx % A == 0 && wA >= A && nx > 6;
     const int nstrips = aligned ? (nx / A + wA / A - 1) / (wA / A) : (nx + wmax - 1) / wmax;
+    // strips (x0, cols) and segments (y0, rows)
+    std::vector<int> sx0(nstrips), scols(nstrips), sy0(nseg), srows(nseg);
     int x0 = aligned ? 3 : 0;
     for (int sx = 0; sx < nstrips; ++sx) {
-        const int cols = aligned ? ((nx / A) / nstrips + (sx < (nx / A) % nstrips ? 1 : 0)) * A
-                                 : nx / nstrips + (sx < nx % nstrips ? 1 : 0);
-        int y0 = 0;
-        for (int sy = 0; sy < nseg; ++sy) {
-            const int r = ny / nseg + (sy < ny % nseg ? 1 : 0);
-            if (r > 0 && cols > 0) {
+        scols[sx] = aligned ? ((nx / A) / nstrips + (sx < (nx / A) % nstrips ? 1 : 0)) * A
+                            : nx / nstrips + (sx < nx % nstrips ? 1 : 0);
+        sx0[sx] = x0;
+        x0 += scols[sx];
+    }
+    int y0 = 0;
+    for (int sy = 0; sy < nseg; ++sy) {
+        srows[sy] = ny / nseg + (sy < ny % nseg ? 1 : 0);
+        sy0[sy] = y0;
+        y0 += srows[sy];
+    }
+    // row of tiles after row of tiles: side-by-side tiles march the same rows at the same
+    // time, so the halo columns they share are still in L2 when the second one reads them
+    for (int sy = 0; sy < nseg; ++sy)
+        for (int sx = 0; sx < nstrips; ++sx)
+            if (srows[sy] > 0 && scols[sx] > 0) {
                 Tile t{};
                 t.inst = inst;
-                t.x0 = x0;
-                t.y0 = y0;
-                t.rows = r;
-                t.cols = cols;
+                t.x0 = sx0[sx];
+                t.y0 = sy0[sy];
+                t.rows = srows[sy];
+                t.cols = scols[sx];
                 out.push_back(t);
             }
-            y0 += r;
-        }
-        x0 += cols;
-    }
 }
 
 std::vector<Tile> xcd_order(const std::vector<Tile>& L, int nxcd)
