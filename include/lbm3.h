@@ -58,7 +58,7 @@ enum { LBM3_PERIODIC = 0 };
  * Eq. 11), reference segregation parameter beta^0 (Eq. 19), periodic
  * boundaries.  Wall wettability is reserved: the paper has no wall model. */
 typedef struct {
-    int32_t nx, ny;              /* >= 1 each; 27*nx*ny < 2^31 */
+    int32_t nx, ny;              /* 1..65535 each (device memory sets the practical limit) */
     double rho0[3];              /* > 0 (the paper validates equal densities 1) */
     double sigma[3];             /* finite, > 0 */
     double tau[3];               /* finite, > 0.5 */

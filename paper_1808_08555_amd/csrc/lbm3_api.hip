@@ -40,8 +40,10 @@ int validate_params(const lbm3_params* p)
         set_error("nx and ny must be >= 1 (got %d x %d)", p->nx, p->ny);
         return LBM3_EINVAL;
     }
-    if ((int64_t)27 * p->nx * p->ny >= ((int64_t)1 << 31)) {
-        set_error("lattice too large: 27*nx*ny must be < 2^31");
+    // rows are grid rows of the per-node kernels (at most 65535); beyond that the limit is
+    // device memory (lbm3_create then returns LBM3_ENOMEM): all element offsets are 64-bit
+    if (p->nx > 65535 || p->ny > 65535) {
+        set_error("nx and ny must be <= 65535 (got %d x %d)", p->nx, p->ny);
         return LBM3_EINVAL;
     }
     for (int k = 0; k < 3; ++k) {

@@ -44,7 +44,8 @@ def _params(**kw):
 @pytest.mark.parametrize("kw,code", [
     (dict(nx=0), lbm3.LBM3_EINVAL),
     (dict(ny=-3), lbm3.LBM3_EINVAL),
-    (dict(nx=20000, ny=20000), lbm3.LBM3_EINVAL),
+    (dict(nx=70000, ny=16), lbm3.LBM3_EINVAL),
+    (dict(nx=16, ny=65536), lbm3.LBM3_EINVAL),
     (dict(tau=(0.5, 1.0, 1.0)), lbm3.LBM3_EINVAL),
     (dict(tau=(1.0, float("nan"), 1.0)), lbm3.LBM3_EINVAL),
     (dict(sigma=(0.0, 0.01, 0.01)), lbm3.LBM3_EINVAL),

@@ -333,3 +333,25 @@ def test_compound_droplet_table1_table2_setup():
     assert max(eps) < 0.015
     assert all(a > b for a, b in zip(eps, eps[1:]))
     assert 1e-6 < min(umax) and max(umax) < 1.71e-5
+
+
+@pytest.mark.parametrize("nx,ny", [(65535, 3), (3, 65535), (65535, 1)])
+def test_lattices_at_the_side_limit(nx, ny):
+    """Sides at the 65535 limit (thin lattices, so the state stays small): after 3 steps, one
+    more step is compared with the oracle at sampled nodes, including both periodic seams;
+    per-fluid mass is conserved."""
+    w = _wl("thin", inputs.random_mixture(nx, ny, 13, tiny_fraction=0.0))
+    L = lbm3.Lattice(nx, ny, w.sigma, w.tau).init(w.rho)
+    m0 = L.observables()[0]["mass"]
+    fa = L.step(3).state()
+    obs = L.observables()[0]
+    fb = L.step(1).state()
+    L.close()
+    assert np.abs(np.asarray(obs["mass"]) / np.asarray(m0) - 1).max() < 1e-13
+    rng = np.random.default_rng(1)
+    xs = np.concatenate([[0, 1, nx - 2, nx - 1], rng.integers(0, nx, 60)])
+    ys = np.concatenate([[0, ny - 1, 0, ny - 1], rng.integers(0, ny, 60)])
+    p = oracle.Params(nx, ny, w.sigma, w.tau)
+    o = oracle.step_nodes(p, fa, xs, ys)
+    g = fb[:, :, ys, xs].transpose(2, 0, 1)
+    assert np.abs(g - o).max() <= TOL_FP64
