@@ -132,8 +132,8 @@ int lbm3_get_tile(const lbm3_t *h, int32_t *threads, int32_t *rows);
 /* Device pointer of the buffer that holds the current state, its element size in
  * bytes, its strides in elements and its number of planes: plane q of node (x, y)
  * is element q*plane_stride + y*row_pitch + x.  After init_fields / set_state
- * (and during an adjoint recording) the state is the 27 populations after
- * collision and recolouring, before streaming (q = k*9 + i, nplanes = 27).  After
+ * the state is the 27 populations after collision and recolouring, before
+ * streaming (q = k*9 + i, nplanes = 27).  After
  * lbm3_step with LBM3_FP64 or LBM3_FP32 (LBM3_FP32_STORAGE keeps the 27
  * populations) it is held factored per node, nplanes = 18: f_dag_i after collision
  * (q = i), c_k = rho_k/rho (q = 9 + k) and V_k = sum_{l != k} beta_kl (rho_k
@@ -144,10 +144,26 @@ int lbm3_state_buffer(const lbm3_t *h, void **dev_ptr, int32_t *elem_bytes, int6
                       int64_t *row_pitch, int32_t *nplanes);
 
 /* ---- batched form: many independent lattices advanced together ---------------
- * count instances with parameters p[0..count-1] (all the same precision; sizes
- * may differ) share one device arena; lbm3_batch_step advances every instance by
- * n steps with one graph launch per chunk of steps (a captured hipGraph of
- * fused-step launches over a flat list of tiles spanning all instances). */
+ * The same step (Sec. 2) on count independent periodic lattices, each with its own
+ * parameters and size, all of one precision, held in one device arena.
+ *
+ * lbm3_batch_create: p[0..count-1] as for lbm3_create (each validated; mixed
+ *   precisions give EINVAL).  hip_stream as for lbm3_create; NULL makes the batch
+ *   create and own a stream (graph capture needs one).  *out is NULL on failure.
+ * lbm3_batch_init_fields: instance idx (0..count-1) from host rho [3][ny][nx] and
+ *   u [2][ny][nx] or NULL, as lbm3_init_fields.  Blocking.  May be called again
+ *   for one instance after the batch has stepped; the others keep their state.
+ * lbm3_batch_step: advances every instance by n >= 0 steps, no host sync.  Every
+ *   launch covers the tiles of all instances; each run of 20 steps replays a
+ *   captured hipGraph.  ESTATE while an instance is uninitialised.
+ * lbm3_batch_observables: blocking; observables of instance idx into *out (may be
+ *   NULL) and its densities into rho_out (host [3][ny][nx], or NULL), as
+ *   lbm3_observables.
+ * lbm3_batch_set_tile: size_class_side = 0 sets threads per workgroup for the
+ *   whole batch (and, with rows > 0, rows for every size class); a side > 0 sets
+ *   the rows of the instances with nx == side (threads must equal the batch's).
+ *   Results do not depend on the shape.
+ * lbm3_batch_destroy: releases everything; NULL is accepted. */
 int lbm3_batch_create(const lbm3_params *p, int32_t count, void *hip_stream, lbm3_batch_t **out);
 int lbm3_batch_init_fields(lbm3_batch_t *b, int32_t idx, const double *rho, const double *u);
 int lbm3_batch_step(lbm3_batch_t *b, int64_t n);
@@ -156,20 +172,28 @@ int lbm3_batch_set_tile(lbm3_batch_t *b, int32_t size_class_side, int32_t thread
 int lbm3_batch_destroy(lbm3_batch_t *b);
 
 /* ---- adjoint (reverse-mode derivative) of the FP64 step ----------------------
- * lbm3_adjoint_record: advances the FP64 state by nsteps (as lbm3_step) and keeps
- * a checkpoint of the state every ckpt_every steps (device memory).
- * lbm3_adjoint: given drho1_T = dL/drho_1(x, T) (host [ny][nx]) for the state at
- * the end of the last recording, returns dL/dsigma (3, order rg, rb, gb) and
- * dL/drho_k(x, 0) (host [3][ny][nx]) for the densities given to init_fields
- * (u == NULL), by a hand-written reverse sweep over the step (recolouring,
- * collision with Guo forcing, force divergence, colour gradient, streaming) with
- * segment recomputation from the checkpoints.  Blocking.  The forward state is
- * left at step T.  Requires LBM3_FP64 and a preceding lbm3_adjoint_record. */
+ * lbm3_adjoint_record: from the state set by lbm3_init_fields(rho, NULL) at step 0
+ *   (else ESTATE), advances the FP64 state by nsteps (as lbm3_step) and keeps a
+ *   checkpoint of the state every ckpt_every steps in device memory (nsteps >= 1
+ *   a multiple of ckpt_every >= 1, else EINVAL).  LBM3_EUNSUPPORTED unless the
+ *   handle is LBM3_FP64.
+ * lbm3_adjoint: given drho1_T = dL/drho_1(x, T) (host [ny][nx], finite) for the
+ *   state at the end of the last recording, returns dL/dsigma in dsigma[3] (order
+ *   rg, rb, gb; may be NULL) and dL/drho_k(x, 0) in drho0 (host [3][ny][nx] for
+ *   the densities given to init_fields; may be NULL).  It runs a hand-written
+ *   reverse sweep over the step (recolouring of Eq. 13 with Eqs. 19-20, collision
+ *   with Guo forcing of Eqs. 8-9, the force of Eq. 7, the colour gradient of
+ *   Eq. 12, streaming), recomputing each segment from its checkpoint.  Blocking;
+ *   allocates a workspace of about 20 ckpt_every + 100 doubles per node (the
+ *   checkpoints hold 18 per node each).  The
+ *   forward state is left at step T.  ESTATE without a recording or after a step
+ *   since it. */
 int lbm3_adjoint_record(lbm3_t *h, int64_t nsteps, int32_t ckpt_every);
 int lbm3_adjoint(lbm3_t *h, const double *drho1_T, double dsigma[3], double *drho0);
 
-/* Plain device copy of nbytes (multiple of 16) from src to dst on hip_stream:
- * the bandwidth reference the roofline figures are compared with. */
+/* Plain device copy of nbytes (a multiple of 16) from device src to device dst on
+ * hip_stream (NULL = null stream), no host sync: the bandwidth reference the
+ * roofline figures are compared with.  EINVAL for NULL pointers or a bad size. */
 int lbm3_device_copy(void *dst, const void *src, int64_t nbytes, void *hip_stream);
 
 #ifdef __cplusplus
