@@ -26,9 +26,10 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS & % HBM roofline: plain FP64 vs FP32 batched vs adjoint step"
 HBM_PEAK_GBS = 8000.0
-# Values read and written once per lattice update.  FP64 and FP32 keep the recoloured state
-# factored per node (f_dag_i, c_k, V_k: 18 values); FP32 storage keeps the 27 populations.
-BYTES_PER_LU = {"fp64": 2 * 18 * 8, "fp32_storage": 2 * 27 * 4, "fp32": 2 * 18 * 4}
+# Bytes of the state of one node between steps: FP64 and FP32 keep the recoloured state
+# factored (f_dag_i, c_k, V_k: 18 values), FP32 storage the 27 populations.  A launch reads
+# and writes the state once, whether it advances one step or two.
+STATE_BYTES = {"fp64": 18 * 8, "fp32_storage": 27 * 4, "fp32": 18 * 4}
 
 
 def log(msg: str):
@@ -92,20 +93,30 @@ def copy_bandwidth(torch, lbm3, nbytes: int = 2 << 30, reps: int = 5) -> float:
     return 2 * nbytes / float(np.median(best)) / 1e9
 
 
-def bench_plain(torch, lbm3, w, precision: str, steps: int, warmup: int):
+def bench_plain(torch, lbm3, w, precision: str, steps: int, warmup: int, steps_per_launch: int = 0):
+    """Times `steps` steps (even, so that two-step launches cover them all when used).
+    Returns MLUPS and the dominant kernel's algorithmic bandwidth: state bytes read and
+    written per launch over the time per launch."""
     st = torch.cuda.current_stream()
     L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, precision=precision, stream=st)
     L.init(w.rho)
-    L.step(warmup)
+    L.set_steps_per_launch(steps_per_launch)
+    L.step(warmup + (warmup % 2 == 0))  # leaves the state factored after an odd first step
     torch.cuda.synchronize()
     t = time_steps(torch, lbm3, L, steps)
-    tile = L.tile()
+    per_launch, t2, wg2 = lbm3.lbm3_get_pair_launch(L.h)
+    tile = {"one_step": list(L.tile()), "steps_per_launch": per_launch}
+    if per_launch == 2:
+        tile["two_step"] = {"threads": t2, "workgroups": wg2}
     obs = L.observables()[0]
     L.close()
     n = w.nx * w.ny
-    mlups = n * steps / t / 1e6
-    return {"mlups": mlups, "ms_per_step": t / steps * 1e3, "tile": list(tile),
-            "gbs": BYTES_PER_LU[precision] * n * steps / t / 1e9, "nonfinite": obs["nonfinite"]}
+    launches = steps // per_launch
+    bytes_per_launch = 2 * STATE_BYTES[precision] * n
+    return {"mlups": n * steps / t / 1e6, "ms_per_step": t / steps * 1e3, "tile": tile,
+            "steps_per_launch": per_launch, "bytes_per_launch": bytes_per_launch,
+            "ms_per_launch": t / launches * 1e3,
+            "gbs": bytes_per_launch * launches / t / 1e9, "nonfinite": obs["nonfinite"]}
 
 
 def bench_batched(torch, lbm3, inputs, steps: int):
@@ -134,7 +145,7 @@ def bench_batched(torch, lbm3, inputs, steps: int):
     t = a.elapsed_time(e) / 1e3
     lbm3.lbm3_batch_destroy(b)
     res = {"instances": len(ws), "nodes": nodes, "mlups": nodes * steps / t / 1e6,
-           "ms_per_step": t / steps * 1e3, "gbs": BYTES_PER_LU["fp32"] * nodes * steps / t / 1e9,
+           "ms_per_step": t / steps * 1e3, "gbs": 2 * STATE_BYTES["fp32"] * nodes * steps / t / 1e9,
            "threads": threads, "rows_by_side": {str(k): v for k, v in rows.items()}}
     side = int(round(nodes ** 0.5))
     weq = inputs.droplet_tiling(side - side % 256 if side >= 512 else side, cell=256)
@@ -220,8 +231,11 @@ def main():
     torch.cuda.set_device(0)
     w = inputs.droplet_tiling(4096)
     log(f"workload {w.name}: {w.nx}x{w.ny}, FP64, {args.warmup} warm-up + {args.steps} timed steps")
+    args.steps += args.steps % 2
     main_res = bench_plain(torch, lbm3, w, "fp64", args.steps, args.warmup)
     log(f"fp64 {main_res}")
+    one_step = bench_plain(torch, lbm3, w, "fp64", args.steps, args.warmup, steps_per_launch=1)
+    log(f"fp64, one step per launch {one_step}")
     extra = {}
     if not args.only_plain:
         for prec in ("fp32_storage", "fp32"):
@@ -242,10 +256,17 @@ def main():
     n = w.nx * w.ny
     achieved = main_res["gbs"]
     traffic = measured_traffic("lbm3_step_fp64_R4096")
+    kernel = ("two steps per launch (k_tiles2)" if main_res["steps_per_launch"] == 2
+              else "one step per launch (k_tiles)")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "bytes_per_lu": BYTES_PER_LU["fp64"], "lu_per_launch": n,
-                "frac_of_device_copy": round(achieved / copy_gbs, 4), "device_copy_gbs": round(copy_gbs, 1)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+                "bytes_per_launch": main_res["bytes_per_launch"],
+                "lu_per_launch": n * main_res["steps_per_launch"],
+                "ms_per_launch": round(main_res["ms_per_launch"], 4),
+                "frac_of_device_copy": round(achieved / copy_gbs, 4), "device_copy_gbs": round(copy_gbs, 1),
+                "one_step_kernel": {"mlups": round(one_step["mlups"], 1), "gbs": round(one_step["gbs"], 1),
+                                    "frac": round(one_step["gbs"] / HBM_PEAK_GBS, 4),
+                                    "frac_of_device_copy": round(one_step["gbs"] / copy_gbs, 4)}}
     cpu = None
     if not args.no_cpu_baseline:
         log("oracle CPU baseline ...")

@@ -25,6 +25,11 @@ CFLAGS = [
     "-Wno-unused-parameter",
     # packed-FP32 instructions disabled for all HIP code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fused only within one source expression (llvm.fmuladd from the front end),
+    # never across statements by the back end: the same arithmetic then rounds the same way
+    # in every kernel that inlines it, which the bitwise equalities between the step's
+    # variants (27-population and factored, single and two-step) rely on
+    "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"),
 ]
 SOURCES = ["lbm3_tiles_f64.hip", "lbm3_tiles_f32s.hip", "lbm3_tiles_f32.hip", "lbm3_step.hip",

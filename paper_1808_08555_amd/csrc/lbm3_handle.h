@@ -22,6 +22,11 @@ struct lbm3 {
     tcg::Instance* dinst = nullptr;     // device copy of the one-instance table
     tcg::Tile* dtiles = nullptr;        // device tile list (XCD-aware order)
     int ntiles = 0;
+    tcg::Tile* dtiles2 = nullptr;       // tile list of the two-step pass (null: not used)
+    int ntiles2 = 0;
+    int threads2 = 0;                   // its threads per workgroup
+    int pass_mode = 0;                  // steps per launch: 0 automatic, 1 one, 2 two
+    bool tile_set = false;              // launch shape chosen by lbm3_set_tile
     double* staging = nullptr;          // device FP64 staging for host transfers
     size_t staging_cap = 0;
     double* partials = nullptr;         // per-workgroup observables partials

@@ -80,17 +80,21 @@ int blocks_per_cu(Prec prec, int threads);
 
 // Tile plans (lbm3_plan.hip).
 // Tiles of one lattice in locality order (row of tiles after row of tiles): strips of at
-// most threads-6 columns spread evenly over nx (line-aligned when nx allows), segments of
+// most threads - 2 halo columns spread evenly over nx (line-aligned when nx allows), segments of
 // about `rows` rows spread evenly over ny.
+// halo: columns (and half the warm-up rows) beyond the strip that one pass needs: 3 for the
+// single step, 6 for the two-step pass.
 void plan_lattice(int inst, int nx, int ny, int threads, int rows, int elem_bytes,
-                  std::vector<Tile>& out);
+                  std::vector<Tile>& out, int halo = 3);
 // Reorders a locality-ordered list so that each XCD (workgroups are dealt to the XCDs in turn)
 // receives one contiguous run of it, keeping neighbouring tiles, and the halos they share, in
 // the same L2.
 std::vector<Tile> xcd_order(const std::vector<Tile>& L, int nxcd);
 // Rows per segment that fit the tile count to the resident workgroup slots.
-int auto_rows(int nx, int ny, int threads, int slots, int elem_bytes);
+int auto_rows(int nx, int ny, int threads, int slots, int elem_bytes, int halo = 3);
 int device_slots(Prec prec, int threads);
+// resident slots of the two-step pass (0 where it does not exist: FP32 storage, 512 threads)
+int device_slots_pair(Prec prec, int threads);
 
 size_t elem_bytes(Prec p);
 uint32_t step_salt(int64_t step);
@@ -111,6 +115,14 @@ LBM3_TILES_DECL(tiles_f32)
 hipError_t tiles_f64_tape(Fmt in, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                           int ntiles, int threads, double* tape, hipStream_t stream);
 constexpr int kTapeFields = 20;
+// Two FP64 / FP32 steps per launch (factored state in and out) over a plan with
+// cols <= threads - 12 (threads 64, 128 or 256); bitwise the same as two single steps.
+hipError_t tiles_f64_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
+                          int ntiles, int threads, hipStream_t stream);
+hipError_t tiles_f32_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
+                          int ntiles, int threads, hipStream_t stream);
+int tiles_f64_pair_occupancy(int threads);
+int tiles_f32_pair_occupancy(int threads);
 
 // Host-side helpers (lbm3_api.hip).
 void set_error(const char* fmt, ...);

@@ -6,21 +6,21 @@
 namespace tcg {
 
 void plan_lattice(int inst, int nx, int ny, int threads, int rows, int elem_bytes,
-                  std::vector<Tile>& out)
+                  std::vector<Tile>& out, int halo)
 {
-    const int wmax = threads - 6;
+    const int wmax = threads - 2 * halo;
     const int nseg = std::max(1, (ny + std::max(rows, 1) - 1) / std::max(rows, 1));
     // Line-aligned strips: widths in units of A elements (one 128-byte line) and strips
-    // starting at x = 3 (mod A), so that lane 0 of every wavefront (column x0 - 3 + 64 w) sits
-    // on a line boundary and unshifted loads cover whole lines.  Used when nx is a multiple
-    // of A and a unit-aligned strip width fits the workgroup.
+    // starting at x = halo (mod A), so that lane 0 of every wavefront (column
+    // x0 - halo + 64 w) sits on a line boundary and unshifted loads cover whole lines.  Used
+    // when nx is a multiple of A and a unit-aligned strip width fits the workgroup.
     const int A = 128 / elem_bytes;
     const int wA = wmax / A * A;
-    const bool aligned = nx % A == 0 && wA >= A && nx > 6;
+    const bool aligned = nx % A == 0 && wA >= A && nx > 2 * halo;
     const int nstrips = aligned ? (nx / A + wA / A - 1) / (wA / A) : (nx + wmax - 1) / wmax;
     // strips (x0, cols) and segments (y0, rows)
     std::vector<int> sx0(nstrips), scols(nstrips), sy0(nseg), srows(nseg);
-    int x0 = aligned ? 3 : 0;
+    int x0 = aligned ? halo : 0;
     for (int sx = 0; sx < nstrips; ++sx) {
         scols[sx] = aligned ? ((nx / A) / nstrips + (sx < (nx / A) % nstrips ? 1 : 0)) * A
                             : nx / nstrips + (sx < nx % nstrips ? 1 : 0);
@@ -61,14 +61,15 @@ std::vector<Tile> xcd_order(const std::vector<Tile>& L, int nxcd)
     return out;
 }
 
-int auto_rows(int nx, int ny, int threads, int slots, int elem_bytes)
+int auto_rows(int nx, int ny, int threads, int slots, int elem_bytes, int halo)
 {
     std::vector<Tile> probe;
-    plan_lattice(0, nx, 1, threads, 1, elem_bytes, probe);
+    plan_lattice(0, nx, 1, threads, 1, elem_bytes, probe, halo);
     const int nstrips = (int)probe.size();
     if (slots < 1) slots = 1;
-    // time ~ rounds * (rows per segment + 6 warm-up rows: the pipeline is two rows deep
-    // and the factored pull starts two source rows further down); fewest rounds, then rows
+    // time ~ rounds * (rows per segment + 2 halo warm-up rows: a step's pipeline is two
+    // rows deep and its factored pull starts two source rows further down, six rows in
+    // all, twelve for the two-step pass); fewest rounds, then fewest rows
     double best = 1e300;
     int best_rows = std::min(ny, 64);
     for (int nseg = 1; nseg <= ny; ++nseg) {
@@ -77,7 +78,7 @@ int auto_rows(int nx, int ny, int threads, int slots, int elem_bytes)
         if (rows > 512) continue;
         const long tiles = (long)nstrips * nseg;
         const long rounds = (tiles + slots - 1) / slots;
-        const double cost = (double)rounds * (rows + 6) * (1.0 + 1e-9 * nseg);
+        const double cost = (double)rounds * (rows + 2 * halo) * (1.0 + 1e-9 * nseg);
         if (cost < best) {
             best = cost;
             best_rows = rows;
@@ -86,12 +87,22 @@ int auto_rows(int nx, int ny, int threads, int slots, int elem_bytes)
     return best_rows;
 }
 
-int device_slots(Prec prec, int threads)
+static int device_cus()
 {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    return blocks_per_cu(prec, threads) * cus;
+    return cus;
+}
+
+int device_slots(Prec prec, int threads) { return blocks_per_cu(prec, threads) * device_cus(); }
+
+int device_slots_pair(Prec prec, int threads)
+{
+    int per_cu = 0;
+    if (prec == Prec::F64) per_cu = tiles_f64_pair_occupancy(threads);
+    if (prec == Prec::F32) per_cu = tiles_f32_pair_occupancy(threads);
+    return per_cu * device_cus();
 }
 
 }  // namespace tcg

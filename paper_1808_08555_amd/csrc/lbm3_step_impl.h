@@ -263,6 +263,123 @@ __device__ __forceinline__ void collide_recolour(const C (&f)[9], const C (&rk)[
     for (int k = 0; k < 3; ++k) ck[k] = rk[k] * irho;
 }
 
+// The pulls of one source row s to rows s+1, s and s-1 (FAC input), in the fixed group order:
+// f_dag(i) gives the f_dag_i pulled by this lane for direction i; X holds the c_k, V_k of the
+// source row by lane (fields 0-2 c_k, 3-8 V_k), read at lane t - e_x,i.  D0 = partial sums of
+// row s (directions with e_y = +1 and 0 received), D1 = those of row s + 1 (e_y = +1
+// received); direction groups by e_y: +1 {2, 5, 6}, 0 {0, 1, 3}, -1 {4, 7, 8}.  Completes row
+// s - 1 into r0, f0.  (The scheduling barriers keep the LDS reads of one group from being
+// hoisted above the previous group, which would hold all 81 of them in registers at once.)
+template <typename C, int NT, typename FD>
+__device__ __forceinline__ void pull_row(FD f_dag, const C (*X)[NT], int t, C (&d0r)[3], C (&d0f)[6],
+                                         C (&d1r)[3], C (&d1f)[3], C (&r0)[3], C (&f0)[9])
+{
+    auto pull = [&](int i, C (&fk)[3]) {
+        const int l = t - EX[i];
+        const C fdi = f_dag(i);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) fk[k] = recon<C>(X[k][l], fdi, X[3 + 2 * k][l], X[4 + 2 * k][l], i);
+    };
+    auto group = [&](int a, int b, int c, C (&g)[3], C& ta, C& tb, C& tc) {
+        C fa[3], fb[3], fc[3];
+        pull(a, fa);
+        pull(b, fb);
+        pull(c, fc);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g[k] = group_sum<C>(fa[k], fb[k], fc[k]);
+        ta = (fa[0] + fa[1]) + fa[2];
+        tb = (fb[0] + fb[1]) + fb[2];
+        tc = (fc[0] + fc[1]) + fc[2];
+    };
+    C g[3];
+    // e_y = -1: completes row s - 1 as (P + Z) + M
+    group(4, 7, 8, g, f0[4], f0[7], f0[8]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r0[k] = d0r[k] + g[k];
+    f0[2] = d0f[0];
+    f0[5] = d0f[1];
+    f0[6] = d0f[2];
+    f0[0] = d0f[3];
+    f0[1] = d0f[4];
+    f0[3] = d0f[5];
+    // e_y = 0: row s is P (from s - 1) + Z
+    group(0, 1, 3, g, d0f[3], d0f[4], d0f[5]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d0r[k] = d1r[k] + g[k];
+    d0f[0] = d1f[0];
+    d0f[1] = d1f[1];
+    d0f[2] = d1f[2];
+    __builtin_amdgcn_sched_barrier(0);
+    // e_y = +1: row s + 1 starts with P
+    group(2, 5, 6, d1r, d1f[0], d1f[1], d1f[2]);
+}
+
+// Stage 2 at lane t: colour gradients of the middle ring row (slot s1; s0 above, s2 below),
+// pair normals n[6] and the stress (Txx, Txy, Tyy) from the densities rk of that row.
+template <typename C, int NT>
+__device__ __forceinline__ void stress_at_lane(const C (*cring)[3][NT], int s0, int s1, int s2, int t,
+                                               const C (&rk)[3], const StepConsts<C>& K, C (&gx)[3],
+                                               C (&gy)[3], C (&n)[6], C& Txx, C& Txy, C& Tyy)
+{
+    C cc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const C* N = cring[s0][k];
+        const C* M = cring[s1][k];
+        const C* S_ = cring[s2][k];
+        gx[k] = ddx<C>(M[t + 1], M[t - 1], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
+        gy[k] = ddy<C>(N[t], S_[t], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
+        cc[k] = M[t];
+    }
+    Txx = C(0);
+    Txy = C(0);
+    Tyy = C(0);
+    constexpr int PK[3] = {0, 0, 1}, PL[3] = {1, 2, 2};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const int k = PK[p], l = PL[p];
+        C Gx, Gy, mag;
+        {
+            // The two products of G nearly cancel where a fluid is present only as a trace;
+            // unfused, their rounding matches the plain IEEE evaluation.
+#pragma clang fp contract(off)
+            Gx = cc[l] * gx[k] - cc[k] * gx[l];
+            Gy = cc[l] * gy[k] - cc[k] * gy[l];
+            mag = sqrt(Gx * Gx + Gy * Gy);
+        }
+        if (mag > K.guard) {
+            const C inv = C(1) / mag;
+            n[2 * p] = Gx * inv;
+            n[2 * p + 1] = Gy * inv;
+            C cf = K.cfac[p] * (rk[k] * rk[l]);
+            cf = cf < C(1) ? cf : C(1);
+            const C coef = K.sig[p] * cf * inv;
+            Txx += coef * (Gy * Gy);
+            Txy -= coef * (Gx * Gy);
+            Tyy += coef * (Gx * Gx);
+        }
+    }
+}
+
+// Stage 3's force at lane t: F = div T over the stress ring (s1 above, s2 middle, s0 below).
+template <typename C, int NT>
+__device__ __forceinline__ void force_at_lane(const C (*tring)[3][NT], int s0, int s1, int s2, int t,
+                                              C& Fx, C& Fy)
+{
+    C d[3][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const C* N = tring[s1][a];  // row above
+        const C* M = tring[s2][a];  // middle row
+        const C* S_ = tring[s0][a]; // row below
+        d[a][0] = ddx<C>(M[t + 1], M[t - 1], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
+        d[a][1] = ddy<C>(N[t], S_[t], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
+    }
+    Fx = d[0][0] + d[1][1];  // d_x T_xx + d_y T_yx
+    Fy = d[1][0] + d[2][1];  // d_x T_xy + d_y T_yy
+}
+
 // The y-marching body shared by the stepping and observing kernels.  The workgroup owns
 // output columns [x0, x0 + cols) (cols <= NT - 6) and output rows [y0, y0 + rows).  Lane t
 // sits on column x0 - 3 + t; lanes 1..cols+4 form densities, 2..cols+3 gradients and
@@ -322,8 +439,7 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
 #pragma unroll
         for (int q = 9; q < NV; ++q) v[q] = C(ld_at(fin + ((int64_t)q * plane + rowo), xoff));
     };
-    // FAC partial sums: D0 = row s (directions with e_y = +1 and 0 received), D1 = row s + 1
-    // (e_y = +1 received).  Direction groups by e_y: +1 {2, 5, 6}, 0 {0, 1, 3}, -1 {4, 7, 8}.
+    // FAC partial sums of the rows above (see pull_row)
     C d0r[3], d0f[6], d1r[3], d1f[3];  // d0f: f_2, f_5, f_6, f_0, f_1, f_3; d1f: f_2, f_5, f_6
     // FAC: publish the c_k, V_k of this lane's column of a source row (v[9..17]) to the
     // neighbouring lanes, in exchange slot `slot` (two slots, used by alternate rows); a
@@ -337,51 +453,9 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
         }
     };
     // FAC: the pulls of source row s (f_dag in v[0..8], c_k and V_k in exchange slot `slot`)
-    // to rows s+1, s and s-1, in the fixed group order; completes row s-1 into r0, f0.
     auto consume_fac = [&](const C (&v)[NV], int slot, C (&r0)[3], C (&f0)[9]) {
         if (!in1) return;
-        const C (*X)[NT] = xb[slot];
-        auto pull = [&](int i, C (&fk)[3]) {
-            const int l = t - EX[i];
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                fk[k] = recon<C>(X[k][l], v[i], X[3 + 2 * k][l], X[4 + 2 * k][l], i);
-        };
-        auto group = [&](int a, int b, int c, C (&g)[3], C& ta, C& tb, C& tc) {
-            C fa[3], fb[3], fc[3];
-            pull(a, fa);
-            pull(b, fb);
-            pull(c, fc);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) g[k] = group_sum<C>(fa[k], fb[k], fc[k]);
-            ta = (fa[0] + fa[1]) + fa[2];
-            tb = (fb[0] + fb[1]) + fb[2];
-            tc = (fc[0] + fc[1]) + fc[2];
-        };
-        C g[3];
-        // e_y = -1: completes row s - 1 as (P + Z) + M.  (The scheduling barriers keep the
-        // LDS reads of one group from being hoisted above the previous group, which would
-        // hold all 81 of them in registers at once.)
-        group(4, 7, 8, g, f0[4], f0[7], f0[8]);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) r0[k] = d0r[k] + g[k];
-        f0[2] = d0f[0];
-        f0[5] = d0f[1];
-        f0[6] = d0f[2];
-        f0[0] = d0f[3];
-        f0[1] = d0f[4];
-        f0[3] = d0f[5];
-        // e_y = 0: row s is P (from s - 1) + Z
-        group(0, 1, 3, g, d0f[3], d0f[4], d0f[5]);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) d0r[k] = d1r[k] + g[k];
-        d0f[0] = d1f[0];
-        d0f[1] = d1f[1];
-        d0f[2] = d1f[2];
-        __builtin_amdgcn_sched_barrier(0);
-        // e_y = +1: row s + 1 starts with P
-        group(2, 5, 6, d1r, d1f[0], d1f[1], d1f[2]);
+        pull_row<C, NT>([&](int i) { return v[i]; }, xb[slot], t, d0r, d0f, d1r, d1f, r0, f0);
     };
     // F27: densities and totals of a row from its 27 pulled populations, same order.
     auto consume_f27 = [&](const C (&v)[NV], C (&r0)[3], C (&f0)[9]) {
@@ -476,16 +550,8 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
         // ---- stage 2: gradients, normals and stress of row j-1 (densities rA)
         C nA[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
         if (j >= 2 && in2) {
-            C gx[3], gy[3], cc[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const C* N = cring[s0][k];
-                const C* M = cring[s1][k];
-                const C* S_ = cring[s2][k];
-                gx[k] = ddx<C>(M[t + 1], M[t - 1], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
-                gy[k] = ddy<C>(N[t], S_[t], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
-                cc[k] = M[t];
-            }
+            C gx[3], gy[3], Txx, Txy, Tyy;
+            stress_at_lane<C, NT>(cring, s0, s1, s2, t, rA, K, gx, gy, nA, Txx, Txy, Tyy);
             if constexpr (TAPE) {
                 // and their concentration gradients, one row later
                 const int yd = y0 - 3 + j;
@@ -496,32 +562,6 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
                         rho_out[(12 + 2 * k) * N + o] = double(gx[k]);
                         rho_out[(13 + 2 * k) * N + o] = double(gy[k]);
                     }
-                }
-            }
-            C Txx = C(0), Txy = C(0), Tyy = C(0);
-            constexpr int PK[3] = {0, 0, 1}, PL[3] = {1, 2, 2};
-#pragma unroll
-            for (int p = 0; p < 3; ++p) {
-                const int k = PK[p], l = PL[p];
-                C Gx, Gy, mag;
-                {
-                    // The two products of G nearly cancel where a fluid is present only as a
-                    // trace; unfused, their rounding matches the plain IEEE evaluation.
-#pragma clang fp contract(off)
-                    Gx = cc[l] * gx[k] - cc[k] * gx[l];
-                    Gy = cc[l] * gy[k] - cc[k] * gy[l];
-                    mag = sqrt(Gx * Gx + Gy * Gy);
-                }
-                if (mag > K.guard) {
-                    const C inv = C(1) / mag;
-                    nA[2 * p] = Gx * inv;
-                    nA[2 * p + 1] = Gy * inv;
-                    C cf = K.cfac[p] * (rA[k] * rA[l]);
-                    cf = cf < C(1) ? cf : C(1);
-                    const C coef = K.sig[p] * cf * inv;
-                    Txx += coef * (Gy * Gy);
-                    Txy -= coef * (Gx * Gy);
-                    Tyy += coef * (Gx * Gx);
                 }
             }
             tring[s1][0][t] = Txx;
@@ -537,17 +577,8 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
         // ---- stage 3: force, collision, recolouring of row j-2 (fB, rB, nB)
         if (j >= 4 && in3) {
             const int yo = y0 + j - 4;
-            C d[3][2];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const C* N = tring[s1][a];  // row j-1
-                const C* M = tring[s2][a];  // row j-2
-                const C* S_ = tring[s0][a]; // row j-3
-                d[a][0] = ddx<C>(M[t + 1], M[t - 1], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
-                d[a][1] = ddy<C>(N[t], S_[t], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
-            }
-            const C Fx = d[0][0] + d[1][1];  // d_x T_xx + d_y T_yx
-            const C Fy = d[1][0] + d[2][1];  // d_x T_xy + d_y T_yy
+            C Fx, Fy;
+            force_at_lane<C, NT>(tring, s0, s1, s2, t, Fx, Fy);
             if constexpr (TAPE) {
                 const int64_t N = (int64_t)nx * ny, o = (int64_t)yo * nx + x;
                 rho_out[18 * N + o] = double(Fx);
@@ -620,6 +651,203 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
         }
 #pragma unroll
         for (int q = 0; q < 6; ++q) nB[q] = nA[q];
+    }
+}
+
+// Two fused steps per pass (factored state in and out; storage type = compute type).  Step A
+// pulls its source rows from global memory as march() does; the rows it recolours never
+// leave the chip: step B pulls them from an LDS exchange row holding all 18 values, and only
+// B's rows are stored.  HBM traffic per step is half that of march(), and the arithmetic is
+// march()'s, so the result equals two single steps bit for bit.  Lane t sits on column
+// x0 - 6 + t.  A forms densities on lanes 1..cols+10 and recolours lanes 3..cols+8 (B's
+// source columns); B forms densities on lanes 4..cols+7 and outputs lanes 6..cols+5, so
+// cols <= NT - 12.  A runs six rows ahead: iteration j consumes A's source row y0 - 4 + j,
+// A recolours row y0 - 7 + j, B consumes that row at once and outputs row y0 - 10 + j.
+template <typename C, int NT>
+__device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict__ fout,
+                                       const KParams& kp, int x0, int y0, int rows, int cols,
+                                       C (*cA)[3][NT], C (*tA)[3][NT], C (*xA)[9][NT],
+                                       C (*cB)[3][NT], C (*tB)[3][NT], C (*xB)[NT])
+{
+    const int nx = kp.nx, ny = kp.ny;
+    const int64_t plane = kp.plane;
+    const int t = threadIdx.x;
+    const int x = wrapi(x0 - 6 + t, nx);
+    const unsigned scol[3] = {(unsigned)wrapi(x + 1, nx) * (unsigned)sizeof(C),
+                              (unsigned)x * (unsigned)sizeof(C),
+                              (unsigned)wrapi(x - 1, nx) * (unsigned)sizeof(C)};
+    const unsigned xoff = (unsigned)x * (unsigned)sizeof(C);
+    const bool a0 = t <= cols + 11;
+    const bool a1 = (t >= 1) && (t <= cols + 10);
+    const bool a2 = (t >= 2) && (t <= cols + 9);
+    const bool a3 = (t >= 3) && (t <= cols + 8);
+    const bool b1 = (t >= 4) && (t <= cols + 7);
+    const bool b2 = (t >= 5) && (t <= cols + 6);
+    const bool b3 = (t >= 6) && (t <= cols + 5);
+    const StepConsts<C> K(kp);
+    const int JA = rows + 10;
+
+    auto load_fac = [&](int s, C (&v)[18]) {
+        const int64_t rowo = (int64_t)wrapi(s, ny) * kp.fpitch;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) v[i] = ld_at(fin + ((int64_t)i * plane + rowo), scol[EX[i] + 1]);
+#pragma unroll
+        for (int q = 9; q < 18; ++q) v[q] = ld_at(fin + ((int64_t)q * plane + rowo), xoff);
+    };
+    auto publish_a = [&](const C (&v)[18], int slot) {
+        if (a0) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) xA[slot][q][t] = v[9 + q];
+        }
+    };
+
+    // A: pipeline, partial sums and the prefetched next source row
+    C fA_a[9], fB_a[9], rA_a[3], rB_a[3], nB_a[6], d0r_a[3], d0f_a[6], d1r_a[3], d1f_a[3], vn[18];
+    // B: pipeline and partial sums
+    C fA_b[9], fB_b[9], rA_b[3], rB_b[3], nB_b[6], d0r_b[3], d0f_b[6], d1r_b[3], d1f_b[3];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fA_a[i] = fB_a[i] = fA_b[i] = fB_b[i] = C(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        rA_a[k] = rB_a[k] = rA_b[k] = rB_b[k] = C(1);
+        d0r_a[k] = d1r_a[k] = d0r_b[k] = d1r_b[k] = C(0);
+        d1f_a[k] = d1f_b[k] = C(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) nB_a[q] = nB_b[q] = d0f_a[q] = d0f_b[q] = C(0);
+#pragma unroll
+    for (int q = 0; q < 18; ++q) vn[q] = C(1);
+
+    // A's pre-roll (as march() with first output row y0 - 3): source rows y0 - 6 and y0 - 5,
+    // then row y0 - 4 published for the first iteration
+    if (a0) load_fac(y0 - 6, vn);
+#pragma unroll 1
+    for (int p = 0; p < 2; ++p) {
+        C v[18], r_[3], f_[9];
+#pragma unroll
+        for (int q = 0; q < 18; ++q) v[q] = vn[q];
+        publish_a(v, p);
+        if (a0) load_fac(y0 - 5 + p, vn);
+        __syncthreads();
+        if (a1)
+            pull_row<C, NT>([&](int i) { return v[i]; }, xA[p], t, d0r_a, d0f_a, d1r_a, d1f_a, r_, f_);
+    }
+    publish_a(vn, 0);
+    __syncthreads();
+
+#pragma unroll 1
+    for (int j = 0; j < JA; ++j) {
+        const int sa0 = j % 3, sa1 = (j + 2) % 3, sa2 = (j + 1) % 3;
+        const int jb = j - 6;
+        const int sb0 = (jb + 6) % 3, sb1 = (jb + 8) % 3, sb2 = (jb + 7) % 3;
+        // ---- A stage 1: densities of row y0 - 5 + j from source row y0 - 4 + j
+        C f0a[9], r0a[3];
+        {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f0a[i] = C(0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) r0a[k] = C(1);
+            C v[18];
+#pragma unroll
+            for (int q = 0; q < 18; ++q) v[q] = vn[q];
+            if (a0 && j + 1 < JA) load_fac(y0 - 3 + j, vn);
+            if (a1)
+                pull_row<C, NT>([&](int i) { return v[i]; }, xA[j & 1], t, d0r_a, d0f_a, d1r_a, d1f_a,
+                                r0a, f0a);
+            const C irho = C(1) / ((r0a[0] + r0a[1]) + r0a[2]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cA[sa0][k][t] = r0a[k] * irho;
+        }
+        __syncthreads();
+        // ---- A stage 2: stress of row y0 - 6 + j; publish the next source row
+        C nA_a[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
+        if (j >= 2 && a2) {
+            C gx[3], gy[3], Txx, Txy, Tyy;
+            stress_at_lane<C, NT>(cA, sa0, sa1, sa2, t, rA_a, K, gx, gy, nA_a, Txx, Txy, Tyy);
+            tA[sa1][0][t] = Txx;
+            tA[sa1][1][t] = Txy;
+            tA[sa1][2][t] = Tyy;
+        }
+        if (j + 1 < JA) publish_a(vn, (j + 1) & 1);
+        __syncthreads();
+        // ---- A stage 3: recolour row y0 - 7 + j into B's exchange row
+        if (j >= 4 && a3) {
+            C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
+            force_at_lane<C, NT>(tA, sa0, sa1, sa2, t, Fx, Fy);
+            collide_recolour<C>(fB_a, rB_a, nB_a, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) xB[i][t] = fd[i];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) xB[9 + k][t] = ck[k];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) xB[12 + q][t] = V[q];
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            fB_a[i] = fA_a[i];
+            fA_a[i] = f0a[i];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            rB_a[k] = rA_a[k];
+            rA_a[k] = r0a[k];
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) nB_a[q] = nA_a[q];
+        __syncthreads();
+        // ---- B stage 1: pulls of source row y0 - 7 + j (the pre-roll for j = 4, 5)
+        C f0b[9], r0b[3];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f0b[i] = C(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r0b[k] = C(1);
+        if (j >= 4 && b1)
+            pull_row<C, NT>([&](int i) { return xB[i][t - EX[i]]; }, xB + 9, t, d0r_b, d0f_b, d1r_b, d1f_b,
+                            r0b, f0b);
+        if (jb >= 0) {
+            const C irho = C(1) / ((r0b[0] + r0b[1]) + r0b[2]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cB[sb0][k][t] = r0b[k] * irho;
+        }
+        __syncthreads();
+        // ---- B stage 2
+        C nA_b[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
+        if (jb >= 2 && b2) {
+            C gx[3], gy[3], Txx, Txy, Tyy;
+            stress_at_lane<C, NT>(cB, sb0, sb1, sb2, t, rA_b, K, gx, gy, nA_b, Txx, Txy, Tyy);
+            tB[sb1][0][t] = Txx;
+            tB[sb1][1][t] = Txy;
+            tB[sb1][2][t] = Tyy;
+        }
+        __syncthreads();
+        // ---- B stage 3: recolour and store row y0 - 4 + jb
+        if (jb >= 4 && b3) {
+            const int yo = y0 - 4 + jb;
+            C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
+            force_at_lane<C, NT>(tB, sb0, sb1, sb2, t, Fx, Fy);
+            collide_recolour<C>(fB_b, rB_b, nB_b, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
+            const int64_t orow = (int64_t)yo * kp.fpitch;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) st_at(fout + ((int64_t)i * plane + orow), xoff, fd[i]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) st_at(fout + ((int64_t)(9 + k) * plane + orow), xoff, ck[k]);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) st_at(fout + ((int64_t)(12 + q) * plane + orow), xoff, V[q]);
+        }
+        if (jb >= 0) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                fB_b[i] = fA_b[i];
+                fA_b[i] = f0b[i];
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                rB_b[k] = rA_b[k];
+                rA_b[k] = r0b[k];
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) nB_b[q] = nA_b[q];
+        }
     }
 }
 
@@ -762,6 +990,57 @@ hipError_t tiles_any(Fmt in, Fmt out, bool obs, const void* fin, void* fout, con
         case 512: return tiles_nt<S, C, 512>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// Two fused steps over a list of tiles (march2); tiles come from a plan with cols <= NT - 12.
+template <typename C, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_tiles2(
+    const C* __restrict__ fin, C* __restrict__ fout, const Instance* __restrict__ inst,
+    const Tile* __restrict__ tiles)
+{
+    __shared__ alignas(16) C ringsA[2][3][3][NT];
+    __shared__ alignas(16) C xA[2][9][NT];
+    __shared__ alignas(16) C ringsB[2][3][3][NT];
+    __shared__ alignas(16) C xB[18][NT];
+    const Tile tl = tiles[blockIdx.x];
+    const KParams kp = inst[tl.inst].kp;
+    const int64_t off = inst[tl.inst].offset;
+    march2<C, NT>(fin + off, fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, ringsA[0], ringsA[1], xA,
+                  ringsB[0], ringsB[1], xB);
+}
+
+template <typename C>
+hipError_t tiles_pair_any(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
+                          int ntiles, int threads, hipStream_t st)
+{
+    switch (threads) {
+        case 64:
+            hipLaunchKernelGGL((k_tiles2<C, 64>), dim3(ntiles), dim3(64), 0, st, (const C*)fin, (C*)fout, inst, tiles);
+            break;
+        case 128:
+            hipLaunchKernelGGL((k_tiles2<C, 128>), dim3(ntiles), dim3(128), 0, st, (const C*)fin, (C*)fout, inst, tiles);
+            break;
+        case 256:
+            hipLaunchKernelGGL((k_tiles2<C, 256>), dim3(ntiles), dim3(256), 0, st, (const C*)fin, (C*)fout, inst, tiles);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename C>
+int pair_occupancy(int threads)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (threads) {
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2<C, 64>, 64, 0); break;
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2<C, 128>, 128, 0); break;
+        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2<C, 256>, 256, 0); break;
+        default: break;
+    }
+    return e == hipSuccess ? nb : 0;
 }
 
 // Resident workgroups per CU of the steady-state step (the format of steady_fmt).

@@ -13,4 +13,12 @@ hipError_t tiles_f32(Fmt in, Fmt out, bool obs, const void* fin, void* fout, con
 
 int tiles_f32_occupancy(int threads) { return tiles_occupancy<float, float>(threads); }
 
+hipError_t tiles_f32_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
+                          int ntiles, int threads, hipStream_t stream)
+{
+    return tiles_pair_any<float>(fin, fout, inst, tiles, ntiles, threads, stream);
+}
+
+int tiles_f32_pair_occupancy(int threads) { return pair_occupancy<float>(threads); }
+
 }  // namespace tcg

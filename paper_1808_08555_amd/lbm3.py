@@ -77,6 +77,9 @@ def lib():
             "lbm3_derived": (I, [P, _DP, _DP, _DP]),
             "lbm3_set_tile": (I, [H, ctypes.c_int32, ctypes.c_int32]),
             "lbm3_get_tile": (I, [H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+            "lbm3_set_steps_per_launch": (I, [H, ctypes.c_int32]),
+            "lbm3_get_pair_launch": (I, [H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32)]),
             "lbm3_state_buffer": (I, [H, ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(ctypes.c_int32)]),
@@ -194,6 +197,19 @@ def lbm3_derived(params: lbm3_params):
 
 def lbm3_set_tile(h, threads: int, rows: int):
     _check(lib().lbm3_set_tile(h, int(threads), int(rows)), "lbm3_set_tile")
+
+
+def lbm3_set_steps_per_launch(h, mode: int):
+    """0 = by lattice size, 1 = one step per launch, 2 = two steps per launch where possible."""
+    _check(lib().lbm3_set_steps_per_launch(h, int(mode)), "lbm3_set_steps_per_launch")
+
+
+def lbm3_get_pair_launch(h):
+    """(steps per launch for pairs, threads, workgroups) of the launch used for pairs of steps."""
+    st, th, wg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().lbm3_get_pair_launch(h, ctypes.byref(st), ctypes.byref(th), ctypes.byref(wg)),
+           "lbm3_get_pair_launch")
+    return st.value, th.value, wg.value
 
 
 def lbm3_get_tile(h):
@@ -317,6 +333,10 @@ class Lattice:
 
     def tile(self):
         return lbm3_get_tile(self.h)
+
+    def set_steps_per_launch(self, mode: int):
+        lbm3_set_steps_per_launch(self.h, mode)
+        return self
 
     def close(self):
         if getattr(self, "h", None) is not None:

@@ -355,3 +355,28 @@ def test_lattices_at_the_side_limit(nx, ny):
     o = oracle.step_nodes(p, fa, xs, ys)
     g = fb[:, :, ys, xs].transpose(2, 0, 1)
     assert np.abs(g - o).max() <= TOL_FP64
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape,tile", [((64, 64), None), ((301, 83), (128, 5)), ((600, 333), (256, 0)),
+                                        ((97, 130), (64, 9))])
+def test_two_step_pass_equals_single_steps_bitwise(shape, tile, precision):
+    """Two steps per launch (the middle state stays on chip) and one step per launch must
+    give the same state bit for bit."""
+    nx, ny = shape
+    R = min(nx, ny) * 0.2
+    disks = [(0, nx * 0.3, ny * 0.5, R), (1, nx * 0.7, ny * 0.5, R)]
+    lab = inputs.label_disks(nx, ny, disks)
+    rho = inputs.add_interface_noise(inputs.rho_from_labels(lab), lab, disks, seed=4)
+    sig, tau = (0.011, 0.013, 0.017), (0.7, 1.0, 1.3)
+    A = lbm3.Lattice(nx, ny, sig, tau, precision=precision).init(rho).set_steps_per_launch(1)
+    B = lbm3.Lattice(nx, ny, sig, tau, precision=precision).init(rho).set_steps_per_launch(2)
+    if tile:
+        A.set_tile(*tile)
+        B.set_tile(*tile)
+    A.step(12)
+    B.step(12)
+    fa, fb = A.state(), B.state()
+    A.close()
+    B.close()
+    assert np.array_equal(fa, fb)
