@@ -317,11 +317,17 @@ __device__ __forceinline__ void pull_row(FD f_dag, const C (*X)[NT], int t, C (&
 
 // Stage 2 at lane t: colour gradients of the middle ring row (slot s1; s0 above, s2 below),
 // pair normals n[6] and the stress (Txx, Txy, Tyy) from the densities rk of that row.
-template <typename C, int NT>
+// on_gradients(gx, gy) sees the gradients before the pair loop (the adjoint's tape).
+struct NoGradientHook {
+    template <typename A>
+    __device__ void operator()(const A&, const A&) const {}
+};
+template <typename C, int NT, typename Hook = NoGradientHook>
 __device__ __forceinline__ void stress_at_lane(const C (*cring)[3][NT], int s0, int s1, int s2, int t,
-                                               const C (&rk)[3], const StepConsts<C>& K, C (&gx)[3],
-                                               C (&gy)[3], C (&n)[6], C& Txx, C& Txy, C& Tyy)
+                                               const C (&rk)[3], const StepConsts<C>& K, C (&n)[6],
+                                               C& Txx, C& Txy, C& Tyy, Hook on_gradients = Hook())
 {
+    C gx[3], gy[3];
     C cc[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -332,6 +338,7 @@ __device__ __forceinline__ void stress_at_lane(const C (*cring)[3][NT], int s0, 
         gy[k] = ddy<C>(N[t], S_[t], N[t + 1], N[t - 1], S_[t + 1], S_[t - 1]);
         cc[k] = M[t];
     }
+    on_gradients(gx, gy);
     Txx = C(0);
     Txy = C(0);
     Tyy = C(0);
@@ -550,19 +557,24 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
         // ---- stage 2: gradients, normals and stress of row j-1 (densities rA)
         C nA[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
         if (j >= 2 && in2) {
-            C gx[3], gy[3], Txx, Txy, Tyy;
-            stress_at_lane<C, NT>(cring, s0, s1, s2, t, rA, K, gx, gy, nA, Txx, Txy, Tyy);
+            C Txx, Txy, Tyy;
             if constexpr (TAPE) {
                 // and their concentration gradients, one row later
                 const int yd = y0 - 3 + j;
-                if (in3 && yd >= y0 && yd < y0 + rows) {
-                    const int64_t N = (int64_t)nx * ny, o = (int64_t)yd * nx + x;
+                const bool own = in3 && yd >= y0 && yd < y0 + rows;
+                const int64_t N = (int64_t)nx * ny, o = (int64_t)yd * nx + x;
+                stress_at_lane<C, NT>(cring, s0, s1, s2, t, rA, K, nA, Txx, Txy, Tyy,
+                                      [&](const C (&gx)[3], const C (&gy)[3]) {
+                                          if (own) {
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        rho_out[(12 + 2 * k) * N + o] = double(gx[k]);
-                        rho_out[(13 + 2 * k) * N + o] = double(gy[k]);
-                    }
-                }
+                                              for (int k = 0; k < 3; ++k) {
+                                                  rho_out[(12 + 2 * k) * N + o] = double(gx[k]);
+                                                  rho_out[(13 + 2 * k) * N + o] = double(gy[k]);
+                                              }
+                                          }
+                                      });
+            } else {
+                stress_at_lane<C, NT>(cring, s0, s1, s2, t, rA, K, nA, Txx, Txy, Tyy);
             }
             tring[s1][0][t] = Txx;
             tring[s1][1][t] = Txy;
@@ -762,8 +774,8 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
         // ---- A stage 2: stress of row y0 - 6 + j; publish the next source row
         C nA_a[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
         if (j >= 2 && a2) {
-            C gx[3], gy[3], Txx, Txy, Tyy;
-            stress_at_lane<C, NT>(cA, sa0, sa1, sa2, t, rA_a, K, gx, gy, nA_a, Txx, Txy, Tyy);
+            C Txx, Txy, Tyy;
+            stress_at_lane<C, NT>(cA, sa0, sa1, sa2, t, rA_a, K, nA_a, Txx, Txy, Tyy);
             tA[sa1][0][t] = Txx;
             tA[sa1][1][t] = Txy;
             tA[sa1][2][t] = Tyy;
@@ -813,8 +825,8 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
         // ---- B stage 2
         C nA_b[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
         if (jb >= 2 && b2) {
-            C gx[3], gy[3], Txx, Txy, Tyy;
-            stress_at_lane<C, NT>(cB, sb0, sb1, sb2, t, rA_b, K, gx, gy, nA_b, Txx, Txy, Tyy);
+            C Txx, Txy, Tyy;
+            stress_at_lane<C, NT>(cB, sb0, sb1, sb2, t, rA_b, K, nA_b, Txx, Txy, Tyy);
             tB[sb1][0][t] = Txx;
             tB[sb1][1][t] = Txy;
             tB[sb1][2][t] = Tyy;
