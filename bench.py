@@ -256,7 +256,7 @@ def main():
     n = w.nx * w.ny
     achieved = main_res["gbs"]
     traffic = measured_traffic("lbm3_step_fp64_R4096")
-    kernel = ("two steps per launch (k_tiles2)" if main_res["steps_per_launch"] == 2
+    kernel = ("two steps per launch (k_tiles2w: one step per wave group)" if main_res["steps_per_launch"] == 2
               else "one step per launch (k_tiles)")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,

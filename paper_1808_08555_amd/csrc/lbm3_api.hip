@@ -198,11 +198,12 @@ int upload_plan(lbm3* h)
         rows = auto_rows(h->kp.nx, h->kp.ny, h->threads, device_slots(h->prec, h->threads), eb);
     std::vector<Tile> L, L2;
     plan_lattice(0, h->kp.nx, h->kp.ny, h->threads, rows, eb, L);
-    // The two-step pass halves the traffic per step but runs one wave per SIMD (FP64) and
-    // needs a 12-row warm-up per tile: it wins on large lattices (measured: FP64 +7%, FP32
-    // +26% at 4096^2, even at 1024^2, slower at 512^2 and below).  Its own default width:
-    // 128 threads for FP64, 256 for FP32; lbm3_set_tile's width applies to both passes.
-    const bool big = (int64_t)h->kp.nx * h->kp.ny >= ((int64_t)1 << 21);
+    // The two-step pass halves the traffic per step but needs a 12-row warm-up per tile:
+    // it wins on large lattices (measured: FP64 +37%, FP32 +22% at 4096^2, FP64 +15% and
+    // FP32 even at 1024^2, no gain at 512^2).  Its own default width: 128 columns for FP64
+    // (256 lanes, one step per wave group), 256 for FP32; lbm3_set_tile's width applies to
+    // both passes.
+    const bool big = (int64_t)h->kp.nx * h->kp.ny >= ((int64_t)1 << 20);
     const bool want2 = h->pass_mode == 2 || (h->pass_mode == 0 && big);
     int t2 = h->tile_set ? h->threads : std::min(h->prec == Prec::F64 ? 128 : 256, h->threads);
     const int slots2 = steady_fmt(h->prec) == Fmt::FAC && want2 ? device_slots_pair(h->prec, t2) : 0;
@@ -537,7 +538,7 @@ int lbm3_get_pair_launch(const lbm3_t* h, int32_t* steps, int32_t* threads, int3
     }
     const bool two = h->ntiles2 > 0;
     if (steps) *steps = two ? 2 : 1;
-    if (threads) *threads = two ? h->threads2 : 0;
+    if (threads) *threads = two ? (h->prec == Prec::F64 ? 2 : 1) * h->threads2 : 0;
     if (workgroups) *workgroups = two ? h->ntiles2 : 0;
     return LBM3_OK;
 }

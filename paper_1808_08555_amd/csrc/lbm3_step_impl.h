@@ -666,11 +666,261 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
     }
 }
 
-// Two fused steps per pass (factored state in and out; storage type = compute type).  Step A
-// pulls its source rows from global memory as march() does; the rows it recolours never
-// leave the chip: step B pulls them from an LDS exchange row holding all 18 values, and only
-// B's rows are stored.  HBM traffic per step is half that of march(), and the arithmetic is
-// march()'s, so the result equals two single steps bit for bit.  Lane t sits on column
+// Two fused steps per pass (factored state in and out; storage type = compute type), each
+// step on its own waves of the workgroup.  Step A (lanes 0..NT-1 of the workgroup) pulls its
+// source rows from global memory as march() does; the rows it recolours never leave the
+// chip: it writes them, all 18 values, to an LDS exchange row xB, from which step B (lanes
+// NT..2NT-1) pulls them; only B's rows are stored.  HBM traffic per step is half that of
+// march(), and the arithmetic is march()'s, so the result equals two single steps bit for
+// bit.  Each wave holds one step's registers, so two waves fit on a SIMD where one thread
+// carrying both steps would not.
+//
+// Lane t of either step sits on column x0 - 6 + t.  A forms densities on lanes 1..cols+10
+// and recolours lanes 3..cols+8 (B's source columns); B forms densities on lanes 4..cols+7
+// and outputs lanes 6..cols+5, so cols <= NT - 12.  Every iteration has three phases, each
+// closed by a barrier that both steps' waves reach (the same number of times: three per
+// pre-roll and three per iteration of a loop of the same length):
+//   phase 0: A densities (stage 1)      B force, recolouring, store (stage 3)
+//   phase 1: A stress (stage 2)         B densities from xB (stage 1)
+//   phase 2: A recolouring into xB      B stress (stage 2)
+// Iteration j: A consumes source row y0 - 4 + j and recolours row y0 - 7 + j into xB; B
+// pulls that row in iteration j + 1 and outputs row y0 - 12 + j.
+template <typename C, int NT>
+struct alignas(16) PairLds {
+    C cA[3][3][NT];  // A: concentration ring (by row mod 3)
+    C tA[3][3][NT];  // A: stress ring
+    C xA[2][9][NT];  // A: c_k, V_k of the source row, double-buffered
+    C cB[3][3][NT];
+    C tB[3][3][NT];
+    C xB[18][NT];    // A's recoloured row: f_dag (0-8), c_k (9-11), V_k (12-17)
+};
+
+template <typename C, int NT>
+__device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KParams& kp, int x0, int y0,
+                                            int rows, int cols, PairLds<C, NT>& L, int t)
+{
+    const int nx = kp.nx, ny = kp.ny;
+    const int64_t plane = kp.plane;
+    const int x = wrapi(x0 - 6 + t, nx);
+    const unsigned scol[3] = {(unsigned)wrapi(x + 1, nx) * (unsigned)sizeof(C),
+                              (unsigned)x * (unsigned)sizeof(C),
+                              (unsigned)wrapi(x - 1, nx) * (unsigned)sizeof(C)};
+    const unsigned xoff = (unsigned)x * (unsigned)sizeof(C);
+    const bool a0 = t <= cols + 11;
+    const bool a1 = (t >= 1) && (t <= cols + 10);
+    const bool a2 = (t >= 2) && (t <= cols + 9);
+    const bool a3 = (t >= 3) && (t <= cols + 8);
+    const StepConsts<C> K(kp);
+    const int JA = rows + 10;
+    const int J = rows + 12;
+
+    auto load_fac = [&](int s, C (&v)[18]) {
+        const int64_t rowo = (int64_t)wrapi(s, ny) * kp.fpitch;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) v[i] = ld_at(fin + ((int64_t)i * plane + rowo), scol[EX[i] + 1]);
+#pragma unroll
+        for (int q = 9; q < 18; ++q) v[q] = ld_at(fin + ((int64_t)q * plane + rowo), xoff);
+    };
+    auto publish = [&](const C (&v)[18], int slot) {
+        if (a0) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) L.xA[slot][q][t] = v[9 + q];
+        }
+    };
+
+    C fA[9], fB[9], rA[3], rB[3], nB[6], d0r[3], d0f[6], d1r[3], d1f[3], vn[18];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fA[i] = fB[i] = C(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        rA[k] = rB[k] = C(1);
+        d0r[k] = d1r[k] = d1f[k] = C(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) nB[q] = d0f[q] = C(0);
+#pragma unroll
+    for (int q = 0; q < 18; ++q) vn[q] = C(1);
+
+    // pre-roll (as march() with first output row y0 - 3): source rows y0 - 6 and y0 - 5, then
+    // row y0 - 4 published for the first iteration; three barriers
+    if (a0) load_fac(y0 - 6, vn);
+#pragma unroll 1
+    for (int p = 0; p < 2; ++p) {
+        C v[18], r_[3], f_[9];
+#pragma unroll
+        for (int q = 0; q < 18; ++q) v[q] = vn[q];
+        publish(v, p);
+        if (a0) load_fac(y0 - 5 + p, vn);
+        __syncthreads();
+        if (a1) pull_row<C, NT>([&](int i) { return v[i]; }, L.xA[p], t, d0r, d0f, d1r, d1f, r_, f_);
+    }
+    publish(vn, 0);
+    __syncthreads();
+
+#pragma unroll 1
+    for (int j = 0; j < J; ++j) {
+        const bool live = j < JA;
+        const int s0 = j % 3, s1 = (j + 2) % 3, s2 = (j + 1) % 3;
+        // phase 0: densities of row y0 - 5 + j from source row y0 - 4 + j
+        C f0[9], r0[3];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f0[i] = C(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r0[k] = C(1);
+        if (live) {
+            C v[18];
+#pragma unroll
+            for (int q = 0; q < 18; ++q) v[q] = vn[q];
+            if (a0 && j + 1 < JA) load_fac(y0 - 3 + j, vn);
+            if (a1) pull_row<C, NT>([&](int i) { return v[i]; }, L.xA[j & 1], t, d0r, d0f, d1r, d1f, r0, f0);
+            const C irho = C(1) / ((r0[0] + r0[1]) + r0[2]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) L.cA[s0][k][t] = r0[k] * irho;
+        }
+        __syncthreads();
+        // phase 1: stress of row y0 - 6 + j; publish the next source row
+        C nA[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
+        if (live && j >= 2 && a2) {
+            C Txx, Txy, Tyy;
+            stress_at_lane<C, NT>(L.cA, s0, s1, s2, t, rA, K, nA, Txx, Txy, Tyy);
+            L.tA[s1][0][t] = Txx;
+            L.tA[s1][1][t] = Txy;
+            L.tA[s1][2][t] = Tyy;
+        }
+        if (j + 1 < JA) publish(vn, (j + 1) & 1);
+        __syncthreads();
+        // phase 2: recolour row y0 - 7 + j into xB
+        if (live && j >= 4 && a3) {
+            C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
+            force_at_lane<C, NT>(L.tA, s0, s1, s2, t, Fx, Fy);
+            collide_recolour<C>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) L.xB[i][t] = fd[i];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) L.xB[9 + k][t] = ck[k];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) L.xB[12 + q][t] = V[q];
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            fB[i] = fA[i];
+            fA[i] = f0[i];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            rB[k] = rA[k];
+            rA[k] = r0[k];
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) nB[q] = nA[q];
+        __syncthreads();
+    }
+}
+
+// B's rows are numbered by m: its stage 1 pulls source row y0 - 1 + m and completes the
+// densities of row y0 - 2 + m (partial sums only for m = -2, -1), its stage 2 forms the
+// stress of row y0 - 3 + m and its stage 3 outputs row y0 - 4 + m.  Stage 1 and 2 of row m run in iteration m + 7 (phases 1, 2), stage 3 in
+// iteration m + 8 (phase 0), so the densities, totals and normals of row m wait across one
+// loop edge (f1, r1, n1) before they move into the pipeline.
+template <typename C, int NT>
+__device__ __forceinline__ void pair_step_b(C* __restrict__ fout, const KParams& kp, int x0, int y0,
+                                            int rows, int cols, PairLds<C, NT>& L, int t)
+{
+    const int nx = kp.nx;
+    const int64_t plane = kp.plane;
+    const int x = wrapi(x0 - 6 + t, nx);
+    const unsigned xoff = (unsigned)x * (unsigned)sizeof(C);
+    const bool b1 = (t >= 4) && (t <= cols + 7);
+    const bool b2 = (t >= 5) && (t <= cols + 6);
+    const bool b3 = (t >= 6) && (t <= cols + 5);
+    const StepConsts<C> K(kp);
+    const int MB = rows + 3;  // last row index m
+    const int J = rows + 12;
+
+    C fA[9], fB[9], rA[3], rB[3], nB[6], d0r[3], d0f[6], d1r[3], d1f[3], f1[9], r1[3], n1[6];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fA[i] = fB[i] = f1[i] = C(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        rA[k] = rB[k] = r1[k] = C(1);
+        d0r[k] = d1r[k] = d1f[k] = C(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) nB[q] = d0f[q] = n1[q] = C(0);
+
+    // A's three pre-roll barriers
+#pragma unroll 1
+    for (int p = 0; p < 3; ++p) __syncthreads();
+
+#pragma unroll 1
+    for (int j = 0; j < J; ++j) {
+        // phase 0: stage 3 of row m3 = j - 8, then row m3 enters the pipeline
+        const int m3 = j - 8;
+        if (m3 >= 4 && m3 <= MB && b3) {
+            const int yo = y0 - 4 + m3;
+            C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
+            force_at_lane<C, NT>(L.tB, (m3 + 6) % 3, (m3 + 8) % 3, (m3 + 7) % 3, t, Fx, Fy);
+            collide_recolour<C>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
+            const int64_t orow = (int64_t)yo * kp.fpitch;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) st_at(fout + ((int64_t)i * plane + orow), xoff, fd[i]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) st_at(fout + ((int64_t)(9 + k) * plane + orow), xoff, ck[k]);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) st_at(fout + ((int64_t)(12 + q) * plane + orow), xoff, V[q]);
+        }
+        if (m3 >= 0 && m3 <= MB) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                fB[i] = fA[i];
+                fA[i] = f1[i];
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                rB[k] = rA[k];
+                rA[k] = r1[k];
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) nB[q] = n1[q];
+        }
+        __syncthreads();
+        // phase 1: stage 1 of row m = j - 7 from A's row in xB
+        const int m = j - 7;
+        const bool live = m >= -2 && m <= MB;
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f1[i] = C(0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) r1[k] = C(1);
+            if (b1)
+                pull_row<C, NT>([&](int i) { return L.xB[i][t - EX[i]]; }, L.xB + 9, t, d0r, d0f, d1r, d1f,
+                                r1, f1);
+            if (m >= 0) {
+                const C irho = C(1) / ((r1[0] + r1[1]) + r1[2]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) L.cB[(m + 6) % 3][k][t] = r1[k] * irho;
+            }
+        }
+        __syncthreads();
+        // phase 2: stage 2 of row m
+        if (live) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) n1[q] = C(0);
+            if (m >= 2 && b2) {
+                C Txx, Txy, Tyy;
+                stress_at_lane<C, NT>(L.cB, (m + 6) % 3, (m + 8) % 3, (m + 7) % 3, t, rA, K, n1, Txx, Txy, Tyy);
+                L.tB[(m + 8) % 3][0][t] = Txx;
+                L.tB[(m + 8) % 3][1][t] = Txy;
+                L.tB[(m + 8) % 3][2][t] = Tyy;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The same two-step pass with each thread carrying both steps (used for FP32, whose two
+// steps fit one thread's registers at two waves per SIMD; measured 5% faster there than the
+// wave-specialised form at 4096^2, while FP64 is 30% faster wave-specialised).  Lane t sits on column
 // x0 - 6 + t.  A forms densities on lanes 1..cols+10 and recolours lanes 3..cols+8 (B's
 // source columns); B forms densities on lanes 4..cols+7 and outputs lanes 6..cols+5, so
 // cols <= NT - 12.  A runs six rows ahead: iteration j consumes A's source row y0 - 4 + j,
@@ -1004,9 +1254,30 @@ hipError_t tiles_any(Fmt in, Fmt out, bool obs, const void* fin, void* fout, con
     }
 }
 
-// Two fused steps over a list of tiles (march2); tiles come from a plan with cols <= NT - 12.
+// Two fused steps over a list of tiles; tiles come from a plan with cols <= NT - 12.  The
+// workgroup has 2 NT lanes: waves of lanes 0..NT-1 run step A, the others step B (the
+// choice is uniform per wave).
 template <typename C, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_tiles2(
+__global__ __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles2w(
+    const C* __restrict__ fin, C* __restrict__ fout, const Instance* __restrict__ inst,
+    const Tile* __restrict__ tiles)
+{
+    static_assert(NT % 64 == 0, "each wave must belong to one step");
+    __shared__ PairLds<C, NT> lds;
+    const Tile tl = tiles[blockIdx.x];
+    const KParams kp = inst[tl.inst].kp;
+    const int64_t off = inst[tl.inst].offset;
+    const int lane0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x);
+    if (lane0 < NT)
+        pair_step_a<C, NT>(fin + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x);
+    else
+        pair_step_b<C, NT>(fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x - NT);
+}
+
+// Two fused steps over a list of tiles, one thread per column carrying both (march2);
+// tiles come from a plan with cols <= NT - 12.
+template <typename C, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_tiles2f(
     const C* __restrict__ fin, C* __restrict__ fout, const Instance* __restrict__ inst,
     const Tile* __restrict__ tiles)
 {
@@ -1021,38 +1292,54 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
                   ringsB[0], ringsB[1], xB);
 }
 
+// The two-step pass: FP64 wave-specialised (k_tiles2w, 2 x threads lanes), FP32 with one
+// thread per column (k_tiles2f, threads lanes); `threads` is the tile width basis NT.
+template <typename C, int NT>
+hipError_t pair_launch(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                       hipStream_t st)
+{
+    if constexpr (sizeof(C) == 8)
+        hipLaunchKernelGGL((k_tiles2w<C, NT>), dim3(ntiles), dim3(2 * NT), 0, st, (const C*)fin, (C*)fout,
+                           inst, tiles);
+    else
+        hipLaunchKernelGGL((k_tiles2f<C, NT>), dim3(ntiles), dim3(NT), 0, st, (const C*)fin, (C*)fout, inst,
+                           tiles);
+    return hipGetLastError();
+}
+
 template <typename C>
 hipError_t tiles_pair_any(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                           int ntiles, int threads, hipStream_t st)
 {
     switch (threads) {
-        case 64:
-            hipLaunchKernelGGL((k_tiles2<C, 64>), dim3(ntiles), dim3(64), 0, st, (const C*)fin, (C*)fout, inst, tiles);
-            break;
-        case 128:
-            hipLaunchKernelGGL((k_tiles2<C, 128>), dim3(ntiles), dim3(128), 0, st, (const C*)fin, (C*)fout, inst, tiles);
-            break;
-        case 256:
-            hipLaunchKernelGGL((k_tiles2<C, 256>), dim3(ntiles), dim3(256), 0, st, (const C*)fin, (C*)fout, inst, tiles);
-            break;
-        default:
-            return hipErrorInvalidValue;
+        case 64: return pair_launch<C, 64>(fin, fout, inst, tiles, ntiles, st);
+        case 128: return pair_launch<C, 128>(fin, fout, inst, tiles, ntiles, st);
+        case 256: return pair_launch<C, 256>(fin, fout, inst, tiles, ntiles, st);
+        default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+}
+
+template <typename C, int NT>
+int pair_occupancy_nt()
+{
+    int nb = 0;
+    hipError_t e;
+    if constexpr (sizeof(C) == 8)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2w<C, NT>, 2 * NT, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2f<C, NT>, NT, 0);
+    return e == hipSuccess ? nb : 0;
 }
 
 template <typename C>
 int pair_occupancy(int threads)
 {
-    int nb = 0;
-    hipError_t e = hipErrorInvalidValue;
     switch (threads) {
-        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2<C, 64>, 64, 0); break;
-        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2<C, 128>, 128, 0); break;
-        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2<C, 256>, 256, 0); break;
-        default: break;
+        case 64: return pair_occupancy_nt<C, 64>();
+        case 128: return pair_occupancy_nt<C, 128>();
+        case 256: return pair_occupancy_nt<C, 256>();
+        default: return 0;
     }
-    return e == hipSuccess ? nb : 0;
 }
 
 // Resident workgroups per CU of the steady-state step (the format of steady_fmt).

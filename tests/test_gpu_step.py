@@ -359,10 +359,11 @@ def test_lattices_at_the_side_limit(nx, ny):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("shape,tile", [((64, 64), None), ((301, 83), (128, 5)), ((600, 333), (256, 0)),
-                                        ((97, 130), (64, 9))])
+                                        ((97, 130), (64, 9)), ((512, 40), (128, 1)), ((1030, 1021), None)])
 def test_two_step_pass_equals_single_steps_bitwise(shape, tile, precision):
     """Two steps per launch (the middle state stays on chip) and one step per launch must
-    give the same state bit for bit."""
+    give the same state bit for bit; single-row tiles and the default plan of a lattice
+    large enough for pairs by default included."""
     nx, ny = shape
     R = min(nx, ny) * 0.2
     disks = [(0, nx * 0.3, ny * 0.5, R), (1, nx * 0.7, ny * 0.5, R)]
@@ -374,6 +375,8 @@ def test_two_step_pass_equals_single_steps_bitwise(shape, tile, precision):
     if tile:
         A.set_tile(*tile)
         B.set_tile(*tile)
+    assert lbm3.lbm3_get_pair_launch(B.h)[0] == 2
+    assert lbm3.lbm3_get_pair_launch(A.h)[0] == 1
     A.step(12)
     B.step(12)
     fa, fb = A.state(), B.state()
