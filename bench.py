@@ -44,18 +44,24 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_tag: str):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary of this kernel, if the
-    summary was taken from the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_pmc.txt")
+def profile_figure(kernel_tag: str, kind: str, key: str):
+    """The first `key: value` figure of the committed rocprofv3 summary
+    profiles/<kernel_tag>_<kind>.txt, if that summary was taken from the current kernel
+    source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_{kind}.txt")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
-    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    t = re.search(re.escape(key) + r":\s*([0-9.eE+]+)", text)
     if not m or not t or m.group(1) != kernel_source_hash():
         return None
     return float(t.group(1))
+
+
+def measured_traffic(kernel_tag: str):
+    """HBM bytes per launch from the committed PMC summary (FETCH_SIZE, WRITE_SIZE)."""
+    return profile_figure(kernel_tag, "pmc", "hbm_bytes_per_launch")
 
 
 def time_steps(torch, lbm3, L, steps: int, reps: int = 3):
@@ -256,6 +262,9 @@ def main():
     n = w.nx * w.ny
     achieved = main_res["gbs"]
     traffic = measured_traffic("lbm3_step_fp64_R4096")
+    # VALU issue fraction of the dominant kernel from the committed instruction counters
+    valu = (profile_figure("lbm3_step_fp64_R4096", "sq_insts", "VALU issue fraction")
+            if main_res["steps_per_launch"] == 2 else None)
     kernel = ("two steps per launch (k_tiles2w: one step per wave group)" if main_res["steps_per_launch"] == 2
               else "one step per launch (k_tiles)")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -264,6 +273,7 @@ def main():
                 "lu_per_launch": n * main_res["steps_per_launch"],
                 "ms_per_launch": round(main_res["ms_per_launch"], 4),
                 "frac_of_device_copy": round(achieved / copy_gbs, 4), "device_copy_gbs": round(copy_gbs, 1),
+                "valu_issue_frac": valu,
                 "one_step_kernel": {"mlups": round(one_step["mlups"], 1), "gbs": round(one_step["gbs"], 1),
                                     "frac": round(one_step["gbs"] / HBM_PEAK_GBS, 4),
                                     "frac_of_device_copy": round(one_step["gbs"] / copy_gbs, 4)}}
