@@ -149,10 +149,15 @@ def bench_batched(torch, lbm3, inputs, steps: int):
         e.record(st)
         torch.cuda.synchronize()
     t = a.elapsed_time(e) / 1e3
+    per_launch, t2, rows2, _ = lbm3.lbm3_batch_get_pair_launch(b)
     lbm3.lbm3_batch_destroy(b)
     res = {"instances": len(ws), "nodes": nodes, "mlups": nodes * steps / t / 1e6,
-           "ms_per_step": t / steps * 1e3, "gbs": 2 * STATE_BYTES["fp32"] * nodes * steps / t / 1e9,
-           "threads": threads, "rows_by_side": {str(k): v for k, v in rows.items()}}
+           "ms_per_step": t / steps * 1e3,
+           "gbs": 2 * STATE_BYTES["fp32"] * nodes * steps / per_launch / t / 1e9,
+           "steps_per_launch": per_launch, "one_step": {"threads": threads,
+                                                        "rows_by_side": {str(k): v for k, v in rows.items()}}}
+    if per_launch == 2:
+        res["two_step"] = {"threads": t2, "rows": rows2}
     side = int(round(nodes ** 0.5))
     weq = inputs.droplet_tiling(side - side % 256 if side >= 512 else side, cell=256)
     res["plain_equal_nodes"] = bench_plain(torch, lbm3, weq, "fp32", steps, 20)["mlups"]
@@ -304,8 +309,8 @@ def main():
                         "per 20 steps",
             "mlups": round(batched["mlups"], 1), "ms_per_step": round(batched["ms_per_step"], 4),
             "gbs": round(batched["gbs"], 1), "frac_of_peak": round(batched["gbs"] / HBM_PEAK_GBS, 4),
-            "nodes": batched["nodes"], "threads": batched["threads"],
-            "rows_by_side": batched["rows_by_side"],
+            "nodes": batched["nodes"], "steps_per_launch": batched["steps_per_launch"],
+            "one_step": batched["one_step"], "two_step": batched.get("two_step"),
             "baseline_plain_fp32_equal_nodes_mlups": round(batched["plain_equal_nodes"], 1),
             "baseline_one_launch_per_instance_mlups": round(batched["per_instance_launches"], 1)}
         line["adjoint_fp64"] = adjoint

@@ -177,12 +177,22 @@ int lbm3_state_buffer(const lbm3_t *h, void **dev_ptr, int32_t *elem_bytes, int6
  *   whole batch (and, with rows > 0, rows for every size class); a side > 0 sets
  *   the rows of the instances with nx == side (threads must equal the batch's).
  *   Results do not depend on the shape.
+ * lbm3_batch_set_steps_per_launch: as lbm3_set_steps_per_launch, for the whole
+ *   batch (0 = two when the instances hold 2^20 nodes or more in all); the
+ *   two-step launch covers every instance once all hold the factored state.
+ *   Results do not depend on the mode (bitwise).  EINVAL for another mode.
+ * lbm3_batch_get_pair_launch: *steps = 2 with the two-step launch's threads per
+ *   workgroup, rows per segment and workgroup count, or *steps = 1 (and zeros)
+ *   when pairs run as two one-step launches.  Any pointer may be NULL.
  * lbm3_batch_destroy: releases everything; NULL is accepted. */
 int lbm3_batch_create(const lbm3_params *p, int32_t count, void *hip_stream, lbm3_batch_t **out);
 int lbm3_batch_init_fields(lbm3_batch_t *b, int32_t idx, const double *rho, const double *u);
 int lbm3_batch_step(lbm3_batch_t *b, int64_t n);
 int lbm3_batch_observables(lbm3_batch_t *b, int32_t idx, lbm3_obs *out, double *rho_out);
 int lbm3_batch_set_tile(lbm3_batch_t *b, int32_t size_class_side, int32_t threads, int32_t rows);
+int lbm3_batch_set_steps_per_launch(lbm3_batch_t *b, int32_t mode);
+int lbm3_batch_get_pair_launch(const lbm3_batch_t *b, int32_t *steps, int32_t *threads, int32_t *rows,
+                               int32_t *workgroups);
 int lbm3_batch_destroy(lbm3_batch_t *b);
 
 /* ---- adjoint (reverse-mode derivative) of the FP64 step ----------------------

@@ -99,12 +99,14 @@ def tune_lattice(nx: int, ny: int, precision: str = "fp64", steps: int = 20,
 
 def tune_batch(batch, sizes, precision: str, steps: int = 20, force: bool = False,
                verbose: bool = False):
-    """Tunes a batch handle in place: threads for the whole launch, then rows per size class.
-    ``sizes`` lists the instances' nx (size classes are its distinct values).  Returns
-    (threads, {side: rows})."""
+    """Tunes a batch handle in place: threads for the whole one-step launch, then rows per
+    size class, then whether two steps per launch (the two-step pass on its own plan) beat
+    one.  ``sizes`` lists the instances' nx (size classes are its distinct values).  Returns
+    (threads, {side: rows}); the chosen steps per launch is set on the handle
+    (lbm3_batch_get_pair_launch reads it back)."""
     import torch
     classes = sorted(set(int(s) for s in sizes))
-    key = f"batch/{_arch(torch)}/{precision}/" + ",".join(f"{s}" for s in sorted(int(s) for s in sizes))
+    key = f"batch2/{_arch(torch)}/{precision}/" + ",".join(f"{s}" for s in sorted(int(s) for s in sizes))
     hit = None if force else _load().get(key)
     if hit:
         t = int(hit["threads"])
@@ -112,7 +114,9 @@ def tune_batch(batch, sizes, precision: str, steps: int = 20, force: bool = Fals
         rows = {int(k): int(v) for k, v in hit["rows"].items()}
         for s, r in rows.items():
             lbm3.lbm3_batch_set_tile(batch, s, t, r)
+        lbm3.lbm3_batch_set_steps_per_launch(batch, int(hit["steps_per_launch"]))
         return t, rows
+    lbm3.lbm3_batch_set_steps_per_launch(batch, 1)
 
     def run(n):
         lbm3.lbm3_batch_step(batch, n)
@@ -140,6 +144,15 @@ def tune_batch(batch, sizes, precision: str, steps: int = 20, force: bool = Fals
             if ms < best_ms:
                 best_ms, rows[s] = ms, r
         lbm3.lbm3_batch_set_tile(batch, s, best_t, rows[s])
+    mode = 1
+    lbm3.lbm3_batch_set_steps_per_launch(batch, 2)
+    if lbm3.lbm3_batch_get_pair_launch(batch)[0] == 2:
+        ms = _time(torch, run, steps)
+        if verbose:
+            print(f"  batch two steps per launch: {ms:.4f} ms/step")
+        if ms < best_ms:
+            best_ms, mode = ms, 2
+    lbm3.lbm3_batch_set_steps_per_launch(batch, mode)
     _store(key, {"threads": best_t, "rows": {str(k): v for k, v in rows.items()},
-                 "ms_per_step": best_ms})
+                 "steps_per_launch": mode, "ms_per_step": best_ms})
     return best_t, rows

@@ -5,7 +5,9 @@
 // Instances hold the factored state after their first step (FP64 and FP32; FP32 storage
 // keeps the 27 populations); a step that finds some instances freshly initialised
 // (27-population format) runs as two launches over the same list, each skipping the
-// instances of the other format.
+// instances of the other format.  Once every instance holds the factored state, pairs of
+// steps can run as one launch of the two-step pass over its own tile list (six-column
+// halo), also inside the graph.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -15,7 +17,7 @@
 #include "lbm3_handle.h"
 
 namespace {
-constexpr int kGraphSteps = 20;  // fused-step launches per captured graph (even: parity kept)
+constexpr int kGraphSteps = 20;  // steps per captured graph (a multiple of 4: parity kept with pairs)
 }
 
 struct lbm3_batch {
@@ -32,6 +34,11 @@ struct lbm3_batch {
     std::map<int, int> rows_by_side;  // rows per segment for instances with nx == side
     tcg::Tile* dtiles = nullptr;      // step list, XCD-ordered
     int ntiles = 0;
+    int pair_mode = 0;                // steps per launch: 0 = by size, 1 = one, 2 = two
+    tcg::Tile* dtiles2 = nullptr;     // two-step list (empty: pairs run as single steps)
+    int ntiles2 = 0;
+    int threads2 = 0;
+    int rows2 = 0;
     tcg::Tile* dobs = nullptr;        // observation list, instance by instance
     std::vector<int> obs_first, obs_count;
     hipGraphExec_t exec[2] = {nullptr, nullptr};  // one graph per starting buffer parity
@@ -93,19 +100,53 @@ static int batch_plan(lbm3_batch* b)
         obs.insert(obs.end(), L.begin(), L.end());
         all.insert(all.end(), L.begin(), L.end());
     }
-    std::vector<Tile> T = xcd_order(all, 8);
+    // the two-step list: its own width (as for a single lattice) and one rows value for all
+    // instances, fitted like the single step's but with the twelve warm-up rows
+    std::vector<Tile> all2;
+    b->rows2 = 0;
+    int64_t nodes = 0;
+    for (int i = 0; i < b->count; ++i) nodes += (int64_t)b->inst[i].kp.nx * b->inst[i].kp.ny;
+    const bool want2 = b->pair_mode == 2 || (b->pair_mode == 0 && nodes >= ((int64_t)1 << 20));
+    const int t2 = std::min(b->prec == Prec::F64 ? 128 : 256, b->threads);
+    const int slots2 = steady_fmt(b->prec) == Fmt::FAC && want2 ? device_slots_pair(b->prec, t2) : 0;
+    if (slots2 > 0) {
+        double best2 = 1e300;
+        for (int r : {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512}) {
+            long tiles = 0;
+            for (int i = 0; i < b->count; ++i) {
+                std::vector<Tile> L;
+                plan_lattice(i, b->inst[i].kp.nx, b->inst[i].kp.ny, t2, r, eb, L, 6);
+                tiles += (long)L.size();
+            }
+            const double cost = (double)((tiles + slots2 - 1) / slots2) * (r + 12);
+            if (cost < best2) {
+                best2 = cost;
+                b->rows2 = r;
+            }
+        }
+        for (int i = 0; i < b->count; ++i)
+            plan_lattice(i, b->inst[i].kp.nx, b->inst[i].kp.ny, t2, b->rows2, eb, all2, 6);
+    }
+    b->threads2 = t2;
+    std::vector<Tile> T = xcd_order(all, 8), T2 = xcd_order(all2, 8);
     (void)hipStreamSynchronize(b->stream);
     drop_graphs(b);
     if (b->dtiles) (void)hipFree(b->dtiles);
+    if (b->dtiles2) (void)hipFree(b->dtiles2);
     if (b->dobs) (void)hipFree(b->dobs);
-    b->dtiles = nullptr;
+    b->dtiles = b->dtiles2 = nullptr;
     b->dobs = nullptr;
+    b->ntiles = b->ntiles2 = 0;
     hipError_t e = hipMalloc((void**)&b->dtiles, T.size() * sizeof(Tile));
     if (e == hipSuccess) e = hipMalloc((void**)&b->dobs, obs.size() * sizeof(Tile));
+    if (e == hipSuccess && !T2.empty()) e = hipMalloc((void**)&b->dtiles2, T2.size() * sizeof(Tile));
     if (e == hipSuccess) e = hipMemcpy(b->dtiles, T.data(), T.size() * sizeof(Tile), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->dobs, obs.data(), obs.size() * sizeof(Tile), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !T2.empty())
+        e = hipMemcpy(b->dtiles2, T2.data(), T2.size() * sizeof(Tile), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "batch tile plan upload");
     b->ntiles = (int)T.size();
+    b->ntiles2 = (int)T2.size();
     return LBM3_OK;
 }
 
@@ -124,7 +165,23 @@ static int ensure_batch_staging(lbm3_batch* b, size_t doubles)
     return LBM3_OK;
 }
 
-// Captures kGraphSteps fused-step launches starting from buffer `parity`.
+// One launch from buffer c of the steady-state step (one step) or of the two-step pass
+// (two steps); either way the result is in buffer c ^ 1.
+static hipError_t launch_steady(lbm3_batch* b, int c, bool two, int64_t step)
+{
+    if (two)
+        return b->prec == Prec::F64
+                   ? tiles_f64_pair(b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles2, b->ntiles2, b->threads2,
+                                    b->stream)
+                   : tiles_f32_pair(b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles2, b->ntiles2, b->threads2,
+                                    b->stream);
+    const Fmt sf = steady_fmt(b->prec);
+    return launch_tiles(b->prec, sf, sf, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles, b->ntiles, b->threads,
+                        step, 0, b->stream);
+}
+
+// Captures launches worth kGraphSteps steps starting from buffer `parity` (an even number
+// of launches either way, so the graph ends on the buffer it started from).
 static int build_graph(lbm3_batch* b, int parity)
 {
     hipGraph_t g = nullptr;
@@ -132,10 +189,9 @@ static int build_graph(lbm3_batch* b, int parity)
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     int c = parity;
     hipError_t le = hipSuccess;
-    for (int s = 0; s < kGraphSteps && le == hipSuccess; ++s) {
-        const Fmt sf = steady_fmt(b->prec);
-        le = launch_tiles(b->prec, sf, sf, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles, b->ntiles,
-                          b->threads, s, 0, b->stream);
+    const bool two = b->ntiles2 > 0;
+    for (int s = 0; s < kGraphSteps && le == hipSuccess; s += two ? 2 : 1) {
+        le = launch_steady(b, c, two, s);
         c ^= 1;
     }
     e = hipStreamEndCapture(b->stream, &g);
@@ -164,6 +220,7 @@ int lbm3_batch_destroy(lbm3_batch_t* b)
         if (b->buf[i]) (void)hipFree(b->buf[i]);
     if (b->dinst) (void)hipFree(b->dinst);
     if (b->dtiles) (void)hipFree(b->dtiles);
+    if (b->dtiles2) (void)hipFree(b->dtiles2);
     if (b->dobs) (void)hipFree(b->dobs);
     if (b->staging) (void)hipFree(b->staging);
     if (b->partials) (void)hipFree(b->partials);
@@ -266,6 +323,35 @@ int lbm3_batch_set_tile(lbm3_batch_t* b, int32_t side, int32_t threads, int32_t 
     return batch_plan(b);
 }
 
+int lbm3_batch_set_steps_per_launch(lbm3_batch_t* b, int32_t mode)
+{
+    if (!b) {
+        set_error("batch is NULL");
+        return LBM3_EINVAL;
+    }
+    if (mode < 0 || mode > 2) {
+        set_error("mode must be 0 (by size), 1 or 2");
+        return LBM3_EINVAL;
+    }
+    b->pair_mode = mode;
+    return batch_plan(b);
+}
+
+int lbm3_batch_get_pair_launch(const lbm3_batch_t* b, int32_t* steps, int32_t* threads, int32_t* rows,
+                               int32_t* workgroups)
+{
+    if (!b) {
+        set_error("batch is NULL");
+        return LBM3_EINVAL;
+    }
+    const bool two = b->ntiles2 > 0;
+    if (steps) *steps = two ? 2 : 1;
+    if (threads) *threads = two ? (b->prec == Prec::F64 ? 2 : 1) * b->threads2 : 0;
+    if (rows) *rows = two ? b->rows2 : 0;
+    if (workgroups) *workgroups = two ? b->ntiles2 : 0;
+    return LBM3_OK;
+}
+
 int lbm3_batch_init_fields(lbm3_batch_t* b, int32_t idx, const double* rho, const double* u)
 {
     if (!b || idx < 0 || idx >= b->count) {
@@ -342,12 +428,13 @@ int lbm3_batch_step(lbm3_batch_t* b, int64_t n)
         n -= kGraphSteps;
         b->step += kGraphSteps;
     }
-    for (; n > 0; --n) {
-        hipError_t e = launch_tiles(b->prec, sf, sf, b->buf[b->cur], b->buf[b->cur ^ 1], b->dinst,
-                                    b->dtiles, b->ntiles, b->threads, b->step, 0, b->stream);
+    while (n > 0) {
+        const bool two = n >= 2 && b->ntiles2 > 0;
+        hipError_t e = launch_steady(b, b->cur, two, b->step);
         if (e != hipSuccess) return hip_fail(e, "batch step launch");
         b->cur ^= 1;
-        b->step += 1;
+        b->step += two ? 2 : 1;
+        n -= two ? 2 : 1;
     }
     return LBM3_OK;
 }

@@ -113,6 +113,21 @@ __device__ __forceinline__ int wrapi(int a, int n)
     return r < 0 ? r + n : r;
 }
 
+// Successive row indices modulo n, the same in every lane: wrapped once at the start, then
+// advanced by one per row on the scalar unit.  (Integer division has no scalar instruction:
+// a % n per row would move every row address of the march into vector registers.)
+struct RowCursor {
+    int r, n;
+    __device__ RowCursor(int a, int n_) : r(__builtin_amdgcn_readfirstlane(wrapi(a, n_))), n(n_) {}
+    // the current row, then advance
+    __device__ int next()
+    {
+        const int c = r;
+        r = r + 1 == n ? 0 : r + 1;
+        return c;
+    }
+};
+
 // Row pointers that are the same in every lane are rebuilt from scalar registers in the
 // global address space, opaque to the optimiser, so that they are not re-associated with
 // the per-lane column offset (which would turn every access into a hoisted 64-bit
@@ -424,11 +439,10 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
 
     // ---- input: F27 pulls all 27 populations of a row directly
     constexpr int NV = IN == Fmt::F27 ? 27 : 18;
-    auto load_f27 = [&](int j, C (&v)[NV]) {
+    auto load_f27 = [&](int r, C (&v)[NV]) {
         const int64_t pitch = kp.pitch;
-        const int r = wrapi(y0 - 2 + j, ny);
-        const int64_t srow[3] = {(int64_t)wrapi(r + 1, ny) * pitch, (int64_t)r * pitch,
-                                 (int64_t)wrapi(r - 1, ny) * pitch};
+        const int64_t srow[3] = {(int64_t)(r + 1 == ny ? 0 : r + 1) * pitch, (int64_t)r * pitch,
+                                 (int64_t)(r == 0 ? ny - 1 : r - 1) * pitch};
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -436,10 +450,10 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
                 v[k * 9 + i] = C(ld_at(fin + ((int64_t)(k * 9 + i) * plane + srow[EY[i] + 1]),
                                        scol[EX[i] + 1]));
     };
-    // ---- input: FAC loads source row s: v[0..8] = f_dag_i(x - e_x,i, s) (pulled along x),
-    // v[9..17] = c_k, V_k of the lane's own column
+    // ---- input: FAC loads source row s (wrapped): v[0..8] = f_dag_i(x - e_x,i, s) (pulled
+    // along x), v[9..17] = c_k, V_k of the lane's own column
     auto load_fac = [&](int s, C (&v)[NV]) {
-        const int64_t rowo = (int64_t)wrapi(s, ny) * kp.fpitch;
+        const int64_t rowo = (int64_t)s * kp.fpitch;
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             v[i] = C(ld_at(fin + ((int64_t)i * plane + rowo), scol[EX[i] + 1]));
@@ -493,19 +507,27 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
 #pragma unroll
     for (int q = 0; q < 3; ++q) d1f[q] = C(0);
 
+    // rows loaded in order: F27 the middle rows y0 - 2, y0 - 1, ...; FAC the source rows
+    // y0 - 3, y0 - 2, ...
+    RowCursor src(IN == Fmt::F27 ? y0 - 2 : y0 - 3, ny);
     if constexpr (IN == Fmt::F27) {
-        if (in1) load_f27(0, vn);
+        const int r = src.next();
+        if (in1) load_f27(r, vn);
     } else {
         // pre-roll: source rows y0 - 3 and y0 - 2 start the partial sums of row y0 - 2, and
         // source row y0 - 1 is published for the first iteration (slots alternate by row)
-        if (in0) load_fac(y0 - 3, vn);
+        {
+            const int r = src.next();
+            if (in0) load_fac(r, vn);
+        }
 #pragma unroll 1
         for (int p = 0; p < 2; ++p) {
             C v[NV], r_[3], f_[9];
 #pragma unroll
             for (int q = 0; q < NV; ++q) v[q] = vn[q];
             publish(v, p);
-            if (in0) load_fac(y0 - 2 + p, vn);
+            const int r = src.next();
+            if (in0) load_fac(r, vn);
             __syncthreads();
             consume_fac(v, p, r_, f_);
         }
@@ -530,12 +552,14 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
             C v[NV];
 #pragma unroll
             for (int q = 0; q < NV; ++q) v[q] = vn[q];
+            const int r = src.next();
             if constexpr (IN == Fmt::F27) {
-                if (in1 && j + 1 < J) load_f27(j + 1, vn);
+                if (in1 && j + 1 < J) load_f27(r, vn);
                 consume_f27(v, r0, f0);
             } else {
-                // source row y0 - 1 + j was published in slot j % 2 before the last barrier
-                if (in0 && j + 1 < J) load_fac(y0 + j, vn);
+                // source row y0 - 1 + j was published in slot j % 2 before the last barrier;
+                // r = row y0 + j
+                if (in0 && j + 1 < J) load_fac(r, vn);
                 consume_fac(v, j & 1, r0, f0);
             }
             const C irho = C(1) / ((r0[0] + r0[1]) + r0[2]);
@@ -715,7 +739,7 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
     const int J = rows + 12;
 
     auto load_fac = [&](int s, C (&v)[18]) {
-        const int64_t rowo = (int64_t)wrapi(s, ny) * kp.fpitch;
+        const int64_t rowo = (int64_t)s * kp.fpitch;
 #pragma unroll
         for (int i = 0; i < 9; ++i) v[i] = ld_at(fin + ((int64_t)i * plane + rowo), scol[EX[i] + 1]);
 #pragma unroll
@@ -743,14 +767,19 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
 
     // pre-roll (as march() with first output row y0 - 3): source rows y0 - 6 and y0 - 5, then
     // row y0 - 4 published for the first iteration; three barriers
-    if (a0) load_fac(y0 - 6, vn);
+    RowCursor src(y0 - 6, ny);  // source rows in load order: y0 - 6, y0 - 5, ...
+    {
+        const int r = src.next();
+        if (a0) load_fac(r, vn);
+    }
 #pragma unroll 1
     for (int p = 0; p < 2; ++p) {
         C v[18], r_[3], f_[9];
 #pragma unroll
         for (int q = 0; q < 18; ++q) v[q] = vn[q];
         publish(v, p);
-        if (a0) load_fac(y0 - 5 + p, vn);
+        const int r = src.next();
+        if (a0) load_fac(r, vn);
         __syncthreads();
         if (a1) pull_row<C, NT>([&](int i) { return v[i]; }, L.xA[p], t, d0r, d0f, d1r, d1f, r_, f_);
     }
@@ -771,7 +800,8 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
             C v[18];
 #pragma unroll
             for (int q = 0; q < 18; ++q) v[q] = vn[q];
-            if (a0 && j + 1 < JA) load_fac(y0 - 3 + j, vn);
+            const int r = src.next();  // row y0 - 3 + j
+            if (a0 && j + 1 < JA) load_fac(r, vn);
             if (a1) pull_row<C, NT>([&](int i) { return v[i]; }, L.xA[j & 1], t, d0r, d0f, d1r, d1f, r0, f0);
             const C irho = C(1) / ((r0[0] + r0[1]) + r0[2]);
 #pragma unroll
@@ -950,7 +980,7 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
     const int JA = rows + 10;
 
     auto load_fac = [&](int s, C (&v)[18]) {
-        const int64_t rowo = (int64_t)wrapi(s, ny) * kp.fpitch;
+        const int64_t rowo = (int64_t)s * kp.fpitch;
 #pragma unroll
         for (int i = 0; i < 9; ++i) v[i] = ld_at(fin + ((int64_t)i * plane + rowo), scol[EX[i] + 1]);
 #pragma unroll
@@ -982,14 +1012,19 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
 
     // A's pre-roll (as march() with first output row y0 - 3): source rows y0 - 6 and y0 - 5,
     // then row y0 - 4 published for the first iteration
-    if (a0) load_fac(y0 - 6, vn);
+    RowCursor src(y0 - 6, ny);  // source rows in load order: y0 - 6, y0 - 5, ...
+    {
+        const int r = src.next();
+        if (a0) load_fac(r, vn);
+    }
 #pragma unroll 1
     for (int p = 0; p < 2; ++p) {
         C v[18], r_[3], f_[9];
 #pragma unroll
         for (int q = 0; q < 18; ++q) v[q] = vn[q];
         publish_a(v, p);
-        if (a0) load_fac(y0 - 5 + p, vn);
+        const int r = src.next();
+        if (a0) load_fac(r, vn);
         __syncthreads();
         if (a1)
             pull_row<C, NT>([&](int i) { return v[i]; }, xA[p], t, d0r_a, d0f_a, d1r_a, d1f_a, r_, f_);
@@ -1012,7 +1047,8 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
             C v[18];
 #pragma unroll
             for (int q = 0; q < 18; ++q) v[q] = vn[q];
-            if (a0 && j + 1 < JA) load_fac(y0 - 3 + j, vn);
+            const int r = src.next();  // row y0 - 3 + j
+            if (a0 && j + 1 < JA) load_fac(r, vn);
             if (a1)
                 pull_row<C, NT>([&](int i) { return v[i]; }, xA[j & 1], t, d0r_a, d0f_a, d1r_a, d1f_a,
                                 r0a, f0a);

@@ -88,6 +88,8 @@ def lib():
             "lbm3_batch_step": (I, [H, ctypes.c_int64]),
             "lbm3_batch_observables": (I, [H, ctypes.c_int32, ctypes.POINTER(lbm3_obs), _DP]),
             "lbm3_batch_set_tile": (I, [H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+            "lbm3_batch_set_steps_per_launch": (I, [H, ctypes.c_int32]),
+            "lbm3_batch_get_pair_launch": (I, [H] + [ctypes.POINTER(ctypes.c_int32)] * 4),
             "lbm3_batch_destroy": (I, [H]),
             "lbm3_adjoint_record": (I, [H, ctypes.c_int64, ctypes.c_int32]),
             "lbm3_adjoint": (I, [H, _DP, _DP, _DP]),
@@ -266,6 +268,17 @@ def lbm3_batch_observables(b, idx: int, nx: int, ny: int, want_rho: bool = False
 
 def lbm3_batch_set_tile(b, side: int, threads: int, rows: int):
     _check(lib().lbm3_batch_set_tile(b, int(side), int(threads), int(rows)), "lbm3_batch_set_tile")
+
+
+def lbm3_batch_set_steps_per_launch(b, mode: int):
+    _check(lib().lbm3_batch_set_steps_per_launch(b, int(mode)), "lbm3_batch_set_steps_per_launch")
+
+
+def lbm3_batch_get_pair_launch(b):
+    """(steps per launch, threads, rows, workgroups) of the batch's launch for pairs of steps."""
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(lib().lbm3_batch_get_pair_launch(b, *[ctypes.byref(x) for x in v]), "lbm3_batch_get_pair_launch")
+    return tuple(x.value for x in v)
 
 
 def lbm3_batch_destroy(b):

@@ -51,6 +51,32 @@ def test_batch_matches_plain_step_bitwise(precision):
     lbm3.lbm3_batch_destroy(b)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("threads", [0, 64, 256])
+def test_batch_two_step_pass_matches_plain_step_bitwise(precision, threads):
+    """With two steps per launch (graph of two-step launches, then eager pairs and an odd last
+    step), every instance equals the plain lattice stepped one step per launch, bitwise."""
+    ws = _mixed_workloads()
+    b = _make_batch(ws, precision)
+    if threads:
+        lbm3.lbm3_batch_set_tile(b, 0, threads, 0)
+    lbm3.lbm3_batch_set_steps_per_launch(b, 2)
+    steps, t2, rows2, wg2 = lbm3.lbm3_batch_get_pair_launch(b)
+    assert steps == 2 and t2 > 0 and rows2 > 0 and wg2 > 0
+    lbm3.lbm3_batch_step(b, 1)   # 27-population -> factored, one step
+    lbm3.lbm3_batch_step(b, 40)  # two graph launches
+    lbm3.lbm3_batch_step(b, 16)  # seven pairs and one single step
+    for i, w in enumerate(ws):
+        obs, rho = _batch_state(b, i, w)
+        L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, w.rho0, w.beta0, precision).init(w.rho)
+        L.set_steps_per_launch(1).step(57)
+        ref = L.densities()
+        L.close()
+        assert obs["step"] == 57
+        assert np.array_equal(rho, ref), (i, w.name)
+    lbm3.lbm3_batch_destroy(b)
+
+
 def test_batch_matches_oracle_fp64():
     ws = _mixed_workloads()
     b = _make_batch(ws, "fp64")
