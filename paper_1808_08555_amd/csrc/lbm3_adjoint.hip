@@ -83,7 +83,7 @@ __device__ __forceinline__ void grad_at(const double* __restrict__ phi, int nx, 
 // colour gradient, modulus, normal and concentration factor of pair p at a node
 struct PairFwd {
     double Gx, Gy, m, nx, ny, C;
-    bool on;  // m > guard
+    bool on;  // m > guard, decided on m^2 as the step decides it
     bool unclipped;
 };
 
@@ -94,8 +94,9 @@ __device__ __forceinline__ PairFwd pair_fwd(const Geo& g, int p, const double (&
     PairFwd r;
     r.Gx = c[l] * gx[k] - c[k] * gx[l];
     r.Gy = c[l] * gy[k] - c[k] * gy[l];
-    r.m = sqrt(r.Gx * r.Gx + r.Gy * r.Gy);
-    r.on = r.m > g.guard;
+    const double g2 = r.Gx * r.Gx + r.Gy * r.Gy;
+    r.m = sqrt(g2);
+    r.on = g2 > g.guard * g.guard;
     r.nx = r.on ? r.Gx / r.m : 0.0;
     r.ny = r.on ? r.Gy / r.m : 0.0;
     const double cf = g.cfac[p] * rk[k] * rk[l];

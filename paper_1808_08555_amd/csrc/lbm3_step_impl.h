@@ -212,9 +212,46 @@ __device__ __forceinline__ C group_sum(C a, C b, C c)
     return (a + b) + c;
 }
 
+// 1/x for a positive normal x (densities, relaxation-time denominators): the hardware
+// reciprocal estimate refined by Newton steps (two in FP64, one in FP32) to within about an
+// ulp, in place of the IEEE division sequence.
+template <typename C>
+__device__ __forceinline__ C recip(C x)
+{
+    if constexpr (sizeof(C) == 8) {
+        double y = __builtin_amdgcn_rcp(x);
+        double e = fma(-x, y, 1.0);
+        y = fma(y, e, y);
+        e = fma(-x, y, 1.0);
+        return fma(y, e, y);
+    } else {
+        const float y = __builtin_amdgcn_rcpf(x);
+        return fmaf(y, fmaf(-x, y, 1.0f), y);
+    }
+}
+
+// 1/sqrt(s) for a positive normal s, the same way (Newton on y = s^(-1/2)).
+template <typename C>
+__device__ __forceinline__ C rsqrt_nr(C s)
+{
+    if constexpr (sizeof(C) == 8) {
+        double y = __builtin_amdgcn_rsq(s);
+        double h = 0.5 * y;
+        double r = fma(-s * y, h, 0.5);
+        y = fma(y, r, y);
+        h = 0.5 * y;
+        r = fma(-s * y, h, 0.5);
+        return fma(y, r, y);
+    } else {
+        const float y = __builtin_amdgcn_rsqf(s);
+        const float h = 0.5f * y;
+        return fmaf(y, fmaf(-s * y, h, 0.5f), y);
+    }
+}
+
 template <typename C>
 struct StepConsts {
-    C sig[3], g[3], beta0, inv_nu[3], cfac[3], guard;
+    C sig[3], g[3], beta0, inv_nu[3], cfac[3], guard2;
     __device__ explicit StepConsts(const KParams& kp)
     {
         for (int p = 0; p < 3; ++p) {
@@ -224,7 +261,7 @@ struct StepConsts {
             cfac[p] = C(kp.cfac[p]);
         }
         beta0 = C(kp.beta0);
-        guard = C(kp.guard);
+        guard2 = C(kp.guard) * C(kp.guard);
     }
 };
 
@@ -238,11 +275,10 @@ __device__ __forceinline__ void collide_recolour(const C (&f)[9], const C (&rk)[
                                                  C (&V)[6], C& ux, C& uy, C& mxh, C& myh)
 {
     const C rho = rk[0] + rk[1] + rk[2];
-    const C irho = C(1) / rho;
-    // rho / nu = sum_k rho_k / nu_k ; tau = 3 nu + 1/2
+    const C irho = recip(rho);
+    // rho / nu = sum_k rho_k / nu_k ; tau = 3 nu + 1/2, so 1/tau = (rho/nu) / (3 rho + (rho/nu)/2)
     const C rho_over_nu = rk[0] * K.inv_nu[0] + rk[1] * K.inv_nu[1] + rk[2] * K.inv_nu[2];
-    const C tau = C(3) * rho / rho_over_nu + C(0.5);
-    const C itau = C(1) / tau;
+    const C itau = rho_over_nu * recip(C(3) * rho + C(0.5) * rho_over_nu);
     // rho u = sum_i f_i e_i + F/2
     const C mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const C my = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
@@ -361,17 +397,18 @@ __device__ __forceinline__ void stress_at_lane(const C (*cring)[3][NT], int s0, 
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         const int k = PK[p], l = PL[p];
-        C Gx, Gy, mag;
+        C Gx, Gy, g2;
         {
             // The two products of G nearly cancel where a fluid is present only as a trace;
             // unfused, their rounding matches the plain IEEE evaluation.
 #pragma clang fp contract(off)
             Gx = cc[l] * gx[k] - cc[k] * gx[l];
             Gy = cc[l] * gy[k] - cc[k] * gy[l];
-            mag = sqrt(Gx * Gx + Gy * Gy);
+            g2 = Gx * Gx + Gy * Gy;
         }
-        if (mag > K.guard) {
-            const C inv = C(1) / mag;
+        // |G| > guard, and 1/|G|
+        if (g2 > K.guard2) {
+            const C inv = rsqrt_nr(g2);
             n[2 * p] = Gx * inv;
             n[2 * p + 1] = Gy * inv;
             C cf = K.cfac[p] * (rk[k] * rk[l]);
@@ -562,7 +599,7 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
                 if (in0 && j + 1 < J) load_fac(r, vn);
                 consume_fac(v, j & 1, r0, f0);
             }
-            const C irho = C(1) / ((r0[0] + r0[1]) + r0[2]);
+            const C irho = recip((r0[0] + r0[1]) + r0[2]);
 #pragma unroll
             for (int k = 0; k < 3; ++k) cring[s0][k][t] = r0[k] * irho;
             if constexpr (TAPE) {
@@ -803,7 +840,7 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
             const int r = src.next();  // row y0 - 3 + j
             if (a0 && j + 1 < JA) load_fac(r, vn);
             if (a1) pull_row<C, NT>([&](int i) { return v[i]; }, L.xA[j & 1], t, d0r, d0f, d1r, d1f, r0, f0);
-            const C irho = C(1) / ((r0[0] + r0[1]) + r0[2]);
+            const C irho = recip((r0[0] + r0[1]) + r0[2]);
 #pragma unroll
             for (int k = 0; k < 3; ++k) L.cA[s0][k][t] = r0[k] * irho;
         }
@@ -926,7 +963,7 @@ __device__ __forceinline__ void pair_step_b(C* __restrict__ fout, const KParams&
                 pull_row<C, NT>([&](int i) { return L.xB[i][t - EX[i]]; }, L.xB + 9, t, d0r, d0f, d1r, d1f,
                                 r1, f1);
             if (m >= 0) {
-                const C irho = C(1) / ((r1[0] + r1[1]) + r1[2]);
+                const C irho = recip((r1[0] + r1[1]) + r1[2]);
 #pragma unroll
                 for (int k = 0; k < 3; ++k) L.cB[(m + 6) % 3][k][t] = r1[k] * irho;
             }
@@ -1052,7 +1089,7 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
             if (a1)
                 pull_row<C, NT>([&](int i) { return v[i]; }, xA[j & 1], t, d0r_a, d0f_a, d1r_a, d1f_a,
                                 r0a, f0a);
-            const C irho = C(1) / ((r0a[0] + r0a[1]) + r0a[2]);
+            const C irho = recip((r0a[0] + r0a[1]) + r0a[2]);
 #pragma unroll
             for (int k = 0; k < 3; ++k) cA[sa0][k][t] = r0a[k] * irho;
         }
@@ -1103,7 +1140,7 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
             pull_row<C, NT>([&](int i) { return xB[i][t - EX[i]]; }, xB + 9, t, d0r_b, d0f_b, d1r_b, d1f_b,
                             r0b, f0b);
         if (jb >= 0) {
-            const C irho = C(1) / ((r0b[0] + r0b[1]) + r0b[2]);
+            const C irho = recip((r0b[0] + r0b[1]) + r0b[2]);
 #pragma unroll
             for (int k = 0; k < 3; ++k) cB[sb0][k][t] = r0b[k] * irho;
         }
