@@ -130,7 +130,8 @@ int lbm3_set_tile(lbm3_t *h, int32_t threads, int32_t rows);
 int lbm3_get_tile(const lbm3_t *h, int32_t *threads, int32_t *rows);
 
 /* How many steps one launch advances in lbm3_step: 0 = chosen by size (two on
- * lattices of 2^20 nodes or more), 1 = one, 2 = two where possible.  A two-step
+ * lattices of 2^18 nodes or more in FP64, 2^20 in FP32), 1 = one, 2 = two where
+ * possible.  A two-step
  * launch keeps the intermediate state on chip and needs the factored state
  * (LBM3_FP64 or LBM3_FP32) and a tile width (lbm3_set_tile's threads) of at most
  * 256; otherwise, and for the odd last step, a one-step launch runs.  Results do not depend on the mode

@@ -199,13 +199,14 @@ int upload_plan(lbm3* h)
     std::vector<Tile> L, L2;
     plan_lattice(0, h->kp.nx, h->kp.ny, h->threads, rows, eb, L);
     // The two-step pass halves the traffic per step but needs a 12-row warm-up per tile:
-    // it wins on large lattices (measured: FP64 +37%, FP32 +22% at 4096^2, FP64 +15% and
-    // FP32 even at 1024^2, no gain at 512^2).  Its own default width: 128 columns for FP64
-    // (256 lanes, one step per wave group), 256 for FP32; lbm3_set_tile's width applies to
-    // both passes.
-    const bool big = (int64_t)h->kp.nx * h->kp.ny >= ((int64_t)1 << 20);
+    // it wins on large lattices (measured, two vs one step per launch: FP64 +52% at 4096^2,
+    // +31% at 1024^2, +12% at 512^2; FP32 +36% at 4096^2, +4% at 1024^2, -17% at 512^2).
+    // Its own default width: 256 columns (FP64: 512 lanes, one step per wave group);
+    // lbm3_set_tile's width applies to both passes.
+    const int64_t min2 = (int64_t)1 << (h->prec == Prec::F64 ? 18 : 20);
+    const bool big = (int64_t)h->kp.nx * h->kp.ny >= min2;
     const bool want2 = h->pass_mode == 2 || (h->pass_mode == 0 && big);
-    int t2 = h->tile_set ? h->threads : std::min(h->prec == Prec::F64 ? 128 : 256, h->threads);
+    int t2 = h->tile_set ? h->threads : std::min(256, h->threads);
     const int slots2 = steady_fmt(h->prec) == Fmt::FAC && want2 ? device_slots_pair(h->prec, t2) : 0;
     if (slots2 > 0) {
         int rows2 = h->rows_request;

@@ -107,7 +107,7 @@ static int batch_plan(lbm3_batch* b)
     int64_t nodes = 0;
     for (int i = 0; i < b->count; ++i) nodes += (int64_t)b->inst[i].kp.nx * b->inst[i].kp.ny;
     const bool want2 = b->pair_mode == 2 || (b->pair_mode == 0 && nodes >= ((int64_t)1 << 20));
-    const int t2 = std::min(b->prec == Prec::F64 ? 128 : 256, b->threads);
+    const int t2 = std::min(256, b->threads);
     const int slots2 = steady_fmt(b->prec) == Fmt::FAC && want2 ? device_slots_pair(b->prec, t2) : 0;
     if (slots2 > 0) {
         double best2 = 1e300;

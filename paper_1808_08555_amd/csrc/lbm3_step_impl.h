@@ -740,12 +740,13 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
 // and recolours lanes 3..cols+8 (B's source columns); B forms densities on lanes 4..cols+7
 // and outputs lanes 6..cols+5, so cols <= NT - 12.  Every iteration has three phases, each
 // closed by a barrier that both steps' waves reach (the same number of times: three per
-// pre-roll and three per iteration of a loop of the same length):
-//   phase 0: A densities (stage 1)      B force, recolouring, store (stage 3)
-//   phase 1: A stress (stage 2)         B densities from xB (stage 1)
-//   phase 2: A recolouring into xB      B stress (stage 2)
+// pre-roll and three per iteration of a loop of the same length).  Both steps run the same
+// stage in the same phase, so the heavy stages meet at the same barrier:
+//   phase 0: densities (stage 1; B pulls the row A recoloured in the previous iteration)
+//   phase 1: stress (stage 2)
+//   phase 2: force, collision and recolouring (stage 3; A into xB, B to HBM)
 // Iteration j: A consumes source row y0 - 4 + j and recolours row y0 - 7 + j into xB; B
-// pulls that row in iteration j + 1 and outputs row y0 - 12 + j.
+// pulls that row in iteration j + 1 and outputs row y0 - 11 + j.
 template <typename C, int NT>
 struct alignas(16) PairLds {
     C cA[3][3][NT];  // A: concentration ring (by row mod 3)
@@ -773,7 +774,7 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
     const bool a3 = (t >= 3) && (t <= cols + 8);
     const StepConsts<C> K(kp);
     const int JA = rows + 10;
-    const int J = rows + 12;
+    const int J = rows + 11;  // one more iteration for B's last row
 
     auto load_fac = [&](int s, C (&v)[18]) {
         const int64_t rowo = (int64_t)s * kp.fpitch;
@@ -884,11 +885,10 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
     }
 }
 
-// B's rows are numbered by m: its stage 1 pulls source row y0 - 1 + m and completes the
-// densities of row y0 - 2 + m (partial sums only for m = -2, -1), its stage 2 forms the
-// stress of row y0 - 3 + m and its stage 3 outputs row y0 - 4 + m.  Stage 1 and 2 of row m run in iteration m + 7 (phases 1, 2), stage 3 in
-// iteration m + 8 (phase 0), so the densities, totals and normals of row m wait across one
-// loop edge (f1, r1, n1) before they move into the pipeline.
+// B's rows are numbered by m: its stage 1 pulls source row y0 - 1 + m (from xB) and
+// completes the densities of row y0 - 2 + m (partial sums only for m = -2, -1), its stage 2
+// forms the stress of row y0 - 3 + m and its stage 3 outputs row y0 - 4 + m.  Row m runs in
+// iteration m + 7, one iteration after A recoloured its source row into xB.
 template <typename C, int NT>
 __device__ __forceinline__ void pair_step_b(C* __restrict__ fout, const KParams& kp, int x0, int y0,
                                             int rows, int cols, PairLds<C, NT>& L, int t)
@@ -902,18 +902,18 @@ __device__ __forceinline__ void pair_step_b(C* __restrict__ fout, const KParams&
     const bool b3 = (t >= 6) && (t <= cols + 5);
     const StepConsts<C> K(kp);
     const int MB = rows + 3;  // last row index m
-    const int J = rows + 12;
+    const int J = rows + 11;
 
-    C fA[9], fB[9], rA[3], rB[3], nB[6], d0r[3], d0f[6], d1r[3], d1f[3], f1[9], r1[3], n1[6];
+    C fA[9], fB[9], rA[3], rB[3], nB[6], d0r[3], d0f[6], d1r[3], d1f[3];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fA[i] = fB[i] = f1[i] = C(0);
+    for (int i = 0; i < 9; ++i) fA[i] = fB[i] = C(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        rA[k] = rB[k] = r1[k] = C(1);
+        rA[k] = rB[k] = C(1);
         d0r[k] = d1r[k] = d1f[k] = C(0);
     }
 #pragma unroll
-    for (int q = 0; q < 6; ++q) nB[q] = d0f[q] = n1[q] = C(0);
+    for (int q = 0; q < 6; ++q) nB[q] = d0f[q] = C(0);
 
     // A's three pre-roll barriers
 #pragma unroll 1
@@ -921,12 +921,41 @@ __device__ __forceinline__ void pair_step_b(C* __restrict__ fout, const KParams&
 
 #pragma unroll 1
     for (int j = 0; j < J; ++j) {
-        // phase 0: stage 3 of row m3 = j - 8, then row m3 enters the pipeline
-        const int m3 = j - 8;
-        if (m3 >= 4 && m3 <= MB && b3) {
-            const int yo = y0 - 4 + m3;
+        const int m = j - 7;
+        const bool live = m >= -2 && m <= MB;
+        const int s0 = (m + 6) % 3, s1 = (m + 8) % 3, s2 = (m + 7) % 3;
+        // phase 0: stage 1 of row m from A's row in xB
+        C f0[9], r0[3];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f0[i] = C(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r0[k] = C(1);
+        if (live) {
+            if (b1)
+                pull_row<C, NT>([&](int i) { return L.xB[i][t - EX[i]]; }, L.xB + 9, t, d0r, d0f, d1r, d1f,
+                                r0, f0);
+            if (m >= 0) {
+                const C irho = recip((r0[0] + r0[1]) + r0[2]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) L.cB[s0][k][t] = r0[k] * irho;
+            }
+        }
+        __syncthreads();
+        // phase 1: stage 2
+        C nA[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
+        if (live && m >= 2 && b2) {
+            C Txx, Txy, Tyy;
+            stress_at_lane<C, NT>(L.cB, s0, s1, s2, t, rA, K, nA, Txx, Txy, Tyy);
+            L.tB[s1][0][t] = Txx;
+            L.tB[s1][1][t] = Txy;
+            L.tB[s1][2][t] = Tyy;
+        }
+        __syncthreads();
+        // phase 2: stage 3, then row m enters the pipeline
+        if (live && m >= 4 && b3) {
+            const int yo = y0 - 4 + m;
             C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
-            force_at_lane<C, NT>(L.tB, (m3 + 6) % 3, (m3 + 8) % 3, (m3 + 7) % 3, t, Fx, Fy);
+            force_at_lane<C, NT>(L.tB, s0, s1, s2, t, Fx, Fy);
             collide_recolour<C>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
             const int64_t orow = (int64_t)yo * kp.fpitch;
 #pragma unroll
@@ -936,50 +965,19 @@ __device__ __forceinline__ void pair_step_b(C* __restrict__ fout, const KParams&
 #pragma unroll
             for (int q = 0; q < 6; ++q) st_at(fout + ((int64_t)(12 + q) * plane + orow), xoff, V[q]);
         }
-        if (m3 >= 0 && m3 <= MB) {
+        if (live && m >= 0) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 fB[i] = fA[i];
-                fA[i] = f1[i];
+                fA[i] = f0[i];
             }
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 rB[k] = rA[k];
-                rA[k] = r1[k];
+                rA[k] = r0[k];
             }
 #pragma unroll
-            for (int q = 0; q < 6; ++q) nB[q] = n1[q];
-        }
-        __syncthreads();
-        // phase 1: stage 1 of row m = j - 7 from A's row in xB
-        const int m = j - 7;
-        const bool live = m >= -2 && m <= MB;
-        if (live) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) f1[i] = C(0);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) r1[k] = C(1);
-            if (b1)
-                pull_row<C, NT>([&](int i) { return L.xB[i][t - EX[i]]; }, L.xB + 9, t, d0r, d0f, d1r, d1f,
-                                r1, f1);
-            if (m >= 0) {
-                const C irho = recip((r1[0] + r1[1]) + r1[2]);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) L.cB[(m + 6) % 3][k][t] = r1[k] * irho;
-            }
-        }
-        __syncthreads();
-        // phase 2: stage 2 of row m
-        if (live) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) n1[q] = C(0);
-            if (m >= 2 && b2) {
-                C Txx, Txy, Tyy;
-                stress_at_lane<C, NT>(L.cB, (m + 6) % 3, (m + 8) % 3, (m + 7) % 3, t, rA, K, n1, Txx, Txy, Tyy);
-                L.tB[(m + 8) % 3][0][t] = Txx;
-                L.tB[(m + 8) % 3][1][t] = Txy;
-                L.tB[(m + 8) % 3][2][t] = Tyy;
-            }
+            for (int q = 0; q < 6; ++q) nB[q] = nA[q];
         }
         __syncthreads();
     }
