@@ -82,7 +82,7 @@ __device__ __forceinline__ void grad_at(const double* __restrict__ phi, int nx, 
 
 // colour gradient, modulus, normal and concentration factor of pair p at a node
 struct PairFwd {
-    double Gx, Gy, m, nx, ny, C;
+    double Gx, Gy, m, im, nx, ny, C;  // im = 1/m where on, else 0
     bool on;  // m > guard, decided on m^2 as the step decides it
     bool unclipped;
 };
@@ -97,8 +97,9 @@ __device__ __forceinline__ PairFwd pair_fwd(const Geo& g, int p, const double (&
     const double g2 = r.Gx * r.Gx + r.Gy * r.Gy;
     r.m = sqrt(g2);
     r.on = g2 > g.guard * g.guard;
-    r.nx = r.on ? r.Gx / r.m : 0.0;
-    r.ny = r.on ? r.Gy / r.m : 0.0;
+    r.im = r.on ? 1.0 / r.m : 0.0;
+    r.nx = r.Gx * r.im;
+    r.ny = r.Gy * r.im;
     const double cf = g.cfac[p] * rk[k] * rk[l];
     r.unclipped = cf < 1.0;
     r.C = r.unclipped ? cf : 1.0;
@@ -109,9 +110,9 @@ __device__ __forceinline__ void node_fields(const AdjWS& w, int64_t N, int64_t j
                                             double (&gx)[3], double (&gy)[3])
 {
     for (int k = 0; k < 3; ++k) rk[k] = w.rho[k * N + j];
-    const double r = rk[0] + rk[1] + rk[2];
+    const double ir = 1.0 / (rk[0] + rk[1] + rk[2]);
     for (int k = 0; k < 3; ++k) {
-        c[k] = rk[k] / r;
+        c[k] = rk[k] * ir;
         gx[k] = w.gc[(2 * k) * N + j];
         gy[k] = w.gc[(2 * k + 1) * N + j];
     }
@@ -130,6 +131,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ la
         double rk[3], c[3], gx[3], gy[3];
         node_fields(w, N, j, rk, c, gx, gy);
         const double rho = rk[0] + rk[1] + rk[2];
+        const double irho = 1.0 / rho, irho3 = irho * irho * irho;
         double f[9];
         for (int i = 0; i < 9; ++i) f[i] = w.ftot[i * N + j];
         PairFwd pf[3];
@@ -138,14 +140,15 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ la
         const double Fx = w.F[j], Fy = w.F[N + j];
         // ---- forward collision
         const double S = rk[0] * g.inv_nu[0] + rk[1] * g.inv_nu[1] + rk[2] * g.inv_nu[2];
-        const double tau = 3.0 * rho / S + 0.5;
+        const double iS = 1.0 / S;
+        const double tau = 3.0 * rho * iS + 0.5;
         const double itau = 1.0 / tau;
         double mx = 0.0, my = 0.0;
         for (int i = 0; i < 9; ++i) {
             mx += f[i] * EX[i];
             my += f[i] * EY[i];
         }
-        const double ux = (mx + 0.5 * Fx) / rho, uy = (my + 0.5 * Fy) / rho;
+        const double ux = (mx + 0.5 * Fx) * irho, uy = (my + 0.5 * Fy) * irho;
         const double uu = ux * ux + uy * uy, uF = ux * Fx + uy * Fy, pref = 1.0 - 0.5 * itau;
         double eu[9], eF[9], feq[9], phi[9], fd[9];
         for (int i = 0; i < 9; ++i) {
@@ -156,14 +159,14 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ la
             fd[i] = f[i] - (f[i] - feq[i]) * itau + phi[i];
         }
         // ---- forward recolouring quantities
-        const double q35 = 35.0 * rk[0] * rk[1] * rk[2] / (rho * rho * rho);
+        const double q35 = 35.0 * rk[0] * rk[1] * rk[2] * irho3;
         const bool ct_free = q35 < 1.0;
         const double ct = ct_free ? q35 : 1.0;
         double beta[3], aa[3], prod[3];
         for (int p = 0; p < 3; ++p) {
             beta[p] = g.beta0 * (1.0 + ct * g.g[p]);
             prod[p] = rk[PK[p]] * rk[PL[p]];
-            aa[p] = beta[p] * prod[p] / rho;
+            aa[p] = beta[p] * prod[p] * irho;
         }
         // ---- reverse of the recolouring
         // dL/dB'_{i,k}(x) = dL/df'_{i,k}(x + e_i) = fbar'_i(x + e_i) + rhobar'_k(x + e_i)
@@ -191,23 +194,23 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ la
             if (pf[p].on) {
                 const double nbx = aa[p] * dVx, nby = aa[p] * dVy;
                 const double nn = pf[p].nx * nbx + pf[p].ny * nby;
-                Gbr[p][0] = (nbx - pf[p].nx * nn) / pf[p].m;
-                Gbr[p][1] = (nby - pf[p].ny * nn) / pf[p].m;
+                Gbr[p][0] = (nbx - pf[p].nx * nn) * pf[p].im;
+                Gbr[p][1] = (nby - pf[p].ny * nn) * pf[p].im;
             }
             // a_p = beta_p rho_k rho_l / rho
-            const double betab = ab * prod[p] / rho;
-            rb[k] += ab * beta[p] * rk[l] / rho;
-            rb[l] += ab * beta[p] * rk[k] / rho;
-            rhob -= ab * aa[p] / rho;
+            const double betab = ab * prod[p] * irho;
+            rb[k] += ab * beta[p] * rk[l] * irho;
+            rb[l] += ab * beta[p] * rk[k] * irho;
+            rhob -= ab * aa[p] * irho;
             // beta_p = beta0 (1 + ct g_p)
             ctb += betab * g.beta0 * g.g[p];
             sig_beta[p] = betab * g.beta0 * ct;  // times g'(X_p) dX_p/dsigma on the host
         }
         if (ct_free) {
-            rb[0] += ctb * 35.0 * rk[1] * rk[2] / (rho * rho * rho);
-            rb[1] += ctb * 35.0 * rk[0] * rk[2] / (rho * rho * rho);
-            rb[2] += ctb * 35.0 * rk[0] * rk[1] / (rho * rho * rho);
-            rhob -= ctb * 3.0 * q35 / rho;
+            rb[0] += ctb * 35.0 * rk[1] * rk[2] * irho3;
+            rb[1] += ctb * 35.0 * rk[0] * rk[2] * irho3;
+            rb[2] += ctb * 35.0 * rk[0] * rk[1] * irho3;
+            rhob -= ctb * 3.0 * q35 * irho;
         }
         // ---- reverse of the collision
         double fb[9], ub[2] = {0, 0}, Fb[2] = {0, 0}, itaub = 0.0, prefb = 0.0, uub = 0.0, uFb = 0.0;
@@ -236,20 +239,20 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ la
         Fb[1] += uFb * uy;
         itaub -= 0.5 * prefb;
         // u = (m + F/2)/rho
-        const double mbx = ub[0] / rho, mby = ub[1] / rho;
+        const double mbx = ub[0] * irho, mby = ub[1] * irho;
         Fb[0] += 0.5 * mbx;
         Fb[1] += 0.5 * mby;
-        rhob -= (ub[0] * ux + ub[1] * uy) / rho;
+        rhob -= (ub[0] * ux + ub[1] * uy) * irho;
         for (int i = 0; i < 9; ++i) fb[i] += mbx * EX[i] + mby * EY[i];
         // itau = 1/tau, tau = 3 rho / S + 1/2, S = sum_k rho_k inv_nu_k
         const double taub = -itaub * itau * itau;
-        rhob += taub * 3.0 / S;
-        const double Sb = -taub * 3.0 * rho / (S * S);
+        rhob += taub * 3.0 * iS;
+        const double Sb = -taub * 3.0 * rho * iS * iS;
         for (int k = 0; k < 3; ++k) rb[k] += Sb * g.inv_nu[k];
         // c_k = rho_k / rho (the node-local uses of c)
         double cr = 0.0;
         for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
-        for (int k = 0; k < 3; ++k) rb[k] += cb[k] / rho - cr / (rho * rho);
+        for (int k = 0; k < 3; ++k) rb[k] += cb[k] * irho - cr * (irho * irho);
         for (int k = 0; k < 3; ++k) rb[k] += rhob;  // rho = sum_k rho_k
         for (int i = 0; i < 9; ++i) lamn[i * N + j] = fb[i];
         for (int k = 0; k < 3; ++k) w.rbar[k * N + j] = rb[k];
@@ -297,15 +300,15 @@ __global__ __launch_bounds__(256) void k_adj_stress(Geo g, AdjWS w)
             if (!f.on) continue;
             double Gbx = w.Gbar[(2 * p) * N + j], Gby = w.Gbar[(2 * p + 1) * N + j];
             const double Q = Tbxx * f.Gy * f.Gy - Tbxy * f.Gx * f.Gy + Tbyy * f.Gx * f.Gx;
-            const double h = g.sigma[p] * f.C / f.m;
+            const double h = g.sigma[p] * f.C * f.im;
             Gbx += h * (2.0 * Tbyy * f.Gx - Tbxy * f.Gy);
             Gby += h * (2.0 * Tbxx * f.Gy - Tbxy * f.Gx);
-            const double mb = -Q * g.sigma[p] * f.C / (f.m * f.m);
-            Gbx += mb * f.Gx / f.m;
-            Gby += mb * f.Gy / f.m;
-            sig_st[p] = Q * f.C / f.m;
+            const double mb = -Q * g.sigma[p] * f.C * (f.im * f.im);
+            Gbx += mb * f.Gx * f.im;
+            Gby += mb * f.Gy * f.im;
+            sig_st[p] = Q * f.C * f.im;
             if (f.unclipped) {
-                const double Cb = Q * g.sigma[p] / f.m;
+                const double Cb = Q * g.sigma[p] * f.im;
                 rb[k] += Cb * g.cfac[p] * rk[l];
                 rb[l] += Cb * g.cfac[p] * rk[k];
             }
@@ -319,7 +322,8 @@ __global__ __launch_bounds__(256) void k_adj_stress(Geo g, AdjWS w)
         }
         double cr = 0.0;
         for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
-        for (int k = 0; k < 3; ++k) w.rbar[k * N + j] += rb[k] + cb[k] / rho - cr / (rho * rho);
+        const double irho = 1.0 / rho;
+        for (int k = 0; k < 3; ++k) w.rbar[k * N + j] += rb[k] + cb[k] * irho - cr * (irho * irho);
         for (int k = 0; k < 3; ++k) {
             w.gcbar[(2 * k) * N + j] = gcb[k][0];
             w.gcbar[(2 * k + 1) * N + j] = gcb[k][1];
@@ -357,7 +361,8 @@ __global__ __launch_bounds__(256) void k_adj_final(Geo g, AdjWS w, double* __res
     }
     double cr = 0.0;
     for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
-    for (int k = 0; k < 3; ++k) lam[(9 + k) * N + j] = w.rbar[k * N + j] + cb[k] / rho - cr / (rho * rho);
+    const double irho = 1.0 / rho;
+    for (int k = 0; k < 3; ++k) lam[(9 + k) * N + j] = w.rbar[k * N + j] + cb[k] * irho - cr * (irho * irho);
 }
 
 // The adjoint state is kept factored per node as (dL/df_i, dL/drho_k), 12 values: f_{i,k}

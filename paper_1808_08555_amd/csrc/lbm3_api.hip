@@ -146,13 +146,14 @@ Prec prec_of(int precision)
     return precision == LBM3_FP64 ? Prec::F64 : (precision == LBM3_FP32_STORAGE ? Prec::F32S : Prec::F32);
 }
 
-// Default launch shape, from sweeps on 256^2 to 4096^2 in every precision: 256 threads (two
-// workgroups per CU) once the lattice is wide enough, rows fitted to the resident slots
-// (auto_rows).
+// Default launch shape of the single step, from sweeps on 256^2 to 4096^2 in every
+// precision: 64 threads below 384 columns, 128 below 768, then 256 (two workgroups per CU);
+// rows fitted to the resident slots (auto_rows).  Narrow strips win on small lattices,
+// where more workgroups with short warm-ups beat wide ones (256^2: +2-4%, 512^2: +2-4%).
 void default_tile(const KParams& kp, Prec prec, int* threads, int* rows)
 {
     (void)prec;
-    *threads = kp.nx >= 250 ? 256 : (kp.nx >= 124 ? 128 : 64);
+    *threads = kp.nx < 384 ? 64 : (kp.nx < 768 ? 128 : 256);
     *rows = 0;
 }
 
@@ -201,12 +202,13 @@ int upload_plan(lbm3* h)
     // The two-step pass halves the traffic per step but needs a 12-row warm-up per tile:
     // it wins on large lattices (measured, two vs one step per launch: FP64 +52% at 4096^2,
     // +31% at 1024^2, +12% at 512^2; FP32 +36% at 4096^2, +4% at 1024^2, -17% at 512^2).
-    // Its own default width: 256 columns (FP64: 512 lanes, one step per wave group);
-    // lbm3_set_tile's width applies to both passes.
+    // Its own default width: 64 columns below 768 (512^2 FP64: +6% over 256), else 256
+    // (FP64: 512 lanes, one step per wave group); lbm3_set_tile's width applies to both
+    // passes.
     const int64_t min2 = (int64_t)1 << (h->prec == Prec::F64 ? 18 : 20);
     const bool big = (int64_t)h->kp.nx * h->kp.ny >= min2;
     const bool want2 = h->pass_mode == 2 || (h->pass_mode == 0 && big);
-    int t2 = h->tile_set ? h->threads : std::min(256, h->threads);
+    int t2 = h->tile_set ? h->threads : (h->kp.nx < 768 ? 64 : 256);
     const int slots2 = steady_fmt(h->prec) == Fmt::FAC && want2 ? device_slots_pair(h->prec, t2) : 0;
     if (slots2 > 0) {
         int rows2 = h->rows_request;

@@ -198,6 +198,25 @@ def test_compound_droplet_laplace_fp64_vs_fp32_storage(s12, s23, tau):
         assert res["fp64"]["drift_40000"] <= 1e-12
 
 
+def test_full_size_two_step_launches_equal_single_steps_bitwise():
+    """4096^2 droplet tiling in the benchmark's launch configuration (two steps per launch,
+    default plan) against one step per launch: bitwise equal after 1 + 2 x 2 steps.  With
+    the sampled oracle comparison of the single step below, this ties the benchmark's
+    kernel to the oracle at full size."""
+    w = inputs.droplet_tiling(4096)
+    A = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau).init(w.rho).set_steps_per_launch(1)
+    B = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau).init(w.rho)
+    assert lbm3.lbm3_get_pair_launch(B.h)[0] == 2
+    A.step(5)
+    B.step(5)
+    fa = A.state()
+    A.close()
+    fb = B.state()
+    B.close()
+    assert np.isfinite(fa).all()
+    assert np.array_equal(fa, fb)
+
+
 def test_full_size_sampled_parity_in_bench_configuration():
     """4096^2 droplet tiling in the launch configuration the benchmark times: after 20
     steps, one more step is compared with the oracle at sampled nodes (strip and segment
