@@ -48,9 +48,12 @@ namespace {
 constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
-// D2Q9 weights.  In FP64 the rest weight is taken as 1 - 4 w_1 - 4 w_5, the double one
-// ulp above the nearest to 4/9, so that the nine weights sum to exactly 1: with the nearest
-// doubles the sum is 1 - 5.55e-17 and every collision would scale the mass by that much.
+// D2Q9 weights, chosen so that the nine sum to exactly 1: otherwise every collision scales
+// the mass by the sum (the equilibrium's zeroth moment is rho times it).  In FP64 the rest
+// weight is 1 - 4 w_1 - 4 w_5, the double one ulp above the nearest to 4/9 (the nearest
+// doubles sum to 1 - 5.55e-17).  In FP32 the nearest floats sum to 1 + 7.45e-9, which
+// drifted the mass by 1.5e-5 over 2000 steps at tau = 1; there w_5 is the float one ulp
+// below the nearest to 1/36 (0x1.c71c70p-6), and 4/9 and 1/9 are the nearest floats.
 template <typename C>
 __device__ __forceinline__ constexpr C wgt(int i)
 {
@@ -58,7 +61,7 @@ __device__ __forceinline__ constexpr C wgt(int i)
         return i == 0 ? 1.0 - 4.0 * (1.0 / 9.0) - 4.0 * (1.0 / 36.0)
                       : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
     else
-        return i == 0 ? C(4.0 / 9.0) : (i < 5 ? C(1.0 / 9.0) : C(1.0 / 36.0));
+        return i == 0 ? C(4.0 / 9.0) : (i < 5 ? C(1.0 / 9.0) : C(0x1.c71c70p-6));
 }
 
 // 32-bit integer mixer ("lowbias32", from Wellons' hash-prospector search): a bijection with
