@@ -281,6 +281,19 @@ def pie(n: int = 8) -> np.ndarray:
     return rho_from_labels(lab)
 
 
+def stratified_lens(n: int = 160, R: float = 20.0, sigma_rg: float = 0.01, sigma_rb: float = 0.01,
+                    sigma_gb: float = 0.01, tau: float = 0.8, steps: int = 0) -> Workload:
+    """A disk of fluid 0 (radius R) at the centre of an n x n periodic lattice whose lower
+    half (y < n/2) is fluid 1 and upper half fluid 2: the droplet between two stratified
+    fluids that spreads into a lens."""
+    c = (n - 1) / 2.0
+    lab = label_disks(n, n, [(0, c, c, R)], background=2)
+    _, y = _grid(n, n)
+    lab[(lab == 2) & (y < n / 2)] = 1
+    return Workload(f"stratified_lens_{n}", n, n, (sigma_rg, sigma_rb, sigma_gb), (tau, tau, tau),
+                    rho=rho_from_labels(lab), steps=steps)
+
+
 def flat_layers(nx: int, ny: int, y_interfaces=(0.25, 0.75), fluids=(2, 0)) -> np.ndarray:
     """Two flat layers uniform in x: fluid fluids[1] for y in [y0*ny, y1*ny), fluids[0] elsewhere."""
     x, y = _grid(nx, ny)

@@ -34,3 +34,50 @@ def compound_laplace(rho: np.ndarray, xc: float, yc: float, sigma_rg: float, sig
     eps = abs(dp_gb * Rg + dp_rg * Rr - (sigma_gb + sigma_rg)) / (sigma_gb + sigma_rg)
     return {"Rr": Rr, "Rg": Rg, "dp_rg": dp_rg, "dp_gb": dp_gb, "dp_total": p_in - p_out,
             "eps": eps}
+
+
+def lens_analytic(theta1: float, theta2: float, area: float):
+    """Lens length and cap heights of Eq. (23) for contact angles theta1, theta2 (radians)
+    and lens area `area`: D = 2 sqrt(A / sum_i (theta_i / sin theta_i - cos theta_i) /
+    sin theta_i), h_i = (D/2) (1 - cos theta_i) / sin theta_i."""
+    s = sum((t / math.sin(t) - math.cos(t)) / math.sin(t) for t in (theta1, theta2))
+    D = 2.0 * math.sqrt(area / s)
+    return D, 0.5 * D * (1 - math.cos(theta1)) / math.sin(theta1), 0.5 * D * (1 - math.cos(theta2)) / math.sin(theta2)
+
+
+def _crossing(v: np.ndarray, level: float, i0: int, step: int) -> float:
+    """Fractional index where the 1-d profile v first crosses `level` walking from i0 in
+    direction step (+1 or -1), by linear interpolation between the two bracketing nodes."""
+    i = i0
+    while 0 <= i + step < len(v):
+        a, b = v[i] - level, v[i + step] - level
+        if a == 0:
+            return float(i)
+        if a * b < 0:
+            return i + step * a / (a - b)
+        i += step
+    raise ValueError("no crossing")
+
+
+def lens_geometry(rho: np.ndarray, y_guess: float, x_far: int = 0):
+    """Length D and cap heights of a lens of fluid 0 on the flat interface between fluid 1
+    (below) and fluid 2 (above), measured on the concentration fields: the flat interface
+    height y_i where c_1 = c_2 in column x_far (away from the lens); D between the two
+    points where c_0 = 1/2 along the line y = y_i; the heights where c_0 = 1/2 above and
+    below y_i along the lens's middle column.  Returns (D, h_up, h_down, y_i)."""
+    c = rho / rho.sum(0)
+    ny, nx = c.shape[1:]
+    y_i = _crossing(c[1, :, x_far] - c[2, :, x_far], 0.0, int(y_guess) - 10, +1)
+    j = int(math.floor(y_i))
+    t = y_i - j
+    row = (1 - t) * c[0, j] + t * c[0, j + 1]
+    xm = int(np.argmax(row))
+    xl = _crossing(row, 0.5, xm, -1)
+    xr = _crossing(row, 0.5, xm, +1)
+    xc = 0.5 * (xl + xr)
+    i = int(math.floor(xc))
+    s = xc - i
+    col = (1 - s) * c[0, :, i] + s * c[0, :, i + 1]
+    y_top = _crossing(col, 0.5, j + 1, +1) if col[j + 1] > 0.5 else y_i
+    y_bot = _crossing(col, 0.5, j, -1) if col[j] > 0.5 else y_i
+    return xr - xl, y_top - y_i, y_i - y_bot, y_i

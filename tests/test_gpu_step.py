@@ -1,13 +1,15 @@
 """Parity of the HIP step (through the C ABI) with the FP64 oracle, element by element,
 plus invariants and error paths of the library on the GPU."""
 import functools
+import json
 import math
+import os
 
 import numpy as np
 import pytest
 
 import oracle
-from analysis import compound_laplace
+from analysis import compound_laplace, lens_analytic, lens_geometry
 from paper_1808_08555_amd import inputs, lbm3
 
 pytestmark = pytest.mark.gpu
@@ -233,6 +235,37 @@ def test_compound_droplet_laplace_fp64_vs_fp32_storage(s12, s23, tau):
         assert res["fp64"]["eps_40000"] < 0.013
         assert res["fp32_storage"]["eps_40000"] < 0.013
         assert res["fp64"]["drift_40000"] <= 1e-12
+
+
+LENS = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table3_lens.json")))
+
+
+@pytest.mark.parametrize("case", sorted(LENS["cases"]))
+def test_lens_between_stratified_fluids_table3(case):
+    """Sec. 4, Table 3: a droplet (R = 20) spreading between two stratified fluids on a
+    160^2 periodic lattice (nu = 0.1, sigma_gb = 0.01) settles into a lens.  After 40 000
+    steps (the lens is stationary from about 20 000 on), its length D and cap heights h1
+    (into the upper fluid, contact angle phi_rg) and h2 (phi_rb) against Eq. (23) with the
+    measured area: within 6 % for D and 3 % for the heights (the paper reports 0.1-5.2 %
+    and 0.4-1.8 %).  Against the paper's simulated columns: within 1.5 nodes for D and
+    0.5 node for the heights."""
+    c = LENS["cases"][case]
+    w = inputs.stratified_lens(160, LENS["setup"]["R"], c["sigma_rg"], c["sigma_rb"], LENS["setup"]["sigma_gb"],
+                               tau=3 * LENS["setup"]["nu"] + 0.5)
+    X, _, _ = lbm3.lbm3_derived(lbm3.make_params(w.nx, w.ny, w.sigma, w.tau))
+    L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau).init(w.rho)
+    try:
+        obs, rho, _ = L.step(40000).observables(want_rho=True)
+    finally:
+        L.close()
+    assert obs["nonfinite"] == 0
+    D, h1, h2, _ = lens_geometry(rho, w.ny / 2)
+    area = float((rho[0] / rho.sum(0)).sum())
+    Da, h1a, h2a = lens_analytic(math.acos(X[0]), math.acos(X[1]), area)
+    print(case, f"D {D:.2f} / {Da:.2f} / paper {c['D_s']}, h1 {h1:.2f} / {h1a:.2f} / {c['h1_s']}, "
+                f"h2 {h2:.2f} / {h2a:.2f} / {c['h2_s']}")
+    assert abs(D / Da - 1) < 0.06 and abs(h1 / h1a - 1) < 0.03 and abs(h2 / h2a - 1) < 0.03
+    assert abs(D - c["D_s"]) < 1.5 and abs(h1 - c["h1_s"]) < 0.5 and abs(h2 - c["h2_s"]) < 0.5
 
 
 def test_full_size_two_step_launches_equal_single_steps_bitwise():
