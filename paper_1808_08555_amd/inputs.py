@@ -294,6 +294,26 @@ def stratified_lens(n: int = 160, R: float = 20.0, sigma_rg: float = 0.01, sigma
                     rho=rho_from_labels(lab), steps=steps)
 
 
+def janus_droplet(n: int, Rr: float, Rg: float, Rb: float, drg: float, dgb: float, sigma,
+                  tau: float = 0.8, y0: float = None, steps: int = 0) -> Workload:
+    """General Janus droplet of fluids 0 (r) and 1 (g) in fluid 2 (b) on an n x n periodic
+    lattice, laid out from its equilibrium geometry: the gb interface a circle of radius Rg
+    centred at (xc, y0), the rb interface radius Rr at (xc, y0 + drg), the rg interface radius
+    Rb at (xc, y0 + dgb), xc = (n - 1) / 2.  Fluid 0 fills the inside of both the rb and rg
+    circles, fluid 1 the inside of the gb circle outside the rg circle."""
+    xc = (n - 1) / 2.0
+    y0 = Rg + 9.0 if y0 is None else y0
+    x, y = _grid(n, n)
+    def inside(cy, R):
+        return (x - xc) ** 2 + (y - cy) ** 2 <= R * R
+    in_r, in_g, in_b = inside(y0 + drg, Rr), inside(y0, Rg), inside(y0 + dgb, Rb)
+    lab = np.full((n, n), 2, dtype=np.int64)
+    lab[in_g & ~in_b] = 1
+    lab[in_r & in_b] = 0
+    return Workload(f"janus_{n}_{drg:g}", n, n, tuple(sigma), (tau, tau, tau), rho=rho_from_labels(lab),
+                    steps=steps, meta={"Rr": Rr, "Rg": Rg, "Rb": Rb, "drg": drg, "dgb": dgb, "y0": y0})
+
+
 def flat_layers(nx: int, ny: int, y_interfaces=(0.25, 0.75), fluids=(2, 0)) -> np.ndarray:
     """Two flat layers uniform in x: fluid fluids[1] for y in [y0*ny, y1*ny), fluids[0] elsewhere."""
     x, y = _grid(nx, ny)

@@ -81,3 +81,55 @@ def lens_geometry(rho: np.ndarray, y_guess: float, x_far: int = 0):
     y_top = _crossing(col, 0.5, j + 1, +1) if col[j + 1] > 0.5 else y_i
     y_bot = _crossing(col, 0.5, j, -1) if col[j] > 0.5 else y_i
     return xr - xl, y_top - y_i, y_i - y_bot, y_i
+
+
+def gjd_geometry(Rr: float, Rg: float, Rb: float, drg: float, sigma_rg: float = 0.01) -> dict:
+    """General Janus droplet of Sec. 4 (fluids r, g inside b): from the radii of the rb, gb
+    and rg interfaces and the distance d_rg between the rb and gb centres, the half central
+    angles and d_gb (Eqs. gjd_01-03), the Neumann angles phi_kl (Eqs. gjd_04/05, chosen by
+    where the gb centre lies) and, with sigma_rg, the other two tensions by the law of sines
+    (Eq. gjd_06)."""
+    tg = math.acos((Rg * Rg + drg * drg - Rr * Rr) / (2 * Rg * drg))
+    chord = Rg * math.sin(tg)
+    tb = math.asin(chord / Rb)
+    tr = math.asin(chord / Rr)
+    dgb = Rg * math.cos(tg) + Rb * math.cos(tb)
+    if Rg * math.cos(tg) >= drg:
+        prb, pgb = math.pi / 2 - tr + tg, math.pi - tr - tb
+    else:
+        prb, pgb = tb + tg, tr - tb
+    prg = math.pi - prb - pgb
+    k = sigma_rg / math.sin(prg)
+    return {"theta_g": tg, "theta_r": tr, "theta_b": tb, "d_gb": dgb, "phi_rb": prb, "phi_gb": pgb,
+            "phi_rg": prg, "sigma_gb": k * math.sin(pgb), "sigma_rb": k * math.sin(prb)}
+
+
+def interface_points(c: np.ndarray, k: int, l: int, third_max: float = 0.05) -> np.ndarray:
+    """Points of the k-l interface: where c_k - c_l changes sign between horizontally or
+    vertically adjacent nodes (linear interpolation), at node pairs where the third fluid's
+    concentration stays below third_max.  Returns an (n, 2) array of (x, y)."""
+    m = 3 - k - l
+    d = c[k] - c[l]
+    pts = []
+    for axis in (0, 1):
+        a, b = (d[:-1, :], d[1:, :]) if axis == 0 else (d[:, :-1], d[:, 1:])
+        ma = c[m][:-1, :] if axis == 0 else c[m][:, :-1]
+        mb = c[m][1:, :] if axis == 0 else c[m][:, 1:]
+        sel = (a * b < 0) & (ma < third_max) & (mb < third_max)
+        jj, ii = np.nonzero(sel)
+        t = a[sel] / (a[sel] - b[sel])
+        if axis == 0:
+            pts.append(np.stack([ii.astype(float), jj + t], 1))
+        else:
+            pts.append(np.stack([ii + t, jj.astype(float)], 1))
+    return np.concatenate(pts)
+
+
+def fit_circle(p: np.ndarray):
+    """Least-squares circle through the points p (algebraic fit of x^2 + y^2 + a x + b y + e
+    = 0).  Returns (xc, yc, R)."""
+    A = np.column_stack([p[:, 0], p[:, 1], np.ones(len(p))])
+    rhs = -(p[:, 0] ** 2 + p[:, 1] ** 2)
+    (a, b, e), *_ = np.linalg.lstsq(A, rhs, rcond=None)
+    xc, yc = -a / 2, -b / 2
+    return xc, yc, math.sqrt(xc * xc + yc * yc - e)
