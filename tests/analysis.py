@@ -133,4 +133,3 @@ def fit_circle(p: np.ndarray):
     (a, b, e), *_ = np.linalg.lstsq(A, rhs, rcond=None)
     xc, yc = -a / 2, -b / 2
     return xc, yc, math.sqrt(xc * xc + yc * yc - e)
-
