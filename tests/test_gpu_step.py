@@ -269,6 +269,35 @@ def test_lens_between_stratified_fluids_table3(case):
     assert abs(D - c["D_s"]) < 1.5 and abs(h1 - c["h1_s"]) < 0.5 and abs(h2 - c["h2_s"]) < 0.5
 
 
+@pytest.mark.parametrize("sigma_rg,state", [(0.01, "critical"), (0.015, "supercritical")])
+def test_complete_spreading_critical_and_supercritical(sigma_rg, state):
+    """Sec. 4, complete spreading: the lens set-up of Table 3 (160^2, R = 20) with
+    sigma_gb = sigma_rb = 0.005 and nu = 0.05, 50 000 steps (steady by then, per the paper).
+    At the critical state (sigma_rg = sigma_gb + sigma_rb) the red droplet ends sitting on
+    the gb interface: it still touches green (some nodes with c_r and c_g above 0.1) and its
+    lowest point lies within 6 nodes of the flat interface.  Above it (sigma_rg = 0.015) the
+    droplet leaves the interface and rises into blue: no red-green contact, lowest point at
+    least 8 nodes above.  (Measured: 26 contact nodes and 3.4 nodes; none and 10.5.)"""
+    w = inputs.stratified_lens(160, 20.0, sigma_rg, 0.005, 0.005, tau=0.65)
+    L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau).init(w.rho)
+    try:
+        obs, rho, _ = L.step(50000).observables(want_rho=True)
+    finally:
+        L.close()
+    assert obs["nonfinite"] == 0
+    c = rho / rho.sum(0)
+    contact = int(((c[0] > 0.1) & (c[1] > 0.1)).sum())
+    d = c[1][:, 0] - c[2][:, 0]  # the flat gb interface, far from the droplet
+    y_i = next(j + d[j] / (d[j] - d[j + 1]) for j in range(50, 110) if d[j] * d[j + 1] < 0)
+    xc = int(round(float((c[0] * np.arange(w.nx)[None, :]).sum() / c[0].sum())))
+    bottom = float(np.nonzero(c[0][:, xc] > 0.5)[0].min())
+    print(state, "contact", contact, "gap", bottom - y_i)
+    if state == "critical":
+        assert contact > 0 and bottom - y_i < 6.0
+    else:
+        assert contact == 0 and bottom - y_i > 8.0
+
+
 GJD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table4_gjd.json")))
 
 
