@@ -163,6 +163,16 @@ __device__ __forceinline__ void st_at(T* base, unsigned byte_off, T v)
     __builtin_nontemporal_store(v, (gT*)(b + byte_off));
 }
 
+// The plane stride as a value the optimiser must take afresh at each row: left alone, it
+// hoists the 18 or 27 plane offsets of a row out of the march loop and keeps them all live
+// in scalar registers, which then spill to vector lanes (FP32 storage: 91 spilled scalars,
+// about 190 lane moves per row).  Recomputed per row they cost a few scalar multiplies.
+__device__ __forceinline__ int64_t fresh_stride(int64_t s)
+{
+    asm volatile("" : "+s"(s));
+    return s;
+}
+
 // Isotropic difference of Eq. (12), 3 sum_i w_i phi(x + e_i) e_i, written as weighted
 // differences of opposite neighbours.  The grouping keeps exact zeros for data that
 // are mirror-symmetric about the node, also when the compiler fuses multiply-adds.
@@ -483,22 +493,24 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
         const int64_t pitch = kp.pitch;
         const int64_t srow[3] = {(int64_t)(r + 1 == ny ? 0 : r + 1) * pitch, (int64_t)r * pitch,
                                  (int64_t)(r == 0 ? ny - 1 : r - 1) * pitch};
+        const int64_t pl = fresh_stride(plane);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
             for (int i = 0; i < 9; ++i)
-                v[k * 9 + i] = C(ld_at(fin + ((int64_t)(k * 9 + i) * plane + srow[EY[i] + 1]),
+                v[k * 9 + i] = C(ld_at(fin + ((int64_t)(k * 9 + i) * pl + srow[EY[i] + 1]),
                                        scol[EX[i] + 1]));
     };
     // ---- input: FAC loads source row s (wrapped): v[0..8] = f_dag_i(x - e_x,i, s) (pulled
     // along x), v[9..17] = c_k, V_k of the lane's own column
     auto load_fac = [&](int s, C (&v)[NV]) {
         const int64_t rowo = (int64_t)s * kp.fpitch;
+        const int64_t pl = fresh_stride(plane);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            v[i] = C(ld_at(fin + ((int64_t)i * plane + rowo), scol[EX[i] + 1]));
+            v[i] = C(ld_at(fin + ((int64_t)i * pl + rowo), scol[EX[i] + 1]));
 #pragma unroll
-        for (int q = 9; q < NV; ++q) v[q] = C(ld_at(fin + ((int64_t)q * plane + rowo), xoff));
+        for (int q = 9; q < NV; ++q) v[q] = C(ld_at(fin + ((int64_t)q * pl + rowo), xoff));
     };
     // FAC partial sums of the rows above (see pull_row)
     C d0r[3], d0f[6], d1r[3], d1f[3];  // d0f: f_2, f_5, f_6, f_0, f_1, f_3; d1f: f_2, f_5, f_6
@@ -664,6 +676,7 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
             collide_recolour<C>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
             if constexpr (!OBS) {
                 const uint32_t key = ((uint32_t)yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt;
+                const int64_t pl = fresh_stride(plane);
                 if constexpr (OUT == Fmt::F27) {
                     const int64_t orow = (int64_t)yo * kp.pitch;
 #pragma unroll
@@ -672,22 +685,22 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
                         for (int i = 0; i < 9; ++i) {
                             const int q = k * 9 + i;
                             const C val = recon<C>(ck[k], fd[i], V[2 * k], V[2 * k + 1], i);
-                            st_at(fout + ((int64_t)q * plane + orow), xoff,
+                            st_at(fout + ((int64_t)q * pl + orow), xoff,
                                   to_storage<S, C>(val, key + (uint32_t)q));
                         }
                 } else {
                     const int64_t orow = (int64_t)yo * kp.fpitch;
 #pragma unroll
                     for (int i = 0; i < 9; ++i)
-                        st_at(fout + ((int64_t)i * plane + orow), xoff,
+                        st_at(fout + ((int64_t)i * pl + orow), xoff,
                               to_storage<S, C>(fd[i], key + (uint32_t)i));
 #pragma unroll
                     for (int k = 0; k < 3; ++k)
-                        st_at(fout + ((int64_t)(9 + k) * plane + orow), xoff,
+                        st_at(fout + ((int64_t)(9 + k) * pl + orow), xoff,
                               to_storage<S, C>(ck[k], key + (uint32_t)(9 + k)));
 #pragma unroll
                     for (int q = 0; q < 6; ++q)
-                        st_at(fout + ((int64_t)(12 + q) * plane + orow), xoff,
+                        st_at(fout + ((int64_t)(12 + q) * pl + orow), xoff,
                               to_storage<S, C>(V[q], key + (uint32_t)(12 + q)));
                 }
             } else {
@@ -780,6 +793,8 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
     const int J = rows + 11;  // one more iteration for B's last row
 
     auto load_fac = [&](int s, C (&v)[18]) {
+        // (plane offsets left to the optimiser here: taking the stride afresh, as the other
+        // marches do, measured 6% slower in this kernel)
         const int64_t rowo = (int64_t)s * kp.fpitch;
 #pragma unroll
         for (int i = 0; i < 9; ++i) v[i] = ld_at(fin + ((int64_t)i * plane + rowo), scol[EX[i] + 1]);
@@ -1019,10 +1034,11 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
 
     auto load_fac = [&](int s, C (&v)[18]) {
         const int64_t rowo = (int64_t)s * kp.fpitch;
+        const int64_t pl = fresh_stride(plane);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) v[i] = ld_at(fin + ((int64_t)i * plane + rowo), scol[EX[i] + 1]);
+        for (int i = 0; i < 9; ++i) v[i] = ld_at(fin + ((int64_t)i * pl + rowo), scol[EX[i] + 1]);
 #pragma unroll
-        for (int q = 9; q < 18; ++q) v[q] = ld_at(fin + ((int64_t)q * plane + rowo), xoff);
+        for (int q = 9; q < 18; ++q) v[q] = ld_at(fin + ((int64_t)q * pl + rowo), xoff);
     };
     auto publish_a = [&](const C (&v)[18], int slot) {
         if (a0) {
@@ -1163,12 +1179,13 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
             force_at_lane<C, NT>(tB, sb0, sb1, sb2, t, Fx, Fy);
             collide_recolour<C>(fB_b, rB_b, nB_b, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
             const int64_t orow = (int64_t)yo * kp.fpitch;
+            const int64_t pl = fresh_stride(plane);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st_at(fout + ((int64_t)i * plane + orow), xoff, fd[i]);
+            for (int i = 0; i < 9; ++i) st_at(fout + ((int64_t)i * pl + orow), xoff, fd[i]);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) st_at(fout + ((int64_t)(9 + k) * plane + orow), xoff, ck[k]);
+            for (int k = 0; k < 3; ++k) st_at(fout + ((int64_t)(9 + k) * pl + orow), xoff, ck[k]);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) st_at(fout + ((int64_t)(12 + q) * plane + orow), xoff, V[q]);
+            for (int q = 0; q < 6; ++q) st_at(fout + ((int64_t)(12 + q) * pl + orow), xoff, V[q]);
         }
         if (jb >= 0) {
 #pragma unroll
