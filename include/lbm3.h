@@ -130,18 +130,19 @@ int lbm3_set_tile(lbm3_t *h, int32_t threads, int32_t rows);
 int lbm3_get_tile(const lbm3_t *h, int32_t *threads, int32_t *rows);
 
 /* How many steps one launch advances in lbm3_step: 0 = chosen by size (two on
- * lattices of 2^18 nodes or more in FP64, 2^20 in FP32), 1 = one, 2 = two where
- * possible.  A two-step
- * launch keeps the intermediate state on chip and needs the factored state
- * (LBM3_FP64 or LBM3_FP32) and a tile width (lbm3_set_tile's threads) of at most
- * 256; otherwise, and for the odd last step, a one-step launch runs.  Results do not depend on the mode
+ * lattices of 2^18 nodes or more in FP64, 2^20 in FP32 and FP32 storage), 1 = one,
+ * 2 = two where possible.  A two-step
+ * launch keeps the intermediate state on chip (in every precision; the first
+ * step of an FP64 or FP32 state loaded in 27-population form runs alone) and needs
+ * a tile width (lbm3_set_tile's threads) of at most 256; otherwise, and for the
+ * odd last step, a one-step launch runs.  Results do not depend on the mode
  * (bitwise).  EINVAL for another mode. */
 int lbm3_set_steps_per_launch(lbm3_t *h, int32_t mode);
 /* The launch lbm3_step uses for pairs of steps: *steps = 2 with its threads per
  * workgroup and workgroup count, or *steps = 1 (and zeros) when pairs run as two
- * one-step launches.  An FP64 two-step workgroup runs each step on its own waves,
- * so its threads are twice its strip width basis; FP32 uses one thread per
- * column for both steps.  Any pointer may be NULL. */
+ * one-step launches.  An FP64 or FP32-storage two-step workgroup runs each step on
+ * its own waves, so its threads are twice its strip width basis; FP32 uses one
+ * thread per column for both steps.  Any pointer may be NULL. */
 int lbm3_get_pair_launch(const lbm3_t *h, int32_t *steps, int32_t *threads, int32_t *workgroups);
 
 /* Device pointer of the buffer that holds the current state, its element size in

@@ -189,8 +189,8 @@ int check_rho_fields(const double* rho, const double* u, int64_t n)
 
 // Builds the tile lists for the handle's launch shape (the single step's and, where the
 // two-step pass exists, its own with the wider halo) and uploads them with the one-entry
-// instance table.  The two-step pass is used for FP64 and FP32 (factored state) with 64 to
-// 256 threads; rows requested explicitly apply to both lists.
+// instance table.  The two-step pass exists for every precision (64 to 256 threads); rows
+// requested explicitly apply to both lists.
 int upload_plan(lbm3* h)
 {
     int rows = h->rows_request;
@@ -209,7 +209,7 @@ int upload_plan(lbm3* h)
     const bool big = (int64_t)h->kp.nx * h->kp.ny >= min2;
     const bool want2 = h->pass_mode == 2 || (h->pass_mode == 0 && big);
     int t2 = h->tile_set ? h->threads : (h->kp.nx < 768 ? 64 : 256);
-    const int slots2 = steady_fmt(h->prec) == Fmt::FAC && want2 ? device_slots_pair(h->prec, t2) : 0;
+    const int slots2 = want2 ? device_slots_pair(h->prec, t2) : 0;
     if (slots2 > 0) {
         int rows2 = h->rows_request;
         if (rows2 <= 0) rows2 = auto_rows(h->kp.nx, h->kp.ny, t2, slots2, eb, 6);
@@ -251,12 +251,9 @@ int step_handle(lbm3* h, int64_t n, bool factored)
     while (n > 0) {
         hipError_t e;
         int done = 1;
-        if (h->fmt == Fmt::FAC && n >= 2 && h->ntiles2 > 0) {
-            e = h->prec == Prec::F64
-                    ? tiles_f64_pair(h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst, h->dtiles2, h->ntiles2,
-                                     h->threads2, h->stream)
-                    : tiles_f32_pair(h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst, h->dtiles2, h->ntiles2,
-                                     h->threads2, h->stream);
+        if (h->fmt == steady_fmt(h->prec) && n >= 2 && h->ntiles2 > 0) {
+            e = launch_pair(h->prec, h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst, h->dtiles2, h->ntiles2,
+                            h->threads2, h->step, h->stream);
             done = 2;
         } else {
             const Fmt out = factored ? Fmt::FAC : Fmt::F27;
@@ -541,7 +538,7 @@ int lbm3_get_pair_launch(const lbm3_t* h, int32_t* steps, int32_t* threads, int3
     }
     const bool two = h->ntiles2 > 0;
     if (steps) *steps = two ? 2 : 1;
-    if (threads) *threads = two ? (h->prec == Prec::F64 ? 2 : 1) * h->threads2 : 0;
+    if (threads) *threads = two ? (h->prec == Prec::F32 ? 1 : 2) * h->threads2 : 0;
     if (workgroups) *workgroups = two ? h->ntiles2 : 0;
     return LBM3_OK;
 }

@@ -108,7 +108,7 @@ static int batch_plan(lbm3_batch* b)
     for (int i = 0; i < b->count; ++i) nodes += (int64_t)b->inst[i].kp.nx * b->inst[i].kp.ny;
     const bool want2 = b->pair_mode == 2 || (b->pair_mode == 0 && nodes >= ((int64_t)1 << 20));
     const int t2 = std::min(256, b->threads);
-    const int slots2 = steady_fmt(b->prec) == Fmt::FAC && want2 ? device_slots_pair(b->prec, t2) : 0;
+    const int slots2 = want2 ? device_slots_pair(b->prec, t2) : 0;
     if (slots2 > 0) {
         double best2 = 1e300;
         for (int r : {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512}) {
@@ -170,11 +170,8 @@ static int ensure_batch_staging(lbm3_batch* b, size_t doubles)
 static hipError_t launch_steady(lbm3_batch* b, int c, bool two, int64_t step)
 {
     if (two)
-        return b->prec == Prec::F64
-                   ? tiles_f64_pair(b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles2, b->ntiles2, b->threads2,
-                                    b->stream)
-                   : tiles_f32_pair(b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles2, b->ntiles2, b->threads2,
-                                    b->stream);
+        return launch_pair(b->prec, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles2, b->ntiles2, b->threads2, step,
+                           b->stream);
     const Fmt sf = steady_fmt(b->prec);
     return launch_tiles(b->prec, sf, sf, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles, b->ntiles, b->threads,
                         step, 0, b->stream);
@@ -346,7 +343,7 @@ int lbm3_batch_get_pair_launch(const lbm3_batch_t* b, int32_t* steps, int32_t* t
     }
     const bool two = b->ntiles2 > 0;
     if (steps) *steps = two ? 2 : 1;
-    if (threads) *threads = two ? (b->prec == Prec::F64 ? 2 : 1) * b->threads2 : 0;
+    if (threads) *threads = two ? (b->prec == Prec::F32 ? 1 : 2) * b->threads2 : 0;
     if (rows) *rows = two ? b->rows2 : 0;
     if (workgroups) *workgroups = two ? b->ntiles2 : 0;
     return LBM3_OK;

@@ -121,8 +121,16 @@ hipError_t tiles_f64_pair(const void* fin, void* fout, const Instance* inst, con
                           int ntiles, int threads, hipStream_t stream);
 hipError_t tiles_f32_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                           int ntiles, int threads, hipStream_t stream);
+// The same for FP32 storage (27-population state in and out), with the stochastic-rounding
+// salts of the two steps.
+hipError_t tiles_f32s_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
+                           int ntiles, int threads, uint32_t salt_a, uint32_t salt_b, hipStream_t stream);
 int tiles_f64_pair_occupancy(int threads);
 int tiles_f32_pair_occupancy(int threads);
+int tiles_f32s_pair_occupancy(int threads);
+// Two steps per launch of any precision from `step` (state in the precision's steady format).
+hipError_t launch_pair(Prec prec, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
+                       int ntiles, int threads, int64_t step, hipStream_t stream);
 
 // Host-side helpers (lbm3_api.hip).
 void set_error(const char* fmt, ...);

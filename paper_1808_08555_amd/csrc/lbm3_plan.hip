@@ -102,6 +102,7 @@ int device_slots_pair(Prec prec, int threads)
     int per_cu = 0;
     if (prec == Prec::F64) per_cu = tiles_f64_pair_occupancy(threads);
     if (prec == Prec::F32) per_cu = tiles_f32_pair_occupancy(threads);
+    if (prec == Prec::F32S) per_cu = tiles_f32s_pair_occupancy(threads);
     return per_cu * device_cus();
 }
 

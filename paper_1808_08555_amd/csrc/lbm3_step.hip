@@ -155,6 +155,19 @@ uint32_t step_salt(int64_t step)
     return x;
 }
 
+hipError_t launch_pair(Prec prec, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
+                       int ntiles, int threads, int64_t step, hipStream_t stream)
+{
+    switch (prec) {
+        case Prec::F64: return tiles_f64_pair(fin, fout, inst, tiles, ntiles, threads, stream);
+        case Prec::F32: return tiles_f32_pair(fin, fout, inst, tiles, ntiles, threads, stream);
+        case Prec::F32S:
+            return tiles_f32s_pair(fin, fout, inst, tiles, ntiles, threads, step_salt(step), step_salt(step + 1),
+                                   stream);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_tiles(Prec prec, Fmt in, Fmt out, const void* fin, void* fout, const Instance* inst,
                         const Tile* tiles, int ntiles, int threads, int64_t step, int filter,
                         hipStream_t st)

@@ -262,6 +262,23 @@ __device__ __forceinline__ C rsqrt_nr(C s)
     }
 }
 
+// Densities rho_k and totals f_i of a node from its 27 pulled populations v(9k + i), added
+// in a fixed order that groups the directions by source row (e_y = +1, 0, -1); every march
+// that pulls the 27-population format uses it, so all of them round alike.
+template <typename C, typename Get>
+__device__ __forceinline__ void densities_f27(Get v, C (&r0)[3], C (&f0)[9])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const C P = group_sum<C>(v(k * 9 + 2), v(k * 9 + 5), v(k * 9 + 6));
+        const C Z = group_sum<C>(v(k * 9 + 0), v(k * 9 + 1), v(k * 9 + 3));
+        const C M = group_sum<C>(v(k * 9 + 4), v(k * 9 + 7), v(k * 9 + 8));
+        r0[k] = (P + Z) + M;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f0[i] = (v(i) + v(9 + i)) + v(18 + i);
+}
+
 template <typename C>
 struct StepConsts {
     C sig[3], g[3], beta0, inv_nu[3], cfac[3], guard2;
@@ -532,15 +549,7 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
     };
     // F27: densities and totals of a row from its 27 pulled populations, same order.
     auto consume_f27 = [&](const C (&v)[NV], C (&r0)[3], C (&f0)[9]) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const C P = group_sum<C>(v[k * 9 + 2], v[k * 9 + 5], v[k * 9 + 6]);
-            const C Z = group_sum<C>(v[k * 9 + 0], v[k * 9 + 1], v[k * 9 + 3]);
-            const C M = group_sum<C>(v[k * 9 + 4], v[k * 9 + 7], v[k * 9 + 8]);
-            r0[k] = (P + Z) + M;
-        }
-#pragma unroll
-        for (int i = 0; i < 9; ++i) f0[i] = (v[i] + v[9 + i]) + v[18 + i];
+        densities_f27<C>([&](int q) { return v[q]; }, r0, f0);
     };
 
     C fA[9], fB[9], rA[3], rB[3], nB[6], vn[NV];
@@ -1204,6 +1213,233 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
     }
 }
 
+// The two-step pass for the 27-population format with FP32 storage and FP64 arithmetic,
+// one step per wave group as in pair_step_a/pair_step_b.  Step A pulls its 27 populations
+// from global memory as march() does and rounds its recoloured populations to float with
+// the stochastic rounding and keys a stored step would use; they go to a ring of three LDS
+// rows (by A's output row mod 3) instead of HBM.  Step B pulls the three rows it needs
+// from the ring.  The result equals two single steps bit for bit.  Lane t of either step
+// sits on column x0 - 6 + t (cols <= NT - 12).  A runs march() over rows y0 - 3 ..
+// y0 + rows + 2: iteration j forms the densities of row y0 - 5 + j and stores row
+// y0 - 7 + j into ring slot j mod 3; B, march() over the tile's own rows, forms the
+// densities of row y0 - 9 + j (A's rows of iterations j - 3 .. j - 1) and stores row
+// y0 - 11 + j.  Three phases per iteration as in the factored pass (densities, stress,
+// collision), no pre-roll, rows + 11 iterations for both steps.
+template <int NT>
+struct alignas(16) Pair27Lds {
+    double cA[3][3][NT];
+    double tA[3][3][NT];
+    double cB[3][3][NT];
+    double tB[3][3][NT];
+    float ring[3][27][NT];  // A's rows as stored: population 9k + i, by row mod 3
+};
+
+template <int NT>
+__device__ __forceinline__ void pair27_step_a(const float* __restrict__ fin, const KParams& kp, int x0, int y0,
+                                              int rows, int cols, Pair27Lds<NT>& L, int t, uint32_t salt)
+{
+    using C = double;
+    const int nx = kp.nx, ny = kp.ny;
+    const int64_t plane = kp.plane;
+    const int x = wrapi(x0 - 6 + t, nx);
+    const unsigned scol[3] = {(unsigned)wrapi(x + 1, nx) * 4u, (unsigned)x * 4u, (unsigned)wrapi(x - 1, nx) * 4u};
+    const bool a1 = (t >= 1) && (t <= cols + 10);
+    const bool a2 = (t >= 2) && (t <= cols + 9);
+    const bool a3 = (t >= 3) && (t <= cols + 8);
+    const StepConsts<C> K(kp);
+    const int JA = rows + 10;
+    const int J = rows + 11;
+
+    // the 27 pulled populations of the middle row r (rows r + 1, r, r - 1 by e_y), as stored
+    auto load = [&](int r, float (&v)[27]) {
+        const int64_t pitch = kp.pitch;
+        const int64_t srow[3] = {(int64_t)(r + 1 == ny ? 0 : r + 1) * pitch, (int64_t)r * pitch,
+                                 (int64_t)(r == 0 ? ny - 1 : r - 1) * pitch};
+        const int64_t pl = fresh_stride(plane);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                v[k * 9 + i] = ld_at(fin + ((int64_t)(k * 9 + i) * pl + srow[EY[i] + 1]), scol[EX[i] + 1]);
+    };
+
+    C fA[9], fB[9], rA[3], rB[3], nB[6];
+    float vn[27];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fA[i] = fB[i] = C(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rA[k] = rB[k] = C(1);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) nB[q] = C(0);
+#pragma unroll
+    for (int q = 0; q < 27; ++q) vn[q] = 1.0f;
+    RowCursor src(y0 - 5, ny);  // middle rows in load order: y0 - 5, y0 - 4, ...
+    {
+        const int r = src.next();
+        if (a1) load(r, vn);
+    }
+
+#pragma unroll 1
+    for (int j = 0; j < J; ++j) {
+        const bool live = j < JA;
+        const int s0 = j % 3, s1 = (j + 2) % 3, s2 = (j + 1) % 3;
+        // phase 0: densities of row y0 - 5 + j; prefetch the next row
+        C f0[9], r0[3];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f0[i] = C(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r0[k] = C(1);
+        if (live) {
+            float v[27];
+#pragma unroll
+            for (int q = 0; q < 27; ++q) v[q] = vn[q];
+            const int r = src.next();
+            if (a1 && j + 1 < JA) load(r, vn);
+            densities_f27<C>([&](int q) { return C(v[q]); }, r0, f0);
+            const C irho = recip((r0[0] + r0[1]) + r0[2]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) L.cA[s0][k][t] = r0[k] * irho;
+        }
+        __syncthreads();
+        // phase 1: stress of row y0 - 6 + j
+        C nA[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
+        if (live && j >= 2 && a2) {
+            C Txx, Txy, Tyy;
+            stress_at_lane<C, NT>(L.cA, s0, s1, s2, t, rA, K, nA, Txx, Txy, Tyy);
+            L.tA[s1][0][t] = Txx;
+            L.tA[s1][1][t] = Txy;
+            L.tA[s1][2][t] = Tyy;
+        }
+        __syncthreads();
+        // phase 2: recolour row y0 - 7 + j and round it as it would be stored
+        if (live && j >= 4 && a3) {
+            const uint32_t yo = (uint32_t)wrapi(y0 - 7 + j, ny);
+            const uint32_t key = (yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt;
+            C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
+            force_at_lane<C, NT>(L.tA, s0, s1, s2, t, Fx, Fy);
+            collide_recolour<C>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const int q = k * 9 + i;
+                    L.ring[s0][q][t] =
+                        to_storage<float, C>(recon<C>(ck[k], fd[i], V[2 * k], V[2 * k + 1], i), key + (uint32_t)q);
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            fB[i] = fA[i];
+            fA[i] = f0[i];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            rB[k] = rA[k];
+            rA[k] = r0[k];
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) nB[q] = nA[q];
+        __syncthreads();
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void pair27_step_b(float* __restrict__ fout, const KParams& kp, int x0, int y0, int rows,
+                                              int cols, Pair27Lds<NT>& L, int t, uint32_t salt)
+{
+    using C = double;
+    const int nx = kp.nx;
+    const int64_t plane = kp.plane;
+    const int x = wrapi(x0 - 6 + t, nx);
+    const unsigned xoff = (unsigned)x * 4u;
+    const bool b1 = (t >= 4) && (t <= cols + 7);
+    const bool b2 = (t >= 5) && (t <= cols + 6);
+    const bool b3 = (t >= 6) && (t <= cols + 5);
+    const StepConsts<C> K(kp);
+    const int J = rows + 11;
+
+    C fA[9], fB[9], rA[3], rB[3], nB[6];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fA[i] = fB[i] = C(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rA[k] = rB[k] = C(1);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) nB[q] = C(0);
+
+#pragma unroll 1
+    for (int j = 0; j < J; ++j) {
+        // march() iteration jb over the tile's rows: densities of row y0 - 2 + jb
+        const int jb = j - 7;
+        const bool live = jb >= 0 && jb < rows + 4;
+        const int s0 = (jb + 9) % 3, s1 = (jb + 11) % 3, s2 = (jb + 10) % 3;
+        // ring slots of A's rows y - 1, y, y + 1 (A iterations j - 3, j - 2, j - 1), by e_y
+        const int rs[3] = {(j + 2) % 3, (j + 1) % 3, j % 3};  // e_y = -1, 0, +1
+        // phase 0: densities from the ring
+        C f0[9], r0[3];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f0[i] = C(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r0[k] = C(1);
+        if (live && b1) {
+            densities_f27<C>(
+                [&](int q) {
+                    const int i = q % 9;
+                    return C(L.ring[rs[EY[i] + 1]][q][t - EX[i]]);
+                },
+                r0, f0);
+        }
+        if (live) {
+            const C irho = recip((r0[0] + r0[1]) + r0[2]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) L.cB[s0][k][t] = r0[k] * irho;
+        }
+        __syncthreads();
+        // phase 1: stress of row y0 - 3 + jb
+        C nA[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
+        if (live && jb >= 2 && b2) {
+            C Txx, Txy, Tyy;
+            stress_at_lane<C, NT>(L.cB, s0, s1, s2, t, rA, K, nA, Txx, Txy, Tyy);
+            L.tB[s1][0][t] = Txx;
+            L.tB[s1][1][t] = Txy;
+            L.tB[s1][2][t] = Tyy;
+        }
+        __syncthreads();
+        // phase 2: collide, recolour and store row y0 - 4 + jb
+        if (live && jb >= 4 && b3) {
+            const int yo = y0 - 4 + jb;
+            const uint32_t key = ((uint32_t)yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt;
+            C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
+            force_at_lane<C, NT>(L.tB, s0, s1, s2, t, Fx, Fy);
+            collide_recolour<C>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
+            const int64_t orow = (int64_t)yo * kp.pitch;
+            const int64_t pl = fresh_stride(plane);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const int q = k * 9 + i;
+                    st_at(fout + ((int64_t)q * pl + orow), xoff,
+                          to_storage<float, C>(recon<C>(ck[k], fd[i], V[2 * k], V[2 * k + 1], i), key + (uint32_t)q));
+                }
+        }
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                fB[i] = fA[i];
+                fA[i] = f0[i];
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                rB[k] = rA[k];
+                rA[k] = r0[k];
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) nB[q] = nA[q];
+        }
+        __syncthreads();
+    }
+}
+
 // Workgroup reduction of the observables partials in `red` (LDS, kObsFields x NT doubles);
 // the caller has synchronised the workgroup before `red` is reused.
 template <int NT>
@@ -1431,6 +1667,61 @@ int pair_occupancy(int threads)
         case 256: return pair_occupancy_nt<C, 256>();
         default: return 0;
     }
+}
+
+// The 27-population two-step pass (FP32 storage), salts of the two steps' stochastic
+// rounding; a workgroup of 2 NT lanes as in k_tiles2w.
+template <int NT>
+__global__ __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles2s(
+    const float* __restrict__ fin, float* __restrict__ fout, const Instance* __restrict__ inst,
+    const Tile* __restrict__ tiles, uint32_t salt_a, uint32_t salt_b)
+{
+    static_assert(NT % 64 == 0, "each wave must belong to one step");
+    __shared__ Pair27Lds<NT> lds;
+    const Tile tl = tiles[blockIdx.x];
+    const KParams kp = inst[tl.inst].kp;
+    const int64_t off = inst[tl.inst].offset;
+    const uint32_t mixi = mix32((uint32_t)tl.inst * 0x9E3779B9U + 0x51ed270bU);
+    const int lane0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x);
+    if (lane0 < NT)
+        pair27_step_a<NT>(fin + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x, salt_a ^ mixi);
+    else
+        pair27_step_b<NT>(fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x - NT, salt_b ^ mixi);
+}
+
+inline hipError_t tiles_pair27_any(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                                   int threads, uint32_t salt_a, uint32_t salt_b, hipStream_t st)
+{
+    switch (threads) {
+        case 64:
+            hipLaunchKernelGGL((k_tiles2s<64>), dim3(ntiles), dim3(128), 0, st, (const float*)fin, (float*)fout, inst,
+                               tiles, salt_a, salt_b);
+            break;
+        case 128:
+            hipLaunchKernelGGL((k_tiles2s<128>), dim3(ntiles), dim3(256), 0, st, (const float*)fin, (float*)fout, inst,
+                               tiles, salt_a, salt_b);
+            break;
+        case 256:
+            hipLaunchKernelGGL((k_tiles2s<256>), dim3(ntiles), dim3(512), 0, st, (const float*)fin, (float*)fout, inst,
+                               tiles, salt_a, salt_b);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+inline int pair27_occupancy(int threads)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (threads) {
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2s<64>, 128, 0); break;
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2s<128>, 256, 0); break;
+        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2s<256>, 512, 0); break;
+        default: break;
+    }
+    return e == hipSuccess ? nb : 0;
 }
 
 // Resident workgroups per CU of the steady-state step (the format of steady_fmt).

@@ -13,4 +13,12 @@ hipError_t tiles_f32s(Fmt in, Fmt out, bool obs, const void* fin, void* fout, co
 
 int tiles_f32s_occupancy(int threads) { return tiles_occupancy<float, double>(threads); }
 
+hipError_t tiles_f32s_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                           int threads, uint32_t salt_a, uint32_t salt_b, hipStream_t stream)
+{
+    return tiles_pair27_any(fin, fout, inst, tiles, ntiles, threads, salt_a, salt_b, stream);
+}
+
+int tiles_f32s_pair_occupancy(int threads) { return pair27_occupancy(threads); }
+
 }  // namespace tcg

@@ -145,13 +145,13 @@ DRIFT_2000 = {"fp32_storage": 1e-6, "fp32": 1.2e-4}
 @pytest.mark.parametrize("precision,rtol", [("fp32", 2e-5), ("fp32_storage", 2e-6)])
 def test_double_droplet_1024_reduced_precision(precision, rtol):
     """The 1024^2 double droplet (two tangent disks of radius 100 in fluid 3, interface
-    noise) in its default launch configuration (FP32: two steps per launch): 10 steps
+    noise) in its default launch configuration (two steps per launch): 10 steps
     against the FP64 oracle element by element, then per-fluid mass drift over 2000 steps
     within DRIFT_2000."""
     w, o = _double_droplet_1024()
     L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, w.rho0, w.beta0, precision).init(w.rho)
     try:
-        assert lbm3.lbm3_get_pair_launch(L.h)[0] == (2 if precision == "fp32" else 1)
+        assert lbm3.lbm3_get_pair_launch(L.h)[0] == 2
         m0 = L.observables()[0]["mass"]
         g = L.step(10).state()
         err = np.abs(g - o).max() / np.abs(o).max()
@@ -513,7 +513,7 @@ def test_lattices_at_the_side_limit(nx, ny):
     assert np.abs(g - o).max() <= TOL_FP64
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_storage"])
 @pytest.mark.parametrize("shape,tile", [((64, 64), None), ((301, 83), (128, 5)), ((600, 333), (256, 0)),
                                         ((97, 130), (64, 9)), ((512, 40), (128, 1)), ((1030, 1021), None),
                                         ((5, 7), (64, 0)), ((1, 5), None), ((3, 2), None), ((2, 1), None)])
