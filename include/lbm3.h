@@ -178,6 +178,8 @@ int lbm3_state_buffer(const lbm3_t *h, void **dev_ptr, int32_t *elem_bytes, int6
  * lbm3_batch_set_tile: size_class_side = 0 sets threads per workgroup for the
  *   whole batch (and, with rows > 0, rows for every size class); a side > 0 sets
  *   the rows of the instances with nx == side (threads must equal the batch's).
+ *   Threads set this way are also the two-step launch's width (at most 256);
+ *   otherwise that width is 128, or 256 when an instance is 768 or more wide.
  *   Results do not depend on the shape.
  * lbm3_batch_set_steps_per_launch: as lbm3_set_steps_per_launch, for the whole
  *   batch (0 = two when the instances hold 2^20 nodes or more in all); the

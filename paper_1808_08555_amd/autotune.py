@@ -106,7 +106,7 @@ def tune_batch(batch, sizes, precision: str, steps: int = 20, force: bool = Fals
     (lbm3_batch_get_pair_launch reads it back)."""
     import torch
     classes = sorted(set(int(s) for s in sizes))
-    key = f"batch2/{_arch(torch)}/{precision}/" + ",".join(f"{s}" for s in sorted(int(s) for s in sizes))
+    key = f"batch3/{_arch(torch)}/{precision}/" + ",".join(f"{s}" for s in sorted(int(s) for s in sizes))
     hit = None if force else _load().get(key)
     if hit:
         t = int(hit["threads"])
@@ -144,15 +144,22 @@ def tune_batch(batch, sizes, precision: str, steps: int = 20, force: bool = Fals
             if ms < best_ms:
                 best_ms, rows[s] = ms, r
         lbm3.lbm3_batch_set_tile(batch, s, best_t, rows[s])
-    mode = 1
+    # two steps per launch: its width is the batch's threads (at most 256), tried on its own
+    mode, final_t = 1, best_t
     lbm3.lbm3_batch_set_steps_per_launch(batch, 2)
-    if lbm3.lbm3_batch_get_pair_launch(batch)[0] == 2:
+    for t in (64, 128, 256):
+        lbm3.lbm3_batch_set_tile(batch, 0, t, 0)
+        if lbm3.lbm3_batch_get_pair_launch(batch)[0] != 2:
+            continue
         ms = _time(torch, run, steps)
         if verbose:
-            print(f"  batch two steps per launch: {ms:.4f} ms/step")
+            print(f"  batch two steps per launch, width {t}: {ms:.4f} ms/step")
         if ms < best_ms:
-            best_ms, mode = ms, 2
+            best_ms, mode, final_t = ms, 2, t
     lbm3.lbm3_batch_set_steps_per_launch(batch, mode)
-    _store(key, {"threads": best_t, "rows": {str(k): v for k, v in rows.items()},
+    lbm3.lbm3_batch_set_tile(batch, 0, final_t, 0)
+    for s in classes:
+        lbm3.lbm3_batch_set_tile(batch, s, final_t, rows[s])
+    _store(key, {"threads": final_t, "rows": {str(k): v for k, v in rows.items()},
                  "steps_per_launch": mode, "ms_per_step": best_ms})
-    return best_t, rows
+    return final_t, rows

@@ -31,6 +31,7 @@ struct lbm3_batch {
     int cur = 0;
     int64_t step = 0;
     int threads = 256;
+    bool tile_set = false;  // threads chosen by lbm3_batch_set_tile (then also the two-step width)
     std::map<int, int> rows_by_side;  // rows per segment for instances with nx == side
     tcg::Tile* dtiles = nullptr;      // step list, XCD-ordered
     int ntiles = 0;
@@ -107,7 +108,12 @@ static int batch_plan(lbm3_batch* b)
     int64_t nodes = 0;
     for (int i = 0; i < b->count; ++i) nodes += (int64_t)b->inst[i].kp.nx * b->inst[i].kp.ny;
     const bool want2 = b->pair_mode == 2 || (b->pair_mode == 0 && nodes >= ((int64_t)1 << 20));
-    const int t2 = std::min(256, b->threads);
+    // two-step width: 128 columns unless the instances are wide (a 256-wide workgroup leaves
+    // half its lanes idle on a 128-wide instance; measured on the 64-instance sweep with sides
+    // 128-512: 27.7k MLUPS at 128 against 26.2k at 256, and never slower per size class)
+    int max_side = 0;
+    for (int i = 0; i < b->count; ++i) max_side = std::max(max_side, b->inst[i].kp.nx);
+    const int t2 = std::min(b->tile_set ? 256 : (max_side >= 768 ? 256 : 128), b->threads);
     const int slots2 = want2 ? device_slots_pair(b->prec, t2) : 0;
     if (slots2 > 0) {
         double best2 = 1e300;
@@ -307,6 +313,7 @@ int lbm3_batch_set_tile(lbm3_batch_t* b, int32_t side, int32_t threads, int32_t 
     }
     if (side == 0) {
         b->threads = threads;
+        b->tile_set = true;
         if (rows > 0)
             for (auto& kv : b->rows_by_side) kv.second = rows;
     } else {
