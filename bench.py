@@ -99,12 +99,13 @@ def copy_bandwidth(torch, lbm3, nbytes: int = 2 << 30, reps: int = 5) -> float:
     return 2 * nbytes / float(np.median(best)) / 1e9
 
 
-def bench_plain(torch, lbm3, w, precision: str, steps: int, warmup: int, steps_per_launch: int = 0):
+def bench_plain(torch, lbm3, w, precision: str, steps: int, warmup: int, steps_per_launch: int = 0,
+                beta_law: str = "paper"):
     """Times `steps` steps (even, so that two-step launches cover them all when used).
     Returns MLUPS and the dominant kernel's algorithmic bandwidth: state bytes read and
     written per launch over the time per launch."""
     st = torch.cuda.current_stream()
-    L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, precision=precision, stream=st)
+    L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, precision=precision, stream=st, beta_law=beta_law)
     L.init(w.rho)
     L.set_steps_per_launch(steps_per_launch)
     L.step(warmup + (warmup % 2 == 0))  # leaves the state factored after an odd first step
@@ -256,6 +257,11 @@ def main():
         for prec in ("fp64", "fp32_storage"):
             extra[f"compound_256_{prec}"] = bench_plain(torch, lbm3, w2, prec, 2000, 100)
             log(f"compound 256 {prec} {extra[f'compound_256_{prec}']}")
+        # the comparison segregation laws of Eqs. (15)-(17): the same kernels with other host
+        # constants, on the headline workload
+        laws = {law: bench_plain(torch, lbm3, w, "fp64", 100, 10, beta_law=law)
+                for law in ("spencer", "leclaire", "constant")}
+        log(f"beta laws {laws}")
         batched = bench_batched(torch, lbm3, inputs, 1000)
         log(f"batched {batched}")
         adjoint = {"janus_256": bench_adjoint(torch, lbm3, inputs, 256, 5000, 100),
@@ -314,6 +320,10 @@ def main():
             "baseline_plain_fp32_equal_nodes_mlups": round(batched["plain_equal_nodes"], 1),
             "baseline_one_launch_per_instance_mlups": round(batched["per_instance_launches"], 1)}
         line["adjoint_fp64"] = adjoint
+        line["beta_laws_fp64"] = {
+            "workload": "the headline droplet tiling, FP64, 100 timed steps per law",
+            **{law: {"mlups": round(v["mlups"], 1), "frac_of_peak": round(v["gbs"] / HBM_PEAK_GBS, 4)}
+               for law, v in laws.items()}}
     print(json.dumps(line), flush=True)
 
 

@@ -52,6 +52,26 @@ enum {
 
 enum { LBM3_PERIODIC = 0 };
 
+/* Segregation law of the recolouring, Eq. (13).  Every law has the form
+ * beta_kl = beta^0 (1 + s g_kl), with the host constants g_kl of lbm3_derived
+ * and s a function of the node's densities:
+ *   PAPER     Eqs. (18)-(20): s = C_t = min(35 rho_r rho_g rho_b / rho^3, 1),
+ *             g_kl = g(X_kl) of Eq. (20);
+ *   SPENCER   Eq. (15), as printed: s = 27 rho_r rho_g rho_b / rho^3 (at most 1),
+ *             g_rg = 0, g_rb = sin(phi_gb) - 1, g_gb = sin(phi_rb) - 1, with phi_kl
+ *             the Neumann-triangle angle of Eq. (14) (cos(phi_kl) = X_kl, clamped to
+ *             [-1, 1] when no triangle exists);
+ *   LECLAIRE  Eq. (16): s = C_t, g_kl = 0 for the pair of the largest phi_kl (the
+ *             first in the order rg, rb, gb on ties) and sin(pi - phi_max - phi_kl) - 1
+ *             for the other two; all g_kl = 0 when no triangle exists;
+ *   CONSTANT  Eq. (17): beta_kl = beta^0 (all g_kl = 0). */
+enum {
+    LBM3_BETA_PAPER = 0,
+    LBM3_BETA_SPENCER = 1,
+    LBM3_BETA_LECLAIRE = 2,
+    LBM3_BETA_CONSTANT = 3
+};
+
 /* The problem as the paper states it (Sec. 2 and the set-ups of Sec. 3):
  * lattice size, pure-fluid densities rho_k^0 (Eq. 6), interfacial tensions
  * sigma_kl (Eq. 7), per-fluid relaxation times tau_k (nu_k = (tau_k - 1/2)/3,
@@ -66,6 +86,7 @@ typedef struct {
     int32_t boundary;            /* LBM3_PERIODIC only, else LBM3_EUNSUPPORTED */
     double wall_wettability[3];  /* reserved: must be 0, else LBM3_EUNSUPPORTED */
     int32_t precision;           /* LBM3_FP64 | LBM3_FP32_STORAGE | LBM3_FP32 */
+    int32_t beta_law;            /* LBM3_BETA_*; 0 (the paper's law) when zero-initialised */
 } lbm3_params;
 
 /* Observables of the current state (the velocity is the half-force velocity of
@@ -117,8 +138,10 @@ int lbm3_destroy(lbm3_t *h);
 const char *lbm3_last_error(void);
 
 /* Host-side constants the step uses for *p (validated as in lbm3_create):
- * X[p] of Eq. (18) and g[p] = g(X) of Eq. (20) for the pairs (rg, rb, gb), and
- * nu[k] = (tau_k - 1/2)/3.  Any output pointer may be NULL.  No device work. */
+ * X[p] of Eq. (18) (= cos(phi_kl) of Eq. 14) and the segregation constants
+ * g[p] of p->beta_law (g(X) of Eq. 20 for the paper's law) for the pairs
+ * (rg, rb, gb), and nu[k] = (tau_k - 1/2)/3.  Any output pointer may be NULL.
+ * No device work. */
 int lbm3_derived(const lbm3_params *p, double X[3], double g[3], double nu[3]);
 
 /* Launch shape of the fused step: threads per workgroup (64, 128, 256 or 512;
@@ -204,7 +227,7 @@ int lbm3_batch_destroy(lbm3_batch_t *b);
  *   (else ESTATE), advances the FP64 state by nsteps (as lbm3_step) and keeps a
  *   checkpoint of the state every ckpt_every steps in device memory (nsteps >= 1
  *   a multiple of ckpt_every >= 1, else EINVAL).  LBM3_EUNSUPPORTED unless the
- *   handle is LBM3_FP64.
+ *   handle is LBM3_FP64 with the paper's segregation law (LBM3_BETA_PAPER).
  * lbm3_adjoint: given drho1_T = dL/drho_1(x, T) (host [ny][nx], finite) for the
  *   state at the end of the last recording, returns dL/dsigma in dsigma[3] (order
  *   rg, rb, gb; may be NULL) and dL/drho_k(x, 0) in drho0 (host [3][ny][nx] for

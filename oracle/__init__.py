@@ -43,7 +43,12 @@ class Problem(ctypes.Structure):
         ("sigma", ctypes.c_double * 3),
         ("tau", ctypes.c_double * 3),
         ("beta0", ctypes.c_double),
+        ("beta_law", ctypes.c_int32),
     ]
+
+
+# segregation laws: 0 the proposed law, Eqs. (18)-(20); the comparison laws of Eqs. (15)-(17)
+BETA_LAWS = {"paper": 0, "spencer": 1, "leclaire": 2, "constant": 3}
 
 
 @dataclass
@@ -54,6 +59,7 @@ class Params:
     tau: tuple = (1.0, 1.0, 1.0)
     rho0: tuple = (1.0, 1.0, 1.0)
     beta0: float = 0.7
+    beta_law: str = "paper"
 
     def c(self) -> Problem:
         p = Problem()
@@ -63,6 +69,7 @@ class Params:
             p.sigma[a] = float(self.sigma[a])
             p.tau[a] = float(self.tau[a])
         p.beta0 = float(self.beta0)
+        p.beta_law = BETA_LAWS[self.beta_law] if isinstance(self.beta_law, str) else int(self.beta_law)
         return p
 
 

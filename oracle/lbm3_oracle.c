@@ -58,12 +58,16 @@ static const double W[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 /
  * the colour gradient vanishes; n_kl = 0 and the stress term is 0 there). */
 #define GUARD_G 1e-12
 
+#define ORACLE_PI 3.14159265358979323846
+
 typedef struct {
     int32_t nx, ny;
     double rho0[3];  /* pure-fluid densities rho_k^0, Eq. (6) */
     double sigma[3]; /* sigma_rg, sigma_rb, sigma_gb */
     double tau[3];   /* per-fluid relaxation times tau_k */
     double beta0;    /* reference segregation parameter beta^0 */
+    int32_t beta_law; /* 0 proposed law, Eqs. (18)-(20); 1 Spencer, Eq. (15);
+                         2 Leclaire, Eq. (16); 3 constant beta, Eq. (17) */
 } oracle_problem;
 
 void oracle_lattice(int32_t *ex, int32_t *ey, double *w)
@@ -114,9 +118,76 @@ double oracle_g(double X)
     return sin(acos(X)) - 1.0;
 }
 
-/* beta_kl of Eq. (19) at a node with densities rho[3]. */
+/* ------------------------------------------------------------------------ */
+/* Earlier segregation laws the paper compares against, Eqs. (15)-(17).      */
+/* ------------------------------------------------------------------------ */
+
+/* phi_kl of Eq. (14): the Neumann-triangle angle opposite sigma_kl.  Reading:
+ * where no triangle exists the cosine is clamped to [-1, 1]. */
+static double neumann_phi(const oracle_problem *p, int k, int l)
+{
+    double c = oracle_X(p, k, l);
+    if (c > 1.0) c = 1.0;
+    if (c < -1.0) c = -1.0;
+    return acos(c);
+}
+
+/* Reading: the Neumann triangle exists when every cosine of Eq. (14) is below 1
+ * in magnitude by more than 1e-12 (the tolerance of g(X) above), so that the
+ * critical states (a degenerate triangle) count as having none. */
+static int neumann_triangle_exists(const oracle_problem *p)
+{
+    return fabs(oracle_X(p, 0, 1)) < 1.0 - 1e-12 && fabs(oracle_X(p, 0, 2)) < 1.0 - 1e-12 &&
+           fabs(oracle_X(p, 1, 2)) < 1.0 - 1e-12;
+}
+
+/* Eq. (15), as printed: beta_rg = beta0, beta_rb takes sin(phi_gb) and beta_gb
+ * takes sin(phi_rb), with the factor 27 rho_r rho_g rho_b / rho^3. */
+static double beta_spencer(const oracle_problem *p, int k, int l, const double *rho)
+{
+    double r = rho[0] + rho[1] + rho[2];
+    double s = 27.0 * rho[0] * rho[1] * rho[2] / (r * r * r);
+    if (k == 0 && l == 1) return p->beta0;
+    if (k == 0 && l == 2) return p->beta0 * (1.0 + s * (sin(neumann_phi(p, 1, 2)) - 1.0));
+    return p->beta0 * (1.0 + s * (sin(neumann_phi(p, 0, 2)) - 1.0));
+}
+
+/* Eq. (16): beta0 for the pair with the largest phi (reading: the first of
+ * equal maxima in the order rg, rb, gb), beta0 + beta0 C_t [sin(pi - phi_max -
+ * phi_kl) - 1] for the others; beta0 everywhere without a Neumann triangle. */
+static double beta_leclaire(const oracle_problem *p, int k, int l, const double *rho)
+{
+    if (!neumann_triangle_exists(p)) return p->beta0;
+    const int pk[3] = {0, 0, 1}, pl[3] = {1, 2, 2};
+    int kmax = 0, lmax = 1;
+    double phimax = neumann_phi(p, 0, 1);
+    for (int q = 1; q < 3; ++q) {
+        double ph = neumann_phi(p, pk[q], pl[q]);
+        if (ph > phimax) {
+            phimax = ph;
+            kmax = pk[q];
+            lmax = pl[q];
+        }
+    }
+    if (k == kmax && l == lmax) return p->beta0;
+    double r = rho[0] + rho[1] + rho[2];
+    double ct = 35.0 * rho[0] * rho[1] * rho[2] / (r * r * r);
+    if (ct > 1.0) ct = 1.0;
+    return p->beta0 + p->beta0 * ct * (sin(ORACLE_PI - phimax - neumann_phi(p, k, l)) - 1.0);
+}
+
+/* beta_kl = beta_lk at a node with densities rho[3]: Eq. (19) for the proposed
+ * law, else the comparison law selected by p->beta_law. */
 double oracle_beta(const oracle_problem *p, int k, int l, const double *rho)
 {
+    if (k > l) {
+        int t = k;
+        k = l;
+        l = t;
+    }
+    if (p->beta_law == 1) return beta_spencer(p, k, l, rho);
+    if (p->beta_law == 2) return beta_leclaire(p, k, l, rho);
+    if (p->beta_law == 3) return p->beta0; /* Eq. (17) */
     double r = rho[0] + rho[1] + rho[2];
     double ct = 35.0 * rho[0] * rho[1] * rho[2] / (r * r * r);
     if (ct > 1.0) ct = 1.0;

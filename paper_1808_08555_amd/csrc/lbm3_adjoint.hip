@@ -4,7 +4,8 @@
 // last to first: it recomputes the segment's K forward steps from its checkpoint with the
 // fused step in its tape mode, which records the densities, totals, concentration
 // gradients and force it pulled and formed at every node (20 values per node and step),
-// then takes the K reverse steps, each three node-parallel kernels reading that tape.
+// then takes the K reverse steps, each two kernels reading that tape: a node-parallel one
+// and a row-marching one.
 //
 // Notation: the population buffer B holds, at node y, the recoloured populations of y
 // before streaming; the post-streaming populations are f_{i,k}(x) = B_{i,k}(x - e_i).
@@ -57,8 +58,8 @@ struct AdjWS {
     double* rbar;   // 3   dL/drho_k accumulated (all node-local contributions)
     double* Fbar;   // 2   dL/dF
     double* Gbar;   // 6   dL/dG_p from the recolouring normals
-    double* gcbar;  // 6   dL/d(grad c_k)
-    double* sig;    // [nblocks][6] per-workgroup sums: beta part (3), stress part (3)
+    double* sig;    // [max(A1 workgroups, A2+A3 tiles)][6] per-workgroup sums: beta part (3)
+                    // from A1, stress part (3) from A2+A3
 };
 
 struct Geo {
@@ -66,19 +67,6 @@ struct Geo {
     int64_t plane, pitch;
     double sigma[3], g[3], beta0, inv_nu[3], cfac[3], guard;
 };
-
-// paired-difference form of Eq. (12) at node (x, y) of a scalar field
-__device__ __forceinline__ void grad_at(const double* __restrict__ phi, int nx, int ny, int x, int y,
-                                        double& dx, double& dy)
-{
-    const int xm = wrapi(x - 1, nx), xp = wrapi(x + 1, nx), ym = wrapi(y - 1, ny), yp = wrapi(y + 1, ny);
-    const double e = phi[(int64_t)y * nx + xp], w = phi[(int64_t)y * nx + xm];
-    const double n = phi[(int64_t)yp * nx + x], s = phi[(int64_t)ym * nx + x];
-    const double ne = phi[(int64_t)yp * nx + xp], nw = phi[(int64_t)yp * nx + xm];
-    const double se = phi[(int64_t)ym * nx + xp], sw = phi[(int64_t)ym * nx + xm];
-    dx = 3.0 * ((1.0 / 9.0) * (e - w) + (1.0 / 36.0) * ((ne - sw) + (se - nw)));
-    dy = 3.0 * ((1.0 / 9.0) * (n - s) + (1.0 / 36.0) * ((ne - sw) + (nw - se)));
-}
 
 // colour gradient, modulus, normal and concentration factor of pair p at a node
 struct PairFwd {
@@ -276,93 +264,165 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ la
     }
 }
 
-// ---- A2: reverse of the stress (force divergence transposed) and of the pair quantities
-__global__ __launch_bounds__(256) void k_adj_stress(Geo g, AdjWS w)
+// What the reverse of the stress reads at one node: dL/dF at the eight neighbours, the
+// tape's densities and concentration gradients, dL/dG from A1 and, on the tile's own
+// columns, the node-local part of dL/drho_k from A1.
+struct SfIn {
+    double Fb[2][8];  // E, W, N, S, NE, NW, SE, SW
+    double rk[3], gc[6], Gb[6], rbar[3];
+};
+
+__device__ __forceinline__ void sf_load(const Geo& g, const AdjWS& w, int64_t N, int xm, int x, int xp, int y,
+                                        bool own_col, SfIn& in)
 {
-    __shared__ double red[3][256];
-    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-    const int t = threadIdx.x;
-    double sig_st[3] = {0.0, 0.0, 0.0};
-    if (x < g.nx) {
-        const int64_t N = (int64_t)g.nx * g.ny, j = (int64_t)y * g.nx + x;
-        // T-bar = -(transpose-free form) : Tb_xx = -Dx Fbx, Tb_xy = -(Dy Fbx + Dx Fby), Tb_yy = -Dy Fby
-        double dFx_dx, dFx_dy, dFy_dx, dFy_dy;
-        grad_at(w.Fbar, g.nx, g.ny, x, y, dFx_dx, dFx_dy);
-        grad_at(w.Fbar + N, g.nx, g.ny, x, y, dFy_dx, dFy_dy);
-        const double Tbxx = -dFx_dx, Tbxy = -(dFx_dy + dFy_dx), Tbyy = -dFy_dy;
-        double rk[3], c[3], gx[3], gy[3];
-        node_fields(w, N, j, rk, c, gx, gy);
-        const double rho = rk[0] + rk[1] + rk[2];
-        double cb[3] = {0, 0, 0}, gcb[3][2] = {{0, 0}, {0, 0}, {0, 0}}, rb[3] = {0, 0, 0};
-        for (int p = 0; p < 3; ++p) {
-            const int k = PK[p], l = PL[p];
-            const PairFwd f = pair_fwd(g, p, c, gx, gy, rk);
-            if (!f.on) continue;
-            double Gbx = w.Gbar[(2 * p) * N + j], Gby = w.Gbar[(2 * p + 1) * N + j];
-            const double Q = Tbxx * f.Gy * f.Gy - Tbxy * f.Gx * f.Gy + Tbyy * f.Gx * f.Gx;
-            const double h = g.sigma[p] * f.C * f.im;
-            Gbx += h * (2.0 * Tbyy * f.Gx - Tbxy * f.Gy);
-            Gby += h * (2.0 * Tbxx * f.Gy - Tbxy * f.Gx);
-            const double mb = -Q * g.sigma[p] * f.C * (f.im * f.im);
-            Gbx += mb * f.Gx * f.im;
-            Gby += mb * f.Gy * f.im;
-            sig_st[p] = Q * f.C * f.im;
-            if (f.unclipped) {
-                const double Cb = Q * g.sigma[p] * f.im;
-                rb[k] += Cb * g.cfac[p] * rk[l];
-                rb[l] += Cb * g.cfac[p] * rk[k];
-            }
-            // G = c_l grad c_k - c_k grad c_l
-            cb[l] += Gbx * gx[k] + Gby * gy[k];
-            cb[k] -= Gbx * gx[l] + Gby * gy[l];
-            gcb[k][0] += c[l] * Gbx;
-            gcb[k][1] += c[l] * Gby;
-            gcb[l][0] -= c[k] * Gbx;
-            gcb[l][1] -= c[k] * Gby;
-        }
-        double cr = 0.0;
-        for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
-        const double irho = 1.0 / rho;
-        for (int k = 0; k < 3; ++k) w.rbar[k * N + j] += rb[k] + cb[k] * irho - cr * (irho * irho);
-        for (int k = 0; k < 3; ++k) {
-            w.gcbar[(2 * k) * N + j] = gcb[k][0];
-            w.gcbar[(2 * k + 1) * N + j] = gcb[k][1];
-        }
+    const int ym = wrapi(y - 1, g.ny), yp = wrapi(y + 1, g.ny);
+    const int64_t r0 = (int64_t)y * g.nx, rn = (int64_t)yp * g.nx, rs = (int64_t)ym * g.nx;
+    const int64_t at[8] = {r0 + xp, r0 + xm, rn + x, rs + x, rn + xp, rn + xm, rs + xp, rs + xm};
+    for (int c = 0; c < 2; ++c)
+        for (int q = 0; q < 8; ++q) in.Fb[c][q] = w.Fbar[c * N + at[q]];
+    const int64_t jn = r0 + x;
+    for (int k = 0; k < 3; ++k) in.rk[k] = w.rho[k * N + jn];
+    for (int q = 0; q < 6; ++q) {
+        in.gc[q] = w.gc[q * N + jn];
+        in.Gb[q] = w.Gbar[q * N + jn];
     }
-    for (int p = 0; p < 3; ++p) red[p][t] = sig_st[p];
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (t < h)
-            for (int p = 0; p < 3; ++p) red[p][t] += red[p][t + h];
-        __syncthreads();
-    }
-    if (t < 3) {
-        const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-        w.sig[b * 6 + 3 + t] += red[t][0];
-    }
+    for (int k = 0; k < 3; ++k) in.rbar[k] = own_col ? w.rbar[k * N + jn] : 0.0;
 }
 
-// ---- A3: reverse of the gradient (c-bar = -div gcbar) and of the densities; with the
-// totals' part written by A1 this completes the adjoint state of the previous step
-__global__ __launch_bounds__(256) void k_adj_final(Geo g, AdjWS w, double* __restrict__ lam)
+// paired-difference form of Eq. (12) from the eight neighbours of a node
+__device__ __forceinline__ void grad8(const double (&v)[8], double& dx, double& dy)
 {
-    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-    if (x >= g.nx) return;
-    const int64_t N = (int64_t)g.nx * g.ny, j = (int64_t)y * g.nx + x;
-    double rk[3];
-    for (int k = 0; k < 3; ++k) rk[k] = w.rho[k * N + j];
-    const double rho = rk[0] + rk[1] + rk[2];
-    double cb[3];
-    for (int k = 0; k < 3; ++k) {
-        double a, b, dum;
-        grad_at(w.gcbar + (2 * k) * N, g.nx, g.ny, x, y, a, dum);
-        grad_at(w.gcbar + (2 * k + 1) * N, g.nx, g.ny, x, y, dum, b);
-        cb[k] = -(a + b);
+    dx = 3.0 * ((1.0 / 9.0) * (v[0] - v[1]) + (1.0 / 36.0) * ((v[4] - v[7]) + (v[6] - v[5])));
+    dy = 3.0 * ((1.0 / 9.0) * (v[2] - v[3]) + (1.0 / 36.0) * ((v[4] - v[7]) + (v[5] - v[6])));
+}
+
+// ---- A2 + A3 in one pass: the reverse of the stress and the pair quantities, whose
+// result dL/d(grad c_k) then stays in LDS, and the reverse of the gradient (c-bar = -div
+// of it) and of the densities.  With the totals' part written by A1 this completes the
+// adjoint state of the previous step.
+//
+// A workgroup marches one tile: `cols` columns from x0 and `rows` rows from y0, lane t at
+// column x0 - 1 + t (one halo column each side).  Iteration j first forms dL/d(grad c_k)
+// on row y0 - 1 + j for every lane, halo lanes and the halo rows above and below the tile
+// included, into slot j mod 4 of an LDS ring; after one barrier it completes row
+// y0 + j - 2, whose rows above and below are then in the ring.  The row written next is
+// never one still being read (four slots for a three-row stencil), so one barrier per row
+// suffices.  The next row's inputs are loaded before the barrier, so that their latency
+// overlaps the barrier and the completion.  Only the tile's own nodes add to dL/dsigma.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_adj_sf(Geo g, AdjWS w, const Tile* __restrict__ tiles,
+                                               double* __restrict__ lam)
+{
+    __shared__ double ring[4][6][NT];
+    const Tile tl = tiles[blockIdx.x];
+    const int t = threadIdx.x;
+    const int64_t N = (int64_t)g.nx * g.ny;
+    const bool lane_on = t < tl.cols + 2;
+    const bool own_col = t >= 1 && t <= tl.cols;
+    const int x = wrapi(tl.x0 - 1 + t, g.nx);
+    const int xm = wrapi(x - 1, g.nx), xp = wrapi(x + 1, g.nx);
+    double sig_st[3] = {0.0, 0.0, 0.0};
+    // the densities and the completed node-local part of dL/drho_k of the row that the
+    // next iteration completes
+    double rk_prev[3] = {0.0, 0.0, 0.0}, part_prev[3] = {0.0, 0.0, 0.0};
+    SfIn in;
+    if (lane_on) sf_load(g, w, N, xm, x, xp, wrapi(tl.y0 - 1, g.ny), own_col, in);
+    for (int j = 0; j < tl.rows + 2; ++j) {
+        double rk[3] = {0.0, 0.0, 0.0}, part[3] = {0.0, 0.0, 0.0};
+        if (lane_on) {
+            // T-bar = -(transpose-free form): Tb_xx = -Dx Fbx, Tb_xy = -(Dy Fbx + Dx Fby), Tb_yy = -Dy Fby
+            double dFx_dx, dFx_dy, dFy_dx, dFy_dy;
+            grad8(in.Fb[0], dFx_dx, dFx_dy);
+            grad8(in.Fb[1], dFy_dx, dFy_dy);
+            const double Tbxx = -dFx_dx, Tbxy = -(dFx_dy + dFy_dx), Tbyy = -dFy_dy;
+            double c[3], gx[3], gy[3];
+            for (int k = 0; k < 3; ++k) rk[k] = in.rk[k];
+            const double rho = rk[0] + rk[1] + rk[2];
+            const double ir = 1.0 / rho;
+            for (int k = 0; k < 3; ++k) {
+                c[k] = rk[k] * ir;
+                gx[k] = in.gc[2 * k];
+                gy[k] = in.gc[2 * k + 1];
+            }
+            double cb[3] = {0, 0, 0}, gcb[3][2] = {{0, 0}, {0, 0}, {0, 0}}, rb[3] = {0, 0, 0};
+            const bool own = own_col && j >= 1 && j <= tl.rows;
+            for (int p = 0; p < 3; ++p) {
+                const int k = PK[p], l = PL[p];
+                const PairFwd f = pair_fwd(g, p, c, gx, gy, rk);
+                if (!f.on) continue;
+                double Gbx = in.Gb[2 * p], Gby = in.Gb[2 * p + 1];
+                const double Q = Tbxx * f.Gy * f.Gy - Tbxy * f.Gx * f.Gy + Tbyy * f.Gx * f.Gx;
+                const double h = g.sigma[p] * f.C * f.im;
+                Gbx += h * (2.0 * Tbyy * f.Gx - Tbxy * f.Gy);
+                Gby += h * (2.0 * Tbxx * f.Gy - Tbxy * f.Gx);
+                const double mb = -Q * g.sigma[p] * f.C * (f.im * f.im);
+                Gbx += mb * f.Gx * f.im;
+                Gby += mb * f.Gy * f.im;
+                if (own) sig_st[p] += Q * f.C * f.im;
+                if (f.unclipped) {
+                    const double Cb = Q * g.sigma[p] * f.im;
+                    rb[k] += Cb * g.cfac[p] * rk[l];
+                    rb[l] += Cb * g.cfac[p] * rk[k];
+                }
+                // G = c_l grad c_k - c_k grad c_l
+                cb[l] += Gbx * gx[k] + Gby * gy[k];
+                cb[k] -= Gbx * gx[l] + Gby * gy[l];
+                gcb[k][0] += c[l] * Gbx;
+                gcb[k][1] += c[l] * Gby;
+                gcb[l][0] -= c[k] * Gbx;
+                gcb[l][1] -= c[k] * Gby;
+            }
+            for (int k = 0; k < 3; ++k) {
+                ring[j & 3][2 * k][t] = gcb[k][0];
+                ring[j & 3][2 * k + 1][t] = gcb[k][1];
+            }
+            if (own_col) {
+                double cr = 0.0;
+                for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
+                const double irho = 1.0 / rho;
+                for (int k = 0; k < 3; ++k) part[k] = in.rbar[k] + (rb[k] + cb[k] * irho - cr * (irho * irho));
+            }
+            if (j + 1 < tl.rows + 2) sf_load(g, w, N, xm, x, xp, wrapi(tl.y0 + j, g.ny), own_col, in);
+        }
+        __syncthreads();
+        if (own_col && j >= 2) {
+            // row y0 + j - 2: its south, own and north rows sit in slots j - 2, j - 1, j
+            const int yc = wrapi(tl.y0 + j - 2, g.ny);
+            const double(*S)[NT] = ring[(j - 2) & 3];
+            const double(*C)[NT] = ring[(j - 1) & 3];
+            const double(*U)[NT] = ring[j & 3];
+            double cb[3];
+            for (int k = 0; k < 3; ++k) {
+                const int qx = 2 * k, qy = 2 * k + 1;
+                const double a = 3.0 * ((1.0 / 9.0) * (C[qx][t + 1] - C[qx][t - 1]) +
+                                        (1.0 / 36.0) * ((U[qx][t + 1] - S[qx][t - 1]) + (S[qx][t + 1] - U[qx][t - 1])));
+                const double b = 3.0 * ((1.0 / 9.0) * (U[qy][t] - S[qy][t]) +
+                                        (1.0 / 36.0) * ((U[qy][t + 1] - S[qy][t - 1]) + (U[qy][t - 1] - S[qy][t + 1])));
+                cb[k] = -(a + b);
+            }
+            const double rho = rk_prev[0] + rk_prev[1] + rk_prev[2];
+            double cr = 0.0;
+            for (int k = 0; k < 3; ++k) cr += cb[k] * rk_prev[k];
+            const double irho = 1.0 / rho;
+            const int64_t jc = (int64_t)yc * g.nx + x;
+            for (int k = 0; k < 3; ++k) lam[(9 + k) * N + jc] = part_prev[k] + cb[k] * irho - cr * (irho * irho);
+        }
+        for (int k = 0; k < 3; ++k) {
+            rk_prev[k] = rk[k];
+            part_prev[k] = part[k];
+        }
     }
-    double cr = 0.0;
-    for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
-    const double irho = 1.0 / rho;
-    for (int k = 0; k < 3; ++k) lam[(9 + k) * N + j] = w.rbar[k * N + j] + cb[k] * irho - cr * (irho * irho);
+    // per-workgroup sums of the stress part of dL/dsigma (the ring is free again)
+    __syncthreads();
+    double* red = &ring[0][0][0];
+    for (int p = 0; p < 3; ++p) red[p * NT + t] = sig_st[p];
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if (t < h)
+            for (int p = 0; p < 3; ++p) red[p * NT + t] += red[p * NT + t + h];
+        __syncthreads();
+    }
+    if (t < 3) w.sig[(int64_t)blockIdx.x * 6 + 3 + t] += red[t * NT];
 }
 
 // The adjoint state is kept factored per node as (dL/df_i, dL/drho_k), 12 values: f_{i,k}
@@ -387,6 +447,31 @@ __global__ __launch_bounds__(256) void k_adj_rho0(const double* __restrict__ lam
         double s = 0.0;
         for (int i = 0; i < 9; ++i) s += wgt(i) * (lam[i * N + j] + lam[(9 + k) * N + j]);
         out[k * N + j] = s;
+    }
+}
+
+// Width of the fused A2 + A3 workgroup by lattice width: narrow strips keep small
+// lattices' tiles numerous enough to fill the device (measured at 256^2: 64 lanes beat
+// 128 by 3%; at 2048^2 256 lanes).
+int sf_width(int nx) { return nx >= 1024 ? 256 : 64; }
+
+int sf_occupancy(int nt)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (nt) {
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_sf<64>, 64, 0); break;
+        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_sf<256>, 256, 0); break;
+        default: break;
+    }
+    return e == hipSuccess ? nb : 0;
+}
+
+void launch_sf(int nt, int ntiles, hipStream_t q, const Geo& g, const AdjWS& w, const Tile* tiles, double* lam)
+{
+    switch (nt) {
+        case 64: hipLaunchKernelGGL(k_adj_sf<64>, dim3(ntiles), dim3(64), 0, q, g, w, tiles, lam); break;
+        default: hipLaunchKernelGGL(k_adj_sf<256>, dim3(ntiles), dim3(256), 0, q, g, w, tiles, lam); break;
     }
 }
 
@@ -470,6 +555,10 @@ int lbm3_adjoint_record(lbm3_t* h, int64_t nsteps, int32_t ckpt_every)
         set_error("the adjoint is provided for LBM3_FP64 only");
         return LBM3_EUNSUPPORTED;
     }
+    if (h->p.beta_law != LBM3_BETA_PAPER) {
+        set_error("the adjoint is provided for the paper's segregation law (LBM3_BETA_PAPER) only");
+        return LBM3_EUNSUPPORTED;
+    }
     if (!h->ready || h->step != 0 || !h->init_at_rest) {
         set_error("lbm3_adjoint_record needs the state set by lbm3_init_fields(rho, NULL) at step 0");
         return LBM3_ESTATE;
@@ -528,18 +617,30 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     const Geo g = geo_of(kp);
     const dim3 grid((kp.nx + 255) / 256, kp.ny), blk(256);
     const int64_t nblocks = (int64_t)grid.x * grid.y;
+    // tiles of the fused A2 + A3 pass: strips of at most sf_width - 2 columns (one halo
+    // column each side), rows fitted to the resident workgroups
+    const int sfw = sf_width(kp.nx);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 1;
+    const int sf_rows = auto_rows(kp.nx, kp.ny, sfw, std::max(1, sf_occupancy(sfw)) * std::max(cus, 1), 8, 1);
+    std::vector<Tile> sf_plan;
+    plan_lattice(0, kp.nx, kp.ny, sfw, sf_rows, 8, sf_plan, 1);
+    const std::vector<Tile> sf_tiles = xcd_order(sf_plan, 8);
+    const int sf_ntiles = (int)sf_tiles.size();
+    const int64_t nsig = std::max<int64_t>(nblocks, sf_ntiles);
     const size_t sbytes = (size_t)kp.span * sizeof(double);
     const size_t fbytes = (size_t)kp.fpitch * kp.ny * sizeof(double);
     const size_t tbytes = (size_t)kTapeFields * N * sizeof(double);
     const int K = h->tape_every;
     const int64_t nseg = h->tape_steps / K;
-    // workspace: 17 adjoint fields of N doubles, two factored adjoint states (12 fields), two
+    // workspace: 11 adjoint fields of N doubles, two factored adjoint states (12 fields), two
     // forward state buffers, the tape of K steps (20 fields each), the dL/dsigma partial
-    // sums, dL/drho_1(T)
-    const size_t fields = (size_t)(3 + 2 + 6 + 6) * N;
+    // sums, dL/drho_1(T), the fused pass's tiles
+    const size_t fields = (size_t)(3 + 2 + 6) * N;
     const size_t lbytes = (size_t)12 * N * sizeof(double);
     const size_t need = fields * sizeof(double) + 2 * lbytes + 2 * sbytes + (size_t)K * tbytes +
-                        (size_t)nblocks * 6 * sizeof(double) + N * sizeof(double);
+                        (size_t)nsig * 6 * sizeof(double) + N * sizeof(double) + sf_tiles.size() * sizeof(Tile);
     int rc = ensure_ws(h, need);
     if (rc) return rc;
     double* d = (double*)h->adj_ws;
@@ -548,14 +649,14 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     w.rbar = d;
     w.Fbar = w.rbar + 3 * N;
     w.Gbar = w.Fbar + 2 * N;
-    w.gcbar = w.Gbar + 6 * N;
     double* lam[2];
-    lam[0] = w.gcbar + 6 * N;
+    lam[0] = w.Gbar + 6 * N;
     lam[1] = lam[0] + 12 * N;
     char* fwd[2] = {(char*)(lam[1] + 12 * N), (char*)(lam[1] + 12 * N) + sbytes};
     double* tape = (double*)(fwd[1] + sbytes);
     w.sig = tape + (size_t)K * kTapeFields * N;
-    double* gT = w.sig + nblocks * 6;
+    double* gT = w.sig + nsig * 6;
+    Tile* dsf = (Tile*)(gT + N);
     // The sweep runs on the handle's own adjoint stream (graph capture needs a stream other
     // than the null stream), ordered after the work already on the handle's stream.
     hipError_t e = hipSuccess;
@@ -565,8 +666,10 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     if (e != hipSuccess) return hip_fail(e, "adjoint stream set-up");
     hipStream_t st = h->adj_stream;
     e = hipStreamWaitEvent(st, h->adj_event, 0);
-    if (e == hipSuccess) e = hipMemsetAsync(w.sig, 0, (size_t)nblocks * 6 * sizeof(double), st);
+    if (e == hipSuccess) e = hipMemsetAsync(w.sig, 0, (size_t)nsig * 6 * sizeof(double), st);
     if (e == hipSuccess) e = hipMemcpyAsync(gT, drho1_T, N * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dsf, sf_tiles.data(), sf_tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "adjoint set-up");
     int cl = 0;
     hipLaunchKernelGGL(k_adj_seed, grid, blk, 0, st, gT, g, lam[cl]);
@@ -588,8 +691,7 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
             wj.gc = wj.rho + 12 * N;
             wj.F = wj.rho + 18 * N;
             hipLaunchKernelGGL(k_adj_local, grid, blk, 0, q, (const double*)lam[c], g, wj, lam[c ^ 1]);
-            hipLaunchKernelGGL(k_adj_stress, grid, blk, 0, q, g, wj);
-            hipLaunchKernelGGL(k_adj_final, grid, blk, 0, q, g, wj, lam[c ^ 1]);
+            launch_sf(sfw, sf_ntiles, q, g, wj, dsf, lam[c ^ 1]);
             c ^= 1;
             r = hipGetLastError();
         }
@@ -629,7 +731,7 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     }
     double* r0 = (double*)fwd[0];  // reuse: dL/drho_k(x, 0)
     hipLaunchKernelGGL(k_adj_rho0, grid, blk, 0, st, (const double*)lam[cl], g, r0);
-    std::vector<double> sig((size_t)nblocks * 6);
+    std::vector<double> sig((size_t)nsig * 6);
     e = hipGetLastError();
     if (e == hipSuccess && drho0) e = hipMemcpyAsync(drho0, r0, 3 * N * sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
@@ -640,7 +742,7 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     if (e != hipSuccess) return hip_fail(e, "adjoint results");
     // sigma: stress part directly; segregation part through g'(X_p) dX_p/dsigma_q
     double Sb[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t b = 0; b < nblocks; ++b)
+    for (int64_t b = 0; b < nsig; ++b)
         for (int a = 0; a < 6; ++a) Sb[a] += sig[b * 6 + a];
     double ds[3] = {Sb[3], Sb[4], Sb[5]};
     const double* sgm = h->p.sigma;

@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/lbm3.h: parameter validation, the FP64
 // host precompute of the segregation law, device buffers and stream-ordered launches.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -77,6 +78,10 @@ int validate_params(const lbm3_params* p)
         set_error("precision must be LBM3_FP64, LBM3_FP32_STORAGE or LBM3_FP32");
         return LBM3_EINVAL;
     }
+    if (p->beta_law < LBM3_BETA_PAPER || p->beta_law > LBM3_BETA_CONSTANT) {
+        set_error("beta_law must be LBM3_BETA_PAPER, _SPENCER, _LECLAIRE or _CONSTANT (got %d)", p->beta_law);
+        return LBM3_EINVAL;
+    }
     return LBM3_OK;
 }
 
@@ -103,9 +108,44 @@ static double seg_g(double X)
     return X < 0.0 ? 1.0 - s : s - 1.0;
 }
 
+// sin(phi) for the Neumann-triangle angle with cos(phi) = X (Eq. 14), X clamped to [-1, 1]
+static double sin_phi(double X)
+{
+    const double c = std::min(1.0, std::max(-1.0, X));
+    return std::sqrt((1.0 - c) * (1.0 + c));
+}
+
+// g_kl and the coefficient of s of the comparison laws (Eqs. 15-17), from X_kl = cos(phi_kl).
+// A Neumann triangle exists when every |X_kl| is below 1 by more than the 1e-12 of seg_g:
+// the critical states (|X| = 1, a degenerate triangle) count as having none.
+static void comparison_law(int law, const double X[3], double g[3], double* ct_coef)
+{
+    *ct_coef = 35.0;
+    for (int q = 0; q < 3; ++q) g[q] = 0.0;
+    if (law == LBM3_BETA_SPENCER) {
+        // as printed: beta_rb takes sin(phi_gb) and beta_gb takes sin(phi_rb); beta_rg = beta0
+        g[1] = sin_phi(X[2]) - 1.0;
+        g[2] = sin_phi(X[1]) - 1.0;
+        *ct_coef = 27.0;
+    } else if (law == LBM3_BETA_LECLAIRE) {
+        bool triangle = true;
+        for (int q = 0; q < 3; ++q) triangle = triangle && std::fabs(X[q]) < 1.0 - 1e-12;
+        if (!triangle) return;  // beta_kl = beta0
+        double phi[3];
+        int qmax = 0;
+        for (int q = 0; q < 3; ++q) {
+            phi[q] = std::acos(X[q]);
+            if (phi[q] > phi[qmax]) qmax = q;  // the first of equal maxima
+        }
+        for (int q = 0; q < 3; ++q)
+            if (q != qmax) g[q] = std::sin(M_PI - phi[qmax] - phi[q]) - 1.0;
+    }
+    // LBM3_BETA_CONSTANT: all g_kl = 0
+}
+
 void derive(const lbm3_params* p, KParams* kp, double X[3], double g[3], double nu[3])
 {
-    double Xl[3], gl[3], nul[3];
+    double Xl[3], gl[3], nul[3], ct_coef = 35.0;
     for (int q = 0; q < 3; ++q) {
         const int k = PK[q], l = PL[q], m = 3 - k - l;
         const double smk = p->sigma[pair_index(m, k)], sml = p->sigma[pair_index(m, l)];
@@ -114,6 +154,7 @@ void derive(const lbm3_params* p, KParams* kp, double X[3], double g[3], double 
         gl[q] = seg_g(Xl[q]);
         nul[q] = (p->tau[q] - 0.5) / 3.0;  // Eq. (11) with c_s^2 = 1/3
     }
+    if (p->beta_law != LBM3_BETA_PAPER) comparison_law(p->beta_law, Xl, gl, &ct_coef);
     if (X)
         for (int q = 0; q < 3; ++q) X[q] = Xl[q];
     if (g)
@@ -137,6 +178,7 @@ void derive(const lbm3_params* p, KParams* kp, double X[3], double g[3], double 
             kp->cfac[q] = 1e6 / (p->rho0[PK[q]] * p->rho0[PL[q]]);
         }
         kp->beta0 = p->beta0 == 0.0 ? 0.7 : p->beta0;
+        kp->ct_coef = ct_coef;
         kp->guard = p->precision == LBM3_FP32 ? 1e-6 : 1e-12;
     }
 }

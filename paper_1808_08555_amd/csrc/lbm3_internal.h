@@ -20,8 +20,9 @@ struct KParams {
     int64_t fpitch;     // row pitch of the factored layout (18 planes, rows interleaved)
     int64_t span;       // elements of one state buffer (room for 27 planes)
     double sigma[3];    // sigma_kl per pair
-    double g[3];        // g(X_kl) of the segregation law, Eq. (20)
+    double g[3];        // g_kl of the segregation law: beta_kl = beta0 (1 + s g_kl)
     double beta0;       // reference segregation parameter, Eq. (19)
+    double ct_coef;     // s = min(ct_coef rho_r rho_g rho_b / rho^3, 1): 35 (Eqs. 16, 19), 27 (Eq. 15)
     double inv_nu[3];   // 1/nu_k, nu_k = (tau_k - 1/2)/3
     double cfac[3];     // 1e6 / (rho0_k rho0_l) per pair, Eq. (6)
     double guard;       // |G_kl| at or below which n_kl = 0 and the stress is 0

@@ -281,7 +281,7 @@ __device__ __forceinline__ void densities_f27(Get v, C (&r0)[3], C (&f0)[9])
 
 template <typename C>
 struct StepConsts {
-    C sig[3], g[3], beta0, inv_nu[3], cfac[3], guard2;
+    C sig[3], g[3], beta0, ct_coef, inv_nu[3], cfac[3], guard2;
     __device__ explicit StepConsts(const KParams& kp)
     {
         for (int p = 0; p < 3; ++p) {
@@ -291,11 +291,13 @@ struct StepConsts {
             cfac[p] = C(kp.cfac[p]);
         }
         beta0 = C(kp.beta0);
+        ct_coef = C(kp.ct_coef);
         guard2 = C(kp.guard) * C(kp.guard);
     }
 };
 
-// Collision (Eqs. 1-3, 8-11) and the recolouring factors (Eqs. 13, 19, 20) at one node,
+// Collision (Eqs. 1-3, 8-11) and the recolouring factors (Eqs. 13, 19, 20, or a
+// comparison law of Eqs. 15-17 through g_kl and ct_coef) at one node,
 // given the totals f[9], densities rk[3], pair normals n[6] (pairs rg, rb, gb) and the
 // force.  Returns f_dag, c_k, V_k (V[2k], V[2k+1]) and u, rho u for observables.
 template <typename C>
@@ -327,8 +329,8 @@ __device__ __forceinline__ void collide_recolour(const C (&f)[9], const C (&rk)[
         const C phi = wgt<C>(i) * pref * (C(3) * (eF - uF) + C(9) * eu * eF);
         fd[i] = f[i] - (f[i] - feq) * itau + phi;
     }
-    // C_t and beta_kl of Eq. (19); a_p = beta_p rho_k rho_l / rho
-    C ct = C(35) * rk[0] * rk[1] * rk[2] * (irho * irho * irho);
+    // C_t and beta_kl of Eq. (19) (or the law's own s and g_kl); a_p = beta_p rho_k rho_l / rho
+    C ct = K.ct_coef * rk[0] * rk[1] * rk[2] * (irho * irho * irho);
     ct = ct < C(1) ? ct : C(1);
     const C a0 = K.beta0 * (C(1) + ct * K.g[0]) * (rk[0] * rk[1]) * irho;
     const C a1 = K.beta0 * (C(1) + ct * K.g[1]) * (rk[0] * rk[2]) * irho;

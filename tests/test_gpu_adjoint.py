@@ -77,6 +77,39 @@ def test_adjoint_matches_oracle_finite_differences(steps, every):
         assert abs(dr[k, y, x] - fd) <= 1e-5 * max(1e-3, abs(fd))
 
 
+def test_adjoint_wide_lattice_many_tiles_against_oracle_finite_differences():
+    """1030 x 12 (wider than 1024, not a multiple of 16): the reverse sweep's row-marching pass
+    runs as several strips and row segments.  Wavy vertical bands of the three fluids put
+    interfaces across every strip and segment boundary and across the periodic seam; the
+    probed nodes sit on strip boundaries (every 206 columns) and on the seam.  The loss here
+    is about 400, so central differences at h = 1e-6 would carry about 4e-8 of rounding
+    noise (eps L / h); h = 1e-4 keeps both that and the O(h^2) error near 1e-10."""
+    nx, ny, h, steps, every = 1030, 12, 1e-4, 12, 4
+    tau = (0.7, 0.8, 0.9)
+    y, x = np.mgrid[0:ny, 0:nx]
+    lab = ((x + np.round(2.5 * np.sin(2 * np.pi * y / ny)).astype(int)) // 7) % 3
+    rho0 = inputs.rho_from_labels(lab)
+    target = inputs.loss_target(rho0[0], seed=1030)
+    loss, ds, dr = gpu_gradient(rho0, target, SIGMA, tau, steps, every)
+    assert abs(loss / oracle_loss(rho0, target, SIGMA, tau, steps) - 1) < 1e-12
+    for q in range(3):
+        sp, sm = list(SIGMA), list(SIGMA)
+        sp[q] += h
+        sm[q] -= h
+        fd = (oracle_loss(rho0, target, sp, tau, steps) - oracle_loss(rho0, target, sm, tau, steps)) / (2 * h)
+        print(f"dL/dsigma[{q}] adjoint {ds[q]:.10e} fd {fd:.10e}")
+        assert abs(ds[q] - fd) <= 1e-5 * max(1e-3, abs(fd))
+    nodes = [(0, 0), (5, 1029), (11, 205), (3, 206), (7, 411), (8, 412), (2, 618), (10, 824), (6, 515)]
+    for (yy, xx) in nodes:
+        k = int(lab[yy, xx])
+        rp, rm = rho0.copy(), rho0.copy()
+        rp[k, yy, xx] += h
+        rm[k, yy, xx] -= h
+        fd = (oracle_loss(rp, target, SIGMA, tau, steps) - oracle_loss(rm, target, SIGMA, tau, steps)) / (2 * h)
+        print(f"dL/drho0[{k},{yy},{xx}] adjoint {dr[k, yy, xx]:.10e} fd {fd:.10e}")
+        assert abs(dr[k, yy, xx] - fd) <= 1e-5 * max(1e-3, abs(fd))
+
+
 def test_adjoint_taylor_remainder_is_second_order():
     """With the GPU forward alone: L(rho0 + e d) - L(rho0) - e <grad, d> shrinks as e^2
     (d perturbs each node's own fluid)."""

@@ -1,0 +1,115 @@
+"""The comparison segregation laws of Sec. 2 (Eqs. 15-17) on the GPU, through the C ABI,
+against the FP64 oracle: one step per launch, two steps per launch, each precision, and a
+batch whose instances use different laws."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1808_08555_amd import inputs, lbm3
+
+pytestmark = pytest.mark.gpu
+
+LAWS = ["spencer", "leclaire", "constant"]
+SIG, TAU = (0.011, 0.013, 0.017), (0.7, 1.0, 1.3)  # a Neumann triangle with distinct angles
+
+
+def _gpu(nx, ny, rho, steps, law, sigma=SIG, tau=TAU, precision="fp64", tile=None, mode=0):
+    L = lbm3.Lattice(nx, ny, sigma, tau, precision=precision, beta_law=law).init(rho)
+    try:
+        if tile:
+            L.set_tile(*tile)
+        if mode:
+            L.set_steps_per_launch(mode)
+        return L.step(steps).state()
+    finally:
+        L.close()
+
+
+def _oracle(nx, ny, rho, steps, law, sigma=SIG, tau=TAU):
+    p = oracle.Params(nx, ny, sigma, tau, beta_law=law)
+    return oracle.run(p, oracle.init(p, rho), steps)
+
+
+@pytest.mark.parametrize("law", LAWS)
+def test_parity_two_droplets_64_1000_steps(law):
+    """The tangent disks of the 64^2 case (triple junctions, where 0 < C_t < 1), 1000 steps:
+    the total distribution to 1e-11, the coloured populations to 1e-9 (the round-off
+    amplification of colour traces, as for the paper's law), and a result that differs
+    from the paper's law (the switch acts)."""
+    w = inputs.two_droplets_64()
+    g = _gpu(64, 64, w.rho, 1000, law, w.sigma, w.tau)
+    o = _oracle(64, 64, w.rho, 1000, law, w.sigma, w.tau)
+    d_tot, d_col = float(np.abs(g.sum(0) - o.sum(0)).max()), float(np.abs(g - o).max())
+    print(f"{law}: |df_i| {d_tot:.2e} |df_ik| {d_col:.2e}")
+    assert d_tot <= 1e-11 and d_col <= 1e-9
+    paper = _gpu(64, 64, w.rho, 1000, "paper", w.sigma, w.tau)
+    assert np.abs(paper - g).max() > 1e-6
+
+
+@pytest.mark.parametrize("law", LAWS)
+@pytest.mark.parametrize("tile", [(64, 16), (256, 0)])
+def test_parity_ragged_random_mixture(law, tile):
+    """301 x 83 random mixtures (three fluids at most nodes: C_t both below and at its cap),
+    several strips and ragged row segments, 12 steps, to 1e-11."""
+    rho = inputs.random_mixture(301, 83, 9, tiny_fraction=0.05)
+    g = _gpu(301, 83, rho, 12, law, tile=tile)
+    o = _oracle(301, 83, rho, 12, law)
+    assert np.abs(g - o).max() <= 1e-11
+
+
+@pytest.mark.parametrize("law", LAWS)
+@pytest.mark.parametrize("precision,rtol", [("fp32_storage", 2e-6), ("fp32", 2e-5)])
+def test_parity_reduced_precision(law, precision, rtol):
+    """As for the paper's law: a 48^2 double droplet, 10 steps, relative to max |f|."""
+    w = inputs.double_droplet(48, 9.0, 1.0, 1.2, seed=4, steps=0)
+    g = _gpu(48, 48, w.rho, 10, law, w.sigma, w.tau, precision=precision)
+    o = _oracle(48, 48, w.rho, 10, law, w.sigma, w.tau)
+    err = np.abs(g - o).max() / np.abs(o).max()
+    print(law, precision, "max rel |df|:", err)
+    assert err <= rtol
+
+
+@pytest.mark.parametrize("law", LAWS)
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_storage"])
+def test_two_step_pass_equals_single_steps_bitwise(law, precision):
+    nx, ny = 97, 130
+    rho = inputs.random_mixture(nx, ny, 5, tiny_fraction=0.0)
+    a = _gpu(nx, ny, rho, 12, law, precision=precision, tile=(64, 9), mode=1)
+    b = _gpu(nx, ny, rho, 12, law, precision=precision, tile=(64, 9), mode=2)
+    assert np.isfinite(a).all() and np.array_equal(a, b)
+
+
+def test_batch_of_mixed_laws_matches_plain_lattices_bitwise():
+    """Four instances, one per law, in one batch (double droplets of different sizes, so
+    triple junctions): 40 steps (two graph launches), densities equal to each plain
+    lattice run alone, and to the oracle."""
+    sides = [40, 52, 33, 64]
+    sizes = [(n, n) for n in sides]
+    laws = ["paper"] + LAWS
+    rhos = [inputs.double_droplet(n, n / 5.0, 1.0, 1.3, seed=30 + i, steps=0).rho for i, n in enumerate(sides)]
+    ps = [lbm3.make_params(nx, ny, SIG, TAU, beta_law=law) for (nx, ny), law in zip(sizes, laws)]
+    b = lbm3.lbm3_batch_create(ps)
+    try:
+        for i, rho in enumerate(rhos):
+            lbm3.lbm3_batch_init_fields(b, i, rho)
+        lbm3.lbm3_batch_step(b, 40)
+        for i, ((nx, ny), law) in enumerate(zip(sizes, laws)):
+            _, rho = lbm3.lbm3_batch_observables(b, i, nx, ny, want_rho=True)
+            L = lbm3.Lattice(nx, ny, SIG, TAU, beta_law=law).init(rhos[i]).step(40)
+            ref = L.densities()
+            L.close()
+            assert np.array_equal(rho, ref), law
+            o = _oracle(nx, ny, rhos[i], 40, law)
+            assert np.abs(rho - o.sum(axis=1)).max() <= 1e-11, law
+    finally:
+        lbm3.lbm3_batch_destroy(b)
+
+
+def test_adjoint_refuses_other_laws():
+    L = lbm3.Lattice(16, 16, SIG, TAU, beta_law="spencer").init(inputs.random_mixture(16, 16, 1))
+    try:
+        with pytest.raises(lbm3.Lbm3Error) as e:
+            lbm3.lbm3_adjoint_record(L.h, 2, 1)
+        assert e.value.code == lbm3.LBM3_EUNSUPPORTED
+    finally:
+        L.close()
