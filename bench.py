@@ -100,12 +100,13 @@ def copy_bandwidth(torch, lbm3, nbytes: int = 2 << 30, reps: int = 5) -> float:
 
 
 def bench_plain(torch, lbm3, w, precision: str, steps: int, warmup: int, steps_per_launch: int = 0,
-                beta_law: str = "paper"):
+                beta_law: str = "paper", forcing: str = "guo"):
     """Times `steps` steps (even, so that two-step launches cover them all when used).
     Returns MLUPS and the dominant kernel's algorithmic bandwidth: state bytes read and
     written per launch over the time per launch."""
     st = torch.cuda.current_stream()
-    L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, precision=precision, stream=st, beta_law=beta_law)
+    L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, precision=precision, stream=st, beta_law=beta_law,
+                     forcing=forcing)
     L.init(w.rho)
     L.set_steps_per_launch(steps_per_launch)
     L.step(warmup + (warmup % 2 == 0))  # leaves the state factored after an odd first step
@@ -262,6 +263,10 @@ def main():
         laws = {law: bench_plain(torch, lbm3, w, "fp64", 100, 10, beta_law=law)
                 for law in ("spencer", "leclaire", "constant")}
         log(f"beta laws {laws}")
+        # the comparison forcing of Eqs. (4)-(5) (single steps), against the paper's forcing
+        # in single steps on the same workload
+        pert = bench_plain(torch, lbm3, w, "fp64", 100, 10, forcing="perturbation")
+        log(f"perturbation forcing {pert}")
         batched = bench_batched(torch, lbm3, inputs, 1000)
         log(f"batched {batched}")
         adjoint = {"janus_256": bench_adjoint(torch, lbm3, inputs, 256, 5000, 100),
@@ -324,6 +329,10 @@ def main():
             "workload": "the headline droplet tiling, FP64, 100 timed steps per law",
             **{law: {"mlups": round(v["mlups"], 1), "frac_of_peak": round(v["gbs"] / HBM_PEAK_GBS, 4)}
                for law, v in laws.items()}}
+        line["perturbation_forcing_fp64"] = {
+            "workload": "the headline droplet tiling, FP64, one step per launch, 100 timed steps",
+            "mlups": round(pert["mlups"], 1), "frac_of_peak": round(pert["gbs"] / HBM_PEAK_GBS, 4),
+            "guo_one_step_mlups": round(one_step["mlups"], 1)}
     print(json.dumps(line), flush=True)
 
 

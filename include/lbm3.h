@@ -72,6 +72,21 @@ enum {
     LBM3_BETA_CONSTANT = 3
 };
 
+/* How the interfacial tension enters the collision (Eq. 1):
+ *   GUO           the paper's method: the force F = div T of Eq. (7) (T from the pair
+ *                 sum of the colour gradients, Eq. 12 for the divergence), applied with
+ *                 Guo's term of Eq. (8) and the half-force velocity of Eq. (9);
+ *   PERTURBATION  the comparison method of Eqs. (4)-(5): no force; the node-local
+ *                 operator Phi_i = sum_k sum_{l != k} (A_kl C_kl / 2) |G_kl|
+ *                 [w_i (e_i . G_kl)^2 / |G_kl|^2 - B_i] with A_kl = A_lk = 9 sigma_kl /
+ *                 (2 tau) at the node's own tau (Eqs. 10-11), B_0 = -4/27,
+ *                 B_1-4 = 2/27, B_5-8 = 5/108, and u = sum_i f_i e_i / rho.  Single
+ *                 steps only (one launch per step), no batch, no adjoint. */
+enum {
+    LBM3_FORCING_GUO = 0,
+    LBM3_FORCING_PERTURBATION = 1
+};
+
 /* The problem as the paper states it (Sec. 2 and the set-ups of Sec. 3):
  * lattice size, pure-fluid densities rho_k^0 (Eq. 6), interfacial tensions
  * sigma_kl (Eq. 7), per-fluid relaxation times tau_k (nu_k = (tau_k - 1/2)/3,
@@ -87,6 +102,7 @@ typedef struct {
     double wall_wettability[3];  /* reserved: must be 0, else LBM3_EUNSUPPORTED */
     int32_t precision;           /* LBM3_FP64 | LBM3_FP32_STORAGE | LBM3_FP32 */
     int32_t beta_law;            /* LBM3_BETA_*; 0 (the paper's law) when zero-initialised */
+    int32_t forcing;             /* LBM3_FORCING_*; 0 (Guo, the paper's) when zero-initialised */
 } lbm3_params;
 
 /* Observables of the current state (the velocity is the half-force velocity of
@@ -159,7 +175,8 @@ int lbm3_get_tile(const lbm3_t *h, int32_t *threads, int32_t *rows);
  * step of an FP64 or FP32 state loaded in 27-population form runs alone) and needs
  * a tile width (lbm3_set_tile's threads) of at most 256; otherwise, and for the
  * odd last step, a one-step launch runs.  Results do not depend on the mode
- * (bitwise).  EINVAL for another mode. */
+ * (bitwise).  EINVAL for another mode; EUNSUPPORTED for 2 with
+ * LBM3_FORCING_PERTURBATION (single steps only). */
 int lbm3_set_steps_per_launch(lbm3_t *h, int32_t mode);
 /* The launch lbm3_step uses for pairs of steps: *steps = 2 with its threads per
  * workgroup and workgroup count, or *steps = 1 (and zeros) when pairs run as two
@@ -187,7 +204,8 @@ int lbm3_state_buffer(const lbm3_t *h, void **dev_ptr, int32_t *elem_bytes, int6
  * parameters and size, all of one precision, held in one device arena.
  *
  * lbm3_batch_create: p[0..count-1] as for lbm3_create (each validated; mixed
- *   precisions give EINVAL).  hip_stream as for lbm3_create; NULL makes the batch
+ *   precisions give EINVAL; LBM3_FORCING_PERTURBATION gives EUNSUPPORTED; segregation
+ *   laws may differ between instances).  hip_stream as for lbm3_create; NULL makes the batch
  *   create and own a stream (graph capture needs one).  *out is NULL on failure.
  * lbm3_batch_init_fields: instance idx (0..count-1) from host rho [3][ny][nx] and
  *   u [2][ny][nx] or NULL, as lbm3_init_fields.  Blocking.  May be called again
@@ -227,7 +245,8 @@ int lbm3_batch_destroy(lbm3_batch_t *b);
  *   (else ESTATE), advances the FP64 state by nsteps (as lbm3_step) and keeps a
  *   checkpoint of the state every ckpt_every steps in device memory (nsteps >= 1
  *   a multiple of ckpt_every >= 1, else EINVAL).  LBM3_EUNSUPPORTED unless the
- *   handle is LBM3_FP64 with the paper's segregation law (LBM3_BETA_PAPER).
+ *   handle is LBM3_FP64 with the paper's segregation law and forcing
+ *   (LBM3_BETA_PAPER, LBM3_FORCING_GUO).
  * lbm3_adjoint: given drho1_T = dL/drho_1(x, T) (host [ny][nx], finite) for the
  *   state at the end of the last recording, returns dL/dsigma in dsigma[3] (order
  *   rg, rb, gb; may be NULL) and dL/drho_k(x, 0) in drho0 (host [3][ny][nx] for

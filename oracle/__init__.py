@@ -44,11 +44,14 @@ class Problem(ctypes.Structure):
         ("tau", ctypes.c_double * 3),
         ("beta0", ctypes.c_double),
         ("beta_law", ctypes.c_int32),
+        ("forcing", ctypes.c_int32),
     ]
 
 
 # segregation laws: 0 the proposed law, Eqs. (18)-(20); the comparison laws of Eqs. (15)-(17)
 BETA_LAWS = {"paper": 0, "spencer": 1, "leclaire": 2, "constant": 3}
+# interfacial tension: the force of Eq. (7) with Guo's term, or the perturbation operator of Eqs. (4)-(5)
+FORCINGS = {"guo": 0, "perturbation": 1}
 
 
 @dataclass
@@ -60,6 +63,7 @@ class Params:
     rho0: tuple = (1.0, 1.0, 1.0)
     beta0: float = 0.7
     beta_law: str = "paper"
+    forcing: str = "guo"
 
     def c(self) -> Problem:
         p = Problem()
@@ -70,6 +74,7 @@ class Params:
             p.tau[a] = float(self.tau[a])
         p.beta0 = float(self.beta0)
         p.beta_law = BETA_LAWS[self.beta_law] if isinstance(self.beta_law, str) else int(self.beta_law)
+        p.forcing = FORCINGS[self.forcing] if isinstance(self.forcing, str) else int(self.forcing)
         return p
 
 
@@ -96,6 +101,7 @@ def lib():
             "oracle_collide_node": (None, [PP, _DP, _DP, ctypes.c_double, ctypes.c_double, _DP, _DP]),
             "oracle_recolour_node": (None, [PP, _DP, _DP, _DP, _DP, _DP]),
             "oracle_stress_node": (None, [PP, _DP, _DP, _DP, _DP]),
+            "oracle_perturbation_node": (None, [PP, _DP, _DP, _DP, _DP]),
             "oracle_gradient": (None, [ctypes.c_int32, ctypes.c_int32, _DP, _DP, _DP]),
             "oracle_step": (ctypes.c_int, [PP, _DP, _DP]),
             "oracle_run": (ctypes.c_int, [PP, _DP, ctypes.c_int64]),
@@ -179,6 +185,14 @@ def stress_node(p: Params, rho_k, gx, gy) -> np.ndarray:
     out = np.zeros(4)
     lib().oracle_stress_node(ctypes.byref(p.c()), _d(_vec(rho_k)), _d(_vec(gx)), _d(_vec(gy)),
                              _d(out))
+    return out
+
+
+def perturbation_node(p: Params, rho_k, gx, gy) -> np.ndarray:
+    """Phi_i of Eqs. (4)-(5) at one node (the comparison forcing)."""
+    out = np.zeros(9)
+    lib().oracle_perturbation_node(ctypes.byref(p.c()), _d(_vec(rho_k)), _d(_vec(gx)), _d(_vec(gy)),
+                                   _d(out))
     return out
 
 
@@ -274,7 +288,8 @@ class use_library:
         # copy the prototypes from the loaded default library
         for name in ("oracle_lattice", "oracle_X", "oracle_g", "oracle_beta", "oracle_feq",
                      "oracle_guo", "oracle_local_tau", "oracle_collide_node",
-                     "oracle_recolour_node", "oracle_stress_node", "oracle_gradient",
+                     "oracle_recolour_node", "oracle_stress_node", "oracle_perturbation_node",
+                     "oracle_gradient",
                      "oracle_step", "oracle_run", "oracle_init", "oracle_fields",
                      "oracle_observables", "oracle_step_nodes", "oracle_num_threads"):
             src = getattr(self._saved, name)

@@ -68,6 +68,8 @@ typedef struct {
     double beta0;    /* reference segregation parameter beta^0 */
     int32_t beta_law; /* 0 proposed law, Eqs. (18)-(20); 1 Spencer, Eq. (15);
                          2 Leclaire, Eq. (16); 3 constant beta, Eq. (17) */
+    int32_t forcing;  /* 0 the force of Eq. (7) with Guo's term, Eqs. (8)-(9);
+                         1 the perturbation operator of Eqs. (4)-(5) */
 } oracle_problem;
 
 void oracle_lattice(int32_t *ex, int32_t *ey, double *w)
@@ -331,6 +333,36 @@ void oracle_stress_node(const oracle_problem *p, const double *rho_k, const doub
         }
 }
 
+/* Perturbation operator of Eqs. (4)-(5), the comparison forcing: at one node
+ * Phi_i = sum_k sum_{l != k} (A_kl C_kl / 2) |G_kl| [w_i (e_i . G_kl)^2 / |G_kl|^2 - B_i]
+ * with B_0 = -4/27, B_1-4 = 2/27, B_5-8 = 5/108 (the values the paper quotes).
+ * Reading: A_kl = A_lk = 9 sigma_kl / (2 tau), from sigma_kl = (A_kl + A_lk) tau / 9,
+ * with tau the node's relaxation time of Eqs. (10)-(11); pairs with |G_kl| at or below
+ * the guard add nothing (the term vanishes with |G_kl| anyway). */
+void oracle_perturbation_node(const oracle_problem *p, const double *rho_k, const double *gx,
+                              const double *gy, double *phi)
+{
+    static const double B[9] = {-4.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0,
+                                5.0 / 108.0, 5.0 / 108.0, 5.0 / 108.0, 5.0 / 108.0};
+    double rho = rho_k[0] + rho_k[1] + rho_k[2];
+    double c[3] = {rho_k[0] / rho, rho_k[1] / rho, rho_k[2] / rho};
+    double tau = oracle_local_tau(p, rho_k);
+    for (int i = 0; i < 9; ++i) phi[i] = 0.0;
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+            if (l == k) continue;
+            double G[2], n[2];
+            double mag = colour_gradient(c, gx, gy, k, l, G, n);
+            if (!(mag > GUARD_G)) continue;
+            double A = 9.0 * sigma_of(p, k, l) / (2.0 * tau);
+            double a = 0.5 * A * concentration_factor(p, rho_k, k, l) * mag;
+            for (int i = 0; i < 9; ++i) {
+                double eG = EX[i] * G[0] + EY[i] * G[1];
+                phi[i] += a * (W[i] * eG * eG / (mag * mag) - B[i]);
+            }
+        }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Grid-wide pieces.                                                         */
 /* ------------------------------------------------------------------------ */
@@ -445,10 +477,15 @@ static void compute_fields(const oracle_problem *p, const double *f, fields *w)
     for (size_t j = 0; j < N; ++j) w->F[N + j] = dx[j];
     oracle_gradient(nx, ny, w->S + 3 * N, dx, dy); /* S_yy */
     for (size_t j = 0; j < N; ++j) w->F[N + j] += dy[j];
+    /* with the perturbation operator no body force acts: u = sum_i f_i e_i / rho and no
+       Guo term */
+    if (p->forcing == 1)
+        for (size_t j = 0; j < 2 * N; ++j) w->F[j] = 0.0;
 }
 
-/* One full time step: collision (Eqs. 1-3, 8-11), recolouring (Eqs. 13, 19,
- * 20) and streaming (Eq. 22), from the post-streaming state f to fnew. */
+/* One full time step: collision (Eqs. 1-3, 8-11, or Eqs. 1-5 with the
+ * perturbation operator), recolouring (Eqs. 13, 19, 20) and streaming (Eq. 22),
+ * from the post-streaming state f to fnew. */
 int oracle_step(const oracle_problem *p, const double *f, double *fnew)
 {
     const int nx = p->nx, ny = p->ny;
@@ -469,6 +506,11 @@ int oracle_step(const oracle_problem *p, const double *f, double *fnew)
             double fi[9], fdag[9], fdd[27];
             for (int i = 0; i < 9; ++i) fi[i] = w.ftot[i * N + j];
             oracle_collide_node(p, rk, fi, w.F[j], w.F[N + j], fdag, NULL);
+            if (p->forcing == 1) { /* Eq. (1) with the operator of Eqs. (4)-(5) */
+                double phi[9];
+                oracle_perturbation_node(p, rk, gx, gy, phi);
+                for (int i = 0; i < 9; ++i) fdag[i] += phi[i];
+            }
             oracle_recolour_node(p, rk, gx, gy, fdag, fdd);
             /* streaming, Eq. (22): f_{i,k}(x + e_i, t + 1) = f_ddag_{i,k}(x, t) */
             for (int k = 0; k < 3; ++k)

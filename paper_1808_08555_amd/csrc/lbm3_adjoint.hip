@@ -555,8 +555,9 @@ int lbm3_adjoint_record(lbm3_t* h, int64_t nsteps, int32_t ckpt_every)
         set_error("the adjoint is provided for LBM3_FP64 only");
         return LBM3_EUNSUPPORTED;
     }
-    if (h->p.beta_law != LBM3_BETA_PAPER) {
-        set_error("the adjoint is provided for the paper's segregation law (LBM3_BETA_PAPER) only");
+    if (h->p.beta_law != LBM3_BETA_PAPER || h->p.forcing != LBM3_FORCING_GUO) {
+        set_error("the adjoint is provided for the paper's segregation law and forcing "
+                  "(LBM3_BETA_PAPER, LBM3_FORCING_GUO) only");
         return LBM3_EUNSUPPORTED;
     }
     if (!h->ready || h->step != 0 || !h->init_at_rest) {

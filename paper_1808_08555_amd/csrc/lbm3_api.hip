@@ -82,6 +82,10 @@ int validate_params(const lbm3_params* p)
         set_error("beta_law must be LBM3_BETA_PAPER, _SPENCER, _LECLAIRE or _CONSTANT (got %d)", p->beta_law);
         return LBM3_EINVAL;
     }
+    if (p->forcing != LBM3_FORCING_GUO && p->forcing != LBM3_FORCING_PERTURBATION) {
+        set_error("forcing must be LBM3_FORCING_GUO or LBM3_FORCING_PERTURBATION (got %d)", p->forcing);
+        return LBM3_EINVAL;
+    }
     return LBM3_OK;
 }
 
@@ -249,7 +253,8 @@ int upload_plan(lbm3* h)
     // passes.
     const int64_t min2 = (int64_t)1 << (h->prec == Prec::F64 ? 18 : 20);
     const bool big = (int64_t)h->kp.nx * h->kp.ny >= min2;
-    const bool want2 = h->pass_mode == 2 || (h->pass_mode == 0 && big);
+    // (the perturbation operator of Eqs. 4-5 runs as single steps only)
+    const bool want2 = h->p.forcing == LBM3_FORCING_GUO && (h->pass_mode == 2 || (h->pass_mode == 0 && big));
     int t2 = h->tile_set ? h->threads : (h->kp.nx < 768 ? 64 : 256);
     const int slots2 = want2 ? device_slots_pair(h->prec, t2) : 0;
     if (slots2 > 0) {
@@ -293,14 +298,15 @@ int step_handle(lbm3* h, int64_t n, bool factored)
     while (n > 0) {
         hipError_t e;
         int done = 1;
-        if (h->fmt == steady_fmt(h->prec) && n >= 2 && h->ntiles2 > 0) {
+        const bool pt = h->p.forcing == LBM3_FORCING_PERTURBATION;
+        if (!pt && h->fmt == steady_fmt(h->prec) && n >= 2 && h->ntiles2 > 0) {
             e = launch_pair(h->prec, h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst, h->dtiles2, h->ntiles2,
                             h->threads2, h->step, h->stream);
             done = 2;
         } else {
             const Fmt out = factored ? Fmt::FAC : Fmt::F27;
             e = launch_tiles(h->prec, h->fmt, out, h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst,
-                             h->dtiles, h->ntiles, h->threads, h->step, 0, h->stream);
+                             h->dtiles, h->ntiles, h->threads, h->step, 0, h->stream, pt);
             h->fmt = out;
         }
         if (e != hipSuccess) return hip_fail(e, "step launch");
@@ -496,7 +502,8 @@ int lbm3_observables(lbm3_t* h, lbm3_obs* out, double* rho_out, double* f_out)
     if (rc) return rc;
     hipError_t e = launch_observe_tiles(h->prec, h->fmt, h->buf[h->cur], h->dinst, h->dtiles,
                                         h->ntiles, h->threads, h->partials,
-                                        rho_out ? h->staging : nullptr, h->stream);
+                                        rho_out ? h->staging : nullptr, h->stream,
+                                        h->p.forcing == LBM3_FORCING_PERTURBATION);
     if (e == hipSuccess) e = launch_reduce_obs(h->partials, h->ntiles, h->obs_dev, h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->obs_host, h->obs_dev, kObsFields * sizeof(double),
@@ -594,6 +601,10 @@ int lbm3_set_steps_per_launch(lbm3_t* h, int32_t mode)
     if (mode < 0 || mode > 2) {
         set_error("mode must be 0 (automatic), 1 or 2");
         return LBM3_EINVAL;
+    }
+    if (mode == 2 && h->p.forcing != LBM3_FORCING_GUO) {
+        set_error("two steps per launch are provided for the force of Eq. (7) with Guo's term only");
+        return LBM3_EUNSUPPORTED;
     }
     const int old = h->pass_mode;
     h->pass_mode = mode;

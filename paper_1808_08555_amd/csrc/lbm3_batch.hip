@@ -252,6 +252,10 @@ int lbm3_batch_create(const lbm3_params* p, int32_t count, void* hip_stream, lbm
             set_error("all instances of a batch must have the same precision");
             return LBM3_EINVAL;
         }
+        if (p[i].forcing != LBM3_FORCING_GUO) {
+            set_error("the batched form runs the force of Eq. (7) with Guo's term only (instance %d)", i);
+            return LBM3_EUNSUPPORTED;
+        }
     }
     lbm3_batch* b = new (std::nothrow) lbm3_batch();
     if (!b) {

@@ -62,13 +62,15 @@ inline Fmt steady_fmt(Prec p) { return p == Prec::F32S ? Fmt::F27 : Fmt::FAC; }
 
 // Launchers (lbm3_step.hip).  All asynchronous on `stream`.  One fused step from a state in
 // format `in` to one in format `out` (F27 -> F27, F27 -> FAC or FAC -> FAC); with
-// filter != 0 a workgroup whose instance is not in format `in` does nothing.
+// filter != 0 a workgroup whose instance is not in format `in` does nothing.  pt selects the
+// perturbation operator of Eqs. (4)-(5) in place of the force and Guo's term (single steps
+// only).
 hipError_t launch_tiles(Prec prec, Fmt in, Fmt out, const void* fin, void* fout, const Instance* inst,
                         const Tile* tiles, int ntiles, int threads, int64_t step, int filter,
-                        hipStream_t stream);
+                        hipStream_t stream, bool pt = false);
 hipError_t launch_observe_tiles(Prec prec, Fmt in, const void* fin, const Instance* inst,
                                 const Tile* tiles, int ntiles, int threads, double* partials,
-                                double* rho_out, hipStream_t stream);
+                                double* rho_out, hipStream_t stream, bool pt = false);
 hipError_t launch_reduce_obs(const double* partials, int nblocks, double* out, hipStream_t stream);
 hipError_t launch_init(Prec prec, const double* rho, const double* u, void* fout,
                        const KParams& kp, hipStream_t stream);
@@ -102,7 +104,8 @@ uint32_t step_salt(int64_t step);
 
 // Per-precision instantiations of the fused step (lbm3_tiles_*.hip).
 #define LBM3_TILES_DECL(NAME)                                                                    \
-    hipError_t NAME(Fmt in, Fmt out, bool obs, const void* fin, void* fout, const Instance* inst, \
+    hipError_t NAME(Fmt in, Fmt out, bool obs, bool pt, const void* fin, void* fout,             \
+                    const Instance* inst,                                                         \
                     const Tile* tiles, int ntiles, int threads, uint32_t salt, int filter,        \
                     double* partials, double* rho_out, hipStream_t stream);                       \
     int NAME##_occupancy(int threads);

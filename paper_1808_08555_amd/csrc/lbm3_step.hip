@@ -170,18 +170,18 @@ hipError_t launch_pair(Prec prec, const void* fin, void* fout, const Instance* i
 
 hipError_t launch_tiles(Prec prec, Fmt in, Fmt out, const void* fin, void* fout, const Instance* inst,
                         const Tile* tiles, int ntiles, int threads, int64_t step, int filter,
-                        hipStream_t st)
+                        hipStream_t st, bool pt)
 {
     const uint32_t salt = step_salt(step);
     switch (prec) {
         case Prec::F64:
-            return tiles_f64(in, out, false, fin, fout, inst, tiles, ntiles, threads, salt, filter,
+            return tiles_f64(in, out, false, pt, fin, fout, inst, tiles, ntiles, threads, salt, filter,
                              nullptr, nullptr, st);
         case Prec::F32S:
-            return tiles_f32s(in, out, false, fin, fout, inst, tiles, ntiles, threads, salt, filter,
+            return tiles_f32s(in, out, false, pt, fin, fout, inst, tiles, ntiles, threads, salt, filter,
                               nullptr, nullptr, st);
         case Prec::F32:
-            return tiles_f32(in, out, false, fin, fout, inst, tiles, ntiles, threads, salt, filter,
+            return tiles_f32(in, out, false, pt, fin, fout, inst, tiles, ntiles, threads, salt, filter,
                              nullptr, nullptr, st);
     }
     return hipErrorInvalidValue;
@@ -189,17 +189,17 @@ hipError_t launch_tiles(Prec prec, Fmt in, Fmt out, const void* fin, void* fout,
 
 hipError_t launch_observe_tiles(Prec prec, Fmt in, const void* fin, const Instance* inst,
                                 const Tile* tiles, int ntiles, int threads, double* partials,
-                                double* rho_out, hipStream_t st)
+                                double* rho_out, hipStream_t st, bool pt)
 {
     switch (prec) {
         case Prec::F64:
-            return tiles_f64(in, in, true, fin, nullptr, inst, tiles, ntiles, threads, 0u, 0,
+            return tiles_f64(in, in, true, pt, fin, nullptr, inst, tiles, ntiles, threads, 0u, 0,
                              partials, rho_out, st);
         case Prec::F32S:
-            return tiles_f32s(in, in, true, fin, nullptr, inst, tiles, ntiles, threads, 0u, 0,
+            return tiles_f32s(in, in, true, pt, fin, nullptr, inst, tiles, ntiles, threads, 0u, 0,
                               partials, rho_out, st);
         case Prec::F32:
-            return tiles_f32(in, in, true, fin, nullptr, inst, tiles, ntiles, threads, 0u, 0,
+            return tiles_f32(in, in, true, pt, fin, nullptr, inst, tiles, ntiles, threads, 0u, 0,
                              partials, rho_out, st);
     }
     return hipErrorInvalidValue;

@@ -300,11 +300,20 @@ struct StepConsts {
 // comparison law of Eqs. 15-17 through g_kl and ct_coef) at one node,
 // given the totals f[9], densities rk[3], pair normals n[6] (pairs rg, rb, gb) and the
 // force.  Returns f_dag, c_k, V_k (V[2k], V[2k+1]) and u, rho u for observables.
-template <typename C>
+//
+// With PT (the perturbation operator of Eqs. 4-5 instead of the force), F = 0 and T holds
+// the node's own stress T = sum_pairs sigma C (|G|^2 I - G G^T)/|G| (row order xx, xy, yy).
+// Eq. (5) summed over the ordered pairs is, with A_kl = 9 sigma_kl / (2 tau) and
+// M = sum_pairs sigma C |G| n n^T = tr(T) I - T (two dimensions),
+//   Phi_i = 9/(2 tau) [w_i e_i . M e_i - tr(T) B_i],
+// where e_i . M e_i is T_yy for e = (+-1, 0), T_xx for (0, +-1) and tr(T) - 2 e_x e_y T_xy
+// on the diagonals; B_0 = -4/27, B_1-4 = 2/27, B_5-8 = 5/108.
+template <typename C, bool PT = false>
 __device__ __forceinline__ void collide_recolour(const C (&f)[9], const C (&rk)[3],
                                                  const C (&n)[6], C Fx, C Fy,
                                                  const StepConsts<C>& K, C (&fd)[9], C (&ck)[3],
-                                                 C (&V)[6], C& ux, C& uy, C& mxh, C& myh)
+                                                 C (&V)[6], C& ux, C& uy, C& mxh, C& myh,
+                                                 const C* T = nullptr)
 {
     const C rho = rk[0] + rk[1] + rk[2];
     const C irho = recip(rho);
@@ -328,6 +337,21 @@ __device__ __forceinline__ void collide_recolour(const C (&f)[9], const C (&rk)[
         const C feq = wgt<C>(i) * rho * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
         const C phi = wgt<C>(i) * pref * (C(3) * (eF - uF) + C(9) * eu * eF);
         fd[i] = f[i] - (f[i] - feq) * itau + phi;
+    }
+    if constexpr (PT) {
+        const C a = C(4.5) * itau;
+        const C tr = T[0] + T[2];
+        const C d0 = tr - C(2) * T[1], d1 = tr + C(2) * T[1];
+        const C B0 = C(-4.0 / 27.0), B1 = C(2.0 / 27.0), B5 = C(5.0 / 108.0);
+        fd[0] += a * (-(tr * B0));
+        fd[1] += a * (wgt<C>(1) * T[2] - tr * B1);
+        fd[3] += a * (wgt<C>(3) * T[2] - tr * B1);
+        fd[2] += a * (wgt<C>(2) * T[0] - tr * B1);
+        fd[4] += a * (wgt<C>(4) * T[0] - tr * B1);
+        fd[5] += a * (wgt<C>(5) * d0 - tr * B5);
+        fd[7] += a * (wgt<C>(7) * d0 - tr * B5);
+        fd[6] += a * (wgt<C>(6) * d1 - tr * B5);
+        fd[8] += a * (wgt<C>(8) * d1 - tr * B5);
     }
     // C_t and beta_kl of Eq. (19) (or the law's own s and g_kl); a_p = beta_p rho_k rho_l / rho
     C ct = K.ct_coef * rk[0] * rk[1] * rk[2] * (irho * irho * irho);
@@ -482,7 +506,7 @@ __device__ __forceinline__ void force_at_lane(const C (*tring)[3][NT], int s0, i
 // the row below, fB, rB two rows below; nB = pair normals two rows below.  With FAC input,
 // also the partial totals and densities of the two rows above (they collect the pulls of
 // each source row as it arrives).  LDS rings are indexed by row mod 3.
-template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT, bool TAPE>
+template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT, bool TAPE, bool PT = false>
 __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__ fout,
                                       const KParams& kp, int x0, int y0, int rows, int cols,
                                       C (*cring)[3][NT], C (*tring)[3][NT], C (*xb)[9][NT],
@@ -676,15 +700,21 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
         // ---- stage 3: force, collision, recolouring of row j-2 (fB, rB, nB)
         if (j >= 4 && in3) {
             const int yo = y0 + j - 4;
-            C Fx, Fy;
-            force_at_lane<C, NT>(tring, s0, s1, s2, t, Fx, Fy);
+            C Fx = C(0), Fy = C(0), Tn[3];
+            if constexpr (PT) {
+                // the perturbation operator needs only this node's stress (middle ring row)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) Tn[a] = tring[s2][a][t];
+            } else {
+                force_at_lane<C, NT>(tring, s0, s1, s2, t, Fx, Fy);
+            }
             if constexpr (TAPE) {
                 const int64_t N = (int64_t)nx * ny, o = (int64_t)yo * nx + x;
                 rho_out[18 * N + o] = double(Fx);
                 rho_out[19 * N + o] = double(Fy);
             }
             C fd[9], ck[3], V[6], ux, uy, mxh, myh;
-            collide_recolour<C>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
+            collide_recolour<C, PT>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
             if constexpr (!OBS) {
                 const uint32_t key = ((uint32_t)yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt;
                 const int64_t pl = fresh_stride(plane);
@@ -1490,7 +1520,7 @@ struct ExchangeLds<C, NT, Fmt::F27> {
 // rho_out as [20][ny][nx] (rho_k, f_i, d_x c_k and d_y c_k per fluid, F_x, F_y): the
 // forward quantities the adjoint needs.  With filter, a workgroup whose instance's state is not in
 // format IN returns at once.
-template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT, bool TAPE = false>
+template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT, bool TAPE = false, bool PT = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles(const S* __restrict__ fin, S* __restrict__ fout,
                                               const Instance* __restrict__ inst,
                                               const Tile* __restrict__ tiles, uint32_t salt,
@@ -1507,7 +1537,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const KParams kp = inst[tl.inst].kp;
     const int64_t off = inst[tl.inst].offset;
     double acc[kObsFields] = {0, 0, 0, 0, 0, 0, 0, 0};
-    march<S, C, NT, OBS, IN, OUT, TAPE>(fin + off, OBS ? nullptr : fout + off, kp, tl.x0, tl.y0, tl.rows,
+    march<S, C, NT, OBS, IN, OUT, TAPE, PT>(fin + off, OBS ? nullptr : fout + off, kp, tl.x0, tl.y0, tl.rows,
                                   tl.cols, cring, tring, ExchangeLds<C, NT, IN>::get(), acc, rho_out,
                                   salt ^ mix32((uint32_t)tl.inst * 0x9E3779B9U + 0x51ed270bU));
     if constexpr (OBS) {
@@ -1516,12 +1546,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
 }
 
-template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT, bool TAPE = false>
+template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT, bool TAPE = false, bool PT = false>
 hipError_t do_tiles(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                     int ntiles, uint32_t salt, int filter, double* partials, double* rho_out,
                     hipStream_t st)
 {
-    hipLaunchKernelGGL((k_tiles<S, C, NT, OBS, IN, OUT, TAPE>), dim3(ntiles), dim3(NT), 0, st,
+    hipLaunchKernelGGL((k_tiles<S, C, NT, OBS, IN, OUT, TAPE, PT>), dim3(ntiles), dim3(NT), 0, st,
                        (const S*)fin, (S*)fout, inst, tiles, salt, filter, partials, rho_out);
     return hipGetLastError();
 }
@@ -1531,30 +1561,43 @@ hipError_t do_tiles(const void* fin, void* fout, const Instance* inst, const Til
 template <typename S, typename C>
 constexpr bool kHasFac = !(sizeof(S) == 4 && sizeof(C) == 8);
 
-template <typename S, typename C, int NT>
-hipError_t tiles_nt(Fmt in, Fmt out, bool obs, const void* fin, void* fout, const Instance* inst,
-                    const Tile* tiles, int ntiles, uint32_t salt, int filter, double* partials,
-                    double* rho_out, hipStream_t st)
+template <typename S, typename C, int NT, bool PT>
+hipError_t tiles_nt_pt(Fmt in, Fmt out, bool obs, const void* fin, void* fout, const Instance* inst,
+                       const Tile* tiles, int ntiles, uint32_t salt, int filter, double* partials,
+                       double* rho_out, hipStream_t st)
 {
     if (in == Fmt::F27 && (obs || out == Fmt::F27)) {
         if (obs)
-            return do_tiles<S, C, NT, true, Fmt::F27, Fmt::F27>(fin, nullptr, inst, tiles, ntiles, 0u,
-                                                               filter, partials, rho_out, st);
-        return do_tiles<S, C, NT, false, Fmt::F27, Fmt::F27>(fin, fout, inst, tiles, ntiles, salt,
-                                                            filter, nullptr, nullptr, st);
+            return do_tiles<S, C, NT, true, Fmt::F27, Fmt::F27, false, PT>(fin, nullptr, inst, tiles, ntiles,
+                                                                          0u, filter, partials, rho_out, st);
+        return do_tiles<S, C, NT, false, Fmt::F27, Fmt::F27, false, PT>(fin, fout, inst, tiles, ntiles, salt,
+                                                                       filter, nullptr, nullptr, st);
     }
     if constexpr (kHasFac<S, C>) {
         if (obs && in == Fmt::FAC)
-            return do_tiles<S, C, NT, true, Fmt::FAC, Fmt::FAC>(fin, nullptr, inst, tiles, ntiles, 0u,
-                                                               filter, partials, rho_out, st);
+            return do_tiles<S, C, NT, true, Fmt::FAC, Fmt::FAC, false, PT>(fin, nullptr, inst, tiles, ntiles,
+                                                                          0u, filter, partials, rho_out, st);
         if (in == Fmt::FAC && out == Fmt::FAC)
-            return do_tiles<S, C, NT, false, Fmt::FAC, Fmt::FAC>(fin, fout, inst, tiles, ntiles, salt,
-                                                                filter, nullptr, nullptr, st);
+            return do_tiles<S, C, NT, false, Fmt::FAC, Fmt::FAC, false, PT>(fin, fout, inst, tiles, ntiles,
+                                                                           salt, filter, nullptr, nullptr, st);
         if (in == Fmt::F27 && out == Fmt::FAC)
-            return do_tiles<S, C, NT, false, Fmt::F27, Fmt::FAC>(fin, fout, inst, tiles, ntiles, salt,
-                                                                filter, nullptr, nullptr, st);
+            return do_tiles<S, C, NT, false, Fmt::F27, Fmt::FAC, false, PT>(fin, fout, inst, tiles, ntiles,
+                                                                           salt, filter, nullptr, nullptr, st);
     }
     return hipErrorInvalidValue;
+}
+
+// pt: the perturbation operator of Eqs. (4)-(5) in place of the force and Guo's term
+template <typename S, typename C, int NT>
+hipError_t tiles_nt(Fmt in, Fmt out, bool obs, bool pt, const void* fin, void* fout, const Instance* inst,
+                    const Tile* tiles, int ntiles, uint32_t salt, int filter, double* partials,
+                    double* rho_out, hipStream_t st)
+{
+    if (pt)
+        return tiles_nt_pt<S, C, NT, true>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, filter,
+                                           partials, rho_out, st);
+    return tiles_nt_pt<S, C, NT, false>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, filter, partials,
+                                        rho_out, st);
 }
 
 // The FP64 step writing the adjoint's tape (rho_out as [20][ny][nx]), factored output.
@@ -1570,15 +1613,15 @@ hipError_t tiles_tape_nt(Fmt in, const void* fin, void* fout, const Instance* in
 }
 
 template <typename S, typename C>
-hipError_t tiles_any(Fmt in, Fmt out, bool obs, const void* fin, void* fout, const Instance* inst,
+hipError_t tiles_any(Fmt in, Fmt out, bool obs, bool pt, const void* fin, void* fout, const Instance* inst,
                      const Tile* tiles, int ntiles, int threads, uint32_t salt, int filter,
                      double* partials, double* rho_out, hipStream_t st)
 {
     switch (threads) {
-        case 64: return tiles_nt<S, C, 64>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
-        case 128: return tiles_nt<S, C, 128>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
-        case 256: return tiles_nt<S, C, 256>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
-        case 512: return tiles_nt<S, C, 512>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
+        case 64: return tiles_nt<S, C, 64>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
+        case 128: return tiles_nt<S, C, 128>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
+        case 256: return tiles_nt<S, C, 256>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
+        case 512: return tiles_nt<S, C, 512>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -3,11 +3,11 @@
 
 namespace tcg {
 
-hipError_t tiles_f32s(Fmt in, Fmt out, bool obs, const void* fin, void* fout, const Instance* inst,
+hipError_t tiles_f32s(Fmt in, Fmt out, bool obs, bool pt, const void* fin, void* fout, const Instance* inst,
                     const Tile* tiles, int ntiles, int threads, uint32_t salt, int filter,
                     double* partials, double* rho_out, hipStream_t stream)
 {
-    return tiles_any<float, double>(in, out, obs, fin, fout, inst, tiles, ntiles, threads, salt, filter,
+    return tiles_any<float, double>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, threads, salt, filter,
                                 partials, rho_out, stream);
 }
 

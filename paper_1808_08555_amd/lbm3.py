@@ -26,6 +26,9 @@ PRECISIONS = {"fp64": LBM3_FP64, "fp32_storage": LBM3_FP32_STORAGE, "fp32": LBM3
 LBM3_BETA_PAPER, LBM3_BETA_SPENCER, LBM3_BETA_LECLAIRE, LBM3_BETA_CONSTANT = 0, 1, 2, 3
 BETA_LAWS = {"paper": LBM3_BETA_PAPER, "spencer": LBM3_BETA_SPENCER, "leclaire": LBM3_BETA_LECLAIRE,
              "constant": LBM3_BETA_CONSTANT}
+# interfacial tension: the force of Eq. (7) with Guo's term, or the perturbation operator of Eqs. (4)-(5)
+LBM3_FORCING_GUO, LBM3_FORCING_PERTURBATION = 0, 1
+FORCINGS = {"guo": LBM3_FORCING_GUO, "perturbation": LBM3_FORCING_PERTURBATION}
 ERROR_NAMES = {0: "LBM3_OK", -1: "LBM3_EINVAL", -2: "LBM3_ENOMEM", -3: "LBM3_EDEVICE",
                -4: "LBM3_EUNSUPPORTED", -5: "LBM3_ENONFINITE", -6: "LBM3_ESTATE"}
 
@@ -36,7 +39,7 @@ class lbm3_params(ctypes.Structure):
         ("rho0", ctypes.c_double * 3), ("sigma", ctypes.c_double * 3),
         ("tau", ctypes.c_double * 3), ("beta0", ctypes.c_double),
         ("boundary", ctypes.c_int32), ("wall_wettability", ctypes.c_double * 3),
-        ("precision", ctypes.c_int32), ("beta_law", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("beta_law", ctypes.c_int32), ("forcing", ctypes.c_int32),
     ]
 
 
@@ -134,7 +137,7 @@ def _stream_handle(stream) -> int | None:
 def make_params(nx: int, ny: int, sigma=(0.01, 0.01, 0.01), tau=(1.0, 1.0, 1.0),
                 rho0=(1.0, 1.0, 1.0), beta0: float = 0.7, precision="fp64",
                 boundary: int = LBM3_PERIODIC, wall_wettability=(0.0, 0.0, 0.0),
-                beta_law="paper") -> lbm3_params:
+                beta_law="paper", forcing="guo") -> lbm3_params:
     p = lbm3_params()
     p.nx, p.ny = int(nx), int(ny)
     for a in range(3):
@@ -146,6 +149,7 @@ def make_params(nx: int, ny: int, sigma=(0.01, 0.01, 0.01), tau=(1.0, 1.0, 1.0),
     p.boundary = int(boundary)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.beta_law = BETA_LAWS[beta_law] if isinstance(beta_law, str) else int(beta_law)
+    p.forcing = FORCINGS[forcing] if isinstance(forcing, str) else int(forcing)
     return p
 
 
@@ -320,10 +324,11 @@ class Lattice:
     precision: str = "fp64"
     stream: object = None
     beta_law: str = "paper"
+    forcing: str = "guo"
 
     def __post_init__(self):
         self.params = make_params(self.nx, self.ny, self.sigma, self.tau, self.rho0, self.beta0,
-                                  self.precision, beta_law=self.beta_law)
+                                  self.precision, beta_law=self.beta_law, forcing=self.forcing)
         self.h = lbm3_create(self.params, self.stream)
 
     def init(self, rho, u=None):
