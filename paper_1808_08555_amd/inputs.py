@@ -314,6 +314,34 @@ def janus_droplet(n: int, Rr: float, Rg: float, Rb: float, drg: float, dgb: floa
                     steps=steps, meta={"Rr": Rr, "Rg": Rg, "Rb": Rb, "drg": drg, "dgb": dgb, "y0": y0})
 
 
+def kissing_droplets(n: int, R: float, d: float, sigma, tau: float = 0.8) -> Workload:
+    """Two droplets of radius R, fluid 0 below and fluid 1 above the centre line
+    y = (n - 1) / 2, centres d apart on the line x = (n - 1) / 2, in fluid 2 (the kissing
+    layout of the near-critical states of Sec. 4).  Where the disks overlap (d < 2 R) the
+    centre line splits them."""
+    c = (n - 1) / 2.0
+    x, y = _grid(n, n)
+    lab = np.full((n, n), 2, dtype=np.int64)
+    lab[((x - c) ** 2 + (y - (c - d / 2)) ** 2 <= R * R) & (y < c)] = 0
+    lab[((x - c) ** 2 + (y - (c + d / 2)) ** 2 <= R * R) & (y >= c)] = 1
+    return Workload(f"kissing_{n}_{d:g}", n, n, tuple(sigma), (tau, tau, tau), rho=rho_from_labels(lab),
+                    meta={"R": R, "d": d, "y_mid": c})
+
+
+def engulfed_droplet(n: int, Rr: float, Rg: float, sigma, tau: float = 0.8) -> Workload:
+    """A disk of fluid 0 (radius Rr) inside a disk of fluid 1 (radius Rg), internally tangent
+    (centres Rg - Rr apart on the line x = (n - 1) / 2), in fluid 2: the critical engulfing
+    layout of Sec. 4."""
+    c = (n - 1) / 2.0
+    d = Rg - Rr
+    x, y = _grid(n, n)
+    lab = np.full((n, n), 2, dtype=np.int64)
+    lab[(x - c) ** 2 + (y - (c - d / 2)) ** 2 <= Rg * Rg] = 1
+    lab[(x - c) ** 2 + (y - (c + d / 2)) ** 2 <= Rr * Rr] = 0
+    return Workload(f"engulfed_{n}", n, n, tuple(sigma), (tau, tau, tau), rho=rho_from_labels(lab),
+                    meta={"Rr": Rr, "Rg": Rg, "d": d})
+
+
 def flat_layers(nx: int, ny: int, y_interfaces=(0.25, 0.75), fluids=(2, 0)) -> np.ndarray:
     """Two flat layers uniform in x: fluid fluids[1] for y in [y0*ny, y1*ny), fluids[0] elsewhere."""
     x, y = _grid(nx, ny)

@@ -133,3 +133,20 @@ def fit_circle(p: np.ndarray):
     (a, b, e), *_ = np.linalg.lstsq(A, rhs, rcond=None)
     xc, yc = -a / 2, -b / 2
     return xc, yc, math.sqrt(xc * xc + yc * yc - e)
+
+
+def contact_length(rho: np.ndarray, y_mid: float, third: int = 2) -> float:
+    """Length of the contact between the two other fluids across the line y = y_mid: the
+    fraction not of fluid `third`, summed along the two lattice rows next to the line and
+    averaged over them (a point contact leaves only the diffuse tails, about 9 nodes at
+    R = 60)."""
+    c = rho / rho.sum(0)
+    rows = [int(math.floor(y_mid)), int(math.ceil(y_mid))]
+    return float(np.mean([(1.0 - c[third, r]).sum() for r in rows]))
+
+
+def mixed_nodes(rho: np.ndarray, k: int, l: int, level: float = 0.2) -> int:
+    """Nodes where both fluids k and l hold more than `level` of the mixture: a measure of
+    the length of the k-l interface (about its length times its width)."""
+    c = rho / rho.sum(0)
+    return int((np.minimum(c[k], c[l]) > level).sum())

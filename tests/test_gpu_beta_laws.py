@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
+from analysis import contact_length, mixed_nodes
 from paper_1808_08555_amd import inputs, lbm3
 
 pytestmark = pytest.mark.gpu
@@ -113,3 +114,40 @@ def test_adjoint_refuses_other_laws():
         assert e.value.code == lbm3.LBM3_EUNSUPPORTED
     finally:
         L.close()
+
+
+def _run(w, law, steps):
+    L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, beta_law=law).init(w.rho)
+    try:
+        obs, rho, _ = L.step(steps).observables(want_rho=True)
+        assert obs["nonfinite"] == 0
+        return rho
+    finally:
+        L.close()
+
+
+def test_critical_kissing_state_paper_law_against_the_comparison_laws():
+    """Sec. 4, near-critical and critical states: two R = 60 droplets (fluids 0, 1) touching
+    in fluid 2 on 300^2, sigma_rg = 0.01 = sigma_rb + sigma_gb (critical, the kissing
+    state), nu = 0.1, 20000 steps.  The paper's law keeps a point contact (only the
+    diffuse tails, about 9 nodes); with the constant beta of Eq. (17) the droplets form a
+    flat contact about 50 nodes long; Eq. (16) has no triangle here and gives the constant
+    law's result (the paper reports the two as almost the same)."""
+    w = inputs.kissing_droplets(300, 60.0, 120.0, (0.01, 0.005, 0.005))
+    res = {law: _run(w, law, 20000) for law in ("paper", "constant", "leclaire")}
+    Lc = {law: contact_length(r, w.meta["y_mid"]) for law, r in res.items()}
+    print("contact length L_rg:", Lc)
+    assert Lc["paper"] < 0.25 * Lc["constant"]
+    assert np.array_equal(res["leclaire"], res["constant"])
+
+
+def test_critical_engulfing_state_paper_law_against_the_constant_law():
+    """Sec. 4, critical engulfing: a fluid-0 disk (R_r = 60) inside a fluid-1 disk (R_g = 80),
+    internally tangent, in fluid 2, sigma_rg = sigma_gb = 0.01, sigma_rb = 0.02 (critical:
+    complete engulfing, no rb interface), 50000 steps.  With the paper's law the rb
+    interface shrinks to a few mixed nodes; with the constant beta of Eq. (17) fluid 0
+    stays exposed to fluid 2 along an arc (hundreds of mixed nodes)."""
+    w = inputs.engulfed_droplet(300, 60.0, 80.0, (0.01, 0.02, 0.01))
+    n = {law: mixed_nodes(_run(w, law, 50000), 0, 2) for law in ("paper", "constant")}
+    print("rb mixed nodes:", n)
+    assert n["paper"] < 0.15 * n["constant"] and n["constant"] > 200
