@@ -80,8 +80,9 @@ enum {
  *                 operator Phi_i = sum_k sum_{l != k} (A_kl C_kl / 2) |G_kl|
  *                 [w_i (e_i . G_kl)^2 / |G_kl|^2 - B_i] with A_kl = A_lk = 9 sigma_kl /
  *                 (2 tau) at the node's own tau (Eqs. 10-11), B_0 = -4/27,
- *                 B_1-4 = 2/27, B_5-8 = 5/108, and u = sum_i f_i e_i / rho.  Single
- *                 steps only (one launch per step), no batch, no adjoint. */
+ *                 B_1-4 = 2/27, B_5-8 = 5/108, and u = sum_i f_i e_i / rho.  Every
+ *                 launch form (one or two steps per launch, the batch when all its
+ *                 instances use it); no adjoint. */
 enum {
     LBM3_FORCING_GUO = 0,
     LBM3_FORCING_PERTURBATION = 1
@@ -175,8 +176,7 @@ int lbm3_get_tile(const lbm3_t *h, int32_t *threads, int32_t *rows);
  * step of an FP64 or FP32 state loaded in 27-population form runs alone) and needs
  * a tile width (lbm3_set_tile's threads) of at most 256; otherwise, and for the
  * odd last step, a one-step launch runs.  Results do not depend on the mode
- * (bitwise).  EINVAL for another mode; EUNSUPPORTED for 2 with
- * LBM3_FORCING_PERTURBATION (single steps only). */
+ * (bitwise).  EINVAL for another mode. */
 int lbm3_set_steps_per_launch(lbm3_t *h, int32_t mode);
 /* The launch lbm3_step uses for pairs of steps: *steps = 2 with its threads per
  * workgroup and workgroup count, or *steps = 1 (and zeros) when pairs run as two
@@ -204,8 +204,8 @@ int lbm3_state_buffer(const lbm3_t *h, void **dev_ptr, int32_t *elem_bytes, int6
  * parameters and size, all of one precision, held in one device arena.
  *
  * lbm3_batch_create: p[0..count-1] as for lbm3_create (each validated; mixed
- *   precisions give EINVAL; LBM3_FORCING_PERTURBATION gives EUNSUPPORTED; segregation
- *   laws may differ between instances).  hip_stream as for lbm3_create; NULL makes the batch
+ *   precisions or forcings give EINVAL; segregation laws may differ between
+ *   instances).  hip_stream as for lbm3_create; NULL makes the batch
  *   create and own a stream (graph capture needs one).  *out is NULL on failure.
  * lbm3_batch_init_fields: instance idx (0..count-1) from host rho [3][ny][nx] and
  *   u [2][ny][nx] or NULL, as lbm3_init_fields.  Blocking.  May be called again

@@ -253,8 +253,7 @@ int upload_plan(lbm3* h)
     // passes.
     const int64_t min2 = (int64_t)1 << (h->prec == Prec::F64 ? 18 : 20);
     const bool big = (int64_t)h->kp.nx * h->kp.ny >= min2;
-    // (the perturbation operator of Eqs. 4-5 runs as single steps only)
-    const bool want2 = h->p.forcing == LBM3_FORCING_GUO && (h->pass_mode == 2 || (h->pass_mode == 0 && big));
+    const bool want2 = h->pass_mode == 2 || (h->pass_mode == 0 && big);
     int t2 = h->tile_set ? h->threads : (h->kp.nx < 768 ? 64 : 256);
     const int slots2 = want2 ? device_slots_pair(h->prec, t2) : 0;
     if (slots2 > 0) {
@@ -299,9 +298,9 @@ int step_handle(lbm3* h, int64_t n, bool factored)
         hipError_t e;
         int done = 1;
         const bool pt = h->p.forcing == LBM3_FORCING_PERTURBATION;
-        if (!pt && h->fmt == steady_fmt(h->prec) && n >= 2 && h->ntiles2 > 0) {
+        if (h->fmt == steady_fmt(h->prec) && n >= 2 && h->ntiles2 > 0) {
             e = launch_pair(h->prec, h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst, h->dtiles2, h->ntiles2,
-                            h->threads2, h->step, h->stream);
+                            h->threads2, h->step, h->stream, pt);
             done = 2;
         } else {
             const Fmt out = factored ? Fmt::FAC : Fmt::F27;
@@ -601,10 +600,6 @@ int lbm3_set_steps_per_launch(lbm3_t* h, int32_t mode)
     if (mode < 0 || mode > 2) {
         set_error("mode must be 0 (automatic), 1 or 2");
         return LBM3_EINVAL;
-    }
-    if (mode == 2 && h->p.forcing != LBM3_FORCING_GUO) {
-        set_error("two steps per launch are provided for the force of Eq. (7) with Guo's term only");
-        return LBM3_EUNSUPPORTED;
     }
     const int old = h->pass_mode;
     h->pass_mode = mode;

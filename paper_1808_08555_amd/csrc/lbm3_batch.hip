@@ -32,6 +32,7 @@ struct lbm3_batch {
     int64_t step = 0;
     int threads = 256;
     bool tile_set = false;  // threads chosen by lbm3_batch_set_tile (then also the two-step width)
+    bool pt = false;        // every instance uses the perturbation operator of Eqs. (4)-(5)
     std::map<int, int> rows_by_side;  // rows per segment for instances with nx == side
     tcg::Tile* dtiles = nullptr;      // step list, XCD-ordered
     int ntiles = 0;
@@ -177,10 +178,10 @@ static hipError_t launch_steady(lbm3_batch* b, int c, bool two, int64_t step)
 {
     if (two)
         return launch_pair(b->prec, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles2, b->ntiles2, b->threads2, step,
-                           b->stream);
+                           b->stream, b->pt);
     const Fmt sf = steady_fmt(b->prec);
     return launch_tiles(b->prec, sf, sf, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles, b->ntiles, b->threads,
-                        step, 0, b->stream);
+                        step, 0, b->stream, b->pt);
 }
 
 // Captures launches worth kGraphSteps steps starting from buffer `parity` (an even number
@@ -252,9 +253,9 @@ int lbm3_batch_create(const lbm3_params* p, int32_t count, void* hip_stream, lbm
             set_error("all instances of a batch must have the same precision");
             return LBM3_EINVAL;
         }
-        if (p[i].forcing != LBM3_FORCING_GUO) {
-            set_error("the batched form runs the force of Eq. (7) with Guo's term only (instance %d)", i);
-            return LBM3_EUNSUPPORTED;
+        if (p[i].forcing != p[0].forcing) {
+            set_error("all instances of a batch must have the same forcing (instance %d)", i);
+            return LBM3_EINVAL;
         }
     }
     lbm3_batch* b = new (std::nothrow) lbm3_batch();
@@ -264,6 +265,7 @@ int lbm3_batch_create(const lbm3_params* p, int32_t count, void* hip_stream, lbm
     }
     b->count = count;
     b->prec = prec_of(p[0].precision);
+    b->pt = p[0].forcing == LBM3_FORCING_PERTURBATION;
     b->inst.resize(count);
     b->ready.assign(count, 0);
     b->fmt.assign(count, Fmt::F27);
@@ -413,12 +415,12 @@ int lbm3_batch_step(lbm3_batch_t* b, int64_t n)
                 if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
                 if (e == hipSuccess)
                     e = launch_tiles(b->prec, Fmt::FAC, Fmt::FAC, b->buf[b->cur], b->buf[b->cur ^ 1],
-                                     b->dinst, b->dtiles, b->ntiles, b->threads, b->step, 1, b->stream);
+                                     b->dinst, b->dtiles, b->ntiles, b->threads, b->step, 1, b->stream, b->pt);
             }
             if (e == hipSuccess)
                 e = launch_tiles(b->prec, Fmt::F27, Fmt::FAC, b->buf[b->cur], b->buf[b->cur ^ 1],
                                  b->dinst, b->dtiles, b->ntiles, b->threads, b->step,
-                                 n27 < b->count ? 1 : 0, b->stream);
+                                 n27 < b->count ? 1 : 0, b->stream, b->pt);
             if (e != hipSuccess) return hip_fail(e, "batch step launch");
             for (auto& f : b->fmt) f = Fmt::FAC;
             b->cur ^= 1;
@@ -475,7 +477,7 @@ int lbm3_batch_observables(lbm3_batch_t* b, int32_t idx, lbm3_obs* out, double* 
     }
     hipError_t e = launch_observe_tiles(b->prec, b->fmt[idx], b->buf[b->cur], b->dinst,
                                         b->dobs + b->obs_first[idx], nb, b->threads, b->partials,
-                                        rho_out ? b->staging : nullptr, b->stream);
+                                        rho_out ? b->staging : nullptr, b->stream, b->pt);
     if (e == hipSuccess) e = launch_reduce_obs(b->partials, nb, b->obs_dev, b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->obs_host, b->obs_dev, kObsFields * sizeof(double), hipMemcpyDeviceToHost, b->stream);

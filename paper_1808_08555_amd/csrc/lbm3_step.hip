@@ -156,14 +156,14 @@ uint32_t step_salt(int64_t step)
 }
 
 hipError_t launch_pair(Prec prec, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
-                       int ntiles, int threads, int64_t step, hipStream_t stream)
+                       int ntiles, int threads, int64_t step, hipStream_t stream, bool pt)
 {
     switch (prec) {
-        case Prec::F64: return tiles_f64_pair(fin, fout, inst, tiles, ntiles, threads, stream);
-        case Prec::F32: return tiles_f32_pair(fin, fout, inst, tiles, ntiles, threads, stream);
+        case Prec::F64: return tiles_f64_pair(fin, fout, inst, tiles, ntiles, threads, pt, stream);
+        case Prec::F32: return tiles_f32_pair(fin, fout, inst, tiles, ntiles, threads, pt, stream);
         case Prec::F32S:
             return tiles_f32s_pair(fin, fout, inst, tiles, ntiles, threads, step_salt(step), step_salt(step + 1),
-                                   stream);
+                                   pt, stream);
     }
     return hipErrorInvalidValue;
 }

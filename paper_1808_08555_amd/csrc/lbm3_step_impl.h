@@ -495,6 +495,23 @@ __device__ __forceinline__ void force_at_lane(const C (*tring)[3][NT], int s0, i
     Fy = d[1][0] + d[2][1];  // d_x T_xy + d_y T_yy
 }
 
+// Stage 3's input to the collision at lane t: the force (force_at_lane), or with PT no force
+// and the lane's own stress from the middle ring row, all that the perturbation operator
+// of Eqs. (4)-(5) needs.
+template <typename C, int NT, bool PT>
+__device__ __forceinline__ void force_or_stress(const C (*tring)[3][NT], int s0, int s1, int s2, int t,
+                                                C& Fx, C& Fy, C (&Tn)[3])
+{
+    if constexpr (PT) {
+        Fx = C(0);
+        Fy = C(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Tn[a] = tring[s2][a][t];
+    } else {
+        force_at_lane<C, NT>(tring, s0, s1, s2, t, Fx, Fy);
+    }
+}
+
 // The y-marching body shared by the stepping and observing kernels.  The workgroup owns
 // output columns [x0, x0 + cols) (cols <= NT - 6) and output rows [y0, y0 + rows).  Lane t
 // sits on column x0 - 3 + t; lanes 1..cols+4 form densities, 2..cols+3 gradients and
@@ -700,14 +717,8 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
         // ---- stage 3: force, collision, recolouring of row j-2 (fB, rB, nB)
         if (j >= 4 && in3) {
             const int yo = y0 + j - 4;
-            C Fx = C(0), Fy = C(0), Tn[3];
-            if constexpr (PT) {
-                // the perturbation operator needs only this node's stress (middle ring row)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) Tn[a] = tring[s2][a][t];
-            } else {
-                force_at_lane<C, NT>(tring, s0, s1, s2, t, Fx, Fy);
-            }
+            C Fx, Fy, Tn[3];
+            force_or_stress<C, NT, PT>(tring, s0, s1, s2, t, Fx, Fy, Tn);
             if constexpr (TAPE) {
                 const int64_t N = (int64_t)nx * ny, o = (int64_t)yo * nx + x;
                 rho_out[18 * N + o] = double(Fx);
@@ -814,7 +825,7 @@ struct alignas(16) PairLds {
     C xB[18][NT];    // A's recoloured row: f_dag (0-8), c_k (9-11), V_k (12-17)
 };
 
-template <typename C, int NT>
+template <typename C, int NT, bool PT = false>
 __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KParams& kp, int x0, int y0,
                                             int rows, int cols, PairLds<C, NT>& L, int t)
 {
@@ -919,8 +930,9 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
         // phase 2: recolour row y0 - 7 + j into xB
         if (live && j >= 4 && a3) {
             C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
-            force_at_lane<C, NT>(L.tA, s0, s1, s2, t, Fx, Fy);
-            collide_recolour<C>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
+            C Tn[3];
+            force_or_stress<C, NT, PT>(L.tA, s0, s1, s2, t, Fx, Fy, Tn);
+            collide_recolour<C, PT>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
 #pragma unroll
             for (int i = 0; i < 9; ++i) L.xB[i][t] = fd[i];
 #pragma unroll
@@ -948,7 +960,7 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
 // completes the densities of row y0 - 2 + m (partial sums only for m = -2, -1), its stage 2
 // forms the stress of row y0 - 3 + m and its stage 3 outputs row y0 - 4 + m.  Row m runs in
 // iteration m + 7, one iteration after A recoloured its source row into xB.
-template <typename C, int NT>
+template <typename C, int NT, bool PT = false>
 __device__ __forceinline__ void pair_step_b(C* __restrict__ fout, const KParams& kp, int x0, int y0,
                                             int rows, int cols, PairLds<C, NT>& L, int t)
 {
@@ -1014,8 +1026,9 @@ __device__ __forceinline__ void pair_step_b(C* __restrict__ fout, const KParams&
         if (live && m >= 4 && b3) {
             const int yo = y0 - 4 + m;
             C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
-            force_at_lane<C, NT>(L.tB, s0, s1, s2, t, Fx, Fy);
-            collide_recolour<C>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
+            C Tn[3];
+            force_or_stress<C, NT, PT>(L.tB, s0, s1, s2, t, Fx, Fy, Tn);
+            collide_recolour<C, PT>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
             const int64_t orow = (int64_t)yo * kp.fpitch;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st_at(fout + ((int64_t)i * plane + orow), xoff, fd[i]);
@@ -1049,7 +1062,7 @@ __device__ __forceinline__ void pair_step_b(C* __restrict__ fout, const KParams&
 // source columns); B forms densities on lanes 4..cols+7 and outputs lanes 6..cols+5, so
 // cols <= NT - 12.  A runs six rows ahead: iteration j consumes A's source row y0 - 4 + j,
 // A recolours row y0 - 7 + j, B consumes that row at once and outputs row y0 - 10 + j.
-template <typename C, int NT>
+template <typename C, int NT, bool PT = false>
 __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict__ fout,
                                        const KParams& kp, int x0, int y0, int rows, int cols,
                                        C (*cA)[3][NT], C (*tA)[3][NT], C (*xA)[9][NT],
@@ -1166,8 +1179,9 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
         // ---- A stage 3: recolour row y0 - 7 + j into B's exchange row
         if (j >= 4 && a3) {
             C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
-            force_at_lane<C, NT>(tA, sa0, sa1, sa2, t, Fx, Fy);
-            collide_recolour<C>(fB_a, rB_a, nB_a, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
+            C Tn[3];
+            force_or_stress<C, NT, PT>(tA, sa0, sa1, sa2, t, Fx, Fy, Tn);
+            collide_recolour<C, PT>(fB_a, rB_a, nB_a, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
 #pragma unroll
             for (int i = 0; i < 9; ++i) xB[i][t] = fd[i];
 #pragma unroll
@@ -1217,8 +1231,9 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
         if (jb >= 4 && b3) {
             const int yo = y0 - 4 + jb;
             C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
-            force_at_lane<C, NT>(tB, sb0, sb1, sb2, t, Fx, Fy);
-            collide_recolour<C>(fB_b, rB_b, nB_b, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
+            C Tn[3];
+            force_or_stress<C, NT, PT>(tB, sb0, sb1, sb2, t, Fx, Fy, Tn);
+            collide_recolour<C, PT>(fB_b, rB_b, nB_b, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
             const int64_t orow = (int64_t)yo * kp.fpitch;
             const int64_t pl = fresh_stride(plane);
 #pragma unroll
@@ -1266,7 +1281,7 @@ struct alignas(16) Pair27Lds {
     float ring[3][27][NT];  // A's rows as stored: population 9k + i, by row mod 3
 };
 
-template <int NT>
+template <int NT, bool PT = false>
 __device__ __forceinline__ void pair27_step_a(const float* __restrict__ fin, const KParams& kp, int x0, int y0,
                                               int rows, int cols, Pair27Lds<NT>& L, int t, uint32_t salt)
 {
@@ -1348,8 +1363,9 @@ __device__ __forceinline__ void pair27_step_a(const float* __restrict__ fin, con
             const uint32_t yo = (uint32_t)wrapi(y0 - 7 + j, ny);
             const uint32_t key = (yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt;
             C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
-            force_at_lane<C, NT>(L.tA, s0, s1, s2, t, Fx, Fy);
-            collide_recolour<C>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
+            C Tn[3];
+            force_or_stress<C, NT, PT>(L.tA, s0, s1, s2, t, Fx, Fy, Tn);
+            collide_recolour<C, PT>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -1375,7 +1391,7 @@ __device__ __forceinline__ void pair27_step_a(const float* __restrict__ fin, con
     }
 }
 
-template <int NT>
+template <int NT, bool PT = false>
 __device__ __forceinline__ void pair27_step_b(float* __restrict__ fout, const KParams& kp, int x0, int y0, int rows,
                                               int cols, Pair27Lds<NT>& L, int t, uint32_t salt)
 {
@@ -1441,8 +1457,9 @@ __device__ __forceinline__ void pair27_step_b(float* __restrict__ fout, const KP
             const int yo = y0 - 4 + jb;
             const uint32_t key = ((uint32_t)yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt;
             C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
-            force_at_lane<C, NT>(L.tB, s0, s1, s2, t, Fx, Fy);
-            collide_recolour<C>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh);
+            C Tn[3];
+            force_or_stress<C, NT, PT>(L.tB, s0, s1, s2, t, Fx, Fy, Tn);
+            collide_recolour<C, PT>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
             const int64_t orow = (int64_t)yo * kp.pitch;
             const int64_t pl = fresh_stride(plane);
 #pragma unroll
@@ -1629,7 +1646,7 @@ hipError_t tiles_any(Fmt in, Fmt out, bool obs, bool pt, const void* fin, void* 
 // Two fused steps over a list of tiles; tiles come from a plan with cols <= NT - 12.  The
 // workgroup has 2 NT lanes: waves of lanes 0..NT-1 run step A, the others step B (the
 // choice is uniform per wave).
-template <typename C, int NT>
+template <typename C, int NT, bool PT = false>
 __global__ __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles2w(
     const C* __restrict__ fin, C* __restrict__ fout, const Instance* __restrict__ inst,
     const Tile* __restrict__ tiles)
@@ -1641,14 +1658,14 @@ __global__ __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(2))) voi
     const int64_t off = inst[tl.inst].offset;
     const int lane0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x);
     if (lane0 < NT)
-        pair_step_a<C, NT>(fin + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x);
+        pair_step_a<C, NT, PT>(fin + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x);
     else
-        pair_step_b<C, NT>(fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x - NT);
+        pair_step_b<C, NT, PT>(fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x - NT);
 }
 
 // Two fused steps over a list of tiles, one thread per column carrying both (march2);
 // tiles come from a plan with cols <= NT - 12.
-template <typename C, int NT>
+template <typename C, int NT, bool PT = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_tiles2f(
     const C* __restrict__ fin, C* __restrict__ fout, const Instance* __restrict__ inst,
     const Tile* __restrict__ tiles)
@@ -1660,33 +1677,42 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
     const Tile tl = tiles[blockIdx.x];
     const KParams kp = inst[tl.inst].kp;
     const int64_t off = inst[tl.inst].offset;
-    march2<C, NT>(fin + off, fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, ringsA[0], ringsA[1], xA,
+    march2<C, NT, PT>(fin + off, fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, ringsA[0], ringsA[1], xA,
                   ringsB[0], ringsB[1], xB);
 }
 
 // The two-step pass: FP64 wave-specialised (k_tiles2w, 2 x threads lanes), FP32 with one
-// thread per column (k_tiles2f, threads lanes); `threads` is the tile width basis NT.
-template <typename C, int NT>
+// thread per column (k_tiles2f, threads lanes); `threads` is the tile width basis NT.  pt:
+// the perturbation operator of Eqs. (4)-(5) in place of the force and Guo's term.
+template <typename C, int NT, bool PT>
 hipError_t pair_launch(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
                        hipStream_t st)
 {
     if constexpr (sizeof(C) == 8)
-        hipLaunchKernelGGL((k_tiles2w<C, NT>), dim3(ntiles), dim3(2 * NT), 0, st, (const C*)fin, (C*)fout,
+        hipLaunchKernelGGL((k_tiles2w<C, NT, PT>), dim3(ntiles), dim3(2 * NT), 0, st, (const C*)fin, (C*)fout,
                            inst, tiles);
     else
-        hipLaunchKernelGGL((k_tiles2f<C, NT>), dim3(ntiles), dim3(NT), 0, st, (const C*)fin, (C*)fout, inst,
+        hipLaunchKernelGGL((k_tiles2f<C, NT, PT>), dim3(ntiles), dim3(NT), 0, st, (const C*)fin, (C*)fout, inst,
                            tiles);
     return hipGetLastError();
 }
 
+template <typename C, int NT>
+hipError_t pair_launch_pt(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                          bool pt, hipStream_t st)
+{
+    return pt ? pair_launch<C, NT, true>(fin, fout, inst, tiles, ntiles, st)
+              : pair_launch<C, NT, false>(fin, fout, inst, tiles, ntiles, st);
+}
+
 template <typename C>
 hipError_t tiles_pair_any(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
-                          int ntiles, int threads, hipStream_t st)
+                          int ntiles, int threads, bool pt, hipStream_t st)
 {
     switch (threads) {
-        case 64: return pair_launch<C, 64>(fin, fout, inst, tiles, ntiles, st);
-        case 128: return pair_launch<C, 128>(fin, fout, inst, tiles, ntiles, st);
-        case 256: return pair_launch<C, 256>(fin, fout, inst, tiles, ntiles, st);
+        case 64: return pair_launch_pt<C, 64>(fin, fout, inst, tiles, ntiles, pt, st);
+        case 128: return pair_launch_pt<C, 128>(fin, fout, inst, tiles, ntiles, pt, st);
+        case 256: return pair_launch_pt<C, 256>(fin, fout, inst, tiles, ntiles, pt, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1716,7 +1742,7 @@ int pair_occupancy(int threads)
 
 // The 27-population two-step pass (FP32 storage), salts of the two steps' stochastic
 // rounding; a workgroup of 2 NT lanes as in k_tiles2w.
-template <int NT>
+template <int NT, bool PT = false>
 __global__ __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles2s(
     const float* __restrict__ fin, float* __restrict__ fout, const Instance* __restrict__ inst,
     const Tile* __restrict__ tiles, uint32_t salt_a, uint32_t salt_b)
@@ -1729,31 +1755,37 @@ __global__ __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(2))) voi
     const uint32_t mixi = mix32((uint32_t)tl.inst * 0x9E3779B9U + 0x51ed270bU);
     const int lane0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x);
     if (lane0 < NT)
-        pair27_step_a<NT>(fin + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x, salt_a ^ mixi);
+        pair27_step_a<NT, PT>(fin + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x, salt_a ^ mixi);
     else
-        pair27_step_b<NT>(fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x - NT, salt_b ^ mixi);
+        pair27_step_b<NT, PT>(fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x - NT, salt_b ^ mixi);
+}
+
+template <int NT, bool PT>
+hipError_t pair27_launch(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                         uint32_t salt_a, uint32_t salt_b, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_tiles2s<NT, PT>), dim3(ntiles), dim3(2 * NT), 0, st, (const float*)fin, (float*)fout, inst,
+                       tiles, salt_a, salt_b);
+    return hipGetLastError();
+}
+
+template <bool PT>
+hipError_t tiles_pair27_pt(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                           int threads, uint32_t salt_a, uint32_t salt_b, hipStream_t st)
+{
+    switch (threads) {
+        case 64: return pair27_launch<64, PT>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, st);
+        case 128: return pair27_launch<128, PT>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, st);
+        case 256: return pair27_launch<256, PT>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 inline hipError_t tiles_pair27_any(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
-                                   int threads, uint32_t salt_a, uint32_t salt_b, hipStream_t st)
+                                   int threads, uint32_t salt_a, uint32_t salt_b, bool pt, hipStream_t st)
 {
-    switch (threads) {
-        case 64:
-            hipLaunchKernelGGL((k_tiles2s<64>), dim3(ntiles), dim3(128), 0, st, (const float*)fin, (float*)fout, inst,
-                               tiles, salt_a, salt_b);
-            break;
-        case 128:
-            hipLaunchKernelGGL((k_tiles2s<128>), dim3(ntiles), dim3(256), 0, st, (const float*)fin, (float*)fout, inst,
-                               tiles, salt_a, salt_b);
-            break;
-        case 256:
-            hipLaunchKernelGGL((k_tiles2s<256>), dim3(ntiles), dim3(512), 0, st, (const float*)fin, (float*)fout, inst,
-                               tiles, salt_a, salt_b);
-            break;
-        default:
-            return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return pt ? tiles_pair27_pt<true>(fin, fout, inst, tiles, ntiles, threads, salt_a, salt_b, st)
+              : tiles_pair27_pt<false>(fin, fout, inst, tiles, ntiles, threads, salt_a, salt_b, st);
 }
 
 inline int pair27_occupancy(int threads)

@@ -14,9 +14,9 @@ hipError_t tiles_f32(Fmt in, Fmt out, bool obs, bool pt, const void* fin, void* 
 int tiles_f32_occupancy(int threads) { return tiles_occupancy<float, float>(threads); }
 
 hipError_t tiles_f32_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
-                          int ntiles, int threads, hipStream_t stream)
+                          int ntiles, int threads, bool pt, hipStream_t stream)
 {
-    return tiles_pair_any<float>(fin, fout, inst, tiles, ntiles, threads, stream);
+    return tiles_pair_any<float>(fin, fout, inst, tiles, ntiles, threads, pt, stream);
 }
 
 int tiles_f32_pair_occupancy(int threads) { return pair_occupancy<float>(threads); }

@@ -14,9 +14,9 @@ hipError_t tiles_f32s(Fmt in, Fmt out, bool obs, bool pt, const void* fin, void*
 int tiles_f32s_occupancy(int threads) { return tiles_occupancy<float, double>(threads); }
 
 hipError_t tiles_f32s_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
-                           int threads, uint32_t salt_a, uint32_t salt_b, hipStream_t stream)
+                           int threads, uint32_t salt_a, uint32_t salt_b, bool pt, hipStream_t stream)
 {
-    return tiles_pair27_any(fin, fout, inst, tiles, ntiles, threads, salt_a, salt_b, stream);
+    return tiles_pair27_any(fin, fout, inst, tiles, ntiles, threads, salt_a, salt_b, pt, stream);
 }
 
 int tiles_f32s_pair_occupancy(int threads) { return pair27_occupancy(threads); }

@@ -26,9 +26,9 @@ hipError_t tiles_f64_tape(Fmt in, const void* fin, void* fout, const Instance* i
 }
 
 hipError_t tiles_f64_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
-                          int ntiles, int threads, hipStream_t stream)
+                          int ntiles, int threads, bool pt, hipStream_t stream)
 {
-    return tiles_pair_any<double>(fin, fout, inst, tiles, ntiles, threads, stream);
+    return tiles_pair_any<double>(fin, fout, inst, tiles, ntiles, threads, pt, stream);
 }
 
 int tiles_f64_pair_occupancy(int threads) { return pair_occupancy<double>(threads); }

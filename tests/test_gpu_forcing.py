@@ -1,6 +1,7 @@
 """The comparison forcing (the perturbation operator of Eqs. 4-5) on the GPU through the C
-ABI: parity with the FP64 oracle, its refusals, and the comparison of Table 2 (the paper's
-forcing gives the smaller spurious velocities)."""
+ABI: parity with the FP64 oracle, every launch form (two steps per launch and the batch
+bitwise equal to single steps), the adjoint's refusal, and the comparison of Table 2 (the
+paper's forcing gives the smaller spurious velocities; the perturbation row reproduced)."""
 import json
 import os
 
@@ -23,7 +24,6 @@ def _gpu(nx, ny, rho, steps, sigma=SIG, tau=TAU, precision="fp64", tile=None, la
     try:
         if tile:
             L.set_tile(*tile)
-        assert lbm3.lbm3_get_pair_launch(L.h)[0] == 1
         return L.step(steps).state()
     finally:
         L.close()
@@ -91,22 +91,76 @@ def test_observables_use_the_force_free_velocity():
     assert abs(obs["u_max"] / ref["u_max"] - 1) < 1e-9
 
 
-def test_large_lattices_stay_on_single_steps_and_refusals():
-    rho = inputs.random_mixture(1024, 512, 1, tiny_fraction=0.0)
-    L = lbm3.Lattice(1024, 512, SIG, TAU, forcing=PT).init(rho)
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_storage"])
+def test_two_step_pass_equals_single_steps_bitwise(precision):
+    nx, ny = 97, 130
+    rho = inputs.random_mixture(nx, ny, 5, tiny_fraction=0.0)
+    out = []
+    for mode in (1, 2):
+        L = lbm3.Lattice(nx, ny, SIG, TAU, precision=precision, forcing=PT).init(rho)
+        L.set_tile(64, 9)
+        L.set_steps_per_launch(mode)
+        assert lbm3.lbm3_get_pair_launch(L.h)[0] == mode
+        out.append(L.step(12).state())
+        L.close()
+    assert np.isfinite(out[0]).all() and np.array_equal(out[0], out[1])
+
+
+def test_full_size_default_launch_pairs_and_matches_the_oracle_on_sampled_nodes():
+    """1024 x 512 (2^19 nodes, two steps per launch by default): 21 steps (ten two-step
+    launches after the first single step), then one more step compared with the oracle's
+    node-local step at sampled nodes, to 1e-11."""
+    nx, ny = 1024, 512
+    w = inputs.double_droplet(512, 60.0, 1.0, 1.3, seed=8, steps=0)
+    rho = np.concatenate([w.rho, w.rho], axis=2)
+    L = lbm3.Lattice(nx, ny, SIG, TAU, forcing=PT).init(rho)
     try:
-        assert lbm3.lbm3_get_pair_launch(L.h)[0] == 1  # 2^19 nodes: Guo forcing would pair
-        with pytest.raises(lbm3.Lbm3Error) as e:
-            L.set_steps_per_launch(2)
-        assert e.value.code == lbm3.LBM3_EUNSUPPORTED
+        assert lbm3.lbm3_get_pair_launch(L.h)[0] == 2
+        fa = L.step(21).state()
+        fb = L.step(1).state()
+    finally:
+        L.close()
+    rng = np.random.default_rng(3)
+    xs = np.concatenate([[0, nx - 1, 511, 512], rng.integers(0, nx, 80)])
+    ys = np.concatenate([[0, ny - 1, 255, 256], rng.integers(0, ny, 80)])
+    p = oracle.Params(nx, ny, SIG, TAU, forcing=PT)
+    o = oracle.step_nodes(p, fa, xs, ys)
+    assert np.abs(fb[:, :, ys, xs].transpose(2, 0, 1) - o).max() <= 1e-11
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_matches_plain_lattices_bitwise(precision):
+    """Three instances with the perturbation operator in one batch, 41 steps (graph launches
+    and eager ones): each equals the plain lattice run alone, bitwise."""
+    ws = [inputs.double_droplet(n, n / 5.0, 1.0, 1.3, seed=40 + n, steps=0) for n in (40, 57, 64)]
+    ps = [lbm3.make_params(w.nx, w.ny, SIG, TAU, precision=precision, forcing=PT) for w in ws]
+    b = lbm3.lbm3_batch_create(ps)
+    try:
+        for i, w in enumerate(ws):
+            lbm3.lbm3_batch_init_fields(b, i, w.rho)
+        lbm3.lbm3_batch_step(b, 41)
+        for i, w in enumerate(ws):
+            _, rho = lbm3.lbm3_batch_observables(b, i, w.nx, w.ny, want_rho=True)
+            L = lbm3.Lattice(w.nx, w.ny, SIG, TAU, precision=precision, forcing=PT).init(w.rho).step(41)
+            ref = L.densities()
+            L.close()
+            assert np.array_equal(rho, ref), i
+    finally:
+        lbm3.lbm3_batch_destroy(b)
+
+
+def test_refusals():
+    """The adjoint covers the paper's forcing only; a batch takes one forcing."""
+    L = lbm3.Lattice(16, 16, SIG, TAU, forcing=PT).init(inputs.random_mixture(16, 16, 1))
+    try:
         with pytest.raises(lbm3.Lbm3Error) as e:
             lbm3.lbm3_adjoint_record(L.h, 2, 1)
         assert e.value.code == lbm3.LBM3_EUNSUPPORTED
     finally:
         L.close()
     with pytest.raises(lbm3.Lbm3Error) as e:
-        lbm3.lbm3_batch_create([lbm3.make_params(16, 16, forcing=PT)])
-    assert e.value.code == lbm3.LBM3_EUNSUPPORTED
+        lbm3.lbm3_batch_create([lbm3.make_params(16, 16), lbm3.make_params(16, 16, forcing=PT)])
+    assert e.value.code == lbm3.LBM3_EINVAL
 
 
 TABLE2 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table2_umax.json")))
