@@ -210,6 +210,30 @@ def bench_adjoint(torch, lbm3, inputs, n: int, steps: int, every: int):
             "reverse_s": round(t2 - t1, 3), "forward_s": round(t1 - t0, 3)}
 
 
+def bench_d3q19(torch, lbm3, inputs, n: int, steps: int):
+    """The D3Q19 form (FP64) on an n^3 lattice of two tangent spheres, timed with HIP events
+    on the lattice's stream.  Algorithmic bytes: the 57 FP64 populations read and written
+    once per update (912 B)."""
+    st = torch.cuda.current_stream()
+    c = (n - 1) / 2
+    R = n / 8.0
+    rho = inputs.spheres(n, n, n, [(0, c - R, c, c, R), (1, c + R, c, c, R)])
+    L = lbm3.Lattice3D(n, n, n, (0.01, 0.01, 0.01), (1.0, 1.0, 1.0), stream=st).init(rho)
+    L.step(5)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    L.step(steps)
+    b.record(st)
+    torch.cuda.synchronize()
+    t = a.elapsed_time(b) / 1e3
+    L.close()
+    lu = n ** 3 * steps
+    return {"workload": f"D3Q19 {n}^3, two tangent spheres of radius {R:g}, FP64, {steps} steps",
+            "mlups": round(lu / t / 1e6, 1), "bytes_per_lu_stated": 912,
+            "frac_of_peak": round(912 * lu / t / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def cpu_baseline(w, steps: int = 8):
     import oracle
 
@@ -266,6 +290,8 @@ def main():
         # the comparison forcing of Eqs. (4)-(5) on the headline workload and launch form
         pert = bench_plain(torch, lbm3, w, "fp64", 100, 10, forcing="perturbation")
         log(f"perturbation forcing {pert}")
+        d3 = bench_d3q19(torch, lbm3, inputs, 128, 60)
+        log(f"d3q19 {d3}")
         batched = bench_batched(torch, lbm3, inputs, 1000)
         log(f"batched {batched}")
         adjoint = {"janus_256": bench_adjoint(torch, lbm3, inputs, 256, 5000, 100),
@@ -324,6 +350,7 @@ def main():
             "baseline_plain_fp32_equal_nodes_mlups": round(batched["plain_equal_nodes"], 1),
             "baseline_one_launch_per_instance_mlups": round(batched["per_instance_launches"], 1)}
         line["adjoint_fp64"] = adjoint
+        line["d3q19_fp64"] = d3
         line["beta_laws_fp64"] = {
             "workload": "the headline droplet tiling, FP64, 100 timed steps per law",
             **{law: {"mlups": round(v["mlups"], 1), "frac_of_peak": round(v["gbs"] / HBM_PEAK_GBS, 4)}

@@ -261,6 +261,40 @@ int lbm3_batch_destroy(lbm3_batch_t *b);
 int lbm3_adjoint_record(lbm3_t *h, int64_t nsteps, int32_t ckpt_every);
 int lbm3_adjoint(lbm3_t *h, const double *drho1_T, double dsigma[3], double *drho0);
 
+/* ---- three-dimensional form (D3Q19) ---------------------------------------------
+ * The step of Sec. 2 (the model is stated for DmQn lattices) on the standard D3Q19
+ * lattice (c_s^2 = 1/3; w_0 = 1/3, w = 1/18 on the axis links, 1/36 on the edge links):
+ * Eq. (12) as the gradient and the force divergence, the stress pair sum of Eq. (7) as a
+ * 3 x 3 tensor, Guo's term and the velocity of Eqs. (8)-(9), the equilibrium of Eq. (3),
+ * the recolouring of Eq. (13) with any segregation law (beta_law), streaming of Eq. (22);
+ * periodic in x, y and z.  FP64 and the paper's forcing only (else LBM3_EUNSUPPORTED).
+ * lbm3d_create: p as for lbm3_create (nx, ny from it), nz in 1..65535; allocates the
+ *   two 57-population state buffers and the intermediates (about 150 doubles per node).
+ * lbm3d_init_fields: rho host [3][nz][ny][nx] (x fastest), finite, >= 0, with rho > 0 at
+ *   every node; fluid at rest (f_{i,k} = w_i rho_k).  Blocking; resets the step count.
+ * lbm3d_step: enqueues n >= 0 steps on the handle's stream (three launches each).
+ * lbm3d_observables: blocking; masses, momentum sum rho u (Eq. 9 velocity), kinetic
+ *   energy, max |u|, and when non-NULL the densities (host [3][nz][ny][nx]) and the
+ *   post-streaming populations (host [3][19][nz][ny][nx], links in the order: rest,
+ *   +-x, +-y, +-z, then (+1,+1,0), (-1,-1,0), (+1,-1,0), (-1,+1,0), (+1,0,+1), (-1,0,-1),
+ *   (+1,0,-1), (-1,0,+1), (0,+1,+1), (0,-1,-1), (0,+1,-1), (0,-1,+1)).  ENONFINITE when
+ *   the state is not finite.
+ * lbm3d_destroy: releases everything; NULL is accepted. */
+typedef struct lbm3d lbm3d_t;
+typedef struct {
+    int64_t step;
+    double mass[3];
+    double momentum[3];
+    double kinetic_energy;
+    double u_max;
+    int32_t nonfinite;
+} lbm3d_obs;
+int lbm3d_create(const lbm3_params *p, int32_t nz, void *hip_stream, lbm3d_t **out);
+int lbm3d_init_fields(lbm3d_t *h, const double *rho);
+int lbm3d_step(lbm3d_t *h, int64_t n);
+int lbm3d_observables(lbm3d_t *h, lbm3d_obs *out, double *rho_out, double *f_out);
+int lbm3d_destroy(lbm3d_t *h);
+
 /* Plain device copy of nbytes (a multiple of 16) from device src to device dst on
  * hip_stream (NULL = null stream), no host sync: the bandwidth reference the
  * roofline figures are compared with.  EINVAL for NULL pointers or a bad size. */

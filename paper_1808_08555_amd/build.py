@@ -37,7 +37,7 @@ CFLAGS = [
 # fuse multiply-adds across statements there: about 13% faster on 2048^2 lattices.
 PER_FILE = {"lbm3_adjoint.hip": ["-ffp-contract=fast"]}
 SOURCES = ["lbm3_tiles_f64.hip", "lbm3_tiles_f32s.hip", "lbm3_tiles_f32.hip", "lbm3_step.hip",
-           "lbm3_plan.hip", "lbm3_api.hip", "lbm3_batch.hip", "lbm3_adjoint.hip"]
+           "lbm3_plan.hip", "lbm3_api.hip", "lbm3_batch.hip", "lbm3_adjoint.hip", "lbm3d.hip"]
 
 
 def _compile(src: str) -> str:

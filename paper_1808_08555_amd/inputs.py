@@ -269,6 +269,21 @@ def random_mixture(nx: int, ny: int, seed: int, tiny_fraction: float = 0.15) -> 
     return rho
 
 
+def random_mixture_3d(nx: int, ny: int, nz: int, seed: int, tiny_fraction: float = 0.15) -> np.ndarray:
+    """random_mixture on an nx x ny x nz lattice: rho [3, nz, ny, nx]."""
+    return random_mixture(nx, ny * nz, seed, tiny_fraction).reshape(3, nz, ny, nx)
+
+
+def spheres(nx: int, ny: int, nz: int, balls) -> np.ndarray:
+    """Densities [3, nz, ny, nx] of fluid-2 background with balls (fluid, cx, cy, cz, R); later
+    balls win where they overlap."""
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(float)
+    lab = np.full((nz, ny, nx), 2, dtype=np.int64)
+    for k, cx, cy, cz, R in balls:
+        lab[(x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 <= R * R] = k
+    return rho_from_labels(lab)
+
+
 def random_velocity(nx: int, ny: int, seed: int, amp: float = 0.02) -> np.ndarray:
     return amp * (2.0 * uniform01(seed, 2 * nx * ny).reshape(2, ny, nx) - 1.0)
 

@@ -43,6 +43,14 @@ class lbm3_params(ctypes.Structure):
     ]
 
 
+class lbm3d_obs(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64), ("mass", ctypes.c_double * 3),
+        ("momentum", ctypes.c_double * 3), ("kinetic_energy", ctypes.c_double),
+        ("u_max", ctypes.c_double), ("nonfinite", ctypes.c_int32),
+    ]
+
+
 class lbm3_obs(ctypes.Structure):
     _fields_ = [
         ("step", ctypes.c_int64), ("mass", ctypes.c_double * 3),
@@ -101,6 +109,11 @@ def lib():
             "lbm3_adjoint_record": (I, [H, ctypes.c_int64, ctypes.c_int32]),
             "lbm3_adjoint": (I, [H, _DP, _DP, _DP]),
             "lbm3_device_copy": (I, [_VP, _VP, ctypes.c_int64, _VP]),
+            "lbm3d_create": (I, [P, ctypes.c_int32, _VP, ctypes.POINTER(H)]),
+            "lbm3d_init_fields": (I, [H, _DP]),
+            "lbm3d_step": (I, [H, ctypes.c_int64]),
+            "lbm3d_observables": (I, [H, ctypes.POINTER(lbm3d_obs), _DP, _DP]),
+            "lbm3d_destroy": (I, [H]),
         }
         for name, (res, args) in protos.items():
             fn = getattr(L, name)
@@ -373,3 +386,49 @@ class Lattice:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------- D3Q19 form
+class Lattice3D:
+    """Owning wrapper around one lbm3d handle (the D3Q19 form, FP64, periodic)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, sigma=(0.01, 0.01, 0.01), tau=(1.0, 1.0, 1.0),
+                 rho0=(1.0, 1.0, 1.0), beta0: float = 0.7, beta_law="paper", stream=None):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.params = make_params(nx, ny, sigma, tau, rho0, beta0, "fp64", beta_law=beta_law)
+        h = ctypes.c_void_p()
+        _check(lib().lbm3d_create(ctypes.byref(self.params), self.nz, _stream_handle(stream), ctypes.byref(h)),
+               "lbm3d_create")
+        self.h = h
+
+    def init(self, rho):
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        assert rho.shape == (3, self.nz, self.ny, self.nx)
+        _check(lib().lbm3d_init_fields(self.h, _dptr(rho)), "lbm3d_init_fields")
+        return self
+
+    def step(self, n: int = 1):
+        _check(lib().lbm3d_step(self.h, int(n)), "lbm3d_step")
+        return self
+
+    def observables(self, want_rho: bool = False, want_f: bool = False):
+        """(dict, rho [3, nz, ny, nx] or None, f [3, 19, nz, ny, nx] or None); blocking."""
+        o = lbm3d_obs()
+        shape = (self.nz, self.ny, self.nx)
+        rho = np.empty((3,) + shape) if want_rho else None
+        f = np.empty((3, 19) + shape) if want_f else None
+        _check(lib().lbm3d_observables(self.h, ctypes.byref(o), _dptr(rho), _dptr(f)), "lbm3d_observables")
+        d = {"step": int(o.step), "mass": np.array(o.mass[:]), "momentum": np.array(o.momentum[:]),
+             "kinetic_energy": float(o.kinetic_energy), "u_max": float(o.u_max), "nonfinite": int(o.nonfinite)}
+        return d, rho, f
+
+    def state(self) -> np.ndarray:
+        return self.observables(want_f=True)[2]
+
+    def densities(self) -> np.ndarray:
+        return self.observables(want_rho=True)[1]
+
+    def close(self):
+        if self.h is not None:
+            _check(lib().lbm3d_destroy(self.h), "lbm3d_destroy")
+            self.h = None

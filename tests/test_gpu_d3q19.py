@@ -1,0 +1,152 @@
+"""The D3Q19 form through the C ABI (lbm3d_*) against the D3Q19 oracle, which is pinned to
+the two-dimensional oracle (tests/test_oracle_d3q19.py)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import d3q19
+from paper_1808_08555_amd import inputs, lbm3
+
+pytestmark = pytest.mark.gpu
+
+SIG, TAU = (0.011, 0.013, 0.017), (0.7, 1.0, 1.3)
+
+
+def _gpu(rho, steps, sigma=SIG, tau=TAU, law="paper"):
+    nz, ny, nx = rho.shape[1:]
+    L = lbm3.Lattice3D(nx, ny, nz, sigma, tau, beta_law=law).init(rho)
+    try:
+        return L.step(steps).state()
+    finally:
+        L.close()
+
+
+def _oracle(rho, steps, sigma=SIG, tau=TAU, law="paper"):
+    nz, ny, nx = rho.shape[1:]
+    p = oracle.Params(nx, ny, sigma, tau, beta_law=law)
+    return d3q19.run(p, nz, d3q19.init(p, nz, rho), steps)
+
+
+@pytest.mark.parametrize("law", ["paper", "leclaire"])
+def test_parity_random_mixture(law):
+    """13 x 11 x 9 random mixtures (three fluids at most nodes), 10 steps, to 1e-11."""
+    rho = inputs.random_mixture_3d(13, 11, 9, 4, tiny_fraction=0.05)
+    err = np.abs(_gpu(rho, 10, law=law) - _oracle(rho, 10, law=law)).max()
+    print(law, err)
+    assert err <= 1e-11
+
+
+def test_parity_two_spheres_along_the_trajectory():
+    """Tangent spheres of fluids 0 and 1 (R = 6) in fluid 2 on 30 x 26 x 22.  After 50 steps
+    the GPU state equals the oracle's to 1e-11.  Further on, round-off differences of the
+    colour traces grow about 1.1-1.2x per step (measured: 2e-13 at step 50, 4e-9 at 150,
+    6e-5 at 200 for the coloured populations), as in two dimensions, so the longer run is
+    checked one step at a time: from the GPU's own state at steps 150-152, one GPU step
+    equals one oracle step to 1e-15."""
+    rho = inputs.spheres(30, 26, 22, [(0, 9.0, 13.0, 11.0, 6.0), (1, 21.0, 13.0, 11.0, 6.0)])
+    p = oracle.Params(30, 26, SIG, TAU)
+    L = lbm3.Lattice3D(30, 26, 22, SIG, TAU).init(rho)
+    try:
+        g = L.step(50).state()
+        o = d3q19.run(p, 22, d3q19.init(p, 22, rho), 50)
+        assert np.abs(g - o).max() <= 1e-11
+        L.step(100)
+        worst = 0.0
+        for _ in range(3):
+            prev = L.state()
+            worst = max(worst, float(np.abs(L.step(1).state() - d3q19.step(p, 22, prev)).max()))
+        print("one step from the GPU state:", worst)
+        assert worst <= 1e-15
+    finally:
+        L.close()
+
+
+@pytest.mark.parametrize("shape", [(1, 2, 3), (2, 1, 1), (3, 4, 1), (257, 3, 2)])
+def test_parity_degenerate_and_ragged(shape):
+    nx, ny, nz = shape
+    rho = inputs.random_mixture_3d(nx, ny, nz, 21, tiny_fraction=0.0)
+    assert np.abs(_gpu(rho, 5) - _oracle(rho, 5)).max() <= 1e-11
+
+
+def test_uniform_along_z_equals_the_2d_step():
+    """A lattice uniform along z evolves as the two-dimensional lattice (populations summed
+    over the links' z component): GPU against GPU, 300 steps."""
+    w = inputs.double_droplet(48, 9.0, 1.0, 1.3, seed=2, steps=0)
+    rho3 = np.repeat(w.rho[:, None], 4, axis=1)
+    f3 = _gpu(rho3, 300, w.sigma, w.tau)
+    L = lbm3.Lattice(48, 48, w.sigma, w.tau).init(w.rho)
+    f2 = L.step(300).state()
+    L.close()
+    e, _ = d3q19.lattice()
+    EX2, EY2 = [0, 1, 0, -1, 0, 1, -1, -1, 1], [0, 0, 1, 0, -1, 1, 1, -1, -1]
+    proj = np.zeros_like(f2)
+    for q in range(9):
+        for i in range(19):
+            if e[i, 0] == EX2[q] and e[i, 1] == EY2[q]:
+                proj[:, q] += f3[:, i, 0]
+    assert np.abs(proj - f2).max() <= 1e-12
+
+
+def test_observables_match_the_oracle():
+    rho = inputs.spheres(20, 18, 16, [(0, 7.0, 9.0, 8.0, 4.0), (1, 13.0, 9.0, 8.0, 4.0)])
+    L = lbm3.Lattice3D(20, 18, 16, SIG, TAU).init(rho).step(50)
+    obs, r, f = L.observables(want_rho=True, want_f=True)
+    L.close()
+    p = oracle.Params(20, 18, SIG, TAU)
+    o = d3q19.observables(p, 16, f)
+    print(obs, o)
+    assert obs["step"] == 50 and obs["nonfinite"] == 0
+    assert np.abs(obs["mass"] / o["mass"] - 1).max() < 1e-13
+    assert np.abs(obs["momentum"] - o["momentum"]).max() < 1e-12
+    assert abs(obs["kinetic_energy"] / o["kinetic_energy"] - 1) < 1e-9
+    assert abs(obs["u_max"] / o["u_max"] - 1) < 1e-9
+    assert np.abs(r - f.sum(axis=1)).max() < 1e-14
+
+
+def test_error_paths():
+    with pytest.raises(lbm3.Lbm3Error) as e:
+        lbm3.Lattice3D(8, 8, 0)
+    assert e.value.code == lbm3.LBM3_EINVAL
+    p = lbm3.make_params(8, 8, precision="fp32")
+    import ctypes
+    h = ctypes.c_void_p()
+    assert lbm3.lib().lbm3d_create(ctypes.byref(p), 8, None, ctypes.byref(h)) == lbm3.LBM3_EUNSUPPORTED
+    p = lbm3.make_params(8, 8, forcing="perturbation")
+    assert lbm3.lib().lbm3d_create(ctypes.byref(p), 8, None, ctypes.byref(h)) == lbm3.LBM3_EUNSUPPORTED
+    L = lbm3.Lattice3D(8, 8, 8)
+    try:
+        with pytest.raises(lbm3.Lbm3Error) as e:
+            L.step(1)
+        assert e.value.code == lbm3.LBM3_ESTATE
+        bad = np.ones((3, 8, 8, 8))
+        bad[1, 2, 3, 4] = -1.0
+        with pytest.raises(lbm3.Lbm3Error) as e:
+            L.init(bad)
+        assert e.value.code == lbm3.LBM3_EINVAL
+    finally:
+        L.close()
+
+
+def test_sphere_young_laplace():
+    """A sphere of fluid 0 in fluid 2 (48^3, sigma = 0.01, tau = 1, 4000 steps): the pressure
+    jump p_in - p_out (p = rho/3, inside r < R/2, outside r > R + 6) against the
+    three-dimensional Young-Laplace law 2 sigma / R, with R from the sphere's volume:
+    within 4% at R = 12 (measured 2.9%), and closer than at R = 8 (measured 6.2%), as the
+    discretization error falls with the radius."""
+    import math
+    n, ratio = 48, {}
+    for R in (8.0, 12.0):
+        c = (n - 1) / 2
+        L = lbm3.Lattice3D(n, n, n, (0.01, 0.01, 0.01), (1.0, 1.0, 1.0)).init(
+            inputs.spheres(n, n, n, [(0, c, c, c, R)]))
+        obs, r, _ = L.step(4000).observables(want_rho=True)
+        L.close()
+        z, y, x = np.mgrid[0:n, 0:n, 0:n].astype(float)
+        rr = np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2)
+        tot = r.sum(0)
+        Reff = (3 * (r[0] / tot).sum() / (4 * math.pi)) ** (1 / 3)
+        dp = tot[rr < Reff / 2].mean() / 3 - tot[rr > Reff + 6].mean() / 3
+        ratio[R] = dp / (2 * 0.01 / Reff)
+        print(f"R={R}: R_eff={Reff:.3f} dp={dp:.4e} ratio={ratio[R]:.4f} u_max={obs['u_max']:.2e}")
+    assert abs(ratio[12.0] - 1) < 0.04
+    assert abs(ratio[12.0] - 1) < abs(ratio[8.0] - 1)
