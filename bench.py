@@ -255,6 +255,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-plain", action="store_true", help="time the headline workload only")
+    ap.add_argument("--only-d3q19", action="store_true", help="time the D3Q19 form only (its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the step, its batched form and its adjoint run on a "
@@ -266,6 +267,9 @@ def main():
     from paper_1808_08555_amd import inputs, lbm3
 
     torch.cuda.set_device(0)
+    if args.only_d3q19:
+        print(json.dumps({"d3q19_fp64": bench_d3q19(torch, lbm3, inputs, 128, args.steps)}), flush=True)
+        return
     w = inputs.droplet_tiling(4096)
     log(f"workload {w.name}: {w.nx}x{w.ny}, FP64, {args.warmup} warm-up + {args.steps} timed steps")
     args.steps += args.steps % 2
