@@ -4,13 +4,13 @@
 // State: the recoloured populations before streaming, 57 planes B[k][i][z][y][x] (pull
 // scheme: f_{i,k}(x) = B_{i,k}(x - e_i)), two buffers.  A step is three node-parallel
 // kernels:
-//   k3_conc     pull, concentrations c_k and densities rho_k         -> c[6][N]
+//   k3_conc     pull; concentrations c_k, densities rho_k, totals f_i -> c[25][N]
 //   k3_stress   grad c_k (Eq. 12), pair normals, C_kl, stress T      -> T[6][N], n[9][N]
-//   k3_collide  pull, F = div T (Eq. 12 again), collision with Guo's term (Eqs. 1-3, 8-11),
+//   k3_collide  F = div T (Eq. 12 again), collision with Guo's term (Eqs. 1-3, 8-11),
 //               recolouring (Eq. 13 with the segregation law)        -> B'[57][N]
-// Bytes per update: the state read twice and written once (1368 B) plus the intermediates
-// (c and rho 48, T and n 120, each written and read once; neighbour re-reads served by the
-// caches).
+// Bytes per update: the state read and written once (912 B) plus the intermediates (the 25
+// planes of k3_conc and the 15 of k3_stress, each written and read once: 320 B; neighbour
+// re-reads served by the caches).
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -104,6 +104,8 @@ __global__ __launch_bounds__(256) void k3_conc(const double* __restrict__ B, Geo
         c[k * g.N + j] = rk[k] * ir;
         c[(3 + k) * g.N + j] = rk[k];
     }
+#pragma unroll
+    for (int i = 0; i < 19; ++i) c[(6 + i) * g.N + j] = ft[i];
 }
 
 // Stress T = sum_pairs sigma C (|G|^2 I - G G^T)/|G| (xx, xy, xz, yy, yz, zz) and the pair
@@ -168,7 +170,7 @@ __device__ __forceinline__ void force19(const double* __restrict__ T, const Geo3
 }
 
 template <bool OBS>
-__global__ __launch_bounds__(256) void k3_collide(const double* __restrict__ B, const double* __restrict__ T,
+__global__ __launch_bounds__(256) void k3_collide(const double* __restrict__ C6, const double* __restrict__ T,
                                                   const double* __restrict__ nrm, Geo3 g, KParams kp,
                                                   double* __restrict__ Bout, double* __restrict__ partials)
 {
@@ -178,8 +180,12 @@ __global__ __launch_bounds__(256) void k3_collide(const double* __restrict__ B, 
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (x < g.nx) {
         const int64_t j = at3(g, x, y, z);
+        // the densities and totals k3_conc pulled
         double rk[3], ft[19];
-        pull_sums(B, g, x, y, z, ft, rk);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) rk[k] = C6[(3 + k) * g.N + j];
+#pragma unroll
+        for (int i = 0; i < 19; ++i) ft[i] = C6[(6 + i) * g.N + j];
         const double rho = rk[0] + rk[1] + rk[2], irho = 1.0 / rho;
         double F[3];
         force19(T, g, x, y, z, F);
@@ -305,7 +311,7 @@ struct lbm3d {
     Geo3 g{};
     hipStream_t stream = nullptr;
     double* buf[2] = {nullptr, nullptr};
-    double* c = nullptr;        // [6][N]: c_k, then rho_k
+    double* c = nullptr;        // [25][N]: c_k, rho_k, f_i of the pulled state
     double* T = nullptr;        // [6][N]
     double* nrm = nullptr;      // [9][N]
     double* partials = nullptr; // [blocks][8]
@@ -370,7 +376,7 @@ int lbm3d_create(const lbm3_params* p, int32_t nz, void* hip_stream, lbm3d_t** o
     const size_t nblocks = (size_t)gr.x * gr.y * gr.z;
     hipError_t e = hipSuccess;
     for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMalloc(&h->buf[b], (size_t)57 * N * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&h->c, (size_t)6 * N * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&h->c, (size_t)25 * N * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&h->T, (size_t)6 * N * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&h->nrm, (size_t)9 * N * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&h->partials, nblocks * 8 * sizeof(double));
@@ -421,9 +427,8 @@ int lbm3d_step(lbm3d_t* h, int64_t n)
     for (int64_t s = 0; s < n; ++s) {
         hipError_t e = fields3(h);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL((k3_collide<false>), grid3(h->g), dim3(256), 0, h->stream,
-                               (const double*)h->buf[h->cur], (const double*)h->T, (const double*)h->nrm, h->g,
-                               h->kp, h->buf[h->cur ^ 1], nullptr);
+            hipLaunchKernelGGL((k3_collide<false>), grid3(h->g), dim3(256), 0, h->stream, (const double*)h->c,
+                               (const double*)h->T, (const double*)h->nrm, h->g, h->kp, h->buf[h->cur ^ 1], nullptr);
             e = hipGetLastError();
         }
         if (e != hipSuccess) return hip_fail(e, "D3Q19 step launch");
@@ -448,7 +453,7 @@ int lbm3d_observables(lbm3d_t* h, lbm3d_obs* out, double* rho_out, double* f_out
     const int64_t N = h->g.N;
     hipError_t e = fields3(h);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL((k3_collide<true>), gr, dim3(256), 0, h->stream, (const double*)h->buf[h->cur],
+        hipLaunchKernelGGL((k3_collide<true>), gr, dim3(256), 0, h->stream, (const double*)h->c,
                            (const double*)h->T, (const double*)h->nrm, h->g, h->kp, (double*)nullptr, h->partials);
         e = hipGetLastError();
     }
