@@ -80,24 +80,20 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x)
 // and b (away from zero); the result is b with probability (v - a)/(b - a), else a, so its
 // expected value is v.  Round to nearest would lose the sub-ulp per-step changes of the
 // near-uniform bulk with a sign that is the same at many nodes, which shows up as a steady
-// drift of each fluid's mass.  The gap is taken on the correct side of a power of two:
-// values just below one (the concentration of a nearly pure fluid) round on the finer grid
-// below it.
+// drift of each fluid's mass.
+// In the bits of the double, a is v with the 29 mantissa bits that FP32 lacks cleared (the
+// sign is separate, so this is toward zero, in v's own binade); adding a uniform 29-bit r to
+// those bits first carries into the kept bits, giving b, exactly when r >= 2^29 - low bits,
+// that is with probability (v - a)/(b - a).  The sum then converts to float exactly.  Below
+// the smallest normal float (2^-126; zero stays zero) the conversion rounds to nearest;
+// beyond the float range and for NaN the result is that of round to nearest, so overflow
+// still shows as Inf and a NaN stays a NaN.
 __device__ __forceinline__ float round_stochastic(double v, uint32_t bits)
 {
-    // a: the float next to v toward zero (the nearest float, stepped back one ulp in
-    // magnitude when it lies beyond v); b: the float next to a away from zero (adding one to
-    // the magnitude bits; from a signed zero this gives the smallest subnormal of that sign).
-    // Branch-free: with v a float already, rem = 0 and a is returned.  Beyond the float range
-    // (and for NaN) the result is that of round to nearest, so overflow still shows as Inf.
-    const float t = (float)v;
-    const float a = fabs((double)t) > fabs(v) ? __uint_as_float(__float_as_uint(t) - 1u) : t;
-    const float b = __uint_as_float(__float_as_uint(a) + 1u);
-    const double rem = fabs(v - (double)a);
-    const double gap = fabs((double)b - (double)a);
-    const double u = (double)(bits >> 8) * (1.0 / 16777216.0);
-    const float r = u * gap < rem ? b : a;
-    return fabs(v) <= 3.4028234663852886e38 ? r : t;  // overflow and NaN as round to nearest
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint64_t s = (u + (uint64_t)(bits >> 3)) & ~((1ull << 29) - 1ull);
+    const float r = (float)__longlong_as_double((long long)s);
+    return fabs(v) <= 3.4028234663852886e38 ? r : (float)v;
 }
 
 // Store of one value in the storage type S from the compute type C.
