@@ -545,3 +545,38 @@ def test_two_step_pass_equals_single_steps_bitwise(shape, tile, precision):
     B.close()
     assert np.isfinite(fa).all()
     assert np.array_equal(fa, fb)
+
+
+def test_fp32_storage_rounding_brackets_and_is_unbiased():
+    """From a state of floats, one FP32-storage step (FP64 arithmetic) stores a stochastic
+    rounding of what the FP64 step computes from the same state: every stored value is one
+    of the two floats around the FP64 value, it rounds away from zero with the probability of
+    its position between them (fraction rounded up against mean position, within 4 standard
+    errors), and the rounding error in units of the float gap averages to zero."""
+    nx, ny = 256, 192
+    rho = inputs.random_mixture(nx, ny, 12, tiny_fraction=0.0)
+    sig, tau = (0.011, 0.013, 0.017), (0.7, 1.0, 1.3)
+    L = lbm3.Lattice(nx, ny, sig, tau).init(rho).step(3)
+    f = L.state().astype(np.float32).astype(np.float64)
+    L.close()
+    out = {}
+    for prec in ("fp64", "fp32_storage"):
+        M = lbm3.Lattice(nx, ny, sig, tau, precision=prec).set_state(f)
+        out[prec] = M.step(1).state()
+        M.close()
+    A, B = out["fp64"].ravel(), out["fp32_storage"].ravel()
+    t = A.astype(np.float32)
+    toward = np.abs(t.astype(np.float64)) > np.abs(A)
+    lo = np.where(toward, np.nextafter(t, np.float32(0)), t).astype(np.float32)
+    hi = np.nextafter(lo, np.where(A < 0, np.float32(-np.inf), np.float32(np.inf))).astype(np.float32)
+    lo64, hi64 = lo.astype(np.float64), hi.astype(np.float64)
+    assert np.all((B == lo64) | (B == hi64))
+    inexact = A != lo64
+    gap = np.abs(hi64 - lo64)[inexact]
+    pos = np.abs(A[inexact] - lo64[inexact]) / gap
+    up = (B[inexact] == hi64[inexact]).astype(np.float64)
+    n = inexact.sum()
+    se = 0.5 / np.sqrt(n)
+    print(f"{n} rounded values: fraction up {up.mean():.5f}, mean position {pos.mean():.5f}, se {se:.1e}")
+    assert abs(up.mean() - pos.mean()) < 4 * se
+    assert abs(np.mean((B[inexact] - A[inexact]) / gap * np.sign(A[inexact]))) < 4 * se
