@@ -256,6 +256,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-plain", action="store_true", help="time the headline workload only")
     ap.add_argument("--only-d3q19", action="store_true", help="time the D3Q19 form only (its own JSON line)")
+    ap.add_argument("--only-batched", action="store_true", help="time the batched form only (its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the step, its batched form and its adjoint run on a "
@@ -267,6 +268,9 @@ def main():
     from paper_1808_08555_amd import inputs, lbm3
 
     torch.cuda.set_device(0)
+    if args.only_batched:
+        print(json.dumps({"batched_fp32": bench_batched(torch, lbm3, inputs, args.steps)}), flush=True)
+        return
     if args.only_d3q19:
         print(json.dumps({"d3q19_fp64": bench_d3q19(torch, lbm3, inputs, 128, args.steps)}), flush=True)
         return
