@@ -56,6 +56,9 @@ def _params(**kw):
     (dict(precision=7), lbm3.LBM3_EINVAL),
     (dict(boundary=1), lbm3.LBM3_EUNSUPPORTED),
     (dict(wall_wettability=(0.0, 0.5, 0.0)), lbm3.LBM3_EUNSUPPORTED),
+    (dict(beta_law=-1), lbm3.LBM3_EINVAL),
+    (dict(beta_law=4), lbm3.LBM3_EINVAL),
+    (dict(forcing=2), lbm3.LBM3_EINVAL),
 ])
 def test_create_rejects_bad_parameters(kw, code):
     p = _params(**kw)
@@ -126,3 +129,15 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True, text=True)
     assert r.returncode == 3, r.stdout + r.stderr
     assert "no fallback" in r.stdout
+
+
+def test_d3q19_create_rejects_bad_parameters():
+    """Validation happens before any device work, so it runs without a GPU."""
+    h = ctypes.c_void_p(12345)
+    for kw, nz, code in [(dict(), 0, lbm3.LBM3_EINVAL), (dict(), 65536, lbm3.LBM3_EINVAL),
+                         (dict(nx=0), 4, lbm3.LBM3_EINVAL), (dict(precision="fp32"), 4, lbm3.LBM3_EUNSUPPORTED),
+                         (dict(forcing="perturbation"), 4, lbm3.LBM3_EUNSUPPORTED)]:
+        p = _params(**kw)
+        assert lbm3.lib().lbm3d_create(ctypes.byref(p), nz, None, ctypes.byref(h)) == code, (kw, nz)
+        assert h.value is None
+    assert lbm3.lib().lbm3d_destroy(None) == lbm3.LBM3_OK
