@@ -34,24 +34,31 @@ struct Geo3 {
     int64_t N;
 };
 
-__device__ __forceinline__ int wrap3(int a, int n)
-{
-    int r = a % n;
-    return r < 0 ? r + n : r;
-}
-
-__device__ __forceinline__ int64_t at3(const Geo3& g, int x, int y, int z)
-{
-    return ((int64_t)wrap3(z, g.nz) * g.ny + wrap3(y, g.ny)) * g.nx + wrap3(x, g.nx);
-}
+// The node indices of (x, y, z) and its neighbours: the wrapped coordinates at offsets -1,
+// 0, +1 per axis, formed once per node (no division per neighbour).
+struct Nb3 {
+    int64_t zo[3], yo[3];
+    int xo[3];
+    __device__ __forceinline__ Nb3(const Geo3& g, int x, int y, int z)
+    {
+        xo[0] = x == 0 ? g.nx - 1 : x - 1, xo[1] = x, xo[2] = x == g.nx - 1 ? 0 : x + 1;
+        const int y0 = y == 0 ? g.ny - 1 : y - 1, y2 = y == g.ny - 1 ? 0 : y + 1;
+        const int z0 = z == 0 ? g.nz - 1 : z - 1, z2 = z == g.nz - 1 ? 0 : z + 1;
+        yo[0] = (int64_t)y0 * g.nx, yo[1] = (int64_t)y * g.nx, yo[2] = (int64_t)y2 * g.nx;
+        const int64_t pl = (int64_t)g.nx * g.ny;
+        zo[0] = z0 * pl, zo[1] = z * pl, zo[2] = z2 * pl;
+    }
+    // the node at offset (dx, dy, dz), each in -1..1
+    __device__ __forceinline__ int64_t at(int dx, int dy, int dz) const { return zo[dz + 1] + yo[dy + 1] + xo[dx + 1]; }
+};
 
 // The post-streaming populations of node (x, y, z): f_{i,k} = B_{i,k}(x - e_i).
-__device__ __forceinline__ void pull57(const double* __restrict__ B, const Geo3& g, int x, int y, int z,
+__device__ __forceinline__ void pull57(const double* __restrict__ B, const Geo3& g, const Nb3& nb,
                                        double (&f)[3][19])
 {
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
-        const int64_t src = at3(g, x - L3X[i], y - L3Y[i], z - L3Z[i]);
+        const int64_t src = nb.at(-L3X[i], -L3Y[i], -L3Z[i]);
 #pragma unroll
         for (int k = 0; k < 3; ++k) f[k][i] = B[(int64_t)(k * 19 + i) * g.N + src];
     }
@@ -59,13 +66,13 @@ __device__ __forceinline__ void pull57(const double* __restrict__ B, const Geo3&
 
 // The totals f_i and densities rho_k of the pulled populations, summed as they arrive (the
 // single populations are not needed again: collision acts on f_i, recolouring on c_k).
-__device__ __forceinline__ void pull_sums(const double* __restrict__ B, const Geo3& g, int x, int y, int z,
+__device__ __forceinline__ void pull_sums(const double* __restrict__ B, const Geo3& g, const Nb3& nb,
                                           double (&ft)[19], double (&rk)[3])
 {
     rk[0] = rk[1] = rk[2] = 0.0;
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
-        const int64_t src = at3(g, x - L3X[i], y - L3Y[i], z - L3Z[i]);
+        const int64_t src = nb.at(-L3X[i], -L3Y[i], -L3Z[i]);
         const double a = B[(int64_t)i * g.N + src], b = B[(int64_t)(19 + i) * g.N + src],
                      c = B[(int64_t)(38 + i) * g.N + src];
         ft[i] = a + b + c;
@@ -76,13 +83,12 @@ __device__ __forceinline__ void pull_sums(const double* __restrict__ B, const Ge
 }
 
 // Eq. (12) over the nine pairs of opposite links: 3 sum_i w_i e_i [phi(x + e_i) - phi(x - e_i)]
-__device__ __forceinline__ void grad19(const double* __restrict__ phi, const Geo3& g, int x, int y, int z,
-                                       double (&d)[3])
+__device__ __forceinline__ void grad19(const double* __restrict__ phi, const Nb3& nb, double (&d)[3])
 {
     d[0] = d[1] = d[2] = 0.0;
 #pragma unroll
     for (int i = 1; i < 19; i += 2) {
-        const double df = phi[at3(g, x + L3X[i], y + L3Y[i], z + L3Z[i])] - phi[at3(g, x - L3X[i], y - L3Y[i], z - L3Z[i])];
+        const double df = phi[nb.at(L3X[i], L3Y[i], L3Z[i])] - phi[nb.at(-L3X[i], -L3Y[i], -L3Z[i])];
         d[0] += w19(i) * L3X[i] * df;
         d[1] += w19(i) * L3Y[i] * df;
         d[2] += w19(i) * L3Z[i] * df;
@@ -95,10 +101,11 @@ __global__ __launch_bounds__(256) void k3_conc(const double* __restrict__ B, Geo
 {
     const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
+    const Nb3 nb(g, x, y, z);
     double ft[19], rk[3];
-    pull_sums(B, g, x, y, z, ft, rk);
+    pull_sums(B, g, nb, ft, rk);
     const double ir = 1.0 / (rk[0] + rk[1] + rk[2]);
-    const int64_t j = at3(g, x, y, z);
+    const int64_t j = nb.at(0, 0, 0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         c[k * g.N + j] = rk[k] * ir;
@@ -115,11 +122,12 @@ __global__ __launch_bounds__(256) void k3_stress(const double* __restrict__ c, G
 {
     const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
-    const int64_t j = at3(g, x, y, z);
+    const Nb3 nb(g, x, y, z);
+    const int64_t j = nb.at(0, 0, 0);
     double gc[3][3], cc[3], rk[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        grad19(c + k * g.N, g, x, y, z, gc[k]);
+        grad19(c + k * g.N, nb, gc[k]);
         cc[k] = c[k * g.N + j];
         rk[k] = c[(3 + k) * g.N + j];
     }
@@ -154,7 +162,7 @@ __global__ __launch_bounds__(256) void k3_stress(const double* __restrict__ c, G
 }
 
 // F_b = sum_a d_a T_ab with the symmetric T stored as (xx, xy, xz, yy, yz, zz)
-__device__ __forceinline__ void force19(const double* __restrict__ T, const Geo3& g, int x, int y, int z,
+__device__ __forceinline__ void force19(const double* __restrict__ T, const Geo3& g, const Nb3& nb,
                                         double (&F)[3])
 {
     constexpr int Q[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
@@ -164,7 +172,7 @@ __device__ __forceinline__ void force19(const double* __restrict__ T, const Geo3
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             double d[3];
-            grad19(T + Q[a][b] * g.N, g, x, y, z, d);
+            grad19(T + Q[a][b] * g.N, nb, d);
             F[b] += d[a];
         }
 }
@@ -179,7 +187,8 @@ __global__ __launch_bounds__(256) void k3_collide(const double* __restrict__ C6,
     const int t = threadIdx.x;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (x < g.nx) {
-        const int64_t j = at3(g, x, y, z);
+        const Nb3 nb(g, x, y, z);
+        const int64_t j = nb.at(0, 0, 0);
         // the densities and totals k3_conc pulled
         double rk[3], ft[19];
 #pragma unroll
@@ -188,7 +197,7 @@ __global__ __launch_bounds__(256) void k3_collide(const double* __restrict__ C6,
         for (int i = 0; i < 19; ++i) ft[i] = C6[(6 + i) * g.N + j];
         const double rho = rk[0] + rk[1] + rk[2], irho = 1.0 / rho;
         double F[3];
-        force19(T, g, x, y, z, F);
+        force19(T, g, nb, F);
         double m[3] = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
@@ -272,10 +281,11 @@ __global__ __launch_bounds__(256) void k3_init(const double* __restrict__ rho, G
 {
     const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
-    const int64_t j = at3(g, x, y, z);
+    const Nb3 nb(g, x, y, z);
+    const int64_t j = nb.at(0, 0, 0);
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
-        const int64_t src = at3(g, x + L3X[i], y + L3Y[i], z + L3Z[i]);
+        const int64_t src = nb.at(L3X[i], L3Y[i], L3Z[i]);
 #pragma unroll
         for (int k = 0; k < 3; ++k) B[(int64_t)(k * 19 + i) * g.N + j] = w19(i) * rho[k * g.N + src];
     }
@@ -287,9 +297,10 @@ __global__ __launch_bounds__(256) void k3_export(const double* __restrict__ B, G
 {
     const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
-    const int64_t j = at3(g, x, y, z);
+    const Nb3 nb(g, x, y, z);
+    const int64_t j = nb.at(0, 0, 0);
     double f[3][19];
-    pull57(B, g, x, y, z, f);
+    pull57(B, g, nb, f);
     for (int k = 0; k < 3; ++k) {
         double s = 0.0;
         for (int i = 0; i < 19; ++i) {
