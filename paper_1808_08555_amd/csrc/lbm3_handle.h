@@ -41,6 +41,7 @@ struct lbm3 {
     void* adj_ws = nullptr;             // adjoint workspace
     size_t adj_ws_bytes = 0;
     hipStream_t adj_stream = nullptr;   // the reverse sweep's own stream (graph capture)
+    hipStream_t adj_stream2 = nullptr;  // the segment recompute, beside the reverse steps
     hipEvent_t adj_event = nullptr;
 };
 

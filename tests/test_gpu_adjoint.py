@@ -110,6 +110,33 @@ def test_adjoint_wide_lattice_many_tiles_against_oracle_finite_differences():
         assert abs(dr[k, yy, xx] - fd) <= 1e-5 * max(1e-3, abs(fd))
 
 
+def test_adjoint_above_the_overlap_size_against_gpu_finite_differences():
+    """2048^2 (2^22 nodes: the sweep runs its segments one after the other in one slot,
+    where smaller lattices overlap the next segment's recompute with the reverse steps),
+    Janus droplet, 6 steps with a checkpoint every 2: dL/dsigma against central differences
+    of the FP64 forward loss (the forward matches the oracle elsewhere), h = 1e-6, within
+    1e-5 relative plus the differences' rounding noise (4 eps L / h)."""
+    n, steps, h = 2048, 6, 1e-6
+    w = inputs.janus_halves(n, 320.0, SIGMA, (0.8, 0.8, 0.8), steps)
+    target = inputs.loss_target(w.rho[0], seed=5550)
+    loss, ds, _ = gpu_gradient(w.rho, target, SIGMA, w.tau, steps, 2)
+
+    def L_at(sig):
+        M = lbm3.Lattice(n, n, sig, w.tau).init(w.rho).step(steps)
+        v = float(((M.densities()[0] - target) ** 2).sum())
+        M.close()
+        return v
+
+    noise = 4 * 2.2e-16 * loss / h
+    for q in range(3):
+        sp, sm = list(SIGMA), list(SIGMA)
+        sp[q] += h
+        sm[q] -= h
+        fd = (L_at(sp) - L_at(sm)) / (2 * h)
+        print(f"dL/dsigma[{q}] adjoint {ds[q]:.10e} fd {fd:.10e} (noise {noise:.1e})")
+        assert abs(ds[q] - fd) <= 1e-5 * abs(fd) + noise
+
+
 def test_adjoint_taylor_remainder_is_second_order():
     """With the GPU forward alone: L(rho0 + e d) - L(rho0) - e <grad, d> shrinks as e^2
     (d perturbs each node's own fluid)."""
