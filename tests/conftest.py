@@ -8,6 +8,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 if HERE not in sys.path:
     sys.path.insert(0, HERE)
 
+# Under pytest-xdist every worker runs the OpenMP oracle.  A full thread team per worker
+# oversubscribes the cores, and the teams' spinning barriers then slow the long oracle runs
+# by an order of magnitude.  Each worker gets its share of the cores instead; this must be
+# set before the oracle library (and its OpenMP runtime) is loaded.
+_WORKERS = int(os.environ.get("PYTEST_XDIST_WORKER_COUNT", "0") or 0)
+if _WORKERS > 1:
+    os.environ["OMP_NUM_THREADS"] = str(max(1, (os.cpu_count() or 1) // _WORKERS))
+    os.environ.setdefault("OMP_WAIT_POLICY", "passive")
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP C-ABI)")
