@@ -257,6 +257,8 @@ def main():
     ap.add_argument("--only-plain", action="store_true", help="time the headline workload only")
     ap.add_argument("--only-d3q19", action="store_true", help="time the D3Q19 form only (its own JSON line)")
     ap.add_argument("--only-batched", action="store_true", help="time the batched form only (its own JSON line)")
+    ap.add_argument("--only-adjoint", action="store_true",
+                    help="time the adjoint on the 2048^2 Janus droplet only (its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the step, its batched form and its adjoint run on a "
@@ -272,7 +274,15 @@ def main():
         print(json.dumps({"batched_fp32": bench_batched(torch, lbm3, inputs, args.steps)}), flush=True)
         return
     if args.only_d3q19:
-        print(json.dumps({"d3q19_fp64": bench_d3q19(torch, lbm3, inputs, 128, args.steps)}), flush=True)
+        res = bench_d3q19(torch, lbm3, inputs, 128, args.steps)
+        # the copy kernel's counters calibrate a PMC run of this mode
+        res["device_copy_gbs"] = round(copy_bandwidth(torch, lbm3), 1)
+        print(json.dumps({"d3q19_fp64": res}), flush=True)
+        return
+    if args.only_adjoint:
+        res = bench_adjoint(torch, lbm3, inputs, 2048, 200, 20)
+        res["device_copy_gbs"] = round(copy_bandwidth(torch, lbm3), 1)
+        print(json.dumps({"adjoint_fp64": {"janus_2048": res}}), flush=True)
         return
     w = inputs.droplet_tiling(4096)
     log(f"workload {w.name}: {w.nx}x{w.ny}, FP64, {args.warmup} warm-up + {args.steps} timed steps")
