@@ -255,7 +255,9 @@ int lbm3_batch_destroy(lbm3_batch_t *b);
  *   with Guo forcing of Eqs. 8-9, the force of Eq. 7, the colour gradient of
  *   Eq. 12, streaming), recomputing each segment from its checkpoint.  Blocking;
  *   allocates a workspace of about 20 ckpt_every + 100 doubles per node (the
- *   checkpoints hold 18 per node each).  The
+ *   checkpoints hold 18 per node each); below 2^22 nodes the tape and forward
+ *   buffers are held twice, since the recompute of the next segment then runs on
+ *   a second stream beside the reverse steps of the current one.  The
  *   forward state is left at step T.  ESTATE without a recording or after a step
  *   since it. */
 int lbm3_adjoint_record(lbm3_t *h, int64_t nsteps, int32_t ckpt_every);
@@ -268,7 +270,8 @@ int lbm3_adjoint(lbm3_t *h, const double *drho1_T, double dsigma[3], double *drh
  * 3 x 3 tensor, Guo's term and the velocity of Eqs. (8)-(9), the equilibrium of Eq. (3),
  * the recolouring of Eq. (13) with any segregation law (beta_law), streaming of Eq. (22);
  * periodic in x, y and z.  FP64 and the paper's forcing only (else LBM3_EUNSUPPORTED).
- * lbm3d_create: p as for lbm3_create (nx, ny from it), nz in 1..65535; allocates the
+ * lbm3d_create: p as for lbm3_create (nx, ny from it), nz in 1..65535, at most 2^31
+ *   nodes (else LBM3_EINVAL); allocates the
  *   two 57-population state buffers and the intermediates (about 150 doubles per node).
  * lbm3d_init_fields: rho host [3][nz][ny][nx] (x fastest), finite, >= 0, with rho > 0 at
  *   every node; fluid at rest (f_{i,k} = w_i rho_k).  Blocking; resets the step count.

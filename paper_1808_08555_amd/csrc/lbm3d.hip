@@ -97,10 +97,33 @@ __device__ __forceinline__ void grad19(const double* __restrict__ phi, const Nb3
     for (int a = 0; a < 3; ++a) d[a] *= 3.0;
 }
 
+// Blocks of 256 consecutive nodes (x fastest, then y, then z) on a one-dimensional grid.
+// Workgroups go to the eight XCDs in turn, and each XCD has its own L2; block b therefore
+// takes the node range of logical block xcd_block(b), so that each XCD works through one
+// contiguous run of blocks (a slab of z) and finds most of its stencil neighbours in its
+// own L2.  The map is a bijection of [0, T) for any T.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t T)
+{
+    const int64_t x = b & 7, k = b >> 3, q = T >> 3, r = T & 7;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// (x, y, z) of this thread's node; false past the last node
+__device__ __forceinline__ bool node3(const Geo3& g, int& x, int& y, int& z)
+{
+    const int64_t n = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (n >= g.N) return false;
+    // N <= 2^31 (checked at creation): 32-bit division suffices
+    const uint32_t n32 = (uint32_t)n, nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
+    const uint32_t p = n32 / nx, zz = p / ny;
+    x = (int)(n32 - p * nx), y = (int)(p - zz * ny), z = (int)zz;
+    return true;
+}
+
 __global__ __launch_bounds__(256) void k3_conc(const double* __restrict__ B, Geo3 g, double* __restrict__ c)
 {
-    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
-    if (x >= g.nx) return;
+    int x, y, z;
+    if (!node3(g, x, y, z)) return;
     const Nb3 nb(g, x, y, z);
     double ft[19], rk[3];
     pull_sums(B, g, nb, ft, rk);
@@ -120,8 +143,8 @@ __global__ __launch_bounds__(256) void k3_conc(const double* __restrict__ B, Geo
 __global__ __launch_bounds__(256) void k3_stress(const double* __restrict__ c, Geo3 g, KParams kp,
                                                  double* __restrict__ T, double* __restrict__ nrm)
 {
-    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
-    if (x >= g.nx) return;
+    int x, y, z;
+    if (!node3(g, x, y, z)) return;
     const Nb3 nb(g, x, y, z);
     const int64_t j = nb.at(0, 0, 0);
     double gc[3][3], cc[3], rk[3];
@@ -183,10 +206,11 @@ __global__ __launch_bounds__(256) void k3_collide(const double* __restrict__ C6,
                                                   double* __restrict__ Bout, double* __restrict__ partials)
 {
     __shared__ double red[OBS ? 8 : 1][256];
-    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    int x, y, z;
+    const bool live = node3(g, x, y, z);
     const int t = threadIdx.x;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (x < g.nx) {
+    if (live) {
         const Nb3 nb(g, x, y, z);
         const int64_t j = nb.at(0, 0, 0);
         // the densities and totals k3_conc pulled
@@ -270,8 +294,7 @@ __global__ __launch_bounds__(256) void k3_collide(const double* __restrict__ C6,
             __syncthreads();
         }
         if (t < 8) {
-            const int64_t b = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-            partials[b * 8 + t] = red[t][0];
+            partials[(int64_t)blockIdx.x * 8 + t] = red[t][0];
         }
     }
 }
@@ -279,8 +302,8 @@ __global__ __launch_bounds__(256) void k3_collide(const double* __restrict__ C6,
 // B_{i,k}(y) = w_i rho_k(y + e_i): the pulled state is f_{i,k} = w_i rho_k (fluid at rest)
 __global__ __launch_bounds__(256) void k3_init(const double* __restrict__ rho, Geo3 g, double* __restrict__ B)
 {
-    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
-    if (x >= g.nx) return;
+    int x, y, z;
+    if (!node3(g, x, y, z)) return;
     const Nb3 nb(g, x, y, z);
     const int64_t j = nb.at(0, 0, 0);
 #pragma unroll
@@ -295,8 +318,8 @@ __global__ __launch_bounds__(256) void k3_init(const double* __restrict__ rho, G
 __global__ __launch_bounds__(256) void k3_export(const double* __restrict__ B, Geo3 g, double* __restrict__ fout,
                                                  double* __restrict__ rho)
 {
-    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
-    if (x >= g.nx) return;
+    int x, y, z;
+    if (!node3(g, x, y, z)) return;
     const Nb3 nb(g, x, y, z);
     const int64_t j = nb.at(0, 0, 0);
     double f[3][19];
@@ -332,7 +355,7 @@ struct lbm3d {
     bool ready = false;
 };
 
-static dim3 grid3(const Geo3& g) { return dim3((g.nx + 255) / 256, g.ny, g.nz); }
+static dim3 grid3(const Geo3& g) { return dim3((unsigned)((g.N + 255) / 256)); }
 
 static void release3(lbm3d* h)
 {
@@ -363,6 +386,10 @@ int lbm3d_create(const lbm3_params* p, int32_t nz, void* hip_stream, lbm3d_t** o
     if (rc) return rc;
     if (nz < 1 || nz > 65535) {
         set_error("nz must be in 1..65535 (got %d)", nz);
+        return LBM3_EINVAL;
+    }
+    if ((int64_t)p->nx * p->ny * nz > ((int64_t)1 << 31)) {
+        set_error("the D3Q19 form takes at most 2^31 nodes (got %d x %d x %d)", (int)p->nx, (int)p->ny, nz);
         return LBM3_EINVAL;
     }
     if (p->precision != LBM3_FP64) {
