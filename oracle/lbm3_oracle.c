@@ -24,10 +24,13 @@
  * (15)-(17) earlier segregation laws, (18)-(20) proposed segregation law,
  * (22) streaming.
  *
- * Parity unpinned: the coefficient 35 of C_t in Eq. (19) only matters where
- * C_t < 1 (near triple junctions) and no closed form fixes it; the checks
- * against the paper cover C_t = 1 and C_t = 0.  The scale 1e6 of C_kl in
- * Eq. (6) is pinned only through C_kl saturating to 1 at interfaces.
+ * The printed constants that no closed form fixes (the 35 of C_t in Eq. (19),
+ * the 10^6 of C_kl in Eq. (6), the comparison laws and the perturbation
+ * operator) are pinned by node-level checks where C_t and C_kl are below
+ * saturation and by agreement, to round-off, with a second transcription of
+ * the step written apart from this one (numpy_step.py).  Parity unpinned:
+ * exact steady-state fields and spurious-velocity values, which the paper does
+ * not print in a form a step-level oracle can reproduce.
  */
 #include <math.h>
 #include <stddef.h>

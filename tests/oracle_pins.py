@@ -187,6 +187,60 @@ def pin_segregation_law():
         assert oracle.beta(p, k, l, (0.4, 0.6, 0.0)) == 0.7
 
 
+def pin_segregation_law_inside_the_junction():
+    """Eq. (19) where 0 < 35 rho_r rho_g rho_b / rho^3 < 1 (near a triple junction, away from
+    its centre): beta_kl = beta0 (1 + C_t g(X_kl)) with C_t = 35 rho_r rho_g rho_b / rho^3
+    unsaturated, and C_t saturating to 1 exactly where that product reaches 1/35."""
+    sig = (0.011, 0.013, 0.017)
+    p = oracle.Params(4, 4, sig, beta0=0.7)
+    pairs = [(0, 1), (0, 2), (1, 2)]
+    for rho in [(0.9, 0.05, 0.05), (0.6, 0.3, 0.1), (0.2, 0.1, 0.7)]:
+        r = sum(rho)
+        ct = 35.0 * rho[0] * rho[1] * rho[2] / r ** 3
+        assert 0.0 < ct < 1.0
+        for k, l in pairs:
+            X = oracle.X(p, k, l)
+            gX = (1 - math.sin(math.acos(X))) if X < 0 else (math.sin(math.acos(X)) - 1)
+            assert abs(oracle.beta(p, k, l, rho) - 0.7 * (1 + ct * gX)) < 1e-15, (rho, k, l)
+    # along rho = (a, a, 1 - 2a), C_t reaches 1 where a^2 (1 - 2a) = 1/35: beta is flat beyond
+    a0 = min(np.roots([-2.0, 1.0, 0.0, -1.0 / 35.0]).real, key=lambda a: abs(a - 0.25))
+    b_sat = oracle.beta(p, 0, 1, (1 / 3, 1 / 3, 1 / 3))
+    assert oracle.beta(p, 0, 1, (a0 + 1e-4, a0 + 1e-4, 1 - 2 * a0 - 2e-4)) == b_sat
+    assert oracle.beta(p, 0, 1, (a0 - 1e-3, a0 - 1e-3, 1 - 2 * a0 + 2e-3)) != b_sat
+
+
+def pin_concentration_factor_below_saturation():
+    """Eq. (6): C_kl = min(10^6 rho_k rho_l / (rho_k^0 rho_l^0), 1).  At a two-fluid node
+    with rho_k rho_l below 10^-6 the stress of Eq. (7) is scaled by 10^6 rho_k rho_l, and
+    by 1 once that product exceeds 10^-6."""
+    p = oracle.Params(4, 4, (0.011, 0.013, 0.017), rho0=(1.0, 1.0, 2.0))
+    gx = np.array([0.1, 0.0, -0.1])
+    gy = np.zeros(3)
+    for r0, expect_c in [(5e-7, 1e6 * 5e-7 * (1 - 5e-7) / 2.0), (3e-6, 1.0)]:
+        rho_k = np.array([r0, 0.0, 1.0 - r0])
+        G = (1 - r0) * 0.1 - r0 * (-0.1)
+        S = oracle.stress_node(p, rho_k, gx, gy)
+        assert abs(S[3] - 0.013 * expect_c * G) < 1e-18 + 1e-14 * abs(S[3]), (r0, S[3])
+
+
+def pin_numpy_transcription():
+    """The C oracle against the independent NumPy transcription of the step
+    (``oracle/numpy_step.py``: printed nine-term sums, ordered pair sums, whole-lattice
+    arrays) on an 8x8 random mixture with tiny and zero densities, where C_kl < 1 and
+    C_t < 1 at some nodes: 4 steps of every segregation law with the force of Eq. (7), and
+    of the paper's law with the perturbation operator of Eqs. (4)-(5), agree to 1e-13."""
+    from oracle import numpy_step
+    rho = inputs.random_mixture(8, 8, 5)
+    sig, tau = (0.011, 0.013, 0.017), (0.7, 1.0, 1.3)
+    cases = [(law, "guo") for law in numpy_step.LAWS] + [("paper", "perturbation")]
+    for law, forcing in cases:
+        p = oracle.Params(8, 8, sig, tau, beta_law=law, forcing=forcing)
+        f0 = numpy_step.init_at_rest(rho)
+        a = oracle.run(p, f0, 4)
+        b = numpy_step.run(f0, 4, sigma=sig, tau=tau, law=law, forcing=forcing)
+        assert np.abs(a - b).max() <= 1e-13, (law, forcing, np.abs(a - b).max())
+
+
 # ----------------------------------------------------------------- node-level recolouring and stress
 def pin_recolour_conservation():
     """Eq. (13) with beta_kl = beta_lk and n_lk = -n_kl: summing over colours returns f_dag;
@@ -386,6 +440,7 @@ def pin_laplace_single_droplet():
 FAST_PINS = [pin_lattice_tables, pin_equilibrium_moments, pin_guo_moments,
              pin_collision_moments, pin_local_tau, pin_gradient_polynomials,
              pin_gradient_fourier_symbol, pin_neumann_geometry, pin_segregation_law,
+             pin_segregation_law_inside_the_junction, pin_concentration_factor_below_saturation,
              pin_recolour_conservation, pin_stress_two_fluid, pin_translation_invariance,
              pin_reflection_rotation_symmetry, pin_flat_interface, pin_flat_interface_profile,
-             pin_taylor_green_viscosity, pin_laplace_single_droplet]
+             pin_taylor_green_viscosity, pin_laplace_single_droplet, pin_numpy_transcription]

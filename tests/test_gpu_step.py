@@ -68,14 +68,19 @@ def test_parity_two_droplets_64_1000_steps():
     fluid's droplet is round-off sensitive (the recolouring term has the magnitude
     beta w rho_k rho_l / rho along a unit normal whatever |G| is, and its anti-diffusion
     amplifies sub-ulp differences ~1.7x per step there), so the coloured populations are held
-    to the trace amplitude over 1000 steps, and to 1e-15 per step along the trajectory."""
+    to the trace amplitude over 1000 steps, and to 1e-15 per step along the trajectory.
+    The scale of that bar is measured on the CPU: the oracle against itself from a start
+    perturbed by one ulp diverges by 3.8e-11 in the colours and 8.5e-11 in the densities over
+    these 1000 steps (test_round_off_conditioning_of_the_two_droplet_case); the GPU rounds
+    differently at every step (grouping, Newton-refined reciprocals), a few ulp each time, so
+    the bar is a few times that: 3e-10."""
     w = inputs.two_droplets_64()
     g = _gpu(w, 1000)
     o = _oracle(w, 1000)
     d_tot, d_col, d_rho = parity(g, o)
     print(f"two droplets 64^2, 1000 steps: |df_i| {d_tot:.2e} |df_ik| {d_col:.2e} |drho_k| {d_rho:.2e}")
     assert d_tot <= TOL_FP64
-    assert d_col <= 1e-9 and d_rho <= 1e-9
+    assert d_col <= 3e-10 and d_rho <= 3e-10
 
 
 def test_single_step_parity_along_trajectory():

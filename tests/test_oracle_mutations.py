@@ -21,6 +21,24 @@ MUTANTS = {
     "stress_double_counted": ("double a = 0.5 * sigma_of(p, k, l)", "double a = sigma_of(p, k, l)"),
     "stress_normal_projector": ("S[3] += a * (1.0 - n[1] * n[1]);", "S[3] += a * (n[1] * n[1]);"),
     "concentration_factor_scale": ("double v = 1e6 * rho_k[k]", "double v = 1e-6 * rho_k[k]"),
+    "concentration_factor_scale_1e4": ("double v = 1e6 * rho_k[k]", "double v = 1e4 * rho_k[k]"),
+    "segregation_ct_coefficient_27": (
+        "double ct = 35.0 * rho[0] * rho[1] * rho[2] / (r * r * r);\n    if (ct > 1.0) ct = 1.0;\n"
+        "    return p->beta0 + p->beta0 * ct * oracle_g",
+        "double ct = 27.0 * rho[0] * rho[1] * rho[2] / (r * r * r);\n    if (ct > 1.0) ct = 1.0;\n"
+        "    return p->beta0 + p->beta0 * ct * oracle_g"),
+    "segregation_ct_not_capped": (
+        "    if (ct > 1.0) ct = 1.0;\n    return p->beta0 + p->beta0 * ct * oracle_g",
+        "    return p->beta0 + p->beta0 * ct * oracle_g"),
+    "leclaire_ct_coefficient_27": (
+        "double ct = 35.0 * rho[0] * rho[1] * rho[2] / (r * r * r);\n    if (ct > 1.0) ct = 1.0;\n"
+        "    return p->beta0 + p->beta0 * ct * (sin(",
+        "double ct = 27.0 * rho[0] * rho[1] * rho[2] / (r * r * r);\n    if (ct > 1.0) ct = 1.0;\n"
+        "    return p->beta0 + p->beta0 * ct * (sin("),
+    "perturbation_A_coefficient": ("double A = 9.0 * sigma_of(p, k, l) / (2.0 * tau);",
+                                   "double A = 9.0 * sigma_of(p, k, l) / tau;"),
+    "perturbation_B_rest": ("{-4.0 / 27.0, 2.0 / 27.0", "{-2.0 / 27.0, 2.0 / 27.0"),
+    "spencer_factor_35": ("double s = 27.0 * rho[0]", "double s = 35.0 * rho[0]"),
     "segregation_branch_sign": ("if (X < 0.0) return 1.0 - sin(acos(X));",
                                 "if (X < 0.0) return sin(acos(X)) - 1.0;"),
     "neumann_opposite_side": ("return (smk * smk + sml * sml - skl * skl) / (2.0 * smk * sml);",
