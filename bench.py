@@ -255,6 +255,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-plain", action="store_true", help="time the headline workload only")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_storage", "fp32"],
+                    help="with --only-plain: the precision timed on the headline workload (its own "
+                         "JSON line unless fp64)")
     ap.add_argument("--only-d3q19", action="store_true", help="time the D3Q19 form only (its own JSON line)")
     ap.add_argument("--only-batched", action="store_true", help="time the batched form only (its own JSON line)")
     ap.add_argument("--only-adjoint", action="store_true",
@@ -285,8 +288,15 @@ def main():
         print(json.dumps({"adjoint_fp64": {"janus_2048": res}}), flush=True)
         return
     w = inputs.droplet_tiling(4096)
-    log(f"workload {w.name}: {w.nx}x{w.ny}, FP64, {args.warmup} warm-up + {args.steps} timed steps")
     args.steps += args.steps % 2
+    if args.only_plain and args.precision != "fp64":
+        # one reduced-precision path on the headline workload (profiling runs)
+        res = bench_plain(torch, lbm3, w, args.precision, args.steps, args.warmup)
+        res["frac_of_peak"] = round(res["gbs"] / HBM_PEAK_GBS, 4)
+        res["device_copy_gbs"] = round(copy_bandwidth(torch, lbm3), 1)
+        print(json.dumps({args.precision: res}), flush=True)
+        return
+    log(f"workload {w.name}: {w.nx}x{w.ny}, FP64, {args.warmup} warm-up + {args.steps} timed steps")
     main_res = bench_plain(torch, lbm3, w, "fp64", args.steps, args.warmup)
     log(f"fp64 {main_res}")
     one_step = bench_plain(torch, lbm3, w, "fp64", args.steps, args.warmup, steps_per_launch=1)

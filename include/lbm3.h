@@ -255,13 +255,21 @@ int lbm3_batch_destroy(lbm3_batch_t *b);
  *   with Guo forcing of Eqs. 8-9, the force of Eq. 7, the colour gradient of
  *   Eq. 12, streaming), recomputing each segment from its checkpoint.  Blocking;
  *   allocates a workspace of about 20 ckpt_every + 100 doubles per node (the
- *   checkpoints hold 18 per node each); below 2^22 nodes the tape and forward
- *   buffers are held twice, since the recompute of the next segment then runs on
- *   a second stream beside the reverse steps of the current one.  The
+ *   checkpoints hold 18 per node each); below 2^22 nodes, where device memory
+ *   allows (lbm3_adjoint_pipeline_slots), the tape and forward buffers are held
+ *   twice, since the recompute of the next segment then runs on a second stream
+ *   beside the reverse steps of the current one.  The
  *   forward state is left at step T.  ESTATE without a recording or after a step
  *   since it. */
 int lbm3_adjoint_record(lbm3_t *h, int64_t nsteps, int32_t ckpt_every);
 int lbm3_adjoint(lbm3_t *h, const double *drho1_T, double dsigma[3], double *drho0);
+/* The pipeline choice of lbm3_adjoint, a pure host function (no device work): 2 slots
+ * (recompute beside the reverse steps) when nodes < 2^22 and the two-slot workspace
+ * ws_two_slots fits in the workspace already held plus device_free (less 1/16 in
+ * reserve), else 1.  lbm3_adjoint also falls back to one slot when the two-slot
+ * allocation fails.  Sizes in bytes. */
+int lbm3_adjoint_pipeline_slots(int64_t nodes, uint64_t ws_two_slots, uint64_t ws_held,
+                                uint64_t device_free);
 
 /* ---- three-dimensional form (D3Q19) ---------------------------------------------
  * The step of Sec. 2 (the model is stated for DmQn lattices) on the standard D3Q19

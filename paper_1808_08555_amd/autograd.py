@@ -36,7 +36,11 @@ class TernaryRun(torch.autograd.Function):
             raise ValueError(f"sigma must be (3,), got {tuple(sigma.shape)}")
         ny, nx = int(rho0.shape[1]), int(rho0.shape[2])
         s = tuple(float(v) for v in _host(sigma))
-        lat = lbm3.Lattice(nx, ny, s, tuple(tau), tuple(rho_pure), beta0, "fp64")
+        # the library's work is ordered on torch's current stream of the input's device (the
+        # stream contract of the binding); on a CPU tensor, on the current device's
+        dev = rho0.device if rho0.device.type == "cuda" else torch.device("cuda", torch.cuda.current_device())
+        stream = torch.cuda.current_stream(dev)
+        lat = lbm3.Lattice(nx, ny, s, tuple(tau), tuple(rho_pure), beta0, "fp64", stream=stream)
         lat.init(_host(rho0))
         lbm3.lbm3_adjoint_record(lat.h, steps, ckpt_every)
         rho_T = lat.densities()

@@ -548,6 +548,18 @@ static int ensure_ws(lbm3* h, size_t bytes)
 
 extern "C" {
 
+int lbm3_adjoint_pipeline_slots(int64_t nodes, uint64_t ws_two_slots, uint64_t ws_held, uint64_t device_free)
+{
+    // The overlap pays below 2^22 nodes (measured: +47% at 256^2, +7% at 512^2, +2% at
+    // 1024^2, none at 2048^2).  A held workspace is freed before a larger one is allocated,
+    // so the two-slot workspace must fit in the free memory plus what is held, keeping 1/16
+    // of it in reserve for the runtime.
+    if (nodes >= ((int64_t)1 << 22)) return 1;
+    if (ws_two_slots <= ws_held) return 2;
+    const uint64_t avail = device_free + ws_held;
+    return ws_two_slots <= avail - avail / 16 ? 2 : 1;
+}
+
 int lbm3_adjoint_record(lbm3_t* h, int64_t nsteps, int32_t ckpt_every)
 {
     if (!h) {
@@ -638,21 +650,27 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     const size_t tbytes = (size_t)kTapeFields * N * sizeof(double);
     const int K = h->tape_every;
     const int64_t nseg = h->tape_steps / K;
-    // Below 2^22 nodes the device has room to recompute the next segment beside the reverse
-    // steps of the current one (measured: +47% at 256^2, +7% at 512^2, +2% at 1024^2, none
-    // at 2048^2), in two pipeline slots; above, the segments run one after the other in one
-    // slot.
-    const bool overlap = N < ((int64_t)1 << 22);
-    const int nslots = overlap ? 2 : 1;
     // workspace: 11 adjoint fields of N doubles, two factored adjoint states (12 fields), per
     // pipeline slot two forward state buffers and the tape of K steps (20 fields each), the
     // dL/dsigma partial sums, dL/drho_1(T), the fused pass's tiles
     const size_t fields = (size_t)(3 + 2 + 6) * N;
     const size_t lbytes = (size_t)12 * N * sizeof(double);
-    const size_t need = fields * sizeof(double) + 2 * lbytes + nslots * (2 * sbytes + (size_t)K * tbytes) +
-                        (size_t)nsig * 6 * sizeof(double) + N * sizeof(double) + sf_tiles.size() * sizeof(Tile);
-    int rc = ensure_ws(h, need);
+    auto need_of = [&](int slots) {
+        return fields * sizeof(double) + 2 * lbytes + slots * (2 * sbytes + (size_t)K * tbytes) +
+               (size_t)nsig * 6 * sizeof(double) + N * sizeof(double) + sf_tiles.size() * sizeof(Tile);
+    };
+    // Two pipeline slots (the recompute of the next segment beside the reverse steps of the
+    // current one) on small lattices where the second slot fits; else one.
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+    int nslots = lbm3_adjoint_pipeline_slots(N, need_of(2), h->adj_ws_bytes, free_b);
+    int rc = ensure_ws(h, need_of(nslots));
+    if (rc == LBM3_ENOMEM && nslots == 2) {
+        nslots = 1;  // the second slot did not fit after all: the one-slot sweep needs half the tape
+        rc = ensure_ws(h, need_of(1));
+    }
     if (rc) return rc;
+    const bool overlap = nslots == 2;
     double* d = (double*)h->adj_ws;
     AdjWS w;
     w.rho = w.ftot = w.gc = w.F = nullptr;  // per step: the tape of that step

@@ -52,6 +52,9 @@ struct lbm3_batch {
     double* obs_host = nullptr;
     std::vector<char> ready;
     std::vector<tcg::Fmt> fmt;  // per instance: F27 after init_fields, FAC after a step
+    // FP32 storage: the step number on the device (equal to `step` once the stream has run),
+    // which salts the stochastic rounding of every launch, graph replays included
+    int64_t* dstep = nullptr;
 };
 
 using namespace tcg;
@@ -173,15 +176,23 @@ static int ensure_batch_staging(lbm3_batch* b, size_t doubles)
 }
 
 // One launch from buffer c of the steady-state step (one step) or of the two-step pass
-// (two steps); either way the result is in buffer c ^ 1.
+// (two steps); either way the result is in buffer c ^ 1.  With FP32 storage the launch takes
+// its rounding salt from the device step counter and is followed by the counter's advance,
+// so that a captured graph rounds every replay with the salts of the absolute steps it runs
+// (the same as a lattice stepped alone).
 static hipError_t launch_steady(lbm3_batch* b, int c, bool two, int64_t step)
 {
+    hipError_t e;
     if (two)
-        return launch_pair(b->prec, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles2, b->ntiles2, b->threads2, step,
-                           b->stream, b->pt);
-    const Fmt sf = steady_fmt(b->prec);
-    return launch_tiles(b->prec, sf, sf, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles, b->ntiles, b->threads,
-                        step, 0, b->stream, b->pt);
+        e = launch_pair(b->prec, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles2, b->ntiles2, b->threads2, step,
+                        b->stream, b->pt, b->dstep);
+    else {
+        const Fmt sf = steady_fmt(b->prec);
+        e = launch_tiles(b->prec, sf, sf, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles, b->ntiles, b->threads,
+                         step, 0, b->stream, b->pt, b->dstep);
+    }
+    if (e == hipSuccess && b->dstep) e = launch_advance_step(b->dstep, two ? 2 : 1, b->stream);
+    return e;
 }
 
 // Captures launches worth kGraphSteps steps starting from buffer `parity` (an even number
@@ -230,6 +241,7 @@ int lbm3_batch_destroy(lbm3_batch_t* b)
     if (b->partials) (void)hipFree(b->partials);
     if (b->obs_dev) (void)hipFree(b->obs_dev);
     if (b->obs_host) (void)hipHostFree(b->obs_host);
+    if (b->dstep) (void)hipFree(b->dstep);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return LBM3_OK;
@@ -293,6 +305,11 @@ int lbm3_batch_create(const lbm3_params* p, int32_t count, void* hip_stream, lbm
         e = hipMemcpy(b->dinst, b->inst.data(), count * sizeof(Instance), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc((void**)&b->obs_dev, kObsFields * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->obs_host, kObsFields * sizeof(double));
+    if (e == hipSuccess && b->prec == Prec::F32S) {
+        const int64_t zero = 0;
+        e = hipMalloc((void**)&b->dstep, sizeof(int64_t));
+        if (e == hipSuccess) e = hipMemcpy(b->dstep, &zero, sizeof zero, hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         int rc = hip_fail(e, "batch allocation");
         lbm3_batch_destroy(b);

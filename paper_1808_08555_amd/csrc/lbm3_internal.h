@@ -63,10 +63,15 @@ inline Fmt steady_fmt(Prec p) { return p == Prec::F32S ? Fmt::F27 : Fmt::FAC; }
 // Launchers (lbm3_step.hip).  All asynchronous on `stream`.  One fused step from a state in
 // format `in` to one in format `out` (F27 -> F27, F27 -> FAC or FAC -> FAC); with
 // filter != 0 a workgroup whose instance is not in format `in` does nothing.  pt selects the
-// perturbation operator of Eqs. (4)-(5) in place of the force and Guo's term.
+// perturbation operator of Eqs. (4)-(5) in place of the force and Guo's term.  With FP32
+// storage the stochastic rounding is salted by the step number: `step`, or, when step_dev
+// is given, the value it points to on the device when the launch runs (a graph replays the
+// same launches at later steps).
 hipError_t launch_tiles(Prec prec, Fmt in, Fmt out, const void* fin, void* fout, const Instance* inst,
                         const Tile* tiles, int ntiles, int threads, int64_t step, int filter,
-                        hipStream_t stream, bool pt = false);
+                        hipStream_t stream, bool pt = false, const int64_t* step_dev = nullptr);
+// Adds n to the device step counter *step_dev (one thread), stream-ordered.
+hipError_t launch_advance_step(int64_t* step_dev, int64_t n, hipStream_t stream);
 hipError_t launch_observe_tiles(Prec prec, Fmt in, const void* fin, const Instance* inst,
                                 const Tile* tiles, int ntiles, int threads, double* partials,
                                 double* rho_out, hipStream_t stream, bool pt = false);
@@ -99,14 +104,25 @@ int device_slots(Prec prec, int threads);
 int device_slots_pair(Prec prec, int threads);
 
 size_t elem_bytes(Prec p);
-uint32_t step_salt(int64_t step);
+// Salt of the stochastic rounding of step `step` (FP32 storage), the same on host and device.
+__host__ __device__ inline uint32_t step_salt(int64_t step)
+{
+    uint32_t x = (uint32_t)step ^ (uint32_t)(step >> 32) * 0x9E3779B9U;
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
 
 // Per-precision instantiations of the fused step (lbm3_tiles_*.hip).
 #define LBM3_TILES_DECL(NAME)                                                                    \
     hipError_t NAME(Fmt in, Fmt out, bool obs, bool pt, const void* fin, void* fout,             \
                     const Instance* inst,                                                         \
-                    const Tile* tiles, int ntiles, int threads, uint32_t salt, int filter,        \
-                    double* partials, double* rho_out, hipStream_t stream);                       \
+                    const Tile* tiles, int ntiles, int threads, uint32_t salt,                    \
+                    const int64_t* step_dev, int filter, double* partials, double* rho_out,       \
+                    hipStream_t stream);                                                          \
     int NAME##_occupancy(int threads);
 LBM3_TILES_DECL(tiles_f64)
 LBM3_TILES_DECL(tiles_f32s)
@@ -128,14 +144,15 @@ hipError_t tiles_f32_pair(const void* fin, void* fout, const Instance* inst, con
 // The same for FP32 storage (27-population state in and out), with the stochastic-rounding
 // salts of the two steps.
 hipError_t tiles_f32s_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
-                           int ntiles, int threads, uint32_t salt_a, uint32_t salt_b, bool pt,
-                           hipStream_t stream);
+                           int ntiles, int threads, uint32_t salt_a, uint32_t salt_b,
+                           const int64_t* step_dev, bool pt, hipStream_t stream);
 int tiles_f64_pair_occupancy(int threads);
 int tiles_f32_pair_occupancy(int threads);
 int tiles_f32s_pair_occupancy(int threads);
 // Two steps per launch of any precision from `step` (state in the precision's steady format).
 hipError_t launch_pair(Prec prec, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
-                       int ntiles, int threads, int64_t step, hipStream_t stream, bool pt = false);
+                       int ntiles, int threads, int64_t step, hipStream_t stream, bool pt = false,
+                       const int64_t* step_dev = nullptr);
 
 // Host-side helpers (lbm3_api.hip).
 void set_error(const char* fmt, ...);

@@ -108,6 +108,12 @@ __global__ __launch_bounds__(256) void k_export(const S* __restrict__ fin, doubl
     }
 }
 
+// The device step counter of a batch: one lane adds the steps a launch advanced.
+__global__ __launch_bounds__(64) void k_advance_step(int64_t* __restrict__ step_dev, int64_t n)
+{
+    if (threadIdx.x == 0) *step_dev += n;
+}
+
 __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
                                               int64_t n)
 {
@@ -144,47 +150,42 @@ __global__ __launch_bounds__(256) void k_export_fac(const S* __restrict__ fin, d
 
 size_t elem_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }
 
-uint32_t step_salt(int64_t step)
-{
-    uint32_t x = (uint32_t)step ^ (uint32_t)(step >> 32) * 0x9E3779B9U;
-    x ^= x >> 16;
-    x *= 0x7feb352dU;
-    x ^= x >> 15;
-    x *= 0x846ca68bU;
-    x ^= x >> 16;
-    return x;
-}
-
 hipError_t launch_pair(Prec prec, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
-                       int ntiles, int threads, int64_t step, hipStream_t stream, bool pt)
+                       int ntiles, int threads, int64_t step, hipStream_t stream, bool pt, const int64_t* step_dev)
 {
     switch (prec) {
         case Prec::F64: return tiles_f64_pair(fin, fout, inst, tiles, ntiles, threads, pt, stream);
         case Prec::F32: return tiles_f32_pair(fin, fout, inst, tiles, ntiles, threads, pt, stream);
         case Prec::F32S:
             return tiles_f32s_pair(fin, fout, inst, tiles, ntiles, threads, step_salt(step), step_salt(step + 1),
-                                   pt, stream);
+                                   step_dev, pt, stream);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_tiles(Prec prec, Fmt in, Fmt out, const void* fin, void* fout, const Instance* inst,
                         const Tile* tiles, int ntiles, int threads, int64_t step, int filter,
-                        hipStream_t st, bool pt)
+                        hipStream_t st, bool pt, const int64_t* step_dev)
 {
     const uint32_t salt = step_salt(step);
     switch (prec) {
         case Prec::F64:
-            return tiles_f64(in, out, false, pt, fin, fout, inst, tiles, ntiles, threads, salt, filter,
+            return tiles_f64(in, out, false, pt, fin, fout, inst, tiles, ntiles, threads, salt, nullptr, filter,
                              nullptr, nullptr, st);
         case Prec::F32S:
-            return tiles_f32s(in, out, false, pt, fin, fout, inst, tiles, ntiles, threads, salt, filter,
+            return tiles_f32s(in, out, false, pt, fin, fout, inst, tiles, ntiles, threads, salt, step_dev, filter,
                               nullptr, nullptr, st);
         case Prec::F32:
-            return tiles_f32(in, out, false, pt, fin, fout, inst, tiles, ntiles, threads, salt, filter,
+            return tiles_f32(in, out, false, pt, fin, fout, inst, tiles, ntiles, threads, salt, nullptr, filter,
                              nullptr, nullptr, st);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_advance_step(int64_t* step_dev, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(64), 0, st, step_dev, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_observe_tiles(Prec prec, Fmt in, const void* fin, const Instance* inst,
@@ -193,13 +194,13 @@ hipError_t launch_observe_tiles(Prec prec, Fmt in, const void* fin, const Instan
 {
     switch (prec) {
         case Prec::F64:
-            return tiles_f64(in, in, true, pt, fin, nullptr, inst, tiles, ntiles, threads, 0u, 0,
+            return tiles_f64(in, in, true, pt, fin, nullptr, inst, tiles, ntiles, threads, 0u, nullptr, 0,
                              partials, rho_out, st);
         case Prec::F32S:
-            return tiles_f32s(in, in, true, pt, fin, nullptr, inst, tiles, ntiles, threads, 0u, 0,
+            return tiles_f32s(in, in, true, pt, fin, nullptr, inst, tiles, ntiles, threads, 0u, nullptr, 0,
                               partials, rho_out, st);
         case Prec::F32:
-            return tiles_f32(in, in, true, pt, fin, nullptr, inst, tiles, ntiles, threads, 0u, 0,
+            return tiles_f32(in, in, true, pt, fin, nullptr, inst, tiles, ntiles, threads, 0u, nullptr, 0,
                              partials, rho_out, st);
     }
     return hipErrorInvalidValue;

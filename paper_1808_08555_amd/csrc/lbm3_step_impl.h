@@ -1532,11 +1532,13 @@ struct ExchangeLds<C, NT, Fmt::F27> {
 // densities rho_k, totals f_i, concentration gradients and force it pulled and formed, to
 // rho_out as [20][ny][nx] (rho_k, f_i, d_x c_k and d_y c_k per fluid, F_x, F_y): the
 // forward quantities the adjoint needs.  With filter, a workgroup whose instance's state is not in
-// format IN returns at once.
+// format IN returns at once.  With FP32 storage the stochastic rounding takes its salt from
+// step_dev (the device's step counter, read when the launch runs) when given, else `salt`.
 template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT, bool TAPE = false, bool PT = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles(const S* __restrict__ fin, S* __restrict__ fout,
                                               const Instance* __restrict__ inst,
                                               const Tile* __restrict__ tiles, uint32_t salt,
+                                              const int64_t* __restrict__ step_dev,
                                               int filter, double* __restrict__ partials,
                                               double* __restrict__ rho_out)
 {
@@ -1550,9 +1552,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const KParams kp = inst[tl.inst].kp;
     const int64_t off = inst[tl.inst].offset;
     double acc[kObsFields] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if constexpr (sizeof(S) == 4 && sizeof(C) == 8 && !OBS) {
+        if (step_dev) salt = step_salt(*step_dev);
+    }
+    // the key of a stored value depends on (step, node, value) only, so an instance of a batch
+    // rounds exactly as the same lattice stepped alone
     march<S, C, NT, OBS, IN, OUT, TAPE, PT>(fin + off, OBS ? nullptr : fout + off, kp, tl.x0, tl.y0, tl.rows,
-                                  tl.cols, cring, tring, ExchangeLds<C, NT, IN>::get(), acc, rho_out,
-                                  salt ^ mix32((uint32_t)tl.inst * 0x9E3779B9U + 0x51ed270bU));
+                                  tl.cols, cring, tring, ExchangeLds<C, NT, IN>::get(), acc, rho_out, salt);
     if constexpr (OBS) {
         __syncthreads();  // the rings are free once every lane has left the march
         block_reduce_obs<NT>(acc, reinterpret_cast<double (*)[NT]>(&rings[0][0][0][0]), partials);
@@ -1562,10 +1568,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 template <typename S, typename C, int NT, bool OBS, Fmt IN, Fmt OUT, bool TAPE = false, bool PT = false>
 hipError_t do_tiles(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                     int ntiles, uint32_t salt, int filter, double* partials, double* rho_out,
-                    hipStream_t st)
+                    hipStream_t st, const int64_t* step_dev = nullptr)
 {
     hipLaunchKernelGGL((k_tiles<S, C, NT, OBS, IN, OUT, TAPE, PT>), dim3(ntiles), dim3(NT), 0, st,
-                       (const S*)fin, (S*)fout, inst, tiles, salt, filter, partials, rho_out);
+                       (const S*)fin, (S*)fout, inst, tiles, salt, step_dev, filter, partials, rho_out);
     return hipGetLastError();
 }
 
@@ -1576,15 +1582,15 @@ constexpr bool kHasFac = !(sizeof(S) == 4 && sizeof(C) == 8);
 
 template <typename S, typename C, int NT, bool PT>
 hipError_t tiles_nt_pt(Fmt in, Fmt out, bool obs, const void* fin, void* fout, const Instance* inst,
-                       const Tile* tiles, int ntiles, uint32_t salt, int filter, double* partials,
-                       double* rho_out, hipStream_t st)
+                       const Tile* tiles, int ntiles, uint32_t salt, const int64_t* step_dev, int filter,
+                       double* partials, double* rho_out, hipStream_t st)
 {
     if (in == Fmt::F27 && (obs || out == Fmt::F27)) {
         if (obs)
             return do_tiles<S, C, NT, true, Fmt::F27, Fmt::F27, false, PT>(fin, nullptr, inst, tiles, ntiles,
                                                                           0u, filter, partials, rho_out, st);
         return do_tiles<S, C, NT, false, Fmt::F27, Fmt::F27, false, PT>(fin, fout, inst, tiles, ntiles, salt,
-                                                                       filter, nullptr, nullptr, st);
+                                                                       filter, nullptr, nullptr, st, step_dev);
     }
     if constexpr (kHasFac<S, C>) {
         if (obs && in == Fmt::FAC)
@@ -1592,10 +1598,12 @@ hipError_t tiles_nt_pt(Fmt in, Fmt out, bool obs, const void* fin, void* fout, c
                                                                           0u, filter, partials, rho_out, st);
         if (in == Fmt::FAC && out == Fmt::FAC)
             return do_tiles<S, C, NT, false, Fmt::FAC, Fmt::FAC, false, PT>(fin, fout, inst, tiles, ntiles,
-                                                                           salt, filter, nullptr, nullptr, st);
+                                                                           salt, filter, nullptr, nullptr, st,
+                                                                           step_dev);
         if (in == Fmt::F27 && out == Fmt::FAC)
             return do_tiles<S, C, NT, false, Fmt::F27, Fmt::FAC, false, PT>(fin, fout, inst, tiles, ntiles,
-                                                                           salt, filter, nullptr, nullptr, st);
+                                                                           salt, filter, nullptr, nullptr, st,
+                                                                           step_dev);
     }
     return hipErrorInvalidValue;
 }
@@ -1603,14 +1611,14 @@ hipError_t tiles_nt_pt(Fmt in, Fmt out, bool obs, const void* fin, void* fout, c
 // pt: the perturbation operator of Eqs. (4)-(5) in place of the force and Guo's term
 template <typename S, typename C, int NT>
 hipError_t tiles_nt(Fmt in, Fmt out, bool obs, bool pt, const void* fin, void* fout, const Instance* inst,
-                    const Tile* tiles, int ntiles, uint32_t salt, int filter, double* partials,
-                    double* rho_out, hipStream_t st)
+                    const Tile* tiles, int ntiles, uint32_t salt, const int64_t* step_dev, int filter,
+                    double* partials, double* rho_out, hipStream_t st)
 {
     if (pt)
-        return tiles_nt_pt<S, C, NT, true>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, filter,
+        return tiles_nt_pt<S, C, NT, true>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, step_dev, filter,
                                            partials, rho_out, st);
-    return tiles_nt_pt<S, C, NT, false>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, filter, partials,
-                                        rho_out, st);
+    return tiles_nt_pt<S, C, NT, false>(in, out, obs, fin, fout, inst, tiles, ntiles, salt, step_dev, filter,
+                                        partials, rho_out, st);
 }
 
 // The FP64 step writing the adjoint's tape (rho_out as [20][ny][nx]), factored output.
@@ -1627,14 +1635,14 @@ hipError_t tiles_tape_nt(Fmt in, const void* fin, void* fout, const Instance* in
 
 template <typename S, typename C>
 hipError_t tiles_any(Fmt in, Fmt out, bool obs, bool pt, const void* fin, void* fout, const Instance* inst,
-                     const Tile* tiles, int ntiles, int threads, uint32_t salt, int filter,
-                     double* partials, double* rho_out, hipStream_t st)
+                     const Tile* tiles, int ntiles, int threads, uint32_t salt, const int64_t* step_dev,
+                     int filter, double* partials, double* rho_out, hipStream_t st)
 {
     switch (threads) {
-        case 64: return tiles_nt<S, C, 64>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
-        case 128: return tiles_nt<S, C, 128>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
-        case 256: return tiles_nt<S, C, 256>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
-        case 512: return tiles_nt<S, C, 512>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, salt, filter, partials, rho_out, st);
+        case 64: return tiles_nt<S, C, 64>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, salt, step_dev, filter, partials, rho_out, st);
+        case 128: return tiles_nt<S, C, 128>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, salt, step_dev, filter, partials, rho_out, st);
+        case 256: return tiles_nt<S, C, 256>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, salt, step_dev, filter, partials, rho_out, st);
+        case 512: return tiles_nt<S, C, 512>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, salt, step_dev, filter, partials, rho_out, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1737,51 +1745,57 @@ int pair_occupancy(int threads)
 }
 
 // The 27-population two-step pass (FP32 storage), salts of the two steps' stochastic
-// rounding; a workgroup of 2 NT lanes as in k_tiles2w.
+// rounding (or, when step_dev is given, those of steps *step_dev and *step_dev + 1, read when
+// the launch runs); a workgroup of 2 NT lanes as in k_tiles2w.
 template <int NT, bool PT = false>
 __global__ __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles2s(
     const float* __restrict__ fin, float* __restrict__ fout, const Instance* __restrict__ inst,
-    const Tile* __restrict__ tiles, uint32_t salt_a, uint32_t salt_b)
+    const Tile* __restrict__ tiles, uint32_t salt_a, uint32_t salt_b, const int64_t* __restrict__ step_dev)
 {
     static_assert(NT % 64 == 0, "each wave must belong to one step");
     __shared__ Pair27Lds<NT> lds;
     const Tile tl = tiles[blockIdx.x];
     const KParams kp = inst[tl.inst].kp;
     const int64_t off = inst[tl.inst].offset;
-    const uint32_t mixi = mix32((uint32_t)tl.inst * 0x9E3779B9U + 0x51ed270bU);
+    if (step_dev) {
+        const int64_t s = *step_dev;
+        salt_a = step_salt(s);
+        salt_b = step_salt(s + 1);
+    }
     const int lane0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x);
     if (lane0 < NT)
-        pair27_step_a<NT, PT>(fin + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x, salt_a ^ mixi);
+        pair27_step_a<NT, PT>(fin + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x, salt_a);
     else
-        pair27_step_b<NT, PT>(fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x - NT, salt_b ^ mixi);
+        pair27_step_b<NT, PT>(fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x - NT, salt_b);
 }
 
 template <int NT, bool PT>
 hipError_t pair27_launch(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
-                         uint32_t salt_a, uint32_t salt_b, hipStream_t st)
+                         uint32_t salt_a, uint32_t salt_b, const int64_t* step_dev, hipStream_t st)
 {
     hipLaunchKernelGGL((k_tiles2s<NT, PT>), dim3(ntiles), dim3(2 * NT), 0, st, (const float*)fin, (float*)fout, inst,
-                       tiles, salt_a, salt_b);
+                       tiles, salt_a, salt_b, step_dev);
     return hipGetLastError();
 }
 
 template <bool PT>
 hipError_t tiles_pair27_pt(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
-                           int threads, uint32_t salt_a, uint32_t salt_b, hipStream_t st)
+                           int threads, uint32_t salt_a, uint32_t salt_b, const int64_t* step_dev, hipStream_t st)
 {
     switch (threads) {
-        case 64: return pair27_launch<64, PT>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, st);
-        case 128: return pair27_launch<128, PT>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, st);
-        case 256: return pair27_launch<256, PT>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, st);
+        case 64: return pair27_launch<64, PT>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, step_dev, st);
+        case 128: return pair27_launch<128, PT>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, step_dev, st);
+        case 256: return pair27_launch<256, PT>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, step_dev, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 inline hipError_t tiles_pair27_any(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
-                                   int threads, uint32_t salt_a, uint32_t salt_b, bool pt, hipStream_t st)
+                                   int threads, uint32_t salt_a, uint32_t salt_b, const int64_t* step_dev, bool pt,
+                                   hipStream_t st)
 {
-    return pt ? tiles_pair27_pt<true>(fin, fout, inst, tiles, ntiles, threads, salt_a, salt_b, st)
-              : tiles_pair27_pt<false>(fin, fout, inst, tiles, ntiles, threads, salt_a, salt_b, st);
+    return pt ? tiles_pair27_pt<true>(fin, fout, inst, tiles, ntiles, threads, salt_a, salt_b, step_dev, st)
+              : tiles_pair27_pt<false>(fin, fout, inst, tiles, ntiles, threads, salt_a, salt_b, step_dev, st);
 }
 
 inline int pair27_occupancy(int threads)

@@ -4,11 +4,11 @@
 namespace tcg {
 
 hipError_t tiles_f32(Fmt in, Fmt out, bool obs, bool pt, const void* fin, void* fout, const Instance* inst,
-                    const Tile* tiles, int ntiles, int threads, uint32_t salt, int filter,
-                    double* partials, double* rho_out, hipStream_t stream)
+                    const Tile* tiles, int ntiles, int threads, uint32_t salt, const int64_t* step_dev,
+                    int filter, double* partials, double* rho_out, hipStream_t stream)
 {
-    return tiles_any<float, float>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, threads, salt, filter,
-                                partials, rho_out, stream);
+    return tiles_any<float, float>(in, out, obs, pt, fin, fout, inst, tiles, ntiles, threads, salt, step_dev,
+                                filter, partials, rho_out, stream);
 }
 
 int tiles_f32_occupancy(int threads) { return tiles_occupancy<float, float>(threads); }

@@ -108,6 +108,8 @@ def lib():
             "lbm3_batch_destroy": (I, [H]),
             "lbm3_adjoint_record": (I, [H, ctypes.c_int64, ctypes.c_int32]),
             "lbm3_adjoint": (I, [H, _DP, _DP, _DP]),
+            "lbm3_adjoint_pipeline_slots": (I, [ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64,
+                                                ctypes.c_uint64]),
             "lbm3_device_copy": (I, [_VP, _VP, ctypes.c_int64, _VP]),
             "lbm3d_create": (I, [P, ctypes.c_int32, _VP, ctypes.POINTER(H)]),
             "lbm3d_init_fields": (I, [H, _DP]),
@@ -322,6 +324,11 @@ def lbm3_adjoint(h, drho1_T: np.ndarray, nx: int, ny: int):
     dr = np.zeros((3, ny, nx))
     _check(lib().lbm3_adjoint(h, _dptr(g), _dptr(ds), _dptr(dr)), "lbm3_adjoint")
     return ds, dr
+
+
+def lbm3_adjoint_pipeline_slots(nodes: int, ws_two_slots: int, ws_held: int, device_free: int) -> int:
+    """Pipeline slots lbm3_adjoint uses (host rule, no device work): 2 or 1."""
+    return int(lib().lbm3_adjoint_pipeline_slots(int(nodes), int(ws_two_slots), int(ws_held), int(device_free)))
 
 
 # ----------------------------------------------------------------- convenience

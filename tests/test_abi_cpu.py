@@ -141,3 +141,18 @@ def test_d3q19_create_rejects_bad_parameters():
         assert lbm3.lib().lbm3d_create(ctypes.byref(p), nz, None, ctypes.byref(h)) == code, (kw, nz)
         assert h.value is None
     assert lbm3.lib().lbm3d_destroy(None) == lbm3.LBM3_OK
+
+
+def test_adjoint_pipeline_slots_rule():
+    """The adjoint's choice of one or two pipeline slots (a host rule): two below 2^22 nodes
+    where the two-slot workspace fits the free device memory plus the workspace already
+    held, less a 1/16 reserve; one otherwise, whatever the memory."""
+    GB = 1 << 30
+    slots = lbm3.lbm3_adjoint_pipeline_slots
+    assert slots(256 * 256, 2 * GB, 0, 200 * GB) == 2
+    assert slots(1 << 22, 2 * GB, 0, 200 * GB) == 1          # large lattice: one slot
+    assert slots((1 << 22) - 1, 268 * GB, 0, 250 * GB) == 1   # two slots do not fit
+    assert slots((1 << 22) - 1, 134 * GB, 0, 250 * GB) == 2
+    assert slots(1000, 10 * GB, 10 * GB, 0) == 2              # already held
+    assert slots(1000, 10 * GB, 6 * GB, 4 * GB) == 1          # 10 of 10 available: reserve
+    assert slots(1000, 9 * GB, 6 * GB, 4 * GB) == 2

@@ -33,10 +33,12 @@ def _make_batch(ws, precision):
     return b
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_storage"])
 def test_batch_matches_plain_step_bitwise(precision):
     """57 steps (two graph launches of 20 steps and 17 eager launches): every instance's
-    densities equal those of the plain lattice run alone, bitwise."""
+    densities equal those of the plain lattice run alone, bitwise.  With FP32 storage this
+    also checks the stochastic rounding: the second graph replay must round with the salts of
+    steps 21-40, as the plain lattice does, not with those of the captured steps 1-20."""
     ws = _mixed_workloads()
     b = _make_batch(ws, precision)
     lbm3.lbm3_batch_step(b, 40)
@@ -51,7 +53,7 @@ def test_batch_matches_plain_step_bitwise(precision):
     lbm3.lbm3_batch_destroy(b)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_storage"])
 @pytest.mark.parametrize("threads", [0, 64, 256])
 def test_batch_two_step_pass_matches_plain_step_bitwise(precision, threads):
     """With two steps per launch (graph of two-step launches, then eager pairs and an odd last
