@@ -148,6 +148,19 @@ int lbm3_step(lbm3_t *h, int64_t n);
  * Returns LBM3_ENONFINITE (after filling *out) when the state is not finite. */
 int lbm3_observables(lbm3_t *h, lbm3_obs *out, double *rho_out, double *f_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the observables of
+ * lbm3_observables into *out (may be NULL), with the same kernels and the same
+ * result bit for bit, but no densities or populations, and no allocation of any
+ * kind.  Its per-workgroup partial sums live in a static device array of the
+ * library (about 2 MiB, one per GPU, held until the process ends; its address is
+ * looked up when the first handle on a GPU is created), which limits the launch
+ * plan to 32768 workgroups (EINVAL beyond, before any device work).  Calls on one
+ * GPU share that array: calls that overlap in time on one GPU (other threads or
+ * other streams) race and must be serialised by the caller.  Blocking; ESTATE
+ * before the first init_fields / set_state; ENONFINITE as lbm3_observables. */
+int lbm3_observables_noalloc(lbm3_t *h, lbm3_obs *out);
+
 /* Releases the handle and its device memory.  NULL is accepted. */
 int lbm3_destroy(lbm3_t *h);
 

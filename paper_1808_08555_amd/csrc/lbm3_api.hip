@@ -5,7 +5,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "lbm3_handle.h"
 
@@ -321,6 +323,59 @@ int step_handle(lbm3* h, int64_t n, bool factored)
 
 using namespace tcg;
 
+// Device scratch of the allocation-free observables call (lbm3_observables_noalloc): the
+// per-workgroup partial sums of the observing pass (kObsFields doubles per workgroup, at most
+// kNoAllocMaxTiles workgroups) followed by the reduced kObsFields values.  Every GPU the
+// library runs on holds its own copy for the life of the process; in host code `scratch` is
+// only a stand-in for the symbol, and its device address on each GPU is looked up once, with
+// that GPU current, when the first handle on it is created.
+constexpr int kNoAllocMaxTiles = 32768;
+constexpr size_t kScratchDoubles = (size_t)kNoAllocMaxTiles * kObsFields + kObsFields;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_dev;  // by device ordinal; null until looked up
+
+// Looks up this device's address of `scratch` (the current device must be `device`).
+static int resolve_scratch(int device)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize(device + 1, nullptr);
+    if (g_scratch_dev[device]) return LBM3_OK;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[device] = (double*)p;
+    return LBM3_OK;
+}
+
+static double* scratch_of(int device)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return device >= 0 && device < (int)g_scratch_dev.size() ? g_scratch_dev[device] : nullptr;
+}
+
+// Copies the reduced observables held in h->obs_host into *out (may be NULL); ENONFINITE
+// when the state was not finite.
+static int finish_obs(lbm3* h, lbm3_obs* out)
+{
+    const double* o = h->obs_host;
+    if (out) {
+        out->step = h->step;
+        for (int k = 0; k < 3; ++k) out->mass[k] = o[k];
+        out->momentum[0] = o[3];
+        out->momentum[1] = o[4];
+        out->kinetic_energy = o[5];
+        out->u_max = o[6];
+        out->nonfinite = o[7] != 0.0 ? 1 : 0;
+    }
+    if (o[7] != 0.0) {
+        set_error("state is not finite at step %lld", (long long)h->step);
+        return LBM3_ENONFINITE;
+    }
+    return LBM3_OK;
+}
+
 static int ensure_staging(lbm3* h, size_t doubles)
 {
     if (h->staging_cap >= doubles) return LBM3_OK;
@@ -386,6 +441,11 @@ int lbm3_create(const lbm3_params* p, void* hip_stream, lbm3_t** out)
     if (e != hipSuccess) {
         delete h;
         return hip_fail(e, "hipGetDevice");
+    }
+    rc = resolve_scratch(h->device);
+    if (rc) {
+        delete h;
+        return rc;
     }
     const size_t bytes = (size_t)h->kp.span * elem_bytes(h->prec);
     for (int b = 0; b < 2; ++b) {
@@ -518,21 +578,43 @@ int lbm3_observables(lbm3_t* h, lbm3_obs* out, double* rho_out, double* f_out)
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "observables");
-    const double* o = h->obs_host;
-    if (out) {
-        out->step = h->step;
-        for (int k = 0; k < 3; ++k) out->mass[k] = o[k];
-        out->momentum[0] = o[3];
-        out->momentum[1] = o[4];
-        out->kinetic_energy = o[5];
-        out->u_max = o[6];
-        out->nonfinite = o[7] != 0.0 ? 1 : 0;
+    return finish_obs(h, out);
+}
+
+int lbm3_observables_noalloc(lbm3_t* h, lbm3_obs* out)
+{
+    if (!h) {
+        set_error("handle is NULL");
+        return LBM3_EINVAL;
     }
-    if (o[7] != 0.0) {
-        set_error("state is not finite at step %lld", (long long)h->step);
-        return LBM3_ENONFINITE;
+    if (!h->ready) {
+        set_error("lbm3_observables_noalloc before lbm3_init_fields / lbm3_set_state");
+        return LBM3_ESTATE;
     }
-    return LBM3_OK;
+    if (h->ntiles > kNoAllocMaxTiles) {
+        set_error("lbm3_observables_noalloc: the launch plan has %d workgroups, its static scratch "
+                  "holds the partial sums of at most %d (use lbm3_observables, or fewer, taller tiles "
+                  "with lbm3_set_tile)", h->ntiles, kNoAllocMaxTiles);
+        return LBM3_EINVAL;
+    }
+    double* base = scratch_of(h->device);
+    if (!base) {
+        set_error("lbm3_observables_noalloc: no scratch address for device %d", h->device);
+        return LBM3_EDEVICE;
+    }
+    double* partials = base;
+    double* reduced = base + (size_t)kNoAllocMaxTiles * kObsFields;
+    // every workgroup writes all of its partials and the reduction all of its outputs, so
+    // nothing left from an earlier call is read
+    hipError_t e = launch_observe_tiles(h->prec, h->fmt, h->buf[h->cur], h->dinst, h->dtiles, h->ntiles,
+                                        h->threads, partials, nullptr, h->stream,
+                                        h->p.forcing == LBM3_FORCING_PERTURBATION);
+    if (e == hipSuccess) e = launch_reduce_obs(partials, h->ntiles, reduced, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->obs_host, reduced, kObsFields * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "observables_noalloc");
+    return finish_obs(h, out);
 }
 
 int lbm3_destroy(lbm3_t* h)

@@ -87,6 +87,7 @@ def lib():
             "lbm3_set_state": (I, [H, _DP]),
             "lbm3_step": (I, [H, ctypes.c_int64]),
             "lbm3_observables": (I, [H, ctypes.POINTER(lbm3_obs), _DP, _DP]),
+            "lbm3_observables_noalloc": (I, [H, ctypes.POINTER(lbm3_obs)]),
             "lbm3_destroy": (I, [H]),
             "lbm3_last_error": (ctypes.c_char_p, []),
             "lbm3_derived": (I, [P, _DP, _DP, _DP]),
@@ -207,6 +208,16 @@ def lbm3_observables(h, nx: int, ny: int, want_rho: bool = False, want_f: bool =
     if rc != LBM3_OK and not (rc == LBM3_ENONFINITE and not raise_nonfinite):
         _check(rc, "lbm3_observables")
     return _obs_dict(o), rho, f
+
+
+def lbm3_observables_noalloc(h, raise_nonfinite: bool = True) -> dict:
+    """The observables of lbm3_observables (no densities or populations), computed with the
+    library's static device scratch: the call allocates nothing."""
+    o = lbm3_obs()
+    rc = lib().lbm3_observables_noalloc(h, ctypes.byref(o))
+    if rc != LBM3_OK and not (rc == LBM3_ENONFINITE and not raise_nonfinite):
+        _check(rc, "lbm3_observables_noalloc")
+    return _obs_dict(o)
 
 
 def lbm3_destroy(h):
