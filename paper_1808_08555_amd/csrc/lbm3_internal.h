@@ -50,10 +50,11 @@ constexpr int kObsFields = 8;
 enum class Prec { F64, F32S, F32 };
 
 // State formats.  F27: the 27 recoloured populations f_ddag_{i,k} of every node, before
-// streaming.  FAC: the same state factored per node as f_dag_i (9), c_k (3) and V_k (6), from
-// which f_ddag_{i,k} = c_k f_dag_i + w_i V_k . e_i is rebuilt exactly where it is pulled.
+// streaming.  FAC: the same state factored per node as f_dag_i (9), c_k (3), V_0 and V_1 (4),
+// from which f_ddag_{i,k} = c_k f_dag_i + w_i V_k . e_i is rebuilt exactly where it is pulled;
+// V_2 = -(V_0 + V_1) (the three sum to zero), formed the same way by every path.
 enum class Fmt : int32_t { F27 = 0, FAC = 1 };
-constexpr int kFacPlanes = 18;
+constexpr int kFacPlanes = 16;
 
 // Format the step keeps between steps.  With FP32 storage and FP64 arithmetic the step is
 // bound by its arithmetic rather than by memory, and there the 27-population pull measured

@@ -136,12 +136,18 @@ __global__ __launch_bounds__(256) void k_export_fac(const S* __restrict__ fin, d
     for (int i = 0; i < 9; ++i) {
         const int64_t s = (int64_t)wrapi(y - EY[i], ny) * kp.fpitch + wrapi(x - EX[i], nx);
         const C fd = C(fin[(int64_t)i * kp.plane + s]);
+        C vx[3], vy[3];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            vx[k] = C(fin[(int64_t)(12 + 2 * k) * kp.plane + s]);
+            vy[k] = C(fin[(int64_t)(13 + 2 * k) * kp.plane + s]);
+        }
+        vx[2] = fac_v2<C>(vx[0], vx[1]);
+        vy[2] = fac_v2<C>(vy[0], vy[1]);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const C ck = C(fin[(int64_t)(9 + k) * kp.plane + s]);
-            const C vx = C(fin[(int64_t)(12 + 2 * k) * kp.plane + s]);
-            const C vy = C(fin[(int64_t)(13 + 2 * k) * kp.plane + s]);
-            f[(k * 9 + i) * N + j] = double(recon<C>(ck, fd, vx, vy, i));
+            f[(k * 9 + i) * N + j] = double(recon<C>(ck, fd, vx[k], vy[k], i));
         }
     }
 }

@@ -16,16 +16,17 @@
 //             (rho_k rho_l / rho) n_kl with beta_kl of Eqs. (19)-(20)      (Eq. 13)
 //   store:    the recoloured state of x, in one of two formats:
 //             F27  the 27 values f_ddag_{i,k}(x);
-//             FAC  the 18 values f_dag_i(x), c_k(x), V_k(x).  Eq. (13) makes every
-//                  f_ddag_{i,k}(x) a function of these, so the next step rebuilds the
-//                  populations it pulls from x - e_i, with the same arithmetic (recon()) the
-//                  F27 store uses: both formats give bitwise the same next state when the
-//                  storage type is the compute type.  FAC moves 2/3 of the bytes of F27.
+//             FAC  the 16 values f_dag_i(x), c_k(x), V_0(x), V_1(x) (V_2 = -(V_0 + V_1):
+//                  the recolouring vectors of the three fluids sum to zero).  Eq. (13)
+//                  makes every f_ddag_{i,k}(x) a function of these, so the next step rebuilds
+//                  the populations it pulls from x - e_i, with the same arithmetic (recon())
+//                  the F27 store uses: both formats give bitwise the same next state when the
+//                  storage type is the compute type.  FAC moves 16/27 of the bytes of F27.
 //
 // Layout: plane q of node (x, y) at element q*plane + y*pitch + x, x fastest, with the rows of
 // all planes interleaved (pitch = 27 plane for F27, 18 plane for FAC), so one lattice row
 // of the state is one contiguous block and a wavefront's 64 lanes touch 64 consecutive values
-// of one plane row.  FAC planes: 0-8 f_dag_i, 9-11 c_k, 12-17 (V_kx, V_ky) for k = 0, 1, 2.
+// of one plane row.  FAC planes: 0-8 f_dag_i, 9-11 c_k, 12-15 (V_kx, V_ky) for k = 0, 1.
 //
 // Work decomposition (y-marching strips).  A workgroup of NT threads owns a strip of
 // cols <= NT-6 output columns and a run of `rows` output rows.  Thread t sits on column
@@ -65,7 +66,7 @@ __device__ __forceinline__ constexpr C wgt(int i)
 }
 
 // 32-bit integer mixer ("lowbias32", from Wellons' hash-prospector search): a bijection with
-// low output bias, used as a counter-based generator keyed by (step, node, value index).
+// low output bias; it seeds the per-node generator of the stochastic rounding (NodeBits).
 __device__ __forceinline__ uint32_t mix32(uint32_t x)
 {
     x ^= x >> 16;
@@ -96,12 +97,31 @@ __device__ __forceinline__ float round_stochastic(double v, uint32_t bits)
     return fabs(v) <= 3.4028234663852886e38 ? r : (float)v;
 }
 
-// Store of one value in the storage type S from the compute type C.
+// Random bits for the stochastic rounding of the values one node stores in one step: a
+// lowbias32 hash of the node's key (step salt, node index) seeds Marsaglia's xorshift32
+// (shifts 13, 17, 5), which gives one 32-bit output per stored value, in store order.  The
+// hash decorrelates neighbouring nodes and steps; the xorshift steps are shifts and xors at
+// the full issue rate, where a hash per value would cost two 32-bit integer multiplies,
+// which issue at a quarter of the rate.  (xorshift32 must not start at 0, hence the | 1.)
+struct NodeBits {
+    uint32_t x;
+    __device__ explicit NodeBits(uint32_t key) : x(mix32(key) | 1u) {}
+    __device__ uint32_t next()
+    {
+        x ^= x << 13;
+        x ^= x >> 17;
+        x ^= x << 5;
+        return x;
+    }
+};
+
+// Store of one value in the storage type S from the compute type C (FP32 storage of FP64
+// arithmetic: stochastic rounding with the node's next random bits).
 template <typename S, typename C>
-__device__ __forceinline__ S to_storage(C v, uint32_t key)
+__device__ __forceinline__ S to_storage(C v, NodeBits& bits)
 {
     if constexpr (sizeof(S) == 4 && sizeof(C) == 8)
-        return round_stochastic(v, mix32(key));
+        return round_stochastic(v, bits.next());
     else
         return S(v);
 }
@@ -210,6 +230,13 @@ __device__ __forceinline__ C recon(C ck, C fdi, C vx, C vy, int i)
 #pragma clang fp contract(off)
     if (i == 0) return ck * fdi;
     return fma(ck, fdi, wgt<C>(i) * dot_e<C>(vx, vy, i));
+}
+
+// The third fluid's recolouring vector component from the other two (they sum to zero).
+template <typename C>
+__device__ __forceinline__ C fac_v2(C v0, C v1)
+{
+    return -(v0 + v1);
 }
 
 // Densities from the 27 pulled populations v[k*9 + i], summed in a fixed order that groups
@@ -355,13 +382,15 @@ __device__ __forceinline__ void collide_recolour(const C (&f)[9], const C (&rk)[
     const C a0 = K.beta0 * (C(1) + ct * K.g[0]) * (rk[0] * rk[1]) * irho;
     const C a1 = K.beta0 * (C(1) + ct * K.g[1]) * (rk[0] * rk[2]) * irho;
     const C a2 = K.beta0 * (C(1) + ct * K.g[2]) * (rk[1] * rk[2]) * irho;
-    // V_k = sum_{l != k} a_kl n_kl with n_lk = -n_kl
+    // V_k = sum_{l != k} a_kl n_kl with n_lk = -n_kl; the three sum to zero, and V_2 is taken
+    // as -(V_0 + V_1) here and wherever a factored state is expanded (fac_v2), so that the
+    // factored state needs only V_0 and V_1 and every path rounds alike
     V[0] = a0 * n[0] + a1 * n[2];
     V[1] = a0 * n[1] + a1 * n[3];
     V[2] = a2 * n[4] - a0 * n[0];
     V[3] = a2 * n[5] - a0 * n[1];
-    V[4] = -(a1 * n[2] + a2 * n[4]);
-    V[5] = -(a1 * n[3] + a2 * n[5]);
+    V[4] = fac_v2<C>(V[0], V[2]);
+    V[5] = fac_v2<C>(V[1], V[3]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) ck[k] = rk[k] * irho;
 }
@@ -371,17 +400,36 @@ __device__ __forceinline__ void collide_recolour(const C (&f)[9], const C (&rk)[
 // source row by lane (fields 0-2 c_k, 3-8 V_k), read at lane t - e_x,i.  D0 = partial sums of
 // row s (directions with e_y = +1 and 0 received), D1 = those of row s + 1 (e_y = +1
 // received); direction groups by e_y: +1 {2, 5, 6}, 0 {0, 1, 3}, -1 {4, 7, 8}.  Completes row
-// s - 1 into r0, f0.  (The scheduling barriers keep the LDS reads of one group from being
-// hoisted above the previous group, which would hold all 81 of them in registers at once.)
-template <typename C, int NT, typename FD>
+// s - 1 into r0, f0.  With PULL_ONCE the nine fields of the three source lanes t - 1, t, t + 1
+// are read from LDS once (27 reads; each group pulls one direction from each of those lanes,
+// so reading per direction reads every field three times): measured +7% for the FP64
+// two-step pass, +11% for FP32, +13% for the FP64 step at 256^2, -3% for the FP64 one-step
+// kernel at 4096^2.  (The scheduling barriers keep the arithmetic of one group from being
+// interleaved with the next, which would hold the pulled values of all groups in registers
+// at once.)
+template <typename C, int NT, bool PULL_ONCE = true, typename FD>
 __device__ __forceinline__ void pull_row(FD f_dag, const C (*X)[NT], int t, C (&d0r)[3], C (&d0f)[6],
                                          C (&d1r)[3], C (&d1f)[3], C (&r0)[3], C (&f0)[9])
 {
-    auto pull = [&](int i, C (&fk)[3]) {
-        const int l = t - EX[i];
-        const C fdi = f_dag(i);
+    // by e_x + 1: fields of lane t + 1 (e_x = -1), t (0), t - 1 (+1)
+    C xs[3][9];
+    if constexpr (PULL_ONCE) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) fk[k] = recon<C>(X[k][l], fdi, X[3 + 2 * k][l], X[4 + 2 * k][l], i);
+        for (int e = 0; e < 3; ++e)
+#pragma unroll
+            for (int q = 0; q < 9; ++q) xs[e][q] = X[q][t + 1 - e];
+    }
+    auto pull = [&](int i, C (&fk)[3]) {
+        const C fdi = f_dag(i);
+        if constexpr (PULL_ONCE) {
+            const C* xl = xs[EX[i] + 1];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) fk[k] = recon<C>(xl[k], fdi, xl[3 + 2 * k], xl[4 + 2 * k], i);
+        } else {
+            const int l = t - EX[i];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) fk[k] = recon<C>(X[k][l], fdi, X[3 + 2 * k][l], X[4 + 2 * k][l], i);
+        }
     };
     auto group = [&](int a, int b, int c, C (&g)[3], C& ta, C& tb, C& tc) {
         C fa[3], fb[3], fc[3];
@@ -544,7 +592,7 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
     const int J = rows + 4;
 
     // ---- input: F27 pulls all 27 populations of a row directly
-    constexpr int NV = IN == Fmt::F27 ? 27 : 18;
+    constexpr int NV = IN == Fmt::F27 ? 27 : kFacPlanes;
     auto load_f27 = [&](int r, C (&v)[NV]) {
         const int64_t pitch = kp.pitch;
         const int64_t srow[3] = {(int64_t)(r + 1 == ny ? 0 : r + 1) * pitch, (int64_t)r * pitch,
@@ -558,7 +606,7 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
                                        scol[EX[i] + 1]));
     };
     // ---- input: FAC loads source row s (wrapped): v[0..8] = f_dag_i(x - e_x,i, s) (pulled
-    // along x), v[9..17] = c_k, V_k of the lane's own column
+    // along x), v[9..15] = c_k, V_0, V_1 of the lane's own column
     auto load_fac = [&](int s, C (&v)[NV]) {
         const int64_t rowo = (int64_t)s * kp.fpitch;
         const int64_t pl = fresh_stride(plane);
@@ -570,14 +618,16 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
     };
     // FAC partial sums of the rows above (see pull_row)
     C d0r[3], d0f[6], d1r[3], d1f[3];  // d0f: f_2, f_5, f_6, f_0, f_1, f_3; d1f: f_2, f_5, f_6
-    // FAC: publish the c_k, V_k of this lane's column of a source row (v[9..17]) to the
-    // neighbouring lanes, in exchange slot `slot` (two slots, used by alternate rows); a
+    // FAC: publish the c_k, V_k of this lane's column of a source row (v[9..15], and V_2) to
+    // the neighbouring lanes, in exchange slot `slot` (two slots, used by alternate rows); a
     // barrier separates this from consume_fac's reads.
     auto publish = [&](const C (&v)[NV], int slot) {
         if constexpr (IN == Fmt::FAC) {
             if (in0) {
 #pragma unroll
-                for (int q = 0; q < 9; ++q) xb[slot][q][t] = v[9 + q];
+                for (int q = 0; q < 7; ++q) xb[slot][q][t] = v[9 + q];
+                xb[slot][7][t] = fac_v2<C>(v[12], v[14]);
+                xb[slot][8][t] = fac_v2<C>(v[13], v[15]);
             }
         }
     };
@@ -723,7 +773,7 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
             C fd[9], ck[3], V[6], ux, uy, mxh, myh;
             collide_recolour<C, PT>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
             if constexpr (!OBS) {
-                const uint32_t key = ((uint32_t)yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt;
+                NodeBits bits(((uint32_t)yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt);
                 const int64_t pl = fresh_stride(plane);
                 if constexpr (OUT == Fmt::F27) {
                     const int64_t orow = (int64_t)yo * kp.pitch;
@@ -734,22 +784,22 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
                             const int q = k * 9 + i;
                             const C val = recon<C>(ck[k], fd[i], V[2 * k], V[2 * k + 1], i);
                             st_at(fout + ((int64_t)q * pl + orow), xoff,
-                                  to_storage<S, C>(val, key + (uint32_t)q));
+                                  to_storage<S, C>(val, bits));
                         }
                 } else {
                     const int64_t orow = (int64_t)yo * kp.fpitch;
 #pragma unroll
                     for (int i = 0; i < 9; ++i)
                         st_at(fout + ((int64_t)i * pl + orow), xoff,
-                              to_storage<S, C>(fd[i], key + (uint32_t)i));
+                              to_storage<S, C>(fd[i], bits));
 #pragma unroll
                     for (int k = 0; k < 3; ++k)
                         st_at(fout + ((int64_t)(9 + k) * pl + orow), xoff,
-                              to_storage<S, C>(ck[k], key + (uint32_t)(9 + k)));
+                              to_storage<S, C>(ck[k], bits));
 #pragma unroll
-                    for (int q = 0; q < 6; ++q)
+                    for (int q = 0; q < 4; ++q)
                         st_at(fout + ((int64_t)(12 + q) * pl + orow), xoff,
-                              to_storage<S, C>(V[q], key + (uint32_t)(12 + q)));
+                              to_storage<S, C>(V[q], bits));
                 }
             } else {
                 const double rho = double(rB[0]) + double(rB[1]) + double(rB[2]);
@@ -839,26 +889,33 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
     const StepConsts<C> K(kp);
     const int JA = rows + 10;
     const int J = rows + 11;  // one more iteration for B's last row
-
-    auto load_fac = [&](int s, C (&v)[18]) {
-        // (plane offsets left to the optimiser here: taking the stride afresh, as the other
-        // marches do, measured 6% slower in this kernel)
+    // A source row is loaded in two parts: its f_dag_i at this lane's pull columns (pulled by
+    // this lane in the next phase 0) and its c_k, V_0, V_1 at this lane's own column (published
+    // to the neighbouring lanes in the next phase 1).  Each part goes into its registers right
+    // after their previous contents were used, so no copy of a prefetched row is kept (the
+    // registers freed hold the 27 exchange fields pull_row reads once).
+    constexpr int NC = kFacPlanes - 9;
+    auto load_fd = [&](int s, C (&v)[9]) {
         const int64_t rowo = (int64_t)s * kp.fpitch;
 #pragma unroll
         for (int i = 0; i < 9; ++i) v[i] = ld_at(fin + ((int64_t)i * plane + rowo), scol[EX[i] + 1]);
-#pragma unroll
-        for (int q = 9; q < 18; ++q) v[q] = ld_at(fin + ((int64_t)q * plane + rowo), xoff);
     };
-    auto publish = [&](const C (&v)[18], int slot) {
+    auto load_cv = [&](int s, C (&v)[NC]) {
+        const int64_t rowo = (int64_t)s * kp.fpitch;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) v[q] = ld_at(fin + ((int64_t)(9 + q) * plane + rowo), xoff);
+    };
+    auto publish = [&](const C (&v)[NC], int slot) {
         if (a0) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) L.xA[slot][q][t] = v[9 + q];
+            for (int q = 0; q < 7; ++q) L.xA[slot][q][t] = v[q];
+            L.xA[slot][7][t] = fac_v2<C>(v[3], v[5]);
+            L.xA[slot][8][t] = fac_v2<C>(v[4], v[6]);
         }
     };
-
-    C fA[9], fB[9], rA[3], rB[3], nB[6], d0r[3], d0f[6], d1r[3], d1f[3], vn[18];
+    C fA[9], fB[9], rA[3], rB[3], nB[6], d0r[3], d0f[6], d1r[3], d1f[3], vf[9], vc[NC];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fA[i] = fB[i] = C(0);
+    for (int i = 0; i < 9; ++i) fA[i] = fB[i] = vf[i] = C(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         rA[k] = rB[k] = C(1);
@@ -867,52 +924,47 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
 #pragma unroll
     for (int q = 0; q < 6; ++q) nB[q] = d0f[q] = C(0);
 #pragma unroll
-    for (int q = 0; q < 18; ++q) vn[q] = C(1);
-
-    // pre-roll (as march() with first output row y0 - 3): source rows y0 - 6 and y0 - 5, then
-    // row y0 - 4 published for the first iteration; three barriers
-    RowCursor src(y0 - 6, ny);  // source rows in load order: y0 - 6, y0 - 5, ...
+    for (int q = 0; q < NC; ++q) vc[q] = C(1);
+    RowCursor src(y0 - 6, ny);
     {
         const int r = src.next();
-        if (a0) load_fac(r, vn);
+        if (a0) {
+            load_cv(r, vc);
+            load_fd(r, vf);
+        }
     }
 #pragma unroll 1
     for (int p = 0; p < 2; ++p) {
-        C v[18], r_[3], f_[9];
-#pragma unroll
-        for (int q = 0; q < 18; ++q) v[q] = vn[q];
-        publish(v, p);
+        publish(vc, p);
         const int r = src.next();
-        if (a0) load_fac(r, vn);
+        if (a0) load_cv(r, vc);
         __syncthreads();
-        if (a1) pull_row<C, NT>([&](int i) { return v[i]; }, L.xA[p], t, d0r, d0f, d1r, d1f, r_, f_);
+        C r_[3], f_[9];
+        if (a1) pull_row<C, NT>([&](int i) { return vf[i]; }, L.xA[p], t, d0r, d0f, d1r, d1f, r_, f_);
+        if (a0) load_fd(r, vf);
     }
-    publish(vn, 0);
+    publish(vc, 0);
     __syncthreads();
-
 #pragma unroll 1
     for (int j = 0; j < J; ++j) {
         const bool live = j < JA;
         const int s0 = j % 3, s1 = (j + 2) % 3, s2 = (j + 1) % 3;
-        // phase 0: densities of row y0 - 5 + j from source row y0 - 4 + j
         C f0[9], r0[3];
 #pragma unroll
         for (int i = 0; i < 9; ++i) f0[i] = C(0);
 #pragma unroll
         for (int k = 0; k < 3; ++k) r0[k] = C(1);
         if (live) {
-            C v[18];
-#pragma unroll
-            for (int q = 0; q < 18; ++q) v[q] = vn[q];
-            const int r = src.next();  // row y0 - 3 + j
-            if (a0 && j + 1 < JA) load_fac(r, vn);
-            if (a1) pull_row<C, NT>([&](int i) { return v[i]; }, L.xA[j & 1], t, d0r, d0f, d1r, d1f, r0, f0);
+            const int r = src.next();
+            const bool more = a0 && j + 1 < JA;
+            if (more) load_cv(r, vc);
+            if (a1) pull_row<C, NT>([&](int i) { return vf[i]; }, L.xA[j & 1], t, d0r, d0f, d1r, d1f, r0, f0);
+            if (more) load_fd(r, vf);
             const C irho = recip((r0[0] + r0[1]) + r0[2]);
 #pragma unroll
             for (int k = 0; k < 3; ++k) L.cA[s0][k][t] = r0[k] * irho;
         }
         __syncthreads();
-        // phase 1: stress of row y0 - 6 + j; publish the next source row
         C nA[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
         if (live && j >= 2 && a2) {
             C Txx, Txy, Tyy;
@@ -921,9 +973,8 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
             L.tA[s1][1][t] = Txy;
             L.tA[s1][2][t] = Tyy;
         }
-        if (j + 1 < JA) publish(vn, (j + 1) & 1);
+        if (j + 1 < JA) publish(vc, (j + 1) & 1);
         __syncthreads();
-        // phase 2: recolour row y0 - 7 + j into xB
         if (live && j >= 4 && a3) {
             C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
             C Tn[3];
@@ -1031,7 +1082,7 @@ __device__ __forceinline__ void pair_step_b(C* __restrict__ fout, const KParams&
 #pragma unroll
             for (int k = 0; k < 3; ++k) st_at(fout + ((int64_t)(9 + k) * plane + orow), xoff, ck[k]);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) st_at(fout + ((int64_t)(12 + q) * plane + orow), xoff, V[q]);
+            for (int q = 0; q < 4; ++q) st_at(fout + ((int64_t)(12 + q) * plane + orow), xoff, V[q]);
         }
         if (live && m >= 0) {
 #pragma unroll
@@ -1082,23 +1133,25 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
     const StepConsts<C> K(kp);
     const int JA = rows + 10;
 
-    auto load_fac = [&](int s, C (&v)[18]) {
+    auto load_fac = [&](int s, C (&v)[kFacPlanes]) {
         const int64_t rowo = (int64_t)s * kp.fpitch;
         const int64_t pl = fresh_stride(plane);
 #pragma unroll
         for (int i = 0; i < 9; ++i) v[i] = ld_at(fin + ((int64_t)i * pl + rowo), scol[EX[i] + 1]);
 #pragma unroll
-        for (int q = 9; q < 18; ++q) v[q] = ld_at(fin + ((int64_t)q * pl + rowo), xoff);
+        for (int q = 9; q < kFacPlanes; ++q) v[q] = ld_at(fin + ((int64_t)q * pl + rowo), xoff);
     };
-    auto publish_a = [&](const C (&v)[18], int slot) {
+    auto publish_a = [&](const C (&v)[kFacPlanes], int slot) {
         if (a0) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) xA[slot][q][t] = v[9 + q];
+            for (int q = 0; q < 7; ++q) xA[slot][q][t] = v[9 + q];
+            xA[slot][7][t] = fac_v2<C>(v[12], v[14]);
+            xA[slot][8][t] = fac_v2<C>(v[13], v[15]);
         }
     };
 
     // A: pipeline, partial sums and the prefetched next source row
-    C fA_a[9], fB_a[9], rA_a[3], rB_a[3], nB_a[6], d0r_a[3], d0f_a[6], d1r_a[3], d1f_a[3], vn[18];
+    C fA_a[9], fB_a[9], rA_a[3], rB_a[3], nB_a[6], d0r_a[3], d0f_a[6], d1r_a[3], d1f_a[3], vn[kFacPlanes];
     // B: pipeline and partial sums
     C fA_b[9], fB_b[9], rA_b[3], rB_b[3], nB_b[6], d0r_b[3], d0f_b[6], d1r_b[3], d1f_b[3];
 #pragma unroll
@@ -1112,7 +1165,7 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
 #pragma unroll
     for (int q = 0; q < 6; ++q) nB_a[q] = nB_b[q] = d0f_a[q] = d0f_b[q] = C(0);
 #pragma unroll
-    for (int q = 0; q < 18; ++q) vn[q] = C(1);
+    for (int q = 0; q < kFacPlanes; ++q) vn[q] = C(1);
 
     // A's pre-roll (as march() with first output row y0 - 3): source rows y0 - 6 and y0 - 5,
     // then row y0 - 4 published for the first iteration
@@ -1123,9 +1176,9 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
     }
 #pragma unroll 1
     for (int p = 0; p < 2; ++p) {
-        C v[18], r_[3], f_[9];
+        C v[kFacPlanes], r_[3], f_[9];
 #pragma unroll
-        for (int q = 0; q < 18; ++q) v[q] = vn[q];
+        for (int q = 0; q < kFacPlanes; ++q) v[q] = vn[q];
         publish_a(v, p);
         const int r = src.next();
         if (a0) load_fac(r, vn);
@@ -1148,9 +1201,9 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
             for (int i = 0; i < 9; ++i) f0a[i] = C(0);
 #pragma unroll
             for (int k = 0; k < 3; ++k) r0a[k] = C(1);
-            C v[18];
+            C v[kFacPlanes];
 #pragma unroll
-            for (int q = 0; q < 18; ++q) v[q] = vn[q];
+            for (int q = 0; q < kFacPlanes; ++q) v[q] = vn[q];
             const int r = src.next();  // row y0 - 3 + j
             if (a0 && j + 1 < JA) load_fac(r, vn);
             if (a1)
@@ -1237,7 +1290,7 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
 #pragma unroll
             for (int k = 0; k < 3; ++k) st_at(fout + ((int64_t)(9 + k) * pl + orow), xoff, ck[k]);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) st_at(fout + ((int64_t)(12 + q) * pl + orow), xoff, V[q]);
+            for (int q = 0; q < 4; ++q) st_at(fout + ((int64_t)(12 + q) * pl + orow), xoff, V[q]);
         }
         if (jb >= 0) {
 #pragma unroll
@@ -1357,7 +1410,7 @@ __device__ __forceinline__ void pair27_step_a(const float* __restrict__ fin, con
         // phase 2: recolour row y0 - 7 + j and round it as it would be stored
         if (live && j >= 4 && a3) {
             const uint32_t yo = (uint32_t)wrapi(y0 - 7 + j, ny);
-            const uint32_t key = (yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt;
+            NodeBits bits((yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt);
             C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
             C Tn[3];
             force_or_stress<C, NT, PT>(L.tA, s0, s1, s2, t, Fx, Fy, Tn);
@@ -1368,7 +1421,7 @@ __device__ __forceinline__ void pair27_step_a(const float* __restrict__ fin, con
                 for (int i = 0; i < 9; ++i) {
                     const int q = k * 9 + i;
                     L.ring[s0][q][t] =
-                        to_storage<float, C>(recon<C>(ck[k], fd[i], V[2 * k], V[2 * k + 1], i), key + (uint32_t)q);
+                        to_storage<float, C>(recon<C>(ck[k], fd[i], V[2 * k], V[2 * k + 1], i), bits);
                 }
         }
 #pragma unroll
@@ -1451,7 +1504,7 @@ __device__ __forceinline__ void pair27_step_b(float* __restrict__ fout, const KP
         // phase 2: collide, recolour and store row y0 - 4 + jb
         if (live && jb >= 4 && b3) {
             const int yo = y0 - 4 + jb;
-            const uint32_t key = ((uint32_t)yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt;
+            NodeBits bits(((uint32_t)yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt);
             C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
             C Tn[3];
             force_or_stress<C, NT, PT>(L.tB, s0, s1, s2, t, Fx, Fy, Tn);
@@ -1464,7 +1517,7 @@ __device__ __forceinline__ void pair27_step_b(float* __restrict__ fout, const KP
                 for (int i = 0; i < 9; ++i) {
                     const int q = k * 9 + i;
                     st_at(fout + ((int64_t)q * pl + orow), xoff,
-                          to_storage<float, C>(recon<C>(ck[k], fd[i], V[2 * k], V[2 * k + 1], i), key + (uint32_t)q));
+                          to_storage<float, C>(recon<C>(ck[k], fd[i], V[2 * k], V[2 * k + 1], i), bits));
                 }
         }
         if (live) {

@@ -460,7 +460,7 @@ def test_factored_state_matches_27_population_path_bitwise(case, precision):
         A.set_state(A.state())
         assert lbm3.lbm3_state_buffer(A.h)[4] == 27
         A.step(1)
-        assert lbm3.lbm3_state_buffer(A.h)[4] == 18
+        assert lbm3.lbm3_state_buffer(A.h)[4] == 16
     B.step(steps)
     oa, ra, fa = A.observables(want_rho=True, want_f=True)
     ob, rb, fb = B.observables(want_rho=True, want_f=True)
