@@ -234,18 +234,54 @@ def bench_d3q19(torch, lbm3, inputs, n: int, steps: int):
             "frac_of_peak": round(912 * lu / t / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def cpu_baseline(w, steps: int = 8):
-    import oracle
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
+
+def _oracle_mlups(oracle, w, steps: int):
     p = oracle.Params(w.nx, w.ny, w.sigma, w.tau)
     f = oracle.init(p, w.rho)
     t0 = time.perf_counter()
-    f = oracle.run(p, f, steps)
+    oracle.run(p, f, steps)
     dt = time.perf_counter() - t0
-    return {"value": w.nx * w.ny * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{steps} FP64 steps of the full {w.nx}x{w.ny} droplet-tiling lattice "
-                      f"({dt:.1f} s, OpenMP over rows)"}
+    return w.nx * w.ny * steps / dt / 1e6, dt
+
+
+def cpu_baseline(w, inputs):
+    """The FP64 oracle on the host: the headline lattice (5 steps of 4096^2), the 256^2
+    compound droplet (1000 steps) and the 1024^2 double droplet (100 steps) with OpenMP over
+    rows on every core the process may use, and the 256^2 droplet (100 steps) on one thread
+    (the oracle as written is serial per row)."""
+    import oracle
+
+    threads = oracle.num_threads()
+    w256 = inputs.compound_droplet(256, 30.0, 60.0, 0.01, 0.01)
+    w1024 = inputs.double_droplet(1024, 100.0, 1.0, 1.0, steps=0)
+    head, t_head = _oracle_mlups(oracle, w, 5)
+    s256, t256 = _oracle_mlups(oracle, w256, 1000)
+    s1024, t1024 = _oracle_mlups(oracle, w1024, 100)
+    oracle.set_num_threads(1)
+    try:
+        one, t_one = _oracle_mlups(oracle, w256, 100)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": round(head, 2), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"5 FP64 steps of the full {w.nx}x{w.ny} droplet-tiling lattice ({t_head:.1f} s, "
+                      f"OpenMP over rows on {threads} threads)",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "usable_cores": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "all_core_mlups": {"droplet_tiling_4096_5_steps": round(head, 2),
+                               "compound_256_1000_steps": round(s256, 2),
+                               "double_droplet_1024_100_steps": round(s1024, 2)},
+            "single_thread_mlups": {"compound_256_100_steps": round(one, 3)},
+            "seconds": round(t_head + t256 + t1024 + t_one, 1)}
 
 
 def main():
@@ -332,7 +368,7 @@ def main():
     achieved = main_res["gbs"]
     traffic = measured_traffic("lbm3_step_fp64_R4096")
     # VALU issue fraction of the dominant kernel from the committed instruction counters
-    valu = (profile_figure("lbm3_step_fp64_R4096", "sq_insts", "VALU issue fraction")
+    valu = (profile_figure("lbm3_step_fp64_R4096", "pmc", "VALU issue fraction")
             if main_res["steps_per_launch"] == 2 else None)
     kernel = ("two steps per launch (k_tiles2w: one step per wave group)" if main_res["steps_per_launch"] == 2
               else "one step per launch (k_tiles)")
@@ -343,13 +379,22 @@ def main():
                 "ms_per_launch": round(main_res["ms_per_launch"], 4),
                 "frac_of_device_copy": round(achieved / copy_gbs, 4), "device_copy_gbs": round(copy_gbs, 1),
                 "valu_issue_frac": valu,
+                "bytes_per_lu": main_res["bytes_per_launch"] / (n * main_res["steps_per_launch"]),
+                # the same MLUPS against other byte counts per lattice update: the 27 FP64
+                # populations read and written once (432 B: the count of a kernel that stores
+                # the populations and runs one step per launch; this kernel stores a factored
+                # state and fuses two steps, so it can exceed 1 against it), and the smallest
+                # exact factored state (15 values: rho_3 and c_3 follow from the others; 120 B
+                # per update in two-step launches)
+                "frac_vs_27_populations_432B": round(main_res["mlups"] * 1e6 * 432 / 1e9 / HBM_PEAK_GBS, 4),
+                "frac_vs_15_values_two_step_120B": round(main_res["mlups"] * 1e6 * 120 / 1e9 / HBM_PEAK_GBS, 4),
                 "one_step_kernel": {"mlups": round(one_step["mlups"], 1), "gbs": round(one_step["gbs"], 1),
                                     "frac": round(one_step["gbs"] / HBM_PEAK_GBS, 4),
                                     "frac_of_device_copy": round(one_step["gbs"] / copy_gbs, 4)}}
     cpu = None
     if not args.no_cpu_baseline:
         log("oracle CPU baseline ...")
-        cpu = cpu_baseline(w)
+        cpu = cpu_baseline(w, inputs)
         log(f"cpu {cpu}")
     line = {
         "metric": METRIC, "value": round(main_res["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,

@@ -110,6 +110,7 @@ def lib():
             "oracle_observables": (ctypes.c_int, [PP, _DP, _DP]),
             "oracle_step_nodes": (ctypes.c_int, [PP, _DP, ctypes.c_int32, _IP, _IP, _DP]),
             "oracle_num_threads": (ctypes.c_int, []),
+            "oracle_set_num_threads": (None, [ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -268,6 +269,11 @@ def num_threads() -> int:
     return int(lib().oracle_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().oracle_set_num_threads(int(n))
+
+
 def density(f: np.ndarray) -> np.ndarray:
     """rho_k = sum_i f_{i,k} of a state (text after the streaming equation)."""
     return f.sum(axis=1)
@@ -291,7 +297,8 @@ class use_library:
                      "oracle_recolour_node", "oracle_stress_node", "oracle_perturbation_node",
                      "oracle_gradient",
                      "oracle_step", "oracle_run", "oracle_init", "oracle_fields",
-                     "oracle_observables", "oracle_step_nodes", "oracle_num_threads"):
+                     "oracle_observables", "oracle_step_nodes", "oracle_num_threads",
+                     "oracle_set_num_threads"):
             src = getattr(self._saved, name)
             dst = getattr(L, name)
             dst.restype = src.restype

@@ -683,3 +683,13 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the OpenMP loops from now on (for the single-thread baseline). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -251,16 +251,14 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ la
             w.Gbar[(2 * p + 1) * N + j] = Gbr[p][1];
         }
     }
-    for (int p = 0; p < 3; ++p) red[p][t] = sig_beta[p];
+    // wavefront sums, then the four wave sums in order
+    for (int p = 0; p < 3; ++p) sig_beta[p] = wave_sum(sig_beta[p]);
+    if ((t & 63) == 0)
+        for (int p = 0; p < 3; ++p) red[p][t >> 6] = sig_beta[p];
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (t < h)
-            for (int p = 0; p < 3; ++p) red[p][t] += red[p][t + h];
-        __syncthreads();
-    }
     if (t < 3) {
         const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-        w.sig[b * 6 + t] += red[t][0];
+        w.sig[b * 6 + t] += ((red[t][0] + red[t][1]) + red[t][2]) + red[t][3];
     }
 }
 
@@ -415,14 +413,15 @@ __global__ __launch_bounds__(NT) void k_adj_sf(Geo g, AdjWS w, const Tile* __res
     // per-workgroup sums of the stress part of dL/dsigma (the ring is free again)
     __syncthreads();
     double* red = &ring[0][0][0];
-    for (int p = 0; p < 3; ++p) red[p * NT + t] = sig_st[p];
+    for (int p = 0; p < 3; ++p) sig_st[p] = wave_sum(sig_st[p]);
+    if ((t & 63) == 0)
+        for (int p = 0; p < 3; ++p) red[p * NT + (t >> 6)] = sig_st[p];
     __syncthreads();
-    for (int h = NT / 2; h > 0; h >>= 1) {
-        if (t < h)
-            for (int p = 0; p < 3; ++p) red[p * NT + t] += red[p * NT + t + h];
-        __syncthreads();
+    if (t < 3) {
+        double v = red[t * NT];
+        for (int q = 1; q < NT / 64; ++q) v += red[t * NT + q];
+        w.sig[(int64_t)blockIdx.x * 6 + 3 + t] += v;
     }
-    if (t < 3) w.sig[(int64_t)blockIdx.x * 6 + 3 + t] += red[t * NT];
 }
 
 // The adjoint state is kept factored per node as (dL/df_i, dL/drho_k), 12 values: f_{i,k}

@@ -47,6 +47,24 @@ struct Instance {
 // Observables partials: 3 masses, 2 momenta, kinetic energy, max|u|, nonfinite flag.
 constexpr int kObsFields = 8;
 
+// Wavefront reductions (butterfly of lane exchanges across the 64 lanes of a wave, no LDS
+// storage); afterwards every lane holds the wave's result.  The max lets a NaN win.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = (o > v || o != o) ? o : v;
+    }
+    return v;
+}
+
 enum class Prec { F64, F32S, F32 };
 
 // State formats.  F27: the 27 recoloured populations f_ddag_{i,k} of every node, before

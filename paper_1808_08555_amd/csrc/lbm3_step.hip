@@ -6,7 +6,9 @@
 namespace tcg {
 namespace {
 
-// Fixed-order second pass over the per-workgroup partials (deterministic).
+// Fixed-order second pass over the per-workgroup partials (deterministic): each lane combines
+// a strided share, then the workgroup reduction (wavefront reductions, then the four wave
+// results in order).
 __global__ __launch_bounds__(256) void k_reduce_obs(const double* __restrict__ partials, int n,
                                                     double* __restrict__ out)
 {
@@ -15,32 +17,9 @@ __global__ __launch_bounds__(256) void k_reduce_obs(const double* __restrict__ p
     double acc[kObsFields] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int b = t; b < n; b += 256) {
 #pragma unroll
-        for (int a = 0; a < kObsFields; ++a) {
-            const double v = partials[(int64_t)b * kObsFields + a];
-            if (a == 6 || a == 7)
-                acc[a] = (v > acc[a] || v != v) ? v : acc[a];
-            else
-                acc[a] += v;
-        }
+        for (int a = 0; a < kObsFields; ++a) acc[a] = obs_combine(a, acc[a], partials[(int64_t)b * kObsFields + a]);
     }
-#pragma unroll
-    for (int a = 0; a < kObsFields; ++a) red[a][t] = acc[a];
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (t < h) {
-#pragma unroll
-            for (int a = 0; a < kObsFields; ++a) {
-                if (a == 6 || a == 7) {
-                    const double o = red[a][t + h];
-                    red[a][t] = (o > red[a][t] || o != o) ? o : red[a][t];
-                } else {
-                    red[a][t] += red[a][t + h];
-                }
-            }
-        }
-        __syncthreads();
-    }
-    if (t < kObsFields) out[t] = red[t][0];
+    block_reduce_obs<256>(acc, red, out);
 }
 
 // Initial populations: with u == null f_{i,k} = w_i rho_k, else (rho_k/rho) f_eq_i(rho, u);

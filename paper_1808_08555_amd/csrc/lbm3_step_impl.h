@@ -1538,31 +1538,40 @@ __device__ __forceinline__ void pair27_step_b(float* __restrict__ fout, const KP
     }
 }
 
-// Workgroup reduction of the observables partials in `red` (LDS, kObsFields x NT doubles);
-// the caller has synchronised the workgroup before `red` is reused.
+// Combination of two partials of observable field a: sums for the masses, momenta and kinetic
+// energy, the maximum for max|u| and the nonfinite flag (a NaN wins).
+__device__ __forceinline__ double obs_combine(int a, double x, double y)
+{
+    if (a == 6 || a == 7) return (y > x || y != y) ? y : x;
+    return x + y;
+}
+
+// Wavefront reduction of every observables field across the 64 lanes of a wave.
+__device__ __forceinline__ void wave_reduce_obs(double (&acc)[kObsFields])
+{
+#pragma unroll
+    for (int a = 0; a < kObsFields; ++a) acc[a] = (a == 6 || a == 7) ? wave_max(acc[a]) : wave_sum(acc[a]);
+}
+
+// Workgroup reduction of the observables partials: a wavefront reduction per wave, then the
+// first lanes combine the NT/64 wave results (from `red`, LDS of at least kObsFields x NT/64
+// doubles) in wave order into out[0 .. kObsFields).  The caller has synchronised the workgroup
+// before `red` is reused.
 template <int NT>
-__device__ void block_reduce_obs(double (&acc)[kObsFields], double (*red)[NT],
-                                 double* __restrict__ partials)
+__device__ void block_reduce_obs(double (&acc)[kObsFields], double (*red)[NT], double* __restrict__ out)
 {
     const int t = threadIdx.x;
+    wave_reduce_obs(acc);
+    if ((t & 63) == 0) {
 #pragma unroll
-    for (int a = 0; a < kObsFields; ++a) red[a][t] = acc[a];
-    __syncthreads();
-    for (int h = NT / 2; h > 0; h >>= 1) {
-        if (t < h) {
-#pragma unroll
-            for (int a = 0; a < kObsFields; ++a) {
-                if (a == 6 || a == 7) {
-                    const double o = red[a][t + h];
-                    red[a][t] = (o > red[a][t] || o != o) ? o : red[a][t];
-                } else {
-                    red[a][t] += red[a][t + h];
-                }
-            }
-        }
-        __syncthreads();
+        for (int a = 0; a < kObsFields; ++a) red[a][t >> 6] = acc[a];
     }
-    if (t < kObsFields) partials[(int64_t)blockIdx.x * kObsFields + t] = red[t][0];
+    __syncthreads();
+    if (t < kObsFields) {
+        double v = red[t][0];
+        for (int w = 1; w < NT / 64; ++w) v = obs_combine(t, v, red[t][w]);
+        out[t] = v;
+    }
 }
 
 template <typename C, int NT, Fmt IN>
@@ -1614,7 +1623,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                   tl.cols, cring, tring, ExchangeLds<C, NT, IN>::get(), acc, rho_out, salt);
     if constexpr (OBS) {
         __syncthreads();  // the rings are free once every lane has left the march
-        block_reduce_obs<NT>(acc, reinterpret_cast<double (*)[NT]>(&rings[0][0][0][0]), partials);
+        block_reduce_obs<NT>(acc, reinterpret_cast<double (*)[NT]>(&rings[0][0][0][0]),
+                             partials + (int64_t)blockIdx.x * kObsFields);
     }
 }
 

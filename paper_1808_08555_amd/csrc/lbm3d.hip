@@ -284,17 +284,16 @@ __global__ __launch_bounds__(256) void k3_collide(const double* __restrict__ C6,
         }
     }
     if constexpr (OBS) {
-        for (int q = 0; q < 8; ++q) red[q][t] = acc[q];
+        // wavefront reductions, then the four wave results in order
+        for (int q = 0; q < 7; ++q) acc[q] = wave_sum(acc[q]);
+        acc[7] = wave_max(acc[7]);
+        if ((t & 63) == 0)
+            for (int q = 0; q < 8; ++q) red[q][t >> 6] = acc[q];
         __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if (t < h) {
-                for (int q = 0; q < 7; ++q) red[q][t] += red[q][t + h];
-                red[7][t] = fmax(red[7][t], red[7][t + h]);
-            }
-            __syncthreads();
-        }
         if (t < 8) {
-            partials[(int64_t)blockIdx.x * 8 + t] = red[t][0];
+            double v = red[t][0];
+            for (int w = 1; w < 4; ++w) v = t < 7 ? v + red[t][w] : fmax(v, red[t][w]);
+            partials[(int64_t)blockIdx.x * 8 + t] = v;
         }
     }
 }

@@ -150,3 +150,86 @@ def mixed_nodes(rho: np.ndarray, k: int, l: int, level: float = 0.2) -> int:
     the length of the k-l interface (about its length times its width)."""
     c = rho / rho.sum(0)
     return int((np.minimum(c[k], c[l]) > level).sum())
+
+
+def circle_intersections(c1, c2):
+    """The two intersection points of circles (xc, yc, R) c1 and c2 (empty if they miss)."""
+    (x1, y1, r1), (x2, y2, r2) = c1, c2
+    d = math.hypot(x2 - x1, y2 - y1)
+    if d == 0 or d > r1 + r2 or d < abs(r1 - r2):
+        return []
+    a = (r1 * r1 - r2 * r2 + d * d) / (2 * d)
+    h = math.sqrt(max(r1 * r1 - a * a, 0.0))
+    xm, ym = x1 + a * (x2 - x1) / d, y1 + a * (y2 - y1) / d
+    return [(xm + h * (y2 - y1) / d, ym - h * (x2 - x1) / d),
+            (xm - h * (y2 - y1) / d, ym + h * (x2 - x1) / d)]
+
+
+def _bilinear(f: np.ndarray, x: float, y: float) -> float:
+    i, j = int(math.floor(x)), int(math.floor(y))
+    s, t = x - i, y - j
+    return float((1 - s) * (1 - t) * f[j, i] + s * (1 - t) * f[j, i + 1]
+                 + (1 - s) * t * f[j + 1, i] + s * t * f[j + 1, i + 1])
+
+
+def junction_phase_angles(rho: np.ndarray, near: tuple = (6.0, 30.0), probe: float = 8.0):
+    """Phase angles at the two triple junctions of a droplet of fluids 0 and 1 in fluid 2
+    (a Janus droplet).  Circles are fitted to the three interfaces (points where two
+    concentrations cross, away from the third fluid); the junctions are the intersections of
+    the 0-1 and 0-2 circles (the 0-2 and 1-2 circles coincide for a perfect Janus droplet,
+    the 0-1 circle meets them at right angles there).  At each junction every interface
+    leaves along its circle's
+    tangent, pointed toward that interface's points at distances `near` from the junction;
+    the three tangents split the full turn into three angles, each assigned to the fluid
+    found `probe` nodes out along its bisector.  Returns [{fluid: angle in radians}, ...]."""
+    c = rho / rho.sum(0)
+    pairs = {"rb": (0, 2), "gb": (1, 2), "rg": (0, 1)}
+    pts = {n: interface_points(c, k, l) for n, (k, l) in pairs.items()}
+    fits = {n: fit_circle(p) for n, p in pts.items()}
+    out = []
+    for J in circle_intersections(fits["rg"], fits["rb"]):
+        dirs = []
+        for n in pairs:
+            xc, yc, _ = fits[n]
+            rx, ry = J[0] - xc, J[1] - yc
+            t = np.array([-ry, rx]) / math.hypot(rx, ry)
+            dist = np.hypot(pts[n][:, 0] - J[0], pts[n][:, 1] - J[1])
+            sel = pts[n][(dist > near[0]) & (dist < near[1])]
+            if len(sel) == 0:
+                raise ValueError(f"no {n} interface points near the junction {J}")
+            if np.dot(sel.mean(0) - np.array(J), t) < 0:
+                t = -t
+            dirs.append(math.atan2(t[1], t[0]))
+        dirs.sort()
+        angles = {}
+        for q in range(3):
+            a0, a1 = dirs[q], dirs[(q + 1) % 3] + (2 * math.pi if q == 2 else 0.0)
+            mid = 0.5 * (a0 + a1)
+            x, y = J[0] + probe * math.cos(mid), J[1] + probe * math.sin(mid)
+            fluid = int(np.argmax([_bilinear(c[k], x, y) for k in range(3)]))
+            angles[fluid] = a1 - a0
+        out.append(angles)
+    return out
+
+
+def pjd_geometry(area_fraction: float, R: float) -> dict:
+    """Perfect Janus droplet (Sec. 4, Eq. pjd): the red and green fluids fill a disk of
+    radius R = R_r = R_g, split by the rg interface, an arc of radius R_b centred d_gb above
+    the disk's centre.  theta_g solves
+      A_r / (A_r + A_g) = [theta - sin cos + tan^2 theta (pi/2 - theta - sin cos)] / pi
+    (bisection on (0, pi/2), where the right side rises from 0 to 1/2), R_b = R tan theta_g and
+    d_gb = R cos theta_g + R_b cos theta_b with R sin theta_g = R_b sin theta_b."""
+    def frac(t):
+        sc = math.sin(t) * math.cos(t)
+        return (t - sc + math.tan(t) ** 2 * (math.pi / 2 - t - sc)) / math.pi
+    lo, hi = 1e-9, math.pi / 2 - 1e-12
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if frac(mid) < area_fraction:
+            lo = mid
+        else:
+            hi = mid
+    tg = 0.5 * (lo + hi)
+    Rb = R * math.tan(tg)
+    tb = math.asin(min(1.0, R * math.sin(tg) / Rb))
+    return {"theta_g": tg, "theta_b": tb, "R_b": Rb, "d_gb": R * math.cos(tg) + Rb * math.cos(tb)}

@@ -215,3 +215,95 @@ def test_reinitialised_instance_in_a_stepped_batch(precision):
         L.close()
         assert np.array_equal(rho, ref), (i, w.name)
     lbm3.lbm3_batch_destroy(b)
+
+
+def test_morphology_batch_in_the_benchmark_plan_matches_plain_bitwise():
+    """The batched form exactly as the benchmark runs it: the 64-instance morphology sweep
+    (sides 128-512, FP32) with the autotuner's plan (the two-step launch where it wins),
+    200 steps (ten replays of the captured graph): every instance's densities equal the
+    same lattice stepped alone, bit for bit."""
+    import torch
+    ws = inputs.morphology_batch()
+    b = _make_batch(ws, "fp32")
+    try:
+        st = torch.cuda.current_stream()
+        with torch.cuda.stream(st):
+            autotune.tune_batch(b, [w.nx for w in ws], "fp32", steps=20)
+        plan = lbm3.lbm3_batch_get_pair_launch(b)
+        print("benchmark plan (steps per launch, threads, rows, workgroups):", plan)
+        for i, w in enumerate(ws):  # tuning stepped the batch: start again from the inputs
+            lbm3.lbm3_batch_init_fields(b, i, w.rho)
+        lbm3.lbm3_batch_step(b, 200)
+        for i, w in enumerate(ws):
+            _, rho = _batch_state(b, i, w)
+            L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, w.rho0, w.beta0, "fp32").init(w.rho).step(200)
+            ref = L.densities()
+            L.close()
+            assert np.array_equal(rho, ref), (i, w.name)
+    finally:
+        lbm3.lbm3_batch_destroy(b)
+
+
+def _classify_contacts(kind, rg, rb, gb, settled):
+    """Checks of one instance's mixed-node counts (nodes where both fluids exceed 0.2) against
+    its Neumann class.  Separate and kissing droplets share no interface (a kissing point
+    contact leaves a few nodes: at most 3 % of the other interfaces), a partial-engulfing
+    (Janus) droplet keeps all three interfaces, each at least 6 % of the longest (the shortest
+    measured: 12.5 %, a Janus droplet whose junction angle in the matrix is 63 degrees).
+    Once `settled`: complete engulfing leaves
+    the engulfed droplet no contact with the matrix (<= 2 % of the engulfing droplet's), the
+    critical engulfing state at most 15 %."""
+    if kind in (morphology.SEPARATE, morphology.KISSING):
+        return rg <= 0.03 * min(rb, gb)
+    if kind == morphology.PARTIAL:
+        return min(rg, rb, gb) >= 0.06 * max(rg, rb, gb)
+    if not settled:
+        return True
+    if kind == morphology.ENGULF_1_BY_0:
+        return gb <= 0.02 * rb and rg > 0
+    if kind == morphology.ENGULF_0_BY_1:
+        return rb <= 0.02 * gb and rg > 0
+    if kind == morphology.CRITICAL_1_BY_0:
+        return gb <= 0.15 * rb and rg > 0
+    if kind == morphology.CRITICAL_0_BY_1:
+        return rb <= 0.15 * gb and rg > 0
+    raise ValueError(kind)
+
+
+def test_morphology_sweep_64_instances():
+    """The whole 8 x 8 sweep of the stability study (Sec. 4.1) as specified: 64 instances
+    (sides 128-512, two tangent disks of radius side/6, sigma_gb = 0.01, ratios 0.25-2.0),
+    FP32, one batch.  The Neumann inequalities give 38 partial-engulfing, 6 + 3
+    complete-engulfing, 6 separate and 11 critical cases (4 kissing, 7 critical engulfing).
+    After the study's 10 000 steps the separate, kissing and partial cases have their class
+    (_classify_contacts); engulfing is still under way in the larger instances (capillary
+    time of a radius-85 droplet ~ 1.5 x 10^4 steps).  After 100 000 steps every instance has
+    its class, the critical engulfing states included."""
+    from analysis import mixed_nodes
+    ws = inputs.morphology_batch()
+    kinds = [morphology.classify(*w.sigma) for w in ws]
+    counts = {}
+    for k in kinds:
+        counts[k] = counts.get(k, 0) + 1
+    assert counts == {morphology.PARTIAL: 38, morphology.ENGULF_1_BY_0: 3, morphology.ENGULF_0_BY_1: 6,
+                      morphology.SEPARATE: 6, morphology.CRITICAL_1_BY_0: 3, morphology.CRITICAL_0_BY_1: 4,
+                      morphology.KISSING: 4}
+    b = _make_batch(ws, "fp32")
+    bad = []
+    try:
+        done = 0
+        for steps, settled in ((10000, False), (100000, True)):
+            lbm3.lbm3_batch_step(b, steps - done)
+            done = steps
+            for i, w in enumerate(ws):
+                obs, rho = _batch_state(b, i, w)
+                assert obs["nonfinite"] == 0 and obs["step"] == steps
+                rg, rb, gb = mixed_nodes(rho, 0, 1), mixed_nodes(rho, 0, 2), mixed_nodes(rho, 1, 2)
+                ok = _classify_contacts(kinds[i], rg, rb, gb, settled)
+                print("step %6d #%2d side %3d r12 %.2f r13 %.2f %-30s rg %5d rb %5d gb %5d %s" %
+                      (steps, i, w.nx, w.meta["r12"], w.meta["r13"], kinds[i], rg, rb, gb, "" if ok else "FAIL"))
+                if not ok:
+                    bad.append((steps, i, kinds[i], rg, rb, gb))
+    finally:
+        lbm3.lbm3_batch_destroy(b)
+    assert not bad, bad

@@ -9,8 +9,8 @@ import numpy as np
 import pytest
 
 import oracle
-from analysis import (compound_laplace, fit_circle, gjd_geometry, interface_points, lens_analytic,
-                      lens_geometry)
+from analysis import (compound_laplace, fit_circle, gjd_geometry, interface_points, junction_phase_angles,
+                      lens_analytic, lens_geometry)
 from paper_1808_08555_amd import inputs, lbm3
 
 pytestmark = pytest.mark.gpu
@@ -147,6 +147,51 @@ def _double_droplet_1024():
 DRIFT_2000 = {"fp32_storage": 1e-6, "fp32": 1.2e-4}
 
 
+# Per-fluid mass drift: the 1e-6 bar for FP32 storage; for FP32 arithmetic the bound of one
+# float ulp (6e-8) of systematic change per step.
+def _drift_bar(precision, steps):
+    return 1e-6 if precision == "fp32_storage" else steps * 6e-8
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_storage"])
+@pytest.mark.parametrize("r12,r13", [(1.0, 1.0), (1.3, 0.8)])
+def test_double_droplet_1024_janus_junction_angles(precision, r12, r13):
+    """The 1024^2 double droplet of the stability study (Sec. 4.1): two tangent disks of radius
+    100 (fluids 0 and 1) in fluid 2 with interface noise, tension ratios
+    sigma_rg / sigma_gb = r12 and sigma_rb / sigma_gb = r13 that form a Neumann triangle, so the
+    pair merges into a Janus droplet.  In FP32 storage and in FP32 arithmetic, in the default
+    launch configuration: per-fluid mass drift within the bars after the study's 50 000 steps
+    and after 200 000; at 200 000 steps the phase angles at both triple junctions lie within
+    3 degrees of the Neumann angles of Eq. (14) (the angle inside fluid m is pi - phi_kl for
+    the other two fluids k, l).  The merged droplet oscillates about its equilibrium for a long
+    time (capillary time sqrt(rho R^3 / sigma) = 10^4 steps, viscous decay R^2 / nu = 6 x 10^4
+    steps at tau = 1): at 50 000 steps the angles are still off by up to 23 degrees, from
+    200 000 on they stay within 0.6 degree (measured)."""
+    w = inputs.double_droplet(1024, 100.0, r12, r13, seed=1808, steps=200000)
+    L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, w.rho0, w.beta0, precision).init(w.rho)
+    try:
+        m0 = L.observables()[0]["mass"]
+        obs50 = L.step(50000).observables()[0]
+        obs, rho, _ = L.step(150000).observables(want_rho=True)
+    finally:
+        L.close()
+    drift50 = float(np.abs(obs50["mass"] / m0 - 1).max())
+    drift = float(np.abs(obs["mass"] / m0 - 1).max())
+    assert obs50["nonfinite"] == 0 and drift50 < _drift_bar(precision, 50000)
+    p = oracle.Params(8, 8, w.sigma)
+    want = {m: math.pi - math.acos(oracle.X(p, *[k for k in range(3) if k != m])) for m in range(3)}
+    got = junction_phase_angles(rho)
+    print(precision, (r12, r13), "drift at 50000 / 200000 steps", drift50, drift, "angles",
+          [{m: round(math.degrees(a), 2) for m, a in sorted(j.items())} for j in got],
+          "Neumann", {m: round(math.degrees(a), 2) for m, a in want.items()})
+    assert obs["nonfinite"] == 0 and drift < _drift_bar(precision, 200000)
+    assert len(got) == 2
+    for j in got:
+        assert sorted(j) == [0, 1, 2]
+        for m in range(3):
+            assert abs(math.degrees(j[m] - want[m])) <= 3.0, (m, j, want)
+
+
 @pytest.mark.parametrize("precision,rtol", [("fp32", 2e-5), ("fp32_storage", 2e-6)])
 def test_double_droplet_1024_reduced_precision(precision, rtol):
     """The 1024^2 double droplet (two tangent disks of radius 100 in fluid 3, interface
@@ -178,10 +223,17 @@ def test_observables_match_oracle():
     p = oracle.Params(w.nx, w.ny, w.sigma, w.tau)
     o = oracle.observables(p, f)
     assert obs["step"] == 300 and obs["nonfinite"] == 0
+    d_ke = abs(obs["kinetic_energy"] / o["kinetic_energy"] - 1)
+    d_um = abs(obs["u_max"] / o["u_max"] - 1)
+    print(f"observables vs oracle: mass {np.abs(obs['mass'] / o['mass'] - 1).max():.1e}, "
+          f"KE {d_ke:.1e}, u_max {d_um:.1e}")
     assert np.abs(obs["mass"] / o["mass"] - 1).max() < 1e-13
     assert np.abs(obs["momentum"] - o["momentum"]).max() < 1e-12
-    assert abs(obs["kinetic_energy"] / o["kinetic_energy"] - 1) < 1e-9
-    assert abs(obs["u_max"] / o["u_max"] - 1) < 1e-9
+    # the observables come from the exported state on both sides, so they differ only by the
+    # order of the reductions (wavefront sums here, compensated node-order sums there) and of
+    # the force's terms
+    assert d_ke < 1e-13  # measured 0 and 4e-16
+    assert d_um < 1e-13
     assert np.abs(rho - oracle.density(f)).max() < 1e-14
 
 
@@ -207,9 +259,17 @@ def test_flat_interface_has_no_x_flow():
     assert abs(obs["momentum"][1]) < 1e-11
 
 
-@pytest.mark.parametrize("s12,s23,tau", [(0.01, 0.01, (1.0, 1.0, 1.0)),
-                                         (0.005, 0.02, (0.8, 0.8, 0.8)),
-                                         (0.02, 0.005, (0.6, 0.8, 1.0))])
+# the nine tension pairs of the compound-droplet study (sigma_rg, sigma_gb in {0.005, 0.01,
+# 0.02}, sigma_rb = sigma_rg + sigma_gb), with equal relaxation times 1.0, 0.8 and 0.6 and one
+# mixed set among them
+COMPOUND_CASES = [(0.01, 0.01, (1.0, 1.0, 1.0)), (0.005, 0.02, (0.8, 0.8, 0.8)),
+                  (0.02, 0.005, (0.6, 0.8, 1.0)), (0.005, 0.005, (1.0, 1.0, 1.0)),
+                  (0.005, 0.01, (0.6, 0.6, 0.6)), (0.01, 0.005, (0.8, 0.8, 0.8)),
+                  (0.01, 0.02, (1.0, 1.0, 1.0)), (0.02, 0.01, (0.6, 0.6, 0.6)),
+                  (0.02, 0.02, (0.8, 0.8, 0.8)), (0.01, 0.01, (0.6, 0.6, 0.6))]
+
+
+@pytest.mark.parametrize("s12,s23,tau", COMPOUND_CASES)
 def test_compound_droplet_laplace_fp64_vs_fp32_storage(s12, s23, tau):
     """256^2 compound droplet (R_r = 30 core of fluid 0, R_g = 60 shell of fluid 1, fluid 2
     outside; sigma_rb = sigma_rg + sigma_gb, exactly critical), 20000 steps in FP64 and in
@@ -236,7 +296,10 @@ def test_compound_droplet_laplace_fp64_vs_fp32_storage(s12, s23, tau):
     assert res["fp32_storage"]["drift"] < 1e-6
     d64, d32 = res["fp64"]["dp_total"], res["fp32_storage"]["dp_total"]
     assert abs(d32 - d64) / d64 <= 0.01
-    assert res["fp64"]["u_max"] < 1e-4
+    # spurious currents scale as sigma / (rho nu) (a capillary number): 1e-4 at the largest
+    # tension 0.02 and nu = 1/6, scaled to the case's largest tension and smallest viscosity
+    nu = (min(tau) - 0.5) / 3.0
+    assert res["fp64"]["u_max"] < 1e-4 * ((s12 + s23) / 0.02) * ((1.0 / 6.0) / nu)
     if "eps_40000" in res["fp64"]:
         assert res["fp64"]["eps_40000"] < 0.013
         assert res["fp32_storage"]["eps_40000"] < 0.013
@@ -338,6 +401,49 @@ def test_general_janus_droplet_table4(row):
     assert abs(dgb / row["d_gb"] - 1) < 0.015
     for measured, neumann in angles.values():
         assert abs(measured - neumann) < 3.0
+
+
+PJD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table5_pjd.json")))
+
+
+@pytest.mark.parametrize("row", PJD["rows"], ids=lambda r: f"f{r['fraction']}")
+def test_perfect_janus_droplet_table5(row):
+    """Sec. 4, Table 5: a perfect Janus droplet (R = 80, sigma_rb = sigma_gb = 0.01,
+    sigma_rg = 1e-8, nu = 0.1, 300^2) laid out at its analytic shape (Eq. pjd).  After 10 000
+    steps (FP64): the outer boundary is one circle (the rb and gb interfaces fitted
+    separately: radius 80 within 0.5 %, centres within 0.5 node), the phase angles at both
+    junctions are the degenerate Neumann angles (matrix 180 degrees, red and green 90, within
+    3 degrees), and the rg arc lies within 6 % (R_b) and 4 % (d_gb) of Table 5.  The rg arc is
+    held by almost no tension (1e-6 of the others), so nothing restores it: it keeps drifting
+    slowly under the junctions' spurious currents (|u| ~ 6e-4), R_b shrinking by about 2 % per
+    10^4 steps at the fraction 0.1 and less at larger fractions (measured)."""
+    from analysis import fit_circle, interface_points, junction_phase_angles, pjd_geometry
+    s = PJD["setup"]
+    g = pjd_geometry(row["fraction"], s["R"])
+    w = inputs.janus_droplet(s["n"], s["R"], s["R"], g["R_b"], 0.0, g["d_gb"],
+                             (s["sigma_rg"], s["sigma_rb"], s["sigma_gb"]), tau=3 * s["nu"] + 0.5,
+                             y0=(s["n"] - 1) / 2.0)
+    L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau).init(w.rho)
+    try:
+        obs, rho, _ = L.step(10000).observables(want_rho=True)
+    finally:
+        L.close()
+    assert obs["nonfinite"] == 0
+    c = rho / rho.sum(0)
+    fr, fg, frg = (fit_circle(interface_points(c, k, l)) for k, l in ((0, 2), (1, 2), (0, 1)))
+    angles = junction_phase_angles(rho)
+    print(row["fraction"], f"outer {fr} {fg} rg {frg}",
+          [{m: round(math.degrees(a), 2) for m, a in sorted(j.items())} for j in angles])
+    for f in (fr, fg):
+        assert abs(f[2] / s["R"] - 1) < 0.005
+    assert math.hypot(fr[0] - fg[0], fr[1] - fg[1]) < 0.5
+    assert len(angles) == 2
+    for j in angles:
+        assert sorted(j) == [0, 1, 2]
+        assert abs(math.degrees(j[2]) - 180.0) <= 3.0
+        assert abs(math.degrees(j[0]) - 90.0) <= 3.0 and abs(math.degrees(j[1]) - 90.0) <= 3.0
+    assert abs(frg[2] / row["R_b"] - 1) < 0.06
+    assert abs((frg[1] - fg[1]) / row["d_gb"] - 1) < 0.04
 
 
 def test_full_size_two_step_launches_equal_single_steps_bitwise():

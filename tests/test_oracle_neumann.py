@@ -72,3 +72,38 @@ def test_table4_layout_pressure_balance(row):
         assert abs(rhs / lhs - 1) < 2e-3
     else:
         assert abs(rhs / lhs - 1) > 0.3
+
+
+PJD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table5_pjd.json")))
+
+
+@pytest.mark.parametrize("row", PJD["rows"], ids=lambda r: f"f{r['fraction']}")
+def test_table5_perfect_janus_geometry(row):
+    """Eq. (pjd) for R = 80 reproduces Table 5's R_b and d_gb (printed to 0.01).  The solution
+    is checked against the geometry it describes, not only the printed numbers: the rg arc
+    meets the droplet's circle at a right angle (R^2 + R_b^2 = d_gb^2, which the zero rg
+    tension requires: the matrix angle at the junction is 180 degrees and the red and green
+    ones 90), and the area of the disk inside the rg circle, counted on a fine grid, is the
+    requested fraction of the disk."""
+    import numpy as np
+    from analysis import pjd_geometry
+    R = PJD["setup"]["R"]
+    g = pjd_geometry(row["fraction"], R)
+    assert abs(g["R_b"] - row["R_b"]) <= 0.01 and abs(g["d_gb"] - row["d_gb"]) <= 0.01
+    assert abs(R * R + g["R_b"] ** 2 - g["d_gb"] ** 2) < 1e-9 * g["d_gb"] ** 2
+    h = R / 1000.0
+    y, x = np.mgrid[-R + h / 2:R:h, -R + h / 2:R:h]
+    disk = x * x + y * y <= R * R
+    cap = disk & (x * x + (y - g["d_gb"]) ** 2 <= g["R_b"] ** 2)
+    assert abs(cap.sum() / disk.sum() - row["fraction"]) < 2e-4
+
+
+def test_perfect_janus_tensions_are_the_degenerate_neumann_limit():
+    """With sigma_rg = 1e-8 and sigma_rb = sigma_gb = 0.01 the oracle's Neumann cosines
+    (Eq. 14) put the matrix angle at the junction at 180 degrees (X_rg within 1e-12 of 1,
+    taken as exactly 1) and the red and green angles at 90 degrees (X_rb = X_gb ~ 5e-7)."""
+    s = PJD["setup"]
+    p = oracle.Params(8, 8, (s["sigma_rg"], s["sigma_rb"], s["sigma_gb"]))
+    assert 1 - oracle.X(p, 0, 1) < 1e-12 and oracle.g(oracle.X(p, 0, 1)) == -1.0
+    for k, l in ((0, 2), (1, 2)):
+        assert abs(math.degrees(math.acos(oracle.X(p, k, l))) - 90.0) < 1e-3
