@@ -343,12 +343,13 @@ def kissing_droplets(n: int, R: float, d: float, sigma, tau: float = 0.8) -> Wor
                     meta={"R": R, "d": d, "y_mid": c})
 
 
-def engulfed_droplet(n: int, Rr: float, Rg: float, sigma, tau: float = 0.8) -> Workload:
-    """A disk of fluid 0 (radius Rr) inside a disk of fluid 1 (radius Rg), internally tangent
-    (centres Rg - Rr apart on the line x = (n - 1) / 2), in fluid 2: the critical engulfing
-    layout of Sec. 4."""
+def engulfed_droplet(n: int, Rr: float, Rg: float, sigma, tau: float = 0.8, d: float | None = None) -> Workload:
+    """A disk of fluid 0 (radius Rr) over a disk of fluid 1 (radius Rg), centres d apart on the
+    line x = (n - 1) / 2 (default Rg - Rr: internally tangent), in fluid 2: the critical
+    engulfing layout of Sec. 4; with d > Rg - Rr fluid 0 pokes out of fluid 1 (near-critical
+    partial engulfing)."""
     c = (n - 1) / 2.0
-    d = Rg - Rr
+    d = Rg - Rr if d is None else d
     x, y = _grid(n, n)
     lab = np.full((n, n), 2, dtype=np.int64)
     lab[(x - c) ** 2 + (y - (c - d / 2)) ** 2 <= Rg * Rg] = 1

@@ -233,3 +233,40 @@ def pjd_geometry(area_fraction: float, R: float) -> dict:
     Rb = R * math.tan(tg)
     tb = math.asin(min(1.0, R * math.sin(tg) / Rb))
     return {"theta_g": tg, "theta_b": tb, "R_b": Rb, "d_gb": R * math.cos(tg) + Rb * math.cos(tb)}
+
+
+def kissing_chord(R: float, sigma_rg: float, sigma_gb: float) -> float:
+    """Length L_rg of the flat interface between two equal droplets of radius R (fluids 0 and
+    1, sigma_rb = sigma_gb) at equilibrium: their centres sit d_rg = R sigma_rg / sigma_gb apart
+    (Sec. 4, Eq. drg) while sigma_gb > sigma_rg / 2, so the shared chord is
+    2 sqrt(R^2 - d_rg^2 / 4); at and below the kissing state it is 0."""
+    if sigma_gb <= sigma_rg / 2:
+        return 0.0
+    d = R * sigma_rg / sigma_gb
+    return 2.0 * math.sqrt(R * R - d * d / 4.0)
+
+
+def engulfed_rb_arc(Rr: float, Rg: float, sigma_rb: float, sigma_gb: float) -> tuple:
+    """Near-critical engulfing (Sec. 4): a droplet of fluid 0 (radius Rr) partly engulfed by
+    one of fluid 1 (radius Rg), sigma_rg = sigma_gb.  Returns (d_rg, L_rb): the distance of the
+    centres, d_rg^2 = Rr^2 + Rg^2 - 2 Rr Rg cos(alpha) with cos(alpha) = sigma_rb / (2 sigma_gb)
+    (d_rg = Rg - Rr at and beyond the critical state sigma_rb = 2 sigma_gb), and the length of
+    fluid 0's arc outside fluid 1, 2 Rr (pi - phi) with phi the angle at fluid 0's centre
+    between its junctions and fluid 1's centre."""
+    if sigma_rb >= 2 * sigma_gb:
+        return Rg - Rr, 0.0
+    ca = sigma_rb / (2 * sigma_gb)
+    d = math.sqrt(Rr * Rr + Rg * Rg - 2 * Rr * Rg * ca)
+    phi = math.acos((Rr * Rr + d * d - Rg * Rg) / (2 * Rr * d))
+    return d, 2 * Rr * (math.pi - phi)
+
+
+def arc_length(points: np.ndarray) -> float:
+    """Length of the circular arc through `points` (an (n, 2) array): the fitted circle's radius
+    times the angular extent of the points about its centre (0 for fewer than 3 points)."""
+    if len(points) < 3:
+        return 0.0
+    xc, yc, R = fit_circle(points)
+    ang = np.sort(np.arctan2(points[:, 1] - yc, points[:, 0] - xc))
+    gaps = np.diff(np.concatenate([ang, ang[:1] + 2 * math.pi]))
+    return R * (2 * math.pi - gaps.max())
