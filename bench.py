@@ -26,10 +26,10 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS & % HBM roofline: plain FP64 vs FP32 batched vs adjoint step"
 HBM_PEAK_GBS = 8000.0
-# Bytes of the state of one node between steps: FP64 and FP32 keep the recoloured state
-# factored (f_dag_i, c_k, V_0, V_1: 16 values), FP32 storage the 27 populations.  A launch
-# reads and writes the state once, whether it advances one step or two.
-STATE_BYTES = {"fp64": 16 * 8, "fp32_storage": 27 * 4, "fp32": 16 * 4}
+# Bytes of the state of one node between steps: every precision keeps the recoloured state
+# factored (f_dag_i, c_k, V_0, V_1: 16 values), in FP64 or FP32.  A launch reads and writes
+# the state once, whether it advances one step or two.
+STATE_BYTES = {"fp64": 16 * 8, "fp32_storage": 16 * 4, "fp32": 16 * 4}
 
 
 def log(msg: str):

@@ -186,7 +186,7 @@ int lbm3_get_tile(const lbm3_t *h, int32_t *threads, int32_t *rows);
  * lattices of 2^18 nodes or more in FP64, 2^20 in FP32 and FP32 storage), 1 = one,
  * 2 = two where possible.  A two-step
  * launch keeps the intermediate state on chip (in every precision; the first
- * step of an FP64 or FP32 state loaded in 27-population form runs alone) and needs
+ * step of a state loaded in 27-population form runs alone) and needs
  * a tile width (lbm3_set_tile's threads) of at most 256; otherwise, and for the
  * odd last step, a one-step launch runs.  Results do not depend on the mode
  * (bitwise).  EINVAL for another mode. */
@@ -202,13 +202,14 @@ int lbm3_get_pair_launch(const lbm3_t *h, int32_t *steps, int32_t *threads, int3
  * bytes, its strides in elements and its number of planes: plane q of node (x, y)
  * is element q*plane_stride + y*row_pitch + x.  After init_fields / set_state
  * the state is the 27 populations after collision and recolouring, before
- * streaming (q = k*9 + i, nplanes = 27).  After
- * lbm3_step with LBM3_FP64 or LBM3_FP32 (LBM3_FP32_STORAGE keeps the 27
- * populations) it is held factored per node, nplanes = 18: f_dag_i after collision
- * (q = i), c_k = rho_k/rho (q = 9 + k) and V_k = sum_{l != k} beta_kl (rho_k
- * rho_l / rho) n_kl (q = 12 + 2k, 13 + 2k), from which Eq. (13) gives every
- * recoloured population as c_k f_dag_i + w_i V_k . e_i.  For measurement tools;
- * the layout is not a stable API. */
+ * streaming (q = k*9 + i, nplanes = 27).  After lbm3_step (any precision) it is
+ * held factored per node, nplanes = 16: f_dag_i after collision (q = i),
+ * c_k = rho_k/rho (q = 9 + k) and V_k = sum_{l != k} beta_kl (rho_k rho_l / rho)
+ * n_kl for k = 0, 1 (q = 12 + 2k, 13 + 2k; V_2 = -(V_0 + V_1) since the three sum
+ * to zero), from which Eq. (13) gives every recoloured population as
+ * c_k f_dag_i + w_i V_k . e_i.  With LBM3_FP32_STORAGE each stored value is the
+ * stochastic rounding of its FP64 value.  For measurement tools; the layout is
+ * not a stable API. */
 int lbm3_state_buffer(const lbm3_t *h, void **dev_ptr, int32_t *elem_bytes, int64_t *plane_stride,
                       int64_t *row_pitch, int32_t *nplanes);
 

@@ -600,7 +600,7 @@ int lbm3_adjoint_record(lbm3_t* h, int64_t nsteps, int32_t ckpt_every)
     hipError_t e = hipMemcpyAsync(h->ckpt[0], h->buf[h->cur], bytes27, hipMemcpyDeviceToDevice, h->stream);
     if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
     for (int64_t c = 1; c <= nseg; ++c) {
-        int rc = step_handle(h, ckpt_every, true);
+        int rc = step_handle(h, ckpt_every);
         if (rc) return rc;
         if (c == nseg) break;
         e = hipMemcpyAsync(h->ckpt[c], h->buf[h->cur], bytesfac, hipMemcpyDeviceToDevice, h->stream);

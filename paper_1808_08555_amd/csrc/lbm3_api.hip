@@ -288,27 +288,22 @@ int upload_plan(lbm3* h)
 }
 
 // Enqueues n fused steps.  A state in the 27-population format (after init_fields or
-// set_state) is converted to the factored format by its first step when `factored`; from
-// the factored format, pairs of steps go through the two-step pass where it exists.
-int step_handle(lbm3* h, int64_t n, bool factored)
+// set_state) is converted to the factored format by its first step; from the factored
+// format, pairs of steps go through the two-step pass where the plan has one.
+int step_handle(lbm3* h, int64_t n)
 {
-    if (h->fmt == Fmt::FAC && !factored && n > 0) {
-        set_error("the 27-population step needs a state in that format (init_fields / set_state)");
-        return LBM3_ESTATE;
-    }
     while (n > 0) {
         hipError_t e;
         int done = 1;
         const bool pt = h->p.forcing == LBM3_FORCING_PERTURBATION;
-        if (h->fmt == steady_fmt(h->prec) && n >= 2 && h->ntiles2 > 0) {
+        if (h->fmt == Fmt::FAC && n >= 2 && h->ntiles2 > 0) {
             e = launch_pair(h->prec, h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst, h->dtiles2, h->ntiles2,
                             h->threads2, h->step, h->stream, pt);
             done = 2;
         } else {
-            const Fmt out = factored ? Fmt::FAC : Fmt::F27;
-            e = launch_tiles(h->prec, h->fmt, out, h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst,
+            e = launch_tiles(h->prec, h->fmt, Fmt::FAC, h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst,
                              h->dtiles, h->ntiles, h->threads, h->step, 0, h->stream, pt);
-            h->fmt = out;
+            h->fmt = Fmt::FAC;
         }
         if (e != hipSuccess) return hip_fail(e, "step launch");
         h->cur ^= 1;
@@ -542,7 +537,7 @@ int lbm3_step(lbm3_t* h, int64_t n)
         set_error("lbm3_step before lbm3_init_fields / lbm3_set_state");
         return LBM3_ESTATE;
     }
-    return step_handle(h, n, steady_fmt(h->prec) == Fmt::FAC);
+    return step_handle(h, n);
 }
 
 int lbm3_observables(lbm3_t* h, lbm3_obs* out, double* rho_out, double* f_out)

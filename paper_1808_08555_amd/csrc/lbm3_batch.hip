@@ -186,11 +186,9 @@ static hipError_t launch_steady(lbm3_batch* b, int c, bool two, int64_t step)
     if (two)
         e = launch_pair(b->prec, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles2, b->ntiles2, b->threads2, step,
                         b->stream, b->pt, b->dstep);
-    else {
-        const Fmt sf = steady_fmt(b->prec);
-        e = launch_tiles(b->prec, sf, sf, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles, b->ntiles, b->threads,
-                         step, 0, b->stream, b->pt, b->dstep);
-    }
+    else
+        e = launch_tiles(b->prec, Fmt::FAC, Fmt::FAC, b->buf[c], b->buf[c ^ 1], b->dinst, b->dtiles, b->ntiles,
+                         b->threads, step, 0, b->stream, b->pt, b->dstep);
     if (e == hipSuccess && b->dstep) e = launch_advance_step(b->dstep, two ? 2 : 1, b->stream);
     return e;
 }
@@ -418,8 +416,7 @@ int lbm3_batch_step(lbm3_batch_t* b, int64_t n)
             set_error("instance %d has not been initialised", i);
             return LBM3_ESTATE;
         }
-    const Fmt sf = steady_fmt(b->prec);
-    if (n > 0 && sf == Fmt::FAC) {
+    if (n > 0) {
         // first step of freshly initialised instances: 27-population -> factored format
         int n27 = 0;
         for (Fmt f : b->fmt) n27 += f == Fmt::F27;
@@ -438,6 +435,8 @@ int lbm3_batch_step(lbm3_batch_t* b, int64_t n)
                 e = launch_tiles(b->prec, Fmt::F27, Fmt::FAC, b->buf[b->cur], b->buf[b->cur ^ 1],
                                  b->dinst, b->dtiles, b->ntiles, b->threads, b->step,
                                  n27 < b->count ? 1 : 0, b->stream, b->pt);
+            // these launches took their salt from b->step; keep the device counter in step
+            if (e == hipSuccess && b->dstep) e = launch_advance_step(b->dstep, 1, b->stream);
             if (e != hipSuccess) return hip_fail(e, "batch step launch");
             for (auto& f : b->fmt) f = Fmt::FAC;
             b->cur ^= 1;

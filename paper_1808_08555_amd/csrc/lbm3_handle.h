@@ -55,5 +55,5 @@ int upload_plan(lbm3* h);
 void adjoint_release(lbm3* h);
 void adjoint_destroy(lbm3* h);  // adjoint_release plus the adjoint stream and event
 // Enqueues n steps; factored = false keeps the 27-population format (the adjoint's tape).
-int step_handle(lbm3* h, int64_t n, bool factored);
+int step_handle(lbm3* h, int64_t n);
 }  // namespace tcg

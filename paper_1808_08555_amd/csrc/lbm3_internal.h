@@ -74,13 +74,8 @@ enum class Prec { F64, F32S, F32 };
 enum class Fmt : int32_t { F27 = 0, FAC = 1 };
 constexpr int kFacPlanes = 16;
 
-// Format the step keeps between steps.  With FP32 storage and FP64 arithmetic the step is
-// bound by its arithmetic rather than by memory, and there the 27-population pull measured
-// faster than rebuilding the populations from the factored state.
-inline Fmt steady_fmt(Prec p) { return p == Prec::F32S ? Fmt::F27 : Fmt::FAC; }
-
 // Launchers (lbm3_step.hip).  All asynchronous on `stream`.  One fused step from a state in
-// format `in` to one in format `out` (F27 -> F27, F27 -> FAC or FAC -> FAC); with
+// format `in` to one in format `out` (F27 -> FAC or FAC -> FAC); with
 // filter != 0 a workgroup whose instance is not in format `in` does nothing.  pt selects the
 // perturbation operator of Eqs. (4)-(5) in place of the force and Guo's term.  With FP32
 // storage the stochastic rounding is salted by the step number: `step`, or, when step_dev
@@ -153,22 +148,21 @@ LBM3_TILES_DECL(tiles_f32)
 hipError_t tiles_f64_tape(Fmt in, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                           int ntiles, int threads, double* tape, hipStream_t stream);
 constexpr int kTapeFields = 20;
-// Two FP64 / FP32 steps per launch (factored state in and out) over a plan with
-// cols <= threads - 12 (threads 64, 128 or 256); bitwise the same as two single steps.  pt
-// as for launch_tiles.
+// Two steps per launch (factored state in and out) over a plan with cols <= threads - 12
+// (threads 64, 128 or 256); bitwise the same as two single steps.  pt as for launch_tiles.
+// FP32 storage takes the stochastic-rounding salts of the two steps, or their step number
+// from step_dev as launch_tiles does.
 hipError_t tiles_f64_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                           int ntiles, int threads, bool pt, hipStream_t stream);
 hipError_t tiles_f32_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                           int ntiles, int threads, bool pt, hipStream_t stream);
-// The same for FP32 storage (27-population state in and out), with the stochastic-rounding
-// salts of the two steps.
 hipError_t tiles_f32s_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                            int ntiles, int threads, uint32_t salt_a, uint32_t salt_b,
                            const int64_t* step_dev, bool pt, hipStream_t stream);
 int tiles_f64_pair_occupancy(int threads);
 int tiles_f32_pair_occupancy(int threads);
 int tiles_f32s_pair_occupancy(int threads);
-// Two steps per launch of any precision from `step` (state in the precision's steady format).
+// Two steps per launch of any precision from `step` (factored state).
 hipError_t launch_pair(Prec prec, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                        int ntiles, int threads, int64_t step, hipStream_t stream, bool pt = false,
                        const int64_t* step_dev = nullptr);

@@ -115,12 +115,16 @@ struct NodeBits {
     }
 };
 
+// Whether stores round (FP32 storage of FP64 arithmetic).
+template <typename S, typename C>
+constexpr bool kRounds = sizeof(S) < sizeof(C);
+
 // Store of one value in the storage type S from the compute type C (FP32 storage of FP64
 // arithmetic: stochastic rounding with the node's next random bits).
 template <typename S, typename C>
 __device__ __forceinline__ S to_storage(C v, NodeBits& bits)
 {
-    if constexpr (sizeof(S) == 4 && sizeof(C) == 8)
+    if constexpr (kRounds<S, C>)
         return round_stochastic(v, bits.next());
     else
         return S(v);
@@ -773,34 +777,19 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
             C fd[9], ck[3], V[6], ux, uy, mxh, myh;
             collide_recolour<C, PT>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
             if constexpr (!OBS) {
+                static_assert(OUT == Fmt::FAC, "steps store the factored format");
                 NodeBits bits(((uint32_t)yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt);
                 const int64_t pl = fresh_stride(plane);
-                if constexpr (OUT == Fmt::F27) {
-                    const int64_t orow = (int64_t)yo * kp.pitch;
+                const int64_t orow = (int64_t)yo * kp.fpitch;
 #pragma unroll
-                    for (int k = 0; k < 3; ++k)
+                for (int i = 0; i < 9; ++i)
+                    st_at(fout + ((int64_t)i * pl + orow), xoff, to_storage<S, C>(fd[i], bits));
 #pragma unroll
-                        for (int i = 0; i < 9; ++i) {
-                            const int q = k * 9 + i;
-                            const C val = recon<C>(ck[k], fd[i], V[2 * k], V[2 * k + 1], i);
-                            st_at(fout + ((int64_t)q * pl + orow), xoff,
-                                  to_storage<S, C>(val, bits));
-                        }
-                } else {
-                    const int64_t orow = (int64_t)yo * kp.fpitch;
+                for (int k = 0; k < 3; ++k)
+                    st_at(fout + ((int64_t)(9 + k) * pl + orow), xoff, to_storage<S, C>(ck[k], bits));
 #pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        st_at(fout + ((int64_t)i * pl + orow), xoff,
-                              to_storage<S, C>(fd[i], bits));
-#pragma unroll
-                    for (int k = 0; k < 3; ++k)
-                        st_at(fout + ((int64_t)(9 + k) * pl + orow), xoff,
-                              to_storage<S, C>(ck[k], bits));
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        st_at(fout + ((int64_t)(12 + q) * pl + orow), xoff,
-                              to_storage<S, C>(V[q], bits));
-                }
+                for (int q = 0; q < 4; ++q)
+                    st_at(fout + ((int64_t)(12 + q) * pl + orow), xoff, to_storage<S, C>(V[q], bits));
             } else {
                 const double rho = double(rB[0]) + double(rB[1]) + double(rB[2]);
                 acc[0] += double(rB[0]);
@@ -871,17 +860,17 @@ struct alignas(16) PairLds {
     C xB[18][NT];    // A's recoloured row: f_dag (0-8), c_k (9-11), V_k (12-17)
 };
 
-template <typename C, int NT, bool PT = false>
-__device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KParams& kp, int x0, int y0,
-                                            int rows, int cols, PairLds<C, NT>& L, int t)
+template <typename S, typename C, int NT, bool PT = false>
+__device__ __forceinline__ void pair_step_a(const S* __restrict__ fin, const KParams& kp, int x0, int y0,
+                                            int rows, int cols, PairLds<C, NT>& L, int t, uint32_t salt)
 {
     const int nx = kp.nx, ny = kp.ny;
     const int64_t plane = kp.plane;
     const int x = wrapi(x0 - 6 + t, nx);
-    const unsigned scol[3] = {(unsigned)wrapi(x + 1, nx) * (unsigned)sizeof(C),
-                              (unsigned)x * (unsigned)sizeof(C),
-                              (unsigned)wrapi(x - 1, nx) * (unsigned)sizeof(C)};
-    const unsigned xoff = (unsigned)x * (unsigned)sizeof(C);
+    const unsigned scol[3] = {(unsigned)wrapi(x + 1, nx) * (unsigned)sizeof(S),
+                              (unsigned)x * (unsigned)sizeof(S),
+                              (unsigned)wrapi(x - 1, nx) * (unsigned)sizeof(S)};
+    const unsigned xoff = (unsigned)x * (unsigned)sizeof(S);
     const bool a0 = t <= cols + 11;
     const bool a1 = (t >= 1) && (t <= cols + 10);
     const bool a2 = (t >= 2) && (t <= cols + 9);
@@ -894,28 +883,33 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
     // to the neighbouring lanes in the next phase 1).  Each part goes into its registers right
     // after their previous contents were used, so no copy of a prefetched row is kept (the
     // registers freed hold the 27 exchange fields pull_row reads once).
+    // (the prefetched values stay in the storage type until used)
     constexpr int NC = kFacPlanes - 9;
-    auto load_fd = [&](int s, C (&v)[9]) {
+    auto load_fd = [&](int s, S (&v)[9]) {
         const int64_t rowo = (int64_t)s * kp.fpitch;
 #pragma unroll
         for (int i = 0; i < 9; ++i) v[i] = ld_at(fin + ((int64_t)i * plane + rowo), scol[EX[i] + 1]);
     };
-    auto load_cv = [&](int s, C (&v)[NC]) {
+    auto load_cv = [&](int s, S (&v)[NC]) {
         const int64_t rowo = (int64_t)s * kp.fpitch;
 #pragma unroll
         for (int q = 0; q < NC; ++q) v[q] = ld_at(fin + ((int64_t)(9 + q) * plane + rowo), xoff);
     };
-    auto publish = [&](const C (&v)[NC], int slot) {
+    auto publish = [&](const S (&v)[NC], int slot) {
         if (a0) {
 #pragma unroll
-            for (int q = 0; q < 7; ++q) L.xA[slot][q][t] = v[q];
-            L.xA[slot][7][t] = fac_v2<C>(v[3], v[5]);
-            L.xA[slot][8][t] = fac_v2<C>(v[4], v[6]);
+            for (int q = 0; q < 7; ++q) L.xA[slot][q][t] = C(v[q]);
+            L.xA[slot][7][t] = fac_v2<C>(C(v[3]), C(v[5]));
+            L.xA[slot][8][t] = fac_v2<C>(C(v[4]), C(v[6]));
         }
     };
-    C fA[9], fB[9], rA[3], rB[3], nB[6], d0r[3], d0f[6], d1r[3], d1f[3], vf[9], vc[NC];
+    C fA[9], fB[9], rA[3], rB[3], nB[6], d0r[3], d0f[6], d1r[3], d1f[3];
+    S vf[9], vc[NC];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fA[i] = fB[i] = vf[i] = C(0);
+    for (int i = 0; i < 9; ++i) {
+        fA[i] = fB[i] = C(0);
+        vf[i] = S(0);
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         rA[k] = rB[k] = C(1);
@@ -924,7 +918,7 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
 #pragma unroll
     for (int q = 0; q < 6; ++q) nB[q] = d0f[q] = C(0);
 #pragma unroll
-    for (int q = 0; q < NC; ++q) vc[q] = C(1);
+    for (int q = 0; q < NC; ++q) vc[q] = S(1);
     RowCursor src(y0 - 6, ny);
     {
         const int r = src.next();
@@ -940,7 +934,7 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
         if (a0) load_cv(r, vc);
         __syncthreads();
         C r_[3], f_[9];
-        if (a1) pull_row<C, NT>([&](int i) { return vf[i]; }, L.xA[p], t, d0r, d0f, d1r, d1f, r_, f_);
+        if (a1) pull_row<C, NT>([&](int i) { return C(vf[i]); }, L.xA[p], t, d0r, d0f, d1r, d1f, r_, f_);
         if (a0) load_fd(r, vf);
     }
     publish(vc, 0);
@@ -958,7 +952,7 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
             const int r = src.next();
             const bool more = a0 && j + 1 < JA;
             if (more) load_cv(r, vc);
-            if (a1) pull_row<C, NT>([&](int i) { return vf[i]; }, L.xA[j & 1], t, d0r, d0f, d1r, d1f, r0, f0);
+            if (a1) pull_row<C, NT>([&](int i) { return C(vf[i]); }, L.xA[j & 1], t, d0r, d0f, d1r, d1f, r0, f0);
             if (more) load_fd(r, vf);
             const C irho = recip((r0[0] + r0[1]) + r0[2]);
 #pragma unroll
@@ -980,12 +974,32 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
             C Tn[3];
             force_or_stress<C, NT, PT>(L.tA, s0, s1, s2, t, Fx, Fy, Tn);
             collide_recolour<C, PT>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
+            if constexpr (kRounds<S, C>) {
+                // the row as a single step would store it: each value rounded with the key of
+                // its node (row y0 - 7 + j, wrapped) and in store order, V_2 formed from the
+                // rounded V_0 and V_1 as the next step's pull forms it
+                const uint32_t yo = (uint32_t)wrapi(y0 - 7 + j, ny);
+                NodeBits bits((yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) L.xB[i][t] = fd[i];
+                for (int i = 0; i < 9; ++i) L.xB[i][t] = C(to_storage<S, C>(fd[i], bits));
 #pragma unroll
-            for (int k = 0; k < 3; ++k) L.xB[9 + k][t] = ck[k];
+                for (int k = 0; k < 3; ++k) L.xB[9 + k][t] = C(to_storage<S, C>(ck[k], bits));
+                C v4[4];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) L.xB[12 + q][t] = V[q];
+                for (int q = 0; q < 4; ++q) {
+                    v4[q] = C(to_storage<S, C>(V[q], bits));
+                    L.xB[12 + q][t] = v4[q];
+                }
+                L.xB[16][t] = fac_v2<C>(v4[0], v4[2]);
+                L.xB[17][t] = fac_v2<C>(v4[1], v4[3]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) L.xB[i][t] = fd[i];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) L.xB[9 + k][t] = ck[k];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) L.xB[12 + q][t] = V[q];
+            }
         }
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -1007,14 +1021,14 @@ __device__ __forceinline__ void pair_step_a(const C* __restrict__ fin, const KPa
 // completes the densities of row y0 - 2 + m (partial sums only for m = -2, -1), its stage 2
 // forms the stress of row y0 - 3 + m and its stage 3 outputs row y0 - 4 + m.  Row m runs in
 // iteration m + 7, one iteration after A recoloured its source row into xB.
-template <typename C, int NT, bool PT = false>
-__device__ __forceinline__ void pair_step_b(C* __restrict__ fout, const KParams& kp, int x0, int y0,
-                                            int rows, int cols, PairLds<C, NT>& L, int t)
+template <typename S, typename C, int NT, bool PT = false>
+__device__ __forceinline__ void pair_step_b(S* __restrict__ fout, const KParams& kp, int x0, int y0,
+                                            int rows, int cols, PairLds<C, NT>& L, int t, uint32_t salt)
 {
     const int nx = kp.nx;
     const int64_t plane = kp.plane;
     const int x = wrapi(x0 - 6 + t, nx);
-    const unsigned xoff = (unsigned)x * (unsigned)sizeof(C);
+    const unsigned xoff = (unsigned)x * (unsigned)sizeof(S);
     const bool b1 = (t >= 4) && (t <= cols + 7);
     const bool b2 = (t >= 5) && (t <= cols + 6);
     const bool b3 = (t >= 6) && (t <= cols + 5);
@@ -1077,12 +1091,16 @@ __device__ __forceinline__ void pair_step_b(C* __restrict__ fout, const KParams&
             force_or_stress<C, NT, PT>(L.tB, s0, s1, s2, t, Fx, Fy, Tn);
             collide_recolour<C, PT>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
             const int64_t orow = (int64_t)yo * kp.fpitch;
+            NodeBits bits(((uint32_t)yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st_at(fout + ((int64_t)i * plane + orow), xoff, fd[i]);
+            for (int i = 0; i < 9; ++i)
+                st_at(fout + ((int64_t)i * plane + orow), xoff, to_storage<S, C>(fd[i], bits));
 #pragma unroll
-            for (int k = 0; k < 3; ++k) st_at(fout + ((int64_t)(9 + k) * plane + orow), xoff, ck[k]);
+            for (int k = 0; k < 3; ++k)
+                st_at(fout + ((int64_t)(9 + k) * plane + orow), xoff, to_storage<S, C>(ck[k], bits));
 #pragma unroll
-            for (int q = 0; q < 4; ++q) st_at(fout + ((int64_t)(12 + q) * plane + orow), xoff, V[q]);
+            for (int q = 0; q < 4; ++q)
+                st_at(fout + ((int64_t)(12 + q) * plane + orow), xoff, to_storage<S, C>(V[q], bits));
         }
         if (live && m >= 0) {
 #pragma unroll
@@ -1309,235 +1327,6 @@ __device__ __forceinline__ void march2(const C* __restrict__ fin, C* __restrict_
     }
 }
 
-// The two-step pass for the 27-population format with FP32 storage and FP64 arithmetic,
-// one step per wave group as in pair_step_a/pair_step_b.  Step A pulls its 27 populations
-// from global memory as march() does and rounds its recoloured populations to float with
-// the stochastic rounding and keys a stored step would use; they go to a ring of three LDS
-// rows (by A's output row mod 3) instead of HBM.  Step B pulls the three rows it needs
-// from the ring.  The result equals two single steps bit for bit.  Lane t of either step
-// sits on column x0 - 6 + t (cols <= NT - 12).  A runs march() over rows y0 - 3 ..
-// y0 + rows + 2: iteration j forms the densities of row y0 - 5 + j and stores row
-// y0 - 7 + j into ring slot j mod 3; B, march() over the tile's own rows, forms the
-// densities of row y0 - 9 + j (A's rows of iterations j - 3 .. j - 1) and stores row
-// y0 - 11 + j.  Three phases per iteration as in the factored pass (densities, stress,
-// collision), no pre-roll, rows + 11 iterations for both steps.
-template <int NT>
-struct alignas(16) Pair27Lds {
-    double cA[3][3][NT];
-    double tA[3][3][NT];
-    double cB[3][3][NT];
-    double tB[3][3][NT];
-    float ring[3][27][NT];  // A's rows as stored: population 9k + i, by row mod 3
-};
-
-template <int NT, bool PT = false>
-__device__ __forceinline__ void pair27_step_a(const float* __restrict__ fin, const KParams& kp, int x0, int y0,
-                                              int rows, int cols, Pair27Lds<NT>& L, int t, uint32_t salt)
-{
-    using C = double;
-    const int nx = kp.nx, ny = kp.ny;
-    const int64_t plane = kp.plane;
-    const int x = wrapi(x0 - 6 + t, nx);
-    const unsigned scol[3] = {(unsigned)wrapi(x + 1, nx) * 4u, (unsigned)x * 4u, (unsigned)wrapi(x - 1, nx) * 4u};
-    const bool a1 = (t >= 1) && (t <= cols + 10);
-    const bool a2 = (t >= 2) && (t <= cols + 9);
-    const bool a3 = (t >= 3) && (t <= cols + 8);
-    const StepConsts<C> K(kp);
-    const int JA = rows + 10;
-    const int J = rows + 11;
-
-    // the 27 pulled populations of the middle row r (rows r + 1, r, r - 1 by e_y), as stored
-    auto load = [&](int r, float (&v)[27]) {
-        const int64_t pitch = kp.pitch;
-        const int64_t srow[3] = {(int64_t)(r + 1 == ny ? 0 : r + 1) * pitch, (int64_t)r * pitch,
-                                 (int64_t)(r == 0 ? ny - 1 : r - 1) * pitch};
-        const int64_t pl = fresh_stride(plane);
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-                v[k * 9 + i] = ld_at(fin + ((int64_t)(k * 9 + i) * pl + srow[EY[i] + 1]), scol[EX[i] + 1]);
-    };
-
-    C fA[9], fB[9], rA[3], rB[3], nB[6];
-    float vn[27];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) fA[i] = fB[i] = C(0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) rA[k] = rB[k] = C(1);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) nB[q] = C(0);
-#pragma unroll
-    for (int q = 0; q < 27; ++q) vn[q] = 1.0f;
-    RowCursor src(y0 - 5, ny);  // middle rows in load order: y0 - 5, y0 - 4, ...
-    {
-        const int r = src.next();
-        if (a1) load(r, vn);
-    }
-
-#pragma unroll 1
-    for (int j = 0; j < J; ++j) {
-        const bool live = j < JA;
-        const int s0 = j % 3, s1 = (j + 2) % 3, s2 = (j + 1) % 3;
-        // phase 0: densities of row y0 - 5 + j; prefetch the next row
-        C f0[9], r0[3];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) f0[i] = C(0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) r0[k] = C(1);
-        if (live) {
-            float v[27];
-#pragma unroll
-            for (int q = 0; q < 27; ++q) v[q] = vn[q];
-            const int r = src.next();
-            if (a1 && j + 1 < JA) load(r, vn);
-            densities_f27<C>([&](int q) { return C(v[q]); }, r0, f0);
-            const C irho = recip((r0[0] + r0[1]) + r0[2]);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) L.cA[s0][k][t] = r0[k] * irho;
-        }
-        __syncthreads();
-        // phase 1: stress of row y0 - 6 + j
-        C nA[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
-        if (live && j >= 2 && a2) {
-            C Txx, Txy, Tyy;
-            stress_at_lane<C, NT>(L.cA, s0, s1, s2, t, rA, K, nA, Txx, Txy, Tyy);
-            L.tA[s1][0][t] = Txx;
-            L.tA[s1][1][t] = Txy;
-            L.tA[s1][2][t] = Tyy;
-        }
-        __syncthreads();
-        // phase 2: recolour row y0 - 7 + j and round it as it would be stored
-        if (live && j >= 4 && a3) {
-            const uint32_t yo = (uint32_t)wrapi(y0 - 7 + j, ny);
-            NodeBits bits((yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt);
-            C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
-            C Tn[3];
-            force_or_stress<C, NT, PT>(L.tA, s0, s1, s2, t, Fx, Fy, Tn);
-            collide_recolour<C, PT>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-#pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    const int q = k * 9 + i;
-                    L.ring[s0][q][t] =
-                        to_storage<float, C>(recon<C>(ck[k], fd[i], V[2 * k], V[2 * k + 1], i), bits);
-                }
-        }
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            fB[i] = fA[i];
-            fA[i] = f0[i];
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            rB[k] = rA[k];
-            rA[k] = r0[k];
-        }
-#pragma unroll
-        for (int q = 0; q < 6; ++q) nB[q] = nA[q];
-        __syncthreads();
-    }
-}
-
-template <int NT, bool PT = false>
-__device__ __forceinline__ void pair27_step_b(float* __restrict__ fout, const KParams& kp, int x0, int y0, int rows,
-                                              int cols, Pair27Lds<NT>& L, int t, uint32_t salt)
-{
-    using C = double;
-    const int nx = kp.nx;
-    const int64_t plane = kp.plane;
-    const int x = wrapi(x0 - 6 + t, nx);
-    const unsigned xoff = (unsigned)x * 4u;
-    const bool b1 = (t >= 4) && (t <= cols + 7);
-    const bool b2 = (t >= 5) && (t <= cols + 6);
-    const bool b3 = (t >= 6) && (t <= cols + 5);
-    const StepConsts<C> K(kp);
-    const int J = rows + 11;
-
-    C fA[9], fB[9], rA[3], rB[3], nB[6];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) fA[i] = fB[i] = C(0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) rA[k] = rB[k] = C(1);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) nB[q] = C(0);
-
-#pragma unroll 1
-    for (int j = 0; j < J; ++j) {
-        // march() iteration jb over the tile's rows: densities of row y0 - 2 + jb
-        const int jb = j - 7;
-        const bool live = jb >= 0 && jb < rows + 4;
-        const int s0 = (jb + 9) % 3, s1 = (jb + 11) % 3, s2 = (jb + 10) % 3;
-        // ring slots of A's rows y - 1, y, y + 1 (A iterations j - 3, j - 2, j - 1), by e_y
-        const int rs[3] = {(j + 2) % 3, (j + 1) % 3, j % 3};  // e_y = -1, 0, +1
-        // phase 0: densities from the ring
-        C f0[9], r0[3];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) f0[i] = C(0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) r0[k] = C(1);
-        if (live && b1) {
-            densities_f27<C>(
-                [&](int q) {
-                    const int i = q % 9;
-                    return C(L.ring[rs[EY[i] + 1]][q][t - EX[i]]);
-                },
-                r0, f0);
-        }
-        if (live) {
-            const C irho = recip((r0[0] + r0[1]) + r0[2]);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) L.cB[s0][k][t] = r0[k] * irho;
-        }
-        __syncthreads();
-        // phase 1: stress of row y0 - 3 + jb
-        C nA[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
-        if (live && jb >= 2 && b2) {
-            C Txx, Txy, Tyy;
-            stress_at_lane<C, NT>(L.cB, s0, s1, s2, t, rA, K, nA, Txx, Txy, Tyy);
-            L.tB[s1][0][t] = Txx;
-            L.tB[s1][1][t] = Txy;
-            L.tB[s1][2][t] = Tyy;
-        }
-        __syncthreads();
-        // phase 2: collide, recolour and store row y0 - 4 + jb
-        if (live && jb >= 4 && b3) {
-            const int yo = y0 - 4 + jb;
-            NodeBits bits(((uint32_t)yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt);
-            C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
-            C Tn[3];
-            force_or_stress<C, NT, PT>(L.tB, s0, s1, s2, t, Fx, Fy, Tn);
-            collide_recolour<C, PT>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
-            const int64_t orow = (int64_t)yo * kp.pitch;
-            const int64_t pl = fresh_stride(plane);
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-#pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    const int q = k * 9 + i;
-                    st_at(fout + ((int64_t)q * pl + orow), xoff,
-                          to_storage<float, C>(recon<C>(ck[k], fd[i], V[2 * k], V[2 * k + 1], i), bits));
-                }
-        }
-        if (live) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                fB[i] = fA[i];
-                fA[i] = f0[i];
-            }
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                rB[k] = rA[k];
-                rA[k] = r0[k];
-            }
-#pragma unroll
-            for (int q = 0; q < 6; ++q) nB[q] = nA[q];
-        }
-        __syncthreads();
-    }
-}
-
 // Combination of two partials of observable field a: sums for the masses, momenta and kinetic
 // energy, the maximum for max|u| and the nonfinite flag (a NaN wins).
 __device__ __forceinline__ double obs_combine(int a, double x, double y)
@@ -1614,7 +1403,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const KParams kp = inst[tl.inst].kp;
     const int64_t off = inst[tl.inst].offset;
     double acc[kObsFields] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if constexpr (sizeof(S) == 4 && sizeof(C) == 8 && !OBS) {
+    if constexpr (kRounds<S, C> && !OBS) {
         if (step_dev) salt = step_salt(*step_dev);
     }
     // the key of a stored value depends on (step, node, value) only, so an instance of a batch
@@ -1638,36 +1427,23 @@ hipError_t do_tiles(const void* fin, void* fout, const Instance* inst, const Til
     return hipGetLastError();
 }
 
-// FP32 storage with FP64 arithmetic keeps the 27-population format (see steady_fmt), so its
-// factored variants are not built.
-template <typename S, typename C>
-constexpr bool kHasFac = !(sizeof(S) == 4 && sizeof(C) == 8);
-
 template <typename S, typename C, int NT, bool PT>
 hipError_t tiles_nt_pt(Fmt in, Fmt out, bool obs, const void* fin, void* fout, const Instance* inst,
                        const Tile* tiles, int ntiles, uint32_t salt, const int64_t* step_dev, int filter,
                        double* partials, double* rho_out, hipStream_t st)
 {
-    if (in == Fmt::F27 && (obs || out == Fmt::F27)) {
-        if (obs)
-            return do_tiles<S, C, NT, true, Fmt::F27, Fmt::F27, false, PT>(fin, nullptr, inst, tiles, ntiles,
-                                                                          0u, filter, partials, rho_out, st);
-        return do_tiles<S, C, NT, false, Fmt::F27, Fmt::F27, false, PT>(fin, fout, inst, tiles, ntiles, salt,
+    if (obs && in == Fmt::F27)
+        return do_tiles<S, C, NT, true, Fmt::F27, Fmt::F27, false, PT>(fin, nullptr, inst, tiles, ntiles, 0u,
+                                                                      filter, partials, rho_out, st);
+    if (obs && in == Fmt::FAC)
+        return do_tiles<S, C, NT, true, Fmt::FAC, Fmt::FAC, false, PT>(fin, nullptr, inst, tiles, ntiles, 0u,
+                                                                      filter, partials, rho_out, st);
+    if (in == Fmt::FAC && out == Fmt::FAC)
+        return do_tiles<S, C, NT, false, Fmt::FAC, Fmt::FAC, false, PT>(fin, fout, inst, tiles, ntiles, salt,
                                                                        filter, nullptr, nullptr, st, step_dev);
-    }
-    if constexpr (kHasFac<S, C>) {
-        if (obs && in == Fmt::FAC)
-            return do_tiles<S, C, NT, true, Fmt::FAC, Fmt::FAC, false, PT>(fin, nullptr, inst, tiles, ntiles,
-                                                                          0u, filter, partials, rho_out, st);
-        if (in == Fmt::FAC && out == Fmt::FAC)
-            return do_tiles<S, C, NT, false, Fmt::FAC, Fmt::FAC, false, PT>(fin, fout, inst, tiles, ntiles,
-                                                                           salt, filter, nullptr, nullptr, st,
-                                                                           step_dev);
-        if (in == Fmt::F27 && out == Fmt::FAC)
-            return do_tiles<S, C, NT, false, Fmt::F27, Fmt::FAC, false, PT>(fin, fout, inst, tiles, ntiles,
-                                                                           salt, filter, nullptr, nullptr, st,
-                                                                           step_dev);
-    }
+    if (in == Fmt::F27 && out == Fmt::FAC)
+        return do_tiles<S, C, NT, false, Fmt::F27, Fmt::FAC, false, PT>(fin, fout, inst, tiles, ntiles, salt,
+                                                                       filter, nullptr, nullptr, st, step_dev);
     return hipErrorInvalidValue;
 }
 
@@ -1713,21 +1489,31 @@ hipError_t tiles_any(Fmt in, Fmt out, bool obs, bool pt, const void* fin, void* 
 // Two fused steps over a list of tiles; tiles come from a plan with cols <= NT - 12.  The
 // workgroup has 2 NT lanes: waves of lanes 0..NT-1 run step A, the others step B (the
 // choice is uniform per wave).
-template <typename C, int NT, bool PT = false>
+// With FP32 storage, salt_a and salt_b salt the two steps' stochastic rounding, or, when
+// step_dev is given, those of steps *step_dev and *step_dev + 1, read when the launch runs.
+template <typename S, typename C, int NT, bool PT = false>
 __global__ __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles2w(
-    const C* __restrict__ fin, C* __restrict__ fout, const Instance* __restrict__ inst,
-    const Tile* __restrict__ tiles)
+    const S* __restrict__ fin, S* __restrict__ fout, const Instance* __restrict__ inst,
+    const Tile* __restrict__ tiles, uint32_t salt_a, uint32_t salt_b, const int64_t* __restrict__ step_dev)
 {
     static_assert(NT % 64 == 0, "each wave must belong to one step");
     __shared__ PairLds<C, NT> lds;
     const Tile tl = tiles[blockIdx.x];
     const KParams kp = inst[tl.inst].kp;
     const int64_t off = inst[tl.inst].offset;
+    if constexpr (kRounds<S, C>) {
+        if (step_dev) {
+            const int64_t s = *step_dev;
+            salt_a = step_salt(s);
+            salt_b = step_salt(s + 1);
+        }
+    }
     const int lane0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x);
     if (lane0 < NT)
-        pair_step_a<C, NT, PT>(fin + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x);
+        pair_step_a<S, C, NT, PT>(fin + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x, salt_a);
     else
-        pair_step_b<C, NT, PT>(fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x - NT);
+        pair_step_b<S, C, NT, PT>(fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x - NT,
+                                  salt_b);
 }
 
 // Two fused steps over a list of tiles, one thread per column carrying both (march2);
@@ -1748,139 +1534,74 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
                   ringsB[0], ringsB[1], xB);
 }
 
-// The two-step pass: FP64 wave-specialised (k_tiles2w, 2 x threads lanes), FP32 with one
-// thread per column (k_tiles2f, threads lanes); `threads` is the tile width basis NT.  pt:
-// the perturbation operator of Eqs. (4)-(5) in place of the force and Guo's term.
-template <typename C, int NT, bool PT>
+// The two-step pass: FP64 arithmetic (FP64 or FP32 storage) wave-specialised (k_tiles2w,
+// 2 x threads lanes), FP32 with one thread per column (k_tiles2f, threads lanes); `threads`
+// is the tile width basis NT.  pt: the perturbation operator of Eqs. (4)-(5) in place of the
+// force and Guo's term.
+template <typename S, typename C, int NT, bool PT>
 hipError_t pair_launch(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
-                       hipStream_t st)
+                       uint32_t salt_a, uint32_t salt_b, const int64_t* step_dev, hipStream_t st)
 {
     if constexpr (sizeof(C) == 8)
-        hipLaunchKernelGGL((k_tiles2w<C, NT, PT>), dim3(ntiles), dim3(2 * NT), 0, st, (const C*)fin, (C*)fout,
-                           inst, tiles);
+        hipLaunchKernelGGL((k_tiles2w<S, C, NT, PT>), dim3(ntiles), dim3(2 * NT), 0, st, (const S*)fin, (S*)fout,
+                           inst, tiles, salt_a, salt_b, step_dev);
     else
         hipLaunchKernelGGL((k_tiles2f<C, NT, PT>), dim3(ntiles), dim3(NT), 0, st, (const C*)fin, (C*)fout, inst,
                            tiles);
     return hipGetLastError();
 }
 
-template <typename C, int NT>
+template <typename S, typename C, int NT>
 hipError_t pair_launch_pt(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
-                          bool pt, hipStream_t st)
+                          uint32_t salt_a, uint32_t salt_b, const int64_t* step_dev, bool pt, hipStream_t st)
 {
-    return pt ? pair_launch<C, NT, true>(fin, fout, inst, tiles, ntiles, st)
-              : pair_launch<C, NT, false>(fin, fout, inst, tiles, ntiles, st);
+    return pt ? pair_launch<S, C, NT, true>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, step_dev, st)
+              : pair_launch<S, C, NT, false>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, step_dev, st);
 }
 
-template <typename C>
-hipError_t tiles_pair_any(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
-                          int ntiles, int threads, bool pt, hipStream_t st)
+template <typename S, typename C>
+hipError_t tiles_pair_any(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                          int threads, uint32_t salt_a, uint32_t salt_b, const int64_t* step_dev, bool pt,
+                          hipStream_t st)
 {
     switch (threads) {
-        case 64: return pair_launch_pt<C, 64>(fin, fout, inst, tiles, ntiles, pt, st);
-        case 128: return pair_launch_pt<C, 128>(fin, fout, inst, tiles, ntiles, pt, st);
-        case 256: return pair_launch_pt<C, 256>(fin, fout, inst, tiles, ntiles, pt, st);
+        case 64: return pair_launch_pt<S, C, 64>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, step_dev, pt, st);
+        case 128: return pair_launch_pt<S, C, 128>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, step_dev, pt, st);
+        case 256: return pair_launch_pt<S, C, 256>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, step_dev, pt, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <typename C, int NT>
+template <typename S, typename C, int NT>
 int pair_occupancy_nt()
 {
     int nb = 0;
     hipError_t e;
     if constexpr (sizeof(C) == 8)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2w<C, NT>, 2 * NT, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2w<S, C, NT>, 2 * NT, 0);
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2f<C, NT>, NT, 0);
     return e == hipSuccess ? nb : 0;
 }
 
-template <typename C>
+template <typename S, typename C>
 int pair_occupancy(int threads)
 {
     switch (threads) {
-        case 64: return pair_occupancy_nt<C, 64>();
-        case 128: return pair_occupancy_nt<C, 128>();
-        case 256: return pair_occupancy_nt<C, 256>();
+        case 64: return pair_occupancy_nt<S, C, 64>();
+        case 128: return pair_occupancy_nt<S, C, 128>();
+        case 256: return pair_occupancy_nt<S, C, 256>();
         default: return 0;
     }
 }
 
-// The 27-population two-step pass (FP32 storage), salts of the two steps' stochastic
-// rounding (or, when step_dev is given, those of steps *step_dev and *step_dev + 1, read when
-// the launch runs); a workgroup of 2 NT lanes as in k_tiles2w.
-template <int NT, bool PT = false>
-__global__ __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles2s(
-    const float* __restrict__ fin, float* __restrict__ fout, const Instance* __restrict__ inst,
-    const Tile* __restrict__ tiles, uint32_t salt_a, uint32_t salt_b, const int64_t* __restrict__ step_dev)
-{
-    static_assert(NT % 64 == 0, "each wave must belong to one step");
-    __shared__ Pair27Lds<NT> lds;
-    const Tile tl = tiles[blockIdx.x];
-    const KParams kp = inst[tl.inst].kp;
-    const int64_t off = inst[tl.inst].offset;
-    if (step_dev) {
-        const int64_t s = *step_dev;
-        salt_a = step_salt(s);
-        salt_b = step_salt(s + 1);
-    }
-    const int lane0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x);
-    if (lane0 < NT)
-        pair27_step_a<NT, PT>(fin + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x, salt_a);
-    else
-        pair27_step_b<NT, PT>(fout + off, kp, tl.x0, tl.y0, tl.rows, tl.cols, lds, (int)threadIdx.x - NT, salt_b);
-}
-
-template <int NT, bool PT>
-hipError_t pair27_launch(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
-                         uint32_t salt_a, uint32_t salt_b, const int64_t* step_dev, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_tiles2s<NT, PT>), dim3(ntiles), dim3(2 * NT), 0, st, (const float*)fin, (float*)fout, inst,
-                       tiles, salt_a, salt_b, step_dev);
-    return hipGetLastError();
-}
-
-template <bool PT>
-hipError_t tiles_pair27_pt(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
-                           int threads, uint32_t salt_a, uint32_t salt_b, const int64_t* step_dev, hipStream_t st)
-{
-    switch (threads) {
-        case 64: return pair27_launch<64, PT>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, step_dev, st);
-        case 128: return pair27_launch<128, PT>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, step_dev, st);
-        case 256: return pair27_launch<256, PT>(fin, fout, inst, tiles, ntiles, salt_a, salt_b, step_dev, st);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-inline hipError_t tiles_pair27_any(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
-                                   int threads, uint32_t salt_a, uint32_t salt_b, const int64_t* step_dev, bool pt,
-                                   hipStream_t st)
-{
-    return pt ? tiles_pair27_pt<true>(fin, fout, inst, tiles, ntiles, threads, salt_a, salt_b, step_dev, st)
-              : tiles_pair27_pt<false>(fin, fout, inst, tiles, ntiles, threads, salt_a, salt_b, step_dev, st);
-}
-
-inline int pair27_occupancy(int threads)
-{
-    int nb = 0;
-    hipError_t e = hipErrorInvalidValue;
-    switch (threads) {
-        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2s<64>, 128, 0); break;
-        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2s<128>, 256, 0); break;
-        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles2s<256>, 512, 0); break;
-        default: break;
-    }
-    return e == hipSuccess ? nb : 0;
-}
-
-// Resident workgroups per CU of the steady-state step (the format of steady_fmt).
+// Resident workgroups per CU of the steady-state step (factored in and out).
 template <typename S, typename C, int NT>
 int occupancy_nt()
 {
-    constexpr Fmt F = kHasFac<S, C> ? Fmt::FAC : Fmt::F27;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<S, C, NT, false, F, F>, NT, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<S, C, NT, false, Fmt::FAC, Fmt::FAC>, NT, 0) !=
+        hipSuccess)
         return 0;
     return nb;
 }

@@ -16,9 +16,9 @@ int tiles_f32_occupancy(int threads) { return tiles_occupancy<float, float>(thre
 hipError_t tiles_f32_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                           int ntiles, int threads, bool pt, hipStream_t stream)
 {
-    return tiles_pair_any<float>(fin, fout, inst, tiles, ntiles, threads, pt, stream);
+    return tiles_pair_any<float, float>(fin, fout, inst, tiles, ntiles, threads, 0u, 0u, nullptr, pt, stream);
 }
 
-int tiles_f32_pair_occupancy(int threads) { return pair_occupancy<float>(threads); }
+int tiles_f32_pair_occupancy(int threads) { return pair_occupancy<float, float>(threads); }
 
 }  // namespace tcg

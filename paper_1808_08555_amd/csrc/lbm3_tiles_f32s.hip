@@ -17,9 +17,10 @@ hipError_t tiles_f32s_pair(const void* fin, void* fout, const Instance* inst, co
                            int threads, uint32_t salt_a, uint32_t salt_b, const int64_t* step_dev, bool pt,
                            hipStream_t stream)
 {
-    return tiles_pair27_any(fin, fout, inst, tiles, ntiles, threads, salt_a, salt_b, step_dev, pt, stream);
+    return tiles_pair_any<float, double>(fin, fout, inst, tiles, ntiles, threads, salt_a, salt_b, step_dev, pt,
+                                          stream);
 }
 
-int tiles_f32s_pair_occupancy(int threads) { return pair27_occupancy(threads); }
+int tiles_f32s_pair_occupancy(int threads) { return pair_occupancy<float, double>(threads); }
 
 }  // namespace tcg

@@ -28,9 +28,9 @@ hipError_t tiles_f64_tape(Fmt in, const void* fin, void* fout, const Instance* i
 hipError_t tiles_f64_pair(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                           int ntiles, int threads, bool pt, hipStream_t stream)
 {
-    return tiles_pair_any<double>(fin, fout, inst, tiles, ntiles, threads, pt, stream);
+    return tiles_pair_any<double, double>(fin, fout, inst, tiles, ntiles, threads, 0u, 0u, nullptr, pt, stream);
 }
 
-int tiles_f64_pair_occupancy(int threads) { return pair_occupancy<double>(threads); }
+int tiles_f64_pair_occupancy(int threads) { return pair_occupancy<double, double>(threads); }
 
 }  // namespace tcg

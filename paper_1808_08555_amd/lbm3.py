@@ -259,7 +259,7 @@ def lbm3_get_tile(h):
 
 def lbm3_state_buffer(h):
     """(device pointer, element bytes, plane stride, row pitch, planes) of the current state
-    buffer: 27 planes of populations after init / set_state, 18 factored planes after a step."""
+    buffer: 27 planes of populations after init / set_state, 16 factored planes after a step."""
     p = ctypes.c_void_p()
     eb = ctypes.c_int32()
     pl = ctypes.c_int64()
