@@ -292,12 +292,12 @@ int lbm3_adjoint_pipeline_slots(int64_t nodes, uint64_t ws_two_slots, uint64_t w
  * 3 x 3 tensor, Guo's term and the velocity of Eqs. (8)-(9), the equilibrium of Eq. (3),
  * the recolouring of Eq. (13) with any segregation law (beta_law), streaming of Eq. (22);
  * periodic in x, y and z.  FP64 and the paper's forcing only (else LBM3_EUNSUPPORTED).
- * lbm3d_create: p as for lbm3_create (nx, ny from it), nz in 1..65535, at most 2^31
- *   nodes (else LBM3_EINVAL); allocates the
- *   two 57-population state buffers and the intermediates (about 150 doubles per node).
+ * lbm3d_create: p as for lbm3_create (nx, ny from it), nz in 1..65535, at most 2^29
+ *   nodes (else LBM3_EINVAL); allocates the two 57-population state buffers and a
+ *   staging buffer for exports (174 doubles per node in all).
  * lbm3d_init_fields: rho host [3][nz][ny][nx] (x fastest), finite, >= 0, with rho > 0 at
  *   every node; fluid at rest (f_{i,k} = w_i rho_k).  Blocking; resets the step count.
- * lbm3d_step: enqueues n >= 0 steps on the handle's stream (three launches each).
+ * lbm3d_step: enqueues n >= 0 steps on the handle's stream (one launch each).
  * lbm3d_observables: blocking; masses, momentum sum rho u (Eq. 9 velocity), kinetic
  *   energy, max |u|, and when non-NULL the densities (host [3][nz][ny][nx]) and the
  *   post-streaming populations (host [3][19][nz][ny][nx], links in the order: rest,

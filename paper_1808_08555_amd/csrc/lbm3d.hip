@@ -2,15 +2,10 @@
 // standard D3Q19 lattice, FP64, the force of Eq. (7) with Guo's term, any segregation law.
 //
 // State: the recoloured populations before streaming, 57 planes B[k][i][z][y][x] (pull
-// scheme: f_{i,k}(x) = B_{i,k}(x - e_i)), two buffers.  A step is three node-parallel
-// kernels:
-//   k3_conc     pull; concentrations c_k, densities rho_k, totals f_i -> c[25][N]
-//   k3_stress   grad c_k (Eq. 12), pair normals, C_kl, stress T      -> T[6][N], n[9][N]
-//   k3_collide  F = div T (Eq. 12 again), collision with Guo's term (Eqs. 1-3, 8-11),
-//               recolouring (Eq. 13 with the segregation law)        -> B'[57][N]
-// Bytes per update: the state read and written once (912 B) plus the intermediates (the 25
-// planes of k3_conc and the 15 of k3_stress, each written and read once: 320 B; neighbour
-// re-reads served by the caches).
+// scheme: f_{i,k}(x) = B_{i,k}(x - e_i)), two buffers.  A step is one launch of the fused
+// march (k3_march): workgroups own x-y blocks of a z segment and march up z, keeping the
+// concentrations and the stress of three planes in LDS rings, so that the state is read
+// and written once per update (912 B) and nothing else goes through HBM.
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -33,6 +28,18 @@ struct Geo3 {
     int nx, ny, nz;
     int64_t N;
 };
+
+// Loads and stores at a byte offset from a plane's base: with at most 2^29 nodes the
+// offset of any node within a plane fits 32 bits, so the uniform base stays in scalar
+// registers and each lane holds a 32-bit offset.
+__device__ __forceinline__ double ld_plane(const double* __restrict__ base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ __forceinline__ void st_plane(double* __restrict__ base, uint32_t byte_off, double v)
+{
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
 
 // The node indices of (x, y, z) and its neighbours: the wrapped coordinates at offsets -1,
 // 0, +1 per axis, formed once per node (no division per neighbour).
@@ -64,97 +71,52 @@ __device__ __forceinline__ void pull57(const double* __restrict__ B, const Geo3&
     }
 }
 
-// The totals f_i and densities rho_k of the pulled populations, summed as they arrive (the
-// single populations are not needed again: collision acts on f_i, recolouring on c_k).
-__device__ __forceinline__ void pull_sums(const double* __restrict__ B, const Geo3& g, const Nb3& nb,
-                                          double (&ft)[19], double (&rk)[3])
+// e_i . (a0, a1, a2) over the nonzero components of link i (each +-1), added in x, y, z
+// order.  A zero component would only add an exact zero, so this is the value of the full
+// sum (up to the sign of a zero result) without the products by zero, which floating point
+// cannot drop by itself.
+__device__ __forceinline__ double edot(int i, double a0, double a1, double a2)
 {
-    rk[0] = rk[1] = rk[2] = 0.0;
+    const int e[3] = {L3X[i], L3Y[i], L3Z[i]};
+    const double a[3] = {a0, a1, a2};
+    double r = 0.0;
+    bool any = false;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        const int64_t src = nb.at(-L3X[i], -L3Y[i], -L3Z[i]);
-        const double a = B[(int64_t)i * g.N + src], b = B[(int64_t)(19 + i) * g.N + src],
-                     c = B[(int64_t)(38 + i) * g.N + src];
-        ft[i] = a + b + c;
-        rk[0] += a;
-        rk[1] += b;
-        rk[2] += c;
-    }
+    for (int c = 0; c < 3; ++c)
+        if (e[c] != 0) {
+            const double v = e[c] > 0 ? a[c] : -a[c];
+            r = any ? r + v : v;
+            any = true;
+        }
+    return r;
 }
 
-// Eq. (12) over the nine pairs of opposite links: 3 sum_i w_i e_i [phi(x + e_i) - phi(x - e_i)]
-__device__ __forceinline__ void grad19(const double* __restrict__ phi, const Nb3& nb, double (&d)[3])
+// Eq. (12) over the nine pairs of opposite links: 3 sum_i w_i e_i [phi(x + e_i) - phi(x - e_i)],
+// phi(dx, dy, dz) the field at offset (dx, dy, dz) from the node (zero components of e_i
+// skipped, as in edot)
+template <typename Get>
+__device__ __forceinline__ void grad19(Get phi, double (&d)[3])
 {
     d[0] = d[1] = d[2] = 0.0;
 #pragma unroll
     for (int i = 1; i < 19; i += 2) {
-        const double df = phi[nb.at(L3X[i], L3Y[i], L3Z[i])] - phi[nb.at(-L3X[i], -L3Y[i], -L3Z[i])];
-        d[0] += w19(i) * L3X[i] * df;
-        d[1] += w19(i) * L3Y[i] * df;
-        d[2] += w19(i) * L3Z[i] * df;
+        const double df = phi(L3X[i], L3Y[i], L3Z[i]) - phi(-L3X[i], -L3Y[i], -L3Z[i]);
+        if (L3X[i] != 0) d[0] += w19(i) * L3X[i] * df;
+        if (L3Y[i] != 0) d[1] += w19(i) * L3Y[i] * df;
+        if (L3Z[i] != 0) d[2] += w19(i) * L3Z[i] * df;
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) d[a] *= 3.0;
 }
 
-// Blocks of 256 consecutive nodes (x fastest, then y, then z) on a one-dimensional grid.
-// Workgroups go to the eight XCDs in turn, and each XCD has its own L2; block b therefore
-// takes the node range of logical block xcd_block(b), so that each XCD works through one
-// contiguous run of blocks (a slab of z) and finds most of its stencil neighbours in its
-// own L2.  The map is a bijection of [0, T) for any T.
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t T)
-{
-    const int64_t x = b & 7, k = b >> 3, q = T >> 3, r = T & 7;
-    return x * q + (x < r ? x : r) + k;
-}
-
-// (x, y, z) of this thread's node; false past the last node
-__device__ __forceinline__ bool node3(const Geo3& g, int& x, int& y, int& z)
-{
-    const int64_t n = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-    if (n >= g.N) return false;
-    // N <= 2^31 (checked at creation): 32-bit division suffices
-    const uint32_t n32 = (uint32_t)n, nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
-    const uint32_t p = n32 / nx, zz = p / ny;
-    x = (int)(n32 - p * nx), y = (int)(p - zz * ny), z = (int)zz;
-    return true;
-}
-
-__global__ __launch_bounds__(256) void k3_conc(const double* __restrict__ B, Geo3 g, double* __restrict__ c)
-{
-    int x, y, z;
-    if (!node3(g, x, y, z)) return;
-    const Nb3 nb(g, x, y, z);
-    double ft[19], rk[3];
-    pull_sums(B, g, nb, ft, rk);
-    const double ir = 1.0 / (rk[0] + rk[1] + rk[2]);
-    const int64_t j = nb.at(0, 0, 0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        c[k * g.N + j] = rk[k] * ir;
-        c[(3 + k) * g.N + j] = rk[k];
-    }
-#pragma unroll
-    for (int i = 0; i < 19; ++i) c[(6 + i) * g.N + j] = ft[i];
-}
-
 // Stress T = sum_pairs sigma C (|G|^2 I - G G^T)/|G| (xx, xy, xz, yy, yz, zz) and the pair
-// normals n_kl (zero at or below the guard), from c_k and rho_k of k3_conc.
-__global__ __launch_bounds__(256) void k3_stress(const double* __restrict__ c, Geo3 g, KParams kp,
-                                                 double* __restrict__ T, double* __restrict__ nrm)
+// normals n_kl (n[3p + a]; zero at or below the guard) of a node from its concentrations
+// cc, their gradients gc and its densities rk (Eq. 7 with C_kl of Eq. 6).
+__device__ __forceinline__ void stress19(const double (&gc)[3][3], const double (&cc)[3], const double (&rk)[3],
+                                         const KParams& kp, double (&t)[6], double (&nrm)[9])
 {
-    int x, y, z;
-    if (!node3(g, x, y, z)) return;
-    const Nb3 nb(g, x, y, z);
-    const int64_t j = nb.at(0, 0, 0);
-    double gc[3][3], cc[3], rk[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        grad19(c + k * g.N, nb, gc[k]);
-        cc[k] = c[k * g.N + j];
-        rk[k] = c[(3 + k) * g.N + j];
-    }
-    double t[6] = {0, 0, 0, 0, 0, 0};
+    for (int q = 0; q < 6; ++q) t[q] = 0.0;
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         const int k = PK3[p], l = PL3[p];
@@ -178,15 +140,14 @@ __global__ __launch_bounds__(256) void k3_stress(const double* __restrict__ c, G
             t[5] += s * (1.0 - n[2] * n[2]);
         }
 #pragma unroll
-        for (int a = 0; a < 3; ++a) nrm[(3 * p + a) * g.N + j] = n[a];
+        for (int a = 0; a < 3; ++a) nrm[3 * p + a] = n[a];
     }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) T[q * g.N + j] = t[q];
 }
 
-// F_b = sum_a d_a T_ab with the symmetric T stored as (xx, xy, xz, yy, yz, zz)
-__device__ __forceinline__ void force19(const double* __restrict__ T, const Geo3& g, const Nb3& nb,
-                                        double (&F)[3])
+// F_b = sum_a d_a T_ab with the symmetric T stored as (xx, xy, xz, yy, yz, zz);
+// T(q, dx, dy, dz) is component q at offset (dx, dy, dz) from the node
+template <typename Get>
+__device__ __forceinline__ void force19(Get T, double (&F)[3])
 {
     constexpr int Q[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
     F[0] = F[1] = F[2] = 0.0;
@@ -195,107 +156,289 @@ __device__ __forceinline__ void force19(const double* __restrict__ T, const Geo3
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             double d[3];
-            grad19(T + Q[a][b] * g.N, nb, d);
+            grad19([&](int dx, int dy, int dz) { return T(Q[a][b], dx, dy, dz); }, d);
             F[b] += d[a];
         }
 }
 
-template <bool OBS>
-__global__ __launch_bounds__(256) void k3_collide(const double* __restrict__ C6, const double* __restrict__ T,
-                                                  const double* __restrict__ nrm, Geo3 g, KParams kp,
-                                                  double* __restrict__ Bout, double* __restrict__ partials)
+// Collision with Guo's term (Eqs. 1-3, 8-11) and recolouring (Eq. 13 with the segregation
+// law) of one node from its densities rk, totals ft, force F and pair normals nrm.  With OBS
+// the node's observables go to acc (rho_k, rho u, kinetic energy, |u|); otherwise every
+// recoloured population is handed to put(k, i, value).
+template <bool OBS, typename Put>
+__device__ __forceinline__ void collide19(const double (&rk)[3], const double (&ft)[19], const double (&F)[3],
+                                          const double (&nrm)[9], const KParams& kp, double (&acc)[8], Put put)
 {
-    __shared__ double red[OBS ? 8 : 1][256];
-    int x, y, z;
-    const bool live = node3(g, x, y, z);
-    const int t = threadIdx.x;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (live) {
-        const Nb3 nb(g, x, y, z);
-        const int64_t j = nb.at(0, 0, 0);
-        // the densities and totals k3_conc pulled
-        double rk[3], ft[19];
+    const double rho = rk[0] + rk[1] + rk[2], irho = 1.0 / rho;
+    double m[3] = {0, 0, 0};
 #pragma unroll
-        for (int k = 0; k < 3; ++k) rk[k] = C6[(3 + k) * g.N + j];
+    for (int i = 0; i < 19; ++i) {
+        if (L3X[i] != 0) m[0] += L3X[i] > 0 ? ft[i] : -ft[i];
+        if (L3Y[i] != 0) m[1] += L3Y[i] > 0 ? ft[i] : -ft[i];
+        if (L3Z[i] != 0) m[2] += L3Z[i] > 0 ? ft[i] : -ft[i];
+    }
+    double u[3], uu = 0.0, uF = 0.0;
 #pragma unroll
-        for (int i = 0; i < 19; ++i) ft[i] = C6[(6 + i) * g.N + j];
-        const double rho = rk[0] + rk[1] + rk[2], irho = 1.0 / rho;
-        double F[3];
-        force19(T, g, nb, F);
-        double m[3] = {0, 0, 0};
-#pragma unroll
-        for (int i = 0; i < 19; ++i) {
-            m[0] += ft[i] * L3X[i];
-            m[1] += ft[i] * L3Y[i];
-            m[2] += ft[i] * L3Z[i];
-        }
-        double u[3], uu = 0.0, uF = 0.0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            u[a] = (m[a] + 0.5 * F[a]) * irho;
-            uu += u[a] * u[a];
-            uF += u[a] * F[a];
-        }
-        if constexpr (OBS) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) acc[k] = rk[k];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) acc[3 + a] = rho * u[a];
-            acc[6] = 0.5 * rho * uu;
-            acc[7] = sqrt(uu);
-        } else {
-            // tau = 3 nu + 1/2 with rho / nu = sum_k rho_k / nu_k (Eqs. 10-11)
-            const double rho_over_nu = rk[0] * kp.inv_nu[0] + rk[1] * kp.inv_nu[1] + rk[2] * kp.inv_nu[2];
-            const double itau = rho_over_nu / (3.0 * rho + 0.5 * rho_over_nu);
-            const double pref = 1.0 - 0.5 * itau;
-            double fd[19];
-#pragma unroll
-            for (int i = 0; i < 19; ++i) {
-                const double eu = L3X[i] * u[0] + L3Y[i] * u[1] + L3Z[i] * u[2];
-                const double eF = L3X[i] * F[0] + L3Y[i] * F[1] + L3Z[i] * F[2];
-                const double feq = w19(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-                const double phi = w19(i) * pref * (3.0 * (eF - uF) + 9.0 * eu * eF);
-                fd[i] = ft[i] - (ft[i] - feq) * itau + phi;
-            }
-            // C_t and beta_kl of the segregation law; a_p = beta_p rho_k rho_l / rho
-            double ct = kp.ct_coef * rk[0] * rk[1] * rk[2] * (irho * irho * irho);
-            ct = ct < 1.0 ? ct : 1.0;
-            double ap[3];
-#pragma unroll
-            for (int p = 0; p < 3; ++p) ap[p] = kp.beta0 * (1.0 + ct * kp.g[p]) * (rk[PK3[p]] * rk[PL3[p]]) * irho;
-            // V_k = sum_{l != k} a_kl n_kl (n_lk = -n_kl)
-            double V[3][3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double n0 = nrm[(0 + a) * g.N + j], n1 = nrm[(3 + a) * g.N + j], n2 = nrm[(6 + a) * g.N + j];
-                V[0][a] = ap[0] * n0 + ap[1] * n1;
-                V[1][a] = ap[2] * n2 - ap[0] * n0;
-                V[2][a] = -(ap[1] * n1 + ap[2] * n2);
-            }
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const double ck = rk[k] * irho;
-#pragma unroll
-                for (int i = 0; i < 19; ++i) {
-                    const double ve = V[k][0] * L3X[i] + V[k][1] * L3Y[i] + V[k][2] * L3Z[i];
-                    Bout[(int64_t)(k * 19 + i) * g.N + j] = ck * fd[i] + w19(i) * ve;
-                }
-            }
-        }
+    for (int a = 0; a < 3; ++a) {
+        u[a] = (m[a] + 0.5 * F[a]) * irho;
+        uu += u[a] * u[a];
+        uF += u[a] * F[a];
     }
     if constexpr (OBS) {
-        // wavefront reductions, then the four wave results in order
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[k] += rk[k];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[3 + a] += rho * u[a];
+        acc[6] += 0.5 * rho * uu;
+        const double um = sqrt(uu);
+        acc[7] = (um > acc[7] || um != um) ? um : acc[7];
+    } else {
+        // tau = 3 nu + 1/2 with rho / nu = sum_k rho_k / nu_k (Eqs. 10-11)
+        const double rho_over_nu = rk[0] * kp.inv_nu[0] + rk[1] * kp.inv_nu[1] + rk[2] * kp.inv_nu[2];
+        const double itau = rho_over_nu / (3.0 * rho + 0.5 * rho_over_nu);
+        const double pref = 1.0 - 0.5 * itau;
+        // C_t and beta_kl of the segregation law; a_p = beta_p rho_k rho_l / rho
+        double ct = kp.ct_coef * rk[0] * rk[1] * rk[2] * (irho * irho * irho);
+        ct = ct < 1.0 ? ct : 1.0;
+        double ap[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) ap[p] = kp.beta0 * (1.0 + ct * kp.g[p]) * (rk[PK3[p]] * rk[PL3[p]]) * irho;
+        // V_k = sum_{l != k} a_kl n_kl (n_lk = -n_kl)
+        double V[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double n0 = nrm[0 + a], n1 = nrm[3 + a], n2 = nrm[6 + a];
+            V[0][a] = ap[0] * n0 + ap[1] * n1;
+            V[1][a] = ap[2] * n2 - ap[0] * n0;
+            V[2][a] = -(ap[1] * n1 + ap[2] * n2);
+        }
+        double ck[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ck[k] = rk[k] * irho;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const double eu = edot(i, u[0], u[1], u[2]);
+            const double eF = edot(i, F[0], F[1], F[2]);
+            const double feq = w19(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+            const double phi = w19(i) * pref * (3.0 * (eF - uF) + 9.0 * eu * eF);
+            const double fd = ft[i] - (ft[i] - feq) * itau + phi;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double ve = edot(i, V[k][0], V[k][1], V[k][2]);
+                put(k, i, ck[k] * fd + w19(i) * ve);
+            }
+            // each link's values leave before the next link's are formed (otherwise the
+            // compiler holds all 57 for one burst of stores)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// ---- the fused step: one kernel per step, marching along z
+// A workgroup of kTX x kTY lanes (lane t at tile column t % kTX, tile row t / kTX; each wave
+// is two whole tile rows) owns the output nodes [x0, x0 + cols) x [y0, y0 + rows) x
+// [z0, z0 + depth), cols <= kTX - 4 and rows <= kTY - 4.  Lane (tx, ty) sits on node column
+// (x0 - 2 + tx, y0 - 2 + ty) (wrapped) and marches up z.  Iteration j, three phases closed
+// by barriers:
+//   stage 1, plane z0 - 2 + j: pull the 57 populations; totals f_i and densities rho_k (kept
+//            in registers for two more iterations); c_k into the LDS ring (all lanes with
+//            tx <= cols + 3, ty <= rows + 3);
+//   stage 2, plane z0 - 3 + j: grad c_k (Eq. 12) from the ring, stress and pair normals
+//            (lanes 1 .. cols + 2, 1 .. rows + 2); T into its LDS ring;
+//   stage 3, plane z0 - 4 + j: F = div T from the ring, collision and recolouring of the
+//            owned nodes (lanes 2 .. cols + 1, 2 .. rows + 1), stored.
+// Rings hold three planes, by plane mod 3.  depth + 4 iterations output the tile's planes.
+// The arithmetic of every node is that of stress19 / force19 / collide19 in a fixed order,
+// so the result does not depend on the tile shape.
+constexpr int kTX = 32, kTY = 16, kT3 = kTX * kTY;
+
+struct Tile3 {
+    int32_t x0, y0, z0, cols, rows, depth;
+};
+
+constexpr int kTS = (kTX - 2) * (kTY - 2);  // lanes that form the stress
+constexpr int kTP = (kTX - 4) * (kTY - 4);  // lanes that own output nodes
+
+struct alignas(16) March3Lds {
+    double c[3][3][kT3];     // c_k by plane mod 3
+    double T[3][6][kTS];     // stress by plane mod 3, on the stress lanes
+    double park[19][kTP];    // per owning lane: the totals f_i of one waiting plane
+};
+
+template <bool OBS>
+__global__ __launch_bounds__(kT3) __attribute__((amdgpu_waves_per_eu(2))) void k3_march(const double* __restrict__ B, Geo3 g, KParams kp,
+                                                const Tile3* __restrict__ tiles, double* __restrict__ Bout,
+                                                double* __restrict__ partials)
+{
+    __shared__ March3Lds L;
+    const Tile3 tl = tiles[blockIdx.x];
+    const int t = threadIdx.x, tx = t % kTX, ty = t / kTX;
+    const bool in1 = tx <= tl.cols + 3 && ty <= tl.rows + 3;
+    const bool in2 = tx >= 1 && tx <= tl.cols + 2 && ty >= 1 && ty <= tl.rows + 2;
+    const bool in3 = tx >= 2 && tx <= tl.cols + 1 && ty >= 2 && ty <= tl.rows + 1;
+    auto wrap = [](int a, int n) {
+        const int r = a % n;
+        return r < 0 ? r + n : r;
+    };
+    const int x = wrap(tl.x0 - 2 + tx, g.nx), y = wrap(tl.y0 - 2 + ty, g.ny);
+    // node offsets within a plane at x - 1, x, x + 1 and y - 1, y, y + 1 (N <= 2^29: the
+    // byte offset of any node fits 32 bits)
+    const uint32_t xo[3] = {(uint32_t)(x == 0 ? g.nx - 1 : x - 1), (uint32_t)x, (uint32_t)(x == g.nx - 1 ? 0 : x + 1)};
+    const uint32_t yo[3] = {(uint32_t)((y == 0 ? g.ny - 1 : y - 1) * g.nx), (uint32_t)(y * g.nx),
+                            (uint32_t)((y == g.ny - 1 ? 0 : y + 1) * g.nx)};
+    const uint32_t pl = (uint32_t)(g.nx * g.ny);
+    // the stress lanes' and owning lanes' slots in the T ring and the park
+    const int tS = (ty - 1) * (kTX - 2) + (tx - 1), tP = (ty - 2) * (kTX - 4) + (tx - 2);
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // The totals f_i of a plane are used two iterations after its pull, so three planes of
+    // them are live at a time: the one pulled (ft), the one waiting (W) and the one collided
+    // (ftB).  Each owning lane parks one of them in LDS (its own slots, so no barrier is
+    // involved): after the pull, ftB comes out of the park, W goes in, and ft becomes W.
+    double W[19], rA[3], rB[3], nB[9];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) W[i] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rA[k] = rB[k] = 1.0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) nB[q] = 0.0;
+    const int J = tl.depth + 4;
+    // plane offset of plane z (wrapped) and the source of link i for planes zo[]
+    auto zoff = [&](int z) { return (uint32_t)wrap(z, g.nz) * pl; };
+    auto src = [&](const uint32_t (&zo)[3], int i) {
+        return (zo[1 - L3Z[i]] + yo[1 - L3Y[i]] + xo[1 - L3X[i]]) * 8u;
+    };
+#pragma unroll 1
+    for (int j = 0; j < J; ++j) {
+        const int zc = wrap(tl.z0 - 2 + j, g.nz);
+        const int s0 = j % 3, s1 = (j + 2) % 3, s2 = (j + 1) % 3;  // planes zc, zc - 1, zc - 2
+        // ---- stage 1: pull of plane zc
+        double ft[19], rk[3] = {1.0, 1.0, 1.0};
+#pragma unroll
+        for (int i = 0; i < 19; ++i) ft[i] = 0.0;
+        if (in1) {
+            // two memory round trips per plane: fluids 0 and 1 (38 loads in flight), then
+            // fluid 2; scheduling barriers keep the compiler from interleaving loads and sums
+            // (which serialises the loads) or from overlapping the batches (more registers
+            // than a lane has at two waves per SIMD)
+            const uint32_t zo[3] = {zoff(zc - 1), zoff(zc), zoff(zc + 1)};
+            double v[38];
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                const uint32_t o = src(zo, i);
+                v[i] = ld_plane(B + (int64_t)i * g.N, o);
+                v[19 + i] = ld_plane(B + (int64_t)(19 + i) * g.N, o);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            rk[0] = rk[1] = rk[2] = 0.0;
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                ft[i] = v[i] + v[19 + i];
+                rk[0] += v[i];
+                rk[1] += v[19 + i];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < 19; ++i) v[i] = ld_plane(B + (int64_t)(38 + i) * g.N, src(zo, i));
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                ft[i] += v[i];
+                rk[2] += v[i];
+            }
+            const double ir = 1.0 / (rk[0] + rk[1] + rk[2]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) L.c[s0][k][t] = rk[k] * ir;
+        }
+        double ftB[19];
+#pragma unroll
+        for (int i = 0; i < 19; ++i) ftB[i] = 0.0;
+        if (in3) {
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                ftB[i] = L.park[i][tP];
+                L.park[i][tP] = W[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 19; ++i) W[i] = ft[i];
+        __syncthreads();
+        // ---- stage 2: stress of plane zc - 1
+        double nA[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) nA[q] = 0.0;
+        if (j >= 2 && in2) {
+            const int sl[3] = {s2, s1, s0};  // by dz + 1
+            double gc[3][3], cc[3], tt[6];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                grad19([&](int dx, int dy, int dz) { return L.c[sl[dz + 1]][k][t + dy * kTX + dx]; }, gc[k]);
+                cc[k] = L.c[s1][k][t];
+            }
+            stress19(gc, cc, rA, kp, tt, nA);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) L.T[s1][q][tS] = tt[q];
+        }
+        __syncthreads();
+        // ---- stage 3: collision and recolouring of plane zc - 2
+        if (j >= 4 && in3) {
+            const int sl[3] = {s0, s2, s1};  // T of planes zc - 3, zc - 2, zc - 1 by dz + 1
+            double F[3];
+            force19([&](int q, int dx, int dy, int dz) { return L.T[sl[dz + 1]][q][tS + dy * (kTX - 2) + dx]; },
+                    F);
+            const uint32_t o = ((uint32_t)(tl.z0 - 4 + j) * pl + yo[1] + (uint32_t)x) * 8u;
+            collide19<OBS>(rB, ftB, F, nB, kp, acc,
+                           [&](int k, int i, double v) { st_plane(Bout + (int64_t)(k * 19 + i) * g.N, o, v); });
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            rB[k] = rA[k];
+            rA[k] = rk[k];
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) nB[q] = nA[q];
+    }
+    if constexpr (OBS) {
+        // wavefront reductions, then the eight waves' results in order (the c ring is free
+        // once every lane has passed the last barrier of the march)
+        __syncthreads();
         for (int q = 0; q < 7; ++q) acc[q] = wave_sum(acc[q]);
         acc[7] = wave_max(acc[7]);
+        double* red = &L.c[0][0][0];
+        constexpr int W = kT3 / 64;
         if ((t & 63) == 0)
-            for (int q = 0; q < 8; ++q) red[q][t >> 6] = acc[q];
+            for (int q = 0; q < 8; ++q) red[q * W + (t >> 6)] = acc[q];
         __syncthreads();
         if (t < 8) {
-            double v = red[t][0];
-            for (int w = 1; w < 4; ++w) v = t < 7 ? v + red[t][w] : fmax(v, red[t][w]);
+            double v = red[t * W];
+            for (int w = 1; w < W; ++w) {
+                const double o = red[t * W + w];
+                v = t < 7 ? v + o : ((o > v || o != o) ? o : v);
+            }
             partials[(int64_t)blockIdx.x * 8 + t] = v;
         }
     }
+}
+
+// Node-parallel kernels (initialisation, export): blocks of 256 consecutive nodes (x
+// fastest, then y, then z) on a one-dimensional grid.  Workgroups go to the eight XCDs in
+// turn; block b takes the node range of logical block xcd_block(b), so that each XCD works
+// through one contiguous run of blocks.  The map is a bijection of [0, T) for any T.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t T)
+{
+    const int64_t x = b & 7, k = b >> 3, q = T >> 3, r = T & 7;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// (x, y, z) of this thread's node; false past the last node
+__device__ __forceinline__ bool node3(const Geo3& g, int& x, int& y, int& z)
+{
+    const int64_t n = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (n >= g.N) return false;
+    // N <= 2^29 (checked at creation): 32-bit division suffices
+    const uint32_t n32 = (uint32_t)n, nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
+    const uint32_t p = n32 / nx, zz = p / ny;
+    x = (int)(n32 - p * nx), y = (int)(p - zz * ny), z = (int)zz;
+    return true;
 }
 
 // B_{i,k}(y) = w_i rho_k(y + e_i): the pulled state is f_{i,k} = w_i rho_k (fluid at rest)
@@ -344,11 +487,11 @@ struct lbm3d {
     Geo3 g{};
     hipStream_t stream = nullptr;
     double* buf[2] = {nullptr, nullptr};
-    double* c = nullptr;        // [25][N]: c_k, rho_k, f_i of the pulled state
-    double* T = nullptr;        // [6][N]
-    double* nrm = nullptr;      // [9][N]
-    double* partials = nullptr; // [blocks][8]
-    double* staging = nullptr;  // [57][N] for exports and uploads
+    Tile3* dtiles = nullptr;     // the march's tile list
+    int ntiles = 0;
+    double* partials = nullptr;  // [ntiles][8]
+    double* staging = nullptr;   // [57][N] for exports and uploads
+    double* rho = nullptr;       // [3][N] densities for exports
     int cur = 0;
     int64_t step = 0;
     bool ready = false;
@@ -359,16 +502,69 @@ static dim3 grid3(const Geo3& g) { return dim3((unsigned)((g.N + 255) / 256)); }
 static void release3(lbm3d* h)
 {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    for (double* q : {h->buf[0], h->buf[1], h->c, h->T, h->nrm, h->partials, h->staging})
+    for (double* q : {h->buf[0], h->buf[1], h->partials, h->staging, h->rho})
         if (q) (void)hipFree(q);
+    if (h->dtiles) (void)hipFree(h->dtiles);
 }
 
-// k3_conc and k3_stress of the current state: the fields k3_collide reads
-static hipError_t fields3(lbm3d* h)
+// n split into parts of at most `most` (as equal as possible): part q is [start, start + len)
+static void split_even(int n, int parts, int q, int& start, int& len)
 {
-    const dim3 gr = grid3(h->g), bl(256);
-    hipLaunchKernelGGL(k3_conc, gr, bl, 0, h->stream, (const double*)h->buf[h->cur], h->g, h->c);
-    hipLaunchKernelGGL(k3_stress, gr, bl, 0, h->stream, (const double*)h->c, h->g, h->kp, h->T, h->nrm);
+    const int base = n / parts, extra = n % parts;
+    start = q * base + (q < extra ? q : extra);
+    len = base + (q < extra ? 1 : 0);
+}
+
+// The march's tiles: the x-y plane cut into at most (kTX - 4) x (kTY - 4) node blocks, the
+// z axis into `nseg` segments chosen so that rounds of resident workgroups x (segment depth
+// + 4 warm-up planes) is least.  Workgroups go to the XCDs in turn, so the list is permuted
+// for each XCD to take a contiguous run of it (neighbouring blocks, whose halos it then
+// finds in its own L2).
+static std::vector<Tile3> plan3(const Geo3& g, int slots)
+{
+    const int ntx = (g.nx + kTX - 5) / (kTX - 4), nty = (g.ny + kTY - 5) / (kTY - 4);
+    const int64_t per_seg = (int64_t)ntx * nty;
+    if (slots < 1) slots = 1;
+    int nseg = 1;
+    double best = 1e300;
+    for (int s = 1; s <= g.nz; ++s) {
+        const int depth = (g.nz + s - 1) / s;
+        const int64_t rounds = (per_seg * s + slots - 1) / slots;
+        const double cost = (double)rounds * (depth + 4) * (1.0 + 1e-9 * s);
+        if (cost < best) {
+            best = cost;
+            nseg = s;
+        }
+        if (depth <= 4) break;
+    }
+    std::vector<Tile3> L;
+    L.reserve((size_t)per_seg * nseg);
+    for (int zs = 0; zs < nseg; ++zs)
+        for (int ty = 0; ty < nty; ++ty)
+            for (int tx = 0; tx < ntx; ++tx) {
+                Tile3 t{};
+                split_even(g.nx, ntx, tx, t.x0, t.cols);
+                split_even(g.ny, nty, ty, t.y0, t.rows);
+                split_even(g.nz, nseg, zs, t.z0, t.depth);
+                L.push_back(t);
+            }
+    const int T = (int)L.size(), nxcd = 8;
+    std::vector<Tile3> out(T);
+    std::vector<int> start(nxcd + 1, 0);
+    for (int x = 0; x < nxcd; ++x) start[x + 1] = start[x] + (T - x + nxcd - 1) / nxcd;
+    for (int b = 0; b < T; ++b) out[b] = L[start[b % nxcd] + b / nxcd];
+    return out;
+}
+
+static hipError_t launch_march(lbm3d* h, bool obs)
+{
+    const double* in = h->buf[h->cur];
+    if (obs)
+        hipLaunchKernelGGL((k3_march<true>), dim3(h->ntiles), dim3(kT3), 0, h->stream, in, h->g, h->kp,
+                           (const Tile3*)h->dtiles, (double*)nullptr, h->partials);
+    else
+        hipLaunchKernelGGL((k3_march<false>), dim3(h->ntiles), dim3(kT3), 0, h->stream, in, h->g, h->kp,
+                           (const Tile3*)h->dtiles, h->buf[h->cur ^ 1], (double*)nullptr);
     return hipGetLastError();
 }
 
@@ -387,8 +583,8 @@ int lbm3d_create(const lbm3_params* p, int32_t nz, void* hip_stream, lbm3d_t** o
         set_error("nz must be in 1..65535 (got %d)", nz);
         return LBM3_EINVAL;
     }
-    if ((int64_t)p->nx * p->ny * nz > ((int64_t)1 << 31)) {
-        set_error("the D3Q19 form takes at most 2^31 nodes (got %d x %d x %d)", (int)p->nx, (int)p->ny, nz);
+    if ((int64_t)p->nx * p->ny * nz > ((int64_t)1 << 29)) {
+        set_error("the D3Q19 form takes at most 2^29 nodes (got %d x %d x %d)", (int)p->nx, (int)p->ny, nz);
         return LBM3_EINVAL;
     }
     if (p->precision != LBM3_FP64) {
@@ -409,15 +605,23 @@ int lbm3d_create(const lbm3_params* p, int32_t nz, void* hip_stream, lbm3d_t** o
     h->g = Geo3{p->nx, p->ny, nz, (int64_t)p->nx * p->ny * nz};
     h->stream = (hipStream_t)hip_stream;
     const int64_t N = h->g.N;
-    const dim3 gr = grid3(h->g);
-    const size_t nblocks = (size_t)gr.x * gr.y * gr.z;
     hipError_t e = hipSuccess;
+    int dev = 0, cus = 0, per_cu = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k3_march<false>, kT3, 0);
+    std::vector<Tile3> tiles;
+    if (e == hipSuccess) {
+        tiles = plan3(h->g, per_cu * cus);
+        h->ntiles = (int)tiles.size();
+    }
     for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMalloc(&h->buf[b], (size_t)57 * N * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&h->c, (size_t)25 * N * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&h->T, (size_t)6 * N * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&h->nrm, (size_t)9 * N * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&h->partials, nblocks * 8 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&h->dtiles, tiles.size() * sizeof(Tile3));
+    if (e == hipSuccess)
+        e = hipMemcpy(h->dtiles, tiles.data(), tiles.size() * sizeof(Tile3), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&h->partials, tiles.size() * 8 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&h->staging, (size_t)57 * N * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&h->rho, (size_t)3 * N * sizeof(double));
     if (e != hipSuccess) {
         rc = hip_fail(e, "hipMalloc (D3Q19 lattice)");
         release3(h);
@@ -462,12 +666,7 @@ int lbm3d_step(lbm3d_t* h, int64_t n)
         return LBM3_ESTATE;
     }
     for (int64_t s = 0; s < n; ++s) {
-        hipError_t e = fields3(h);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL((k3_collide<false>), grid3(h->g), dim3(256), 0, h->stream, (const double*)h->c,
-                               (const double*)h->T, (const double*)h->nrm, h->g, h->kp, h->buf[h->cur ^ 1], nullptr);
-            e = hipGetLastError();
-        }
+        hipError_t e = launch_march(h, false);
         if (e != hipSuccess) return hip_fail(e, "D3Q19 step launch");
         h->cur ^= 1;
         h->step += 1;
@@ -486,24 +685,18 @@ int lbm3d_observables(lbm3d_t* h, lbm3d_obs* out, double* rho_out, double* f_out
         return LBM3_ESTATE;
     }
     const dim3 gr = grid3(h->g);
-    const size_t nblocks = (size_t)gr.x * gr.y * gr.z;
+    const size_t nblocks = (size_t)h->ntiles;
     const int64_t N = h->g.N;
-    hipError_t e = fields3(h);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL((k3_collide<true>), gr, dim3(256), 0, h->stream, (const double*)h->c,
-                           (const double*)h->T, (const double*)h->nrm, h->g, h->kp, (double*)nullptr, h->partials);
-        e = hipGetLastError();
-    }
+    hipError_t e = launch_march(h, true);
     std::vector<double> part(nblocks * 8);
     if (e == hipSuccess)
         e = hipMemcpyAsync(part.data(), h->partials, part.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess && (rho_out || f_out)) {
-        // the densities go to c (rewritten by the next step's k3_conc)
         hipLaunchKernelGGL(k3_export, gr, dim3(256), 0, h->stream, (const double*)h->buf[h->cur], h->g,
-                           f_out ? h->staging : nullptr, h->c);
+                           f_out ? h->staging : nullptr, h->rho);
         e = hipGetLastError();
         if (e == hipSuccess && rho_out)
-            e = hipMemcpyAsync(rho_out, h->c, (size_t)3 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+            e = hipMemcpyAsync(rho_out, h->rho, (size_t)3 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
         if (e == hipSuccess && f_out)
             e = hipMemcpyAsync(f_out, h->staging, (size_t)57 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     }
