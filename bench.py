@@ -36,7 +36,7 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash(files=("lbm3_step_impl.h", "lbm3_tiles_f64.hip", "lbm3_internal.h")) -> str:
+def kernel_source_hash(files=("lbm3_step_impl.h", "lbm3_rounding.h", "lbm3_tiles_f64.hip", "lbm3_internal.h")) -> str:
     """Hash of the kernel sources a profile summary was taken from (the 2D step's by
     default; the D3Q19 form's summaries use its own source)."""
     h = hashlib.sha256()
@@ -56,7 +56,7 @@ def profile_figure(kernel_tag: str, kind: str, key: str):
     text = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     t = re.search(re.escape(key) + r":\s*([0-9.eE+]+)", text)
-    files = ("lbm3d.hip",) if kernel_tag.startswith("lbm3d") else None
+    files = ("lbm3d.hip", "lbm3_rounding.h") if kernel_tag.startswith("lbm3d") else None
     current = kernel_source_hash(files) if files else kernel_source_hash()
     if not m or not t or m.group(1) != current:
         return None
@@ -214,15 +214,15 @@ def bench_adjoint(torch, lbm3, inputs, n: int, steps: int, every: int):
             "reverse_s": round(t2 - t1, 3), "forward_s": round(t1 - t0, 3)}
 
 
-def bench_d3q19(torch, lbm3, inputs, n: int, steps: int):
-    """The D3Q19 form (FP64) on an n^3 lattice of two tangent spheres, timed with HIP events
-    on the lattice's stream.  Algorithmic bytes: the 57 FP64 populations read and written
-    once per update (912 B)."""
+def bench_d3q19(torch, lbm3, inputs, n: int, steps: int, precision: str = "fp64"):
+    """The D3Q19 form on an n^3 lattice of two tangent spheres, timed with HIP events on the
+    lattice's stream.  Algorithmic bytes: the 57 populations read and written once per
+    update (912 B in FP64, 456 B in FP32 or FP32 storage)."""
     st = torch.cuda.current_stream()
     c = (n - 1) / 2
     R = n / 8.0
     rho = inputs.spheres(n, n, n, [(0, c - R, c, c, R), (1, c + R, c, c, R)])
-    L = lbm3.Lattice3D(n, n, n, (0.01, 0.01, 0.01), (1.0, 1.0, 1.0), stream=st).init(rho)
+    L = lbm3.Lattice3D(n, n, n, (0.01, 0.01, 0.01), (1.0, 1.0, 1.0), stream=st, precision=precision).init(rho)
     L.step(5)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -233,10 +233,11 @@ def bench_d3q19(torch, lbm3, inputs, n: int, steps: int):
     t = a.elapsed_time(b) / 1e3
     L.close()
     lu = n ** 3 * steps
-    res = {"workload": f"D3Q19 {n}^3, two tangent spheres of radius {R:g}, FP64, {steps} steps",
-           "mlups": round(lu / t / 1e6, 1), "bytes_per_lu_stated": 912,
-           "frac_of_peak": round(912 * lu / t / 1e9 / HBM_PEAK_GBS, 4), "kernel": "k3_march (one launch per step)"}
-    if n == 128:
+    b = 912 if precision == "fp64" else 456
+    res = {"workload": f"D3Q19 {n}^3, two tangent spheres of radius {R:g}, {precision}, {steps} steps",
+           "mlups": round(lu / t / 1e6, 1), "bytes_per_lu_stated": b,
+           "frac_of_peak": round(b * lu / t / 1e9 / HBM_PEAK_GBS, 4), "kernel": "k3_march (one launch per step)"}
+    if n == 128 and precision == "fp64":
         # counters of the committed summary, if taken from the current source
         res["traffic_over_algorithmic"] = profile_figure("lbm3d_d3q19_128", "pmc", "traffic_over_algorithmic")
         res["valu_issue_frac"] = profile_figure("lbm3d_d3q19_128", "pmc", "VALU issue fraction")
@@ -365,6 +366,8 @@ def main():
         log(f"perturbation forcing {pert}")
         d3 = bench_d3q19(torch, lbm3, inputs, 128, 60)
         log(f"d3q19 {d3}")
+        d3r = {prec: bench_d3q19(torch, lbm3, inputs, 128, 60, prec) for prec in ("fp32_storage", "fp32")}
+        log(f"d3q19 reduced precision {d3r}")
         batched = bench_batched(torch, lbm3, inputs, 1000)
         log(f"batched {batched}")
         adjoint = {"janus_256": bench_adjoint(torch, lbm3, inputs, 256, 5000, 100),
@@ -433,6 +436,8 @@ def main():
             "baseline_one_launch_per_instance_mlups": round(batched["per_instance_launches"], 1)}
         line["adjoint_fp64"] = adjoint
         line["d3q19_fp64"] = d3
+        for prec, v in d3r.items():
+            line[f"d3q19_{prec}"] = v
         line["beta_laws_fp64"] = {
             "workload": "the headline droplet tiling, FP64, 100 timed steps per law",
             **{law: {"mlups": round(v["mlups"], 1), "frac_of_peak": round(v["gbs"] / HBM_PEAK_GBS, 4)}

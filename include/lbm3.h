@@ -291,10 +291,12 @@ int lbm3_adjoint_pipeline_slots(int64_t nodes, uint64_t ws_two_slots, uint64_t w
  * Eq. (12) as the gradient and the force divergence, the stress pair sum of Eq. (7) as a
  * 3 x 3 tensor, Guo's term and the velocity of Eqs. (8)-(9), the equilibrium of Eq. (3),
  * the recolouring of Eq. (13) with any segregation law (beta_law), streaming of Eq. (22);
- * periodic in x, y and z.  FP64 and the paper's forcing only (else LBM3_EUNSUPPORTED).
+ * periodic in x, y and z.  Any precision (FP32 storage: each stored population the
+ * stochastic rounding of its FP64 value); the paper's forcing only (else
+ * LBM3_EUNSUPPORTED).
  * lbm3d_create: p as for lbm3_create (nx, ny from it), nz in 1..65535, at most 2^29
- *   nodes (else LBM3_EINVAL); allocates the two 57-population state buffers and a
- *   staging buffer for exports (174 doubles per node in all).
+ *   nodes (else LBM3_EINVAL); allocates the two 57-population state buffers (in the
+ *   storage type) and a staging buffer for exports (57 + 3 doubles per node).
  * lbm3d_init_fields: rho host [3][nz][ny][nx] (x fastest), finite, >= 0, with rho > 0 at
  *   every node; fluid at rest (f_{i,k} = w_i rho_k).  Blocking; resets the step count.
  * lbm3d_step: enqueues n >= 0 steps on the handle's stream (one launch each).

@@ -1,5 +1,6 @@
 // The three-dimensional (D3Q19) form of the ternary step: the paper's model (Sec. 2) on the
-// standard D3Q19 lattice, FP64, the force of Eq. (7) with Guo's term, any segregation law.
+// standard D3Q19 lattice, the force of Eq. (7) with Guo's term, any segregation law, in FP64,
+// FP32, or FP32 storage with FP64 arithmetic (stochastic rounding on store).
 //
 // State: the recoloured populations before streaming, 57 planes B[k][i][z][y][x] (pull
 // scheme: f_{i,k}(x) = B_{i,k}(x - e_i)), two buffers.  A step is one launch of the fused
@@ -12,16 +13,27 @@
 #include <vector>
 
 #include "lbm3_handle.h"
+#include "lbm3_rounding.h"
 
 namespace tcg {
 namespace {
 
 // D3Q19 links: rest, six axis links, twelve edge links; link i odd and i + 1 are opposite.
-// Weights 1/3, 1/18, 1/36; c_s^2 = 1/3.
+// Weights 1/3, 1/18, 1/36; c_s^2 = 1/3.  In FP32 the nearest floats sum to 1 + 1.5e-8, and
+// every collision would scale the mass by that sum (the equilibrium's zeroth moment); the
+// float weights are therefore one ulp above 1/3 and one ulp below 1/18 and 1/36, whose sum
+// is exactly 1.
 constexpr int L3X[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 constexpr int L3Y[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 constexpr int L3Z[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-__device__ __forceinline__ double w19(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+template <typename C>
+__device__ __forceinline__ C w19(int i)
+{
+    if constexpr (sizeof(C) == 8)
+        return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+    else
+        return i == 0 ? 0x1.555558p-2f : (i <= 6 ? 0x1.c71c70p-5f : 0x1.c71c70p-6f);
+}
 constexpr int PK3[3] = {0, 0, 1}, PL3[3] = {1, 2, 2};
 
 struct Geo3 {
@@ -32,13 +44,15 @@ struct Geo3 {
 // Loads and stores at a byte offset from a plane's base: with at most 2^29 nodes the
 // offset of any node within a plane fits 32 bits, so the uniform base stays in scalar
 // registers and each lane holds a 32-bit offset.
-__device__ __forceinline__ double ld_plane(const double* __restrict__ base, uint32_t byte_off)
+template <typename S>
+__device__ __forceinline__ S ld_plane(const S* __restrict__ base, uint32_t byte_off)
 {
-    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
+    return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + byte_off);
 }
-__device__ __forceinline__ void st_plane(double* __restrict__ base, uint32_t byte_off, double v)
+template <typename S>
+__device__ __forceinline__ void st_plane(S* __restrict__ base, uint32_t byte_off, S v)
 {
-    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
+    *reinterpret_cast<S*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
 // The node indices of (x, y, z) and its neighbours: the wrapped coordinates at offsets -1,
@@ -60,14 +74,15 @@ struct Nb3 {
 };
 
 // The post-streaming populations of node (x, y, z): f_{i,k} = B_{i,k}(x - e_i).
-__device__ __forceinline__ void pull57(const double* __restrict__ B, const Geo3& g, const Nb3& nb,
+template <typename S>
+__device__ __forceinline__ void pull57(const S* __restrict__ B, const Geo3& g, const Nb3& nb,
                                        double (&f)[3][19])
 {
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
         const int64_t src = nb.at(-L3X[i], -L3Y[i], -L3Z[i]);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) f[k][i] = B[(int64_t)(k * 19 + i) * g.N + src];
+        for (int k = 0; k < 3; ++k) f[k][i] = double(B[(int64_t)(k * 19 + i) * g.N + src]);
     }
 }
 
@@ -75,16 +90,17 @@ __device__ __forceinline__ void pull57(const double* __restrict__ B, const Geo3&
 // order.  A zero component would only add an exact zero, so this is the value of the full
 // sum (up to the sign of a zero result) without the products by zero, which floating point
 // cannot drop by itself.
-__device__ __forceinline__ double edot(int i, double a0, double a1, double a2)
+template <typename C>
+__device__ __forceinline__ C edot(int i, C a0, C a1, C a2)
 {
     const int e[3] = {L3X[i], L3Y[i], L3Z[i]};
-    const double a[3] = {a0, a1, a2};
-    double r = 0.0;
+    const C a[3] = {a0, a1, a2};
+    C r = C(0);
     bool any = false;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
         if (e[c] != 0) {
-            const double v = e[c] > 0 ? a[c] : -a[c];
+            const C v = e[c] > 0 ? a[c] : -a[c];
             r = any ? r + v : v;
             any = true;
         }
@@ -94,50 +110,51 @@ __device__ __forceinline__ double edot(int i, double a0, double a1, double a2)
 // Eq. (12) over the nine pairs of opposite links: 3 sum_i w_i e_i [phi(x + e_i) - phi(x - e_i)],
 // phi(dx, dy, dz) the field at offset (dx, dy, dz) from the node (zero components of e_i
 // skipped, as in edot)
-template <typename Get>
-__device__ __forceinline__ void grad19(Get phi, double (&d)[3])
+template <typename C, typename Get>
+__device__ __forceinline__ void grad19(Get phi, C (&d)[3])
 {
-    d[0] = d[1] = d[2] = 0.0;
+    d[0] = d[1] = d[2] = C(0);
 #pragma unroll
     for (int i = 1; i < 19; i += 2) {
-        const double df = phi(L3X[i], L3Y[i], L3Z[i]) - phi(-L3X[i], -L3Y[i], -L3Z[i]);
-        if (L3X[i] != 0) d[0] += w19(i) * L3X[i] * df;
-        if (L3Y[i] != 0) d[1] += w19(i) * L3Y[i] * df;
-        if (L3Z[i] != 0) d[2] += w19(i) * L3Z[i] * df;
+        const C df = phi(L3X[i], L3Y[i], L3Z[i]) - phi(-L3X[i], -L3Y[i], -L3Z[i]);
+        if (L3X[i] != 0) d[0] += w19<C>(i) * C(L3X[i]) * df;
+        if (L3Y[i] != 0) d[1] += w19<C>(i) * C(L3Y[i]) * df;
+        if (L3Z[i] != 0) d[2] += w19<C>(i) * C(L3Z[i]) * df;
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) d[a] *= 3.0;
+    for (int a = 0; a < 3; ++a) d[a] *= C(3);
 }
 
 // Stress T = sum_pairs sigma C (|G|^2 I - G G^T)/|G| (xx, xy, xz, yy, yz, zz) and the pair
 // normals n_kl (n[3p + a]; zero at or below the guard) of a node from its concentrations
 // cc, their gradients gc and its densities rk (Eq. 7 with C_kl of Eq. 6).
-__device__ __forceinline__ void stress19(const double (&gc)[3][3], const double (&cc)[3], const double (&rk)[3],
-                                         const KParams& kp, double (&t)[6], double (&nrm)[9])
+template <typename C>
+__device__ __forceinline__ void stress19(const C (&gc)[3][3], const C (&cc)[3], const C (&rk)[3], const KParams& kp,
+                                         C (&t)[6], C (&nrm)[9])
 {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) t[q] = 0.0;
+    for (int q = 0; q < 6; ++q) t[q] = C(0);
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         const int k = PK3[p], l = PL3[p];
-        double G[3];
+        C G[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) G[a] = cc[l] * gc[k][a] - cc[k] * gc[l][a];
-        const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
-        double n[3] = {0.0, 0.0, 0.0};
-        if (g2 > kp.guard * kp.guard) {
-            const double m = sqrt(g2), im = 1.0 / m;
+        const C g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+        C n[3] = {C(0), C(0), C(0)};
+        if (g2 > C(kp.guard * kp.guard)) {
+            const C m = sqrt(g2), im = C(1) / m;
 #pragma unroll
             for (int a = 0; a < 3; ++a) n[a] = G[a] * im;
-            double cf = kp.cfac[p] * (rk[k] * rk[l]);
-            cf = cf < 1.0 ? cf : 1.0;
-            const double s = kp.sigma[p] * cf * m;  // sigma C |G| (I - n n)
-            t[0] += s * (1.0 - n[0] * n[0]);
+            C cf = C(kp.cfac[p]) * (rk[k] * rk[l]);
+            cf = cf < C(1) ? cf : C(1);
+            const C s = C(kp.sigma[p]) * cf * m;  // sigma C |G| (I - n n)
+            t[0] += s * (C(1) - n[0] * n[0]);
             t[1] -= s * (n[0] * n[1]);
             t[2] -= s * (n[0] * n[2]);
-            t[3] += s * (1.0 - n[1] * n[1]);
+            t[3] += s * (C(1) - n[1] * n[1]);
             t[4] -= s * (n[1] * n[2]);
-            t[5] += s * (1.0 - n[2] * n[2]);
+            t[5] += s * (C(1) - n[2] * n[2]);
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) nrm[3 * p + a] = n[a];
@@ -146,17 +163,17 @@ __device__ __forceinline__ void stress19(const double (&gc)[3][3], const double 
 
 // F_b = sum_a d_a T_ab with the symmetric T stored as (xx, xy, xz, yy, yz, zz);
 // T(q, dx, dy, dz) is component q at offset (dx, dy, dz) from the node
-template <typename Get>
-__device__ __forceinline__ void force19(Get T, double (&F)[3])
+template <typename C, typename Get>
+__device__ __forceinline__ void force19(Get T, C (&F)[3])
 {
     constexpr int Q[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
-    F[0] = F[1] = F[2] = 0.0;
+    F[0] = F[1] = F[2] = C(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            double d[3];
-            grad19([&](int dx, int dy, int dz) { return T(Q[a][b], dx, dy, dz); }, d);
+            C d[3];
+            grad19<C>([&](int dx, int dy, int dz) { return T(Q[a][b], dx, dy, dz); }, d);
             F[b] += d[a];
         }
 }
@@ -165,67 +182,67 @@ __device__ __forceinline__ void force19(Get T, double (&F)[3])
 // law) of one node from its densities rk, totals ft, force F and pair normals nrm.  With OBS
 // the node's observables go to acc (rho_k, rho u, kinetic energy, |u|); otherwise every
 // recoloured population is handed to put(k, i, value).
-template <bool OBS, typename Put>
-__device__ __forceinline__ void collide19(const double (&rk)[3], const double (&ft)[19], const double (&F)[3],
-                                          const double (&nrm)[9], const KParams& kp, double (&acc)[8], Put put)
+template <typename C, bool OBS, typename Put>
+__device__ __forceinline__ void collide19(const C (&rk)[3], const C (&ft)[19], const C (&F)[3], const C (&nrm)[9],
+                                          const KParams& kp, double (&acc)[8], Put put)
 {
-    const double rho = rk[0] + rk[1] + rk[2], irho = 1.0 / rho;
-    double m[3] = {0, 0, 0};
+    const C rho = rk[0] + rk[1] + rk[2], irho = C(1) / rho;
+    C m[3] = {C(0), C(0), C(0)};
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
         if (L3X[i] != 0) m[0] += L3X[i] > 0 ? ft[i] : -ft[i];
         if (L3Y[i] != 0) m[1] += L3Y[i] > 0 ? ft[i] : -ft[i];
         if (L3Z[i] != 0) m[2] += L3Z[i] > 0 ? ft[i] : -ft[i];
     }
-    double u[3], uu = 0.0, uF = 0.0;
+    C u[3], uu = C(0), uF = C(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        u[a] = (m[a] + 0.5 * F[a]) * irho;
+        u[a] = (m[a] + C(0.5) * F[a]) * irho;
         uu += u[a] * u[a];
         uF += u[a] * F[a];
     }
     if constexpr (OBS) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) acc[k] += rk[k];
+        for (int k = 0; k < 3; ++k) acc[k] += double(rk[k]);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) acc[3 + a] += rho * u[a];
-        acc[6] += 0.5 * rho * uu;
-        const double um = sqrt(uu);
+        for (int a = 0; a < 3; ++a) acc[3 + a] += double(rho * u[a]);
+        acc[6] += 0.5 * double(rho) * double(uu);
+        const double um = sqrt(double(uu));
         acc[7] = (um > acc[7] || um != um) ? um : acc[7];
     } else {
         // tau = 3 nu + 1/2 with rho / nu = sum_k rho_k / nu_k (Eqs. 10-11)
-        const double rho_over_nu = rk[0] * kp.inv_nu[0] + rk[1] * kp.inv_nu[1] + rk[2] * kp.inv_nu[2];
-        const double itau = rho_over_nu / (3.0 * rho + 0.5 * rho_over_nu);
-        const double pref = 1.0 - 0.5 * itau;
+        const C rho_over_nu = rk[0] * C(kp.inv_nu[0]) + rk[1] * C(kp.inv_nu[1]) + rk[2] * C(kp.inv_nu[2]);
+        const C itau = rho_over_nu / (C(3) * rho + C(0.5) * rho_over_nu);
+        const C pref = C(1) - C(0.5) * itau;
         // C_t and beta_kl of the segregation law; a_p = beta_p rho_k rho_l / rho
-        double ct = kp.ct_coef * rk[0] * rk[1] * rk[2] * (irho * irho * irho);
-        ct = ct < 1.0 ? ct : 1.0;
-        double ap[3];
+        C ct = C(kp.ct_coef) * rk[0] * rk[1] * rk[2] * (irho * irho * irho);
+        ct = ct < C(1) ? ct : C(1);
+        C ap[3];
 #pragma unroll
-        for (int p = 0; p < 3; ++p) ap[p] = kp.beta0 * (1.0 + ct * kp.g[p]) * (rk[PK3[p]] * rk[PL3[p]]) * irho;
+        for (int p = 0; p < 3; ++p) ap[p] = C(kp.beta0) * (C(1) + ct * C(kp.g[p])) * (rk[PK3[p]] * rk[PL3[p]]) * irho;
         // V_k = sum_{l != k} a_kl n_kl (n_lk = -n_kl)
-        double V[3][3];
+        C V[3][3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double n0 = nrm[0 + a], n1 = nrm[3 + a], n2 = nrm[6 + a];
+            const C n0 = nrm[0 + a], n1 = nrm[3 + a], n2 = nrm[6 + a];
             V[0][a] = ap[0] * n0 + ap[1] * n1;
             V[1][a] = ap[2] * n2 - ap[0] * n0;
             V[2][a] = -(ap[1] * n1 + ap[2] * n2);
         }
-        double ck[3];
+        C ck[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) ck[k] = rk[k] * irho;
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-            const double eu = edot(i, u[0], u[1], u[2]);
-            const double eF = edot(i, F[0], F[1], F[2]);
-            const double feq = w19(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-            const double phi = w19(i) * pref * (3.0 * (eF - uF) + 9.0 * eu * eF);
-            const double fd = ft[i] - (ft[i] - feq) * itau + phi;
+            const C eu = edot<C>(i, u[0], u[1], u[2]);
+            const C eF = edot<C>(i, F[0], F[1], F[2]);
+            const C feq = w19<C>(i) * rho * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
+            const C phi = w19<C>(i) * pref * (C(3) * (eF - uF) + C(9) * eu * eF);
+            const C fd = ft[i] - (ft[i] - feq) * itau + phi;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const double ve = edot(i, V[k][0], V[k][1], V[k][2]);
-                put(k, i, ck[k] * fd + w19(i) * ve);
+                const C ve = edot<C>(i, V[k][0], V[k][1], V[k][2]);
+                put(k, i, ck[k] * fd + w19<C>(i) * ve);
             }
             // each link's values leave before the next link's are formed (otherwise the
             // compiler holds all 57 for one burst of stores)
@@ -259,18 +276,23 @@ struct Tile3 {
 constexpr int kTS = (kTX - 2) * (kTY - 2);  // lanes that form the stress
 constexpr int kTP = (kTX - 4) * (kTY - 4);  // lanes that own output nodes
 
+template <typename C>
 struct alignas(16) March3Lds {
-    double c[3][3][kT3];     // c_k by plane mod 3
-    double T[3][6][kTS];     // stress by plane mod 3, on the stress lanes
-    double park[19][kTP];    // per owning lane: the totals f_i of one waiting plane
+    C c[3][3][kT3];     // c_k by plane mod 3
+    C T[3][6][kTS];     // stress by plane mod 3, on the stress lanes
+    C park[19][kTP];    // per owning lane: the totals f_i of one waiting plane
 };
 
-template <bool OBS>
-__global__ __launch_bounds__(kT3) __attribute__((amdgpu_waves_per_eu(2))) void k3_march(const double* __restrict__ B, Geo3 g, KParams kp,
-                                                const Tile3* __restrict__ tiles, double* __restrict__ Bout,
-                                                double* __restrict__ partials)
+// S: storage type, C: compute type.  With FP32 storage of FP64 arithmetic each stored value
+// is rounded stochastically with the random bits of its node (key: node index and the
+// step's salt), in store order.
+template <typename S, typename C, bool OBS>
+__global__ __launch_bounds__(kT3) __attribute__((amdgpu_waves_per_eu(2))) void k3_march(
+    const S* __restrict__ B, Geo3 g, KParams kp, const Tile3* __restrict__ tiles, S* __restrict__ Bout,
+    double* __restrict__ partials, uint32_t salt)
 {
-    __shared__ March3Lds L;
+    static_assert(sizeof(double) * 8 * (kT3 / 64) <= sizeof(C) * 3 * 3 * kT3, "c ring too small for the reduction");
+    __shared__ March3Lds<C> L;
     const Tile3 tl = tiles[blockIdx.x];
     const int t = threadIdx.x, tx = t % kTX, ty = t / kTX;
     const bool in1 = tx <= tl.cols + 3 && ty <= tl.rows + 3;
@@ -294,42 +316,42 @@ __global__ __launch_bounds__(kT3) __attribute__((amdgpu_waves_per_eu(2))) void k
     // them are live at a time: the one pulled (ft), the one waiting (W) and the one collided
     // (ftB).  Each owning lane parks one of them in LDS (its own slots, so no barrier is
     // involved): after the pull, ftB comes out of the park, W goes in, and ft becomes W.
-    double W[19], rA[3], rB[3], nB[9];
+    C W[19], rA[3], rB[3], nB[9];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) W[i] = 0.0;
+    for (int i = 0; i < 19; ++i) W[i] = C(0);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) rA[k] = rB[k] = 1.0;
+    for (int k = 0; k < 3; ++k) rA[k] = rB[k] = C(1);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) nB[q] = 0.0;
+    for (int q = 0; q < 9; ++q) nB[q] = C(0);
     const int J = tl.depth + 4;
     // plane offset of plane z (wrapped) and the source of link i for planes zo[]
     auto zoff = [&](int z) { return (uint32_t)wrap(z, g.nz) * pl; };
     auto src = [&](const uint32_t (&zo)[3], int i) {
-        return (zo[1 - L3Z[i]] + yo[1 - L3Y[i]] + xo[1 - L3X[i]]) * 8u;
+        return (zo[1 - L3Z[i]] + yo[1 - L3Y[i]] + xo[1 - L3X[i]]) * (uint32_t)sizeof(S);
     };
 #pragma unroll 1
     for (int j = 0; j < J; ++j) {
         const int zc = wrap(tl.z0 - 2 + j, g.nz);
         const int s0 = j % 3, s1 = (j + 2) % 3, s2 = (j + 1) % 3;  // planes zc, zc - 1, zc - 2
         // ---- stage 1: pull of plane zc
-        double ft[19], rk[3] = {1.0, 1.0, 1.0};
+        C ft[19], rk[3] = {C(1), C(1), C(1)};
 #pragma unroll
-        for (int i = 0; i < 19; ++i) ft[i] = 0.0;
+        for (int i = 0; i < 19; ++i) ft[i] = C(0);
         if (in1) {
             // two memory round trips per plane: fluids 0 and 1 (38 loads in flight), then
             // fluid 2; scheduling barriers keep the compiler from interleaving loads and sums
             // (which serialises the loads) or from overlapping the batches (more registers
             // than a lane has at two waves per SIMD)
             const uint32_t zo[3] = {zoff(zc - 1), zoff(zc), zoff(zc + 1)};
-            double v[38];
+            C v[38];
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
                 const uint32_t o = src(zo, i);
-                v[i] = ld_plane(B + (int64_t)i * g.N, o);
-                v[19 + i] = ld_plane(B + (int64_t)(19 + i) * g.N, o);
+                v[i] = C(ld_plane(B + (int64_t)i * g.N, o));
+                v[19 + i] = C(ld_plane(B + (int64_t)(19 + i) * g.N, o));
             }
             __builtin_amdgcn_sched_barrier(0);
-            rk[0] = rk[1] = rk[2] = 0.0;
+            rk[0] = rk[1] = rk[2] = C(0);
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
                 ft[i] = v[i] + v[19 + i];
@@ -338,20 +360,20 @@ __global__ __launch_bounds__(kT3) __attribute__((amdgpu_waves_per_eu(2))) void k
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int i = 0; i < 19; ++i) v[i] = ld_plane(B + (int64_t)(38 + i) * g.N, src(zo, i));
+            for (int i = 0; i < 19; ++i) v[i] = C(ld_plane(B + (int64_t)(38 + i) * g.N, src(zo, i)));
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
                 ft[i] += v[i];
                 rk[2] += v[i];
             }
-            const double ir = 1.0 / (rk[0] + rk[1] + rk[2]);
+            const C ir = C(1) / (rk[0] + rk[1] + rk[2]);
 #pragma unroll
             for (int k = 0; k < 3; ++k) L.c[s0][k][t] = rk[k] * ir;
         }
-        double ftB[19];
+        C ftB[19];
 #pragma unroll
-        for (int i = 0; i < 19; ++i) ftB[i] = 0.0;
+        for (int i = 0; i < 19; ++i) ftB[i] = C(0);
         if (in3) {
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
@@ -363,18 +385,18 @@ __global__ __launch_bounds__(kT3) __attribute__((amdgpu_waves_per_eu(2))) void k
         for (int i = 0; i < 19; ++i) W[i] = ft[i];
         __syncthreads();
         // ---- stage 2: stress of plane zc - 1
-        double nA[9];
+        C nA[9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) nA[q] = 0.0;
+        for (int q = 0; q < 9; ++q) nA[q] = C(0);
         if (j >= 2 && in2) {
             const int sl[3] = {s2, s1, s0};  // by dz + 1
-            double gc[3][3], cc[3], tt[6];
+            C gc[3][3], cc[3], tt[6];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                grad19([&](int dx, int dy, int dz) { return L.c[sl[dz + 1]][k][t + dy * kTX + dx]; }, gc[k]);
+                grad19<C>([&](int dx, int dy, int dz) { return L.c[sl[dz + 1]][k][t + dy * kTX + dx]; }, gc[k]);
                 cc[k] = L.c[s1][k][t];
             }
-            stress19(gc, cc, rA, kp, tt, nA);
+            stress19<C>(gc, cc, rA, kp, tt, nA);
 #pragma unroll
             for (int q = 0; q < 6; ++q) L.T[s1][q][tS] = tt[q];
         }
@@ -382,12 +404,15 @@ __global__ __launch_bounds__(kT3) __attribute__((amdgpu_waves_per_eu(2))) void k
         // ---- stage 3: collision and recolouring of plane zc - 2
         if (j >= 4 && in3) {
             const int sl[3] = {s0, s2, s1};  // T of planes zc - 3, zc - 2, zc - 1 by dz + 1
-            double F[3];
-            force19([&](int q, int dx, int dy, int dz) { return L.T[sl[dz + 1]][q][tS + dy * (kTX - 2) + dx]; },
-                    F);
-            const uint32_t o = ((uint32_t)(tl.z0 - 4 + j) * pl + yo[1] + (uint32_t)x) * 8u;
-            collide19<OBS>(rB, ftB, F, nB, kp, acc,
-                           [&](int k, int i, double v) { st_plane(Bout + (int64_t)(k * 19 + i) * g.N, o, v); });
+            C F[3];
+            force19<C>([&](int q, int dx, int dy, int dz) { return L.T[sl[dz + 1]][q][tS + dy * (kTX - 2) + dx]; },
+                       F);
+            const uint32_t node = (uint32_t)(tl.z0 - 4 + j) * pl + yo[1] + (uint32_t)x;
+            const uint32_t o = node * (uint32_t)sizeof(S);
+            NodeBits bits(node * 57u ^ salt);
+            collide19<C, OBS>(rB, ftB, F, nB, kp, acc, [&](int k, int i, C v) {
+                st_plane(Bout + (int64_t)(k * 19 + i) * g.N, o, to_storage<S, C>(v, bits));
+            });
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -403,7 +428,7 @@ __global__ __launch_bounds__(kT3) __attribute__((amdgpu_waves_per_eu(2))) void k
         __syncthreads();
         for (int q = 0; q < 7; ++q) acc[q] = wave_sum(acc[q]);
         acc[7] = wave_max(acc[7]);
-        double* red = &L.c[0][0][0];
+        double* red = reinterpret_cast<double*>(&L.c[0][0][0]);
         constexpr int W = kT3 / 64;
         if ((t & 63) == 0)
             for (int q = 0; q < 8; ++q) red[q * W + (t >> 6)] = acc[q];
@@ -442,7 +467,8 @@ __device__ __forceinline__ bool node3(const Geo3& g, int& x, int& y, int& z)
 }
 
 // B_{i,k}(y) = w_i rho_k(y + e_i): the pulled state is f_{i,k} = w_i rho_k (fluid at rest)
-__global__ __launch_bounds__(256) void k3_init(const double* __restrict__ rho, Geo3 g, double* __restrict__ B)
+template <typename S, typename C>
+__global__ __launch_bounds__(256) void k3_init(const double* __restrict__ rho, Geo3 g, S* __restrict__ B)
 {
     int x, y, z;
     if (!node3(g, x, y, z)) return;
@@ -452,12 +478,13 @@ __global__ __launch_bounds__(256) void k3_init(const double* __restrict__ rho, G
     for (int i = 0; i < 19; ++i) {
         const int64_t src = nb.at(L3X[i], L3Y[i], L3Z[i]);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) B[(int64_t)(k * 19 + i) * g.N + j] = w19(i) * rho[k * g.N + src];
+        for (int k = 0; k < 3; ++k) B[(int64_t)(k * 19 + i) * g.N + j] = S(w19<C>(i) * C(rho[k * g.N + src]));
     }
 }
 
 // the post-streaming populations [3][19][N] and densities [3][N] of the state
-__global__ __launch_bounds__(256) void k3_export(const double* __restrict__ B, Geo3 g, double* __restrict__ fout,
+template <typename S>
+__global__ __launch_bounds__(256) void k3_export(const S* __restrict__ B, Geo3 g, double* __restrict__ fout,
                                                  double* __restrict__ rho)
 {
     int x, y, z;
@@ -486,7 +513,8 @@ struct lbm3d {
     KParams kp{};
     Geo3 g{};
     hipStream_t stream = nullptr;
-    double* buf[2] = {nullptr, nullptr};
+    Prec prec = Prec::F64;
+    void* buf[2] = {nullptr, nullptr};  // the state, in the storage type of prec
     Tile3* dtiles = nullptr;     // the march's tile list
     int ntiles = 0;
     double* partials = nullptr;  // [ntiles][8]
@@ -502,7 +530,7 @@ static dim3 grid3(const Geo3& g) { return dim3((unsigned)((g.N + 255) / 256)); }
 static void release3(lbm3d* h)
 {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    for (double* q : {h->buf[0], h->buf[1], h->partials, h->staging, h->rho})
+    for (void* q : {h->buf[0], h->buf[1], (void*)h->partials, (void*)h->staging, (void*)h->rho})
         if (q) (void)hipFree(q);
     if (h->dtiles) (void)hipFree(h->dtiles);
 }
@@ -556,15 +584,67 @@ static std::vector<Tile3> plan3(const Geo3& g, int slots)
     return out;
 }
 
+template <typename S, typename C>
+static hipError_t launch_march_t(lbm3d* h, bool obs)
+{
+    const S* in = (const S*)h->buf[h->cur];
+    const uint32_t salt = step_salt(h->step);
+    if (obs)
+        hipLaunchKernelGGL((k3_march<S, C, true>), dim3(h->ntiles), dim3(kT3), 0, h->stream, in, h->g, h->kp,
+                           (const Tile3*)h->dtiles, (S*)nullptr, h->partials, 0u);
+    else
+        hipLaunchKernelGGL((k3_march<S, C, false>), dim3(h->ntiles), dim3(kT3), 0, h->stream, in, h->g, h->kp,
+                           (const Tile3*)h->dtiles, (S*)h->buf[h->cur ^ 1], (double*)nullptr, salt);
+    return hipGetLastError();
+}
+
 static hipError_t launch_march(lbm3d* h, bool obs)
 {
-    const double* in = h->buf[h->cur];
-    if (obs)
-        hipLaunchKernelGGL((k3_march<true>), dim3(h->ntiles), dim3(kT3), 0, h->stream, in, h->g, h->kp,
-                           (const Tile3*)h->dtiles, (double*)nullptr, h->partials);
+    switch (h->prec) {
+        case Prec::F64: return launch_march_t<double, double>(h, obs);
+        case Prec::F32S: return launch_march_t<float, double>(h, obs);
+        case Prec::F32: return launch_march_t<float, float>(h, obs);
+    }
+    return hipErrorInvalidValue;
+}
+
+static hipError_t march_occupancy(Prec prec, int* per_cu)
+{
+    switch (prec) {
+        case Prec::F64:
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k3_march<double, double, false>, kT3, 0);
+        case Prec::F32S:
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k3_march<float, double, false>, kT3, 0);
+        case Prec::F32:
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k3_march<float, float, false>, kT3, 0);
+    }
+    return hipErrorInvalidValue;
+}
+
+static hipError_t launch_init3(lbm3d* h, const double* rho)
+{
+    const dim3 gr = grid3(h->g), bl(256);
+    switch (h->prec) {
+        case Prec::F64:
+            hipLaunchKernelGGL((k3_init<double, double>), gr, bl, 0, h->stream, rho, h->g, (double*)h->buf[0]);
+            break;
+        case Prec::F32S:
+            hipLaunchKernelGGL((k3_init<float, double>), gr, bl, 0, h->stream, rho, h->g, (float*)h->buf[0]);
+            break;
+        case Prec::F32:
+            hipLaunchKernelGGL((k3_init<float, float>), gr, bl, 0, h->stream, rho, h->g, (float*)h->buf[0]);
+            break;
+    }
+    return hipGetLastError();
+}
+
+static hipError_t launch_export3(lbm3d* h, double* fout, double* rho)
+{
+    const dim3 gr = grid3(h->g), bl(256);
+    if (h->prec == Prec::F64)
+        hipLaunchKernelGGL((k3_export<double>), gr, bl, 0, h->stream, (const double*)h->buf[h->cur], h->g, fout, rho);
     else
-        hipLaunchKernelGGL((k3_march<false>), dim3(h->ntiles), dim3(kT3), 0, h->stream, in, h->g, h->kp,
-                           (const Tile3*)h->dtiles, h->buf[h->cur ^ 1], (double*)nullptr);
+        hipLaunchKernelGGL((k3_export<float>), gr, bl, 0, h->stream, (const float*)h->buf[h->cur], h->g, fout, rho);
     return hipGetLastError();
 }
 
@@ -587,10 +667,6 @@ int lbm3d_create(const lbm3_params* p, int32_t nz, void* hip_stream, lbm3d_t** o
         set_error("the D3Q19 form takes at most 2^29 nodes (got %d x %d x %d)", (int)p->nx, (int)p->ny, nz);
         return LBM3_EINVAL;
     }
-    if (p->precision != LBM3_FP64) {
-        set_error("the D3Q19 form is provided in LBM3_FP64 only");
-        return LBM3_EUNSUPPORTED;
-    }
     if (p->forcing != LBM3_FORCING_GUO) {
         set_error("the D3Q19 form runs the force of Eq. (7) with Guo's term only");
         return LBM3_EUNSUPPORTED;
@@ -601,6 +677,7 @@ int lbm3d_create(const lbm3_params* p, int32_t nz, void* hip_stream, lbm3d_t** o
         return LBM3_ENOMEM;
     }
     h->p = *p;
+    h->prec = prec_of(p->precision);
     derive(p, &h->kp, nullptr, nullptr, nullptr);
     h->g = Geo3{p->nx, p->ny, nz, (int64_t)p->nx * p->ny * nz};
     h->stream = (hipStream_t)hip_stream;
@@ -609,13 +686,14 @@ int lbm3d_create(const lbm3_params* p, int32_t nz, void* hip_stream, lbm3d_t** o
     int dev = 0, cus = 0, per_cu = 0;
     e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k3_march<false>, kT3, 0);
+    if (e == hipSuccess) e = march_occupancy(h->prec, &per_cu);
     std::vector<Tile3> tiles;
     if (e == hipSuccess) {
         tiles = plan3(h->g, per_cu * cus);
         h->ntiles = (int)tiles.size();
     }
-    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMalloc(&h->buf[b], (size_t)57 * N * sizeof(double));
+    const size_t eb = h->prec == Prec::F64 ? sizeof(double) : sizeof(float);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMalloc(&h->buf[b], (size_t)57 * N * eb);
     if (e == hipSuccess) e = hipMalloc(&h->dtiles, tiles.size() * sizeof(Tile3));
     if (e == hipSuccess)
         e = hipMemcpy(h->dtiles, tiles.data(), tiles.size() * sizeof(Tile3), hipMemcpyHostToDevice);
@@ -643,9 +721,7 @@ int lbm3d_init_fields(lbm3d_t* h, const double* rho)
     if (rc) return rc;
     hipError_t e = hipMemcpyAsync(h->staging, rho, (size_t)3 * N * sizeof(double), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k3_init, grid3(h->g), dim3(256), 0, h->stream, (const double*)h->staging, h->g,
-                           h->buf[0]);
-        e = hipGetLastError();
+        e = launch_init3(h, (const double*)h->staging);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "D3Q19 init");
@@ -692,9 +768,7 @@ int lbm3d_observables(lbm3d_t* h, lbm3d_obs* out, double* rho_out, double* f_out
     if (e == hipSuccess)
         e = hipMemcpyAsync(part.data(), h->partials, part.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess && (rho_out || f_out)) {
-        hipLaunchKernelGGL(k3_export, gr, dim3(256), 0, h->stream, (const double*)h->buf[h->cur], h->g,
-                           f_out ? h->staging : nullptr, h->rho);
-        e = hipGetLastError();
+        e = launch_export3(h, f_out ? h->staging : nullptr, h->rho);
         if (e == hipSuccess && rho_out)
             e = hipMemcpyAsync(rho_out, h->rho, (size_t)3 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
         if (e == hipSuccess && f_out)

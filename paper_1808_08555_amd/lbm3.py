@@ -408,12 +408,14 @@ class Lattice:
 
 # ----------------------------------------------------------------- D3Q19 form
 class Lattice3D:
-    """Owning wrapper around one lbm3d handle (the D3Q19 form, FP64, periodic)."""
+    """Owning wrapper around one lbm3d handle (the D3Q19 form, periodic; precision "fp64",
+    "fp32_storage" or "fp32")."""
 
     def __init__(self, nx: int, ny: int, nz: int, sigma=(0.01, 0.01, 0.01), tau=(1.0, 1.0, 1.0),
-                 rho0=(1.0, 1.0, 1.0), beta0: float = 0.7, beta_law="paper", stream=None):
+                 rho0=(1.0, 1.0, 1.0), beta0: float = 0.7, beta_law="paper", stream=None,
+                 precision: str = "fp64"):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
-        self.params = make_params(nx, ny, sigma, tau, rho0, beta0, "fp64", beta_law=beta_law)
+        self.params = make_params(nx, ny, sigma, tau, rho0, beta0, precision, beta_law=beta_law)
         h = ctypes.c_void_p()
         _check(lib().lbm3d_create(ctypes.byref(self.params), self.nz, _stream_handle(stream), ctypes.byref(h)),
                "lbm3d_create")
