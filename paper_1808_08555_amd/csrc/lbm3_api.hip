@@ -443,13 +443,11 @@ int lbm3_create(const lbm3_params* p, void* hip_stream, lbm3_t** out)
         return rc;
     }
     const size_t bytes = (size_t)h->kp.span * elem_bytes(h->prec);
-    for (int b = 0; b < 2; ++b) {
-        e = hipMalloc(&h->buf[b], bytes);
-        if (e != hipSuccess) {
-            rc = hip_fail(e, "hipMalloc(populations)");
-            lbm3_destroy(h);
-            return rc;
-        }
+    e = alloc_state_pair(bytes, h->buf);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "hipMalloc(populations)");
+        lbm3_destroy(h);
+        return rc;
     }
     e = hipMalloc((void**)&h->obs_dev, kObsFields * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc((void**)&h->obs_host, kObsFields * sizeof(double));
@@ -616,8 +614,7 @@ int lbm3_destroy(lbm3_t* h)
 {
     if (!h) return LBM3_OK;
     (void)hipStreamSynchronize(h->stream);
-    for (int b = 0; b < 2; ++b)
-        if (h->buf[b]) (void)hipFree(h->buf[b]);
+    free_state_pair(h->buf);
     if (h->staging) (void)hipFree(h->staging);
     if (h->partials) (void)hipFree(h->partials);
     if (h->obs_dev) (void)hipFree(h->obs_dev);

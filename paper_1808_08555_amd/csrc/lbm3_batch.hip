@@ -229,8 +229,7 @@ int lbm3_batch_destroy(lbm3_batch_t* b)
     if (!b) return LBM3_OK;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graphs(b);
-    for (int i = 0; i < 2; ++i)
-        if (b->buf[i]) (void)hipFree(b->buf[i]);
+    free_state_pair(b->buf);
     if (b->dinst) (void)hipFree(b->dinst);
     if (b->dtiles) (void)hipFree(b->dtiles);
     if (b->dtiles2) (void)hipFree(b->dtiles2);
@@ -297,7 +296,7 @@ int lbm3_batch_create(const lbm3_params* p, int32_t count, void* hip_stream, lbm
         b->own_stream = e == hipSuccess;
     }
     const size_t bytes = (size_t)total * elem_bytes(b->prec);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc(&b->buf[i], bytes);
+    if (e == hipSuccess) e = alloc_state_pair(bytes, b->buf);
     if (e == hipSuccess) e = hipMalloc((void**)&b->dinst, count * sizeof(Instance));
     if (e == hipSuccess)
         e = hipMemcpy(b->dinst, b->inst.data(), count * sizeof(Instance), hipMemcpyHostToDevice);

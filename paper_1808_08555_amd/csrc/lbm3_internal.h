@@ -17,7 +17,7 @@ struct KParams {
     int32_t nx, ny;
     int64_t plane;      // elements between the same node in consecutive planes
     int64_t pitch;      // row pitch of the 27-population layout (27 planes, rows interleaved)
-    int64_t fpitch;     // row pitch of the factored layout (18 planes, rows interleaved)
+    int64_t fpitch;     // row pitch of the factored layout (16 planes, rows interleaved)
     int64_t span;       // elements of one state buffer (room for 27 planes)
     double sigma[3];    // sigma_kl per pair
     double g[3];        // g_kl of the segregation law: beta_kl = beta0 (1 + s g_kl)
@@ -111,6 +111,10 @@ void plan_lattice(int inst, int nx, int ny, int threads, int rows, int elem_byte
 // receives one contiguous run of it, keeping neighbouring tiles, and the halos they share, in
 // the same L2.
 std::vector<Tile> xcd_order(const std::vector<Tile>& L, int nxcd);
+// The two state buffers of a step (read one, write the other) in one allocation, the second
+// an odd number of MiB after the first (see lbm3_plan.hip); buf[1] is not freed on its own.
+hipError_t alloc_state_pair(size_t bytes, void* buf[2]);
+void free_state_pair(void* buf[2]);
 // Rows per segment that fit the tile count to the resident workgroup slots.
 int auto_rows(int nx, int ny, int threads, int slots, int elem_bytes, int halo = 3);
 int device_slots(Prec prec, int threads);

@@ -13,12 +13,13 @@ void plan_lattice(int inst, int nx, int ny, int threads, int rows, int elem_byte
     // Aligned strips: widths in units of A elements and strips starting at x = halo (mod A), so
     // that lane 0 of every wavefront (column x0 - halo + 64 w) sits on a unit boundary.  Used
     // when nx is a multiple of A and a unit-aligned strip width fits the workgroup.  The
-    // single step takes 128-byte units (one cache line).  The two-step pass (halo 6, one
-    // workgroup per CU) takes 32-byte units, which lets the strips fill the device: at 4096
-    // FP64 columns 17 strips of 240-244 columns give 255 workgroups for 256 CUs, where
-    // line-aligned strips of at most 240 columns need 18 strips and leave 252 (measured 3.7%
-    // faster).
-    const int A = (halo == 6 ? 32 : 128) / elem_bytes;
+    // single step takes 128-byte units (one cache line).  The two-step pass (halo 6) takes
+    // units of four columns (32 bytes in FP64, 16 in FP32), which lets the strips fill the
+    // device: at 4096 columns 17 strips of 240-244 columns give 255 workgroups for 256 CUs
+    // (one per CU), where line-aligned strips of at most 240 columns need 18 strips and leave
+    // 252 (measured: FP64 3.7% faster; FP32 storage 7% and FP32 5% faster than with
+    // eight-column units).
+    const int A = halo == 6 ? 4 : 128 / elem_bytes;
     const int wA = wmax / A * A;
     const bool aligned = nx % A == 0 && wA >= A && nx > 2 * halo;
     const int nstrips = aligned ? (nx / A + wA / A - 1) / (wA / A) : (nx + wmax - 1) / wmax;
@@ -63,6 +64,31 @@ std::vector<Tile> xcd_order(const std::vector<Tile>& L, int nxcd)
         out[b] = L[start[x] + k];
     }
     return out;
+}
+
+// A step reads one state buffer and writes the other at the same offsets at the same time.
+// With the two an even number of MiB apart (what two separate allocations of a size that is
+// a multiple of 2 MiB give), the FP64 two-step pass ran at 29.0k MLUPS at 4096^2; an odd
+// number of MiB apart, at 30.0k, in every run (measured with distances of the buffer size
+// plus 0, 64 KiB, 1, 2 and 3 MiB): the concurrent read and write streams then fall on
+// different HBM channels.
+hipError_t alloc_state_pair(size_t bytes, void* buf[2])
+{
+    constexpr size_t MiB = (size_t)1 << 20;
+    const size_t off = (bytes + 2 * MiB - 1) / (2 * MiB) * (2 * MiB) + MiB;
+    buf[0] = buf[1] = nullptr;
+    void* base = nullptr;
+    hipError_t e = hipMalloc(&base, off + bytes);
+    if (e != hipSuccess) return e;
+    buf[0] = base;
+    buf[1] = (char*)base + off;
+    return hipSuccess;
+}
+
+void free_state_pair(void* buf[2])
+{
+    if (buf[0]) (void)hipFree(buf[0]);
+    buf[0] = buf[1] = nullptr;
 }
 
 int auto_rows(int nx, int ny, int threads, int slots, int elem_bytes, int halo)

@@ -765,14 +765,15 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
     }
 }
 
-// Two fused steps per pass (factored state in and out; storage type = compute type), each
-// step on its own waves of the workgroup.  Step A (lanes 0..NT-1 of the workgroup) pulls its
-// source rows from global memory as march() does; the rows it recolours never leave the
-// chip: it writes them, all 18 values, to an LDS exchange row xB, from which step B (lanes
-// NT..2NT-1) pulls them; only B's rows are stored.  HBM traffic per step is half that of
-// march(), and the arithmetic is march()'s, so the result equals two single steps bit for
-// bit.  Each wave holds one step's registers, so two waves fit on a SIMD where one thread
-// carrying both steps would not.
+// Two fused steps per pass (factored state in and out; FP64 arithmetic, FP64 or FP32
+// storage), each step on its own waves of the workgroup.  Step A (lanes 0..NT-1 of the
+// workgroup) pulls its source rows from global memory as march() does; the rows it recolours
+// never leave the chip: it writes them (the 16 stored values and V_2, rounded as a store
+// would round them) to an LDS exchange row xB, from which step B (lanes NT..2NT-1) pulls
+// them; only B's rows are stored.  HBM traffic per step is half that of march(), and the
+// arithmetic is march()'s, so the result equals two single steps bit for bit.  Each wave
+// holds one step's registers, so two waves fit on a SIMD where one thread carrying both
+// steps would not.
 //
 // Lane t of either step sits on column x0 - 6 + t.  A forms densities on lanes 1..cols+10
 // and recolours lanes 3..cols+8 (B's source columns); B forms densities on lanes 4..cols+7

@@ -530,7 +530,8 @@ static dim3 grid3(const Geo3& g) { return dim3((unsigned)((g.N + 255) / 256)); }
 static void release3(lbm3d* h)
 {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    for (void* q : {h->buf[0], h->buf[1], (void*)h->partials, (void*)h->staging, (void*)h->rho})
+    free_state_pair(h->buf);
+    for (void* q : {(void*)h->partials, (void*)h->staging, (void*)h->rho})
         if (q) (void)hipFree(q);
     if (h->dtiles) (void)hipFree(h->dtiles);
 }
@@ -693,7 +694,7 @@ int lbm3d_create(const lbm3_params* p, int32_t nz, void* hip_stream, lbm3d_t** o
         h->ntiles = (int)tiles.size();
     }
     const size_t eb = h->prec == Prec::F64 ? sizeof(double) : sizeof(float);
-    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMalloc(&h->buf[b], (size_t)57 * N * eb);
+    if (e == hipSuccess) e = alloc_state_pair((size_t)57 * N * eb, h->buf);
     if (e == hipSuccess) e = hipMalloc(&h->dtiles, tiles.size() * sizeof(Tile3));
     if (e == hipSuccess)
         e = hipMemcpy(h->dtiles, tiles.data(), tiles.size() * sizeof(Tile3), hipMemcpyHostToDevice);
@@ -760,7 +761,6 @@ int lbm3d_observables(lbm3d_t* h, lbm3d_obs* out, double* rho_out, double* f_out
         set_error("lbm3d_observables before lbm3d_init_fields");
         return LBM3_ESTATE;
     }
-    const dim3 gr = grid3(h->g);
     const size_t nblocks = (size_t)h->ntiles;
     const int64_t N = h->g.N;
     hipError_t e = launch_march(h, true);
