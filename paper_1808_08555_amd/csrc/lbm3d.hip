@@ -536,7 +536,7 @@ static void release3(lbm3d* h)
     if (h->dtiles) (void)hipFree(h->dtiles);
 }
 
-// n split into parts of at most `most` (as equal as possible): part q is [start, start + len)
+// n split into `parts` parts as equal as possible: part q is [start, start + len)
 static void split_even(int n, int parts, int q, int& start, int& len)
 {
     const int base = n / parts, extra = n % parts;
