@@ -338,34 +338,25 @@ __global__ __launch_bounds__(kT3) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int i = 0; i < 19; ++i) ft[i] = C(0);
         if (in1) {
-            // two memory round trips per plane: fluids 0 and 1 (38 loads in flight), then
-            // fluid 2; scheduling barriers keep the compiler from interleaving loads and sums
-            // (which serialises the loads) or from overlapping the batches (more registers
-            // than a lane has at two waves per SIMD)
+            // one memory round trip per plane: the 57 loads are issued together, and a
+            // scheduling barrier keeps the compiler from interleaving the sums with them
+            // (which serialises the loads)
             const uint32_t zo[3] = {zoff(zc - 1), zoff(zc), zoff(zc + 1)};
-            C v[38];
+            C v[57];
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
                 const uint32_t o = src(zo, i);
-                v[i] = C(ld_plane(B + (int64_t)i * g.N, o));
-                v[19 + i] = C(ld_plane(B + (int64_t)(19 + i) * g.N, o));
+#pragma unroll
+                for (int k = 0; k < 3; ++k) v[k * 19 + i] = C(ld_plane(B + (int64_t)(k * 19 + i) * g.N, o));
             }
             __builtin_amdgcn_sched_barrier(0);
             rk[0] = rk[1] = rk[2] = C(0);
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
-                ft[i] = v[i] + v[19 + i];
+                ft[i] = v[i] + v[19 + i] + v[38 + i];
                 rk[0] += v[i];
                 rk[1] += v[19 + i];
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int i = 0; i < 19; ++i) v[i] = C(ld_plane(B + (int64_t)(38 + i) * g.N, src(zo, i)));
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int i = 0; i < 19; ++i) {
-                ft[i] += v[i];
-                rk[2] += v[i];
+                rk[2] += v[38 + i];
             }
             const C ir = C(1) / (rk[0] + rk[1] + rk[2]);
 #pragma unroll
