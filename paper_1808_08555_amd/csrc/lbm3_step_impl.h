@@ -782,8 +782,10 @@ __device__ __forceinline__ void march(const S* __restrict__ fin, S* __restrict__
 // pre-roll and three per iteration of a loop of the same length).  Both steps run the same
 // stage in the same phase, so the heavy stages meet at the same barrier:
 //   phase 0: densities (stage 1; B pulls the row A recoloured in the previous iteration)
-//   phase 1: stress (stage 2)
-//   phase 2: force, collision and recolouring (stage 3; A into xB, B to HBM)
+//   phase 1: stress (stage 2; B stores the f_dag_i of its previous output row)
+//   phase 2: force, collision and recolouring (stage 3; A into xB, B's c_k, V_k to HBM)
+// A's global loads and B's stores are placed so that the three phases of the two steps
+// take about as long as each other.
 // Iteration j: A consumes source row y0 - 4 + j and recolours row y0 - 7 + j into xB; B
 // pulls that row in iteration j + 1 and outputs row y0 - 11 + j.
 template <typename C, int NT>
@@ -816,10 +818,15 @@ __device__ __forceinline__ void pair_step_a(const S* __restrict__ fin, const KPa
     const int J = rows + 11;  // one more iteration for B's last row
     // A source row is loaded in two parts: its f_dag_i at this lane's pull columns (pulled by
     // this lane in the next phase 0) and its c_k, V_0, V_1 at this lane's own column (published
-    // to the neighbouring lanes in the next phase 1).  Each part goes into its registers right
-    // after their previous contents were used, so no copy of a prefetched row is kept (the
-    // registers freed hold the 27 exchange fields pull_row reads once).
-    // (the prefetched values stay in the storage type until used)
+    // to the neighbouring lanes in phase 1).  Each part goes into its registers once their
+    // previous contents were used, so no copy of a prefetched row is kept (the registers freed
+    // hold the 27 exchange fields pull_row reads once): the f_dag_i at the end of phase 0,
+    // after the pull, and the c_k, V_k of the row after next at the start of phase 2, after
+    // the publish, a whole iteration before they are published.  Loads issued at the start
+    // of phase 0 queue behind B's stores of the phase before and hold up A's pull, the
+    // longest stage of its iteration (measured: A's phase 0 took 3.6k cycles with the c_k,
+    // V_k loads there against B's 2.2k, and B waited that difference at every iteration).
+    // The prefetched values stay in the storage type until used.
     constexpr int NC = kFacPlanes - 9;
     auto load_fd = [&](int s, S (&v)[9]) {
         const int64_t rowo = (int64_t)s * kp.fpitch;
@@ -874,6 +881,7 @@ __device__ __forceinline__ void pair_step_a(const S* __restrict__ fin, const KPa
         if (a0) load_fd(r, vf);
     }
     publish(vc, 0);
+    if (a0) load_cv(src.r, vc);  // for the loop's first publish
     __syncthreads();
 #pragma unroll 1
     for (int j = 0; j < J; ++j) {
@@ -887,7 +895,6 @@ __device__ __forceinline__ void pair_step_a(const S* __restrict__ fin, const KPa
         if (live) {
             const int r = src.next();
             const bool more = a0 && j + 1 < JA;
-            if (more) load_cv(r, vc);
             if (a1) pull_row<C, NT>([&](int i) { return C(vf[i]); }, L.xA[j & 1], t, d0r, d0f, d1r, d1f, r0, f0);
             if (more) load_fd(r, vf);
             const C irho = recip((r0[0] + r0[1]) + r0[2]);
@@ -905,6 +912,8 @@ __device__ __forceinline__ void pair_step_a(const S* __restrict__ fin, const KPa
         }
         if (j + 1 < JA) publish(vc, (j + 1) & 1);
         __syncthreads();
+        // the c_k, V_k of the row src.next() returns in the next iteration
+        if (a0 && j + 2 < JA) load_cv(src.r, vc);
         if (live && j >= 4 && a3) {
             C Fx, Fy, fd[9], ck[3], V[6], ux, uy, mxh, myh;
             C Tn[3];
@@ -972,6 +981,18 @@ __device__ __forceinline__ void pair_step_b(S* __restrict__ fout, const KParams&
     const int MB = rows + 3;  // last row index m
     const int J = rows + 11;
 
+    // The f_dag_i of an output row are stored at the end of the next iteration's phase 1, its
+    // c_k, V_k at once: B's phase 2 (collision and 16 stores) is the longest phase of the pair
+    // and A waits for it at every iteration (measured 3.5k cycles against A's 2.1-2.5k).
+    S fdp[9];
+    int64_t prow = -1;  // row offset of the f_dag_i held in fdp, or -1
+    auto store_fd = [&]() {
+        if (prow >= 0) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) st_at(fout + ((int64_t)i * plane + prow), xoff, fdp[i]);
+            prow = -1;
+        }
+    };
     C fA[9], fB[9], rA[3], rB[3], nB[6], d0r[3], d0f[6], d1r[3], d1f[3];
 #pragma unroll
     for (int i = 0; i < 9; ++i) fA[i] = fB[i] = C(0);
@@ -1018,6 +1039,7 @@ __device__ __forceinline__ void pair_step_b(S* __restrict__ fout, const KParams&
             L.tB[s1][1][t] = Txy;
             L.tB[s1][2][t] = Tyy;
         }
+        store_fd();
         __syncthreads();
         // phase 2: stage 3, then row m enters the pipeline
         if (live && m >= 4 && b3) {
@@ -1028,9 +1050,10 @@ __device__ __forceinline__ void pair_step_b(S* __restrict__ fout, const KParams&
             collide_recolour<C, PT>(fB, rB, nB, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
             const int64_t orow = (int64_t)yo * kp.fpitch;
             NodeBits bits(((uint32_t)yo * (uint32_t)nx + (uint32_t)x) * 27u ^ salt);
+            // rounded in store order, the f_dag_i first
 #pragma unroll
-            for (int i = 0; i < 9; ++i)
-                st_at(fout + ((int64_t)i * plane + orow), xoff, to_storage<S, C>(fd[i], bits));
+            for (int i = 0; i < 9; ++i) fdp[i] = to_storage<S, C>(fd[i], bits);
+            prow = orow;
 #pragma unroll
             for (int k = 0; k < 3; ++k)
                 st_at(fout + ((int64_t)(9 + k) * plane + orow), xoff, to_storage<S, C>(ck[k], bits));
@@ -1054,6 +1077,7 @@ __device__ __forceinline__ void pair_step_b(S* __restrict__ fout, const KParams&
         }
         __syncthreads();
     }
+    store_fd();
 }
 
 // The same two-step pass with each thread carrying both steps (used for FP32, whose two
