@@ -26,7 +26,7 @@ _LIB = os.path.join(_HERE, "liblbm3_oracle.so")
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, IEEE double, no FMA contraction, OpenMP over rows)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+        tmp = f"{_LIB}.{os.getpid()}.tmp"  # one per process: parallel test workers may build at once
         subprocess.run(
             ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
              "-Wall", "-Wextra", "-Wno-unused-parameter", _SRC, "-o", tmp, "-lm"],

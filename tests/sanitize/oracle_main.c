@@ -30,9 +30,9 @@ int oracle_step_nodes(const oracle_problem *p, const double *f, int32_t count, c
                       const int32_t *ys, double *out);
 void oracle_gradient(int32_t nx, int32_t ny, const double *phi, double *dx, double *dy);
 void oracle_set_num_threads(int n);
-void oracle3d_init(const oracle_problem *p, int32_t nz, const double *rho, double *f);
-int oracle3d_run(const oracle_problem *p, int32_t nz, double *f, int64_t nsteps);
-int oracle3d_observables(const oracle_problem *p, int32_t nz, const double *f, double *out);
+int oracle3d_init(const oracle_problem *p, int32_t nz, int32_t q, const double *rho, double *f);
+int oracle3d_run(const oracle_problem *p, int32_t nz, int32_t q, double *f, int64_t nsteps);
+int oracle3d_observables(const oracle_problem *p, int32_t nz, int32_t q, const double *f, double *out);
 
 static uint64_t state = 0x9e3779b97f4a7c15ull;
 static double uniform(void)
@@ -99,18 +99,19 @@ int main(void)
                     free(dy);
             }
     static const int shapes3[][3] = {{1, 2, 3}, {2, 1, 1}, {4, 3, 5}};
+    for (int q = 19; q <= 27; q += 8)
     for (size_t s = 0; s < sizeof shapes3 / sizeof shapes3[0]; ++s)
         for (int law = 0; law < 4; ++law) {
             oracle_problem p = {shapes3[s][0], shapes3[s][1], {1.0, 1.0, 1.0}, {0.011, 0.013, 0.017},
                                 {0.7, 1.0, 1.3}, 0.7, law, 0};
             const int nz = shapes3[s][2];
             const size_t n = (size_t)p.nx * p.ny * nz;
-            double *rho = malloc(3 * n * sizeof(double)), *f = malloc(57 * n * sizeof(double)), obs[8];
+            double *rho = malloc(3 * n * sizeof(double)), *f = malloc(3 * q * n * sizeof(double)), obs[8];
             mixture(rho, n);
-            oracle3d_init(&p, nz, rho, f);
-            bad |= oracle3d_run(&p, nz, f, 4) != 0;
-            bad |= oracle3d_observables(&p, nz, f, obs) != 0;
-            bad |= check("state3d", f, 57 * n);
+            bad |= oracle3d_init(&p, nz, q, rho, f) != 0;
+            bad |= oracle3d_run(&p, nz, q, f, 4) != 0;
+            bad |= oracle3d_observables(&p, nz, q, f, obs) != 0;
+            bad |= check("state3d", f, 3 * q * n);
             free(rho), free(f);
         }
     printf(bad ? "FAILED\n" : "ok\n");

@@ -1,10 +1,10 @@
 """The D3Q19 form through the C ABI (lbm3d_*) against the D3Q19 oracle, which is pinned to
-the two-dimensional oracle (tests/test_oracle_d3q19.py)."""
+the two-dimensional oracle (tests/test_oracle_d3.py)."""
 import numpy as np
 import pytest
 
 import oracle
-from oracle import d3q19
+from oracle import d3
 from paper_1808_08555_amd import inputs, lbm3
 
 pytestmark = pytest.mark.gpu
@@ -24,7 +24,7 @@ def _gpu(rho, steps, sigma=SIG, tau=TAU, law="paper", precision="fp64"):
 def _oracle(rho, steps, sigma=SIG, tau=TAU, law="paper"):
     nz, ny, nx = rho.shape[1:]
     p = oracle.Params(nx, ny, sigma, tau, beta_law=law)
-    return d3q19.run(p, nz, d3q19.init(p, nz, rho), steps)
+    return d3.run(p, nz, d3.init(p, nz, rho), steps)
 
 
 @pytest.mark.parametrize("law", ["paper", "leclaire"])
@@ -48,13 +48,13 @@ def test_parity_two_spheres_along_the_trajectory():
     L = lbm3.Lattice3D(30, 26, 22, SIG, TAU).init(rho)
     try:
         g = L.step(50).state()
-        o = d3q19.run(p, 22, d3q19.init(p, 22, rho), 50)
+        o = d3.run(p, 22, d3.init(p, 22, rho), 50)
         assert np.abs(g - o).max() <= 1e-11
         L.step(100)
         worst = 0.0
         for _ in range(3):
             prev = L.state()
-            worst = max(worst, float(np.abs(L.step(1).state() - d3q19.step(p, 22, prev)).max()))
+            worst = max(worst, float(np.abs(L.step(1).state() - d3.step(p, 22, prev)).max()))
         print("one step from the GPU state:", worst)
         assert worst <= 1e-15
     finally:
@@ -77,7 +77,7 @@ def test_uniform_along_z_equals_the_2d_step():
     L = lbm3.Lattice(48, 48, w.sigma, w.tau).init(w.rho)
     f2 = L.step(300).state()
     L.close()
-    e, _ = d3q19.lattice()
+    e, _ = d3.lattice()
     EX2, EY2 = [0, 1, 0, -1, 0, 1, -1, -1, 1], [0, 0, 1, 0, -1, 1, 1, -1, -1]
     proj = np.zeros_like(f2)
     for q in range(9):
@@ -93,7 +93,7 @@ def test_observables_match_the_oracle():
     obs, r, f = L.observables(want_rho=True, want_f=True)
     L.close()
     p = oracle.Params(20, 18, SIG, TAU)
-    o = d3q19.observables(p, 16, f)
+    o = d3.observables(p, 16, f)
     print(obs, o)
     assert obs["step"] == 50 and obs["nonfinite"] == 0
     assert np.abs(obs["mass"] / o["mass"] - 1).max() < 1e-13
