@@ -285,27 +285,32 @@ int lbm3_adjoint(lbm3_t *h, const double *drho1_T, double dsigma[3], double *drh
 int lbm3_adjoint_pipeline_slots(int64_t nodes, uint64_t ws_two_slots, uint64_t ws_held,
                                 uint64_t device_free);
 
-/* ---- three-dimensional form (D3Q19) ---------------------------------------------
+/* ---- three-dimensional form (D3Q19, D3Q27) --------------------------------------
  * The step of Sec. 2 (the model is stated for DmQn lattices) on the standard D3Q19
- * lattice (c_s^2 = 1/3; w_0 = 1/3, w = 1/18 on the axis links, 1/36 on the edge links):
- * Eq. (12) as the gradient and the force divergence, the stress pair sum of Eq. (7) as a
- * 3 x 3 tensor, Guo's term and the velocity of Eqs. (8)-(9), the equilibrium of Eq. (3),
- * the recolouring of Eq. (13) with any segregation law (beta_law), streaming of Eq. (22);
- * periodic in x, y and z.  Any precision (FP32 storage: each stored population the
- * stochastic rounding of its FP64 value); the paper's forcing only (else
- * LBM3_EUNSUPPORTED).
- * lbm3d_create: p as for lbm3_create (nx, ny from it), nz in 1..65535, at most 2^29
- *   nodes (else LBM3_EINVAL); allocates the two 57-population state buffers (in the
- *   storage type) and a staging buffer for exports (57 + 3 doubles per node).
+ * lattice (c_s^2 = 1/3; w_0 = 1/3, w = 1/18 on the axis links, 1/36 on the edge links) or
+ * the standard D3Q27 lattice (c_s^2 = 1/3; w_0 = 8/27, 2/27 on the axis links, 1/54 on the
+ * edge links, 1/216 on the corner links): Eq. (12) as the gradient and the force
+ * divergence, the stress pair sum of Eq. (7) as a 3 x 3 tensor, Guo's term and the
+ * velocity of Eqs. (8)-(9), the equilibrium of Eq. (3), the recolouring of Eq. (13) with
+ * any segregation law (beta_law), streaming of Eq. (22); periodic in x, y and z.  Any
+ * precision (FP32 storage: each stored population the stochastic rounding of its FP64
+ * value); the paper's forcing only (else LBM3_EUNSUPPORTED).  Q below is the lattice's
+ * number of links, 19 or 27.
+ * lbm3d_create_lattice: p as for lbm3_create (nx, ny from it), nz in 1..65535, q = 19 or
+ *   27, at most 2^29 nodes (else LBM3_EINVAL); allocates the two 3Q-population state
+ *   buffers (in the storage type) and a staging buffer for exports (3Q + 3 doubles per
+ *   node).
+ * lbm3d_create: lbm3d_create_lattice with q = 19.
  * lbm3d_init_fields: rho host [3][nz][ny][nx] (x fastest), finite, >= 0, with rho > 0 at
  *   every node; fluid at rest (f_{i,k} = w_i rho_k).  Blocking; resets the step count.
  * lbm3d_step: enqueues n >= 0 steps on the handle's stream (one launch each).
  * lbm3d_observables: blocking; masses, momentum sum rho u (Eq. 9 velocity), kinetic
  *   energy, max |u|, and when non-NULL the densities (host [3][nz][ny][nx]) and the
- *   post-streaming populations (host [3][19][nz][ny][nx], links in the order: rest,
+ *   post-streaming populations (host [3][Q][nz][ny][nx], links in the order: rest,
  *   +-x, +-y, +-z, then (+1,+1,0), (-1,-1,0), (+1,-1,0), (-1,+1,0), (+1,0,+1), (-1,0,-1),
- *   (+1,0,-1), (-1,0,+1), (0,+1,+1), (0,-1,-1), (0,+1,-1), (0,-1,+1)).  ENONFINITE when
- *   the state is not finite.
+ *   (+1,0,-1), (-1,0,+1), (0,+1,+1), (0,-1,-1), (0,+1,-1), (0,-1,+1), and for D3Q27 then
+ *   (+1,+1,+1), (-1,-1,-1), (+1,+1,-1), (-1,-1,+1), (+1,-1,+1), (-1,+1,-1), (-1,+1,+1),
+ *   (+1,-1,-1)).  ENONFINITE when the state is not finite.
  * lbm3d_destroy: releases everything; NULL is accepted. */
 typedef struct lbm3d lbm3d_t;
 typedef struct {
@@ -316,6 +321,7 @@ typedef struct {
     double u_max;
     int32_t nonfinite;
 } lbm3d_obs;
+int lbm3d_create_lattice(const lbm3_params *p, int32_t nz, int32_t q, void *hip_stream, lbm3d_t **out);
 int lbm3d_create(const lbm3_params *p, int32_t nz, void *hip_stream, lbm3d_t **out);
 int lbm3d_init_fields(lbm3d_t *h, const double *rho);
 int lbm3d_step(lbm3d_t *h, int64_t n);

@@ -1,12 +1,13 @@
-// The three-dimensional (D3Q19) form of the ternary step: the paper's model (Sec. 2) on the
-// standard D3Q19 lattice, the force of Eq. (7) with Guo's term, any segregation law, in FP64,
-// FP32, or FP32 storage with FP64 arithmetic (stochastic rounding on store).
+// The three-dimensional form of the ternary step: the paper's model (Sec. 2) on the standard
+// D3Q19 or D3Q27 lattice, the force of Eq. (7) with Guo's term, any segregation law, in
+// FP64, FP32, or FP32 storage with FP64 arithmetic (stochastic rounding on store).
 //
-// State: the recoloured populations before streaming, 57 planes B[k][i][z][y][x] (pull
+// State: the recoloured populations before streaming, 3Q planes B[k][i][z][y][x] (pull
 // scheme: f_{i,k}(x) = B_{i,k}(x - e_i)), two buffers.  A step is one launch of the fused
 // march (k3_march): workgroups own x-y blocks of a z segment and march up z, keeping the
 // concentrations and the stress of three planes in LDS rings, so that the state is read
-// and written once per update (912 B) and nothing else goes through HBM.
+// and written once per update (912 B for D3Q19 in FP64, 1296 B for D3Q27) and nothing else
+// goes through HBM.
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -18,21 +19,31 @@
 namespace tcg {
 namespace {
 
-// D3Q19 links: rest, six axis links, twelve edge links; link i odd and i + 1 are opposite.
-// Weights 1/3, 1/18, 1/36; c_s^2 = 1/3.  In FP32 the nearest floats sum to 1 + 1.5e-8, and
-// every collision would scale the mass by that sum (the equilibrium's zeroth moment); the
-// float weights are therefore one ulp above 1/3 and one ulp below 1/18 and 1/36, whose sum
-// is exactly 1.
-constexpr int L3X[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-constexpr int L3Y[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-constexpr int L3Z[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-template <typename C>
-__device__ __forceinline__ C w19(int i)
+// Links: rest, six axis links, twelve edge links (the D3Q19 lattice ends here), eight corner
+// links (D3Q27); link i odd and i + 1 are opposite.  c_s^2 = 1/3 on both.  D3Q19 weights 1/3,
+// 1/18, 1/36; D3Q27 weights 8/27, 2/27, 1/54, 1/216.  In FP32 the nearest floats sum to
+// 1 + 1.5e-8 (D3Q19) and 1 + 7.5e-9 (D3Q27), and every collision would scale the mass by that
+// sum (the equilibrium's zeroth moment); the float weights are therefore chosen one ulp off
+// where needed so that their sum is exactly 1: D3Q19 one ulp above 1/3 and one ulp below
+// 1/18 and 1/36; D3Q27 one ulp below 8/27 and one ulp above 1/54.
+constexpr int L3X[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1};
+constexpr int L3Y[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, -1, 1, 1, -1};
+constexpr int L3Z[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, 1, -1};
+template <typename C, int Q>
+__device__ __forceinline__ C w3(int i)
 {
-    if constexpr (sizeof(C) == 8)
-        return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
-    else
-        return i == 0 ? 0x1.555558p-2f : (i <= 6 ? 0x1.c71c70p-5f : 0x1.c71c70p-6f);
+    static_assert(Q == 19 || Q == 27, "D3Q19 or D3Q27");
+    if constexpr (Q == 19) {
+        if constexpr (sizeof(C) == 8)
+            return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+        else
+            return i == 0 ? 0x1.555558p-2f : (i <= 6 ? 0x1.c71c70p-5f : 0x1.c71c70p-6f);
+    } else {
+        if constexpr (sizeof(C) == 8)
+            return i == 0 ? 8.0 / 27.0 : (i <= 6 ? 2.0 / 27.0 : (i <= 18 ? 1.0 / 54.0 : 1.0 / 216.0));
+        else
+            return i == 0 ? 0x1.2f684ap-2f : (i <= 6 ? 0x1.2f684cp-4f : (i <= 18 ? 0x1.2f684ep-6f : 0x1.2f684cp-8f));
+    }
 }
 constexpr int PK3[3] = {0, 0, 1}, PL3[3] = {1, 2, 2};
 
@@ -74,15 +85,14 @@ struct Nb3 {
 };
 
 // The post-streaming populations of node (x, y, z): f_{i,k} = B_{i,k}(x - e_i).
-template <typename S>
-__device__ __forceinline__ void pull57(const S* __restrict__ B, const Geo3& g, const Nb3& nb,
-                                       double (&f)[3][19])
+template <typename S, int Q>
+__device__ __forceinline__ void pull3(const S* __restrict__ B, const Geo3& g, const Nb3& nb, double (&f)[3][Q])
 {
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 0; i < Q; ++i) {
         const int64_t src = nb.at(-L3X[i], -L3Y[i], -L3Z[i]);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) f[k][i] = double(B[(int64_t)(k * 19 + i) * g.N + src]);
+        for (int k = 0; k < 3; ++k) f[k][i] = double(B[(int64_t)(k * Q + i) * g.N + src]);
     }
 }
 
@@ -107,19 +117,19 @@ __device__ __forceinline__ C edot(int i, C a0, C a1, C a2)
     return r;
 }
 
-// Eq. (12) over the nine pairs of opposite links: 3 sum_i w_i e_i [phi(x + e_i) - phi(x - e_i)],
-// phi(dx, dy, dz) the field at offset (dx, dy, dz) from the node (zero components of e_i
-// skipped, as in edot)
-template <typename C, typename Get>
-__device__ __forceinline__ void grad19(Get phi, C (&d)[3])
+// Eq. (12) over the (Q - 1)/2 pairs of opposite links: 3 sum_i w_i e_i [phi(x + e_i) -
+// phi(x - e_i)], phi(dx, dy, dz) the field at offset (dx, dy, dz) from the node (zero
+// components of e_i skipped, as in edot)
+template <typename C, int Q, typename Get>
+__device__ __forceinline__ void grad3(Get phi, C (&d)[3])
 {
     d[0] = d[1] = d[2] = C(0);
 #pragma unroll
-    for (int i = 1; i < 19; i += 2) {
+    for (int i = 1; i < Q; i += 2) {
         const C df = phi(L3X[i], L3Y[i], L3Z[i]) - phi(-L3X[i], -L3Y[i], -L3Z[i]);
-        if (L3X[i] != 0) d[0] += w19<C>(i) * C(L3X[i]) * df;
-        if (L3Y[i] != 0) d[1] += w19<C>(i) * C(L3Y[i]) * df;
-        if (L3Z[i] != 0) d[2] += w19<C>(i) * C(L3Z[i]) * df;
+        if (L3X[i] != 0) d[0] += w3<C, Q>(i) * C(L3X[i]) * df;
+        if (L3Y[i] != 0) d[1] += w3<C, Q>(i) * C(L3Y[i]) * df;
+        if (L3Z[i] != 0) d[2] += w3<C, Q>(i) * C(L3Z[i]) * df;
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) d[a] *= C(3);
@@ -129,7 +139,7 @@ __device__ __forceinline__ void grad19(Get phi, C (&d)[3])
 // normals n_kl (n[3p + a]; zero at or below the guard) of a node from its concentrations
 // cc, their gradients gc and its densities rk (Eq. 7 with C_kl of Eq. 6).
 template <typename C>
-__device__ __forceinline__ void stress19(const C (&gc)[3][3], const C (&cc)[3], const C (&rk)[3], const KParams& kp,
+__device__ __forceinline__ void stress3(const C (&gc)[3][3], const C (&cc)[3], const C (&rk)[3], const KParams& kp,
                                          C (&t)[6], C (&nrm)[9])
 {
 #pragma unroll
@@ -163,17 +173,17 @@ __device__ __forceinline__ void stress19(const C (&gc)[3][3], const C (&cc)[3], 
 
 // F_b = sum_a d_a T_ab with the symmetric T stored as (xx, xy, xz, yy, yz, zz);
 // T(q, dx, dy, dz) is component q at offset (dx, dy, dz) from the node
-template <typename C, typename Get>
-__device__ __forceinline__ void force19(Get T, C (&F)[3])
+template <typename C, int Q, typename Get>
+__device__ __forceinline__ void force3(Get T, C (&F)[3])
 {
-    constexpr int Q[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    constexpr int QI[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
     F[0] = F[1] = F[2] = C(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             C d[3];
-            grad19<C>([&](int dx, int dy, int dz) { return T(Q[a][b], dx, dy, dz); }, d);
+            grad3<C, Q>([&](int dx, int dy, int dz) { return T(QI[a][b], dx, dy, dz); }, d);
             F[b] += d[a];
         }
 }
@@ -182,14 +192,14 @@ __device__ __forceinline__ void force19(Get T, C (&F)[3])
 // law) of one node from its densities rk, totals ft, force F and pair normals nrm.  With OBS
 // the node's observables go to acc (rho_k, rho u, kinetic energy, |u|); otherwise every
 // recoloured population is handed to put(k, i, value).
-template <typename C, bool OBS, typename Put>
-__device__ __forceinline__ void collide19(const C (&rk)[3], const C (&ft)[19], const C (&F)[3], const C (&nrm)[9],
-                                          const KParams& kp, double (&acc)[8], Put put)
+template <typename C, int Q, bool OBS, typename Put>
+__device__ __forceinline__ void collide3(const C (&rk)[3], const C (&ft)[Q], const C (&F)[3], const C (&nrm)[9],
+                                         const KParams& kp, double (&acc)[8], Put put)
 {
     const C rho = rk[0] + rk[1] + rk[2], irho = C(1) / rho;
     C m[3] = {C(0), C(0), C(0)};
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 0; i < Q; ++i) {
         if (L3X[i] != 0) m[0] += L3X[i] > 0 ? ft[i] : -ft[i];
         if (L3Y[i] != 0) m[1] += L3Y[i] > 0 ? ft[i] : -ft[i];
         if (L3Z[i] != 0) m[2] += L3Z[i] > 0 ? ft[i] : -ft[i];
@@ -233,31 +243,31 @@ __device__ __forceinline__ void collide19(const C (&rk)[3], const C (&ft)[19], c
 #pragma unroll
         for (int k = 0; k < 3; ++k) ck[k] = rk[k] * irho;
 #pragma unroll
-        for (int i = 0; i < 19; ++i) {
+        for (int i = 0; i < Q; ++i) {
             const C eu = edot<C>(i, u[0], u[1], u[2]);
             const C eF = edot<C>(i, F[0], F[1], F[2]);
-            const C feq = w19<C>(i) * rho * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
-            const C phi = w19<C>(i) * pref * (C(3) * (eF - uF) + C(9) * eu * eF);
+            const C feq = w3<C, Q>(i) * rho * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
+            const C phi = w3<C, Q>(i) * pref * (C(3) * (eF - uF) + C(9) * eu * eF);
             const C fd = ft[i] - (ft[i] - feq) * itau + phi;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const C ve = edot<C>(i, V[k][0], V[k][1], V[k][2]);
-                put(k, i, ck[k] * fd + w19<C>(i) * ve);
+                put(k, i, ck[k] * fd + w3<C, Q>(i) * ve);
             }
             // each link's values leave before the next link's are formed (otherwise the
-            // compiler holds all 57 for one burst of stores)
+            // compiler holds all 3Q for one burst of stores)
             __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
 
 // ---- the fused step: one kernel per step, marching along z
-// A workgroup of kTX x kTY lanes (lane t at tile column t % kTX, tile row t / kTX; each wave
-// is two whole tile rows) owns the output nodes [x0, x0 + cols) x [y0, y0 + rows) x
-// [z0, z0 + depth), cols <= kTX - 4 and rows <= kTY - 4.  Lane (tx, ty) sits on node column
+// A workgroup of TX x TY lanes (lane t at tile column t % TX, tile row t / TX; each wave is
+// two whole tile rows) owns the output nodes [x0, x0 + cols) x [y0, y0 + rows) x
+// [z0, z0 + depth), cols <= TX - 4 and rows <= TY - 4.  Lane (tx, ty) sits on node column
 // (x0 - 2 + tx, y0 - 2 + ty) (wrapped) and marches up z.  Iteration j, three phases closed
 // by barriers:
-//   stage 1, plane z0 - 2 + j: pull the 57 populations; totals f_i and densities rho_k (kept
+//   stage 1, plane z0 - 2 + j: pull the 3Q populations; totals f_i and densities rho_k (kept
 //            in registers for two more iterations); c_k into the LDS ring (all lanes with
 //            tx <= cols + 3, ty <= rows + 3);
 //   stage 2, plane z0 - 3 + j: grad c_k (Eq. 12) from the ring, stress and pair normals
@@ -265,34 +275,42 @@ __device__ __forceinline__ void collide19(const C (&rk)[3], const C (&ft)[19], c
 //   stage 3, plane z0 - 4 + j: F = div T from the ring, collision and recolouring of the
 //            owned nodes (lanes 2 .. cols + 1, 2 .. rows + 1), stored.
 // Rings hold three planes, by plane mod 3.  depth + 4 iterations output the tile's planes.
-// The arithmetic of every node is that of stress19 / force19 / collide19 in a fixed order,
-// so the result does not depend on the tile shape.
-constexpr int kTX = 32, kTY = 16, kT3 = kTX * kTY;
+// The arithmetic of every node is that of stress3 / force3 / collide3 in a fixed order, so
+// the result does not depend on the tile shape.  D3Q27 takes tiles of 32 x 14 lanes, so
+// that its larger park still leaves the FP64 rings within the 160 KB of LDS (145 KB against
+// 148 KB for D3Q19 on 32 x 16).
+template <int Q>
+struct Tile3Shape {
+    static constexpr int TX = 32, TY = Q == 27 ? 14 : 16, T = TX * TY;
+    static constexpr int TS = (TX - 2) * (TY - 2);  // lanes that form the stress
+    static constexpr int TP = (TX - 4) * (TY - 4);  // lanes that own output nodes
+};
 
 struct Tile3 {
     int32_t x0, y0, z0, cols, rows, depth;
 };
 
-constexpr int kTS = (kTX - 2) * (kTY - 2);  // lanes that form the stress
-constexpr int kTP = (kTX - 4) * (kTY - 4);  // lanes that own output nodes
-
-template <typename C>
+template <typename C, int Q>
 struct alignas(16) March3Lds {
-    C c[3][3][kT3];     // c_k by plane mod 3
-    C T[3][6][kTS];     // stress by plane mod 3, on the stress lanes
-    C park[19][kTP];    // per owning lane: the totals f_i of one waiting plane
+    using Sh = Tile3Shape<Q>;
+    C c[3][3][Sh::T];    // c_k by plane mod 3
+    C T[3][6][Sh::TS];   // stress by plane mod 3, on the stress lanes
+    C park[Q][Sh::TP];   // per owning lane: the totals f_i of one waiting plane
 };
 
 // S: storage type, C: compute type.  With FP32 storage of FP64 arithmetic each stored value
 // is rounded stochastically with the random bits of its node (key: node index and the
 // step's salt), in store order.
-template <typename S, typename C, bool OBS>
-__global__ __launch_bounds__(kT3) __attribute__((amdgpu_waves_per_eu(2))) void k3_march(
+template <typename S, typename C, bool OBS, int Q>
+__global__ __launch_bounds__(Tile3Shape<Q>::T) __attribute__((amdgpu_waves_per_eu(2))) void k3_march(
     const S* __restrict__ B, Geo3 g, KParams kp, const Tile3* __restrict__ tiles, S* __restrict__ Bout,
     double* __restrict__ partials, uint32_t salt)
 {
+    using Sh = Tile3Shape<Q>;
+    constexpr int kTX = Sh::TX, kT3 = Sh::T;
+    static_assert(kT3 % 64 == 0 && (2 * kTX) % 64 == 0, "each wave is whole tile rows");
     static_assert(sizeof(double) * 8 * (kT3 / 64) <= sizeof(C) * 3 * 3 * kT3, "c ring too small for the reduction");
-    __shared__ March3Lds<C> L;
+    __shared__ March3Lds<C, Q> L;
     const Tile3 tl = tiles[blockIdx.x];
     const int t = threadIdx.x, tx = t % kTX, ty = t / kTX;
     const bool in1 = tx <= tl.cols + 3 && ty <= tl.rows + 3;
@@ -316,9 +334,9 @@ __global__ __launch_bounds__(kT3) __attribute__((amdgpu_waves_per_eu(2))) void k
     // them are live at a time: the one pulled (ft), the one waiting (W) and the one collided
     // (ftB).  Each owning lane parks one of them in LDS (its own slots, so no barrier is
     // involved): after the pull, ftB comes out of the park, W goes in, and ft becomes W.
-    C W[19], rA[3], rB[3], nB[9];
+    C W[Q], rA[3], rB[3], nB[9];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) W[i] = C(0);
+    for (int i = 0; i < Q; ++i) W[i] = C(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) rA[k] = rB[k] = C(1);
 #pragma unroll
@@ -334,46 +352,63 @@ __global__ __launch_bounds__(kT3) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int zc = wrap(tl.z0 - 2 + j, g.nz);
         const int s0 = j % 3, s1 = (j + 2) % 3, s2 = (j + 1) % 3;  // planes zc, zc - 1, zc - 2
         // ---- stage 1: pull of plane zc
-        C ft[19], rk[3] = {C(1), C(1), C(1)};
+        C ft[Q], rk[3] = {C(1), C(1), C(1)};
 #pragma unroll
-        for (int i = 0; i < 19; ++i) ft[i] = C(0);
+        for (int i = 0; i < Q; ++i) ft[i] = C(0);
         if (in1) {
-            // one memory round trip per plane: the 57 loads are issued together, and a
-            // scheduling barrier keeps the compiler from interleaving the sums with them
-            // (which serialises the loads)
             const uint32_t zo[3] = {zoff(zc - 1), zoff(zc), zoff(zc + 1)};
-            C v[57];
-#pragma unroll
-            for (int i = 0; i < 19; ++i) {
-                const uint32_t o = src(zo, i);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) v[k * 19 + i] = C(ld_plane(B + (int64_t)(k * 19 + i) * g.N, o));
-            }
-            __builtin_amdgcn_sched_barrier(0);
             rk[0] = rk[1] = rk[2] = C(0);
+            if constexpr (Q == 19) {
+                // one memory round trip per plane: the 57 loads are issued together, and a
+                // scheduling barrier keeps the compiler from interleaving the sums with them
+                // (which serialises the loads)
+                C v[3 * Q];
 #pragma unroll
-            for (int i = 0; i < 19; ++i) {
-                ft[i] = v[i] + v[19 + i] + v[38 + i];
-                rk[0] += v[i];
-                rk[1] += v[19 + i];
-                rk[2] += v[38 + i];
+                for (int i = 0; i < Q; ++i) {
+                    const uint32_t o = src(zo, i);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) v[k * Q + i] = C(ld_plane(B + (int64_t)(k * Q + i) * g.N, o));
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    ft[i] = v[i] + v[Q + i] + v[2 * Q + i];
+                    rk[0] += v[i];
+                    rk[1] += v[Q + i];
+                    rk[2] += v[2 * Q + i];
+                }
+            } else {
+                // one round trip per fluid (all 81 values of a plane would not fit beside the
+                // live registers); the totals add the fluids in the same order
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    C v[Q];
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) v[i] = C(ld_plane(B + (int64_t)(k * Q + i) * g.N, src(zo, i)));
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) {
+                        ft[i] = k == 0 ? v[i] : ft[i] + v[i];
+                        rk[k] += v[i];
+                    }
+                }
             }
             const C ir = C(1) / (rk[0] + rk[1] + rk[2]);
 #pragma unroll
             for (int k = 0; k < 3; ++k) L.c[s0][k][t] = rk[k] * ir;
         }
-        C ftB[19];
+        C ftB[Q];
 #pragma unroll
-        for (int i = 0; i < 19; ++i) ftB[i] = C(0);
+        for (int i = 0; i < Q; ++i) ftB[i] = C(0);
         if (in3) {
 #pragma unroll
-            for (int i = 0; i < 19; ++i) {
+            for (int i = 0; i < Q; ++i) {
                 ftB[i] = L.park[i][tP];
                 L.park[i][tP] = W[i];
             }
         }
 #pragma unroll
-        for (int i = 0; i < 19; ++i) W[i] = ft[i];
+        for (int i = 0; i < Q; ++i) W[i] = ft[i];
         __syncthreads();
         // ---- stage 2: stress of plane zc - 1
         C nA[9];
@@ -384,10 +419,10 @@ __global__ __launch_bounds__(kT3) __attribute__((amdgpu_waves_per_eu(2))) void k
             C gc[3][3], cc[3], tt[6];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                grad19<C>([&](int dx, int dy, int dz) { return L.c[sl[dz + 1]][k][t + dy * kTX + dx]; }, gc[k]);
+                grad3<C, Q>([&](int dx, int dy, int dz) { return L.c[sl[dz + 1]][k][t + dy * kTX + dx]; }, gc[k]);
                 cc[k] = L.c[s1][k][t];
             }
-            stress19<C>(gc, cc, rA, kp, tt, nA);
+            stress3<C>(gc, cc, rA, kp, tt, nA);
 #pragma unroll
             for (int q = 0; q < 6; ++q) L.T[s1][q][tS] = tt[q];
         }
@@ -396,13 +431,13 @@ __global__ __launch_bounds__(kT3) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (j >= 4 && in3) {
             const int sl[3] = {s0, s2, s1};  // T of planes zc - 3, zc - 2, zc - 1 by dz + 1
             C F[3];
-            force19<C>([&](int q, int dx, int dy, int dz) { return L.T[sl[dz + 1]][q][tS + dy * (kTX - 2) + dx]; },
-                       F);
+            force3<C, Q>([&](int q, int dx, int dy, int dz) { return L.T[sl[dz + 1]][q][tS + dy * (kTX - 2) + dx]; },
+                         F);
             const uint32_t node = (uint32_t)(tl.z0 - 4 + j) * pl + yo[1] + (uint32_t)x;
             const uint32_t o = node * (uint32_t)sizeof(S);
-            NodeBits bits(node * 57u ^ salt);
-            collide19<C, OBS>(rB, ftB, F, nB, kp, acc, [&](int k, int i, C v) {
-                st_plane(Bout + (int64_t)(k * 19 + i) * g.N, o, to_storage<S, C>(v, bits));
+            NodeBits bits(node * (3u * Q) ^ salt);
+            collide3<C, Q, OBS>(rB, ftB, F, nB, kp, acc, [&](int k, int i, C v) {
+                st_plane(Bout + (int64_t)(k * Q + i) * g.N, o, to_storage<S, C>(v, bits));
             });
         }
 #pragma unroll
@@ -458,7 +493,7 @@ __device__ __forceinline__ bool node3(const Geo3& g, int& x, int& y, int& z)
 }
 
 // B_{i,k}(y) = w_i rho_k(y + e_i): the pulled state is f_{i,k} = w_i rho_k (fluid at rest)
-template <typename S, typename C>
+template <typename S, typename C, int Q>
 __global__ __launch_bounds__(256) void k3_init(const double* __restrict__ rho, Geo3 g, S* __restrict__ B)
 {
     int x, y, z;
@@ -466,15 +501,15 @@ __global__ __launch_bounds__(256) void k3_init(const double* __restrict__ rho, G
     const Nb3 nb(g, x, y, z);
     const int64_t j = nb.at(0, 0, 0);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 0; i < Q; ++i) {
         const int64_t src = nb.at(L3X[i], L3Y[i], L3Z[i]);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) B[(int64_t)(k * 19 + i) * g.N + j] = S(w19<C>(i) * C(rho[k * g.N + src]));
+        for (int k = 0; k < 3; ++k) B[(int64_t)(k * Q + i) * g.N + j] = S(w3<C, Q>(i) * C(rho[k * g.N + src]));
     }
 }
 
-// the post-streaming populations [3][19][N] and densities [3][N] of the state
-template <typename S>
+// the post-streaming populations [3][Q][N] and densities [3][N] of the state
+template <typename S, int Q>
 __global__ __launch_bounds__(256) void k3_export(const S* __restrict__ B, Geo3 g, double* __restrict__ fout,
                                                  double* __restrict__ rho)
 {
@@ -482,13 +517,13 @@ __global__ __launch_bounds__(256) void k3_export(const S* __restrict__ B, Geo3 g
     if (!node3(g, x, y, z)) return;
     const Nb3 nb(g, x, y, z);
     const int64_t j = nb.at(0, 0, 0);
-    double f[3][19];
-    pull57(B, g, nb, f);
+    double f[3][Q];
+    pull3<S, Q>(B, g, nb, f);
     for (int k = 0; k < 3; ++k) {
         double s = 0.0;
-        for (int i = 0; i < 19; ++i) {
+        for (int i = 0; i < Q; ++i) {
             s += f[k][i];
-            if (fout) fout[(int64_t)(k * 19 + i) * g.N + j] = f[k][i];
+            if (fout) fout[(int64_t)(k * Q + i) * g.N + j] = f[k][i];
         }
         rho[k * g.N + j] = s;
     }
@@ -505,11 +540,12 @@ struct lbm3d {
     Geo3 g{};
     hipStream_t stream = nullptr;
     Prec prec = Prec::F64;
+    int q = 19;                         // links: 19 or 27
     void* buf[2] = {nullptr, nullptr};  // the state, in the storage type of prec
     Tile3* dtiles = nullptr;     // the march's tile list
     int ntiles = 0;
     double* partials = nullptr;  // [ntiles][8]
-    double* staging = nullptr;   // [57][N] for exports and uploads
+    double* staging = nullptr;   // [3q][N] for exports and uploads
     double* rho = nullptr;       // [3][N] densities for exports
     int cur = 0;
     int64_t step = 0;
@@ -535,14 +571,16 @@ static void split_even(int n, int parts, int q, int& start, int& len)
     len = base + (q < extra ? 1 : 0);
 }
 
-// The march's tiles: the x-y plane cut into at most (kTX - 4) x (kTY - 4) node blocks, the
-// z axis into `nseg` segments chosen so that rounds of resident workgroups x (segment depth
-// + 4 warm-up planes) is least.  Workgroups go to the XCDs in turn, so the list is permuted
-// for each XCD to take a contiguous run of it (neighbouring blocks, whose halos it then
-// finds in its own L2).
-static std::vector<Tile3> plan3(const Geo3& g, int slots)
+// The march's tiles: the x-y plane cut into at most (TX - 4) x (TY - 4) node blocks (the
+// lattice's tile shape), the z axis into `nseg` segments chosen so that rounds of resident
+// workgroups x (segment depth + 4 warm-up planes) is least.  Workgroups go to the XCDs in
+// turn, so the list is permuted for each XCD to take a contiguous run of it (neighbouring
+// blocks, whose halos it then finds in its own L2).
+static std::vector<Tile3> plan3(const Geo3& g, int slots, int q)
 {
-    const int ntx = (g.nx + kTX - 5) / (kTX - 4), nty = (g.ny + kTY - 5) / (kTY - 4);
+    const int TX = q == 27 ? Tile3Shape<27>::TX : Tile3Shape<19>::TX;
+    const int TY = q == 27 ? Tile3Shape<27>::TY : Tile3Shape<19>::TY;
+    const int ntx = (g.nx + TX - 5) / (TX - 4), nty = (g.ny + TY - 5) / (TY - 4);
     const int64_t per_seg = (int64_t)ntx * nty;
     if (slots < 1) slots = 1;
     int nseg = 1;
@@ -576,73 +614,101 @@ static std::vector<Tile3> plan3(const Geo3& g, int slots)
     return out;
 }
 
-template <typename S, typename C>
+template <typename S, typename C, int Q>
 static hipError_t launch_march_t(lbm3d* h, bool obs)
 {
     const S* in = (const S*)h->buf[h->cur];
     const uint32_t salt = step_salt(h->step);
+    constexpr int T = Tile3Shape<Q>::T;
     if (obs)
-        hipLaunchKernelGGL((k3_march<S, C, true>), dim3(h->ntiles), dim3(kT3), 0, h->stream, in, h->g, h->kp,
+        hipLaunchKernelGGL((k3_march<S, C, true, Q>), dim3(h->ntiles), dim3(T), 0, h->stream, in, h->g, h->kp,
                            (const Tile3*)h->dtiles, (S*)nullptr, h->partials, 0u);
     else
-        hipLaunchKernelGGL((k3_march<S, C, false>), dim3(h->ntiles), dim3(kT3), 0, h->stream, in, h->g, h->kp,
+        hipLaunchKernelGGL((k3_march<S, C, false, Q>), dim3(h->ntiles), dim3(T), 0, h->stream, in, h->g, h->kp,
                            (const Tile3*)h->dtiles, (S*)h->buf[h->cur ^ 1], (double*)nullptr, salt);
     return hipGetLastError();
 }
 
-static hipError_t launch_march(lbm3d* h, bool obs)
+template <int Q>
+static hipError_t launch_march_q(lbm3d* h, bool obs)
 {
     switch (h->prec) {
-        case Prec::F64: return launch_march_t<double, double>(h, obs);
-        case Prec::F32S: return launch_march_t<float, double>(h, obs);
-        case Prec::F32: return launch_march_t<float, float>(h, obs);
+        case Prec::F64: return launch_march_t<double, double, Q>(h, obs);
+        case Prec::F32S: return launch_march_t<float, double, Q>(h, obs);
+        case Prec::F32: return launch_march_t<float, float, Q>(h, obs);
     }
     return hipErrorInvalidValue;
 }
 
-static hipError_t march_occupancy(Prec prec, int* per_cu)
+static hipError_t launch_march(lbm3d* h, bool obs)
 {
+    return h->q == 27 ? launch_march_q<27>(h, obs) : launch_march_q<19>(h, obs);
+}
+
+template <int Q>
+static hipError_t march_occupancy_q(Prec prec, int* per_cu)
+{
+    constexpr int T = Tile3Shape<Q>::T;
     switch (prec) {
         case Prec::F64:
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k3_march<double, double, false>, kT3, 0);
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k3_march<double, double, false, Q>, T, 0);
         case Prec::F32S:
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k3_march<float, double, false>, kT3, 0);
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k3_march<float, double, false, Q>, T, 0);
         case Prec::F32:
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k3_march<float, float, false>, kT3, 0);
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k3_march<float, float, false, Q>, T, 0);
     }
     return hipErrorInvalidValue;
 }
 
-static hipError_t launch_init3(lbm3d* h, const double* rho)
+static hipError_t march_occupancy(Prec prec, int q, int* per_cu)
+{
+    return q == 27 ? march_occupancy_q<27>(prec, per_cu) : march_occupancy_q<19>(prec, per_cu);
+}
+
+template <int Q>
+static hipError_t launch_init3_q(lbm3d* h, const double* rho)
 {
     const dim3 gr = grid3(h->g), bl(256);
     switch (h->prec) {
         case Prec::F64:
-            hipLaunchKernelGGL((k3_init<double, double>), gr, bl, 0, h->stream, rho, h->g, (double*)h->buf[0]);
+            hipLaunchKernelGGL((k3_init<double, double, Q>), gr, bl, 0, h->stream, rho, h->g, (double*)h->buf[0]);
             break;
         case Prec::F32S:
-            hipLaunchKernelGGL((k3_init<float, double>), gr, bl, 0, h->stream, rho, h->g, (float*)h->buf[0]);
+            hipLaunchKernelGGL((k3_init<float, double, Q>), gr, bl, 0, h->stream, rho, h->g, (float*)h->buf[0]);
             break;
         case Prec::F32:
-            hipLaunchKernelGGL((k3_init<float, float>), gr, bl, 0, h->stream, rho, h->g, (float*)h->buf[0]);
+            hipLaunchKernelGGL((k3_init<float, float, Q>), gr, bl, 0, h->stream, rho, h->g, (float*)h->buf[0]);
             break;
     }
+    return hipGetLastError();
+}
+
+static hipError_t launch_init3(lbm3d* h, const double* rho)
+{
+    return h->q == 27 ? launch_init3_q<27>(h, rho) : launch_init3_q<19>(h, rho);
+}
+
+template <int Q>
+static hipError_t launch_export3_q(lbm3d* h, double* fout, double* rho)
+{
+    const dim3 gr = grid3(h->g), bl(256);
+    if (h->prec == Prec::F64)
+        hipLaunchKernelGGL((k3_export<double, Q>), gr, bl, 0, h->stream, (const double*)h->buf[h->cur], h->g, fout,
+                           rho);
+    else
+        hipLaunchKernelGGL((k3_export<float, Q>), gr, bl, 0, h->stream, (const float*)h->buf[h->cur], h->g, fout,
+                           rho);
     return hipGetLastError();
 }
 
 static hipError_t launch_export3(lbm3d* h, double* fout, double* rho)
 {
-    const dim3 gr = grid3(h->g), bl(256);
-    if (h->prec == Prec::F64)
-        hipLaunchKernelGGL((k3_export<double>), gr, bl, 0, h->stream, (const double*)h->buf[h->cur], h->g, fout, rho);
-    else
-        hipLaunchKernelGGL((k3_export<float>), gr, bl, 0, h->stream, (const float*)h->buf[h->cur], h->g, fout, rho);
-    return hipGetLastError();
+    return h->q == 27 ? launch_export3_q<27>(h, fout, rho) : launch_export3_q<19>(h, fout, rho);
 }
 
 extern "C" {
 
-int lbm3d_create(const lbm3_params* p, int32_t nz, void* hip_stream, lbm3d_t** out)
+int lbm3d_create_lattice(const lbm3_params* p, int32_t nz, int32_t q, void* hip_stream, lbm3d_t** out)
 {
     if (out) *out = nullptr;
     if (!out) {
@@ -651,16 +717,21 @@ int lbm3d_create(const lbm3_params* p, int32_t nz, void* hip_stream, lbm3d_t** o
     }
     int rc = validate_params(p);
     if (rc) return rc;
+    if (q != 19 && q != 27) {
+        set_error("the three-dimensional form takes the D3Q19 or the D3Q27 lattice (q = 19 or 27, got %d)", (int)q);
+        return LBM3_EINVAL;
+    }
     if (nz < 1 || nz > 65535) {
         set_error("nz must be in 1..65535 (got %d)", nz);
         return LBM3_EINVAL;
     }
     if ((int64_t)p->nx * p->ny * nz > ((int64_t)1 << 29)) {
-        set_error("the D3Q19 form takes at most 2^29 nodes (got %d x %d x %d)", (int)p->nx, (int)p->ny, nz);
+        set_error("the three-dimensional form takes at most 2^29 nodes (got %d x %d x %d)", (int)p->nx, (int)p->ny,
+                  nz);
         return LBM3_EINVAL;
     }
     if (p->forcing != LBM3_FORCING_GUO) {
-        set_error("the D3Q19 form runs the force of Eq. (7) with Guo's term only");
+        set_error("the three-dimensional form runs the force of Eq. (7) with Guo's term only");
         return LBM3_EUNSUPPORTED;
     }
     lbm3d* h = new (std::nothrow) lbm3d();
@@ -670,6 +741,7 @@ int lbm3d_create(const lbm3_params* p, int32_t nz, void* hip_stream, lbm3d_t** o
     }
     h->p = *p;
     h->prec = prec_of(p->precision);
+    h->q = q;
     derive(p, &h->kp, nullptr, nullptr, nullptr);
     h->g = Geo3{p->nx, p->ny, nz, (int64_t)p->nx * p->ny * nz};
     h->stream = (hipStream_t)hip_stream;
@@ -678,28 +750,33 @@ int lbm3d_create(const lbm3_params* p, int32_t nz, void* hip_stream, lbm3d_t** o
     int dev = 0, cus = 0, per_cu = 0;
     e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = march_occupancy(h->prec, &per_cu);
+    if (e == hipSuccess) e = march_occupancy(h->prec, q, &per_cu);
     std::vector<Tile3> tiles;
     if (e == hipSuccess) {
-        tiles = plan3(h->g, per_cu * cus);
+        tiles = plan3(h->g, per_cu * cus, q);
         h->ntiles = (int)tiles.size();
     }
     const size_t eb = h->prec == Prec::F64 ? sizeof(double) : sizeof(float);
-    if (e == hipSuccess) e = alloc_state_pair((size_t)57 * N * eb, h->buf);
+    if (e == hipSuccess) e = alloc_state_pair((size_t)3 * q * N * eb, h->buf);
     if (e == hipSuccess) e = hipMalloc(&h->dtiles, tiles.size() * sizeof(Tile3));
     if (e == hipSuccess)
         e = hipMemcpy(h->dtiles, tiles.data(), tiles.size() * sizeof(Tile3), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&h->partials, tiles.size() * 8 * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&h->staging, (size_t)57 * N * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&h->staging, (size_t)3 * q * N * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&h->rho, (size_t)3 * N * sizeof(double));
     if (e != hipSuccess) {
-        rc = hip_fail(e, "hipMalloc (D3Q19 lattice)");
+        rc = hip_fail(e, "hipMalloc (three-dimensional lattice)");
         release3(h);
         delete h;
         return rc;
     }
     *out = h;
     return LBM3_OK;
+}
+
+int lbm3d_create(const lbm3_params* p, int32_t nz, void* hip_stream, lbm3d_t** out)
+{
+    return lbm3d_create_lattice(p, nz, 19, hip_stream, out);
 }
 
 int lbm3d_init_fields(lbm3d_t* h, const double* rho)
@@ -716,7 +793,7 @@ int lbm3d_init_fields(lbm3d_t* h, const double* rho)
         e = launch_init3(h, (const double*)h->staging);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(e, "D3Q19 init");
+    if (e != hipSuccess) return hip_fail(e, "three-dimensional init");
     h->cur = 0;
     h->step = 0;
     h->ready = true;
@@ -735,7 +812,7 @@ int lbm3d_step(lbm3d_t* h, int64_t n)
     }
     for (int64_t s = 0; s < n; ++s) {
         hipError_t e = launch_march(h, false);
-        if (e != hipSuccess) return hip_fail(e, "D3Q19 step launch");
+        if (e != hipSuccess) return hip_fail(e, "three-dimensional step launch");
         h->cur ^= 1;
         h->step += 1;
     }
@@ -763,10 +840,11 @@ int lbm3d_observables(lbm3d_t* h, lbm3d_obs* out, double* rho_out, double* f_out
         if (e == hipSuccess && rho_out)
             e = hipMemcpyAsync(rho_out, h->rho, (size_t)3 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
         if (e == hipSuccess && f_out)
-            e = hipMemcpyAsync(f_out, h->staging, (size_t)57 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+            e = hipMemcpyAsync(f_out, h->staging, (size_t)3 * h->q * N * sizeof(double), hipMemcpyDeviceToHost,
+                               h->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(e, "D3Q19 observables");
+    if (e != hipSuccess) return hip_fail(e, "three-dimensional observables");
     lbm3d_obs o{};
     o.step = h->step;
     bool finite = true;
@@ -785,7 +863,7 @@ int lbm3d_observables(lbm3d_t* h, lbm3d_obs* out, double* rho_out, double* f_out
     o.nonfinite = finite ? 0 : 1;
     if (out) *out = o;
     if (!finite) {
-        set_error("the D3Q19 state is not finite at step %lld", (long long)h->step);
+        set_error("the three-dimensional state is not finite at step %lld", (long long)h->step);
         return LBM3_ENONFINITE;
     }
     return LBM3_OK;

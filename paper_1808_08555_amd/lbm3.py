@@ -113,6 +113,7 @@ def lib():
                                                 ctypes.c_uint64]),
             "lbm3_device_copy": (I, [_VP, _VP, ctypes.c_int64, _VP]),
             "lbm3d_create": (I, [P, ctypes.c_int32, _VP, ctypes.POINTER(H)]),
+            "lbm3d_create_lattice": (I, [P, ctypes.c_int32, ctypes.c_int32, _VP, ctypes.POINTER(H)]),
             "lbm3d_init_fields": (I, [H, _DP]),
             "lbm3d_step": (I, [H, ctypes.c_int64]),
             "lbm3d_observables": (I, [H, ctypes.POINTER(lbm3d_obs), _DP, _DP]),
@@ -408,17 +409,17 @@ class Lattice:
 
 # ----------------------------------------------------------------- D3Q19 form
 class Lattice3D:
-    """Owning wrapper around one lbm3d handle (the D3Q19 form, periodic; precision "fp64",
-    "fp32_storage" or "fp32")."""
+    """Owning wrapper around one lbm3d handle (the three-dimensional form, periodic; lattice
+    q = 19 (D3Q19) or 27 (D3Q27); precision "fp64", "fp32_storage" or "fp32")."""
 
     def __init__(self, nx: int, ny: int, nz: int, sigma=(0.01, 0.01, 0.01), tau=(1.0, 1.0, 1.0),
                  rho0=(1.0, 1.0, 1.0), beta0: float = 0.7, beta_law="paper", stream=None,
-                 precision: str = "fp64"):
-        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+                 precision: str = "fp64", q: int = 19):
+        self.nx, self.ny, self.nz, self.q = int(nx), int(ny), int(nz), int(q)
         self.params = make_params(nx, ny, sigma, tau, rho0, beta0, precision, beta_law=beta_law)
         h = ctypes.c_void_p()
-        _check(lib().lbm3d_create(ctypes.byref(self.params), self.nz, _stream_handle(stream), ctypes.byref(h)),
-               "lbm3d_create")
+        _check(lib().lbm3d_create_lattice(ctypes.byref(self.params), self.nz, self.q, _stream_handle(stream),
+                                          ctypes.byref(h)), "lbm3d_create_lattice")
         self.h = h
 
     def init(self, rho):
@@ -432,11 +433,11 @@ class Lattice3D:
         return self
 
     def observables(self, want_rho: bool = False, want_f: bool = False):
-        """(dict, rho [3, nz, ny, nx] or None, f [3, 19, nz, ny, nx] or None); blocking."""
+        """(dict, rho [3, nz, ny, nx] or None, f [3, q, nz, ny, nx] or None); blocking."""
         o = lbm3d_obs()
         shape = (self.nz, self.ny, self.nx)
         rho = np.empty((3,) + shape) if want_rho else None
-        f = np.empty((3, 19) + shape) if want_f else None
+        f = np.empty((3, self.q) + shape) if want_f else None
         _check(lib().lbm3d_observables(self.h, ctypes.byref(o), _dptr(rho), _dptr(f)), "lbm3d_observables")
         d = {"step": int(o.step), "mass": np.array(o.mass[:]), "momentum": np.array(o.momentum[:]),
              "kinetic_energy": float(o.kinetic_energy), "u_max": float(o.u_max), "nonfinite": int(o.nonfinite)}

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     text = open(os.path.join(ROOT, "include", "lbm3.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm3_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lbm3d?_\w+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 20
     out = subprocess.run(["nm", "-D", "--defined-only", lbm3.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
-    exported = set(re.findall(r"\bT (lbm3_\w+)", out))
+    exported = set(re.findall(r"\bT (lbm3d?_\w+)", out))
     missing = [n for n in names if n not in exported]
     assert not missing, missing
     L = lbm3.lib()
@@ -131,7 +131,7 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
     assert "no fallback" in r.stdout
 
 
-def test_d3q19_create_rejects_bad_parameters():
+def test_d3_create_rejects_bad_parameters():
     """Validation happens before any device work, so it runs without a GPU."""
     h = ctypes.c_void_p(12345)
     for kw, nz, code in [(dict(), 0, lbm3.LBM3_EINVAL), (dict(), 65536, lbm3.LBM3_EINVAL),
@@ -139,6 +139,14 @@ def test_d3q19_create_rejects_bad_parameters():
                          (dict(forcing="perturbation"), 4, lbm3.LBM3_EUNSUPPORTED)]:
         p = _params(**kw)
         assert lbm3.lib().lbm3d_create(ctypes.byref(p), nz, None, ctypes.byref(h)) == code, (kw, nz)
+        assert h.value is None
+        h = ctypes.c_void_p(12345)
+        assert lbm3.lib().lbm3d_create_lattice(ctypes.byref(p), nz, 27, None, ctypes.byref(h)) == code, (kw, nz)
+        assert h.value is None
+    # only the D3Q19 and D3Q27 lattices
+    for q in (0, 9, 15, 18, 20, 26, 28):
+        h = ctypes.c_void_p(12345)
+        assert lbm3.lib().lbm3d_create_lattice(ctypes.byref(_params()), 4, q, None, ctypes.byref(h)) == lbm3.LBM3_EINVAL
         assert h.value is None
     assert lbm3.lib().lbm3d_destroy(None) == lbm3.LBM3_OK
 

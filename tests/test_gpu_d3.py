@@ -1,5 +1,6 @@
-"""The D3Q19 form through the C ABI (lbm3d_*) against the D3Q19 oracle, which is pinned to
-the two-dimensional oracle (tests/test_oracle_d3.py)."""
+"""The three-dimensional form through the C ABI (lbm3d_*), on the D3Q19 and the D3Q27
+lattice, against the three-dimensional oracle, which is pinned to the two-dimensional oracle
+(tests/test_oracle_d3.py)."""
 import numpy as np
 import pytest
 
@@ -10,33 +11,36 @@ from paper_1808_08555_amd import inputs, lbm3
 pytestmark = pytest.mark.gpu
 
 SIG, TAU = (0.011, 0.013, 0.017), (0.7, 1.0, 1.3)
+QS = [19, 27]
 
 
-def _gpu(rho, steps, sigma=SIG, tau=TAU, law="paper", precision="fp64"):
+def _gpu(rho, steps, sigma=SIG, tau=TAU, law="paper", precision="fp64", q=19):
     nz, ny, nx = rho.shape[1:]
-    L = lbm3.Lattice3D(nx, ny, nz, sigma, tau, beta_law=law, precision=precision).init(rho)
+    L = lbm3.Lattice3D(nx, ny, nz, sigma, tau, beta_law=law, precision=precision, q=q).init(rho)
     try:
         return L.step(steps).state()
     finally:
         L.close()
 
 
-def _oracle(rho, steps, sigma=SIG, tau=TAU, law="paper"):
+def _oracle(rho, steps, sigma=SIG, tau=TAU, law="paper", q=19):
     nz, ny, nx = rho.shape[1:]
     p = oracle.Params(nx, ny, sigma, tau, beta_law=law)
-    return d3.run(p, nz, d3.init(p, nz, rho), steps)
+    return d3.run(p, nz, d3.init(p, nz, rho, q), steps)
 
 
+@pytest.mark.parametrize("q", QS)
 @pytest.mark.parametrize("law", ["paper", "leclaire"])
-def test_parity_random_mixture(law):
+def test_parity_random_mixture(law, q):
     """13 x 11 x 9 random mixtures (three fluids at most nodes), 10 steps, to 1e-11."""
     rho = inputs.random_mixture_3d(13, 11, 9, 4, tiny_fraction=0.05)
-    err = np.abs(_gpu(rho, 10, law=law) - _oracle(rho, 10, law=law)).max()
-    print(law, err)
+    err = np.abs(_gpu(rho, 10, law=law, q=q) - _oracle(rho, 10, law=law, q=q)).max()
+    print(q, law, err)
     assert err <= 1e-11
 
 
-def test_parity_two_spheres_along_the_trajectory():
+@pytest.mark.parametrize("q", QS)
+def test_parity_two_spheres_along_the_trajectory(q):
     """Tangent spheres of fluids 0 and 1 (R = 6) in fluid 2 on 30 x 26 x 22.  After 50 steps
     the GPU state equals the oracle's to 1e-11.  Further on, round-off differences of the
     colour traces grow about 1.1-1.2x per step (measured: 2e-13 at step 50, 4e-9 at 150,
@@ -45,10 +49,10 @@ def test_parity_two_spheres_along_the_trajectory():
     equals one oracle step to 1e-15."""
     rho = inputs.spheres(30, 26, 22, [(0, 9.0, 13.0, 11.0, 6.0), (1, 21.0, 13.0, 11.0, 6.0)])
     p = oracle.Params(30, 26, SIG, TAU)
-    L = lbm3.Lattice3D(30, 26, 22, SIG, TAU).init(rho)
+    L = lbm3.Lattice3D(30, 26, 22, SIG, TAU, q=q).init(rho)
     try:
         g = L.step(50).state()
-        o = d3.run(p, 22, d3.init(p, 22, rho), 50)
+        o = d3.run(p, 22, d3.init(p, 22, rho, q), 50)
         assert np.abs(g - o).max() <= 1e-11
         L.step(100)
         worst = 0.0
@@ -61,35 +65,40 @@ def test_parity_two_spheres_along_the_trajectory():
         L.close()
 
 
-@pytest.mark.parametrize("shape", [(1, 2, 3), (2, 1, 1), (3, 4, 1), (257, 3, 2)])
-def test_parity_degenerate_and_ragged(shape):
+@pytest.mark.parametrize("q", QS)
+@pytest.mark.parametrize("shape", [(1, 2, 3), (2, 1, 1), (3, 4, 1), (257, 3, 2), (61, 23, 7)])
+def test_parity_degenerate_and_ragged(shape, q):
+    """Lattices narrower than the stencil in some direction, and ragged ones of several tiles
+    in x and y (tiles own 28 x 12 columns for D3Q19 and 28 x 10 for D3Q27)."""
     nx, ny, nz = shape
     rho = inputs.random_mixture_3d(nx, ny, nz, 21, tiny_fraction=0.0)
-    assert np.abs(_gpu(rho, 5) - _oracle(rho, 5)).max() <= 1e-11
+    assert np.abs(_gpu(rho, 5, q=q) - _oracle(rho, 5, q=q)).max() <= 1e-11
 
 
-def test_uniform_along_z_equals_the_2d_step():
+@pytest.mark.parametrize("q3", QS)
+def test_uniform_along_z_equals_the_2d_step(q3):
     """A lattice uniform along z evolves as the two-dimensional lattice (populations summed
     over the links' z component): GPU against GPU, 300 steps."""
     w = inputs.double_droplet(48, 9.0, 1.0, 1.3, seed=2, steps=0)
     rho3 = np.repeat(w.rho[:, None], 4, axis=1)
-    f3 = _gpu(rho3, 300, w.sigma, w.tau)
+    f3 = _gpu(rho3, 300, w.sigma, w.tau, q=q3)
     L = lbm3.Lattice(48, 48, w.sigma, w.tau).init(w.rho)
     f2 = L.step(300).state()
     L.close()
-    e, _ = d3.lattice()
+    e, _ = d3.lattice(q3)
     EX2, EY2 = [0, 1, 0, -1, 0, 1, -1, -1, 1], [0, 0, 1, 0, -1, 1, 1, -1, -1]
     proj = np.zeros_like(f2)
     for q in range(9):
-        for i in range(19):
+        for i in range(q3):
             if e[i, 0] == EX2[q] and e[i, 1] == EY2[q]:
                 proj[:, q] += f3[:, i, 0]
     assert np.abs(proj - f2).max() <= 1e-12
 
 
-def test_observables_match_the_oracle():
+@pytest.mark.parametrize("q", QS)
+def test_observables_match_the_oracle(q):
     rho = inputs.spheres(20, 18, 16, [(0, 7.0, 9.0, 8.0, 4.0), (1, 13.0, 9.0, 8.0, 4.0)])
-    L = lbm3.Lattice3D(20, 18, 16, SIG, TAU).init(rho).step(50)
+    L = lbm3.Lattice3D(20, 18, 16, SIG, TAU, q=q).init(rho).step(50)
     obs, r, f = L.observables(want_rho=True, want_f=True)
     L.close()
     p = oracle.Params(20, 18, SIG, TAU)
@@ -125,7 +134,8 @@ def test_error_paths():
         L.close()
 
 
-def test_sphere_young_laplace():
+@pytest.mark.parametrize("q", QS)
+def test_sphere_young_laplace(q):
     """A sphere of fluid 0 in fluid 2 (48^3, sigma = 0.01, tau = 1, 4000 steps): the pressure
     jump p_in - p_out (p = rho/3, inside r < R/2, outside r > R + 6) against the
     three-dimensional Young-Laplace law 2 sigma / R, with R from the sphere's volume:
@@ -135,7 +145,7 @@ def test_sphere_young_laplace():
     n, ratio = 48, {}
     for R in (8.0, 12.0):
         c = (n - 1) / 2
-        L = lbm3.Lattice3D(n, n, n, (0.01, 0.01, 0.01), (1.0, 1.0, 1.0)).init(
+        L = lbm3.Lattice3D(n, n, n, (0.01, 0.01, 0.01), (1.0, 1.0, 1.0), q=q).init(
             inputs.spheres(n, n, n, [(0, c, c, c, R)]))
         obs, r, _ = L.step(4000).observables(want_rho=True)
         L.close()
@@ -145,27 +155,29 @@ def test_sphere_young_laplace():
         Reff = (3 * (r[0] / tot).sum() / (4 * math.pi)) ** (1 / 3)
         dp = tot[rr < Reff / 2].mean() / 3 - tot[rr > Reff + 6].mean() / 3
         ratio[R] = dp / (2 * 0.01 / Reff)
-        print(f"R={R}: R_eff={Reff:.3f} dp={dp:.4e} ratio={ratio[R]:.4f} u_max={obs['u_max']:.2e}")
+        print(f"D3Q{q} R={R}: R_eff={Reff:.3f} dp={dp:.4e} ratio={ratio[R]:.4f} u_max={obs['u_max']:.2e}")
     assert abs(ratio[12.0] - 1) < 0.04
     assert abs(ratio[12.0] - 1) < abs(ratio[8.0] - 1)
 
 
+@pytest.mark.parametrize("q", QS)
 @pytest.mark.parametrize("precision,rtol", [("fp32_storage", 2e-6), ("fp32", 2e-5)])
-def test_reduced_precision_parity(precision, rtol):
+def test_reduced_precision_parity(precision, rtol, q):
     """FP32 storage (FP64 arithmetic, each stored population rounded stochastically) and FP32
     arithmetic against the FP64 oracle after 10 steps, relative to the largest population:
     a random mixture with interfaces everywhere and two tangent spheres."""
     cases = [inputs.random_mixture_3d(13, 11, 9, 4, tiny_fraction=0.0),
              inputs.spheres(30, 26, 22, [(0, 9.0, 13.0, 11.0, 6.0), (1, 21.0, 13.0, 11.0, 6.0)])]
     for rho in cases:
-        g, o = _gpu(rho, 10, precision=precision), _oracle(rho, 10)
+        g, o = _gpu(rho, 10, precision=precision, q=q), _oracle(rho, 10, q=q)
         err = np.abs(g - o).max() / np.abs(o).max()
-        print(precision, rho.shape, "max rel |df|:", err)
+        print(q, precision, rho.shape, "max rel |df|:", err)
         assert err <= rtol
 
 
+@pytest.mark.parametrize("q", QS)
 @pytest.mark.parametrize("precision,bar", [("fp32_storage", 1e-6), ("fp32", 1.2e-4)])
-def test_reduced_precision_mass_drift(precision, bar):
+def test_reduced_precision_mass_drift(precision, bar, q):
     """Per-fluid mass over 2000 steps of two tangent spheres (R = 8, 40 x 32 x 32): FP32
     storage keeps the drift below 1e-6 (unbiased stochastic rounding), FP32 arithmetic below
     the 2D bar of one ulp (6e-8) per step (1.2e-4).  Stochastic rounding is deterministic:
@@ -173,14 +185,14 @@ def test_reduced_precision_mass_drift(precision, bar):
     rho = inputs.spheres(40, 32, 32, [(0, 12.0, 16.0, 16.0, 8.0), (1, 28.0, 16.0, 16.0, 8.0)])
     runs = []
     for _ in range(2 if precision == "fp32_storage" else 1):
-        L = lbm3.Lattice3D(40, 32, 32, SIG, TAU, precision=precision).init(rho)
+        L = lbm3.Lattice3D(40, 32, 32, SIG, TAU, precision=precision, q=q).init(rho)
         try:
             m0 = L.observables()[0]["mass"]
             obs, r, _ = L.step(2000).observables(want_rho=True)
         finally:
             L.close()
         drift = np.abs(obs["mass"] / m0 - 1).max()
-        print(precision, "mass drift over 2000 steps:", drift)
+        print(q, precision, "mass drift over 2000 steps:", drift)
         assert obs["nonfinite"] == 0 and drift < bar
         runs.append(r)
     if len(runs) == 2:
