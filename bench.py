@@ -214,15 +214,17 @@ def bench_adjoint(torch, lbm3, inputs, n: int, steps: int, every: int):
             "reverse_s": round(t2 - t1, 3), "forward_s": round(t1 - t0, 3)}
 
 
-def bench_d3q19(torch, lbm3, inputs, n: int, steps: int, precision: str = "fp64"):
-    """The D3Q19 form on an n^3 lattice of two tangent spheres, timed with HIP events on the
-    lattice's stream.  Algorithmic bytes: the 57 populations read and written once per
-    update (912 B in FP64, 456 B in FP32 or FP32 storage)."""
+def bench_d3q19(torch, lbm3, inputs, n: int, steps: int, precision: str = "fp64", q: int = 19):
+    """The three-dimensional form (D3Q19, or D3Q27 with q = 27) on an n^3 lattice of two
+    tangent spheres, timed with HIP events on the lattice's stream.  Algorithmic bytes: the 3q
+    populations read and written once per update (D3Q19 912 B in FP64, 456 B in FP32 or FP32
+    storage; D3Q27 1296 B and 648 B)."""
     st = torch.cuda.current_stream()
     c = (n - 1) / 2
     R = n / 8.0
     rho = inputs.spheres(n, n, n, [(0, c - R, c, c, R), (1, c + R, c, c, R)])
-    L = lbm3.Lattice3D(n, n, n, (0.01, 0.01, 0.01), (1.0, 1.0, 1.0), stream=st, precision=precision).init(rho)
+    L = lbm3.Lattice3D(n, n, n, (0.01, 0.01, 0.01), (1.0, 1.0, 1.0), stream=st, precision=precision,
+                       q=q).init(rho)
     L.step(5)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -233,14 +235,15 @@ def bench_d3q19(torch, lbm3, inputs, n: int, steps: int, precision: str = "fp64"
     t = a.elapsed_time(b) / 1e3
     L.close()
     lu = n ** 3 * steps
-    b = 912 if precision == "fp64" else 456
-    res = {"workload": f"D3Q19 {n}^3, two tangent spheres of radius {R:g}, {precision}, {steps} steps",
+    b = 2 * 3 * q * (8 if precision == "fp64" else 4)
+    res = {"workload": f"D3Q{q} {n}^3, two tangent spheres of radius {R:g}, {precision}, {steps} steps",
            "mlups": round(lu / t / 1e6, 1), "bytes_per_lu_stated": b,
            "frac_of_peak": round(b * lu / t / 1e9 / HBM_PEAK_GBS, 4), "kernel": "k3_march (one launch per step)"}
     if n == 128 and precision == "fp64":
         # counters of the committed summary, if taken from the current source
-        res["traffic_over_algorithmic"] = profile_figure("lbm3d_d3q19_128", "pmc", "traffic_over_algorithmic")
-        res["valu_issue_frac"] = profile_figure("lbm3d_d3q19_128", "pmc", "VALU issue fraction")
+        tag = f"lbm3d_d3q{q}_128"
+        res["traffic_over_algorithmic"] = profile_figure(tag, "pmc", "traffic_over_algorithmic")
+        res["valu_issue_frac"] = profile_figure(tag, "pmc", "VALU issue fraction")
     return res
 
 
@@ -305,6 +308,7 @@ def main():
                     help="with --only-plain: the precision timed on the headline workload (its own "
                          "JSON line unless fp64)")
     ap.add_argument("--only-d3q19", action="store_true", help="time the D3Q19 form only (its own JSON line)")
+    ap.add_argument("--only-d3q27", action="store_true", help="time the D3Q27 form only (its own JSON line)")
     ap.add_argument("--only-batched", action="store_true", help="time the batched form only (its own JSON line)")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="time the adjoint on the 2048^2 Janus droplet only (its own JSON line)")
@@ -322,11 +326,12 @@ def main():
     if args.only_batched:
         print(json.dumps({"batched_fp32": bench_batched(torch, lbm3, inputs, args.steps)}), flush=True)
         return
-    if args.only_d3q19:
-        res = bench_d3q19(torch, lbm3, inputs, 128, args.steps)
+    if args.only_d3q19 or args.only_d3q27:
+        q = 27 if args.only_d3q27 else 19
+        res = bench_d3q19(torch, lbm3, inputs, 128, args.steps, q=q)
         # the copy kernel's counters calibrate a PMC run of this mode
         res["device_copy_gbs"] = round(copy_bandwidth(torch, lbm3), 1)
-        print(json.dumps({"d3q19_fp64": res}), flush=True)
+        print(json.dumps({f"d3q{q}_fp64": res}), flush=True)
         return
     if args.only_adjoint:
         res = bench_adjoint(torch, lbm3, inputs, 2048, 200, 20)
@@ -368,6 +373,8 @@ def main():
         log(f"d3q19 {d3}")
         d3r = {prec: bench_d3q19(torch, lbm3, inputs, 128, 60, prec) for prec in ("fp32_storage", "fp32")}
         log(f"d3q19 reduced precision {d3r}")
+        d27 = {prec: bench_d3q19(torch, lbm3, inputs, 128, 40, prec, q=27) for prec in ("fp64", "fp32_storage", "fp32")}
+        log(f"d3q27 {d27}")
         batched = bench_batched(torch, lbm3, inputs, 1000)
         log(f"batched {batched}")
         adjoint = {"janus_256": bench_adjoint(torch, lbm3, inputs, 256, 5000, 100),
@@ -438,6 +445,8 @@ def main():
         line["d3q19_fp64"] = d3
         for prec, v in d3r.items():
             line[f"d3q19_{prec}"] = v
+        for prec, v in d27.items():
+            line[f"d3q27_{prec}"] = v
         line["beta_laws_fp64"] = {
             "workload": "the headline droplet tiling, FP64, 100 timed steps per law",
             **{law: {"mlups": round(v["mlups"], 1), "frac_of_peak": round(v["gbs"] / HBM_PEAK_GBS, 4)}

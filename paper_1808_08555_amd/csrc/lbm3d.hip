@@ -358,28 +358,31 @@ __global__ __launch_bounds__(Tile3Shape<Q>::T) __attribute__((amdgpu_waves_per_e
         if (in1) {
             const uint32_t zo[3] = {zoff(zc - 1), zoff(zc), zoff(zc + 1)};
             rk[0] = rk[1] = rk[2] = C(0);
-            if constexpr (Q == 19) {
-                // one memory round trip per plane: the 57 loads are issued together, and a
+            if constexpr (Q == 19 || sizeof(S) == 4) {
+                // one memory round trip per plane: the 3Q loads are issued together, and a
                 // scheduling barrier keeps the compiler from interleaving the sums with them
-                // (which serialises the loads)
-                C v[3 * Q];
+                // (which serialises the loads).  The values stay in the storage type until
+                // summed (half the registers with FP32 storage: D3Q27 FP32 storage then fits
+                // one batch, 18% faster than one per fluid).
+                S v[3 * Q];
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     const uint32_t o = src(zo, i);
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) v[k * Q + i] = C(ld_plane(B + (int64_t)(k * Q + i) * g.N, o));
+                    for (int k = 0; k < 3; ++k) v[k * Q + i] = ld_plane(B + (int64_t)(k * Q + i) * g.N, o);
                 }
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    ft[i] = v[i] + v[Q + i] + v[2 * Q + i];
-                    rk[0] += v[i];
-                    rk[1] += v[Q + i];
-                    rk[2] += v[2 * Q + i];
+                    const C a = C(v[i]), b = C(v[Q + i]), c = C(v[2 * Q + i]);
+                    ft[i] = a + b + c;
+                    rk[0] += a;
+                    rk[1] += b;
+                    rk[2] += c;
                 }
             } else {
-                // one round trip per fluid (all 81 values of a plane would not fit beside the
-                // live registers); the totals add the fluids in the same order
+                // D3Q27 in FP64: one round trip per fluid (all 81 values of a plane would not
+                // fit beside the live registers); the totals add the fluids in the same order
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     C v[Q];
