@@ -69,7 +69,8 @@ def test_parity_two_spheres_along_the_trajectory(q):
 @pytest.mark.parametrize("shape", [(1, 2, 3), (2, 1, 1), (3, 4, 1), (257, 3, 2), (61, 23, 7)])
 def test_parity_degenerate_and_ragged(shape, q):
     """Lattices narrower than the stencil in some direction, and ragged ones of several tiles
-    in x and y (tiles own 28 x 12 columns for D3Q19 and 28 x 10 for D3Q27)."""
+    in x and y (tiles own 28 x 12 columns for D3Q19 and 28 x 10 for D3Q27 in FP64 arithmetic,
+    28 x 20 in FP32)."""
     nx, ny, nz = shape
     rho = inputs.random_mixture_3d(nx, ny, nz, 21, tiny_fraction=0.0)
     assert np.abs(_gpu(rho, 5, q=q) - _oracle(rho, 5, q=q)).max() <= 1e-11
