@@ -183,13 +183,15 @@ int lbm3_set_tile(lbm3_t *h, int32_t threads, int32_t rows);
 int lbm3_get_tile(const lbm3_t *h, int32_t *threads, int32_t *rows);
 
 /* How many steps one launch advances in lbm3_step: 0 = chosen by size (two on
- * lattices of 2^18 nodes or more in FP64, 2^20 in FP32 and FP32 storage), 1 = one,
- * 2 = two where possible.  A two-step
- * launch keeps the intermediate state on chip (in every precision; the first
- * step of a state loaded in 27-population form runs alone) and needs
- * a tile width (lbm3_set_tile's threads) of at most 256; otherwise, and for the
- * odd last step, a one-step launch runs.  Results do not depend on the mode
- * (bitwise).  EINVAL for another mode. */
+ * lattices of 2^19 nodes or more in FP64, of more than 2^20 in FP32 and FP32
+ * storage), 1 = one, 2 = two where possible.  A two-step launch keeps the
+ * intermediate state on chip (in every precision; the first step of a state loaded
+ * in 27-population form runs alone) and needs a tile width (lbm3_set_tile's
+ * threads) of at most 256; otherwise, and for the odd last step, a one-step launch
+ * runs.  One-step launches on lattices of at most 2^20 nodes take two-dimensional
+ * blocks of 28 x 12 nodes (no row march) unless lbm3_set_tile chose a shape.
+ * Results do not depend on the mode or the kernel (bitwise).  EINVAL for another
+ * mode. */
 int lbm3_set_steps_per_launch(lbm3_t *h, int32_t mode);
 /* The launch lbm3_step uses for pairs of steps: *steps = 2 with its threads per
  * workgroup and workgroup count, or *steps = 1 (and zeros) when pairs run as two

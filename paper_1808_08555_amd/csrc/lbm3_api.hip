@@ -239,6 +239,12 @@ int check_rho_fields(const double* rho, const double* u, int64_t n)
 // two-step pass exists, its own with the wider halo) and uploads them with the one-entry
 // instance table.  The two-step pass exists for every precision (64 to 256 threads); rows
 // requested explicitly apply to both lists.
+// Lattices up to this many nodes take their single steps on the block kernel (measured
+// against the row march's single step: 1.7-1.9x faster at 128^2 and 256^2, 1.4-1.5x at
+// 512^2 in FP32 and FP32 storage; at 1448^2 the march, 15.2k / 20.6k / 29.4k MLUPS in
+// FP64 / FP32 storage / FP32, runs below the two-step pass anyway).
+constexpr int64_t kBlockMaxNodes = (int64_t)1 << 20;
+
 int upload_plan(lbm3* h)
 {
     int rows = h->rows_request;
@@ -248,12 +254,14 @@ int upload_plan(lbm3* h)
     std::vector<Tile> L, L2;
     plan_lattice(0, h->kp.nx, h->kp.ny, h->threads, rows, eb, L);
     // The two-step pass halves the traffic per step but needs a 12-row warm-up per tile:
-    // it wins on large lattices (measured, two vs one step per launch: FP64 +52% at 4096^2,
-    // +31% at 1024^2, +12% at 512^2; FP32 +36% at 4096^2, +4% at 1024^2, -17% at 512^2).
-    // Its own default width: 64 columns below 768 (512^2 FP64: +6% over 256), else 256
-    // (FP64: 512 lanes, one step per wave group); lbm3_set_tile's width applies to both
-    // passes.
-    const int64_t min2 = (int64_t)1 << (h->prec == Prec::F64 ? 18 : 20);
+    // it wins on large lattices.  Below, single steps on the block kernel win (measured,
+    // square compound droplets, block step vs two-step pass: FP64 12.0k vs 10.2k MLUPS at
+    // 512^2, 15.8k vs 16.5k at 768^2, 17.3k vs 20.8k at 1024^2; FP32 storage 17.7k vs 17.3k
+    // and FP32 31.2k vs 26.7k at 1024^2).  So pairs from 2^19 nodes in FP64 and above 2^20
+    // in FP32 and FP32 storage.  The pass's own default width: 64 columns below 768 (512^2
+    // FP64: +6% over 256), else 256 (FP64: 512 lanes, one step per wave group);
+    // lbm3_set_tile's width applies to both passes.
+    const int64_t min2 = h->prec == Prec::F64 ? (int64_t)1 << 19 : ((int64_t)1 << 20) + 1;
     const bool big = (int64_t)h->kp.nx * h->kp.ny >= min2;
     const bool want2 = h->pass_mode == 2 || (h->pass_mode == 0 && big);
     int t2 = h->tile_set ? h->threads : (h->kp.nx < 768 ? 64 : 256);
@@ -264,14 +272,21 @@ int upload_plan(lbm3* h)
         plan_lattice(0, h->kp.nx, h->kp.ny, t2, rows2, eb, L2, 6);
     }
     h->threads2 = t2;
-    std::vector<Tile> T = xcd_order(L, 8), T2 = xcd_order(L2, 8);
+    // Single steps of a small lattice go to the block kernel (no march warm-up), unless
+    // lbm3_set_tile chose a march shape.
+    std::vector<Tile> LB;
+    if (!h->tile_set && h->pass_mode != 2 && (int64_t)h->kp.nx * h->kp.ny <= kBlockMaxNodes)
+        plan_blocks(0, h->kp.nx, h->kp.ny, LB);
+    std::vector<Tile> T = xcd_order(L, 8), T2 = xcd_order(L2, 8), TB = xcd_order(LB, 8);
     (void)hipStreamSynchronize(h->stream);
     if (h->dtiles) (void)hipFree(h->dtiles);
     if (h->dtiles2) (void)hipFree(h->dtiles2);
-    h->dtiles = h->dtiles2 = nullptr;
-    h->ntiles = h->ntiles2 = 0;
+    if (h->dtilesb) (void)hipFree(h->dtilesb);
+    h->dtiles = h->dtiles2 = h->dtilesb = nullptr;
+    h->ntiles = h->ntiles2 = h->ntilesb = 0;
     hipError_t e = hipMalloc((void**)&h->dtiles, T.size() * sizeof(Tile));
     if (e == hipSuccess && !T2.empty()) e = hipMalloc((void**)&h->dtiles2, T2.size() * sizeof(Tile));
+    if (e == hipSuccess && !TB.empty()) e = hipMalloc((void**)&h->dtilesb, TB.size() * sizeof(Tile));
     if (e == hipSuccess && !h->dinst) e = hipMalloc((void**)&h->dinst, sizeof(Instance));
     Instance I{};
     I.kp = h->kp;
@@ -279,10 +294,13 @@ int upload_plan(lbm3* h)
     if (e == hipSuccess) e = hipMemcpy(h->dtiles, T.data(), T.size() * sizeof(Tile), hipMemcpyHostToDevice);
     if (e == hipSuccess && !T2.empty())
         e = hipMemcpy(h->dtiles2, T2.data(), T2.size() * sizeof(Tile), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !TB.empty())
+        e = hipMemcpy(h->dtilesb, TB.data(), TB.size() * sizeof(Tile), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h->dinst, &I, sizeof I, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "tile plan upload");
     h->ntiles = (int)T.size();
     h->ntiles2 = (int)T2.size();
+    h->ntilesb = (int)TB.size();
     h->rows = rows;
     return LBM3_OK;
 }
@@ -300,6 +318,9 @@ int step_handle(lbm3* h, int64_t n)
             e = launch_pair(h->prec, h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst, h->dtiles2, h->ntiles2,
                             h->threads2, h->step, h->stream, pt);
             done = 2;
+        } else if (h->fmt == Fmt::FAC && h->ntilesb > 0) {
+            e = launch_block(h->prec, h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst, h->dtilesb, h->ntilesb,
+                             h->step, h->stream, pt);
         } else {
             e = launch_tiles(h->prec, h->fmt, Fmt::FAC, h->buf[h->cur], h->buf[h->cur ^ 1], h->dinst,
                              h->dtiles, h->ntiles, h->threads, h->step, 0, h->stream, pt);
@@ -621,6 +642,7 @@ int lbm3_destroy(lbm3_t* h)
     if (h->obs_host) (void)hipHostFree(h->obs_host);
     if (h->dtiles) (void)hipFree(h->dtiles);
     if (h->dtiles2) (void)hipFree(h->dtiles2);
+    if (h->dtilesb) (void)hipFree(h->dtilesb);
     if (h->dinst) (void)hipFree(h->dinst);
     adjoint_destroy(h);
     delete h;

@@ -25,6 +25,8 @@ struct lbm3 {
     tcg::Tile* dtiles2 = nullptr;       // tile list of the two-step pass (null: not used)
     int ntiles2 = 0;
     int threads2 = 0;                   // its threads per workgroup
+    tcg::Tile* dtilesb = nullptr;       // block list of the one-step block kernel (null: not used)
+    int ntilesb = 0;
     int pass_mode = 0;                  // steps per launch: 0 automatic, 1 one, 2 two
     bool tile_set = false;              // launch shape chosen by lbm3_set_tile
     double* staging = nullptr;          // device FP64 staging for host transfers

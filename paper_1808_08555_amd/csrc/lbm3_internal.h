@@ -111,6 +111,9 @@ void plan_lattice(int inst, int nx, int ny, int threads, int rows, int elem_byte
 // receives one contiguous run of it, keeping neighbouring tiles, and the halos they share, in
 // the same L2.
 std::vector<Tile> xcd_order(const std::vector<Tile>& L, int nxcd);
+// Blocks of one lattice for launch_block: at most kBlockCols x kBlockRows nodes each, sizes
+// spread evenly over nx and ny, row of blocks after row of blocks.
+void plan_blocks(int inst, int nx, int ny, std::vector<Tile>& out);
 // The two state buffers of a step (read one, write the other) in one allocation, the second
 // an odd number of MiB after the first (see lbm3_plan.hip); buf[1] is not freed on its own.
 hipError_t alloc_state_pair(size_t bytes, void* buf[2]);
@@ -170,6 +173,19 @@ int tiles_f32s_pair_occupancy(int threads);
 hipError_t launch_pair(Prec prec, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                        int ntiles, int threads, int64_t step, hipStream_t stream, bool pt = false,
                        const int64_t* step_dev = nullptr);
+// One step (factored state in and out) on two-dimensional blocks: tiles from plan_blocks,
+// workgroups of kBlockThreads lanes; bitwise the same as the march's step.  pt, step and
+// step_dev as for launch_tiles.
+constexpr int kBlockCols = 28, kBlockRows = 12, kBlockThreads = 512;
+hipError_t tiles_f64_block(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                           uint32_t salt, const int64_t* step_dev, bool pt, hipStream_t stream);
+hipError_t tiles_f32_block(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                           uint32_t salt, const int64_t* step_dev, bool pt, hipStream_t stream);
+hipError_t tiles_f32s_block(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                            uint32_t salt, const int64_t* step_dev, bool pt, hipStream_t stream);
+hipError_t launch_block(Prec prec, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
+                        int ntiles, int64_t step, hipStream_t stream, bool pt = false,
+                        const int64_t* step_dev = nullptr);
 
 // Host-side helpers (lbm3_api.hip).
 void set_error(const char* fmt, ...);

@@ -53,6 +53,28 @@ void plan_lattice(int inst, int nx, int ny, int threads, int rows, int elem_byte
             }
 }
 
+void plan_blocks(int inst, int nx, int ny, std::vector<Tile>& out)
+{
+    const int nbx = (nx + kBlockCols - 1) / kBlockCols, nby = (ny + kBlockRows - 1) / kBlockRows;
+    int y0 = 0;
+    for (int by = 0; by < nby; ++by) {
+        const int rows = ny / nby + (by < ny % nby ? 1 : 0);
+        int x0 = 0;
+        for (int bx = 0; bx < nbx; ++bx) {
+            const int cols = nx / nbx + (bx < nx % nbx ? 1 : 0);
+            Tile t{};
+            t.inst = inst;
+            t.x0 = x0;
+            t.y0 = y0;
+            t.rows = rows;
+            t.cols = cols;
+            out.push_back(t);
+            x0 += cols;
+        }
+        y0 += rows;
+    }
+}
+
 std::vector<Tile> xcd_order(const std::vector<Tile>& L, int nxcd)
 {
     const int T = (int)L.size();

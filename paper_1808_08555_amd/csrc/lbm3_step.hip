@@ -167,6 +167,18 @@ hipError_t launch_tiles(Prec prec, Fmt in, Fmt out, const void* fin, void* fout,
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_block(Prec prec, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
+                        int ntiles, int64_t step, hipStream_t st, bool pt, const int64_t* step_dev)
+{
+    const uint32_t salt = step_salt(step);
+    switch (prec) {
+        case Prec::F64: return tiles_f64_block(fin, fout, inst, tiles, ntiles, salt, nullptr, pt, st);
+        case Prec::F32S: return tiles_f32s_block(fin, fout, inst, tiles, ntiles, salt, step_dev, pt, st);
+        case Prec::F32: return tiles_f32_block(fin, fout, inst, tiles, ntiles, salt, nullptr, pt, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_advance_step(int64_t* step_dev, int64_t n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(64), 0, st, step_dev, n);

@@ -1578,5 +1578,155 @@ int tiles_occupancy(int threads)
     }
 }
 
+// ---- One step on two-dimensional blocks (small lattices)
+// The row march pays a warm-up of six rows per segment and one barrier-separated memory
+// round trip per row; on a small lattice, whose segments must be short to fill the device,
+// that is most of its time.  Here a workgroup of BX x BY lanes (lane t at column t % BX,
+// row t / BX) owns the output nodes [x0, x0 + cols) x [y0, y0 + rows), cols <= BX - 4 and
+// rows <= BY - 4, and lane (tx, ty) sits on node (x0 - 2 + tx, y0 - 2 + ty): all rows at
+// once, one load round trip, three barriers.
+//   1. every lane issues the loads of its node's pull (the f_dag_i at x - e_i) and the
+//      workgroup stages the c_k, V_k of the nodes within three of the block in LDS;
+//   2. lanes within two of the block: densities and totals, the groups of pull_row in its
+//      order (so every sum rounds as in the march); c_k to LDS;
+//   3. lanes within one: gradients, pair normals and stress (stress_at_lane); T to LDS;
+//   4. the owned lanes: force (force_or_stress), collision and recolouring
+//      (collide_recolour), the factored store, rounded as the march rounds it.
+// Factored input and output only (a state in the 27-population format takes one step of
+// the march first).
+constexpr int kBlockX = 32, kBlockY = 16;
+static_assert(kBlockX - 4 == kBlockCols && kBlockY - 4 == kBlockRows && kBlockX * kBlockY == kBlockThreads,
+              "block plan and kernel agree");
+
+template <typename C, int BX, int BY>
+struct alignas(16) BlockLds {
+    C cv[BY + 2][9][BX + 2];  // c_k, V_0, V_1, V_2 of the nodes one ring beyond the lanes'
+    C c[BY][3][BX];           // c_k of the lanes' nodes
+    C T[BY][3][BX];           // stress of the lanes' nodes
+};
+
+template <typename S, typename C, int BX, int BY, bool PT>
+__global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(2))) void k_block(
+    const S* __restrict__ fin, S* __restrict__ fout, const Instance* __restrict__ inst,
+    const Tile* __restrict__ tiles, uint32_t salt, const int64_t* __restrict__ step_dev)
+{
+    static_assert(BX % 64 == 0 || 64 % BX == 0, "waves are whole tile rows");
+    __shared__ BlockLds<C, BX, BY> L;
+    const Tile tl = tiles[blockIdx.x];
+    const KParams kp = inst[tl.inst].kp;
+    const int64_t off = inst[tl.inst].offset;
+    fin += off;
+    fout += off;
+    if constexpr (kRounds<S, C>) {
+        if (step_dev) salt = step_salt(*step_dev);
+    }
+    const int nx = kp.nx, ny = kp.ny, cols = tl.cols, rows = tl.rows;
+    const int64_t plane = kp.plane, pitch = kp.fpitch;
+    const int t = threadIdx.x, tx = t % BX, ty = t / BX;
+    const bool in1 = tx <= cols + 3 && ty <= rows + 3;
+    const bool in2 = tx >= 1 && tx <= cols + 2 && ty >= 1 && ty <= rows + 2;
+    const bool in3 = tx >= 2 && tx <= cols + 1 && ty >= 2 && ty <= rows + 1;
+    const int x = wrapi(tl.x0 - 2 + tx, nx), y = wrapi(tl.y0 - 2 + ty, ny);
+    const StepConsts<C> K(kp);
+    // 1. the pull's f_dag_i (in flight while the c_k, V_k are staged)
+    S fq[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fq[i] = S(0);
+    if (in1) {
+        const int xs[3] = {wrapi(x + 1, nx), x, wrapi(x - 1, nx)};  // by e_x + 1
+        const int64_t ys[3] = {(int64_t)wrapi(y + 1, ny) * pitch, (int64_t)y * pitch,
+                               (int64_t)wrapi(y - 1, ny) * pitch};  // by e_y + 1
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fq[i] = fin[(int64_t)i * plane + ys[EY[i] + 1] + xs[EX[i] + 1]];
+    }
+    // node (x0 - 3 + u, y0 - 3 + w) at cv[w][.][u]
+    const int CW = cols + 6, CH = rows + 6;
+    for (int e = t; e < CW * CH; e += BX * BY) {
+        const int w = e / CW, u = e - w * CW;
+        const int64_t o = (int64_t)wrapi(tl.y0 - 3 + w, ny) * pitch + wrapi(tl.x0 - 3 + u, nx);
+        C v[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) v[q] = C(fin[(int64_t)(9 + q) * plane + o]);
+#pragma unroll
+        for (int q = 0; q < 7; ++q) L.cv[w][q][u] = v[q];
+        L.cv[w][7][u] = fac_v2<C>(v[3], v[5]);
+        L.cv[w][8][u] = fac_v2<C>(v[4], v[6]);
+    }
+    __syncthreads();
+    // 2. densities and totals: the source rows' groups (e_y = +1, 0, -1) as pull_row adds them
+    C r0[3] = {C(1), C(1), C(1)}, f0[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f0[i] = C(0);
+    if (in1) {
+        auto pull = [&](int i, C (&fk)[3]) {
+            const int u = tx + 1 - EX[i], w = ty + 1 - EY[i];
+            const C fdi = C(fq[i]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                fk[k] = recon<C>(L.cv[w][k][u], fdi, L.cv[w][3 + 2 * k][u], L.cv[w][4 + 2 * k][u], i);
+        };
+        auto group = [&](int a, int b, int c, C (&g)[3]) {
+            C fa[3], fb[3], fc[3];
+            pull(a, fa);
+            pull(b, fb);
+            pull(c, fc);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) g[k] = group_sum<C>(fa[k], fb[k], fc[k]);
+            f0[a] = (fa[0] + fa[1]) + fa[2];
+            f0[b] = (fb[0] + fb[1]) + fb[2];
+            f0[c] = (fc[0] + fc[1]) + fc[2];
+        };
+        C gp[3], gz[3], gm[3];
+        group(2, 5, 6, gp);
+        group(0, 1, 3, gz);
+        group(4, 7, 8, gm);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r0[k] = (gp[k] + gz[k]) + gm[k];
+        const C irho = recip((r0[0] + r0[1]) + r0[2]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) L.c[ty][k][tx] = r0[k] * irho;
+    }
+    __syncthreads();
+    // 3. stress (rows: ty + 1 above, ty, ty - 1 below)
+    C n[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
+    if (in2) {
+        C Txx, Txy, Tyy;
+        stress_at_lane<C, BX>(L.c, ty + 1, ty, ty - 1, tx, r0, K, n, Txx, Txy, Tyy);
+        L.T[ty][0][tx] = Txx;
+        L.T[ty][1][tx] = Txy;
+        L.T[ty][2][tx] = Tyy;
+    }
+    __syncthreads();
+    // 4. force, collision, recolouring, store
+    if (in3) {
+        C Fx, Fy, Tn[3];
+        force_or_stress<C, BX, PT>(L.T, ty - 1, ty + 1, ty, tx, Fx, Fy, Tn);
+        C fd[9], ck[3], V[6], ux, uy, mxh, myh;
+        collide_recolour<C, PT>(f0, r0, n, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
+        NodeBits bits(((uint32_t)y * (uint32_t)nx + (uint32_t)x) * 27u ^ salt);
+        S* o = fout + (int64_t)y * pitch + x;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) o[(int64_t)i * plane] = to_storage<S, C>(fd[i], bits);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) o[(int64_t)(9 + k) * plane] = to_storage<S, C>(ck[k], bits);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[(int64_t)(12 + q) * plane] = to_storage<S, C>(V[q], bits);
+    }
+}
+
+template <typename S, typename C>
+hipError_t tiles_block_any(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                           uint32_t salt, const int64_t* step_dev, bool pt, hipStream_t st)
+{
+    constexpr int BX = kBlockX, BY = kBlockY;
+    if (pt)
+        hipLaunchKernelGGL((k_block<S, C, BX, BY, true>), dim3(ntiles), dim3(BX * BY), 0, st, (const S*)fin,
+                           (S*)fout, inst, tiles, salt, step_dev);
+    else
+        hipLaunchKernelGGL((k_block<S, C, BX, BY, false>), dim3(ntiles), dim3(BX * BY), 0, st, (const S*)fin,
+                           (S*)fout, inst, tiles, salt, step_dev);
+    return hipGetLastError();
+}
+
 }  // namespace
 }  // namespace tcg

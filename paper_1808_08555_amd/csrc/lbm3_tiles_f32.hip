@@ -21,4 +21,10 @@ hipError_t tiles_f32_pair(const void* fin, void* fout, const Instance* inst, con
 
 int tiles_f32_pair_occupancy(int threads) { return pair_occupancy<float, float>(threads); }
 
+hipError_t tiles_f32_block(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                              uint32_t salt, const int64_t* step_dev, bool pt, hipStream_t stream)
+{
+    return tiles_block_any<float, float>(fin, fout, inst, tiles, ntiles, salt, step_dev, pt, stream);
+}
+
 }  // namespace tcg

@@ -23,4 +23,10 @@ hipError_t tiles_f32s_pair(const void* fin, void* fout, const Instance* inst, co
 
 int tiles_f32s_pair_occupancy(int threads) { return pair_occupancy<float, double>(threads); }
 
+hipError_t tiles_f32s_block(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                               uint32_t salt, const int64_t* step_dev, bool pt, hipStream_t stream)
+{
+    return tiles_block_any<float, double>(fin, fout, inst, tiles, ntiles, salt, step_dev, pt, stream);
+}
+
 }  // namespace tcg

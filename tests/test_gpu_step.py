@@ -196,13 +196,17 @@ def test_double_droplet_1024_janus_junction_angles(precision, r12, r13):
 @pytest.mark.parametrize("precision,rtol", [("fp32", 2e-5), ("fp32_storage", 2e-6)])
 def test_double_droplet_1024_reduced_precision(precision, rtol):
     """The 1024^2 double droplet (two tangent disks of radius 100 in fluid 3, interface
-    noise) in its default launch configuration (two steps per launch): 10 steps
-    against the FP64 oracle element by element, then per-fluid mass drift over 2000 steps
-    within DRIFT_2000."""
+    noise) in its default launch configuration (one step per launch on blocks; then again
+    with two steps per launch): 10 steps against the FP64 oracle element by element, then
+    per-fluid mass drift over 2000 steps within DRIFT_2000."""
     w, o = _double_droplet_1024()
     L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, w.rho0, w.beta0, precision).init(w.rho)
+    L2 = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, w.rho0, w.beta0, precision).init(w.rho).set_steps_per_launch(2)
     try:
-        assert lbm3.lbm3_get_pair_launch(L.h)[0] == 2
+        assert lbm3.lbm3_get_pair_launch(L.h)[0] == 1 and lbm3.lbm3_get_pair_launch(L2.h)[0] == 2
+        assert np.array_equal(L2.step(10).state(), L.step(10).state())
+        L.close()
+        L = lbm3.Lattice(w.nx, w.ny, w.sigma, w.tau, w.rho0, w.beta0, precision).init(w.rho)
         m0 = L.observables()[0]["mass"]
         g = L.step(10).state()
         err = np.abs(g - o).max() / np.abs(o).max()
@@ -214,6 +218,7 @@ def test_double_droplet_1024_reduced_precision(precision, rtol):
         assert obs["nonfinite"] == 0 and drift < DRIFT_2000[precision]
     finally:
         L.close()
+        L2.close()
 
 
 def test_observables_match_oracle():
@@ -652,6 +657,35 @@ def test_two_step_pass_equals_single_steps_bitwise(shape, tile, precision):
     assert lbm3.lbm3_get_pair_launch(A.h)[0] == 1
     A.step(12)
     B.step(12)
+    fa, fb = A.state(), B.state()
+    A.close()
+    B.close()
+    assert np.isfinite(fa).all()
+    assert np.array_equal(fa, fb)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_storage"])
+@pytest.mark.parametrize("forcing", ["guo", "perturbation"])
+@pytest.mark.parametrize("shape", [(64, 64), (37, 29), (57, 25), (100, 61), (256, 256), (29, 13), (1, 1),
+                                   (3, 2), (2, 7), (1, 40), (70, 1)])
+def test_block_step_equals_march_bitwise(shape, forcing, precision):
+    """Single steps of a small lattice run on the block kernel (no row march); they must
+    give the march's state bit for bit (the march is what a lattice with a chosen launch
+    shape runs): ragged blocks, one-block lattices and lattices narrower than the halo."""
+    nx, ny = shape
+    if min(nx, ny) < 8:
+        rho = inputs.random_mixture(nx, ny, 5, tiny_fraction=0.05)
+    else:
+        R = min(nx, ny) * 0.2
+        disks = [(0, nx * 0.3, ny * 0.5, R), (1, nx * 0.7, ny * 0.5, R)]
+        lab = inputs.label_disks(nx, ny, disks)
+        rho = inputs.add_interface_noise(inputs.rho_from_labels(lab), lab, disks, seed=7)
+    sig, tau = (0.011, 0.013, 0.017), (0.7, 1.0, 1.3)
+    kw = dict(precision=precision, forcing=forcing)
+    A = lbm3.Lattice(nx, ny, sig, tau, **kw).init(rho).set_steps_per_launch(1)
+    B = lbm3.Lattice(nx, ny, sig, tau, **kw).init(rho).set_steps_per_launch(1).set_tile(64, 0)
+    A.step(9)
+    B.step(9)
     fa, fb = A.state(), B.state()
     A.close()
     B.close()
