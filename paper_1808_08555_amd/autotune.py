@@ -47,16 +47,21 @@ def _arch(torch) -> str:
 
 
 def _time(torch, fn, steps: int) -> float:
+    """Median of three timings of `steps` steps, after `steps` untimed ones: a batch
+    re-captures its graph after a shape change, and that must not land in a timed run."""
     st = torch.cuda.current_stream()
-    fn(2)
-    torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record(st)
     fn(steps)
-    b.record(st)
     torch.cuda.synchronize()
-    return a.elapsed_time(b) / steps
+    ts = []
+    for _ in range(3):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        fn(steps)
+        b.record(st)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b) / steps)
+    return sorted(ts)[1]
 
 
 def _cell_fields(nx: int, ny: int):

@@ -91,6 +91,20 @@ int main()
                         int tp = 0, tr = 0;
                         default_tile(KParams{}, Prec::F64, &tp, &tr);
                     }
+    // block plans: every node in exactly one block of at most kBlockCols x kBlockRows
+    for (int nx : {1, 2, 27, 28, 29, 57, 256, 1000, 65535})
+        for (int ny : {1, 11, 12, 13, 100, 1024}) {
+            std::vector<Tile> L;
+            plan_blocks(2, nx, ny, L);
+            std::vector<unsigned char> hit((size_t)nx * ny, 0);
+            for (const Tile& t : L) {
+                bad |= t.inst != 2 || t.cols < 1 || t.cols > kBlockCols || t.rows < 1 || t.rows > kBlockRows;
+                bad |= t.x0 < 0 || t.y0 < 0 || t.x0 + t.cols > nx || t.y0 + t.rows > ny;
+                for (int y = t.y0; y < t.y0 + t.rows; ++y)
+                    for (int x = t.x0; x < t.x0 + t.cols; ++x) ++hit[(size_t)y * nx + x];
+            }
+            for (unsigned char h : hit) bad |= h != 1;
+        }
     // the adjoint's two-slot rule
     for (int64_t nodes : {(int64_t)1, (int64_t)1 << 21, (int64_t)1 << 22})
         for (uint64_t free_b : {0ull, 1ull << 20, 1ull << 40})
