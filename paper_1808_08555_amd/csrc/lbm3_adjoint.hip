@@ -719,9 +719,16 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     // (segment 0 starts from the 27-population state and runs eagerly).
     auto recompute = [&](hipStream_t q, Fmt in, int b) -> hipError_t {
         hipError_t r = hipSuccess;
-        for (int j = 0; j < K && r == hipSuccess; ++j)
-            r = tiles_f64_tape(j == 0 ? in : Fmt::FAC, fwd[b][j & 1], fwd[b][(j + 1) & 1], h->dinst, h->dtiles,
-                               h->ntiles, h->threads, tape[b] + (size_t)j * kTapeFields * N, q);
+        for (int j = 0; j < K && r == hipSuccess; ++j) {
+            const Fmt fj = j == 0 ? in : Fmt::FAC;
+            double* tj = tape[b] + (size_t)j * kTapeFields * N;
+            // small lattices: the block step (as the forward steps took), else the march
+            r = fj == Fmt::FAC && h->ntilesb > 0
+                    ? tiles_f64_block_tape(fwd[b][j & 1], fwd[b][(j + 1) & 1], h->dinst, h->dtilesb, h->ntilesb, tj,
+                                           q)
+                    : tiles_f64_tape(fj, fwd[b][j & 1], fwd[b][(j + 1) & 1], h->dinst, h->dtiles, h->ntiles,
+                                     h->threads, tj, q);
+        }
         return r;
     };
     auto reverse = [&](hipStream_t q, int b, int cl0) -> hipError_t {

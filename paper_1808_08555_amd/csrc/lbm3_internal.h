@@ -183,6 +183,10 @@ hipError_t tiles_f32_block(const void* fin, void* fout, const Instance* inst, co
                            uint32_t salt, const int64_t* step_dev, bool pt, hipStream_t stream);
 hipError_t tiles_f32s_block(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
                             uint32_t salt, const int64_t* step_dev, bool pt, hipStream_t stream);
+// The FP64 block step (factored state in) that also writes the adjoint's tape, as
+// tiles_f64_tape does.
+hipError_t tiles_f64_block_tape(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                                double* tape, hipStream_t stream);
 hipError_t launch_block(Prec prec, const void* fin, void* fout, const Instance* inst, const Tile* tiles,
                         int ntiles, int64_t step, hipStream_t stream, bool pt = false,
                         const int64_t* step_dev = nullptr);

@@ -1593,7 +1593,8 @@ int tiles_occupancy(int threads)
 //   4. the owned lanes: force (force_or_stress), collision and recolouring
 //      (collide_recolour), the factored store, rounded as the march rounds it.
 // Factored input and output only (a state in the 27-population format takes one step of
-// the march first).
+// the march first).  With TAPE (FP64) the owned lanes also write the adjoint's tape as the
+// march does: densities, totals, concentration gradients and force, tape[20][ny][nx].
 constexpr int kBlockX = 32, kBlockY = 16;
 static_assert(kBlockX - 4 == kBlockCols && kBlockY - 4 == kBlockRows && kBlockX * kBlockY == kBlockThreads,
               "block plan and kernel agree");
@@ -1605,10 +1606,11 @@ struct alignas(16) BlockLds {
     C T[BY][3][BX];           // stress of the lanes' nodes
 };
 
-template <typename S, typename C, int BX, int BY, bool PT>
+template <typename S, typename C, int BX, int BY, bool PT, bool TAPE = false>
 __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(2))) void k_block(
     const S* __restrict__ fin, S* __restrict__ fout, const Instance* __restrict__ inst,
-    const Tile* __restrict__ tiles, uint32_t salt, const int64_t* __restrict__ step_dev)
+    const Tile* __restrict__ tiles, uint32_t salt, const int64_t* __restrict__ step_dev,
+    double* __restrict__ tape = nullptr)
 {
     static_assert(BX % 64 == 0 || 64 % BX == 0, "waves are whole tile rows");
     __shared__ BlockLds<C, BX, BY> L;
@@ -1686,12 +1688,34 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
         for (int k = 0; k < 3; ++k) L.c[ty][k][tx] = r0[k] * irho;
     }
+    const int64_t NN = (int64_t)nx * ny, on = (int64_t)y * nx + x;  // tape index
+    if constexpr (TAPE) {
+        if (in3) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) tape[k * NN + on] = double(r0[k]);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) tape[(3 + i) * NN + on] = double(f0[i]);
+        }
+    }
     __syncthreads();
     // 3. stress (rows: ty + 1 above, ty, ty - 1 below)
     C n[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
     if (in2) {
         C Txx, Txy, Tyy;
-        stress_at_lane<C, BX>(L.c, ty + 1, ty, ty - 1, tx, r0, K, n, Txx, Txy, Tyy);
+        if constexpr (TAPE) {
+            stress_at_lane<C, BX>(L.c, ty + 1, ty, ty - 1, tx, r0, K, n, Txx, Txy, Tyy,
+                                  [&](const C (&gx)[3], const C (&gy)[3]) {
+                                      if (in3) {
+#pragma unroll
+                                          for (int k = 0; k < 3; ++k) {
+                                              tape[(12 + 2 * k) * NN + on] = double(gx[k]);
+                                              tape[(13 + 2 * k) * NN + on] = double(gy[k]);
+                                          }
+                                      }
+                                  });
+        } else {
+            stress_at_lane<C, BX>(L.c, ty + 1, ty, ty - 1, tx, r0, K, n, Txx, Txy, Tyy);
+        }
         L.T[ty][0][tx] = Txx;
         L.T[ty][1][tx] = Txy;
         L.T[ty][2][tx] = Tyy;
@@ -1701,6 +1725,10 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(2))) vo
     if (in3) {
         C Fx, Fy, Tn[3];
         force_or_stress<C, BX, PT>(L.T, ty - 1, ty + 1, ty, tx, Fx, Fy, Tn);
+        if constexpr (TAPE) {
+            tape[18 * NN + on] = double(Fx);
+            tape[19 * NN + on] = double(Fy);
+        }
         C fd[9], ck[3], V[6], ux, uy, mxh, myh;
         collide_recolour<C, PT>(f0, r0, n, Fx, Fy, K, fd, ck, V, ux, uy, mxh, myh, Tn);
         NodeBits bits(((uint32_t)y * (uint32_t)nx + (uint32_t)x) * 27u ^ salt);
@@ -1712,6 +1740,16 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
         for (int q = 0; q < 4; ++q) o[(int64_t)(12 + q) * plane] = to_storage<S, C>(V[q], bits);
     }
+}
+
+// The FP64 block step writing the adjoint's tape (Guo forcing).
+inline hipError_t tiles_block_tape(const void* fin, void* fout, const Instance* inst, const Tile* tiles,
+                                   int ntiles, double* tape, hipStream_t st)
+{
+    constexpr int BX = kBlockX, BY = kBlockY;
+    hipLaunchKernelGGL((k_block<double, double, BX, BY, false, true>), dim3(ntiles), dim3(BX * BY), 0, st,
+                       (const double*)fin, (double*)fout, inst, tiles, 0u, (const int64_t*)nullptr, tape);
+    return hipGetLastError();
 }
 
 template <typename S, typename C>

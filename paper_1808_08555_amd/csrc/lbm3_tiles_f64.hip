@@ -33,6 +33,12 @@ hipError_t tiles_f64_pair(const void* fin, void* fout, const Instance* inst, con
 
 int tiles_f64_pair_occupancy(int threads) { return pair_occupancy<double, double>(threads); }
 
+hipError_t tiles_f64_block_tape(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
+                                double* tape, hipStream_t stream)
+{
+    return tiles_block_tape(fin, fout, inst, tiles, ntiles, tape, stream);
+}
+
 hipError_t tiles_f64_block(const void* fin, void* fout, const Instance* inst, const Tile* tiles, int ntiles,
                               uint32_t salt, const int64_t* step_dev, bool pt, hipStream_t stream)
 {
