@@ -424,6 +424,114 @@ __global__ __launch_bounds__(NT) void k_adj_sf(Geo g, AdjWS w, const Tile* __res
     }
 }
 
+// The same pass on two-dimensional blocks (small lattices, where the march's two warm-up
+// rows per tile and its row-by-row round trips are most of the time): a workgroup of
+// BX x BY lanes owns at most (BX - 2) x (BY - 2) nodes, lane (tx, ty) on node
+// (x0 - 1 + tx, y0 - 1 + ty).  Every lane forms dL/d(grad c_k) of its node into LDS as the
+// march does for a row; after one barrier the owned lanes complete their nodes.  The
+// arithmetic of every node is the march's.
+template <int BX, int BY>
+__global__ __launch_bounds__(BX * BY) void k_adj_sf_block(Geo g, AdjWS w, const Tile* __restrict__ tiles,
+                                                          double* __restrict__ lam)
+{
+    __shared__ double gb[BY][6][BX];
+    const Tile tl = tiles[blockIdx.x];
+    const int t = threadIdx.x, tx = t % BX, ty = t / BX;
+    const int64_t N = (int64_t)g.nx * g.ny;
+    const bool on = tx <= tl.cols + 1 && ty <= tl.rows + 1;
+    const bool own = tx >= 1 && tx <= tl.cols && ty >= 1 && ty <= tl.rows;
+    const int x = wrapi(tl.x0 - 1 + tx, g.nx), y = wrapi(tl.y0 - 1 + ty, g.ny);
+    double sig_st[3] = {0.0, 0.0, 0.0};
+    double rk[3] = {0.0, 0.0, 0.0}, part[3] = {0.0, 0.0, 0.0};
+    if (on) {
+        SfIn in;
+        sf_load(g, w, N, wrapi(x - 1, g.nx), x, wrapi(x + 1, g.nx), y, own, in);
+        double dFx_dx, dFx_dy, dFy_dx, dFy_dy;
+        grad8(in.Fb[0], dFx_dx, dFx_dy);
+        grad8(in.Fb[1], dFy_dx, dFy_dy);
+        const double Tbxx = -dFx_dx, Tbxy = -(dFx_dy + dFy_dx), Tbyy = -dFy_dy;
+        double c[3], gx[3], gy[3];
+        for (int k = 0; k < 3; ++k) rk[k] = in.rk[k];
+        const double rho = rk[0] + rk[1] + rk[2];
+        const double ir = 1.0 / rho;
+        for (int k = 0; k < 3; ++k) {
+            c[k] = rk[k] * ir;
+            gx[k] = in.gc[2 * k];
+            gy[k] = in.gc[2 * k + 1];
+        }
+        double cb[3] = {0, 0, 0}, gcb[3][2] = {{0, 0}, {0, 0}, {0, 0}}, rb[3] = {0, 0, 0};
+        for (int p = 0; p < 3; ++p) {
+            const int k = PK[p], l = PL[p];
+            const PairFwd f = pair_fwd(g, p, c, gx, gy, rk);
+            if (!f.on) continue;
+            double Gbx = in.Gb[2 * p], Gby = in.Gb[2 * p + 1];
+            const double Q = Tbxx * f.Gy * f.Gy - Tbxy * f.Gx * f.Gy + Tbyy * f.Gx * f.Gx;
+            const double h = g.sigma[p] * f.C * f.im;
+            Gbx += h * (2.0 * Tbyy * f.Gx - Tbxy * f.Gy);
+            Gby += h * (2.0 * Tbxx * f.Gy - Tbxy * f.Gx);
+            const double mb = -Q * g.sigma[p] * f.C * (f.im * f.im);
+            Gbx += mb * f.Gx * f.im;
+            Gby += mb * f.Gy * f.im;
+            if (own) sig_st[p] += Q * f.C * f.im;
+            if (f.unclipped) {
+                const double Cb = Q * g.sigma[p] * f.im;
+                rb[k] += Cb * g.cfac[p] * rk[l];
+                rb[l] += Cb * g.cfac[p] * rk[k];
+            }
+            cb[l] += Gbx * gx[k] + Gby * gy[k];
+            cb[k] -= Gbx * gx[l] + Gby * gy[l];
+            gcb[k][0] += c[l] * Gbx;
+            gcb[k][1] += c[l] * Gby;
+            gcb[l][0] -= c[k] * Gbx;
+            gcb[l][1] -= c[k] * Gby;
+        }
+        for (int k = 0; k < 3; ++k) {
+            gb[ty][2 * k][tx] = gcb[k][0];
+            gb[ty][2 * k + 1][tx] = gcb[k][1];
+        }
+        if (own) {
+            double cr = 0.0;
+            for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
+            const double irho = 1.0 / rho;
+            for (int k = 0; k < 3; ++k) part[k] = in.rbar[k] + (rb[k] + cb[k] * irho - cr * (irho * irho));
+        }
+    }
+    __syncthreads();
+    if (own) {
+        const double(*S)[BX] = gb[ty - 1];
+        const double(*C)[BX] = gb[ty];
+        const double(*U)[BX] = gb[ty + 1];
+        double cb[3];
+        for (int k = 0; k < 3; ++k) {
+            const int qx = 2 * k, qy = 2 * k + 1;
+            const double a = 3.0 * ((1.0 / 9.0) * (C[qx][tx + 1] - C[qx][tx - 1]) +
+                                    (1.0 / 36.0) * ((U[qx][tx + 1] - S[qx][tx - 1]) + (S[qx][tx + 1] - U[qx][tx - 1])));
+            const double b = 3.0 * ((1.0 / 9.0) * (U[qy][tx] - S[qy][tx]) +
+                                    (1.0 / 36.0) * ((U[qy][tx + 1] - S[qy][tx - 1]) + (U[qy][tx - 1] - S[qy][tx + 1])));
+            cb[k] = -(a + b);
+        }
+        const double rho = rk[0] + rk[1] + rk[2];
+        double cr = 0.0;
+        for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
+        const double irho = 1.0 / rho;
+        const int64_t jc = (int64_t)y * g.nx + x;
+        for (int k = 0; k < 3; ++k) lam[(9 + k) * N + jc] = part[k] + cb[k] * irho - cr * (irho * irho);
+    }
+    // per-workgroup sums of the stress part of dL/dsigma (the LDS is free again)
+    __syncthreads();
+    double* red = &gb[0][0][0];
+    constexpr int W = BX * BY / 64;
+    for (int p = 0; p < 3; ++p) sig_st[p] = wave_sum(sig_st[p]);
+    if ((t & 63) == 0)
+        for (int p = 0; p < 3; ++p) red[p * W + (t >> 6)] = sig_st[p];
+    __syncthreads();
+    if (t < 3) {
+        double v = red[t * W];
+        for (int q = 1; q < W; ++q) v += red[t * W + q];
+        w.sig[(int64_t)blockIdx.x * 6 + 3 + t] += v;
+    }
+}
+
 // The adjoint state is kept factored per node as (dL/df_i, dL/drho_k), 12 values: f_{i,k}
 // enters the step only through f_i = sum_k f_{i,k} and rho_k = sum_i f_{i,k}, so
 // dL/df_{i,k}(x) = dL/df_i(x) + dL/drho_k(x) and dL/dB_{i,k}(x - e_i) is that sum.
@@ -466,12 +574,46 @@ int sf_occupancy(int nt)
     return e == hipSuccess ? nb : 0;
 }
 
+// The fused A2 + A3 pass on blocks of 32 x kSfBlockY lanes for lattices of at most
+// kSfBlockMaxNodes nodes, else the march.
+constexpr int kSfBlockX = 32, kSfBlockY = 8;
+constexpr int64_t kSfBlockMaxNodes = (int64_t)1 << 20;
+
+// nt: march width (64 or 256), or 0 for the block pass
 void launch_sf(int nt, int ntiles, hipStream_t q, const Geo& g, const AdjWS& w, const Tile* tiles, double* lam)
 {
     switch (nt) {
+        case 0:
+            hipLaunchKernelGGL((k_adj_sf_block<kSfBlockX, kSfBlockY>), dim3(ntiles), dim3(kSfBlockX * kSfBlockY), 0, q,
+                               g, w, tiles, lam);
+            break;
         case 64: hipLaunchKernelGGL(k_adj_sf<64>, dim3(ntiles), dim3(64), 0, q, g, w, tiles, lam); break;
         default: hipLaunchKernelGGL(k_adj_sf<256>, dim3(ntiles), dim3(256), 0, q, g, w, tiles, lam); break;
     }
+}
+
+// Blocks of at most cmax x rmax nodes, sizes spread evenly, row of blocks after row of blocks.
+std::vector<Tile> plan_even_blocks(int nx, int ny, int cmax, int rmax)
+{
+    std::vector<Tile> out;
+    const int nbx = (nx + cmax - 1) / cmax, nby = (ny + rmax - 1) / rmax;
+    int y0 = 0;
+    for (int by = 0; by < nby; ++by) {
+        const int rows = ny / nby + (by < ny % nby ? 1 : 0);
+        int x0 = 0;
+        for (int bx = 0; bx < nbx; ++bx) {
+            const int cols = nx / nbx + (bx < nx % nbx ? 1 : 0);
+            Tile t{};
+            t.x0 = x0;
+            t.y0 = y0;
+            t.rows = rows;
+            t.cols = cols;
+            out.push_back(t);
+            x0 += cols;
+        }
+        y0 += rows;
+    }
+    return out;
 }
 
 Geo geo_of(const KParams& kp)
@@ -632,15 +774,21 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     const Geo g = geo_of(kp);
     const dim3 grid((kp.nx + 255) / 256, kp.ny), blk(256);
     const int64_t nblocks = (int64_t)grid.x * grid.y;
-    // tiles of the fused A2 + A3 pass: strips of at most sf_width - 2 columns (one halo
-    // column each side), rows fitted to the resident workgroups
-    const int sfw = sf_width(kp.nx);
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        cus = 1;
-    const int sf_rows = auto_rows(kp.nx, kp.ny, sfw, std::max(1, sf_occupancy(sfw)) * std::max(cus, 1), 8, 1);
+    // tiles of the fused A2 + A3 pass: on small lattices blocks (one halo node each side),
+    // else strips of at most sf_width - 2 columns, rows fitted to the resident workgroups
+    const bool sf_block = N <= kSfBlockMaxNodes;
+    const int sfw = sf_block ? 0 : sf_width(kp.nx);
     std::vector<Tile> sf_plan;
-    plan_lattice(0, kp.nx, kp.ny, sfw, sf_rows, 8, sf_plan, 1);
+    if (sf_block) {
+        sf_plan = plan_even_blocks(kp.nx, kp.ny, kSfBlockX - 2, kSfBlockY - 2);
+    } else {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 1;
+        const int sf_rows = auto_rows(kp.nx, kp.ny, sfw, std::max(1, sf_occupancy(sfw)) * std::max(cus, 1), 8, 1);
+        plan_lattice(0, kp.nx, kp.ny, sfw, sf_rows, 8, sf_plan, 1);
+    }
     const std::vector<Tile> sf_tiles = xcd_order(sf_plan, 8);
     const int sf_ntiles = (int)sf_tiles.size();
     const int64_t nsig = std::max<int64_t>(nblocks, sf_ntiles);
