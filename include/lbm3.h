@@ -174,11 +174,13 @@ const char *lbm3_last_error(void);
  * No device work. */
 int lbm3_derived(const lbm3_params *p, double X[3], double g[3], double nu[3]);
 
-/* Launch shape of the fused step: threads per workgroup (64, 128, 256 or 512;
- * each workgroup owns a strip of at most threads-6 columns) and rows marched
- * per workgroup (>= 1; 0 = chosen so that the number of workgroups fits the
- * device's resident slots).  Results do not depend on the shape (bitwise).
- * get_tile returns the rows actually used. */
+/* Launch shape of the fused step's row march: threads per workgroup (64, 128,
+ * 256 or 512; each workgroup owns a strip of at most threads-6 columns) and rows
+ * marched per workgroup (>= 1; 0 = chosen so that the number of workgroups fits
+ * the device's resident slots).  Setting a shape keeps one-step launches on the
+ * march (a lattice of at most 2^20 nodes otherwise takes them on blocks, see
+ * lbm3_set_steps_per_launch).  Results do not depend on the shape (bitwise).
+ * get_tile returns the march's shape, with the rows actually used. */
 int lbm3_set_tile(lbm3_t *h, int32_t threads, int32_t rows);
 int lbm3_get_tile(const lbm3_t *h, int32_t *threads, int32_t *rows);
 
