@@ -276,7 +276,10 @@ int lbm3_batch_destroy(lbm3_batch_t *b);
  *   checkpoints hold 18 per node each); below 2^22 nodes, where device memory
  *   allows (lbm3_adjoint_pipeline_slots), the tape and forward buffers are held
  *   twice, since the recompute of the next segment then runs on a second stream
- *   beside the reverse steps of the current one.  The
+ *   beside the reverse steps of the current one.  The reverse steps run on
+ *   two-dimensional blocks where the forward's one-step launches do (at most 2^20
+ *   nodes, no shape set by lbm3_set_tile, steps-per-launch mode other than 2), else
+ *   on the row march; the result does not depend on which.  The
  *   forward state is left at step T.  ESTATE without a recording or after a step
  *   since it. */
 int lbm3_adjoint_record(lbm3_t *h, int64_t nsteps, int32_t ckpt_every);

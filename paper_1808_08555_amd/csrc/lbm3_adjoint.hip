@@ -107,6 +107,153 @@ __device__ __forceinline__ void node_fields(const AdjWS& w, int64_t N, int64_t j
 }
 
 // ---- A1: node-local reverse of collision and recolouring
+// The node-local reverse of collision and recolouring at node (x, y) (A1): dL/df_i of the
+// new adjoint state (fb), the node-local part of dL/drho_k (rb), dL/dF, dL/dG of the three
+// pairs and the dL/dsigma contributions of the segregation law.
+struct LocalOut {
+    double fb[9], rb[3], Fb[2], Gb[3][2], sigb[3];
+};
+
+__device__ __forceinline__ void adj_local_node(const double* __restrict__ lamp, const Geo& g, const AdjWS& w, int x,
+                                               int y, LocalOut& o)
+{
+    const int64_t N = (int64_t)g.nx * g.ny, j = (int64_t)y * g.nx + x;
+    double rk[3], c[3], gx[3], gy[3];
+    node_fields(w, N, j, rk, c, gx, gy);
+    const double rho = rk[0] + rk[1] + rk[2];
+    const double irho = 1.0 / rho, irho3 = irho * irho * irho;
+    double f[9];
+    for (int i = 0; i < 9; ++i) f[i] = w.ftot[i * N + j];
+    PairFwd pf[3];
+    for (int p = 0; p < 3; ++p) pf[p] = pair_fwd(g, p, c, gx, gy, rk);
+    // the force the forward step formed at this node (div T, Eq. 7 with Eq. 12)
+    const double Fx = w.F[j], Fy = w.F[N + j];
+    // ---- forward collision
+    const double S = rk[0] * g.inv_nu[0] + rk[1] * g.inv_nu[1] + rk[2] * g.inv_nu[2];
+    const double iS = 1.0 / S;
+    const double tau = 3.0 * rho * iS + 0.5;
+    const double itau = 1.0 / tau;
+    double mx = 0.0, my = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        mx += f[i] * EX[i];
+        my += f[i] * EY[i];
+    }
+    const double ux = (mx + 0.5 * Fx) * irho, uy = (my + 0.5 * Fy) * irho;
+    const double uu = ux * ux + uy * uy, uF = ux * Fx + uy * Fy, pref = 1.0 - 0.5 * itau;
+    double eu[9], eF[9], feq[9], phi[9], fd[9];
+    for (int i = 0; i < 9; ++i) {
+        eu[i] = EX[i] * ux + EY[i] * uy;
+        eF[i] = EX[i] * Fx + EY[i] * Fy;
+        feq[i] = wgt(i) * rho * (1.0 + 3.0 * eu[i] + 4.5 * eu[i] * eu[i] - 1.5 * uu);
+        phi[i] = wgt(i) * pref * (3.0 * (eF[i] - uF) + 9.0 * eu[i] * eF[i]);
+        fd[i] = f[i] - (f[i] - feq[i]) * itau + phi[i];
+    }
+    // ---- forward recolouring quantities
+    const double q35 = 35.0 * rk[0] * rk[1] * rk[2] * irho3;
+    const bool ct_free = q35 < 1.0;
+    const double ct = ct_free ? q35 : 1.0;
+    double beta[3], aa[3], prod[3];
+    for (int p = 0; p < 3; ++p) {
+        beta[p] = g.beta0 * (1.0 + ct * g.g[p]);
+        prod[p] = rk[PK[p]] * rk[PL[p]];
+        aa[p] = beta[p] * prod[p] * irho;
+    }
+    // ---- reverse of the recolouring
+    // dL/dB'_{i,k}(x) = dL/df'_{i,k}(x + e_i) = fbar'_i(x + e_i) + rhobar'_k(x + e_i)
+    double ob[27];
+    for (int i = 0; i < 9; ++i) {
+        const int64_t nb = (int64_t)wrapi(y + EY[i], g.ny) * g.nx + wrapi(x + EX[i], g.nx);
+        const double fbi = lamp[i * N + nb];
+        for (int k = 0; k < 3; ++k) ob[k * 9 + i] = fbi + lamp[(9 + k) * N + nb];
+    }
+    double fdb[9], cb[3] = {0, 0, 0}, Vb[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int i = 0; i < 9; ++i) fdb[i] = c[0] * ob[i] + c[1] * ob[9 + i] + c[2] * ob[18 + i];
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 9; ++i) {
+            cb[k] += fd[i] * ob[k * 9 + i];
+            Vb[k][0] += wgt(i) * EX[i] * ob[k * 9 + i];
+            Vb[k][1] += wgt(i) * EY[i] * ob[k * 9 + i];
+        }
+    double rb[3] = {0, 0, 0}, rhob = 0.0, ctb = 0.0, Gbr[3][2];
+    for (int p = 0; p < 3; ++p) {
+        const int k = PK[p], l = PL[p];
+        const double dVx = Vb[k][0] - Vb[l][0], dVy = Vb[k][1] - Vb[l][1];
+        const double ab = dVx * pf[p].nx + dVy * pf[p].ny;
+        // n_p = G/m: dL/dG = (nb - n (n . nb)) / m with nb = a_p (Vb_k - Vb_l)
+        Gbr[p][0] = Gbr[p][1] = 0.0;
+        if (pf[p].on) {
+            const double nbx = aa[p] * dVx, nby = aa[p] * dVy;
+            const double nn = pf[p].nx * nbx + pf[p].ny * nby;
+            Gbr[p][0] = (nbx - pf[p].nx * nn) * pf[p].im;
+            Gbr[p][1] = (nby - pf[p].ny * nn) * pf[p].im;
+        }
+        // a_p = beta_p rho_k rho_l / rho
+        const double betab = ab * prod[p] * irho;
+        rb[k] += ab * beta[p] * rk[l] * irho;
+        rb[l] += ab * beta[p] * rk[k] * irho;
+        rhob -= ab * aa[p] * irho;
+        // beta_p = beta0 (1 + ct g_p)
+        ctb += betab * g.beta0 * g.g[p];
+        o.sigb[p] = betab * g.beta0 * ct;  // times g'(X_p) dX_p/dsigma on the host
+    }
+    if (ct_free) {
+        rb[0] += ctb * 35.0 * rk[1] * rk[2] * irho3;
+        rb[1] += ctb * 35.0 * rk[0] * rk[2] * irho3;
+        rb[2] += ctb * 35.0 * rk[0] * rk[1] * irho3;
+        rhob -= ctb * 3.0 * q35 * irho;
+    }
+    // ---- reverse of the collision
+    double fb[9], ub[2] = {0, 0}, Fb[2] = {0, 0}, itaub = 0.0, prefb = 0.0, uub = 0.0, uFb = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        const double feqb = fdb[i] * itau;
+        fb[i] = fdb[i] * (1.0 - itau);
+        itaub += fdb[i] * (feq[i] - f[i]);
+        const double phib = fdb[i];
+        prefb += phib * wgt(i) * (3.0 * (eF[i] - uF) + 9.0 * eu[i] * eF[i]);
+        const double A = phib * wgt(i) * pref;
+        const double eFb = A * (3.0 + 9.0 * eu[i]);
+        double eub = 9.0 * A * eF[i];
+        uFb -= 3.0 * A;
+        rhob += feqb * wgt(i) * (1.0 + 3.0 * eu[i] + 4.5 * eu[i] * eu[i] - 1.5 * uu);
+        const double Bf = feqb * wgt(i) * rho;
+        eub += Bf * (3.0 + 9.0 * eu[i]);
+        uub -= 1.5 * Bf;
+        ub[0] += eub * EX[i];
+        ub[1] += eub * EY[i];
+        Fb[0] += eFb * EX[i];
+        Fb[1] += eFb * EY[i];
+    }
+    ub[0] += uFb * Fx + 2.0 * uub * ux;
+    ub[1] += uFb * Fy + 2.0 * uub * uy;
+    Fb[0] += uFb * ux;
+    Fb[1] += uFb * uy;
+    itaub -= 0.5 * prefb;
+    // u = (m + F/2)/rho
+    const double mbx = ub[0] * irho, mby = ub[1] * irho;
+    Fb[0] += 0.5 * mbx;
+    Fb[1] += 0.5 * mby;
+    rhob -= (ub[0] * ux + ub[1] * uy) * irho;
+    for (int i = 0; i < 9; ++i) fb[i] += mbx * EX[i] + mby * EY[i];
+    // itau = 1/tau, tau = 3 rho / S + 1/2, S = sum_k rho_k inv_nu_k
+    const double taub = -itaub * itau * itau;
+    rhob += taub * 3.0 * iS;
+    const double Sb = -taub * 3.0 * rho * iS * iS;
+    for (int k = 0; k < 3; ++k) rb[k] += Sb * g.inv_nu[k];
+    // c_k = rho_k / rho (the node-local uses of c)
+    double cr = 0.0;
+    for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
+    for (int k = 0; k < 3; ++k) rb[k] += cb[k] * irho - cr * (irho * irho);
+    for (int k = 0; k < 3; ++k) rb[k] += rhob;  // rho = sum_k rho_k
+    for (int i = 0; i < 9; ++i) o.fb[i] = fb[i];
+    for (int k = 0; k < 3; ++k) o.rb[k] = rb[k];
+    o.Fb[0] = Fb[0];
+    o.Fb[1] = Fb[1];
+    for (int p = 0; p < 3; ++p) {
+        o.Gb[p][0] = Gbr[p][0];
+        o.Gb[p][1] = Gbr[p][1];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ lamp, Geo g, AdjWS w,
                                                    double* __restrict__ lamn)
 {
@@ -115,140 +262,17 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ la
     const int t = threadIdx.x;
     double sig_beta[3] = {0.0, 0.0, 0.0};
     if (x < g.nx) {
+        LocalOut o;
+        adj_local_node(lamp, g, w, x, y, o);
         const int64_t N = (int64_t)g.nx * g.ny, j = (int64_t)y * g.nx + x;
-        double rk[3], c[3], gx[3], gy[3];
-        node_fields(w, N, j, rk, c, gx, gy);
-        const double rho = rk[0] + rk[1] + rk[2];
-        const double irho = 1.0 / rho, irho3 = irho * irho * irho;
-        double f[9];
-        for (int i = 0; i < 9; ++i) f[i] = w.ftot[i * N + j];
-        PairFwd pf[3];
-        for (int p = 0; p < 3; ++p) pf[p] = pair_fwd(g, p, c, gx, gy, rk);
-        // the force the forward step formed at this node (div T, Eq. 7 with Eq. 12)
-        const double Fx = w.F[j], Fy = w.F[N + j];
-        // ---- forward collision
-        const double S = rk[0] * g.inv_nu[0] + rk[1] * g.inv_nu[1] + rk[2] * g.inv_nu[2];
-        const double iS = 1.0 / S;
-        const double tau = 3.0 * rho * iS + 0.5;
-        const double itau = 1.0 / tau;
-        double mx = 0.0, my = 0.0;
-        for (int i = 0; i < 9; ++i) {
-            mx += f[i] * EX[i];
-            my += f[i] * EY[i];
-        }
-        const double ux = (mx + 0.5 * Fx) * irho, uy = (my + 0.5 * Fy) * irho;
-        const double uu = ux * ux + uy * uy, uF = ux * Fx + uy * Fy, pref = 1.0 - 0.5 * itau;
-        double eu[9], eF[9], feq[9], phi[9], fd[9];
-        for (int i = 0; i < 9; ++i) {
-            eu[i] = EX[i] * ux + EY[i] * uy;
-            eF[i] = EX[i] * Fx + EY[i] * Fy;
-            feq[i] = wgt(i) * rho * (1.0 + 3.0 * eu[i] + 4.5 * eu[i] * eu[i] - 1.5 * uu);
-            phi[i] = wgt(i) * pref * (3.0 * (eF[i] - uF) + 9.0 * eu[i] * eF[i]);
-            fd[i] = f[i] - (f[i] - feq[i]) * itau + phi[i];
-        }
-        // ---- forward recolouring quantities
-        const double q35 = 35.0 * rk[0] * rk[1] * rk[2] * irho3;
-        const bool ct_free = q35 < 1.0;
-        const double ct = ct_free ? q35 : 1.0;
-        double beta[3], aa[3], prod[3];
+        for (int i = 0; i < 9; ++i) lamn[i * N + j] = o.fb[i];
+        for (int k = 0; k < 3; ++k) w.rbar[k * N + j] = o.rb[k];
+        w.Fbar[j] = o.Fb[0];
+        w.Fbar[N + j] = o.Fb[1];
         for (int p = 0; p < 3; ++p) {
-            beta[p] = g.beta0 * (1.0 + ct * g.g[p]);
-            prod[p] = rk[PK[p]] * rk[PL[p]];
-            aa[p] = beta[p] * prod[p] * irho;
-        }
-        // ---- reverse of the recolouring
-        // dL/dB'_{i,k}(x) = dL/df'_{i,k}(x + e_i) = fbar'_i(x + e_i) + rhobar'_k(x + e_i)
-        double ob[27];
-        for (int i = 0; i < 9; ++i) {
-            const int64_t nb = (int64_t)wrapi(y + EY[i], g.ny) * g.nx + wrapi(x + EX[i], g.nx);
-            const double fbi = lamp[i * N + nb];
-            for (int k = 0; k < 3; ++k) ob[k * 9 + i] = fbi + lamp[(9 + k) * N + nb];
-        }
-        double fdb[9], cb[3] = {0, 0, 0}, Vb[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-        for (int i = 0; i < 9; ++i) fdb[i] = c[0] * ob[i] + c[1] * ob[9 + i] + c[2] * ob[18 + i];
-        for (int k = 0; k < 3; ++k)
-            for (int i = 0; i < 9; ++i) {
-                cb[k] += fd[i] * ob[k * 9 + i];
-                Vb[k][0] += wgt(i) * EX[i] * ob[k * 9 + i];
-                Vb[k][1] += wgt(i) * EY[i] * ob[k * 9 + i];
-            }
-        double rb[3] = {0, 0, 0}, rhob = 0.0, ctb = 0.0, Gbr[3][2];
-        for (int p = 0; p < 3; ++p) {
-            const int k = PK[p], l = PL[p];
-            const double dVx = Vb[k][0] - Vb[l][0], dVy = Vb[k][1] - Vb[l][1];
-            const double ab = dVx * pf[p].nx + dVy * pf[p].ny;
-            // n_p = G/m: dL/dG = (nb - n (n . nb)) / m with nb = a_p (Vb_k - Vb_l)
-            Gbr[p][0] = Gbr[p][1] = 0.0;
-            if (pf[p].on) {
-                const double nbx = aa[p] * dVx, nby = aa[p] * dVy;
-                const double nn = pf[p].nx * nbx + pf[p].ny * nby;
-                Gbr[p][0] = (nbx - pf[p].nx * nn) * pf[p].im;
-                Gbr[p][1] = (nby - pf[p].ny * nn) * pf[p].im;
-            }
-            // a_p = beta_p rho_k rho_l / rho
-            const double betab = ab * prod[p] * irho;
-            rb[k] += ab * beta[p] * rk[l] * irho;
-            rb[l] += ab * beta[p] * rk[k] * irho;
-            rhob -= ab * aa[p] * irho;
-            // beta_p = beta0 (1 + ct g_p)
-            ctb += betab * g.beta0 * g.g[p];
-            sig_beta[p] = betab * g.beta0 * ct;  // times g'(X_p) dX_p/dsigma on the host
-        }
-        if (ct_free) {
-            rb[0] += ctb * 35.0 * rk[1] * rk[2] * irho3;
-            rb[1] += ctb * 35.0 * rk[0] * rk[2] * irho3;
-            rb[2] += ctb * 35.0 * rk[0] * rk[1] * irho3;
-            rhob -= ctb * 3.0 * q35 * irho;
-        }
-        // ---- reverse of the collision
-        double fb[9], ub[2] = {0, 0}, Fb[2] = {0, 0}, itaub = 0.0, prefb = 0.0, uub = 0.0, uFb = 0.0;
-        for (int i = 0; i < 9; ++i) {
-            const double feqb = fdb[i] * itau;
-            fb[i] = fdb[i] * (1.0 - itau);
-            itaub += fdb[i] * (feq[i] - f[i]);
-            const double phib = fdb[i];
-            prefb += phib * wgt(i) * (3.0 * (eF[i] - uF) + 9.0 * eu[i] * eF[i]);
-            const double A = phib * wgt(i) * pref;
-            const double eFb = A * (3.0 + 9.0 * eu[i]);
-            double eub = 9.0 * A * eF[i];
-            uFb -= 3.0 * A;
-            rhob += feqb * wgt(i) * (1.0 + 3.0 * eu[i] + 4.5 * eu[i] * eu[i] - 1.5 * uu);
-            const double Bf = feqb * wgt(i) * rho;
-            eub += Bf * (3.0 + 9.0 * eu[i]);
-            uub -= 1.5 * Bf;
-            ub[0] += eub * EX[i];
-            ub[1] += eub * EY[i];
-            Fb[0] += eFb * EX[i];
-            Fb[1] += eFb * EY[i];
-        }
-        ub[0] += uFb * Fx + 2.0 * uub * ux;
-        ub[1] += uFb * Fy + 2.0 * uub * uy;
-        Fb[0] += uFb * ux;
-        Fb[1] += uFb * uy;
-        itaub -= 0.5 * prefb;
-        // u = (m + F/2)/rho
-        const double mbx = ub[0] * irho, mby = ub[1] * irho;
-        Fb[0] += 0.5 * mbx;
-        Fb[1] += 0.5 * mby;
-        rhob -= (ub[0] * ux + ub[1] * uy) * irho;
-        for (int i = 0; i < 9; ++i) fb[i] += mbx * EX[i] + mby * EY[i];
-        // itau = 1/tau, tau = 3 rho / S + 1/2, S = sum_k rho_k inv_nu_k
-        const double taub = -itaub * itau * itau;
-        rhob += taub * 3.0 * iS;
-        const double Sb = -taub * 3.0 * rho * iS * iS;
-        for (int k = 0; k < 3; ++k) rb[k] += Sb * g.inv_nu[k];
-        // c_k = rho_k / rho (the node-local uses of c)
-        double cr = 0.0;
-        for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
-        for (int k = 0; k < 3; ++k) rb[k] += cb[k] * irho - cr * (irho * irho);
-        for (int k = 0; k < 3; ++k) rb[k] += rhob;  // rho = sum_k rho_k
-        for (int i = 0; i < 9; ++i) lamn[i * N + j] = fb[i];
-        for (int k = 0; k < 3; ++k) w.rbar[k * N + j] = rb[k];
-        w.Fbar[j] = Fb[0];
-        w.Fbar[N + j] = Fb[1];
-        for (int p = 0; p < 3; ++p) {
-            w.Gbar[(2 * p) * N + j] = Gbr[p][0];
-            w.Gbar[(2 * p + 1) * N + j] = Gbr[p][1];
+            w.Gbar[(2 * p) * N + j] = o.Gb[p][0];
+            w.Gbar[(2 * p + 1) * N + j] = o.Gb[p][1];
+            sig_beta[p] = o.sigb[p];
         }
     }
     // wavefront sums, then the four wave sums in order
@@ -424,12 +448,110 @@ __global__ __launch_bounds__(NT) void k_adj_sf(Geo g, AdjWS w, const Tile* __res
     }
 }
 
-// The same pass on two-dimensional blocks (small lattices, where the march's two warm-up
-// rows per tile and its row-by-row round trips are most of the time): a workgroup of
-// BX x BY lanes owns at most (BX - 2) x (BY - 2) nodes, lane (tx, ty) on node
-// (x0 - 1 + tx, y0 - 1 + ty).  Every lane forms dL/d(grad c_k) of its node into LDS as the
-// march does for a row; after one barrier the owned lanes complete their nodes.  The
-// arithmetic of every node is the march's.
+// A2 at one node (the reverse of the stress and the pair quantities), as the march forms it
+// for a row: from dL/dF at the eight neighbours (E, W, N, S, NE, NW, SE, SW), the tape's
+// densities rk and gradients gc, dL/dG (Gb) and, for an owned node, A1's node-local dL/drho_k
+// (rbar): dL/d(grad c_k) (gcb), the node's part of dL/drho_k (part, owned nodes) and the
+// stress part of dL/dsigma (sig_st, owned nodes).
+__device__ __forceinline__ void sf_node(const Geo& g, const double (&Fb)[2][8], const double (&rkin)[3],
+                                        const double (&gcin)[6], const double (&Gbin)[6], const double (&rbar)[3],
+                                        bool own, double (&gcb)[3][2], double (&part)[3], double (&sig_st)[3])
+{
+    double dFx_dx, dFx_dy, dFy_dx, dFy_dy;
+    grad8(Fb[0], dFx_dx, dFx_dy);
+    grad8(Fb[1], dFy_dx, dFy_dy);
+    const double Tbxx = -dFx_dx, Tbxy = -(dFx_dy + dFy_dx), Tbyy = -dFy_dy;
+    double rk[3], c[3], gx[3], gy[3];
+    for (int k = 0; k < 3; ++k) rk[k] = rkin[k];
+    const double rho = rk[0] + rk[1] + rk[2];
+    const double ir = 1.0 / rho;
+    for (int k = 0; k < 3; ++k) {
+        c[k] = rk[k] * ir;
+        gx[k] = gcin[2 * k];
+        gy[k] = gcin[2 * k + 1];
+    }
+    double cb[3] = {0, 0, 0}, rb[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k) gcb[k][0] = gcb[k][1] = 0.0;
+    for (int p = 0; p < 3; ++p) {
+        const int k = PK[p], l = PL[p];
+        const PairFwd f = pair_fwd(g, p, c, gx, gy, rk);
+        if (!f.on) continue;
+        double Gbx = Gbin[2 * p], Gby = Gbin[2 * p + 1];
+        const double Q = Tbxx * f.Gy * f.Gy - Tbxy * f.Gx * f.Gy + Tbyy * f.Gx * f.Gx;
+        const double h = g.sigma[p] * f.C * f.im;
+        Gbx += h * (2.0 * Tbyy * f.Gx - Tbxy * f.Gy);
+        Gby += h * (2.0 * Tbxx * f.Gy - Tbxy * f.Gx);
+        const double mb = -Q * g.sigma[p] * f.C * (f.im * f.im);
+        Gbx += mb * f.Gx * f.im;
+        Gby += mb * f.Gy * f.im;
+        if (own) sig_st[p] += Q * f.C * f.im;
+        if (f.unclipped) {
+            const double Cb = Q * g.sigma[p] * f.im;
+            rb[k] += Cb * g.cfac[p] * rk[l];
+            rb[l] += Cb * g.cfac[p] * rk[k];
+        }
+        cb[l] += Gbx * gx[k] + Gby * gy[k];
+        cb[k] -= Gbx * gx[l] + Gby * gy[l];
+        gcb[k][0] += c[l] * Gbx;
+        gcb[k][1] += c[l] * Gby;
+        gcb[l][0] -= c[k] * Gbx;
+        gcb[l][1] -= c[k] * Gby;
+    }
+    if (own) {
+        double cr = 0.0;
+        for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
+        const double irho = 1.0 / rho;
+        for (int k = 0; k < 3; ++k) part[k] = rbar[k] + (rb[k] + cb[k] * irho - cr * (irho * irho));
+    }
+}
+
+// A3 at an owned node: dL/drho_k of the new adjoint state from dL/d(grad c_k) of the rows
+// below (S), at (C) and above (U) the node, at column t, and the node's part.
+template <int BX>
+__device__ __forceinline__ void a3_node(const double (*S)[BX], const double (*C)[BX], const double (*U)[BX], int t,
+                                        const double (&rk)[3], const double (&part)[3], double (&out)[3])
+{
+    double cb[3];
+    for (int k = 0; k < 3; ++k) {
+        const int qx = 2 * k, qy = 2 * k + 1;
+        const double a = 3.0 * ((1.0 / 9.0) * (C[qx][t + 1] - C[qx][t - 1]) +
+                                (1.0 / 36.0) * ((U[qx][t + 1] - S[qx][t - 1]) + (S[qx][t + 1] - U[qx][t - 1])));
+        const double b = 3.0 * ((1.0 / 9.0) * (U[qy][t] - S[qy][t]) +
+                                (1.0 / 36.0) * ((U[qy][t + 1] - S[qy][t - 1]) + (U[qy][t - 1] - S[qy][t + 1])));
+        cb[k] = -(a + b);
+    }
+    const double rho = rk[0] + rk[1] + rk[2];
+    double cr = 0.0;
+    for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
+    const double irho = 1.0 / rho;
+    for (int k = 0; k < 3; ++k) out[k] = part[k] + cb[k] * irho - cr * (irho * irho);
+}
+
+// Per-workgroup sums of six dL/dsigma parts into w.sig[blockIdx.x][0..5] (red: LDS of at
+// least 6 x waves doubles, free on entry).
+template <int NT>
+__device__ __forceinline__ void add_sig6(const double (&v)[6], double* red, double* __restrict__ sig)
+{
+    constexpr int W = NT / 64;
+    const int t = threadIdx.x;
+    double s[6];
+    for (int q = 0; q < 6; ++q) s[q] = wave_sum(v[q]);
+    if ((t & 63) == 0)
+        for (int q = 0; q < 6; ++q) red[q * W + (t >> 6)] = s[q];
+    __syncthreads();
+    if (t < 6) {
+        double a = red[t * W];
+        for (int k = 1; k < W; ++k) a += red[t * W + k];
+        sig[(int64_t)blockIdx.x * 6 + t] += a;
+    }
+}
+
+// A2 + A3 on two-dimensional blocks (small lattices, where the march's two warm-up rows
+// per tile and its row-by-row round trips are most of the time): a workgroup of BX x BY
+// lanes owns at most (BX - 2) x (BY - 2) nodes, lane (tx, ty) on node (x0 - 1 + tx,
+// y0 - 1 + ty).  Every lane forms dL/d(grad c_k) of its node into LDS as the march does for
+// a row; after one barrier the owned lanes complete their nodes.  The arithmetic of every
+// node is the march's.
 template <int BX, int BY>
 __global__ __launch_bounds__(BX * BY) void k_adj_sf_block(Geo g, AdjWS w, const Tile* __restrict__ tiles,
                                                           double* __restrict__ lam)
@@ -441,95 +563,102 @@ __global__ __launch_bounds__(BX * BY) void k_adj_sf_block(Geo g, AdjWS w, const 
     const bool on = tx <= tl.cols + 1 && ty <= tl.rows + 1;
     const bool own = tx >= 1 && tx <= tl.cols && ty >= 1 && ty <= tl.rows;
     const int x = wrapi(tl.x0 - 1 + tx, g.nx), y = wrapi(tl.y0 - 1 + ty, g.ny);
-    double sig_st[3] = {0.0, 0.0, 0.0};
-    double rk[3] = {0.0, 0.0, 0.0}, part[3] = {0.0, 0.0, 0.0};
+    double sig[6] = {0, 0, 0, 0, 0, 0}, sig_st[3] = {0, 0, 0};
+    double rk[3] = {0, 0, 0}, part[3] = {0, 0, 0};
     if (on) {
         SfIn in;
         sf_load(g, w, N, wrapi(x - 1, g.nx), x, wrapi(x + 1, g.nx), y, own, in);
-        double dFx_dx, dFx_dy, dFy_dx, dFy_dy;
-        grad8(in.Fb[0], dFx_dx, dFx_dy);
-        grad8(in.Fb[1], dFy_dx, dFy_dy);
-        const double Tbxx = -dFx_dx, Tbxy = -(dFx_dy + dFy_dx), Tbyy = -dFy_dy;
-        double c[3], gx[3], gy[3];
-        for (int k = 0; k < 3; ++k) rk[k] = in.rk[k];
-        const double rho = rk[0] + rk[1] + rk[2];
-        const double ir = 1.0 / rho;
+        double gcb[3][2];
+        sf_node(g, in.Fb, in.rk, in.gc, in.Gb, in.rbar, own, gcb, part, sig_st);
         for (int k = 0; k < 3; ++k) {
-            c[k] = rk[k] * ir;
-            gx[k] = in.gc[2 * k];
-            gy[k] = in.gc[2 * k + 1];
-        }
-        double cb[3] = {0, 0, 0}, gcb[3][2] = {{0, 0}, {0, 0}, {0, 0}}, rb[3] = {0, 0, 0};
-        for (int p = 0; p < 3; ++p) {
-            const int k = PK[p], l = PL[p];
-            const PairFwd f = pair_fwd(g, p, c, gx, gy, rk);
-            if (!f.on) continue;
-            double Gbx = in.Gb[2 * p], Gby = in.Gb[2 * p + 1];
-            const double Q = Tbxx * f.Gy * f.Gy - Tbxy * f.Gx * f.Gy + Tbyy * f.Gx * f.Gx;
-            const double h = g.sigma[p] * f.C * f.im;
-            Gbx += h * (2.0 * Tbyy * f.Gx - Tbxy * f.Gy);
-            Gby += h * (2.0 * Tbxx * f.Gy - Tbxy * f.Gx);
-            const double mb = -Q * g.sigma[p] * f.C * (f.im * f.im);
-            Gbx += mb * f.Gx * f.im;
-            Gby += mb * f.Gy * f.im;
-            if (own) sig_st[p] += Q * f.C * f.im;
-            if (f.unclipped) {
-                const double Cb = Q * g.sigma[p] * f.im;
-                rb[k] += Cb * g.cfac[p] * rk[l];
-                rb[l] += Cb * g.cfac[p] * rk[k];
-            }
-            cb[l] += Gbx * gx[k] + Gby * gy[k];
-            cb[k] -= Gbx * gx[l] + Gby * gy[l];
-            gcb[k][0] += c[l] * Gbx;
-            gcb[k][1] += c[l] * Gby;
-            gcb[l][0] -= c[k] * Gbx;
-            gcb[l][1] -= c[k] * Gby;
-        }
-        for (int k = 0; k < 3; ++k) {
+            rk[k] = in.rk[k];
             gb[ty][2 * k][tx] = gcb[k][0];
             gb[ty][2 * k + 1][tx] = gcb[k][1];
-        }
-        if (own) {
-            double cr = 0.0;
-            for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
-            const double irho = 1.0 / rho;
-            for (int k = 0; k < 3; ++k) part[k] = in.rbar[k] + (rb[k] + cb[k] * irho - cr * (irho * irho));
         }
     }
     __syncthreads();
     if (own) {
-        const double(*S)[BX] = gb[ty - 1];
-        const double(*C)[BX] = gb[ty];
-        const double(*U)[BX] = gb[ty + 1];
-        double cb[3];
-        for (int k = 0; k < 3; ++k) {
-            const int qx = 2 * k, qy = 2 * k + 1;
-            const double a = 3.0 * ((1.0 / 9.0) * (C[qx][tx + 1] - C[qx][tx - 1]) +
-                                    (1.0 / 36.0) * ((U[qx][tx + 1] - S[qx][tx - 1]) + (S[qx][tx + 1] - U[qx][tx - 1])));
-            const double b = 3.0 * ((1.0 / 9.0) * (U[qy][tx] - S[qy][tx]) +
-                                    (1.0 / 36.0) * ((U[qy][tx + 1] - S[qy][tx - 1]) + (U[qy][tx - 1] - S[qy][tx + 1])));
-            cb[k] = -(a + b);
-        }
-        const double rho = rk[0] + rk[1] + rk[2];
-        double cr = 0.0;
-        for (int k = 0; k < 3; ++k) cr += cb[k] * rk[k];
-        const double irho = 1.0 / rho;
+        double out[3];
+        a3_node<BX>(gb[ty - 1], gb[ty], gb[ty + 1], tx, rk, part, out);
         const int64_t jc = (int64_t)y * g.nx + x;
-        for (int k = 0; k < 3; ++k) lam[(9 + k) * N + jc] = part[k] + cb[k] * irho - cr * (irho * irho);
+        for (int k = 0; k < 3; ++k) lam[(9 + k) * N + jc] = out[k];
     }
-    // per-workgroup sums of the stress part of dL/dsigma (the LDS is free again)
+    // the stress part of dL/dsigma (the LDS is free again)
     __syncthreads();
-    double* red = &gb[0][0][0];
-    constexpr int W = BX * BY / 64;
-    for (int p = 0; p < 3; ++p) sig_st[p] = wave_sum(sig_st[p]);
-    if ((t & 63) == 0)
-        for (int p = 0; p < 3; ++p) red[p * W + (t >> 6)] = sig_st[p];
-    __syncthreads();
-    if (t < 3) {
-        double v = red[t * W];
-        for (int q = 1; q < W; ++q) v += red[t * W + q];
-        w.sig[(int64_t)blockIdx.x * 6 + 3 + t] += v;
+    for (int p = 0; p < 3; ++p) sig[3 + p] = sig_st[p];
+    add_sig6<BX * BY>(sig, &gb[0][0][0], w.sig);
+}
+
+// One whole reverse step, A1 + A2 + A3, on two-dimensional blocks (small lattices): a
+// workgroup of BX x BY lanes owns at most (BX - 4) x (BY - 4) nodes, lane (tx, ty) on node
+// (x0 - 2 + tx, y0 - 2 + ty).  Every lane runs A1 at its node (adj_local_node) and puts its
+// dL/dF in LDS; the lanes within one of the block run A2 (sf_node) on those and put dL/d(grad
+// c_k) in LDS; the owned lanes run A3.  dL/dF, dL/dG and A1's dL/drho_k stay on chip, and a
+// step is one launch instead of two.  Each node's arithmetic is that of k_adj_local and the
+// march.
+template <int BX, int BY>
+__global__ __launch_bounds__(BX * BY) void k_adj_block(const double* __restrict__ lamp, Geo g, AdjWS w,
+                                                       const Tile* __restrict__ tiles, double* __restrict__ lamn)
+{
+    __shared__ double Fs[BY][2][BX];
+    __shared__ double gb[BY][6][BX];
+    const Tile tl = tiles[blockIdx.x];
+    const int t = threadIdx.x, tx = t % BX, ty = t / BX;
+    const int64_t N = (int64_t)g.nx * g.ny;
+    const bool in1 = tx <= tl.cols + 3 && ty <= tl.rows + 3;
+    const bool in2 = tx >= 1 && tx <= tl.cols + 2 && ty >= 1 && ty <= tl.rows + 2;
+    const bool own = tx >= 2 && tx <= tl.cols + 1 && ty >= 2 && ty <= tl.rows + 1;
+    const int x = wrapi(tl.x0 - 2 + tx, g.nx), y = wrapi(tl.y0 - 2 + ty, g.ny);
+    const int64_t j = (int64_t)y * g.nx + x;
+    double sig[6] = {0, 0, 0, 0, 0, 0}, sig_st[3] = {0, 0, 0};
+    LocalOut o;
+    for (int p = 0; p < 3; ++p) o.Gb[p][0] = o.Gb[p][1] = o.rb[p] = 0.0;
+    if (in1) {
+        adj_local_node(lamp, g, w, x, y, o);
+        Fs[ty][0][tx] = o.Fb[0];
+        Fs[ty][1][tx] = o.Fb[1];
+        if (own) {
+            for (int i = 0; i < 9; ++i) lamn[i * N + j] = o.fb[i];
+            for (int p = 0; p < 3; ++p) sig[p] = o.sigb[p];
+        }
     }
+    __syncthreads();
+    double rk[3] = {0, 0, 0}, part[3] = {0, 0, 0};
+    if (in2) {
+        double Fb[2][8];
+        for (int c = 0; c < 2; ++c) {
+            Fb[c][0] = Fs[ty][c][tx + 1];
+            Fb[c][1] = Fs[ty][c][tx - 1];
+            Fb[c][2] = Fs[ty + 1][c][tx];
+            Fb[c][3] = Fs[ty - 1][c][tx];
+            Fb[c][4] = Fs[ty + 1][c][tx + 1];
+            Fb[c][5] = Fs[ty + 1][c][tx - 1];
+            Fb[c][6] = Fs[ty - 1][c][tx + 1];
+            Fb[c][7] = Fs[ty - 1][c][tx - 1];
+        }
+        double gc[6], Gb[6];
+        for (int k = 0; k < 3; ++k) rk[k] = w.rho[k * N + j];
+        for (int q = 0; q < 6; ++q) gc[q] = w.gc[q * N + j];
+        for (int p = 0; p < 3; ++p) {
+            Gb[2 * p] = o.Gb[p][0];
+            Gb[2 * p + 1] = o.Gb[p][1];
+        }
+        double gcb[3][2];
+        sf_node(g, Fb, rk, gc, Gb, o.rb, own, gcb, part, sig_st);
+        for (int k = 0; k < 3; ++k) {
+            gb[ty][2 * k][tx] = gcb[k][0];
+            gb[ty][2 * k + 1][tx] = gcb[k][1];
+        }
+    }
+    __syncthreads();
+    if (own) {
+        double out[3];
+        a3_node<BX>(gb[ty - 1], gb[ty], gb[ty + 1], tx, rk, part, out);
+        for (int k = 0; k < 3; ++k) lamn[(9 + k) * N + j] = out[k];
+    }
+    __syncthreads();
+    for (int p = 0; p < 3; ++p) sig[3 + p] = sig_st[p];
+    add_sig6<BX * BY>(sig, &gb[0][0][0], w.sig);
 }
 
 // The adjoint state is kept factored per node as (dL/df_i, dL/drho_k), 12 values: f_{i,k}
@@ -574,9 +703,16 @@ int sf_occupancy(int nt)
     return e == hipSuccess ? nb : 0;
 }
 
-// The fused A2 + A3 pass on blocks of 32 x kSfBlockY lanes for lattices of at most
-// kSfBlockMaxNodes nodes, else the march.
+// The reverse steps by lattice size: up to kAdjFusedMaxNodes nodes one launch of k_adj_block
+// per step (blocks of kAdjBlockX x kAdjBlockY lanes); up to kSfBlockMaxNodes k_adj_local and
+// k_adj_sf_block (blocks of kSfBlockX x kSfBlockY lanes); above, or where the forward's
+// one-step launches keep to the march, k_adj_local and the march.
+// Measured (adjoint MLUPS, fused vs two kernels): 3.23k vs 2.64k at 256^2, 3.56k vs 3.99k
+// at 512^2, 3.62k vs 3.80k at 1024^2; the fused step runs A1 on the halo ring too, which
+// costs more than the launch it saves once the lattice fills the device.
 constexpr int kSfBlockX = 32, kSfBlockY = 8;
+constexpr int kAdjBlockX = 32, kAdjBlockY = 16;
+constexpr int64_t kAdjFusedMaxNodes = (int64_t)1 << 17;
 constexpr int64_t kSfBlockMaxNodes = (int64_t)1 << 20;
 
 // nt: march width (64 or 256), or 0 for the block pass
@@ -774,12 +910,17 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     const Geo g = geo_of(kp);
     const dim3 grid((kp.nx + 255) / 256, kp.ny), blk(256);
     const int64_t nblocks = (int64_t)grid.x * grid.y;
-    // tiles of the fused A2 + A3 pass: on small lattices blocks (one halo node each side),
-    // else strips of at most sf_width - 2 columns, rows fitted to the resident workgroups
-    const bool sf_block = N <= kSfBlockMaxNodes;
+    // tiles of the fused A2 + A3 pass: blocks where the forward takes its one-step blocks
+    // (ntilesb > 0: at most 2^20 nodes and no march shape chosen by lbm3_set_tile or
+    // lbm3_set_steps_per_launch(2)), else strips of at most sf_width - 2 columns, rows
+    // fitted to the resident workgroups
+    const bool sf_block = h->ntilesb > 0 && N <= kSfBlockMaxNodes;
+    const bool fused = sf_block && N <= kAdjFusedMaxNodes;
     const int sfw = sf_block ? 0 : sf_width(kp.nx);
     std::vector<Tile> sf_plan;
-    if (sf_block) {
+    if (fused) {
+        sf_plan = plan_even_blocks(kp.nx, kp.ny, kAdjBlockX - 4, kAdjBlockY - 4);
+    } else if (sf_block) {
         sf_plan = plan_even_blocks(kp.nx, kp.ny, kSfBlockX - 2, kSfBlockY - 2);
     } else {
         int dev = 0, cus = 0;
@@ -888,8 +1029,13 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
             wj.ftot = wj.rho + 3 * N;
             wj.gc = wj.rho + 12 * N;
             wj.F = wj.rho + 18 * N;
-            hipLaunchKernelGGL(k_adj_local, grid, blk, 0, q, (const double*)lam[c], g, wj, lam[c ^ 1]);
-            launch_sf(sfw, sf_ntiles, q, g, wj, dsf, lam[c ^ 1]);
+            if (fused) {
+                hipLaunchKernelGGL((k_adj_block<kAdjBlockX, kAdjBlockY>), dim3(sf_ntiles), dim3(kAdjBlockX * kAdjBlockY),
+                                   0, q, (const double*)lam[c], g, wj, (const Tile*)dsf, lam[c ^ 1]);
+            } else {
+                hipLaunchKernelGGL(k_adj_local, grid, blk, 0, q, (const double*)lam[c], g, wj, lam[c ^ 1]);
+                launch_sf(sfw, sf_ntiles, q, g, wj, dsf, lam[c ^ 1]);
+            }
             c ^= 1;
             r = hipGetLastError();
         }

@@ -29,9 +29,13 @@ def sharp_janus(nx, ny, R):
     return inputs.rho_from_labels(lab), lab
 
 
-def gpu_gradient(rho0, target, sigma, tau, steps, every):
+def gpu_gradient(rho0, target, sigma, tau, steps, every, tile=None):
+    """tile = (threads, rows) sets a row-march shape, which keeps the forward's one-step
+    launches and the reverse steps on the march."""
     ny, nx = rho0.shape[1:]
     L = lbm3.Lattice(nx, ny, sigma, tau).init(rho0)
+    if tile is not None:
+        lbm3.lbm3_set_tile(L.h, *tile)
     lbm3.lbm3_adjoint_record(L.h, steps, every)
     rho_T = L.densities()
     g = 2.0 * (rho_T[0] - target)
@@ -78,8 +82,8 @@ def test_adjoint_matches_oracle_finite_differences(steps, every):
 
 
 def test_adjoint_wide_lattice_many_tiles_against_oracle_finite_differences():
-    """1030 x 12 (wider than 1024, not a multiple of 16): the reverse sweep's row-marching pass
-    runs as several strips and row segments.  Wavy vertical bands of the three fluids put
+    """1030 x 12 (wider than 1024, not a multiple of 16) with a march shape set, so the
+    reverse sweep's row-marching pass runs as several strips and row segments.  Wavy vertical bands of the three fluids put
     interfaces across every strip and segment boundary and across the periodic seam; the
     probed nodes sit on strip boundaries (every 206 columns) and on the seam.  The loss here
     is about 400, so central differences at h = 1e-6 would carry about 4e-8 of rounding
@@ -90,8 +94,10 @@ def test_adjoint_wide_lattice_many_tiles_against_oracle_finite_differences():
     lab = ((x + np.round(2.5 * np.sin(2 * np.pi * y / ny)).astype(int)) // 7) % 3
     rho0 = inputs.rho_from_labels(lab)
     target = inputs.loss_target(rho0[0], seed=1030)
-    loss, ds, dr = gpu_gradient(rho0, target, SIGMA, tau, steps, every)
+    loss, ds, dr = gpu_gradient(rho0, target, SIGMA, tau, steps, every, tile=(256, 0))
     assert abs(loss / oracle_loss(rho0, target, SIGMA, tau, steps) - 1) < 1e-12
+    _, ds_b, dr_b = gpu_gradient(rho0, target, SIGMA, tau, steps, every)  # the fused block step
+    assert np.allclose(ds_b, ds, rtol=1e-10, atol=0) and np.allclose(dr_b, dr, rtol=1e-9, atol=1e-12)
     for q in range(3):
         sp, sm = list(SIGMA), list(SIGMA)
         sp[q] += h
@@ -108,6 +114,39 @@ def test_adjoint_wide_lattice_many_tiles_against_oracle_finite_differences():
         fd = (oracle_loss(rp, target, SIGMA, tau, steps) - oracle_loss(rm, target, SIGMA, tau, steps)) / (2 * h)
         print(f"dL/drho0[{k},{yy},{xx}] adjoint {dr[k, yy, xx]:.10e} fd {fd:.10e}")
         assert abs(dr[k, yy, xx] - fd) <= 1e-5 * max(1e-3, abs(fd))
+
+
+@pytest.mark.parametrize("n", [384, 1024])
+def test_adjoint_block_pass_against_march_and_gpu_finite_differences(n):
+    """Lattices past the fused reverse step's 2^17 nodes, up to the block pass's 2^20
+    (384^2, 1024^2): the reverse steps run k_adj_local and the two-dimensional block pass.
+    Janus droplet of radius 3n/16, 6 steps with a checkpoint every 2.  The gradients equal
+    those of the row march (a march shape set) to summation order, and dL/dsigma matches
+    central differences of the FP64 forward loss as in the 2048^2 case."""
+    steps, h = 6, 1e-6
+    w = inputs.janus_halves(n, 3 * n / 16, SIGMA, (0.8, 0.8, 0.8), steps)
+    target = inputs.loss_target(w.rho[0], seed=5551)
+    loss, ds, dr = gpu_gradient(w.rho, target, SIGMA, w.tau, steps, 2)
+    loss_m, ds_m, dr_m = gpu_gradient(w.rho, target, SIGMA, w.tau, steps, 2, tile=(256, 0))
+    assert loss == loss_m
+    assert np.allclose(ds, ds_m, rtol=1e-10, atol=0), (ds, ds_m)
+    scale = np.abs(dr_m).max()
+    assert np.abs(dr - dr_m).max() <= 1e-12 * scale
+
+    def L_at(sig):
+        M = lbm3.Lattice(n, n, sig, w.tau).init(w.rho).step(steps)
+        v = float(((M.densities()[0] - target) ** 2).sum())
+        M.close()
+        return v
+
+    noise = 4 * 2.2e-16 * loss / h
+    for q in range(3):
+        sp, sm = list(SIGMA), list(SIGMA)
+        sp[q] += h
+        sm[q] -= h
+        fd = (L_at(sp) - L_at(sm)) / (2 * h)
+        print(f"n={n} dL/dsigma[{q}] adjoint {ds[q]:.10e} fd {fd:.10e} (noise {noise:.1e})")
+        assert abs(ds[q] - fd) <= 1e-5 * abs(fd) + noise
 
 
 def test_adjoint_above_the_overlap_size_against_gpu_finite_differences():
