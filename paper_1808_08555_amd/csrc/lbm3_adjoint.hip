@@ -728,30 +728,6 @@ void launch_sf(int nt, int ntiles, hipStream_t q, const Geo& g, const AdjWS& w, 
     }
 }
 
-// Blocks of at most cmax x rmax nodes, sizes spread evenly, row of blocks after row of blocks.
-std::vector<Tile> plan_even_blocks(int nx, int ny, int cmax, int rmax)
-{
-    std::vector<Tile> out;
-    const int nbx = (nx + cmax - 1) / cmax, nby = (ny + rmax - 1) / rmax;
-    int y0 = 0;
-    for (int by = 0; by < nby; ++by) {
-        const int rows = ny / nby + (by < ny % nby ? 1 : 0);
-        int x0 = 0;
-        for (int bx = 0; bx < nbx; ++bx) {
-            const int cols = nx / nbx + (bx < nx % nbx ? 1 : 0);
-            Tile t{};
-            t.x0 = x0;
-            t.y0 = y0;
-            t.rows = rows;
-            t.cols = cols;
-            out.push_back(t);
-            x0 += cols;
-        }
-        y0 += rows;
-    }
-    return out;
-}
-
 Geo geo_of(const KParams& kp)
 {
     Geo g;
@@ -919,9 +895,9 @@ int lbm3_adjoint(lbm3_t* h, const double* drho1_T, double dsigma[3], double* drh
     const int sfw = sf_block ? 0 : sf_width(kp.nx);
     std::vector<Tile> sf_plan;
     if (fused) {
-        sf_plan = plan_even_blocks(kp.nx, kp.ny, kAdjBlockX - 4, kAdjBlockY - 4);
+        plan_blocks(0, kp.nx, kp.ny, kAdjBlockX - 4, kAdjBlockY - 4, sf_plan);
     } else if (sf_block) {
-        sf_plan = plan_even_blocks(kp.nx, kp.ny, kSfBlockX - 2, kSfBlockY - 2);
+        plan_blocks(0, kp.nx, kp.ny, kSfBlockX - 2, kSfBlockY - 2, sf_plan);
     } else {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) != hipSuccess ||

@@ -276,7 +276,7 @@ int upload_plan(lbm3* h)
     // lbm3_set_tile chose a march shape.
     std::vector<Tile> LB;
     if (!h->tile_set && h->pass_mode != 2 && (int64_t)h->kp.nx * h->kp.ny <= kBlockMaxNodes)
-        plan_blocks(0, h->kp.nx, h->kp.ny, LB);
+        plan_blocks(0, h->kp.nx, h->kp.ny, kBlockCols, kBlockRows, LB);
     std::vector<Tile> T = xcd_order(L, 8), T2 = xcd_order(L2, 8), TB = xcd_order(LB, 8);
     (void)hipStreamSynchronize(h->stream);
     if (h->dtiles) (void)hipFree(h->dtiles);

@@ -111,9 +111,9 @@ void plan_lattice(int inst, int nx, int ny, int threads, int rows, int elem_byte
 // receives one contiguous run of it, keeping neighbouring tiles, and the halos they share, in
 // the same L2.
 std::vector<Tile> xcd_order(const std::vector<Tile>& L, int nxcd);
-// Blocks of one lattice for launch_block: at most kBlockCols x kBlockRows nodes each, sizes
-// spread evenly over nx and ny, row of blocks after row of blocks.
-void plan_blocks(int inst, int nx, int ny, std::vector<Tile>& out);
+// Blocks of one lattice: at most cmax x rmax nodes each (kBlockCols x kBlockRows for
+// launch_block), sizes spread evenly over nx and ny, row of blocks after row of blocks.
+void plan_blocks(int inst, int nx, int ny, int cmax, int rmax, std::vector<Tile>& out);
 // The two state buffers of a step (read one, write the other) in one allocation, the second
 // an odd number of MiB after the first (see lbm3_plan.hip); buf[1] is not freed on its own.
 hipError_t alloc_state_pair(size_t bytes, void* buf[2]);

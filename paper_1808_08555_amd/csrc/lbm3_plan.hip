@@ -53,9 +53,9 @@ void plan_lattice(int inst, int nx, int ny, int threads, int rows, int elem_byte
             }
 }
 
-void plan_blocks(int inst, int nx, int ny, std::vector<Tile>& out)
+void plan_blocks(int inst, int nx, int ny, int cmax, int rmax, std::vector<Tile>& out)
 {
-    const int nbx = (nx + kBlockCols - 1) / kBlockCols, nby = (ny + kBlockRows - 1) / kBlockRows;
+    const int nbx = (nx + cmax - 1) / cmax, nby = (ny + rmax - 1) / rmax;
     int y0 = 0;
     for (int by = 0; by < nby; ++by) {
         const int rows = ny / nby + (by < ny % nby ? 1 : 0);

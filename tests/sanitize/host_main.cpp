@@ -91,14 +91,18 @@ int main()
                         int tp = 0, tr = 0;
                         default_tile(KParams{}, Prec::F64, &tp, &tr);
                     }
-    // block plans: every node in exactly one block of at most kBlockCols x kBlockRows
-    for (int nx : {1, 2, 27, 28, 29, 57, 256, 1000, 65535})
-        for (int ny : {1, 11, 12, 13, 100, 1024}) {
+    // block plans (the step's 28 x 12 and the adjoint's 28 x 12 and 30 x 6): every node in
+    // exactly one block of at most cmax x rmax
+    const int shapes[][2] = {{kBlockCols, kBlockRows}, {30, 6}};
+    for (const auto& cr : shapes)
+    for (int nx : {1, 2, 27, 28, 29, 31, 57, 256, 1000, 65535})
+        for (int ny : {1, 5, 6, 7, 11, 12, 13, 100, 1024}) {
+            const int cmax = cr[0], rmax = cr[1];
             std::vector<Tile> L;
-            plan_blocks(2, nx, ny, L);
+            plan_blocks(2, nx, ny, cmax, rmax, L);
             std::vector<unsigned char> hit((size_t)nx * ny, 0);
             for (const Tile& t : L) {
-                bad |= t.inst != 2 || t.cols < 1 || t.cols > kBlockCols || t.rows < 1 || t.rows > kBlockRows;
+                bad |= t.inst != 2 || t.cols < 1 || t.cols > cmax || t.rows < 1 || t.rows > rmax;
                 bad |= t.x0 < 0 || t.y0 < 0 || t.x0 + t.cols > nx || t.y0 + t.rows > ny;
                 for (int y = t.y0; y < t.y0 + t.rows; ++y)
                     for (int x = t.x0; x < t.x0 + t.cols; ++x) ++hit[(size_t)y * nx + x];
