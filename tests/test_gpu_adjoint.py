@@ -116,6 +116,26 @@ def test_adjoint_wide_lattice_many_tiles_against_oracle_finite_differences():
         assert abs(dr[k, yy, xx] - fd) <= 1e-5 * max(1e-3, abs(fd))
 
 
+@pytest.mark.parametrize("shape", [(1, 1), (3, 2), (2, 7), (1, 40), (70, 1), (29, 13), (37, 29)])
+def test_adjoint_fused_block_equals_march_on_tiny_and_ragged_lattices(shape):
+    """The fused block reverse step (and the block recompute) against the row march (a march
+    shape set) on lattices narrower than the halo, one-block lattices and ragged blocks:
+    random three-fluid mixtures with near-zero entries, 6 steps with a checkpoint every 2.
+    Each node's arithmetic is the same on both paths; only the dL/dsigma partial sums add in
+    another order, and the back end may contract multiply-adds differently per kernel."""
+    nx, ny = shape
+    rho0 = inputs.random_mixture(nx, ny, 11, tiny_fraction=0.05)
+    tau = (0.7, 0.8, 0.9)
+    target = inputs.loss_target(rho0[0], seed=77)
+    loss, ds, dr = gpu_gradient(rho0, target, SIGMA, tau, 6, 2)
+    loss_m, ds_m, dr_m = gpu_gradient(rho0, target, SIGMA, tau, 6, 2, tile=(64, 0))
+    assert loss == loss_m
+    assert abs(loss / oracle_loss(rho0, target, SIGMA, tau, 6) - 1) < 1e-12
+    assert np.isfinite(ds).all() and np.isfinite(dr).all()
+    assert np.allclose(ds, ds_m, rtol=1e-9, atol=1e-12 * np.abs(ds_m).max()), (ds, ds_m)
+    assert np.abs(dr - dr_m).max() <= 1e-11 * max(np.abs(dr_m).max(), 1e-300)
+
+
 @pytest.mark.parametrize("n", [384, 1024])
 def test_adjoint_block_pass_against_march_and_gpu_finite_differences(n):
     """Lattices past the fused reverse step's 2^17 nodes, up to the block pass's 2^20
