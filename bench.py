@@ -145,7 +145,8 @@ def bench_batched(torch, lbm3, inputs, steps: int):
     for i, w in enumerate(ws):
         lbm3.lbm3_batch_init_fields(b, i, w.rho)
     with torch.cuda.stream(st):
-        threads, rows = autotune.tune_batch(b, [w.nx for w in ws], "fp32", steps=40)
+        # tuned afresh on every run (force): a cached plan from another run is not re-measured
+        threads, rows = autotune.tune_batch(b, [w.nx for w in ws], "fp32", steps=40, force=True)
         lbm3.lbm3_batch_step(b, 40)
         torch.cuda.synchronize()
         a = torch.cuda.Event(enable_timing=True)

@@ -47,20 +47,21 @@ def _arch(torch) -> str:
 
 
 def _time(torch, fn, steps: int) -> float:
-    """Median of three timings of `steps` steps, after `steps` untimed ones: a batch
-    re-captures its graph after a shape change, and that must not land in a timed run."""
-    st = torch.cuda.current_stream()
+    """Median of three timings (ms per step) of `steps` steps, after `steps` untimed ones: a
+    batch re-captures its graph after a shape change, and that must not land in a timed run.
+    Each run is bracketed by device-wide synchronisation and timed on the host, so the
+    timing holds whichever stream the handle orders its work on (a batch created without a
+    stream runs on a stream of its own, which events on torch's current stream would not
+    bracket)."""
+    import time
     fn(steps)
     torch.cuda.synchronize()
     ts = []
     for _ in range(3):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(st)
+        t0 = time.perf_counter()
         fn(steps)
-        b.record(st)
         torch.cuda.synchronize()
-        ts.append(a.elapsed_time(b) / steps)
+        ts.append((time.perf_counter() - t0) * 1e3 / steps)
     return sorted(ts)[1]
 
 

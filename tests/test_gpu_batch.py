@@ -155,6 +155,24 @@ def test_autotuner_choice_is_applied_and_cached(tmp_path, monkeypatch):
     lbm3.lbm3_batch_destroy(b)
 
 
+def test_autotuner_times_a_batch_on_its_own_stream():
+    """A batch created without a stream orders its work on a stream of its own; the tuner's
+    timing must still cover that work.  64 instances (6.3 M nodes) in FP32 move at least
+    64 B per node and step, so a timing that implied more than the 8 TB/s HBM peak would
+    have missed the kernels (launch overhead alone is a few microseconds per step)."""
+    import torch
+    ws = inputs.morphology_batch()
+    b = _make_batch(ws, "fp32")
+    try:
+        nodes = sum(w.nx * w.ny for w in ws)
+        ms = autotune._time(torch, lambda n: lbm3.lbm3_batch_step(b, n), 20)
+        floor_ms = nodes * 64 / 8e12 * 1e3
+        print(f"batch timing {ms:.4f} ms/step, HBM floor {floor_ms:.4f} ms/step")
+        assert ms >= floor_ms
+    finally:
+        lbm3.lbm3_batch_destroy(b)
+
+
 def _contact(c, a, b, lo=0.2):
     return int(((c[a] > lo) & (c[b] > lo)).sum())
 
@@ -217,18 +235,16 @@ def test_reinitialised_instance_in_a_stepped_batch(precision):
     lbm3.lbm3_batch_destroy(b)
 
 
-def test_morphology_batch_in_the_benchmark_plan_matches_plain_bitwise():
+def test_morphology_batch_in_the_benchmark_plan_matches_plain_bitwise(monkeypatch, tmp_path):
     """The batched form exactly as the benchmark runs it: the 64-instance morphology sweep
     (sides 128-512, FP32) with the autotuner's plan (the two-step launch where it wins),
     200 steps (ten replays of the captured graph): every instance's densities equal the
-    same lattice stepped alone, bit for bit."""
-    import torch
+    same lattice stepped alone, bit for bit.  The tuning goes to a cache of the test's own."""
+    monkeypatch.setenv("LBM3_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
     ws = inputs.morphology_batch()
     b = _make_batch(ws, "fp32")
     try:
-        st = torch.cuda.current_stream()
-        with torch.cuda.stream(st):
-            autotune.tune_batch(b, [w.nx for w in ws], "fp32", steps=20)
+        autotune.tune_batch(b, [w.nx for w in ws], "fp32", steps=20)
         plan = lbm3.lbm3_batch_get_pair_launch(b)
         print("benchmark plan (steps per launch, threads, rows, workgroups):", plan)
         for i, w in enumerate(ws):  # tuning stepped the batch: start again from the inputs
