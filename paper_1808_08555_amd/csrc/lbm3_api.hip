@@ -273,7 +273,7 @@ int upload_plan(lbm3* h)
     }
     h->threads2 = t2;
     // Single steps of a small lattice go to the block kernel (no march warm-up), unless
-    // lbm3_set_tile chose a march shape.
+    // lbm3_set_tile chose a march shape or steps-per-launch mode 2 asks for pairs.
     std::vector<Tile> LB;
     if (!h->tile_set && h->pass_mode != 2 && (int64_t)h->kp.nx * h->kp.ny <= kBlockMaxNodes)
         plan_blocks(0, h->kp.nx, h->kp.ny, kBlockCols, kBlockRows, LB);
