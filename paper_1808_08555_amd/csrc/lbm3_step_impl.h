@@ -292,13 +292,24 @@ __device__ __forceinline__ void collide_recolour(const C (&f)[9], const C (&rk)[
     const C uu = ux * ux + uy * uy;
     const C uF = ux * Fx + uy * Fy;
     const C pref = C(1) - C(0.5) * itau;
+    // f_dag_i = (1 - 1/tau) f_i + (1/tau) f_eq_i + Phi_i, with the per-node factors of the
+    // three weight classes formed once: (1/tau) w rho and w (1 - 1/(2 tau)).  In terms of
+    // e.u and 3 e.F, f_eq_i / (w rho) = (1 - 1.5 u.u) + e.u (3 + 4.5 e.u) and
+    // Phi_i / (w (1 - 1/(2 tau))) = (3 e.F - 3 u.F) + (3 e.u)(3 e.F).
+    const C omi = C(1) - itau;
+    const C c0 = C(1) - C(1.5) * uu;
+    const C tuF = C(3) * uF, tFx = C(3) * Fx, tFy = C(3) * Fy;
+    const C tr = itau * rho;
+    const C W1[3] = {wgt<C>(0) * tr, wgt<C>(1) * tr, wgt<C>(5) * tr};
+    const C W2[3] = {wgt<C>(0) * pref, wgt<C>(1) * pref, wgt<C>(5) * pref};
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
+        const int cls = i == 0 ? 0 : (i < 5 ? 1 : 2);
         const C eu = C(EX[i]) * ux + C(EY[i]) * uy;
-        const C eF = C(EX[i]) * Fx + C(EY[i]) * Fy;
-        const C feq = wgt<C>(i) * rho * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
-        const C phi = wgt<C>(i) * pref * (C(3) * (eF - uF) + C(9) * eu * eF);
-        fd[i] = f[i] - (f[i] - feq) * itau + phi;
+        const C teF = C(EX[i]) * tFx + C(EY[i]) * tFy;
+        const C P = fma(eu, fma(C(4.5), eu, C(3)), c0);
+        const C Q = fma(C(3) * eu, teF, teF - tuF);
+        fd[i] = fma(f[i], omi, fma(W1[cls], P, W2[cls] * Q));
     }
     if constexpr (PT) {
         const C a = C(4.5) * itau;
