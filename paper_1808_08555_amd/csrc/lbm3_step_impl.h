@@ -129,17 +129,18 @@ __device__ __forceinline__ int64_t fresh_stride(int64_t s)
 }
 
 // Isotropic difference of Eq. (12), 3 sum_i w_i phi(x + e_i) e_i, written as weighted
-// differences of opposite neighbours.  The grouping keeps exact zeros for data that
-// are mirror-symmetric about the node, also when the compiler fuses multiply-adds.
+// differences of opposite neighbours with the factor 3 taken into the weights (3 w = 1/3 on
+// the axes, 1/12 on the diagonals).  The grouping keeps exact zeros for data that are
+// mirror-symmetric about the node, also when the compiler fuses multiply-adds.
 template <typename C>
 __device__ __forceinline__ C ddx(C e, C w, C ne, C nw, C se, C sw)
 {
-    return C(3) * (C(1.0 / 9.0) * (e - w) + C(1.0 / 36.0) * ((ne - sw) + (se - nw)));
+    return C(1.0 / 3.0) * (e - w) + C(1.0 / 12.0) * ((ne - sw) + (se - nw));
 }
 template <typename C>
 __device__ __forceinline__ C ddy(C n, C s, C ne, C nw, C se, C sw)
 {
-    return C(3) * (C(1.0 / 9.0) * (n - s) + C(1.0 / 36.0) * ((ne - sw) + (nw - se)));
+    return C(1.0 / 3.0) * (n - s) + C(1.0 / 12.0) * ((ne - sw) + (nw - se));
 }
 
 // V . e_i for the nine lattice directions, written out (no multiplications by 0 or 1).
@@ -243,12 +244,12 @@ __device__ __forceinline__ void densities_f27(Get v, C (&r0)[3], C (&f0)[9])
 
 template <typename C>
 struct StepConsts {
-    C sig[3], g[3], beta0, ct_coef, inv_nu[3], cfac[3], guard2;
+    C sig[3], bg[3], beta0, ct_coef, inv_nu[3], cfac[3], guard2;  // bg = beta0 g_kl
     __device__ explicit StepConsts(const KParams& kp)
     {
         for (int p = 0; p < 3; ++p) {
             sig[p] = C(kp.sigma[p]);
-            g[p] = C(kp.g[p]);
+            bg[p] = C(kp.beta0 * kp.g[p]);
             inv_nu[p] = C(kp.inv_nu[p]);
             cfac[p] = C(kp.cfac[p]);
         }
@@ -329,9 +330,10 @@ __device__ __forceinline__ void collide_recolour(const C (&f)[9], const C (&rk)[
     // C_t and beta_kl of Eq. (19) (or the law's own s and g_kl); a_p = beta_p rho_k rho_l / rho
     C ct = K.ct_coef * rk[0] * rk[1] * rk[2] * (irho * irho * irho);
     ct = ct < C(1) ? ct : C(1);
-    const C a0 = K.beta0 * (C(1) + ct * K.g[0]) * (rk[0] * rk[1]) * irho;
-    const C a1 = K.beta0 * (C(1) + ct * K.g[1]) * (rk[0] * rk[2]) * irho;
-    const C a2 = K.beta0 * (C(1) + ct * K.g[2]) * (rk[1] * rk[2]) * irho;
+    // beta_p = beta0 (1 + s g_p) = beta0 + s (beta0 g_p)
+    const C a0 = fma(ct, K.bg[0], K.beta0) * (rk[0] * rk[1]) * irho;
+    const C a1 = fma(ct, K.bg[1], K.beta0) * (rk[0] * rk[2]) * irho;
+    const C a2 = fma(ct, K.bg[2], K.beta0) * (rk[1] * rk[2]) * irho;
     // V_k = sum_{l != k} a_kl n_kl with n_lk = -n_kl; the three sum to zero, and V_2 is taken
     // as -(V_0 + V_1) here and wherever a factored state is expanded (fac_v2), so that the
     // factored state needs only V_0 and V_1 and every path rounds alike
