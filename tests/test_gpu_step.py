@@ -742,3 +742,10 @@ def test_fp32_storage_rounding_brackets_and_is_unbiased():
     assert n > 0.9 * A.size
     assert abs(up.mean() - pos.mean()) < 4 * se
     assert abs(np.mean((B[inexact] - A[inexact]) / gap * np.sign(A[inexact]))) < 4 * se
+    # plane by plane as well: a node's 16 values take consecutive random numbers of one
+    # sequence, so each plane must be unbiased on its own (4.5 standard errors each)
+    planes = np.repeat(np.arange(16), nx * ny)[inexact]
+    for q in range(16):
+        m = planes == q
+        se_q = 0.5 / np.sqrt(m.sum())
+        assert abs(up[m].mean() - pos[m].mean()) < 4.5 * se_q, (q, up[m].mean(), pos[m].mean())
